@@ -1,0 +1,144 @@
+/*
+ * ltriples — perturbative-triples energy E(T) of one local-natural-orbital
+ * (LNO) domain over high-spin restricted-open-shell, semicanonical orbitals
+ * with spin-unrestricted amplitudes, on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (Szabo, Csoka, Kallay, Nagy, arXiv:2311.10048,
+ * Sec. "Open-Shell LNO-CCSD(T) Ansatz", eq. cim_pt_energy summed over the
+ * central index, and Sec. "Correlation energy calculation in the LIS" for
+ * the inputs): with D = e_i + e_j + e_k - e_a - e_b - e_c,
+ *
+ *   W^{abc}_{ijk} = P(i/jk)P(a/bc)[ sum_e t^{ae}_{jk}<ei||bc> - sum_m t^{bc}_{im}<ma||jk> ]
+ *   V^{abc}_{ijk} = P(i/jk)P(a/bc)[ t^a_i <jk||bc> + f_ia t^{bc}_{jk} ]
+ *   E(T) = 1/36 sum_{ijkabc} W (W + V) / D = E4 + E_ST + E_DT,
+ *
+ * summed over the four spin blocks aaa, aab, abb, bbb.  Two-electron
+ * integrals are density fitted in a natural-auxiliary-function basis shared
+ * by both spins (Sec. "Natural auxiliary functions"):
+ * (pq|rs) = sum_Q B^Q_pq B^Q_rs, <pq||rs> = (pr|qs) - (ps|qr).
+ *
+ * Conventions
+ *  - All input arrays are FP64, row-major, C-contiguous, in DEVICE memory,
+ *    owned by the caller and only read.  Layouts:
+ *      t1a [noa][nva]            t1b [nob][nvb]
+ *      t2aa [noa][noa][nva][nva] antisymmetric in (i,j) and in (a,b)
+ *      t2bb [nob][nob][nvb][nvb] antisymmetric in (I,J) and in (A,B)
+ *      t2ab [noa][nob][nva][nvb] t^{aB}_{iJ} at [i][J][a][B], no symmetry
+ *      Boo_x [naux][no_x][no_x], Bov_x [naux][no_x][nv_x],
+ *      Bvv_x [naux][nv_x][nv_x]   (x = a, b; oo and vv symmetric in p,q)
+ *      eo_x [no_x], ev_x [nv_x]   semicanonical orbital energies (Eh)
+ *      fov_x [no_x][nv_x]         occupied-virtual Fock block
+ *  - SOMOs are alpha occupied and beta virtual orbitals.
+ *  - Outputs are FP64 in device memory.  Low-precision copies of the inputs
+ *    live in the caller's workspace.  The energy epilogue (V, D, the
+ *    division and all reductions) is always FP64.
+ *  - A work item is one unique occupied triplet (block, p, q, r):
+ *      block 0 aaa (i<j<k), 1 aab (i<j alpha, K beta),
+ *      2 abb (I<J beta, k alpha), 3 bbb (I<J<K).
+ *  - Results are deterministic: bitwise identical across runs and batch
+ *    sizes for the same inputs, precision and item list.
+ *
+ * Errors: every entry point returns LT_OK (0) or a negative code; on error
+ * nothing is enqueued and ltriples_last_error() (thread-local) describes it.
+ */
+#ifndef LTRIPLES_H
+#define LTRIPLES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LT_OK 0
+#define LT_EINVAL (-1)      /* null pointer or negative dimension */
+#define LT_ESHAPE (-2)      /* inconsistent dimensions or item list */
+#define LT_EDENOM (-3)      /* max occupied e >= min virtual e: some D >= 0 */
+#define LT_EPREC (-4)       /* unsupported precision */
+#define LT_EWORKSPACE (-5)  /* workspace too small */
+#define LT_EHIP (-6)        /* HIP runtime error */
+#define LT_ENONFINITE (-7)  /* NaN/Inf in the orbital energies */
+
+/* Arithmetic of the W contractions.  LT_FP64: FP64 matrix cores.
+ * LT_FP32: FP32 matrix cores, FP32 accumulation.  LT_BF16X3: each FP32
+ * operand split as hi = bf16(x), lo = bf16(x - hi), products
+ * hi*hi + hi*lo + lo*hi on BF16 matrix cores with FP32 accumulation.
+ * LT_BF16: single BF16 product (ablation only). */
+typedef enum {
+  LT_FP64 = 0,
+  LT_FP32 = 1,
+  LT_BF16X3 = 2,
+  LT_BF16 = 3
+} ltriples_precision;
+
+/* One LIS domain: sizes and device pointers in the layouts above.  A pointer
+ * may be NULL only when its array has zero elements. */
+typedef struct ltriples_domain {
+  int32_t noa, nob, nva, nvb, naux;
+  const double *t1a, *t1b;
+  const double *t2aa, *t2bb, *t2ab;
+  const double *Boo_a, *Bov_a, *Bvv_a;
+  const double *Boo_b, *Bov_b, *Bvv_b;
+  const double *eo_a, *ev_a, *eo_b, *ev_b;
+  const double *fov_a, *fov_b;
+} ltriples_domain;
+
+/* Options; a NULL options pointer means all defaults (zeros). */
+typedef struct ltriples_options {
+  /* bytes of workspace the per-batch triples intermediates may use;
+   * 0 = default (8 GiB, capped by the work) */
+  size_t batch_budget;
+  /* optional HOST array [n_items][4] of (block, p, q, r) restricting the
+   * energy to these items (NULL = all unique triplets of the domain) */
+  const int32_t* items;
+  int32_t n_items;
+  /* optional DEVICE array [n_items][3] receiving {E4, E_ST, E_DT} per item,
+   * in the order of `items` (or of the full enumeration) */
+  double* e_items;
+  /* items per batch (0 = automatic) */
+  int32_t batch_items;
+  int32_t reserved[7];
+} ltriples_options;
+
+/* Host-only validation of sizes, pointers, precision and item list.  Makes
+ * no HIP call and reads no device memory. */
+int ltriples_validate(const ltriples_domain* d, int32_t precision,
+                      const ltriples_options* o);
+
+/* Host-only: workspace bytes ltriples_energy needs for this domain,
+ * precision and options. */
+int ltriples_workspace_size(const ltriples_domain* d, int32_t precision,
+                            const ltriples_options* o, size_t* bytes);
+
+/* Host-only: algorithmic W-contraction flop count of the item list (the
+ * GEMMs of the spin-block working equations over the full virtual cube,
+ * 2 flops per multiply-add); n_items_out receives the number of items. */
+int ltriples_flops(const ltriples_domain* d, const ltriples_options* o,
+                   double* flops, int64_t* n_items_out);
+
+/* E(T) of one domain, enqueued on `stream` (a hipStream_t; NULL = default).
+ *   e_out  device double[1]: E(T)
+ *   parts  device double[4][3] or NULL: per block {E4, E_ST, E_DT}
+ *   ws     device workspace of ws_bytes >= ltriples_workspace_size(), or
+ *          NULL to let the library allocate and free it inside the call.
+ * The call reads the orbital energies back to the host once (a synchronous
+ * copy) to check that every denominator is negative (LT_EDENOM) and finite
+ * (LT_ENONFINITE); everything else is asynchronous on `stream`.
+ * Fewer than 3 occupied orbitals in total, or empty virtual spaces, give
+ * E = 0 and LT_OK. */
+int ltriples_energy(const ltriples_domain* d, int32_t precision,
+                    const ltriples_options* o, double* e_out, double* parts,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* Description of the last error on this thread ("" if none). */
+const char* ltriples_last_error(void);
+
+/* Library version string. */
+const char* ltriples_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LTRIPLES_H */

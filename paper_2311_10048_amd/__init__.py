@@ -1,0 +1,205 @@
+"""ltriples: perturbative-triples energy E(T) of one LNO domain on MI355X.
+
+Thin Python binding over the C ABI in ``include/ltriples.h`` (libltriples.so,
+HIP for gfx950).  Only argument marshalling happens here: every step of the
+(T) path runs in the library's kernels.  PyTorch provides device memory and
+the current stream; the library is required, there is no fallback.
+
+    import paper_2311_10048_amd as lt
+    e, parts = lt.ltriples_energy(tensors, lt.LT_FP32)
+
+``tensors`` maps the field names of ``ltriples_domain`` (t1a, t1b, t2aa,
+t2bb, t2ab, Boo_a, Bov_a, Bvv_a, Boo_b, Bov_b, Bvv_b, eo_a, ev_a, eo_b, ev_b,
+fov_a, fov_b) to contiguous float64 tensors on the current HIP device, in the
+layouts documented in the header.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Mapping, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libltriples.so")
+
+LT_OK = 0
+LT_EINVAL = -1
+LT_ESHAPE = -2
+LT_EDENOM = -3
+LT_EPREC = -4
+LT_EWORKSPACE = -5
+LT_EHIP = -6
+LT_ENONFINITE = -7
+
+LT_FP64 = 0
+LT_FP32 = 1
+LT_BF16X3 = 2
+LT_BF16 = 3
+PRECISIONS = {"fp64": LT_FP64, "fp32": LT_FP32, "bf16x3": LT_BF16X3, "bf16": LT_BF16}
+
+ARRAY_FIELDS = ("t1a", "t1b", "t2aa", "t2bb", "t2ab", "Boo_a", "Bov_a", "Bvv_a",
+                "Boo_b", "Bov_b", "Bvv_b", "eo_a", "ev_a", "eo_b", "ev_b", "fov_a", "fov_b")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class Domain(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_int32) for n in ("noa", "nob", "nva", "nvb", "naux")]
+                + [(n, ctypes.c_void_p) for n in ARRAY_FIELDS])
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("batch_budget", ctypes.c_size_t),
+                ("items", ctypes.c_void_p),
+                ("n_items", ctypes.c_int32),
+                ("e_items", ctypes.c_void_p),
+                ("batch_items", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+class LtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ltriples error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None):
+    """Load libltriples.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} not found: build it with `python -m paper_2311_10048_amd.build`")
+    lib = ctypes.CDLL(p)
+    Dp, Op = ctypes.POINTER(Domain), ctypes.POINTER(Options)
+    lib.ltriples_validate.argtypes = [Dp, ctypes.c_int32, Op]
+    lib.ltriples_workspace_size.argtypes = [Dp, ctypes.c_int32, Op, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ltriples_flops.argtypes = [Dp, Op, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.ltriples_energy.argtypes = [Dp, ctypes.c_int32, Op, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.ltriples_last_error.restype = ctypes.c_char_p
+    lib.ltriples_version.restype = ctypes.c_char_p
+    for f in ("ltriples_validate", "ltriples_workspace_size", "ltriples_flops", "ltriples_energy"):
+        getattr(lib, f).restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def ltriples_last_error() -> str:
+    return load_library().ltriples_last_error().decode()
+
+
+def ltriples_version() -> str:
+    return load_library().ltriples_version().decode()
+
+
+def _check(code: int):
+    if code != LT_OK:
+        raise LtError(code, ltriples_last_error())
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    raise TypeError(f"cannot take a device pointer of {type(x)}")
+
+
+def make_domain(dims, tensors: Optional[Mapping[str, object]] = None) -> Domain:
+    """ltriples_domain from (noa, nob, nva, nvb, naux) and device tensors
+    (or raw device addresses) keyed by field name; missing arrays are NULL."""
+    d = Domain()
+    d.noa, d.nob, d.nva, d.nvb, d.naux = (int(x) for x in dims)
+    tensors = tensors or {}
+    for n in ARRAY_FIELDS:
+        t = tensors.get(n)
+        if t is not None and hasattr(t, "is_contiguous"):
+            if not t.is_contiguous():
+                raise ValueError(f"{n} must be contiguous")
+            if str(t.dtype) != "torch.float64":
+                raise ValueError(f"{n} must be float64")
+        setattr(d, n, _ptr(t))
+    return d
+
+
+def make_options(items=None, e_items=None, batch_budget: int = 0, batch_items: int = 0):
+    """ltriples_options; `items` is a host int32 array [n][4] (kept alive by
+    the returned tuple's second element)."""
+    o = Options()
+    o.batch_budget = int(batch_budget)
+    o.batch_items = int(batch_items)
+    keep = None
+    if items is not None:
+        keep = np.ascontiguousarray(np.asarray(items, dtype=np.int32).reshape(-1, 4))
+        o.items = keep.ctypes.data
+        o.n_items = keep.shape[0]
+    o.e_items = _ptr(e_items)
+    return o, keep
+
+
+def ltriples_validate(dom: Domain, precision: int, options: Optional[Options] = None) -> int:
+    lib = load_library()
+    return lib.ltriples_validate(ctypes.byref(dom), int(precision),
+                                 ctypes.byref(options) if options is not None else None)
+
+
+def ltriples_workspace_size(dom: Domain, precision: int, options: Optional[Options] = None) -> int:
+    lib = load_library()
+    n = ctypes.c_size_t(0)
+    _check(lib.ltriples_workspace_size(ctypes.byref(dom), int(precision),
+                                       ctypes.byref(options) if options is not None else None,
+                                       ctypes.byref(n)))
+    return n.value
+
+
+def ltriples_flops(dom: Domain, options: Optional[Options] = None):
+    """(algorithmic W-contraction flops, number of items) of the item list."""
+    lib = load_library()
+    f = ctypes.c_double(0)
+    n = ctypes.c_int64(0)
+    _check(lib.ltriples_flops(ctypes.byref(dom), ctypes.byref(options) if options is not None else None,
+                              ctypes.byref(f), ctypes.byref(n)))
+    return f.value, n.value
+
+
+def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP32, items=None,
+                    e_items=None, batch_budget: int = 0, batch_items: int = 0, workspace=None,
+                    stream=None):
+    """E(T) of one domain on the current HIP device.
+
+    Returns (e, parts): a float64 device tensor of shape [1] and one of shape
+    [4, 3] (blocks aaa, aab, abb, bbb x {E4, E_ST, E_DT}).  `workspace`, if
+    given, is a uint8 device tensor at least ltriples_workspace_size() long;
+    otherwise one is allocated through torch.  The call is asynchronous on
+    `stream` (default: torch's current stream) except for one small
+    synchronous read of the orbital energies.
+    """
+    import torch
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    dom = make_domain(dims, tensors)
+    opts, keep = make_options(items, e_items, batch_budget, batch_items)
+    dev = next(t for t in tensors.values() if hasattr(t, "device")).device
+    need = ltriples_workspace_size(dom, precision, opts)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    e = torch.empty(1, dtype=torch.float64, device=dev)
+    parts = torch.empty(4, 3, dtype=torch.float64, device=dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    lib = load_library()
+    code = lib.ltriples_energy(ctypes.byref(dom), int(precision), ctypes.byref(opts),
+                               e.data_ptr(), parts.data_ptr(), workspace.data_ptr(),
+                               workspace.numel(), st.cuda_stream)
+    _check(code)
+    del keep
+    return e, parts

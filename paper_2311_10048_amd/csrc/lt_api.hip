@@ -1,0 +1,678 @@
+// C ABI of ltriples: validation, planning, workspace layout and the launch
+// sequence of the (T) energy of one domain.
+//
+// Launch sequence (all on the caller's stream):
+//  1. convert/copy the DF factors into k-major, padded operand layouts;
+//  2. FP64 builds of the small integral classes (ov|oo) and (ov|ov) and the
+//     operands derived from them (<ma||jk>, (aj|MK), (jm|CK), <qr||yz>);
+//  3. amplitude operands (transposed, pair-packed, spin-permuted copies);
+//  4. the (ov|vv) slabs <ei||bc> (pair packed), (jb|EC), (be|KC) built by
+//     MFMA GEMMs over the auxiliary index;
+//  5. per spin block, batches of occupied triplets: contraction GEMMs into
+//     batch buffers, then the FP64 energy epilogue and per-item reduction;
+//  6. per-block parts and the total, summed in a fixed order.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lt_internal.h"
+#include "ltriples.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(...)                                                                  \
+  do {                                                                               \
+    hipError_t e_ = (__VA_ARGS__);                                                   \
+    if (e_ != hipSuccess)                                                            \
+      return fail(LT_EHIP, "HIP error %s at %s:%d", hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                         \
+  } while (0)
+
+inline int64_t ld4(int64_t n) { return (n + 3) & ~int64_t(3); }
+inline int64_t npair(int64_t n) { return n * (n - 1) / 2; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+struct Dims {
+  int64_t o[2], v[2], Q;
+};
+
+Dims dims_of(const ltriples_domain* d) {
+  Dims x;
+  x.o[0] = d->noa; x.o[1] = d->nob; x.v[0] = d->nva; x.v[1] = d->nvb; x.Q = d->naux;
+  return x;
+}
+
+// block b -> (sigma, is_mixed): 0 aaa, 1 aab (sigma=a), 2 abb (sigma=b), 3 bbb
+inline int blk_sigma(int b) { return (b == 0 || b == 1) ? 0 : 1; }
+inline bool blk_mixed(int b) { return b == 1 || b == 2; }
+
+int check_items(const Dims& D, const ltriples_options* o) {
+  if (!o || !o->items) return LT_OK;
+  if (o->n_items < 0) return fail(LT_EINVAL, "n_items < 0");
+  for (int32_t n = 0; n < o->n_items; ++n) {
+    const int32_t* it = o->items + 4 * n;
+    const int b = it[0];
+    if (b < 0 || b > 3) return fail(LT_ESHAPE, "item %d: bad block %d", n, b);
+    const int s = blk_sigma(b);
+    const int64_t os = D.o[s], ot = D.o[1 - s];
+    if (blk_mixed(b)) {
+      if (!(0 <= it[1] && it[1] < it[2] && it[2] < os && 0 <= it[3] && it[3] < ot))
+        return fail(LT_ESHAPE, "item %d: bad indices (%d,%d,%d,%d)", n, b, it[1], it[2], it[3]);
+    } else {
+      if (!(0 <= it[1] && it[1] < it[2] && it[2] < it[3] && it[3] < os))
+        return fail(LT_ESHAPE, "item %d: bad indices (%d,%d,%d,%d)", n, b, it[1], it[2], it[3]);
+    }
+  }
+  return LT_OK;
+}
+
+int validate(const ltriples_domain* d, int32_t prec, const ltriples_options* o) {
+  if (!d) return fail(LT_EINVAL, "domain is NULL");
+  if (d->noa < 0 || d->nob < 0 || d->nva < 0 || d->nvb < 0 || d->naux < 0)
+    return fail(LT_EINVAL, "negative dimension");
+  if (prec != LT_FP64 && prec != LT_FP32)
+    return fail(LT_EPREC, "precision %d not supported by this build", prec);
+  const int64_t oa = d->noa, ob = d->nob, va = d->nva, vb = d->nvb, Q = d->naux;
+  struct P { const double* p; int64_t n; const char* name; } ps[] = {
+      {d->t1a, oa * va, "t1a"}, {d->t1b, ob * vb, "t1b"},
+      {d->t2aa, oa * oa * va * va, "t2aa"}, {d->t2bb, ob * ob * vb * vb, "t2bb"},
+      {d->t2ab, oa * ob * va * vb, "t2ab"},
+      {d->Boo_a, Q * oa * oa, "Boo_a"}, {d->Bov_a, Q * oa * va, "Bov_a"}, {d->Bvv_a, Q * va * va, "Bvv_a"},
+      {d->Boo_b, Q * ob * ob, "Boo_b"}, {d->Bov_b, Q * ob * vb, "Bov_b"}, {d->Bvv_b, Q * vb * vb, "Bvv_b"},
+      {d->eo_a, oa, "eo_a"}, {d->ev_a, va, "ev_a"}, {d->eo_b, ob, "eo_b"}, {d->ev_b, vb, "ev_b"},
+      {d->fov_a, oa * va, "fov_a"}, {d->fov_b, ob * vb, "fov_b"}};
+  for (auto& x : ps)
+    if (x.n > 0 && !x.p) return fail(LT_EINVAL, "%s is NULL", x.name);
+  if ((va > 0 || vb > 0) && (oa + ob) >= 3 && Q == 0)
+    return fail(LT_ESHAPE, "naux = 0");
+  if (va > 46340 || vb > 46340 || oa > 4096 || ob > 4096)
+    return fail(LT_ESHAPE, "dimension too large");
+  if (o && o->items && o->n_items > 0) {
+    const int r = check_items(dims_of(d), o);
+    if (r) return r;
+  }
+  if (o && o->items == nullptr && o->n_items != 0)
+    return fail(LT_EINVAL, "n_items given without items");
+  return LT_OK;
+}
+
+// Items grouped by block: trip (p,q,r) and the caller-order index.
+struct ItemLists {
+  std::vector<int32_t> trip[4];
+  std::vector<int32_t> dst[4];
+  int64_t total = 0;
+};
+
+void build_items(const Dims& D, const ltriples_options* o, ItemLists& L) {
+  if (o && o->items) {
+    for (int32_t n = 0; n < o->n_items; ++n) {
+      const int32_t* it = o->items + 4 * n;
+      L.trip[it[0]].insert(L.trip[it[0]].end(), {it[1], it[2], it[3]});
+      L.dst[it[0]].push_back(n);
+    }
+    L.total = o->n_items;
+    return;
+  }
+  int32_t n = 0;
+  const int32_t oa = (int32_t)D.o[0], ob = (int32_t)D.o[1];
+  for (int32_t i = 0; i < oa; ++i)
+    for (int32_t j = i + 1; j < oa; ++j)
+      for (int32_t k = j + 1; k < oa; ++k) { L.trip[0].insert(L.trip[0].end(), {i, j, k}); L.dst[0].push_back(n++); }
+  for (int32_t i = 0; i < oa; ++i)
+    for (int32_t j = i + 1; j < oa; ++j)
+      for (int32_t k = 0; k < ob; ++k) { L.trip[1].insert(L.trip[1].end(), {i, j, k}); L.dst[1].push_back(n++); }
+  for (int32_t i = 0; i < ob; ++i)
+    for (int32_t j = i + 1; j < ob; ++j)
+      for (int32_t k = 0; k < oa; ++k) { L.trip[2].insert(L.trip[2].end(), {i, j, k}); L.dst[2].push_back(n++); }
+  for (int32_t i = 0; i < ob; ++i)
+    for (int32_t j = i + 1; j < ob; ++j)
+      for (int32_t k = j + 1; k < ob; ++k) { L.trip[3].insert(L.trip[3].end(), {i, j, k}); L.dst[3].push_back(n++); }
+  L.total = n;
+}
+
+int64_t count_all_items(const Dims& D) {
+  const int64_t oa = D.o[0], ob = D.o[1];
+  return oa * (oa - 1) * (oa - 2) / 6 + oa * (oa - 1) / 2 * ob + ob * (ob - 1) / 2 * oa +
+         ob * (ob - 1) * (ob - 2) / 6;
+}
+
+double item_flops(const Dims& D, int b) {
+  const int s = blk_sigma(b), t = 1 - s;
+  const double o = (double)D.o[s], v = (double)D.v[s], ot = (double)D.o[t], vt = (double)D.v[t];
+  if (!blk_mixed(b)) return 6 * v * v * v * v + 6 * v * v * v * o;
+  return 4 * v * v * vt * vt + 6 * v * v * v * vt + 4 * v * v * vt * ot + 6 * v * v * vt * o;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace plan
+// ---------------------------------------------------------------------------
+struct Buf { size_t off = 0, bytes = 0; };
+
+struct Plan {
+  int prec = 0;
+  size_t ts = 8;          // compute element size
+  Dims D;
+  int64_t n_blk[4] = {0, 0, 0, 0};
+  bool need_as[2] = {false, false};     // As, Tp, T2T, GamT, U of spin s
+  bool need_mix[2] = {false, false};    // mixed block with pair spin s
+  bool any_mix = false;
+  int64_t ldv[2], ldvv[2], ldnp[2], ldcb[2], ldov[2], ldoo[2];
+  // persistent
+  Buf BvvP[2], BovR[2], BovP64[2], BooP64[2];
+  Buf As[2], Tp[2], T2T[2], GamT[2], U[2];
+  Buf LmixT[2], Mst[2], Mts[2], Tmix[2], ZpT[2], TmT[2], OOT[2];
+  Buf OVab, e_items, trip, dst, order, firstcnt;
+  // scratch
+  Buf scratch;
+  size_t sc_OO[2][2], sc_OV[2];   // offsets within scratch (phase 1a)
+  int64_t nb[4];                  // items per batch
+  size_t per_item[4];             // batch bytes per item (T outputs)
+  size_t part_off[4];             // partials offset within scratch (phase 2)
+  int64_t ntile[4];
+  size_t total = 0;
+};
+
+void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options* o,
+                 const ItemLists& L, Plan& P) {
+  P.prec = prec;
+  P.ts = prec == LT_FP64 ? 8 : 4;
+  P.D = dims_of(d);
+  const Dims& D = P.D;
+  for (int b = 0; b < 4; ++b) P.n_blk[b] = (int64_t)L.dst[b].size();
+  for (int b = 0; b < 4; ++b)
+    if (P.n_blk[b] > 0) {
+      P.need_as[blk_sigma(b)] = true;
+      if (blk_mixed(b)) { P.need_mix[blk_sigma(b)] = true; P.any_mix = true; }
+    }
+  for (int s = 0; s < 2; ++s) {
+    P.ldv[s] = ld4(D.v[s]);
+    P.ldvv[s] = ld4(D.v[s] * D.v[s]);
+    P.ldnp[s] = ld4(npair(D.v[s]));
+    P.ldcb[s] = ld4(D.v[s] * D.v[1 - s]);
+    P.ldov[s] = ld4(D.o[s] * D.v[s]);
+    P.ldoo[s] = ld4(D.o[s] * D.o[s]);
+  }
+  size_t off = 0;
+  auto take = [&](Buf& b, size_t bytes) { b.off = off; b.bytes = bytes; off = align256(off + bytes); };
+  const size_t ts = P.ts;
+  const int64_t Q = D.Q;
+  for (int s = 0; s < 2; ++s) {
+    const bool need_df = P.need_as[s] || P.any_mix;
+    const int64_t os = D.o[s], vs = D.v[s];
+    if (need_df) {
+      take(P.BvvP[s], ts * Q * P.ldvv[s]);
+      take(P.BovR[s], ts * os * Q * P.ldv[s]);
+      take(P.BovP64[s], 8 * Q * P.ldov[s]);
+      take(P.BooP64[s], 8 * Q * P.ldoo[s]);
+    }
+    if (P.need_as[s]) {
+      take(P.As[s], ts * os * vs * P.ldnp[s]);
+      take(P.Tp[s], ts * os * os * P.ldnp[s]);
+      take(P.T2T[s], ts * os * os * vs * P.ldv[s]);
+      take(P.GamT[s], ts * os * os * os * P.ldv[s]);
+      take(P.U[s], 8 * os * os * vs * P.ldv[s]);
+    }
+    if (P.need_mix[s]) {
+      const int t = 1 - s;
+      const int64_t ot = D.o[t], vt = D.v[t];
+      take(P.LmixT[s], ts * os * ot * vt * P.ldv[s]);
+      take(P.Mst[s], ts * os * vt * P.ldcb[s]);
+      take(P.Mts[s], ts * ot * vs * P.ldcb[s]);
+      take(P.Tmix[s], ts * os * ot * P.ldcb[s]);
+      take(P.ZpT[s], ts * os * ot * ot * P.ldv[s]);
+      take(P.TmT[s], ts * os * ot * vs * P.ldv[t]);
+      take(P.OOT[s], ts * ot * os * os * P.ldv[t]);
+    }
+  }
+  if (P.any_mix) take(P.OVab, 8 * D.o[0] * D.v[0] * D.o[1] * D.v[1]);
+  take(P.e_items, 8 * 3 * std::max<int64_t>(L.total, 1));
+  take(P.trip, 4 * 3 * std::max<int64_t>(L.total, 1));
+  take(P.dst, 4 * std::max<int64_t>(L.total, 1));
+  take(P.order, 4 * std::max<int64_t>(L.total, 1));
+  take(P.firstcnt, 4 * 8);
+
+  // scratch, phase 1a: (ov|oo) classes and same-spin (ov|ov)
+  size_t s1a = 0;
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      const bool need = (x == y) ? P.need_as[x] : P.any_mix;
+      P.sc_OO[x][y] = s1a;
+      if (need) s1a = align256(s1a + 8 * (size_t)(D.o[x] * D.v[x] * D.o[y] * D.o[y]));
+    }
+  for (int s = 0; s < 2; ++s) {
+    P.sc_OV[s] = s1a;
+    if (P.need_as[s]) s1a = align256(s1a + 8 * (size_t)(D.o[s] * D.v[s] * D.o[s] * D.v[s]));
+  }
+  // phase 1b: (eb|ic) before pair packing
+  size_t s1b = 0;
+  for (int s = 0; s < 2; ++s)
+    if (P.need_as[s]) s1b = std::max(s1b, ts * (size_t)(D.o[s] * D.v[s] * D.v[s] * P.ldv[s]));
+  // phase 2: batch buffers + partials
+  const size_t budget = (o && o->batch_budget) ? o->batch_budget : (size_t(8) << 30);
+  size_t s2 = 0;
+  for (int b = 0; b < 4; ++b) {
+    P.nb[b] = 0; P.per_item[b] = 0; P.ntile[b] = 0; P.part_off[b] = 0;
+    if (P.n_blk[b] == 0) continue;
+    const int s = blk_sigma(b), t = 1 - s;
+    const int64_t vs = D.v[s], vt = D.v[t];
+    size_t outb;
+    int64_t nt;
+    if (!blk_mixed(b)) {
+      outb = ts * (size_t)(vs * P.ldnp[s]);
+      const int64_t n = cdiv(vs, lt::ET);
+      nt = n * (n + 1) * (n + 2) / 6;
+    } else {
+      outb = ts * (size_t)(vs * P.ldcb[s] + vt * P.ldnp[s]);
+      const int64_t ns = cdiv(vs, lt::ET), nt_ = cdiv(vt, lt::ET);
+      nt = ns * (ns + 1) / 2 * nt_;
+    }
+    P.ntile[b] = nt;
+    const size_t per = align256(outb) + align256(8 * 3 * (size_t)std::max<int64_t>(nt, 1));
+    P.per_item[b] = outb;
+    int64_t nb = (o && o->batch_items > 0) ? o->batch_items : (int64_t)std::max<size_t>(1, budget / per);
+    nb = std::min<int64_t>(nb, P.n_blk[b]);
+    nb = std::min<int64_t>(nb, 65535);
+    P.nb[b] = nb;
+    const size_t need = (size_t)nb * per + 1024;
+    s2 = std::max(s2, need);
+  }
+  const size_t sc = std::max(std::max(s1a, s1b), s2);
+  take(P.scratch, std::max<size_t>(sc, 256));
+  P.total = off;
+}
+
+void log_plan(const Plan& P) {
+  if (!getenv("LTRIPLES_LOG")) return;
+  fprintf(stderr, "[ltriples] plan prec=%d total=%zu bytes\n", P.prec, P.total);
+  const char* sp = "ab";
+  auto pr = [&](const char* n, int s, const Buf& b) {
+    if (b.bytes) fprintf(stderr, "[ltriples] buf %s_%c off=%zu bytes=%zu\n", n, sp[s], b.off, b.bytes);
+  };
+  for (int s = 0; s < 2; ++s) {
+    pr("BvvP", s, P.BvvP[s]); pr("BovR", s, P.BovR[s]); pr("BovP64", s, P.BovP64[s]); pr("BooP64", s, P.BooP64[s]);
+    pr("As", s, P.As[s]); pr("Tp", s, P.Tp[s]); pr("T2T", s, P.T2T[s]); pr("GamT", s, P.GamT[s]); pr("U", s, P.U[s]);
+    pr("LmixT", s, P.LmixT[s]); pr("Mst", s, P.Mst[s]); pr("Mts", s, P.Mts[s]); pr("Tmix", s, P.Tmix[s]);
+    pr("ZpT", s, P.ZpT[s]); pr("TmT", s, P.TmT[s]); pr("OOT", s, P.OOT[s]);
+  }
+  pr("OVab", 0, P.OVab);
+  pr("scratch", 0, P.scratch);
+  for (int b = 0; b < 4; ++b)
+    if (P.n_blk[b])
+      fprintf(stderr, "[ltriples] block %d items=%lld batch=%lld tiles=%lld\n", b, (long long)P.n_blk[b],
+              (long long)P.nb[b], (long long)P.ntile[b]);
+}
+
+template <typename T> T* at(void* ws, const Buf& b) { return (T*)((char*)ws + b.off); }
+
+// ---------------------------------------------------------------------------
+// Launch sequence
+// ---------------------------------------------------------------------------
+template <typename T>
+int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltriples_options* o,
+        double* e_out, double* parts, void* ws, hipStream_t st) {
+  const Dims& D = P.D;
+  const int64_t Q = D.Q;
+  const double* Bvv[2] = {d->Bvv_a, d->Bvv_b};
+  const double* Bov[2] = {d->Bov_a, d->Bov_b};
+  const double* Boo[2] = {d->Boo_a, d->Boo_b};
+  const double* T2ss[2] = {d->t2aa, d->t2bb};
+  const double* T1[2] = {d->t1a, d->t1b};
+  const double* Fov[2] = {d->fov_a, d->fov_b};
+  const double* EO[2] = {d->eo_a, d->eo_b};
+  const double* EV[2] = {d->ev_a, d->ev_b};
+  char* scr = (char*)ws + P.scratch.off;
+
+  // --- item arrays ---------------------------------------------------------
+  std::vector<int32_t> trip, dst;
+  int32_t fc[8];
+  for (int b = 0; b < 4; ++b) {
+    fc[b] = (int32_t)dst.size();
+    fc[4 + b] = (int32_t)L.dst[b].size();
+    trip.insert(trip.end(), L.trip[b].begin(), L.trip[b].end());
+    dst.insert(dst.end(), L.dst[b].begin(), L.dst[b].end());
+  }
+  int32_t* d_trip = at<int32_t>(ws, P.trip);
+  int32_t* d_dst = at<int32_t>(ws, P.dst);
+  int32_t* d_fc = at<int32_t>(ws, P.firstcnt);
+  if (!trip.empty()) {
+    HIPCHK(hipMemcpyAsync(d_trip, trip.data(), trip.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_dst, dst.data(), dst.size() * 4, hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(hipMemcpyAsync(d_fc, fc, sizeof(fc), hipMemcpyHostToDevice, st));
+  // host vectors must outlive the copies
+  HIPCHK(hipStreamSynchronize(st));
+  double* e_items = (o && o->e_items) ? o->e_items : at<double>(ws, P.e_items);
+
+  // --- 1. DF factor layouts --------------------------------------------------
+  for (int s = 0; s < 2; ++s) {
+    if (!P.BvvP[s].bytes) continue;
+    const int64_t os = D.o[s], vs = D.v[s];
+    HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.BvvP[s]), 0, 0, P.ldvv[s], 1, 1, Q, vs * vs,
+                                        Bvv[s], 0, 0, vs * vs, 1, nullptr, 0, 0, 0, 0, st));
+    HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.BovR[s]), 0, Q * P.ldv[s], P.ldv[s], 1, os, Q, vs,
+                                        Bov[s], 0, vs, os * vs, 1, nullptr, 0, 0, 0, 0, st));
+    HIPCHK(lt::launch_copy4d<double, double>(at<double>(ws, P.BovP64[s]), 0, 0, P.ldov[s], 1, 1, Q, os * vs,
+                                             Bov[s], 0, 0, os * vs, 1, nullptr, 0, 0, 0, 0, st));
+    HIPCHK(lt::launch_copy4d<double, double>(at<double>(ws, P.BooP64[s]), 0, 0, P.ldoo[s], 1, 1, Q, os * os,
+                                             Boo[s], 0, 0, os * os, 1, nullptr, 0, 0, 0, 0, st));
+  }
+
+  auto gemm64 = [&](int64_t M, int64_t N, const double* Lp, int64_t lks, const double* Rp, int64_t rks,
+                    double* out, int64_t ldo) -> hipError_t {
+    lt::GemmArgs<double> g{};
+    g.M = (int32_t)M; g.N = (int32_t)N; g.nbatch = 1; g.mode = 0;
+    g.out = out; g.s_mr = ldo; g.s_nr = 1;
+    g.L = Lp; g.lks = lks; g.R = Rp; g.rks = rks; g.K = (int32_t)Q;
+    return lt::launch_gemm<double>(g, st);
+  };
+
+  // --- 2. (ov|oo), (ov|ov) in FP64 and derived operands -----------------------
+  double* OO[2][2];
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      OO[x][y] = (double*)(scr + P.sc_OO[x][y]);
+      const bool need = (x == y) ? P.need_as[x] : P.any_mix;
+      if (!need) continue;
+      // OO_xy[k][a][m][j] = (ka|mj)
+      HIPCHK(gemm64(D.o[x] * D.v[x], D.o[y] * D.o[y], at<double>(ws, P.BovP64[x]), P.ldov[x],
+                    at<double>(ws, P.BooP64[y]), P.ldoo[y], OO[x][y], D.o[y] * D.o[y]));
+    }
+  for (int s = 0; s < 2; ++s) {
+    if (!P.need_as[s]) continue;
+    const int64_t o = D.o[s], v = D.v[s], lv = P.ldv[s];
+    double* OV = (double*)(scr + P.sc_OV[s]);
+    HIPCHK(gemm64(o * v, o * v, at<double>(ws, P.BovP64[s]), P.ldov[s], at<double>(ws, P.BovP64[s]),
+                  P.ldov[s], OV, o * v));
+    // U[q][r][y][z] = OV[q][y][r][z] - OV[q][z][r][y]
+    HIPCHK(lt::launch_copy4d<double, double>(at<double>(ws, P.U[s]), o * v * lv, v * lv, lv, o, o, v, v,
+                                             OV, v * o * v, v, o * v, 1, OV, v * o * v, v, 1, o * v, st));
+    // GamT[j][k][m][a] = OO[k][a][m][j] - OO[j][a][m][k]
+    const double* oo = OO[s][s];
+    HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.GamT[s]), o * o * lv, o * lv, lv, o, o, o, v,
+                                        oo, 1, v * o * o, o, o * o, oo, v * o * o, 1, o, o * o, st));
+  }
+  if (P.any_mix) {
+    const int64_t oa = D.o[0], va = D.v[0], ob = D.o[1], vb = D.v[1];
+    HIPCHK(gemm64(oa * va, ob * vb, at<double>(ws, P.BovP64[0]), P.ldov[0], at<double>(ws, P.BovP64[1]),
+                  P.ldov[1], at<double>(ws, P.OVab), ob * vb));
+  }
+  for (int s = 0; s < 2; ++s) {
+    if (!P.need_mix[s]) continue;
+    const int t = 1 - s;
+    const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
+    // ZpT[j][K][M][a] = OO_st[j][a][M][K]
+    HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.ZpT[s]), ot * ot * P.ldv[s], ot * P.ldv[s], P.ldv[s],
+                                        os, ot, ot, vs, OO[s][t], vs * ot * ot, 1, ot, ot * ot,
+                                        nullptr, 0, 0, 0, 0, st));
+    // OOT[K][j][m][C] = OO_ts[K][C][j][m]
+    HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.OOT[s]), os * os * P.ldv[t], os * P.ldv[t], P.ldv[t],
+                                        ot, os, os, vt, OO[t][s], vt * os * os, os, 1, os * os,
+                                        nullptr, 0, 0, 0, 0, st));
+  }
+
+  // --- 3. amplitude operands ----------------------------------------------------
+  const int64_t oa = D.o[0], ob = D.o[1], va = D.v[0], vb = D.v[1];
+  for (int s = 0; s < 2; ++s) {
+    if (!P.need_as[s]) continue;
+    const int64_t o = D.o[s], v = D.v[s], lv = P.ldv[s];
+    // T2T[i][j][e][a] = t2[i][j][a][e]
+    HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.T2T[s]), o * v * lv, v * lv, lv, o, o, v, v,
+                                        T2ss[s], o * v * v, v * v, 1, v, nullptr, 0, 0, 0, 0, st));
+    // Tp[i][m][p(a<b)] = t2[i][m][a][b]
+    HIPCHK(lt::launch_pack_pairs<double, T>(at<T>(ws, P.Tp[s]), P.ldnp[s], o * o, (int32_t)v, T2ss[s],
+                                            v * v, v, 1, false, st));
+  }
+  // mixed amplitude t^{xY}_{pQ} (p,x of pair spin; Q,Y of odd spin): strides (p, Q, x, Y)
+  int64_t mstr[2][4] = {{ob * va * vb, va * vb, vb, 1}, {va * vb, ob * va * vb, 1, vb}};
+  for (int s = 0; s < 2; ++s) {
+    if (!P.need_mix[s]) continue;
+    const int t = 1 - s;
+    const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
+    const int64_t* m = mstr[s];
+    // LmixT[i][K][E][a] = t^{aE}_{iK}
+    HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.LmixT[s]), ot * vt * P.ldv[s], vt * P.ldv[s], P.ldv[s],
+                                        os, ot, vt, vs, d->t2ab, m[0], m[1], m[3], m[2], nullptr, 0, 0, 0, 0, st));
+    // Tmix[i][K][C*vs+b] = t^{bC}_{iK}
+    HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.Tmix[s]), ot * P.ldcb[s], P.ldcb[s], vs,
+                                        os, ot, vt, vs, d->t2ab, m[0], m[1], m[3], m[2], nullptr, 0, 0, 0, 0, st));
+    // TmT[i][K][e][C] = t^{eC}_{iK}
+    HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.TmT[s]), ot * vs * P.ldv[t], vs * P.ldv[t], P.ldv[t],
+                                        os, ot, vs, vt, d->t2ab, m[0], m[1], m[2], m[3], nullptr, 0, 0, 0, 0, st));
+  }
+
+  // --- 4. (ov|vv) slabs ------------------------------------------------------------
+  auto gemmT = [&](int64_t M, int64_t N, int64_t nbatch, const T* Lp, int64_t lks, int64_t lbs, const T* Rp,
+                   int64_t rks, int64_t rbs, T* out, int64_t obs, int64_t s_mq, int64_t s_mr, int32_t mdiv,
+                   int64_t s_nq, int64_t s_nr, int32_t ndiv) -> hipError_t {
+    lt::GemmArgs<T> g{};
+    g.M = (int32_t)M; g.N = (int32_t)N; g.nbatch = (int32_t)nbatch; g.mode = 0;
+    g.out = out; g.obs = obs; g.s_mq = s_mq; g.s_mr = s_mr; g.mdiv = mdiv; g.s_nq = s_nq; g.s_nr = s_nr; g.ndiv = ndiv;
+    g.L = Lp; g.lks = lks; g.lbs = lbs; g.R = Rp; g.rks = rks; g.rbs = rbs; g.K = (int32_t)Q;
+    return lt::launch_gemm<T>(g, st);
+  };
+  for (int s = 0; s < 2; ++s) {
+    if (!P.need_as[s]) continue;
+    const int64_t o = D.o[s], v = D.v[s], lv = P.ldv[s];
+    T* Kx = (T*)scr;
+    // Kx[i][(e,b)][c] = (eb|ic)
+    HIPCHK(gemmT(v * v, v, o, at<T>(ws, P.BvvP[s]), P.ldvv[s], 0, at<T>(ws, P.BovR[s]), lv, Q * lv,
+                 Kx, v * v * lv, 0, lv, 0, 0, 1, 0));
+    // As[i][e][p(b<c)] = Kx[i][e][b][c] - Kx[i][e][c][b]
+    HIPCHK(lt::launch_pack_pairs<T, T>(at<T>(ws, P.As[s]), P.ldnp[s], o * v, (int32_t)v, Kx, v * lv, lv, 1,
+                                       true, st));
+  }
+  for (int s = 0; s < 2; ++s) {
+    if (!P.need_mix[s]) continue;
+    const int t = 1 - s;
+    const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t], lc = P.ldcb[s];
+    // Mst[j][E][C*vs+b] = (jb|EC): rows (E,C), cols b
+    HIPCHK(gemmT(vt * vt, vs, os, at<T>(ws, P.BvvP[t]), P.ldvv[t], 0, at<T>(ws, P.BovR[s]), P.ldv[s],
+                 Q * P.ldv[s], at<T>(ws, P.Mst[s]), vt * lc, lc, vs, (int32_t)vt, 0, 1, 0));
+    // Mts[K][e][C*vs+b] = (be|KC): rows C, cols (e,b)
+    HIPCHK(gemmT(vt, vs * vs, ot, at<T>(ws, P.BovR[t]), P.ldv[t], Q * P.ldv[t], at<T>(ws, P.BvvP[s]),
+                 P.ldvv[s], 0, at<T>(ws, P.Mts[s]), vs * lc, 0, vs, 0, lc, 1, (int32_t)vs));
+  }
+
+  // --- 5. triplet batches --------------------------------------------------------------
+  for (int b = 0; b < 4; ++b) {
+    const int64_t nblk = P.n_blk[b];
+    if (nblk == 0) continue;
+    const int s = blk_sigma(b), t = 1 - s;
+    const bool mixed = blk_mixed(b);
+    const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
+    lt::ItemOps<T> ops{};
+    ops.o_s = (int32_t)os; ops.v_s = (int32_t)vs; ops.o_t = (int32_t)ot; ops.v_t = (int32_t)vt;
+    ops.ld_vs = P.ldv[s]; ops.ld_vt = P.ldv[t]; ops.ld_np = P.ldnp[s]; ops.ld_cb = P.ldcb[s];
+    ops.T2T = at<T>(ws, P.T2T[s]); ops.Tp = at<T>(ws, P.Tp[s]); ops.As = at<T>(ws, P.As[s]);
+    ops.GamT = at<T>(ws, P.GamT[s]);
+    if (mixed) {
+      ops.LmixT = at<T>(ws, P.LmixT[s]); ops.Mst = at<T>(ws, P.Mst[s]); ops.Mts = at<T>(ws, P.Mts[s]);
+      ops.Tmix = at<T>(ws, P.Tmix[s]); ops.ZpT = at<T>(ws, P.ZpT[s]); ops.TmT = at<T>(ws, P.TmT[s]);
+      ops.OOT = at<T>(ws, P.OOT[s]);
+    }
+    const int64_t nb = P.nb[b];
+    T* out1 = (T*)scr;
+    const size_t o1 = align256(P.ts * (size_t)(mixed ? vs * P.ldcb[s] : vs * P.ldnp[s]));
+    T* out2 = (T*)(scr + (size_t)nb * o1);
+    const size_t o2 = mixed ? align256(P.ts * (size_t)(vt * P.ldnp[s])) : 0;
+    double* part = (double*)(scr + (size_t)nb * (o1 + o2));
+    const int64_t nt = P.ntile[b];
+    for (int64_t first = 0; first < nblk; first += nb) {
+      const int64_t n = std::min<int64_t>(nb, nblk - first);
+      const int32_t* items = d_trip + 3 * (fc[b] + first);
+      ops.items = items;
+      lt::GemmArgs<T> g{};
+      g.nbatch = (int32_t)n; g.mode = 1; g.s_nr = 1;
+      if (!mixed) {
+        ops.kind = 0;
+        g.M = (int32_t)vs; g.N = (int32_t)npair(vs); g.out = out1; g.obs = (int64_t)(o1 / P.ts); g.s_mr = P.ldnp[s];
+        g.ops = ops;
+        HIPCHK(lt::launch_gemm<T>(g, st));
+        lt::EpiSame<T> e{};
+        e.o = (int32_t)os; e.v = (int32_t)vs; e.ld_np = P.ldnp[s];
+        e.S = out1; e.s_item = (int64_t)(o1 / P.ts); e.items = items;
+        e.nt = (int32_t)cdiv(vs, lt::ET); e.ntri = (int32_t)nt;
+        e.eo = EO[s]; e.ev = EV[s]; e.t1 = T1[s]; e.f = Fov[s]; e.t2 = T2ss[s];
+        e.U = at<double>(ws, P.U[s]); e.ld_v = P.ldv[s]; e.part = part;
+        HIPCHK(lt::launch_epi_same<T>(e, (int32_t)n, st));
+      } else {
+        ops.kind = 1;
+        g.M = (int32_t)vs; g.N = (int32_t)(vt * vs); g.out = out1; g.obs = (int64_t)(o1 / P.ts); g.s_mr = P.ldcb[s];
+        g.ops = ops;
+        HIPCHK(lt::launch_gemm<T>(g, st));
+        ops.kind = 2;
+        g.M = (int32_t)vt; g.N = (int32_t)npair(vs); g.out = out2; g.obs = (int64_t)(o2 / P.ts); g.s_mr = P.ldnp[s];
+        g.ops = ops;
+        HIPCHK(lt::launch_gemm<T>(g, st));
+        lt::EpiMixed<T> e{};
+        e.o_s = (int32_t)os; e.v_s = (int32_t)vs; e.o_t = (int32_t)ot; e.v_t = (int32_t)vt;
+        e.ld_np = P.ldnp[s]; e.ld_cb = P.ldcb[s];
+        e.G = out1; e.g_item = (int64_t)(o1 / P.ts); e.Y = out2; e.y_item = (int64_t)(o2 / P.ts);
+        e.items = items;
+        e.nts = (int32_t)cdiv(vs, lt::ET); e.ntt = (int32_t)cdiv(vt, lt::ET); e.ntiles = (int32_t)nt;
+        e.eo_s = EO[s]; e.ev_s = EV[s]; e.eo_t = EO[t]; e.ev_t = EV[t];
+        e.t1_s = T1[s]; e.t1_t = T1[t]; e.f_s = Fov[s]; e.f_t = Fov[t]; e.t2ss = T2ss[s];
+        e.U = at<double>(ws, P.U[s]); e.ld_vs = P.ldv[s];
+        const double* ovab = at<double>(ws, P.OVab);
+        // OVab[i_a][a_a][J_b][B_b]
+        const int64_t so[4] = {va * ob * vb, ob * vb, vb, 1};   // (occ_a, vir_a, occ_b, vir_b)
+        e.ov = ovab;
+        if (s == 0) { e.ov_o = so[0]; e.ov_v = so[1]; e.ov_O = so[2]; e.ov_V = so[3]; }
+        else { e.ov_o = so[2]; e.ov_v = so[3]; e.ov_O = so[0]; e.ov_V = so[1]; }
+        e.tm = d->t2ab; e.tm_o = mstr[s][0]; e.tm_v = mstr[s][2]; e.tm_O = mstr[s][1]; e.tm_V = mstr[s][3];
+        e.part = part;
+        HIPCHK(lt::launch_epi_mixed<T>(e, (int32_t)n, st));
+      }
+      HIPCHK(lt::launch_reduce_items(part, (int32_t)n, (int32_t)nt, d_dst + fc[b] + first, e_items, st));
+    }
+  }
+
+  // --- 6. totals ----------------------------------------------------------------------
+  HIPCHK(lt::launch_reduce_final(e_items, d_dst, d_fc, d_fc + 4, parts, e_out, st));
+  (void)ob;
+  return LT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ltriples_validate(const ltriples_domain* d, int32_t precision, const ltriples_options* o) {
+  g_err.clear();
+  return validate(d, precision, o);
+}
+
+int ltriples_workspace_size(const ltriples_domain* d, int32_t precision, const ltriples_options* o,
+                            size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(LT_EINVAL, "bytes is NULL");
+  const int r = validate(d, precision, o);
+  if (r) return r;
+  ItemLists L;
+  build_items(dims_of(d), o, L);
+  Plan P;
+  plan_domain(d, precision, o, L, P);
+  *bytes = P.total;
+  return LT_OK;
+}
+
+int ltriples_flops(const ltriples_domain* d, const ltriples_options* o, double* flops, int64_t* n_items_out) {
+  g_err.clear();
+  if (!d || !flops) return fail(LT_EINVAL, "NULL argument");
+  const Dims D = dims_of(d);
+  if (o && o->items) {
+    const int r = check_items(D, o);
+    if (r) return r;
+    double f = 0;
+    for (int32_t n = 0; n < o->n_items; ++n) f += item_flops(D, o->items[4 * n]);
+    *flops = f;
+    if (n_items_out) *n_items_out = o->n_items;
+    return LT_OK;
+  }
+  const int64_t oa = D.o[0], ob = D.o[1];
+  const int64_t cnt[4] = {oa * (oa - 1) * (oa - 2) / 6, oa * (oa - 1) / 2 * ob, ob * (ob - 1) / 2 * oa,
+                          ob * (ob - 1) * (ob - 2) / 6};
+  double f = 0;
+  for (int b = 0; b < 4; ++b) f += (double)cnt[b] * item_flops(D, b);
+  *flops = f;
+  if (n_items_out) *n_items_out = count_all_items(D);
+  return LT_OK;
+}
+
+int ltriples_energy(const ltriples_domain* d, int32_t precision, const ltriples_options* o, double* e_out,
+                    double* parts, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int r = validate(d, precision, o);
+  if (r) return r;
+  if (!e_out) return fail(LT_EINVAL, "e_out is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  const Dims D = dims_of(d);
+
+  // denominators: every occupied energy below every virtual energy, all finite
+  {
+    double omax = -INFINITY, vmin = INFINITY;
+    for (int s = 0; s < 2; ++s) {
+      const double* eo = s ? d->eo_b : d->eo_a;
+      const double* ev = s ? d->ev_b : d->ev_a;
+      std::vector<double> ho(D.o[s]), hv(D.v[s]);
+      if (D.o[s]) HIPCHK(hipMemcpy(ho.data(), eo, 8 * D.o[s], hipMemcpyDeviceToHost));
+      if (D.v[s]) HIPCHK(hipMemcpy(hv.data(), ev, 8 * D.v[s], hipMemcpyDeviceToHost));
+      for (double x : ho) { if (!std::isfinite(x)) return fail(LT_ENONFINITE, "non-finite occupied energy"); omax = std::max(omax, x); }
+      for (double x : hv) { if (!std::isfinite(x)) return fail(LT_ENONFINITE, "non-finite virtual energy"); vmin = std::min(vmin, x); }
+    }
+    if (omax >= vmin) return fail(LT_EDENOM, "max occupied energy %.6g >= min virtual energy %.6g", omax, vmin);
+  }
+
+  ItemLists L;
+  build_items(D, o, L);
+  Plan P;
+  plan_domain(d, precision, o, L, P);
+  log_plan(P);
+  bool own = false;
+  if (ws == nullptr) {
+    HIPCHK(hipMalloc(&ws, P.total));
+    own = true;
+  } else if (ws_bytes < P.total) {
+    return fail(LT_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, P.total);
+  }
+  if (o && o->e_items && L.total > 0) HIPCHK(lt::launch_zero(o->e_items, 3 * L.total, st));
+  HIPCHK(lt::launch_zero(at<double>(ws, P.e_items), 3 * std::max<int64_t>(L.total, 1), st));
+  if (L.total == 0 || (D.v[0] == 0 && D.v[1] == 0)) {
+    HIPCHK(lt::launch_zero(e_out, 1, st));
+    if (parts) HIPCHK(lt::launch_zero(parts, 12, st));
+    if (own) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(ws)); }
+    return LT_OK;
+  }
+  if (precision == LT_FP64) r = run<double>(d, P, L, o, e_out, parts, ws, st);
+  else r = run<float>(d, P, L, o, e_out, parts, ws, st);
+  if (own) {
+    hipError_t e1 = hipStreamSynchronize(st);
+    hipError_t e2 = hipFree(ws);
+    if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) return fail(LT_EHIP, "HIP error at workspace release");
+  }
+  return r;
+}
+
+const char* ltriples_last_error(void) { return g_err.c_str(); }
+
+const char* ltriples_version(void) { return "ltriples 0.1.0 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,312 @@
+// FP64 energy epilogue of the triples path.
+//
+// For one occupied triplet the contraction GEMMs leave, per output layout,
+//   same spin:  S[a][p(b<c)]            W^{abc} = S[a][bc] - S[b][ac] + S[c][ab]   (a<b<c)
+//   mixed:      G[a][C*v+b], Y[C][p(a<b)]  W^{abC} = G[a][Cb] - G[b][Ca] + Y[C][ab] (a<b)
+// (the virtual permutation operator P(a/bc) resp. P(ab) applied by reading
+// the intermediates at permuted indices).  A work-group takes a 16^3 tile of
+// the unique virtual range, stages the permuted reads and the small FP64 V
+// ingredients in LDS, forms W, V = V_t1 + V_f, D = e_i+e_j+e_k-e_a-e_b-e_c and
+// accumulates W*W/D, W*V_t1/D, W*V_f/D in FP64, reduced over the wave by
+// shuffles and over the work-group in LDS in a fixed order.  Each tile
+// writes its own partial, so the later per-item sums are independent of
+// scheduling.
+#include "lt_internal.h"
+
+namespace lt {
+
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+__device__ inline void block_write3(double e4, double est, double edt, double* dst) {
+  __shared__ double red[4][3];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  e4 = wave_sum(e4); est = wave_sum(est); edt = wave_sum(edt);
+  if (lane == 0) { red[wave][0] = e4; red[wave][1] = est; red[wave][2] = edt; }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int q = threadIdx.x;
+    dst[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+  }
+}
+
+// tile triples A <= B <= C ordered by C, then B, then A
+__device__ inline void tri_decode(int t, int& A, int& B, int& C) {
+  int c = 0;
+  while ((c + 1) * (c + 2) * (c + 3) / 6 <= t) ++c;
+  t -= c * (c + 1) * (c + 2) / 6;
+  int b = 0;
+  while ((b + 1) * (b + 2) / 2 <= t) ++b;
+  t -= b * (b + 1) / 2;
+  A = t; B = b; C = c;
+}
+
+constexpr int SROW = ET * ET + 1;   // padded LDS row for [ta][tc*16+tb]
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_epi_same(EpiSame<T> a) {
+  __shared__ T Sb[ET][SROW];        // S[b][p(a,c)]
+  __shared__ T Sc[ET][SROW];        // S[c][p(a,b)]
+  __shared__ double Uac[3][ET][ET + 1], Uba[3][ET][ET + 1], Tac[3][ET][ET + 1], Tba[3][ET][ET + 1];
+  __shared__ double t1a[3][ET], fa[3][ET], eva[ET];
+
+  const int tid = threadIdx.x;
+  int TA, TB, TC;
+  tri_decode(blockIdx.x, TA, TB, TC);
+  const int item = blockIdx.y;
+  const int32_t* it = a.items + 3 * item;
+  const int occ[3] = {it[0], it[1], it[2]};
+  const int v = a.v;
+  const int a0 = TA * ET, b0 = TB * ET, c0 = TC * ET;
+  const T* S = a.S + (int64_t)item * a.s_item;
+  const int64_t ldp = a.ld_np;
+  // occupied pair (q, r), sign and t1 index of the three occupied permutations
+  const int pq[3] = {occ[1], occ[0], occ[1]};
+  const int pr[3] = {occ[2], occ[2], occ[0]};
+  const double sg[3] = {1.0, -1.0, -1.0};
+  const int64_t vv = (int64_t)v * v;
+
+  for (int e = tid; e < ET * ET * ET; e += 256) {
+    const int ta = e & 15, tb = (e >> 4) & 15, tc = e >> 8;
+    const int aa = a0 + ta, bb = b0 + tb, cc = c0 + tc;
+    T x = 0, y = 0;
+    if (cc < v && bb < v) {
+      if (aa < cc) x = S[bb * ldp + (int64_t)cc * (cc - 1) / 2 + aa];
+      if (aa < bb) y = S[cc * ldp + (int64_t)bb * (bb - 1) / 2 + aa];
+    }
+    Sb[ta][tc * ET + tb] = x;
+    Sc[ta][tc * ET + tb] = y;
+  }
+  for (int e = tid; e < 3 * ET * ET; e += 256) {
+    const int pp = e / (ET * ET), r = e % (ET * ET), ta = r & 15, tx = r >> 4;
+    const int aa = a0 + ta, cc = c0 + tx, bb = b0 + tx;
+    const int64_t ub = ((int64_t)pq[pp] * a.o + pr[pp]) * v * a.ld_v;
+    const int64_t tb_ = ((int64_t)pq[pp] * a.o + pr[pp]) * vv;
+    const bool ac = aa < v && cc < v, ba = aa < v && bb < v;
+    Uac[pp][ta][tx] = ac ? a.U[ub + aa * a.ld_v + cc] : 0.0;
+    Tac[pp][ta][tx] = ac ? a.t2[tb_ + aa * v + cc] : 0.0;
+    Uba[pp][tx][ta] = ba ? a.U[ub + bb * a.ld_v + aa] : 0.0;
+    Tba[pp][tx][ta] = ba ? a.t2[tb_ + bb * v + aa] : 0.0;
+  }
+  if (tid < 3 * ET) {
+    const int pp = tid / ET, ta = tid % ET, aa = a0 + ta;
+    t1a[pp][ta] = aa < v ? a.t1[(int64_t)occ[pp] * v + aa] : 0.0;
+    fa[pp][ta] = aa < v ? a.f[(int64_t)occ[pp] * v + aa] : 0.0;
+  } else if (tid < 4 * ET) {
+    const int ta = tid - 3 * ET, aa = a0 + ta;
+    eva[ta] = aa < v ? a.ev[aa] : 0.0;
+  }
+  __syncthreads();
+
+  const int tb = tid & 15, tc = tid >> 4;
+  const int b = b0 + tb, c = c0 + tc;
+  double e4 = 0.0, est = 0.0, edt = 0.0;
+  if (b < c && c < v) {
+    double Ubc[3], Tbc[3], t1b[3], fb[3], t1c[3], fc[3];
+#pragma unroll
+    for (int pp = 0; pp < 3; ++pp) {
+      const int64_t blk = (int64_t)pq[pp] * a.o + pr[pp];
+      Ubc[pp] = sg[pp] * a.U[blk * v * a.ld_v + b * a.ld_v + c];
+      Tbc[pp] = sg[pp] * a.t2[blk * vv + (int64_t)b * v + c];
+      t1b[pp] = sg[pp] * a.t1[(int64_t)occ[pp] * v + b];
+      fb[pp] = sg[pp] * a.f[(int64_t)occ[pp] * v + b];
+      t1c[pp] = sg[pp] * a.t1[(int64_t)occ[pp] * v + c];
+      fc[pp] = sg[pp] * a.f[(int64_t)occ[pp] * v + c];
+    }
+    const double dbc = (a.eo[occ[0]] + a.eo[occ[1]] + a.eo[occ[2]]) - a.ev[b] - a.ev[c];
+    const T* Srow = S + (int64_t)c * (c - 1) / 2 + b;
+    const int na = min(ET, b - a0);
+    for (int ta = 0; ta < na; ++ta) {
+      const int aa = a0 + ta;
+      const double w = (double)Srow[aa * ldp] - (double)Sb[ta][tc * ET + tb] + (double)Sc[ta][tc * ET + tb];
+      double vt = 0.0, vf = 0.0;
+#pragma unroll
+      for (int pp = 0; pp < 3; ++pp) {
+        vt += t1a[pp][ta] * Ubc[pp] - t1b[pp] * Uac[pp][ta][tc] - t1c[pp] * Uba[pp][tb][ta];
+        vf += fa[pp][ta] * Tbc[pp] - fb[pp] * Tac[pp][ta][tc] - fc[pp] * Tba[pp][tb][ta];
+      }
+      // t1a/fa carry no sign: fold the occupied-permutation sign of the first term here
+      const double d = dbc - eva[ta];
+      const double wd = w / d;
+      e4 += wd * w;
+      est += wd * vt;
+      edt += wd * vf;
+    }
+  }
+  block_write3(e4, est, edt, a.part + ((int64_t)item * a.ntri + blockIdx.x) * 3);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_epi_mixed(EpiMixed<T> a) {
+  __shared__ T Gb[ET][SROW];        // G[b][C*v+a]
+  __shared__ T Yl[ET][SROW];        // Y[C][p(a,b)]
+  __shared__ double OVj[ET][ET + 1], OVi[ET][ET + 1], Tmj[ET][ET + 1], Tmi[ET][ET + 1];
+  __shared__ double Uab[ET][ET + 1], T2ab[ET][ET + 1];
+  __shared__ double t1ai[ET], t1aj[ET], fai[ET], faj[ET], eva[ET];
+
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x;
+  const int TC = tile % a.ntt, pi = tile / a.ntt;
+  int TB = 0;
+  while ((TB + 1) * (TB + 2) / 2 <= pi) ++TB;
+  const int TA = pi - TB * (TB + 1) / 2;
+  const int item = blockIdx.y;
+  const int32_t* it = a.items + 3 * item;
+  const int i = it[0], j = it[1], K = it[2];
+  const int vs = a.v_s, vt = a.v_t;
+  const int a0 = TA * ET, b0 = TB * ET, c0 = TC * ET;
+  const T* G = a.G + (int64_t)item * a.g_item;
+  const T* Y = a.Y + (int64_t)item * a.y_item;
+  const int64_t lc = a.ld_cb, lp = a.ld_np;
+
+  for (int e = tid; e < ET * ET * ET; e += 256) {
+    const int ta = e & 15, tb = (e >> 4) & 15, tc = e >> 8;
+    const int aa = a0 + ta, bb = b0 + tb, cc = c0 + tc;
+    T x = 0, y = 0;
+    if (aa < vs && bb < vs && cc < vt) {
+      x = G[bb * lc + (int64_t)cc * vs + aa];
+      if (aa < bb) y = Y[cc * lp + (int64_t)bb * (bb - 1) / 2 + aa];
+    }
+    Gb[ta][tc * ET + tb] = x;
+    Yl[ta][tc * ET + tb] = y;
+  }
+  for (int e = tid; e < ET * ET; e += 256) {
+    const int ta = e & 15, tx = e >> 4;
+    const int aa = a0 + ta, cc = c0 + tx, bb = b0 + tx;
+    const bool ac = aa < vs && cc < vt, ab = aa < vs && bb < vs;
+    OVj[ta][tx] = ac ? a.ov[j * a.ov_o + aa * a.ov_v + K * a.ov_O + cc * a.ov_V] : 0.0;
+    OVi[ta][tx] = ac ? a.ov[i * a.ov_o + aa * a.ov_v + K * a.ov_O + cc * a.ov_V] : 0.0;
+    Tmj[ta][tx] = ac ? a.tm[j * a.tm_o + aa * a.tm_v + K * a.tm_O + cc * a.tm_V] : 0.0;
+    Tmi[ta][tx] = ac ? a.tm[i * a.tm_o + aa * a.tm_v + K * a.tm_O + cc * a.tm_V] : 0.0;
+    const int64_t ij = (int64_t)i * a.o_s + j;
+    Uab[tx][ta] = ab ? a.U[(ij * vs + aa) * a.ld_vs + bb] : 0.0;
+    T2ab[tx][ta] = ab ? a.t2ss[(ij * vs + aa) * vs + bb] : 0.0;
+  }
+  if (tid < ET) {
+    const int aa = a0 + tid;
+    const bool ok = aa < vs;
+    t1ai[tid] = ok ? a.t1_s[(int64_t)i * vs + aa] : 0.0;
+    t1aj[tid] = ok ? a.t1_s[(int64_t)j * vs + aa] : 0.0;
+    fai[tid] = ok ? a.f_s[(int64_t)i * vs + aa] : 0.0;
+    faj[tid] = ok ? a.f_s[(int64_t)j * vs + aa] : 0.0;
+    eva[tid] = ok ? a.ev_s[aa] : 0.0;
+  }
+  __syncthreads();
+
+  const int tb = tid & 15, tc = tid >> 4;
+  const int b = b0 + tb, C = c0 + tc;
+  double e4 = 0.0, est = 0.0, edt = 0.0;
+  if (b < vs && C < vt) {
+    const double OVjb = a.ov[j * a.ov_o + b * a.ov_v + K * a.ov_O + C * a.ov_V];
+    const double OVib = a.ov[i * a.ov_o + b * a.ov_v + K * a.ov_O + C * a.ov_V];
+    const double Tmjb = a.tm[j * a.tm_o + b * a.tm_v + K * a.tm_O + C * a.tm_V];
+    const double Tmib = a.tm[i * a.tm_o + b * a.tm_v + K * a.tm_O + C * a.tm_V];
+    const double t1bi = a.t1_s[(int64_t)i * vs + b], t1bj = a.t1_s[(int64_t)j * vs + b];
+    const double fbi = a.f_s[(int64_t)i * vs + b], fbj = a.f_s[(int64_t)j * vs + b];
+    const double t1C = a.t1_t[(int64_t)K * vt + C], fC = a.f_t[(int64_t)K * vt + C];
+    const double dbc = (a.eo_s[i] + a.eo_s[j] + a.eo_t[K]) - a.ev_s[b] - a.ev_t[C];
+    const T* Grow = G + (int64_t)C * vs + b;
+    const int na = min(ET, b - a0);
+    for (int ta = 0; ta < na; ++ta) {
+      const int aa = a0 + ta;
+      const double w = (double)Grow[aa * lc] - (double)Gb[ta][tc * ET + tb] + (double)Yl[ta][tc * ET + tb];
+      const double vt1 = t1ai[ta] * OVjb - t1aj[ta] * OVib - t1bi * OVj[ta][tc] + t1bj * OVi[ta][tc]
+                         + t1C * Uab[tb][ta];
+      const double vfo = fai[ta] * Tmjb - faj[ta] * Tmib - fbi * Tmj[ta][tc] + fbj * Tmi[ta][tc]
+                         + fC * T2ab[tb][ta];
+      const double d = dbc - eva[ta];
+      const double wd = w / d;
+      e4 += wd * w;
+      est += wd * vt1;
+      edt += wd * vfo;
+    }
+  }
+  block_write3(e4, est, edt, a.part + ((int64_t)item * a.ntiles + tile) * 3);
+}
+
+template <typename T>
+hipError_t launch_epi_same(const EpiSame<T>& a, int32_t nitems, hipStream_t s) {
+  if (nitems <= 0 || a.ntri <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_epi_same<T>), dim3(a.ntri, nitems), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_epi_mixed(const EpiMixed<T>& a, int32_t nitems, hipStream_t s) {
+  if (nitems <= 0 || a.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_epi_mixed<T>), dim3(a.ntiles, nitems), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_epi_same<float>(const EpiSame<float>&, int32_t, hipStream_t);
+template hipError_t launch_epi_same<double>(const EpiSame<double>&, int32_t, hipStream_t);
+template hipError_t launch_epi_mixed<float>(const EpiMixed<float>&, int32_t, hipStream_t);
+template hipError_t launch_epi_mixed<double>(const EpiMixed<double>&, int32_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions
+// ---------------------------------------------------------------------------
+__device__ inline void tree3(double* sh, double& x0, double& x1, double& x2) {
+  const int t = threadIdx.x;
+  sh[t] = x0; sh[256 + t] = x1; sh[512 + t] = x2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      sh[t] += sh[t + w];
+      sh[256 + t] += sh[256 + t + w];
+      sh[512 + t] += sh[512 + t + w];
+    }
+    __syncthreads();
+  }
+  x0 = sh[0]; x1 = sh[256]; x2 = sh[512];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_reduce_items(const double* part, int32_t ntiles,
+                                                      const int32_t* dst, double* e_items) {
+  __shared__ double sh[768];
+  const int item = blockIdx.x;
+  const double* p = part + (int64_t)item * ntiles * 3;
+  double x0 = 0, x1 = 0, x2 = 0;
+  for (int t = threadIdx.x; t < ntiles; t += 256) { x0 += p[3 * t]; x1 += p[3 * t + 1]; x2 += p[3 * t + 2]; }
+  tree3(sh, x0, x1, x2);
+  if (threadIdx.x == 0) {
+    double* d = e_items + 3 * (int64_t)dst[item];
+    d[0] = x0; d[1] = x1; d[2] = x2;
+  }
+}
+
+hipError_t launch_reduce_items(const double* part, int32_t nitems, int32_t ntiles,
+                               const int32_t* dst, double* e_items, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_items, dim3(nitems), dim3(256), 0, s, part, ntiles, dst, e_items);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_reduce_final(const double* e_items, const int32_t* order,
+                                                      const int32_t* first, const int32_t* count,
+                                                      double* parts, double* e_out) {
+  __shared__ double sh[768];
+  double tot = 0.0;
+  for (int blk = 0; blk < 4; ++blk) {
+    double x0 = 0, x1 = 0, x2 = 0;
+    for (int n = threadIdx.x; n < count[blk]; n += 256) {
+      const double* e = e_items + 3 * (int64_t)order[first[blk] + n];
+      x0 += e[0]; x1 += e[1]; x2 += e[2];
+    }
+    tree3(sh, x0, x1, x2);
+    if (threadIdx.x == 0 && parts) { parts[3 * blk] = x0; parts[3 * blk + 1] = x1; parts[3 * blk + 2] = x2; }
+    tot += (x0 + x1) + x2;
+  }
+  if (threadIdx.x == 0) e_out[0] = tot;
+}
+
+hipError_t launch_reduce_final(const double* e_items, const int32_t* order,
+                               const int32_t* first, const int32_t* count,
+                               double* parts, double* e_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, e_items, order, first, count, parts, e_out);
+  return hipGetLastError();
+}
+
+}  // namespace lt

@@ -1,0 +1,245 @@
+// Segmented, k-major MFMA GEMM for gfx950.
+//
+//   C[m][n] = sum_s sign_s sum_k Lt_s[k][m] R_s[k][n]
+//
+// Used for (a) the density-fitting builds of the (ov|vv), (ov|oo) and
+// (ov|ov) integral classes (one segment, K = naux) and (b) the triples
+// contractions of one occupied triplet, where the segments are the terms of
+// the spin-block working equations that share an output layout (the
+// occupied permutations P(i/jk) / P(ij) concatenated along K).
+//
+// Tiling: a work-group of 4 waves owns a BM x BN output tile, BM = MB row
+// blocks of the MFMA shape (the whole virtual range of a triplet GEMM for
+// MB <= 16), BN = 4 column blocks (one per wave).  K advances in chunks of
+// 16 staged through double-buffered LDS; every global load is a 16-byte
+// vector along a contiguous operand row.  Work-groups are renumbered so that
+// consecutive logical tiles run on the same XCD (the dispatcher deals
+// work-groups round-robin over the 8 XCDs), which keeps a triplet's small
+// L operand and an R-operand tile shared by the row tiles in one L2.
+#include "lt_internal.h"
+
+namespace lt {
+
+// Segment idx of the contraction of one occupied triplet (i, j, k); all
+// arguments are wave-uniform, so the descriptor lives in scalar registers.
+template <typename T>
+__device__ inline Seg<T> item_seg(const ItemOps<T>& s, int64_t i, int64_t j, int64_t k, int idx) {
+  const int64_t o = s.o_s, v = s.v_s, ot = s.o_t, vt = s.v_t;
+  const int64_t lv = s.ld_vs, lt_ = s.ld_vt, lp = s.ld_np, lc = s.ld_cb;
+  if (s.kind == 0) {
+    // S[a][p(b<c)] = P(i/jk)[sum_e t^{ae}_{jk}<ei||bc> - sum_m <ma||jk> t^{bc}_{im}]
+    const int64_t tb = v * lv, ab = v * lp, gb = o * lv, pb = o * lp;
+    switch (idx) {
+      case 0: return {s.T2T + (j * o + k) * tb, lv, s.As + i * ab, lp, (int32_t)v, 1.f};
+      case 1: return {s.T2T + (i * o + k) * tb, lv, s.As + j * ab, lp, (int32_t)v, -1.f};
+      case 2: return {s.T2T + (j * o + i) * tb, lv, s.As + k * ab, lp, (int32_t)v, -1.f};
+      case 3: return {s.GamT + (j * o + k) * gb, lv, s.Tp + i * pb, lp, (int32_t)o, -1.f};
+      case 4: return {s.GamT + (i * o + k) * gb, lv, s.Tp + j * pb, lp, (int32_t)o, 1.f};
+      default: return {s.GamT + (j * o + i) * gb, lv, s.Tp + k * pb, lp, (int32_t)o, 1.f};
+    }
+  }
+  if (s.kind == 1) {
+    // G[a][C*v+b] = sum_E t^{aE}_{iK}(jb|EC) - sum_E t^{aE}_{jK}(ib|EC) + sum_e t^{ae}_{ij}(be|KC)
+    //             - sum_m <am||ij> t^{bC}_{mK} + sum_M (aj|MK) t^{bC}_{iM} - sum_M (ai|MK) t^{bC}_{jM}
+    switch (idx) {
+      case 0: return {s.LmixT + (i * ot + k) * vt * lv, lv, s.Mst + j * vt * lc, lc, (int32_t)vt, 1.f};
+      case 1: return {s.LmixT + (j * ot + k) * vt * lv, lv, s.Mst + i * vt * lc, lc, (int32_t)vt, -1.f};
+      case 2: return {s.T2T + (i * o + j) * v * lv, lv, s.Mts + k * v * lc, lc, (int32_t)v, 1.f};
+      case 3: return {s.GamT + (i * o + j) * o * lv, lv, s.Tmix + k * lc, ot * lc, (int32_t)o, 1.f};
+      case 4: return {s.ZpT + (j * ot + k) * ot * lv, lv, s.Tmix + i * ot * lc, lc, (int32_t)ot, 1.f};
+      default: return {s.ZpT + (i * ot + k) * ot * lv, lv, s.Tmix + j * ot * lc, lc, (int32_t)ot, -1.f};
+    }
+  }
+  // Y[C][p(a<b)] = -sum_e t^{eC}_{iK}<je||ab> + sum_e t^{eC}_{jK}<ie||ab>
+  //              - sum_m (jm|CK) t^{ab}_{im} + sum_m (im|CK) t^{ab}_{jm}
+  switch (idx) {
+    case 0: return {s.TmT + (i * ot + k) * v * lt_, lt_, s.As + j * v * lp, lp, (int32_t)v, 1.f};
+    case 1: return {s.TmT + (j * ot + k) * v * lt_, lt_, s.As + i * v * lp, lp, (int32_t)v, -1.f};
+    case 2: return {s.OOT + (k * o + j) * o * lt_, lt_, s.Tp + i * o * lp, lp, (int32_t)o, -1.f};
+    default: return {s.OOT + (k * o + i) * o * lt_, lt_, s.Tp + j * o * lp, lp, (int32_t)o, 1.f};
+  }
+}
+
+template <typename T> struct Vec;
+template <> struct Vec<float> { typedef float4 type; static constexpr int N = 4; };
+template <> struct Vec<double> { typedef double2 type; static constexpr int N = 2; };
+
+template <typename T>
+__device__ inline typename Vec<T>::type vscale(typename Vec<T>::type v, float s) {
+  if constexpr (Vec<T>::N == 4) { v.x *= s; v.y *= s; v.z *= s; v.w *= s; }
+  else { v.x *= (double)s; v.y *= (double)s; }
+  return v;
+}
+
+template <typename T, int MB>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs<T> g) {
+  using F = MF<T>;
+  using V = typename Vec<T>::type;
+  constexpr int VN = Vec<T>::N;
+  constexpr int BR = F::BR, BC = F::BC;
+  constexpr int BM = MB * BR;
+  constexpr int BN = 4 * BC;
+  constexpr int BK = 16;
+  constexpr int AROW = BM / VN, BROW = BN / VN;       // vectors per staged row
+  constexpr int AV = BK * AROW, BV = BK * BROW;
+  constexpr int AVT = (AV + 255) / 256, BVT = (BV + 255) / 256;
+
+  __shared__ __attribute__((aligned(16))) T As[2][BK][BM];
+  __shared__ __attribute__((aligned(16))) T Bs[2][BK][BN];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  // logical tile id: consecutive ids share an XCD
+  int b = blockIdx.x;
+  {
+    const int nblk = gridDim.x, x = b & 7, q = nblk >> 3, r = nblk & 7;
+    b = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + (b >> 3);
+  }
+  const int mtile = b % g.mt; b /= g.mt;
+  const int ntile = b % g.nt; b /= g.nt;
+  const int batch = b;
+  const int m0 = mtile * BM, n0 = ntile * BN;
+
+  int64_t ti = 0, tj = 0, tk = 0;
+  int nseg = 1;
+  if (g.mode == 1) {
+    const int32_t* it = g.ops.items + 3 * batch;
+    ti = it[0]; tj = it[1]; tk = it[2];
+    nseg = g.ops.kind == 2 ? 4 : 6;
+  }
+  auto seg = [&](int idx) -> Seg<T> {
+    if (g.mode == 0)
+      return {g.L + (int64_t)batch * g.lbs, g.lks, g.R + (int64_t)batch * g.rbs, g.rks, g.K, 1.f};
+    return item_seg(g.ops, ti, tj, tk, idx);
+  };
+
+  typename F::acc_t acc[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < F::NACC; ++r) acc[mb][r] = 0;
+
+  V ra[AVT], rb[BVT];
+  auto gload = [&](int s, int k0) {
+    const Seg<T> sg = seg(s);
+#pragma unroll
+    for (int u = 0; u < AVT; ++u) {
+      const int e = tid + u * 256;
+      V v = {};
+      if (e < AV) {
+        const int kk = e / AROW, m = m0 + (e % AROW) * VN, k = k0 + kk;
+        if (k < sg.K && m < g.M) v = vscale<T>(*(const V*)(sg.L + (int64_t)k * sg.lks + m), sg.sign);
+      }
+      ra[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < BVT; ++u) {
+      const int e = tid + u * 256;
+      V v = {};
+      if (e < BV) {
+        const int kk = e / BROW, n = n0 + (e % BROW) * VN, k = k0 + kk;
+        if (k < sg.K && n < g.N) v = *(const V*)(sg.R + (int64_t)k * sg.rks + n);
+      }
+      rb[u] = v;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < AVT; ++u) {
+      const int e = tid + u * 256;
+      if (e < AV) *(V*)&As[buf][e / AROW][(e % AROW) * VN] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < BVT; ++u) {
+      const int e = tid + u * 256;
+      if (e < BV) *(V*)&Bs[buf][e / BROW][(e % BROW) * VN] = rb[u];
+    }
+  };
+
+  int s = 0, k0 = 0;
+  while (s < nseg && seg(s).K <= 0) ++s;
+  if (s < nseg) { gload(s, k0); sstore(0); }
+  __syncthreads();
+  int cur = 0;
+  while (s < nseg) {
+    k0 += BK;
+    while (s < nseg && k0 >= seg(s).K) { ++s; k0 = 0; }
+    const bool more = s < nseg;
+    if (more) gload(s, k0);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += F::KS) {
+      const T bv = Bs[cur][ks + F::a_k(lane)][wave * BC + F::c_col(lane)];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const T av = As[cur][ks + F::a_k(lane)][mb * BR + F::a_row(lane)];
+        acc[mb] = F::mma(av, bv, acc[mb]);
+      }
+    }
+    if (more) sstore(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  // store
+  T* out = g.out + (int64_t)batch * g.obs;
+  const int n = n0 + wave * BC + F::c_col(lane);
+  if (n < g.N) {
+    const int64_t noff = g.ndiv ? (int64_t)(n / g.ndiv) * g.s_nq + (int64_t)(n % g.ndiv) * g.s_nr
+                                : (int64_t)n * g.s_nr;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int r = 0; r < F::NACC; ++r) {
+        const int m = m0 + mb * BR + F::c_row(lane, r);
+        if (m < g.M) {
+          const int64_t moff = g.mdiv ? (int64_t)(m / g.mdiv) * g.s_mq + (int64_t)(m % g.mdiv) * g.s_mr
+                                      : (int64_t)m * g.s_mr;
+          out[moff + noff] = acc[mb][r];
+        }
+      }
+  }
+}
+
+template <typename T, int MB>
+static hipError_t launch_mb(GemmArgs<T> g, hipStream_t s) {
+  constexpr int BM = MB * MF<T>::BR, BN = 4 * MF<T>::BC;
+  g.mt = (g.M + BM - 1) / BM;
+  g.nt = (g.N + BN - 1) / BN;
+  const int64_t nblk = (int64_t)g.mt * g.nt * g.nbatch;
+  if (nblk <= 0) return hipSuccess;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_gemm<T, MB>), dim3((unsigned)nblk), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// Row-block count: the whole M range in one tile when it fits 16 blocks,
+// otherwise tiles of 4 blocks.
+template <> hipError_t launch_gemm<float>(const GemmArgs<float>& g, hipStream_t s) {
+  const int need = (g.M + 31) / 32;
+  if (need <= 1) return launch_mb<float, 1>(g, s);
+  if (need <= 2) return launch_mb<float, 2>(g, s);
+  if (need <= 3) return launch_mb<float, 3>(g, s);
+  if (need <= 4) return launch_mb<float, 4>(g, s);
+  if (need <= 6) return launch_mb<float, 6>(g, s);
+  if (need <= 8) return launch_mb<float, 8>(g, s);
+  if (need <= 10) return launch_mb<float, 10>(g, s);
+  if (need <= 12) return launch_mb<float, 12>(g, s);
+  if (need <= 16) return launch_mb<float, 16>(g, s);
+  return launch_mb<float, 4>(g, s);
+}
+
+template <> hipError_t launch_gemm<double>(const GemmArgs<double>& g, hipStream_t s) {
+  const int need = (g.M + 15) / 16;
+  if (need <= 2) return launch_mb<double, 2>(g, s);
+  if (need <= 4) return launch_mb<double, 4>(g, s);
+  if (need <= 6) return launch_mb<double, 6>(g, s);
+  if (need <= 8) return launch_mb<double, 8>(g, s);
+  if (need <= 12) return launch_mb<double, 12>(g, s);
+  if (need <= 16) return launch_mb<double, 16>(g, s);
+  if (need <= 20) return launch_mb<double, 20>(g, s);
+  if (need <= 24) return launch_mb<double, 24>(g, s);
+  if (need <= 32) return launch_mb<double, 32>(g, s);
+  return launch_mb<double, 8>(g, s);
+}
+
+}  // namespace lt

@@ -1,0 +1,156 @@
+// Internal declarations shared by the HIP translation units of ltriples.
+// gfx950 (CDNA4) only: wave64, MFMA matrix cores, 160 KB LDS per CU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace lt {
+
+// ---------------------------------------------------------------------------
+// Matrix-core traits.  Lane layouts were checked on gfx950 with an in-bounds
+// probe: for every shape below the A operand of lane l is A[row(l)][k(l)],
+// the B operand is B[k(l)][col(l)], and accumulator element r of lane l is
+// C[c_row(l, r)][col(l)].
+// ---------------------------------------------------------------------------
+template <typename T> struct MF;
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <> struct MF<float> {            // v_mfma_f32_32x32x2_f32
+  static constexpr int BR = 32, BC = 32, KS = 2, NACC = 16;
+  typedef f32x16 acc_t;
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int a_row(int l) { return l & 31; }
+  __device__ static inline int a_k(int l) { return l >> 5; }
+  __device__ static inline int c_row(int l, int r) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
+  __device__ static inline int c_col(int l) { return l & 31; }
+};
+
+template <> struct MF<double> {           // v_mfma_f64_16x16x4_f64
+  static constexpr int BR = 16, BC = 16, KS = 4, NACC = 4;
+  typedef f64x4 acc_t;
+  __device__ static inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int a_row(int l) { return l & 15; }
+  __device__ static inline int a_k(int l) { return l >> 4; }
+  __device__ static inline int c_row(int l, int r) { return (l >> 4) + 4 * r; }
+  __device__ static inline int c_col(int l) { return l & 15; }
+};
+
+// ---------------------------------------------------------------------------
+// Segmented GEMM:  C[m][n] = sum_s sign_s sum_k Lt_s[k][m] * R_s[k][n].
+// Both operands are k-major (row k contiguous in m resp. n), with row
+// strides that are multiples of 4 elements and 16-byte aligned rows.
+// ---------------------------------------------------------------------------
+template <typename T> struct Seg {
+  const T* L; int64_t lks;
+  const T* R; int64_t rks;
+  int32_t K; float sign;
+};
+
+// Prepared operands of one spin block (sigma = spin of the same-spin pair,
+// tau = spin of the odd index of a mixed block).  All row lengths padded.
+template <typename T> struct ItemOps {
+  int32_t kind;                 // 0: S (same spin), 1: G (mixed), 2: Y (mixed)
+  int32_t o_s, v_s, o_t, v_t;
+  int64_t ld_vs, ld_vt, ld_np, ld_cb;
+  const T* T2T;    // [o_s][o_s][v_s][ld_vs]   T2T[i][j][e][a] = t^{ae}_{ij}
+  const T* Tp;     // [o_s][o_s][ld_np]        Tp[i][m][p(a<b)] = t^{ab}_{im}
+  const T* As;     // [o_s][v_s][ld_np]        As[i][e][p(b<c)] = <ei||bc>
+  const T* GamT;   // [o_s][o_s][o_s][ld_vs]   GamT[j][k][m][a] = <ma||jk>
+  const T* LmixT;  // [o_s][o_t][v_t][ld_vs]   LmixT[i][K][E][a] = t^{aE}_{iK}
+  const T* Mst;    // [o_s][v_t][ld_cb]        Mst[j][E][C*v_s+b] = (jb|EC)
+  const T* Mts;    // [o_t][v_s][ld_cb]        Mts[K][e][C*v_s+b] = (be|KC)
+  const T* Tmix;   // [o_s][o_t][ld_cb]        Tmix[i][K][C*v_s+b] = t^{bC}_{iK}
+  const T* ZpT;    // [o_s][o_t][o_t][ld_vs]   ZpT[j][K][M][a] = (aj|MK)
+  const T* TmT;    // [o_s][o_t][v_s][ld_vt]   TmT[i][K][e][C] = t^{eC}_{iK}
+  const T* OOT;    // [o_t][o_s][o_s][ld_vt]   OOT[K][j][m][C] = (jm|CK)
+  const int32_t* items;  // [n][3] occupied triplets of the batch
+};
+
+template <typename T> struct GemmArgs {
+  int32_t M, N, nbatch, mt, nt;
+  int32_t mode;                 // 0: single strided segment per batch, 1: item
+  // output: out + b*obs + (m/mdiv)*s_mq + (m%mdiv)*s_mr + (n/ndiv)*s_nq + (n%ndiv)*s_nr
+  T* out; int64_t obs;
+  int64_t s_mq, s_mr, s_nq, s_nr;
+  int32_t mdiv, ndiv;
+  // mode 0
+  const T* L; int64_t lks, lbs;
+  const T* R; int64_t rks, rbs;
+  int32_t K;
+  // mode 1
+  ItemOps<T> ops;
+};
+
+// ---------------------------------------------------------------------------
+// Energy epilogues (FP64): W assembly from the contraction outputs, V, D,
+// per-tile partial sums of {E4, E_ST, E_DT}.
+// ---------------------------------------------------------------------------
+constexpr int ET = 16;   // epilogue tile edge
+
+template <typename T> struct EpiSame {
+  int32_t o, v; int64_t ld_np;
+  const T* S; int64_t s_item;          // S[item][a][ld_np]
+  const int32_t* items;                // [n][3]
+  int32_t nt, ntri;
+  const double *eo, *ev, *t1, *f, *t2; // t2 [o][o][v][v] (input)
+  const double* U; int64_t ld_v;       // U[q][r][y][ld_v] = <qr||yz>
+  double* part;                        // [n][ntri][3]
+};
+
+template <typename T> struct EpiMixed {
+  int32_t o_s, v_s, o_t, v_t; int64_t ld_np, ld_cb;
+  const T* G; int64_t g_item;          // G[item][a][ld_cb]
+  const T* Y; int64_t y_item;          // Y[item][C][ld_np]
+  const int32_t* items;
+  int32_t nts, ntt, ntiles;
+  const double *eo_s, *ev_s, *eo_t, *ev_t, *t1_s, *t1_t, *f_s, *f_t;
+  const double* t2ss;                  // [o_s][o_s][v_s][v_s] (input)
+  const double* U; int64_t ld_vs;      // U_s[i][j][a][ld_vs] = <ij||ab>
+  // (jb|KC) at ov + j*ov_o + b*ov_v + K*ov_O + C*ov_V ; t^{bC}_{jK} likewise
+  const double* ov; int64_t ov_o, ov_v, ov_O, ov_V;
+  const double* tm; int64_t tm_o, tm_v, tm_O, tm_V;
+  double* part;                        // [n][ntiles][3]
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (all asynchronous on `s`)
+// ---------------------------------------------------------------------------
+template <typename T> hipError_t launch_gemm(const GemmArgs<T>& g, hipStream_t s);
+
+// out[d0][d1][d2][d3] (out strides os0..os2, unit stride in d3)
+//   = in[d0*s0 + d1*s1 + d2*s2 + d3*s3] - (in2 ? in2[d0*u0 + ... + d3*u3] : 0)
+template <typename Tin, typename Tout>
+hipError_t launch_copy4d(Tout* out, int64_t os0, int64_t os1, int64_t os2,
+                         int64_t d0, int64_t d1, int64_t d2, int64_t d3,
+                         const Tin* in, int64_t s0, int64_t s1, int64_t s2, int64_t s3,
+                         const Tin* in2, int64_t u0, int64_t u1, int64_t u2, int64_t u3,
+                         hipStream_t s);
+
+// out[r][p(x<y)] = in[r*rs + x*xs + y*ys] - (antisym ? in[r*rs + y*xs + x*ys] : 0)
+// for x < y < n, p(x,y) = y(y-1)/2 + x; out row stride ldo.
+template <typename Tin, typename Tout>
+hipError_t launch_pack_pairs(Tout* out, int64_t ldo, int64_t rows, int32_t n,
+                             const Tin* in, int64_t rs, int64_t xs, int64_t ys,
+                             bool antisym, hipStream_t s);
+
+template <typename T> hipError_t launch_epi_same(const EpiSame<T>& a, int32_t nitems, hipStream_t s);
+template <typename T> hipError_t launch_epi_mixed(const EpiMixed<T>& a, int32_t nitems, hipStream_t s);
+
+// e_items[dst[b]][0..2] = sum over t of part[b][t][0..2] (fixed order)
+hipError_t launch_reduce_items(const double* part, int32_t nitems, int32_t ntiles,
+                               const int32_t* dst, double* e_items, hipStream_t s);
+// parts[blk][q] = sum of e_items[n][q] over n in [first[blk], first[blk]+count[blk]) of the
+// block-ordered index list `order`; e_out = sum of parts.
+hipError_t launch_reduce_final(const double* e_items, const int32_t* order,
+                               const int32_t* first, const int32_t* count,
+                               double* parts, double* e_out, hipStream_t s);
+hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
+
+}  // namespace lt

@@ -1,0 +1,116 @@
+// Operand preparation: strided 4-D copies (permutation, precision change,
+// optional antisymmetrisation by subtracting a second strided view) and
+// pair packing (x<y) with optional antisymmetrisation.  These run once per
+// call and are memory bound; they lay every contraction operand out k-major
+// with padded, 16-byte aligned rows.
+#include "lt_internal.h"
+
+namespace lt {
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void k_copy4d(Tout* out, int64_t os0, int64_t os1, int64_t os2,
+                                                int64_t d0, int64_t d1, int64_t d2, int64_t d3,
+                                                const Tin* in, int64_t s0, int64_t s1, int64_t s2, int64_t s3,
+                                                const Tin* in2, int64_t u0, int64_t u1, int64_t u2, int64_t u3) {
+  const int64_t total = d0 * d1 * d2 * d3;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e;
+    const int64_t x3 = r % d3; r /= d3;
+    const int64_t x2 = r % d2; r /= d2;
+    const int64_t x1 = r % d1; r /= d1;
+    const int64_t x0 = r;
+    double val = (double)in[x0 * s0 + x1 * s1 + x2 * s2 + x3 * s3];
+    if (in2) val -= (double)in2[x0 * u0 + x1 * u1 + x2 * u2 + x3 * u3];
+    out[x0 * os0 + x1 * os1 + x2 * os2 + x3] = (Tout)val;
+  }
+}
+
+template <typename Tin, typename Tout>
+hipError_t launch_copy4d(Tout* out, int64_t os0, int64_t os1, int64_t os2,
+                         int64_t d0, int64_t d1, int64_t d2, int64_t d3,
+                         const Tin* in, int64_t s0, int64_t s1, int64_t s2, int64_t s3,
+                         const Tin* in2, int64_t u0, int64_t u1, int64_t u2, int64_t u3,
+                         hipStream_t s) {
+  const int64_t total = d0 * d1 * d2 * d3;
+  if (total <= 0) return hipSuccess;
+  int64_t nb = (total + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL((k_copy4d<Tin, Tout>), dim3((unsigned)nb), dim3(256), 0, s, out, os0, os1, os2,
+                     d0, d1, d2, d3, in, s0, s1, s2, s3, in2, u0, u1, u2, u3);
+  return hipGetLastError();
+}
+
+// p = y(y-1)/2 + x, x < y
+__device__ inline void pair_of(int64_t p, int32_t& x, int32_t& y) {
+  int32_t yy = (int32_t)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
+  while ((int64_t)yy * (yy - 1) / 2 > p) --yy;
+  while ((int64_t)(yy + 1) * yy / 2 <= p) ++yy;
+  y = yy;
+  x = (int32_t)(p - (int64_t)yy * (yy - 1) / 2);
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void k_pack_pairs(Tout* out, int64_t ldo, int64_t rows, int32_t n,
+                                                    const Tin* in, int64_t rs, int64_t xs, int64_t ys,
+                                                    bool antisym) {
+  const int64_t np = (int64_t)n * (n - 1) / 2;
+  const int64_t total = rows * np;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / np, p = e % np;
+    int32_t x, y;
+    pair_of(p, x, y);
+    const Tin* base = in + r * rs;
+    double val = (double)base[x * xs + y * ys];
+    if (antisym) val -= (double)base[y * xs + x * ys];
+    out[r * ldo + p] = (Tout)val;
+  }
+}
+
+template <typename Tin, typename Tout>
+hipError_t launch_pack_pairs(Tout* out, int64_t ldo, int64_t rows, int32_t n,
+                             const Tin* in, int64_t rs, int64_t xs, int64_t ys,
+                             bool antisym, hipStream_t s) {
+  const int64_t total = rows * ((int64_t)n * (n - 1) / 2);
+  if (total <= 0) return hipSuccess;
+  int64_t nb = (total + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL((k_pack_pairs<Tin, Tout>), dim3((unsigned)nb), dim3(256), 0, s, out, ldo, rows, n,
+                     in, rs, xs, ys, antisym);
+  return hipGetLastError();
+}
+
+template hipError_t launch_copy4d<double, double>(double*, int64_t, int64_t, int64_t, int64_t, int64_t,
+                                                  int64_t, int64_t, const double*, int64_t, int64_t,
+                                                  int64_t, int64_t, const double*, int64_t, int64_t,
+                                                  int64_t, int64_t, hipStream_t);
+template hipError_t launch_copy4d<double, float>(float*, int64_t, int64_t, int64_t, int64_t, int64_t,
+                                                 int64_t, int64_t, const double*, int64_t, int64_t,
+                                                 int64_t, int64_t, const double*, int64_t, int64_t,
+                                                 int64_t, int64_t, hipStream_t);
+template hipError_t launch_copy4d<float, float>(float*, int64_t, int64_t, int64_t, int64_t, int64_t,
+                                                int64_t, int64_t, const float*, int64_t, int64_t,
+                                                int64_t, int64_t, const float*, int64_t, int64_t,
+                                                int64_t, int64_t, hipStream_t);
+template hipError_t launch_pack_pairs<double, double>(double*, int64_t, int64_t, int32_t, const double*,
+                                                      int64_t, int64_t, int64_t, bool, hipStream_t);
+template hipError_t launch_pack_pairs<double, float>(float*, int64_t, int64_t, int32_t, const double*,
+                                                     int64_t, int64_t, int64_t, bool, hipStream_t);
+template hipError_t launch_pack_pairs<float, float>(float*, int64_t, int64_t, int32_t, const float*,
+                                                    int64_t, int64_t, int64_t, bool, hipStream_t);
+
+__global__ void k_zero(double* p, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = 0.0;
+}
+
+hipError_t launch_zero(double* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t nb = (n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)nb), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace lt

@@ -1,0 +1,103 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared
+symbol, validates arguments with the documented error codes, and counts
+flops by the documented formula.  No GPU is needed (no compute calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2311_10048_amd as lt
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ltriples.h")
+
+
+def _lib():
+    if not os.path.exists(lt.LIB_PATH):
+        pytest.skip("libltriples.so not built")
+    return lt.load_library()
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(ltriples_\w+)\s*\(", src, re.M)))
+
+
+def test_exports_every_declared_symbol():
+    lib = _lib()
+    names = _declared()
+    assert "ltriples_energy" in names and len(names) >= 6
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lt.ltriples_version().startswith("ltriples")
+
+
+def _fake_domain(dims, null=()):
+    # fake, never-dereferenced device addresses: validation only checks for NULL
+    t = {n: (0 if n in null else 0x1000 * (k + 1)) for k, n in enumerate(lt.ARRAY_FIELDS)}
+    return lt.make_domain(dims, t)
+
+
+def test_validate_ok_and_errors():
+    _lib()
+    d = _fake_domain((4, 3, 10, 11, 20))
+    assert lt.ltriples_validate(d, lt.LT_FP64) == lt.LT_OK
+    assert lt.ltriples_validate(d, lt.LT_FP32) == lt.LT_OK
+    assert lt.ltriples_validate(d, 17) == lt.LT_EPREC
+    assert lt.ltriples_validate(_fake_domain((4, -1, 10, 11, 20)), lt.LT_FP64) == lt.LT_EINVAL
+    assert lt.ltriples_validate(_fake_domain((4, 3, 10, 11, 20), null=("t2ab",)), lt.LT_FP64) == lt.LT_EINVAL
+    assert "t2ab" in lt.ltriples_last_error()
+    assert lt.ltriples_validate(_fake_domain((4, 3, 10, 11, 0)), lt.LT_FP64) == lt.LT_ESHAPE
+    # NULL allowed for empty arrays
+    assert lt.ltriples_validate(_fake_domain((4, 0, 10, 11, 20), null=("t1b", "t2bb", "t2ab", "Boo_b",
+                                                                       "Bov_b", "eo_b", "fov_b")),
+                                lt.LT_FP64) == lt.LT_OK
+
+
+@pytest.mark.parametrize("item,code", [
+    ((0, 0, 1, 2), lt.LT_OK), ((0, 1, 0, 2), lt.LT_ESHAPE), ((0, 0, 1, 4), lt.LT_ESHAPE),
+    ((1, 0, 1, 2), lt.LT_OK), ((1, 0, 1, 3), lt.LT_ESHAPE), ((2, 0, 2, 3), lt.LT_OK),
+    ((2, 0, 3, 0), lt.LT_ESHAPE), ((3, 0, 1, 2), lt.LT_OK), ((4, 0, 1, 2), lt.LT_ESHAPE),
+])
+def test_validate_items(item, code):
+    _lib()
+    d = _fake_domain((4, 3, 10, 11, 20))
+    o, keep = lt.make_options(items=[item])
+    assert lt.ltriples_validate(d, lt.LT_FP64, o) == code
+
+
+def _flops_formula(oa, ob, va, vb):
+    c = lambda n, k: float(np.prod([n - i for i in range(k)]) / np.prod(range(1, k + 1))) if n >= k else 0.0
+    return (c(oa, 3) * (6 * va**4 + 6 * va**3 * oa) + c(ob, 3) * (6 * vb**4 + 6 * vb**3 * ob)
+            + c(oa, 2) * ob * (4 * va**2 * vb**2 + 6 * va**3 * vb + 4 * va**2 * vb * ob + 6 * va**2 * vb * oa)
+            + oa * c(ob, 2) * (4 * va**2 * vb**2 + 6 * vb**3 * va + 4 * vb**2 * va * oa + 6 * vb**2 * va * ob))
+
+
+@pytest.mark.parametrize("name", ["tiny", "lno", "grad", "large"])
+def test_flops_and_item_counts(name):
+    _lib()
+    oa, ob, va, vb, q = synth.SHAPES[name]
+    f, n = lt.ltriples_flops(_fake_domain((oa, ob, va, vb, q)))
+    assert abs(f - _flops_formula(oa, ob, va, vb)) <= 1e-12 * f
+    assert n == oa * (oa - 1) * (oa - 2) // 6 + oa * (oa - 1) // 2 * ob + ob * (ob - 1) // 2 * oa \
+        + ob * (ob - 1) * (ob - 2) // 6
+
+
+def test_workspace_size_grows_with_precision():
+    _lib()
+    d = _fake_domain((5, 4, 30, 31, 120))
+    w64 = lt.ltriples_workspace_size(d, lt.LT_FP64)
+    w32 = lt.ltriples_workspace_size(d, lt.LT_FP32)
+    assert w64 > w32 > 0
+
+
+def test_energy_rejects_bad_args_without_gpu_work():
+    lib = _lib()
+    d = _fake_domain((4, 3, 10, 11, 20))
+    code = lib.ltriples_energy(ctypes.byref(d), 9, None, None, None, None, 0, None)
+    assert code == lt.LT_EPREC
+    code = lib.ltriples_energy(ctypes.byref(d), lt.LT_FP64, None, None, None, None, 0, None)
+    assert code == lt.LT_EINVAL

@@ -1,0 +1,95 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances (relative to max(1 Eh, |E|)): FP64 1e-11 on E and
+every per-block part, FP32 1e-8 on E; per-item values at the same bars.  The
+parts E_ST / E_DT are compared against their own magnitudes.
+"""
+import numpy as np
+import pytest
+
+import paper_2311_10048_amd as lt
+import synth
+from oracle import blocks
+from tests.gpu_util import gpu_energy, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL_E = {lt.LT_FP64: 1e-11, lt.LT_FP32: 1e-8}
+TOL_PART = {lt.LT_FP64: 1e-10, lt.LT_FP32: 1e-4}
+
+SHAPES = {
+    "tiny": synth.SHAPES["tiny"],          # (5,4,30,31,120)
+    "ragged": (6, 5, 45, 47, 96),          # several tiles, ragged tails everywhere
+    "no_beta_occ": (4, 0, 21, 22, 40),     # only the aaa block
+    "one_beta": (3, 1, 17, 18, 30),        # aaa, aab
+    "wide": (3, 3, 70, 67, 64),            # v > 64: several GEMM and epilogue tiles
+}
+
+
+def _check(dom, prec, ref=None, items=None):
+    ref = ref if ref is not None else blocks.energy(dom, items=items, return_items=items is not None)
+    E, parts, e_items = gpu_energy(dom, prec, items=items)
+    scale = max(1.0, abs(ref["E"]))
+    assert abs(E - ref["E"]) / scale <= TOL_E[prec], (E, ref["E"])
+    for b in range(4):
+        r4, rs, rd = ref["parts"][b]
+        g4, gs, gd = parts[b]
+        assert abs(g4 - r4) <= TOL_E[prec] * max(1.0, abs(r4)) * 10, (b, g4, r4)
+        if rs != 0:
+            assert abs(gs - rs) <= TOL_PART[prec] * abs(rs) + 1e-300, (b, gs, rs)
+        if rd != 0:
+            assert abs(gd - rd) <= TOL_PART[prec] * abs(rd) + 1e-300, (b, gd, rd)
+    if items is not None:
+        for n in range(len(items)):
+            ri, gi = ref["items"][n], e_items[n]
+            s = max(1.0, abs(ri[0]))
+            assert abs(gi[0] - ri[0]) <= 10 * TOL_E[prec] * s, (n, gi, ri)
+    return E, ref["E"]
+
+
+@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32])
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_parity_shapes(name, prec):
+    dom = synth.make_domain(*SHAPES[name], seed=synth.BASE_SEED + 17)
+    print(f"[parity] {name} {SHAPES[name]} prec={prec}", flush=True)
+    _check(dom, prec)
+
+
+@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32])
+def test_workspace_garbage_never_read(prec):
+    """A NaN-filled workspace gives the same result: no never-written word of
+    the workspace (row padding included) reaches the energy.  The two spins
+    have different padded row lengths here (70 -> 72, 67 -> 68)."""
+    dom = synth.make_domain(*SHAPES["wide"], seed=synth.BASE_SEED + 17)
+    E0, p0, _ = gpu_energy(dom, prec, ws_fill=0.0)
+    E1, p1, _ = gpu_energy(dom, prec, ws_fill=float("nan"))
+    assert E0 == E1 and np.array_equal(p0, p1)
+
+
+def test_parity_config0_items_fp64():
+    """Per-item values of every triplet of the small domain, in caller order."""
+    dom = synth.config_domain("tiny")
+    items = blocks.enumerate_items(dom.noa, dom.nob)[::-1].copy()
+    _check(dom, lt.LT_FP64, items=items)
+
+
+def test_fewer_than_three_occupied_is_zero():
+    dom = synth.make_domain(1, 1, 8, 9, 20, seed=3)
+    E, parts, _ = gpu_energy(dom, lt.LT_FP64)
+    assert E == 0.0 and np.all(parts == 0.0)
+
+
+def test_small_batches_bitwise_equal():
+    """Batch size does not change a single bit of the result."""
+    dom = synth.make_domain(*SHAPES["ragged"], seed=5)
+    E1, p1, _ = gpu_energy(dom, lt.LT_FP32)
+    E2, p2, _ = gpu_energy(dom, lt.LT_FP32, batch_items=3)
+    assert E1 == E2 and np.array_equal(p1, p2)
+
+
+def test_denominator_check():
+    dom = synth.make_domain(3, 2, 6, 7, 16, seed=3)
+    bad = dom.replace(eo_a=dom.eo_a + 2.0)
+    with pytest.raises(lt.LtError) as ei:
+        gpu_energy(bad, lt.LT_FP64)
+    assert ei.value.code == lt.LT_EDENOM
