@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark: perturbative-triples energy E(T) of one LNO-sized domain on one
+MI355X, in triples GFLOP/s.
+
+One step is one full ltriples_energy call on the domain (operand layouts,
+density-fitting integral builds, every occupied triplet of the four spin
+blocks, FP64 energy epilogue and reductions), with the inputs resident in HBM.
+The printed JSON line also carries:
+  roofline      the triplet-contraction GEMM kernel (k_tgemm) against the
+                matrix-core peak of its dtype, timed live with HIP events
+  fp64_gpu      the same path in FP64 (the "plain FP64 GPU" baseline), timed
+                on a stratified item sample and scaled to the whole domain
+  parity        per-item values of the timed run against the FP64 CPU oracle
+                on the CPU-baseline items, and against the FP64 GPU run
+  cpu_baseline  the FP64 CPU oracle timed on the host on a small item sample
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "(T) triples GFLOP/s & MFMA util vs plain FP64 GPU, at |ΔE(T)|≤1e-6 Eh"
+# dense matrix-core peaks of MI355X (TFLOP/s)
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16": 2500.0}
+
+
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [p.get("num_threads", 0) for p in threadpool_info() if p.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return os.cpu_count() or 1
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--workload", default="lno", choices=["tiny", "lno", "grad"])
+    ap.add_argument("--fp64-sample", type=int, default=48, help="items per block for the FP64 GPU comparison")
+    ap.add_argument("--cpu-sample", type=int, default=1, help="items per block for the CPU oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}): "
+              "the (T) energy of one domain is measured on a single MI355X; see DESIGN.md for how "
+              "the path would shard across GPUs.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2311_10048_amd as lt
+    import synth
+
+    lt.load_library()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    prec = lt.PRECISIONS[args.precision]
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    t0 = time.time()
+    dom = synth.config_domain(args.workload)
+    log(f"generated {args.workload} domain {dom.dims} in {time.time() - t0:.1f} s")
+    tens = {k: torch.from_numpy(v).to(dev) for k, v in dom.arrays().items()}
+    torch.cuda.synchronize()
+    d = lt.make_domain(dom.dims, tens)
+    F_all, n_all = lt.ltriples_flops(d)
+    ws = torch.empty(lt.ltriples_workspace_size(d, prec), dtype=torch.uint8, device=dev)
+    e_items = torch.zeros(n_all, 3, dtype=torch.float64, device=dev)
+    log(f"items {n_all}, algorithmic flops {F_all:.4e}, workspace {ws.numel() / 1e9:.1f} GB")
+
+    def step():
+        st = lt.Stats()
+        e, parts = lt.ltriples_energy(tens, dom.dims, prec, e_items=e_items, workspace=ws, stats=st)
+        return e, parts, st
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {w + 1}/{args.warmup} done")
+    stats = []
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    tw = time.perf_counter()
+    ev0.record()
+    for k in range(args.steps):
+        e, parts, st = step()
+        stats.append(st)
+        log(f"step {k + 1}/{args.steps}: {st.total_ms / 1e3:.2f} s")
+    ev1.record()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - tw) * 1e3
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    E = float(e.item())
+    parts = parts.cpu().numpy()
+    value = F_all / (ms_per_step * 1e-3) / 1e9
+
+    gemm_ms = sum(s.triples_gemm_ms for s in stats)
+    gemm_flops = sum(s.triples_gemm_flops for s in stats)
+    launches = sum(s.triples_gemm_launches for s in stats)
+    achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    roofline = {"bound": "mfma", "kernel": "k_tgemm (triplet contraction GEMM)",
+                "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "avg_launch_ms": round(gemm_ms / max(launches, 1), 4),
+                "launches_per_step": launches // max(len(stats), 1),
+                "flops_per_launch": gemm_flops / max(launches, 1)}
+    phase = {"setup_ms": round(stats[-1].setup_ms, 2), "triples_gemm_ms": round(stats[-1].triples_gemm_ms, 2),
+             "epilogue_ms": round(stats[-1].epilogue_ms, 2), "total_ms": round(stats[-1].total_ms, 2)}
+    log(f"E = {E:.10e}  {ms_per_step / 1e3:.2f} s/step  {value:.1f} GFLOP/s  gemm {achieved:.1f} TFLOP/s")
+
+    # ---- FP64 GPU path on a stratified sample, scaled to the domain -----------------------
+    fp64 = None
+    items64 = synth.sample_items(dom.noa, dom.nob, args.fp64_sample, seed=2311)
+    if args.fp64_sample > 0 and len(items64):
+        o64, _keep = lt.make_options(items=items64)
+        F_s, n_s = lt.ltriples_flops(d, o64)
+        ws64 = torch.empty(lt.ltriples_workspace_size(d, lt.LT_FP64, o64), dtype=torch.uint8, device=dev)
+        ei64 = torch.zeros(n_s, 3, dtype=torch.float64, device=dev)
+        st64 = lt.Stats()
+        lt.ltriples_energy(tens, dom.dims, lt.LT_FP64, items=items64, e_items=ei64, workspace=ws64, stats=st64)
+        torch.cuda.synchronize()
+        per_flop_ms = (st64.triples_gemm_ms + st64.epilogue_ms) / F_s
+        est_ms = st64.setup_ms + per_flop_ms * F_all
+        # the timed run's values at the same items
+        full_idx = _item_index(dom.noa, dom.nob, items64)
+        mine = e_items.cpu().numpy()[full_idx]
+        ref64 = ei64.cpu().numpy()
+        s_mine, s_ref = mine.sum(), ref64.sum()
+        fp64 = {"sample_items": int(n_s), "sample_ms": round(st64.total_ms, 2),
+                "est_full_s": round(est_ms / 1e3, 2), "speedup_vs_fp64": round(est_ms / ms_per_step, 3),
+                "sample_rel_diff_vs_fp64": float(abs(s_mine - s_ref) / max(1.0, abs(s_ref))),
+                "gemm_tflops": round(st64.triples_gemm_flops / (st64.triples_gemm_ms * 1e-3) / 1e12, 2)}
+        log(f"fp64 sample: est {est_ms / 1e3:.1f} s for the domain, speedup {est_ms / ms_per_step:.2f}x")
+        del ws64
+
+    # ---- CPU oracle baseline + parity on its items ------------------------------------------
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline and args.cpu_sample > 0:
+        from oracle import blocks
+        itc = synth.sample_items(dom.noa, dom.nob, args.cpu_sample, seed=11)
+        oc, _k2 = lt.make_options(items=itc)
+        F_c, n_c = lt.ltriples_flops(d, oc)
+        tc = time.perf_counter()
+        ref = blocks.energy(dom, items=itc, return_items=True)
+        dt = time.perf_counter() - tc
+        cpu = {"value": round(F_c / dt / 1e9, 3), "unit": "GFLOP/s", "cores": _blas_threads(), "kind": "oracle",
+               "sample": f"{n_c} occupied triplets ({args.cpu_sample} per spin block) of the same domain, "
+                         f"{F_c:.3e} flops in {dt:.1f} s, NumPy FP64",
+               "seconds": round(dt, 2), "est_full_domain_s": round(dt * F_all / F_c, 1)}
+        full_idx = _item_index(dom.noa, dom.nob, itc)
+        g = e_items.cpu().numpy()[full_idx]
+        r = ref["items"]
+        tot = np.abs(g.sum(axis=1) - r.sum(axis=1)) / np.maximum(1.0, np.abs(r.sum(axis=1)))
+        parity = {"oracle_items": int(n_c), "max_rel_err_item_E": float(tot.max()),
+                  "tolerance": 1e-8 if args.precision == "fp32" else 1e-11, "pass": bool(tot.max() <= (1e-8 if args.precision == "fp32" else 1e-11))}
+        log(f"cpu oracle {dt:.1f} s for {n_c} items; max item rel err {tot.max():.2e}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} domain: noa={dom.noa} nob={dom.nob} nva={dom.nva} "
+                               f"nvb={dom.nvb} naux={dom.naux}, all {n_all} occupied triplets",
+                   "algorithmic_flops": F_all, "precision": args.precision,
+                   "wall_ms_per_step": round(wall_ms / args.steps, 2)},
+        "E": E,
+        "parts": parts.tolist(),
+        "phases": phase,
+        "roofline": roofline,
+        "mfma_util": roofline["frac"],
+        "fp64_gpu": fp64,
+        "parity": parity,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _item_index(noa, nob, items):
+    """Positions of (block, p, q, r) items in the library's full enumeration
+    order (block, then lexicographic)."""
+    c0 = noa * (noa - 1) * (noa - 2) // 6
+    c1 = noa * (noa - 1) // 2 * nob
+    c2 = nob * (nob - 1) // 2 * noa
+    base = [0, c0, c0 + c1, c0 + c1 + c2]
+    idx = []
+    for b, p, q, r in np.asarray(items).reshape(-1, 4):
+        if b in (0, 3):
+            n = nob if b == 3 else noa
+            # rank of (p<q<r) in lexicographic order
+            k = 0
+            for i in range(p):
+                k += (n - 1 - i) * (n - 2 - i) // 2
+            for j in range(p + 1, q):
+                k += n - 1 - j
+            k += r - q - 1
+        else:
+            n = noa if b == 1 else nob
+            m = nob if b == 1 else noa
+            k = 0
+            for i in range(p):
+                k += (n - 1 - i) * m
+            k += (q - p - 1) * m + r
+        idx.append(base[b] + k)
+    return np.asarray(idx, dtype=np.int64)
+
+
+if __name__ == "__main__":
+    main()

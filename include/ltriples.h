@@ -84,6 +84,20 @@ typedef struct ltriples_domain {
   const double *fov_a, *fov_b;
 } ltriples_domain;
 
+/* Per-phase timings of one call (filled only when requested through
+ * ltriples_options.stats).  Times are HIP-event times on the call's stream. */
+typedef struct ltriples_stats {
+  double total_ms;              /* first to last enqueued kernel */
+  double setup_ms;              /* operand layouts and integral builds */
+  double triples_gemm_ms;       /* sum over the triplet-contraction launches */
+  double epilogue_ms;           /* sum over energy epilogues and per-item sums */
+  int64_t triples_gemm_launches;
+  double triples_gemm_flops;    /* 2*M*N*K of those launches (unpadded shapes) */
+  double algorithmic_flops;     /* W-contraction flops of the item list, as
+                                   counted by ltriples_flops() */
+  int64_t n_items;
+} ltriples_stats;
+
 /* Options; a NULL options pointer means all defaults (zeros). */
 typedef struct ltriples_options {
   /* bytes of workspace the per-batch triples intermediates may use;
@@ -98,7 +112,11 @@ typedef struct ltriples_options {
   double* e_items;
   /* items per batch (0 = automatic) */
   int32_t batch_items;
-  int32_t reserved[7];
+  /* optional HOST pointer: when set, the call records HIP events around
+   * each phase and launch, waits for the stream before returning, and
+   * fills *stats */
+  ltriples_stats* stats;
+  int32_t reserved[4];
 } ltriples_options;
 
 /* Host-only validation of sizes, pointers, precision and item list.  Makes

@@ -50,13 +50,28 @@ class Domain(ctypes.Structure):
                 + [(n, ctypes.c_void_p) for n in ARRAY_FIELDS])
 
 
+class Stats(ctypes.Structure):
+    _fields_ = [("total_ms", ctypes.c_double),
+                ("setup_ms", ctypes.c_double),
+                ("triples_gemm_ms", ctypes.c_double),
+                ("epilogue_ms", ctypes.c_double),
+                ("triples_gemm_launches", ctypes.c_int64),
+                ("triples_gemm_flops", ctypes.c_double),
+                ("algorithmic_flops", ctypes.c_double),
+                ("n_items", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Options(ctypes.Structure):
     _fields_ = [("batch_budget", ctypes.c_size_t),
                 ("items", ctypes.c_void_p),
                 ("n_items", ctypes.c_int32),
                 ("e_items", ctypes.c_void_p),
                 ("batch_items", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("stats", ctypes.POINTER(Stats)),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class LtError(RuntimeError):
@@ -132,12 +147,15 @@ def make_domain(dims, tensors: Optional[Mapping[str, object]] = None) -> Domain:
     return d
 
 
-def make_options(items=None, e_items=None, batch_budget: int = 0, batch_items: int = 0):
+def make_options(items=None, e_items=None, batch_budget: int = 0, batch_items: int = 0,
+                 stats: Optional[Stats] = None):
     """ltriples_options; `items` is a host int32 array [n][4] (kept alive by
     the returned tuple's second element)."""
     o = Options()
     o.batch_budget = int(batch_budget)
     o.batch_items = int(batch_items)
+    if stats is not None:
+        o.stats = ctypes.pointer(stats)
     keep = None
     if items is not None:
         keep = np.ascontiguousarray(np.asarray(items, dtype=np.int32).reshape(-1, 4))
@@ -174,7 +192,7 @@ def ltriples_flops(dom: Domain, options: Optional[Options] = None):
 
 def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP32, items=None,
                     e_items=None, batch_budget: int = 0, batch_items: int = 0, workspace=None,
-                    stream=None):
+                    stream=None, stats: Optional[Stats] = None):
     """E(T) of one domain on the current HIP device.
 
     Returns (e, parts): a float64 device tensor of shape [1] and one of shape
@@ -182,13 +200,14 @@ def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP3
     given, is a uint8 device tensor at least ltriples_workspace_size() long;
     otherwise one is allocated through torch.  The call is asynchronous on
     `stream` (default: torch's current stream) except for one small
-    synchronous read of the orbital energies.
+    synchronous read of the orbital energies.  Passing a ``Stats`` object
+    makes the call time its phases with HIP events and wait for the stream.
     """
     import torch
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     dom = make_domain(dims, tensors)
-    opts, keep = make_options(items, e_items, batch_budget, batch_items)
+    opts, keep = make_options(items, e_items, batch_budget, batch_items, stats)
     dev = next(t for t in tensors.values() if hasattr(t, "device")).device
     need = ltriples_workspace_size(dom, precision, opts)
     if workspace is None:

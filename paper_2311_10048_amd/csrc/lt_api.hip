@@ -322,12 +322,36 @@ void log_plan(const Plan& P) {
 
 template <typename T> T* at(void* ws, const Buf& b) { return (T*)((char*)ws + b.off); }
 
+// HIP-event timing of the call's phases (only when the caller asks for stats)
+struct Timing {
+  bool on = false;
+  hipStream_t st = nullptr;
+  std::vector<hipEvent_t> evs;
+  hipEvent_t start = nullptr, setup_end = nullptr, end = nullptr;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> gemm, epi;
+  double gemm_flops = 0;
+  hipEvent_t mark() {
+    if (!on) return nullptr;
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    (void)hipEventRecord(e, st);
+    evs.push_back(e);
+    return e;
+  }
+  ~Timing() { for (auto e : evs) (void)hipEventDestroy(e); }
+  static double ms(hipEvent_t a, hipEvent_t b) {
+    float x = 0.f;
+    if (a && b) (void)hipEventElapsedTime(&x, a, b);
+    return (double)x;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Launch sequence
 // ---------------------------------------------------------------------------
 template <typename T>
 int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltriples_options* o,
-        double* e_out, double* parts, void* ws, hipStream_t st) {
+        double* e_out, double* parts, void* ws, hipStream_t st, Timing& tm) {
   const Dims& D = P.D;
   const int64_t Q = D.Q;
   const double* Bvv[2] = {d->Bvv_a, d->Bvv_b};
@@ -360,6 +384,7 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
   // host vectors must outlive the copies
   HIPCHK(hipStreamSynchronize(st));
   double* e_items = (o && o->e_items) ? o->e_items : at<double>(ws, P.e_items);
+  tm.start = tm.mark();
 
   // --- 1. DF factor layouts --------------------------------------------------
   for (int s = 0; s < 2; ++s) {
@@ -491,6 +516,7 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
                  P.ldvv[s], 0, at<T>(ws, P.Mts[s]), vs * lc, 0, vs, 0, lc, 1, (int32_t)vs));
   }
 
+  tm.setup_end = tm.mark();
   // --- 5. triplet batches --------------------------------------------------------------
   for (int b = 0; b < 4; ++b) {
     const int64_t nblk = P.n_blk[b];
@@ -521,11 +547,18 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
       ops.items = items;
       lt::GemmArgs<T> g{};
       g.nbatch = (int32_t)n; g.mode = 1; g.s_nr = 1;
+      hipEvent_t ea = nullptr;
       if (!mixed) {
         ops.kind = 0;
         g.M = (int32_t)vs; g.N = (int32_t)npair(vs); g.out = out1; g.obs = (int64_t)(o1 / P.ts); g.s_mr = P.ldnp[s];
         g.ops = ops;
-        HIPCHK(lt::launch_gemm<T>(g, st));
+        {
+          hipEvent_t a = tm.mark();
+          HIPCHK(lt::launch_gemm<T>(g, st));
+          tm.gemm.push_back({a, tm.mark()});
+          tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(3 * vs + 3 * os) * (double)n;
+        }
+        ea = tm.mark();
         lt::EpiSame<T> e{};
         e.o = (int32_t)os; e.v = (int32_t)vs; e.ld_np = P.ldnp[s];
         e.S = out1; e.s_item = (int64_t)(o1 / P.ts); e.items = items;
@@ -537,11 +570,22 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
         ops.kind = 1;
         g.M = (int32_t)vs; g.N = (int32_t)(vt * vs); g.out = out1; g.obs = (int64_t)(o1 / P.ts); g.s_mr = P.ldcb[s];
         g.ops = ops;
-        HIPCHK(lt::launch_gemm<T>(g, st));
+        {
+          hipEvent_t a = tm.mark();
+          HIPCHK(lt::launch_gemm<T>(g, st));
+          tm.gemm.push_back({a, tm.mark()});
+          tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(2 * vt + vs + os + 2 * ot) * (double)n;
+        }
         ops.kind = 2;
         g.M = (int32_t)vt; g.N = (int32_t)npair(vs); g.out = out2; g.obs = (int64_t)(o2 / P.ts); g.s_mr = P.ldnp[s];
         g.ops = ops;
-        HIPCHK(lt::launch_gemm<T>(g, st));
+        {
+          hipEvent_t a = tm.mark();
+          HIPCHK(lt::launch_gemm<T>(g, st));
+          tm.gemm.push_back({a, tm.mark()});
+          tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(2 * vs + 2 * os) * (double)n;
+        }
+        ea = tm.mark();
         lt::EpiMixed<T> e{};
         e.o_s = (int32_t)os; e.v_s = (int32_t)vs; e.o_t = (int32_t)ot; e.v_t = (int32_t)vt;
         e.ld_np = P.ldnp[s]; e.ld_cb = P.ldcb[s];
@@ -562,11 +606,13 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
         HIPCHK(lt::launch_epi_mixed<T>(e, (int32_t)n, st));
       }
       HIPCHK(lt::launch_reduce_items(part, (int32_t)n, (int32_t)nt, d_dst + fc[b] + first, e_items, st));
+      tm.epi.push_back({ea, tm.mark()});
     }
   }
 
   // --- 6. totals ----------------------------------------------------------------------
   HIPCHK(lt::launch_reduce_final(e_items, d_dst, d_fc, d_fc + 4, parts, e_out, st));
+  tm.end = tm.mark();
   (void)ob;
   return LT_OK;
 }
@@ -661,8 +707,26 @@ int ltriples_energy(const ltriples_domain* d, int32_t precision, const ltriples_
     if (own) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(ws)); }
     return LT_OK;
   }
-  if (precision == LT_FP64) r = run<double>(d, P, L, o, e_out, parts, ws, st);
-  else r = run<float>(d, P, L, o, e_out, parts, ws, st);
+  Timing tm;
+  tm.on = o && o->stats;
+  tm.st = st;
+  if (precision == LT_FP64) r = run<double>(d, P, L, o, e_out, parts, ws, st, tm);
+  else r = run<float>(d, P, L, o, e_out, parts, ws, st, tm);
+  if (r == LT_OK && tm.on) {
+    HIPCHK(hipStreamSynchronize(st));
+    ltriples_stats* S = o->stats;
+    *S = ltriples_stats{};
+    S->total_ms = Timing::ms(tm.start, tm.end);
+    S->setup_ms = Timing::ms(tm.start, tm.setup_end);
+    for (auto& x : tm.gemm) S->triples_gemm_ms += Timing::ms(x.first, x.second);
+    for (auto& x : tm.epi) S->epilogue_ms += Timing::ms(x.first, x.second);
+    S->triples_gemm_launches = (int64_t)tm.gemm.size();
+    S->triples_gemm_flops = tm.gemm_flops;
+    double f = 0;
+    for (int b = 0; b < 4; ++b) f += (double)P.n_blk[b] * item_flops(D, b);
+    S->algorithmic_flops = f;
+    S->n_items = L.total;
+  }
   if (own) {
     hipError_t e1 = hipStreamSynchronize(st);
     hipError_t e2 = hipFree(ws);

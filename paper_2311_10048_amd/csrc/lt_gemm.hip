@@ -71,15 +71,17 @@ __device__ inline typename Vec<T>::type vscale(typename Vec<T>::type v, float s)
   return v;
 }
 
-template <typename T, int MB>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs<T> g) {
+// Work-group tile: 4 waves in a WM x (4/WM) grid; each wave owns MBW x NBW
+// MFMA blocks, so BM = WM*MBW*BR rows and BN = (4/WM)*NBW*BC columns.
+template <typename T, int MBW, int NBW, int WM, int BK>
+__device__ __forceinline__ void gemm_body(const GemmArgs<T>& g) {
   using F = MF<T>;
   using V = typename Vec<T>::type;
   constexpr int VN = Vec<T>::N;
   constexpr int BR = F::BR, BC = F::BC;
-  constexpr int BM = MB * BR;
-  constexpr int BN = 4 * BC;
-  constexpr int BK = 16;
+  constexpr int WN = 4 / WM;
+  constexpr int BM = WM * MBW * BR;
+  constexpr int BN = WN * NBW * BC;
   constexpr int AROW = BM / VN, BROW = BN / VN;       // vectors per staged row
   constexpr int AV = BK * AROW, BV = BK * BROW;
   constexpr int AVT = (AV + 255) / 256, BVT = (BV + 255) / 256;
@@ -88,6 +90,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<T> g) {
   __shared__ __attribute__((aligned(16))) T Bs[2][BK][BN];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
 
   // logical tile id: consecutive ids share an XCD
   int b = blockIdx.x;
@@ -113,11 +116,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<T> g) {
     return item_seg(g.ops, ti, tj, tk, idx);
   };
 
-  typename F::acc_t acc[MB];
+  typename F::acc_t acc[MBW][NBW];
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
+  for (int mb = 0; mb < MBW; ++mb)
 #pragma unroll
-    for (int r = 0; r < F::NACC; ++r) acc[mb][r] = 0;
+    for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+      for (int r = 0; r < F::NACC; ++r) acc[mb][nb][r] = 0;
 
   V ra[AVT], rb[BVT];
   auto gload = [&](int s, int k0) {
@@ -161,6 +166,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<T> g) {
   if (s < nseg) { gload(s, k0); sstore(0); }
   __syncthreads();
   int cur = 0;
+  const int arow0 = wm * MBW * BR + F::a_row(lane);
+  const int bcol0 = wn * NBW * BC + F::c_col(lane);
   while (s < nseg) {
     k0 += BK;
     while (s < nseg && k0 >= seg(s).K) { ++s; k0 = 0; }
@@ -168,11 +175,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<T> g) {
     if (more) gload(s, k0);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += F::KS) {
-      const T bv = Bs[cur][ks + F::a_k(lane)][wave * BC + F::c_col(lane)];
+      const int kr = ks + F::a_k(lane);
+      T bv[NBW];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const T av = As[cur][ks + F::a_k(lane)][mb * BR + F::a_row(lane)];
-        acc[mb] = F::mma(av, bv, acc[mb]);
+      for (int nb = 0; nb < NBW; ++nb) bv[nb] = Bs[cur][kr][bcol0 + nb * BC];
+#pragma unroll
+      for (int mb = 0; mb < MBW; ++mb) {
+        const T av = As[cur][kr][arow0 + mb * BR];
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = F::mma(av, bv[nb], acc[mb][nb]);
       }
     }
     if (more) sstore(cur ^ 1);
@@ -182,64 +193,78 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<T> g) {
 
   // store
   T* out = g.out + (int64_t)batch * g.obs;
-  const int n = n0 + wave * BC + F::c_col(lane);
-  if (n < g.N) {
+#pragma unroll
+  for (int nb = 0; nb < NBW; ++nb) {
+    const int n = n0 + bcol0 + nb * BC;
+    if (n >= g.N) continue;
     const int64_t noff = g.ndiv ? (int64_t)(n / g.ndiv) * g.s_nq + (int64_t)(n % g.ndiv) * g.s_nr
                                 : (int64_t)n * g.s_nr;
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
+    for (int mb = 0; mb < MBW; ++mb)
 #pragma unroll
       for (int r = 0; r < F::NACC; ++r) {
-        const int m = m0 + mb * BR + F::c_row(lane, r);
+        const int m = m0 + wm * MBW * BR + mb * BR + F::c_row(lane, r);
         if (m < g.M) {
           const int64_t moff = g.mdiv ? (int64_t)(m / g.mdiv) * g.s_mq + (int64_t)(m % g.mdiv) * g.s_mr
                                       : (int64_t)m * g.s_mr;
-          out[moff + noff] = acc[mb][r];
+          out[moff + noff] = acc[mb][nb][r];
         }
       }
   }
 }
 
-template <typename T, int MB>
-static hipError_t launch_mb(GemmArgs<T> g, hipStream_t s) {
-  constexpr int BM = MB * MF<T>::BR, BN = 4 * MF<T>::BC;
+// Two entry points with distinct names so that profiles separate the
+// integral builds from the triplet contractions.
+template <typename T, int MBW, int NBW, int WM, int BK>
+__global__ __launch_bounds__(256) void k_dfgemm(GemmArgs<T> g) { gemm_body<T, MBW, NBW, WM, BK>(g); }
+template <typename T, int MBW, int NBW, int WM, int BK>
+__global__ __launch_bounds__(256) void k_tgemm(GemmArgs<T> g) { gemm_body<T, MBW, NBW, WM, BK>(g); }
+
+template <typename T, int MBW, int NBW, int WM, int BK>
+hipError_t launch_cfg(GemmArgs<T> g, hipStream_t s) {
+  constexpr int BM = WM * MBW * MF<T>::BR, BN = (4 / WM) * NBW * MF<T>::BC;
   g.mt = (g.M + BM - 1) / BM;
   g.nt = (g.N + BN - 1) / BN;
   const int64_t nblk = (int64_t)g.mt * g.nt * g.nbatch;
   if (nblk <= 0) return hipSuccess;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_gemm<T, MB>), dim3((unsigned)nblk), dim3(256), 0, s, g);
+  if (g.mode == 1)
+    hipLaunchKernelGGL((k_tgemm<T, MBW, NBW, WM, BK>), dim3((unsigned)nblk), dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL((k_dfgemm<T, MBW, NBW, WM, BK>), dim3((unsigned)nblk), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
-// Row-block count: the whole M range in one tile when it fits 16 blocks,
-// otherwise tiles of 4 blocks.
+#ifndef LT_GEMM_NO_DISPATCH
+// Row-block count: the whole M range in one tile when it fits, otherwise
+// tiles of 4 row blocks.
 template <> hipError_t launch_gemm<float>(const GemmArgs<float>& g, hipStream_t s) {
   const int need = (g.M + 31) / 32;
-  if (need <= 1) return launch_mb<float, 1>(g, s);
-  if (need <= 2) return launch_mb<float, 2>(g, s);
-  if (need <= 3) return launch_mb<float, 3>(g, s);
-  if (need <= 4) return launch_mb<float, 4>(g, s);
-  if (need <= 6) return launch_mb<float, 6>(g, s);
-  if (need <= 8) return launch_mb<float, 8>(g, s);
-  if (need <= 10) return launch_mb<float, 10>(g, s);
-  if (need <= 12) return launch_mb<float, 12>(g, s);
-  if (need <= 16) return launch_mb<float, 16>(g, s);
-  return launch_mb<float, 4>(g, s);
+  if (need <= 1) return launch_cfg<float, 1, 1, 1, 16>(g, s);
+  if (need <= 2) return launch_cfg<float, 2, 1, 1, 16>(g, s);
+  if (need <= 3) return launch_cfg<float, 3, 1, 1, 16>(g, s);
+  if (need <= 4) return launch_cfg<float, 4, 1, 1, 16>(g, s);
+  if (need <= 6) return launch_cfg<float, 6, 1, 1, 16>(g, s);
+  if (need <= 8) return launch_cfg<float, 8, 1, 1, 16>(g, s);
+  if (need <= 10) return launch_cfg<float, 10, 1, 1, 16>(g, s);
+  if (need <= 12) return launch_cfg<float, 12, 1, 1, 16>(g, s);
+  if (need <= 16) return launch_cfg<float, 16, 1, 1, 16>(g, s);
+  return launch_cfg<float, 4, 1, 1, 16>(g, s);
 }
 
 template <> hipError_t launch_gemm<double>(const GemmArgs<double>& g, hipStream_t s) {
   const int need = (g.M + 15) / 16;
-  if (need <= 2) return launch_mb<double, 2>(g, s);
-  if (need <= 4) return launch_mb<double, 4>(g, s);
-  if (need <= 6) return launch_mb<double, 6>(g, s);
-  if (need <= 8) return launch_mb<double, 8>(g, s);
-  if (need <= 12) return launch_mb<double, 12>(g, s);
-  if (need <= 16) return launch_mb<double, 16>(g, s);
-  if (need <= 20) return launch_mb<double, 20>(g, s);
-  if (need <= 24) return launch_mb<double, 24>(g, s);
-  if (need <= 32) return launch_mb<double, 32>(g, s);
-  return launch_mb<double, 8>(g, s);
+  if (need <= 2) return launch_cfg<double, 2, 1, 1, 16>(g, s);
+  if (need <= 4) return launch_cfg<double, 4, 1, 1, 16>(g, s);
+  if (need <= 6) return launch_cfg<double, 6, 1, 1, 16>(g, s);
+  if (need <= 8) return launch_cfg<double, 8, 1, 1, 16>(g, s);
+  if (need <= 12) return launch_cfg<double, 12, 1, 1, 16>(g, s);
+  if (need <= 16) return launch_cfg<double, 16, 1, 1, 16>(g, s);
+  if (need <= 20) return launch_cfg<double, 20, 1, 1, 16>(g, s);
+  if (need <= 24) return launch_cfg<double, 24, 1, 1, 16>(g, s);
+  if (need <= 32) return launch_cfg<double, 32, 1, 1, 16>(g, s);
+  return launch_cfg<double, 8, 1, 1, 16>(g, s);
 }
+#endif
 
 }  // namespace lt
