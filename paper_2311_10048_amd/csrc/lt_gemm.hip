@@ -236,34 +236,34 @@ hipError_t launch_cfg(GemmArgs<T> g, hipStream_t s) {
 }
 
 #ifndef LT_GEMM_NO_DISPATCH
-// Row-block count: the whole M range in one tile when it fits, otherwise
-// tiles of 4 row blocks.
+// Tile choice (measured on gfx950 at the triplet-contraction shapes): the
+// whole M range in one work-group tile when it fits, 2 x 2 waves for
+// M > 96; FP64 with K chunks of 8.  Large-M integral builds use 128-row tiles.
 template <> hipError_t launch_gemm<float>(const GemmArgs<float>& g, hipStream_t s) {
   const int need = (g.M + 31) / 32;
   if (need <= 1) return launch_cfg<float, 1, 1, 1, 16>(g, s);
   if (need <= 2) return launch_cfg<float, 2, 1, 1, 16>(g, s);
   if (need <= 3) return launch_cfg<float, 3, 1, 1, 16>(g, s);
-  if (need <= 4) return launch_cfg<float, 4, 1, 1, 16>(g, s);
-  if (need <= 6) return launch_cfg<float, 6, 1, 1, 16>(g, s);
-  if (need <= 8) return launch_cfg<float, 8, 1, 1, 16>(g, s);
-  if (need <= 10) return launch_cfg<float, 10, 1, 1, 16>(g, s);
-  if (need <= 12) return launch_cfg<float, 12, 1, 1, 16>(g, s);
-  if (need <= 16) return launch_cfg<float, 16, 1, 1, 16>(g, s);
-  return launch_cfg<float, 4, 1, 1, 16>(g, s);
+  if (need <= 4) return launch_cfg<float, 2, 2, 2, 16>(g, s);
+  if (need <= 6) return launch_cfg<float, 3, 2, 2, 16>(g, s);
+  if (need <= 8) return launch_cfg<float, 4, 2, 2, 16>(g, s);
+  if (need <= 10) return launch_cfg<float, 5, 2, 2, 16>(g, s);
+  if (need <= 12) return launch_cfg<float, 6, 2, 2, 16>(g, s);
+  if (need <= 16) return launch_cfg<float, 4, 2, 2, 16>(g, s);   // two row tiles
+  return launch_cfg<float, 2, 2, 2, 16>(g, s);
 }
 
 template <> hipError_t launch_gemm<double>(const GemmArgs<double>& g, hipStream_t s) {
   const int need = (g.M + 15) / 16;
-  if (need <= 2) return launch_cfg<double, 2, 1, 1, 16>(g, s);
-  if (need <= 4) return launch_cfg<double, 4, 1, 1, 16>(g, s);
-  if (need <= 6) return launch_cfg<double, 6, 1, 1, 16>(g, s);
-  if (need <= 8) return launch_cfg<double, 8, 1, 1, 16>(g, s);
-  if (need <= 12) return launch_cfg<double, 12, 1, 1, 16>(g, s);
-  if (need <= 16) return launch_cfg<double, 16, 1, 1, 16>(g, s);
-  if (need <= 20) return launch_cfg<double, 20, 1, 1, 16>(g, s);
-  if (need <= 24) return launch_cfg<double, 24, 1, 1, 16>(g, s);
-  if (need <= 32) return launch_cfg<double, 32, 1, 1, 16>(g, s);
-  return launch_cfg<double, 8, 1, 1, 16>(g, s);
+  if (need <= 2) return launch_cfg<double, 2, 1, 1, 8>(g, s);
+  if (need <= 4) return launch_cfg<double, 4, 1, 1, 8>(g, s);
+  if (need <= 8) return launch_cfg<double, 4, 2, 2, 8>(g, s);
+  if (need <= 12) return launch_cfg<double, 6, 2, 2, 8>(g, s);
+  if (need <= 16) return launch_cfg<double, 8, 2, 2, 8>(g, s);
+  if (need <= 20) return launch_cfg<double, 10, 2, 2, 8>(g, s);
+  if (need <= 24) return launch_cfg<double, 12, 2, 2, 8>(g, s);
+  if (need <= 32) return launch_cfg<double, 16, 2, 2, 8>(g, s);
+  return launch_cfg<double, 4, 2, 2, 8>(g, s);
 }
 #endif
 
