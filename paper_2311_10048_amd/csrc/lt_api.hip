@@ -88,8 +88,8 @@ int validate(const ltriples_domain* d, int32_t prec, const ltriples_options* o) 
   if (!d) return fail(LT_EINVAL, "domain is NULL");
   if (d->noa < 0 || d->nob < 0 || d->nva < 0 || d->nvb < 0 || d->naux < 0)
     return fail(LT_EINVAL, "negative dimension");
-  if (prec != LT_FP64 && prec != LT_FP32)
-    return fail(LT_EPREC, "precision %d not supported by this build", prec);
+  if (prec != LT_FP64 && prec != LT_FP32 && prec != LT_BF16X3 && prec != LT_BF16)
+    return fail(LT_EPREC, "unsupported precision %d", prec);
   const int64_t oa = d->noa, ob = d->nob, va = d->nva, vb = d->nvb, Q = d->naux;
   struct P { const double* p; int64_t n; const char* name; } ps[] = {
       {d->t1a, oa * va, "t1a"}, {d->t1b, ob * vb, "t1b"},
@@ -180,6 +180,10 @@ struct Plan {
   Buf As[2], Tp[2], T2T[2], GamT[2], U[2];
   Buf LmixT[2], Mst[2], Mts[2], Tmix[2], ZpT[2], TmT[2], OOT[2];
   Buf OVab, e_items, trip, dst, order, firstcnt;
+  // BF16 modes: hi/lo octet copies of the contraction operands
+  int bf = 0;                     // 0: none, 3: split products, 1: plain bf16
+  enum { T2T8, As8, GamT8, Tp8, LmixT8, Mst8, Mts8, Tmix8, Tmx28, ZpT8, TmT8, OOT8, NT8 };
+  Buf O8h[2][NT8], O8l[2][NT8];
   // scratch
   Buf scratch;
   size_t sc_OO[2][2], sc_OV[2];   // offsets within scratch (phase 1a)
@@ -193,7 +197,7 @@ struct Plan {
 void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options* o,
                  const ItemLists& L, Plan& P) {
   P.prec = prec;
-  P.ts = prec == LT_FP64 ? 8 : 4;
+  P.ts = prec == LT_FP64 ? 8 : 4;   // BF16 modes prepare FP32 operands, then split them
   P.D = dims_of(d);
   const Dims& D = P.D;
   for (int b = 0; b < 4; ++b) P.n_blk[b] = (int64_t)L.dst[b].size();
@@ -243,6 +247,35 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
     }
   }
   if (P.any_mix) take(P.OVab, 8 * D.o[0] * D.v[0] * D.o[1] * D.v[1]);
+  P.bf = prec == LT_BF16X3 ? 3 : (prec == LT_BF16 ? 1 : 0);
+  if (P.bf) {
+    auto k8 = [](int64_t k) { return (k + 7) & ~int64_t(7); };
+    auto take8 = [&](int s, int t, int64_t nblk, int64_t K, int64_t ld) {
+      const size_t bytes = 2 * (size_t)(nblk * k8(K) * ld);
+      take(P.O8h[s][t], bytes);
+      take(P.O8l[s][t], bytes);
+    };
+    for (int s = 0; s < 2; ++s) {
+      const int t = 1 - s;
+      const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
+      if (P.need_as[s]) {
+        take8(s, Plan::T2T8, os * os, vs, P.ldv[s]);
+        take8(s, Plan::As8, os, vs, P.ldnp[s]);
+        take8(s, Plan::GamT8, os * os, os, P.ldv[s]);
+        take8(s, Plan::Tp8, os, os, P.ldnp[s]);
+      }
+      if (P.need_mix[s]) {
+        take8(s, Plan::LmixT8, os * ot, vt, P.ldv[s]);
+        take8(s, Plan::Mst8, os, vt, P.ldcb[s]);
+        take8(s, Plan::Mts8, ot, vs, P.ldcb[s]);
+        take8(s, Plan::Tmix8, os, ot, P.ldcb[s]);
+        take8(s, Plan::Tmx28, ot, os, P.ldcb[s]);
+        take8(s, Plan::ZpT8, os * ot, ot, P.ldv[s]);
+        take8(s, Plan::TmT8, os * ot, vs, P.ldv[t]);
+        take8(s, Plan::OOT8, ot * os, os, P.ldv[t]);
+      }
+    }
+  }
   take(P.e_items, 8 * 3 * std::max<int64_t>(L.total, 1));
   take(P.trip, 4 * 3 * std::max<int64_t>(L.total, 1));
   take(P.dst, 4 * std::max<int64_t>(L.total, 1));
@@ -516,6 +549,34 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
                  P.ldvv[s], 0, at<T>(ws, P.Mts[s]), vs * lc, 0, vs, 0, lc, 1, (int32_t)vs));
   }
 
+  if (P.bf) {
+    auto split = [&](int s, int t8, int64_t nblk, int64_t K, int64_t ld, int64_t ncol, const T* in, int64_t ibs,
+                     int64_t iks) -> hipError_t {
+      return lt::launch_split8(at<lt::bf16_t>(ws, P.O8h[s][t8]), at<lt::bf16_t>(ws, P.O8l[s][t8]), nblk, (int32_t)K,
+                               ld, (int32_t)ncol, (const float*)in, ibs, iks, st);
+    };
+    for (int s = 0; s < 2; ++s) {
+      const int t = 1 - s;
+      const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
+      const int64_t lv = P.ldv[s], lvt = P.ldv[t], lp = P.ldnp[s], lc = P.ldcb[s], np = npair(vs);
+      if (P.need_as[s]) {
+        HIPCHK(split(s, Plan::T2T8, os * os, vs, lv, vs, at<T>(ws, P.T2T[s]), vs * lv, lv));
+        HIPCHK(split(s, Plan::As8, os, vs, lp, np, at<T>(ws, P.As[s]), vs * lp, lp));
+        HIPCHK(split(s, Plan::GamT8, os * os, os, lv, vs, at<T>(ws, P.GamT[s]), os * lv, lv));
+        HIPCHK(split(s, Plan::Tp8, os, os, lp, np, at<T>(ws, P.Tp[s]), os * lp, lp));
+      }
+      if (P.need_mix[s]) {
+        HIPCHK(split(s, Plan::LmixT8, os * ot, vt, lv, vs, at<T>(ws, P.LmixT[s]), vt * lv, lv));
+        HIPCHK(split(s, Plan::Mst8, os, vt, lc, vt * vs, at<T>(ws, P.Mst[s]), vt * lc, lc));
+        HIPCHK(split(s, Plan::Mts8, ot, vs, lc, vt * vs, at<T>(ws, P.Mts[s]), vs * lc, lc));
+        HIPCHK(split(s, Plan::Tmix8, os, ot, lc, vt * vs, at<T>(ws, P.Tmix[s]), ot * lc, lc));
+        HIPCHK(split(s, Plan::Tmx28, ot, os, lc, vt * vs, at<T>(ws, P.Tmix[s]), lc, ot * lc));
+        HIPCHK(split(s, Plan::ZpT8, os * ot, ot, lv, vs, at<T>(ws, P.ZpT[s]), ot * lv, lv));
+        HIPCHK(split(s, Plan::TmT8, os * ot, vs, lvt, vt, at<T>(ws, P.TmT[s]), vs * lvt, lvt));
+        HIPCHK(split(s, Plan::OOT8, ot * os, os, lvt, vt, at<T>(ws, P.OOT[s]), os * lvt, lvt));
+      }
+    }
+  }
   tm.setup_end = tm.mark();
   // --- 5. triplet batches --------------------------------------------------------------
   for (int b = 0; b < 4; ++b) {
@@ -534,6 +595,28 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
       ops.Tmix = at<T>(ws, P.Tmix[s]); ops.ZpT = at<T>(ws, P.ZpT[s]); ops.TmT = at<T>(ws, P.TmT[s]);
       ops.OOT = at<T>(ws, P.OOT[s]);
     }
+    lt::ItemOps8 o8{};
+    if (P.bf) {
+      o8.o_s = ops.o_s; o8.v_s = ops.v_s; o8.o_t = ops.o_t; o8.v_t = ops.v_t;
+      o8.ld_vs = ops.ld_vs; o8.ld_vt = ops.ld_vt; o8.ld_np = ops.ld_np; o8.ld_cb = ops.ld_cb;
+      auto H = [&](int t8) { return P.O8h[s][t8].bytes ? at<lt::bf16_t>(ws, P.O8h[s][t8]) : nullptr; };
+      auto Lo = [&](int t8) { return P.O8l[s][t8].bytes ? at<lt::bf16_t>(ws, P.O8l[s][t8]) : nullptr; };
+      o8.T2Th = H(Plan::T2T8); o8.T2Tl = Lo(Plan::T2T8); o8.Ash = H(Plan::As8); o8.Asl = Lo(Plan::As8);
+      o8.GamTh = H(Plan::GamT8); o8.GamTl = Lo(Plan::GamT8); o8.Tph = H(Plan::Tp8); o8.Tpl = Lo(Plan::Tp8);
+      o8.LmixTh = H(Plan::LmixT8); o8.LmixTl = Lo(Plan::LmixT8); o8.Msth = H(Plan::Mst8); o8.Mstl = Lo(Plan::Mst8);
+      o8.Mtsh = H(Plan::Mts8); o8.Mtsl = Lo(Plan::Mts8); o8.Tmixh = H(Plan::Tmix8); o8.Tmixl = Lo(Plan::Tmix8);
+      o8.Tmx2h = H(Plan::Tmx28); o8.Tmx2l = Lo(Plan::Tmx28); o8.ZpTh = H(Plan::ZpT8); o8.ZpTl = Lo(Plan::ZpT8);
+      o8.TmTh = H(Plan::TmT8); o8.TmTl = Lo(Plan::TmT8); o8.OOTh = H(Plan::OOT8); o8.OOTl = Lo(Plan::OOT8);
+    }
+    // contraction of one batch: FP64/FP32 matrix cores, or split BF16
+    auto contract = [&](lt::GemmArgs<T>& g) -> hipError_t {
+      if (!P.bf) return lt::launch_gemm<T>(g, st);
+      lt::GemmArgs16 h{};
+      h.M = g.M; h.N = g.N; h.nbatch = g.nbatch; h.nprod = P.bf;
+      h.out = (float*)g.out; h.obs = g.obs; h.ldo = g.s_mr;
+      h.ops = o8; h.ops.kind = g.ops.kind; h.ops.items = g.ops.items;
+      return lt::launch_gemm_bf16(h, st);
+    };
     const int64_t nb = P.nb[b];
     T* out1 = (T*)scr;
     const size_t o1 = align256(P.ts * (size_t)(mixed ? vs * P.ldcb[s] : vs * P.ldnp[s]));
@@ -554,7 +637,7 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
         g.ops = ops;
         {
           hipEvent_t a = tm.mark();
-          HIPCHK(lt::launch_gemm<T>(g, st));
+          HIPCHK(contract(g));
           tm.gemm.push_back({a, tm.mark()});
           tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(3 * vs + 3 * os) * (double)n;
         }
@@ -572,7 +655,7 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
         g.ops = ops;
         {
           hipEvent_t a = tm.mark();
-          HIPCHK(lt::launch_gemm<T>(g, st));
+          HIPCHK(contract(g));
           tm.gemm.push_back({a, tm.mark()});
           tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(2 * vt + vs + os + 2 * ot) * (double)n;
         }
@@ -581,7 +664,7 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
         g.ops = ops;
         {
           hipEvent_t a = tm.mark();
-          HIPCHK(lt::launch_gemm<T>(g, st));
+          HIPCHK(contract(g));
           tm.gemm.push_back({a, tm.mark()});
           tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(2 * vs + 2 * os) * (double)n;
         }
@@ -711,7 +794,7 @@ int ltriples_energy(const ltriples_domain* d, int32_t precision, const ltriples_
   tm.on = o && o->stats;
   tm.st = st;
   if (precision == LT_FP64) r = run<double>(d, P, L, o, e_out, parts, ws, st, tm);
-  else r = run<float>(d, P, L, o, e_out, parts, ws, st, tm);
+  else r = run<float>(d, P, L, o, e_out, parts, ws, st, tm);   // FP32, BF16X3, BF16
   if (r == LT_OK && tm.on) {
     HIPCHK(hipStreamSynchronize(st));
     ltriples_stats* S = o->stats;

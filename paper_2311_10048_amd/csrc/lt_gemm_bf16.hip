@@ -1,0 +1,230 @@
+// Triplet contractions on the BF16 matrix cores with split-precision
+// operands: every FP32 operand x is carried as hi = bf16(x) and
+// lo = bf16(x - hi) (prepared once per call in octet layout), and each
+// product is formed as hi*hi + hi*lo + lo*hi with FP32 accumulation
+// (v_mfma_f32_32x32x16_bf16, three instructions per K step), or as the
+// single hi*hi product for the plain-BF16 ablation.  The dropped lo*lo term
+// and the rounding of lo leave a relative error of about 2^-16 per product.
+//
+// Tiling mirrors the FP32 kernel: 4 waves in a 2x2 grid, each owning
+// MBW x NBW 32x32 blocks, the whole virtual range of the contraction in one
+// work-group tile, K advancing by 16 (two octets) per double-buffered LDS
+// stage; every global load is one 16-byte octet.
+#include "lt_internal.h"
+
+namespace lt {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline int64_t k8(int64_t k) { return (k + 7) & ~int64_t(7); }
+
+// Segment idx of the contraction of triplet (i, j, k); see item_seg in
+// lt_gemm.hip for the equations (same terms, same order, same signs).
+__device__ inline Seg8 item_seg8(const ItemOps8& s, int64_t i, int64_t j, int64_t k, int idx) {
+  const int64_t o = s.o_s, v = s.v_s, ot = s.o_t, vt = s.v_t;
+  const int64_t lv = s.ld_vs, lt_ = s.ld_vt, lp = s.ld_np, lc = s.ld_cb;
+  const int64_t kv = k8(v), ko = k8(o), kvt = k8(vt), kot = k8(ot);
+  // block sizes (elements) of each octet tensor
+  const int64_t bT2T = kv * lv, bAs = kv * lp, bGam = ko * lv, bTp = ko * lp;
+  auto mk = [](const bf16_t* Lh, const bf16_t* Ll, int64_t lo, int64_t ll, const bf16_t* Rh, const bf16_t* Rl,
+               int64_t ro, int64_t rl, int64_t K, float sg) -> Seg8 {
+    return {Lh + lo, Ll + lo, ll * 8, Rh + ro, Rl + ro, rl * 8, (int32_t)K, sg};
+  };
+  if (s.kind == 0) {
+    switch (idx) {
+      case 0: return mk(s.T2Th, s.T2Tl, (j * o + k) * bT2T, lv, s.Ash, s.Asl, i * bAs, lp, v, 1.f);
+      case 1: return mk(s.T2Th, s.T2Tl, (i * o + k) * bT2T, lv, s.Ash, s.Asl, j * bAs, lp, v, -1.f);
+      case 2: return mk(s.T2Th, s.T2Tl, (j * o + i) * bT2T, lv, s.Ash, s.Asl, k * bAs, lp, v, -1.f);
+      case 3: return mk(s.GamTh, s.GamTl, (j * o + k) * bGam, lv, s.Tph, s.Tpl, i * bTp, lp, o, -1.f);
+      case 4: return mk(s.GamTh, s.GamTl, (i * o + k) * bGam, lv, s.Tph, s.Tpl, j * bTp, lp, o, 1.f);
+      default: return mk(s.GamTh, s.GamTl, (j * o + i) * bGam, lv, s.Tph, s.Tpl, k * bTp, lp, o, 1.f);
+    }
+  }
+  if (s.kind == 1) {
+    const int64_t bLm = kvt * lv, bMst = kvt * lc, bMts = kv * lc, bTmx2 = ko * lc, bTmix = kot * lc,
+                  bZp = kot * lv;
+    switch (idx) {
+      case 0: return mk(s.LmixTh, s.LmixTl, (i * ot + k) * bLm, lv, s.Msth, s.Mstl, j * bMst, lc, vt, 1.f);
+      case 1: return mk(s.LmixTh, s.LmixTl, (j * ot + k) * bLm, lv, s.Msth, s.Mstl, i * bMst, lc, vt, -1.f);
+      case 2: return mk(s.T2Th, s.T2Tl, (i * o + j) * bT2T, lv, s.Mtsh, s.Mtsl, k * bMts, lc, v, 1.f);
+      case 3: return mk(s.GamTh, s.GamTl, (i * o + j) * bGam, lv, s.Tmx2h, s.Tmx2l, k * bTmx2, lc, o, 1.f);
+      case 4: return mk(s.ZpTh, s.ZpTl, (j * ot + k) * bZp, lv, s.Tmixh, s.Tmixl, i * bTmix, lc, ot, 1.f);
+      default: return mk(s.ZpTh, s.ZpTl, (i * ot + k) * bZp, lv, s.Tmixh, s.Tmixl, j * bTmix, lc, ot, -1.f);
+    }
+  }
+  const int64_t bTmT = kv * lt_, bOOT = ko * lt_;
+  switch (idx) {
+    case 0: return mk(s.TmTh, s.TmTl, (i * ot + k) * bTmT, lt_, s.Ash, s.Asl, j * bAs, lp, v, 1.f);
+    case 1: return mk(s.TmTh, s.TmTl, (j * ot + k) * bTmT, lt_, s.Ash, s.Asl, i * bAs, lp, v, -1.f);
+    case 2: return mk(s.OOTh, s.OOTl, (k * o + j) * bOOT, lt_, s.Tph, s.Tpl, i * bTp, lp, o, -1.f);
+    default: return mk(s.OOTh, s.OOTl, (k * o + i) * bOOT, lt_, s.Tph, s.Tpl, j * bTp, lp, o, 1.f);
+  }
+}
+
+__device__ inline bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast(bf16x8, u); }
+
+template <int MBW, int NBW, int WM, int NPROD>
+__global__ __launch_bounds__(256) void k_tgemm_bf16(GemmArgs16 g) {
+  constexpr int BR = 32, BC = 32, BKQ = 2;      // 16 k per stage
+  constexpr int WN = 4 / WM;
+  constexpr int BM = WM * MBW * BR, BN = WN * NBW * BC;
+  constexpr int AO = BKQ * BM, BO = BKQ * BN;   // octets per stage (each of hi, lo)
+  constexpr int AVT = (2 * AO + 255) / 256, BVT = (2 * BO + 255) / 256;
+  typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+  __shared__ uint4 As[2][2][BKQ][BM];   // [buf][hi/lo][q][m]
+  __shared__ uint4 Bs[2][2][BKQ][BN];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  int b = blockIdx.x;
+  {
+    const int nblk = gridDim.x, x = b & 7, q = nblk >> 3, r = nblk & 7;
+    b = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + (b >> 3);
+  }
+  const int mtile = b % g.mt; b /= g.mt;
+  const int ntile = b % g.nt; b /= g.nt;
+  const int batch = b;
+  const int m0 = mtile * BM, n0 = ntile * BN;
+  const int32_t* it = g.ops.items + 3 * batch;
+  const int64_t ti = it[0], tj = it[1], tk = it[2];
+  const int nseg = g.ops.kind == 2 ? 4 : 6;
+
+  f32x16 acc[MBW][NBW];
+#pragma unroll
+  for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.f;
+
+  uint4 ra[AVT], rb[BVT];
+  auto gload = [&](int s, int k0) {
+    const Seg8 sg = item_seg8(g.ops, ti, tj, tk, s);
+    const uint32_t flip = sg.sign < 0.f ? 0x80008000u : 0u;
+#pragma unroll
+    for (int u = 0; u < AVT; ++u) {
+      const int e = tid + u * 256;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (e < 2 * AO) {
+        const int hl = e / AO, r = e % AO, q = r / BM, m = m0 + r % BM, k = k0 + 8 * q;
+        if (k < sg.K && m < g.M) {
+          const bf16_t* base = hl ? sg.Ll : sg.Lh;
+          v = *(const uint4*)(base + (int64_t)(k >> 3) * sg.lq + (int64_t)m * 8);
+          v.x ^= flip; v.y ^= flip; v.z ^= flip; v.w ^= flip;
+        }
+      }
+      ra[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < BVT; ++u) {
+      const int e = tid + u * 256;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (e < 2 * BO) {
+        const int hl = e / BO, r = e % BO, q = r / BN, n = n0 + r % BN, k = k0 + 8 * q;
+        if (k < sg.K && n < g.N) {
+          const bf16_t* base = hl ? sg.Rl : sg.Rh;
+          v = *(const uint4*)(base + (int64_t)(k >> 3) * sg.rq + (int64_t)n * 8);
+        }
+      }
+      rb[u] = v;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < AVT; ++u) {
+      const int e = tid + u * 256;
+      if (e < 2 * AO) { const int hl = e / AO, r = e % AO; As[buf][hl][r / BM][r % BM] = ra[u]; }
+    }
+#pragma unroll
+    for (int u = 0; u < BVT; ++u) {
+      const int e = tid + u * 256;
+      if (e < 2 * BO) { const int hl = e / BO, r = e % BO; Bs[buf][hl][r / BN][r % BN] = rb[u]; }
+    }
+  };
+
+  constexpr int BK = 8 * BKQ;
+  int s = 0, k0 = 0;
+  while (s < nseg && item_seg8(g.ops, ti, tj, tk, s).K <= 0) ++s;
+  if (s < nseg) { gload(s, k0); sstore(0); }
+  __syncthreads();
+  int cur = 0;
+  const int arow = wm * MBW * BR + (lane & 31);
+  const int bcol = wn * NBW * BC + (lane & 31);
+  const int q = lane >> 5;
+  while (s < nseg) {
+    k0 += BK;
+    while (s < nseg && k0 >= item_seg8(g.ops, ti, tj, tk, s).K) { ++s; k0 = 0; }
+    const bool more = s < nseg;
+    if (more) gload(s, k0);
+    bf16x8 bh[NBW], bl[NBW];
+#pragma unroll
+    for (int nb = 0; nb < NBW; ++nb) {
+      bh[nb] = as_bf16x8(Bs[cur][0][q][bcol + nb * BC]);
+      if (NPROD == 3) bl[nb] = as_bf16x8(Bs[cur][1][q][bcol + nb * BC]);
+    }
+#pragma unroll
+    for (int mb = 0; mb < MBW; ++mb) {
+      const bf16x8 ah = as_bf16x8(As[cur][0][q][arow + mb * BR]);
+      bf16x8 al;
+      if (NPROD == 3) al = as_bf16x8(As[cur][1][q][arow + mb * BR]);
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) {
+        if (NPROD == 3) {
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[nb], acc[mb][nb], 0, 0, 0);
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[nb], acc[mb][nb], 0, 0, 0);
+        }
+        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[nb], acc[mb][nb], 0, 0, 0);
+      }
+    }
+    if (more) sstore(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  float* out = g.out + (int64_t)batch * g.obs;
+#pragma unroll
+  for (int nb = 0; nb < NBW; ++nb) {
+    const int n = n0 + bcol + nb * BC;
+    if (n >= g.N) continue;
+#pragma unroll
+    for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wm * MBW * BR + mb * BR + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (m < g.M) out[(int64_t)m * g.ldo + n] = acc[mb][nb][r];
+      }
+  }
+}
+
+template <int MBW, int NBW, int WM, int NPROD>
+static hipError_t launch16(GemmArgs16 g, hipStream_t s) {
+  constexpr int BM = WM * MBW * 32, BN = (4 / WM) * NBW * 32;
+  g.mt = (g.M + BM - 1) / BM;
+  g.nt = (g.N + BN - 1) / BN;
+  const int64_t nblk = (int64_t)g.mt * g.nt * g.nbatch;
+  if (nblk <= 0) return hipSuccess;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_tgemm_bf16<MBW, NBW, WM, NPROD>), dim3((unsigned)nblk), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+template <int NPROD>
+static hipError_t dispatch16(const GemmArgs16& g, hipStream_t s) {
+  const int need = (g.M + 31) / 32;
+  if (need <= 1) return launch16<1, 1, 1, NPROD>(g, s);
+  if (need <= 2) return launch16<2, 1, 1, NPROD>(g, s);
+  if (need <= 3) return launch16<3, 1, 1, NPROD>(g, s);
+  if (need <= 4) return launch16<2, 2, 2, NPROD>(g, s);
+  if (need <= 6) return launch16<3, 2, 2, NPROD>(g, s);
+  if (need <= 8) return launch16<4, 2, 2, NPROD>(g, s);
+  if (need <= 10) return launch16<5, 2, 2, NPROD>(g, s);
+  if (need <= 12) return launch16<6, 2, 2, NPROD>(g, s);
+  return launch16<4, 2, 2, NPROD>(g, s);   // several row tiles
+}
+
+hipError_t launch_gemm_bf16(const GemmArgs16& g, hipStream_t s) {
+  return g.nprod == 3 ? dispatch16<3>(g, s) : dispatch16<1>(g, s);
+}
+
+}  // namespace lt

@@ -89,6 +89,55 @@ template <typename T> struct GemmArgs {
 };
 
 // ---------------------------------------------------------------------------
+// BF16 split operands.  A prepared FP32 operand viewed as [nblk][K][ld]
+// (block, contraction row k, column) is stored as two bf16 arrays
+// hi = bf16(x), lo = bf16(x - hi), each in "octet" layout
+// [nblk][K8/8][ld][8] with K8 = K rounded up to 8 (extra rows zero): one
+// 16-byte word holds 8 consecutive k of one column, which is exactly one
+// lane's operand of the 32x32x16 BF16 matrix instruction.
+// ---------------------------------------------------------------------------
+typedef uint16_t bf16_t;
+
+struct Seg8 {
+  const bf16_t *Lh, *Ll; int64_t lq;   // L octet (q, m) at L + q*lq + m*8
+  const bf16_t *Rh, *Rl; int64_t rq;   // R octet (q, n) at R + q*rq + n*8
+  int32_t K; float sign;
+};
+
+struct ItemOps8 {
+  int32_t kind;                          // 0: S, 1: G, 2: Y (as ItemOps)
+  int32_t o_s, v_s, o_t, v_t;
+  int64_t ld_vs, ld_vt, ld_np, ld_cb;
+  // hi/lo octet tensors; block = leading indices, K = contraction rows
+  const bf16_t *T2Th, *T2Tl;     // blk (i,j)  K v_s  ld_vs
+  const bf16_t *Tph, *Tpl;       // blk i      K o_s  ld_np
+  const bf16_t *Ash, *Asl;       // blk i      K v_s  ld_np
+  const bf16_t *GamTh, *GamTl;   // blk (j,k)  K o_s  ld_vs
+  const bf16_t *LmixTh, *LmixTl; // blk (i,K)  K v_t  ld_vs
+  const bf16_t *Msth, *Mstl;     // blk j      K v_t  ld_cb
+  const bf16_t *Mtsh, *Mtsl;     // blk K      K v_s  ld_cb
+  const bf16_t *Tmixh, *Tmixl;   // blk i      K o_t  ld_cb   (t^{bC}_{iM} over M)
+  const bf16_t *Tmx2h, *Tmx2l;   // blk K      K o_s  ld_cb   (t^{bC}_{mK} over m)
+  const bf16_t *ZpTh, *ZpTl;     // blk (j,K)  K o_t  ld_vs
+  const bf16_t *TmTh, *TmTl;     // blk (i,K)  K v_s  ld_vt
+  const bf16_t *OOTh, *OOTl;     // blk (K,j)  K o_s  ld_vt
+  const int32_t* items;
+};
+
+struct GemmArgs16 {
+  int32_t M, N, nbatch, mt, nt;
+  int32_t nprod;                         // 3: hi*hi + hi*lo + lo*hi, 1: hi*hi
+  float* out; int64_t obs, ldo;
+  ItemOps8 ops;
+};
+
+hipError_t launch_gemm_bf16(const GemmArgs16& g, hipStream_t s);
+
+// hi/lo octet tensors from FP32 in[b*ibs + k*iks + c], c < ncol, k < K.
+hipError_t launch_split8(bf16_t* hi, bf16_t* lo, int64_t nblk, int32_t K, int64_t ld, int32_t ncol,
+                         const float* in, int64_t ibs, int64_t iks, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // Energy epilogues (FP64): W assembly from the contraction outputs, V, D,
 // per-tile partial sums of {E4, E_ST, E_DT}.
 // ---------------------------------------------------------------------------

@@ -100,6 +100,53 @@ template hipError_t launch_pack_pairs<double, float>(float*, int64_t, int64_t, i
 template hipError_t launch_pack_pairs<float, float>(float*, int64_t, int64_t, int32_t, const float*,
                                                     int64_t, int64_t, int64_t, bool, hipStream_t);
 
+// Round-to-nearest-even FP32 -> BF16 (finite inputs; NaN stays NaN).
+__device__ inline uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// One thread per octet (block, q, column): 8 consecutive contraction rows of
+// one column, split into hi = bf16(x) and lo = bf16(x - hi).
+__global__ __launch_bounds__(256) void k_split8(bf16_t* hi, bf16_t* lo, int64_t nblk, int32_t K, int64_t ld,
+                                                int32_t ncol, const float* in, int64_t ibs, int64_t iks) {
+  const int64_t nq = (K + 7) / 8;
+  const int64_t total = nblk * nq * ld;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e % ld, bq = e / ld, q = bq % nq, bb = bq / nq;
+    uint16_t h[8], l[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t k = 8 * q + t;
+      float x = 0.f;
+      if (k < K && c < ncol) x = in[bb * ibs + k * iks + c];
+      h[t] = bf16_rne(x);
+      l[t] = bf16_rne(x - bf16_to_f(h[t]));
+    }
+    uint4 vh, vl;
+    vh.x = h[0] | ((uint32_t)h[1] << 16); vh.y = h[2] | ((uint32_t)h[3] << 16);
+    vh.z = h[4] | ((uint32_t)h[5] << 16); vh.w = h[6] | ((uint32_t)h[7] << 16);
+    vl.x = l[0] | ((uint32_t)l[1] << 16); vl.y = l[2] | ((uint32_t)l[3] << 16);
+    vl.z = l[4] | ((uint32_t)l[5] << 16); vl.w = l[6] | ((uint32_t)l[7] << 16);
+    *(uint4*)(hi + e * 8) = vh;
+    *(uint4*)(lo + e * 8) = vl;
+  }
+}
+
+hipError_t launch_split8(bf16_t* hi, bf16_t* lo, int64_t nblk, int32_t K, int64_t ld, int32_t ncol,
+                         const float* in, int64_t ibs, int64_t iks, hipStream_t s) {
+  const int64_t total = nblk * ((K + 7) / 8) * ld;
+  if (total <= 0) return hipSuccess;
+  int64_t nb = (total + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_split8, dim3((unsigned)nb), dim3(256), 0, s, hi, lo, nblk, K, ld, ncol, in, ibs, iks);
+  return hipGetLastError();
+}
+
 __global__ void k_zero(double* p, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     p[e] = 0.0;
