@@ -116,7 +116,11 @@ typedef struct ltriples_options {
    * each phase and launch, waits for the stream before returning, and
    * fills *stats */
   ltriples_stats* stats;
-  int32_t reserved[4];
+  /* ltriples_energy_batched only: 1 = capture the launch sequence into a
+   * hipGraph on the first call and replay it on later calls with the same
+   * shapes, pointers, workspace and options (requires a caller workspace) */
+  int32_t graph;
+  int32_t reserved[3];
 } ltriples_options;
 
 /* Host-only validation of sizes, pointers, precision and item list.  Makes
@@ -148,6 +152,32 @@ int ltriples_flops(const ltriples_domain* d, const ltriples_options* o,
 int ltriples_energy(const ltriples_domain* d, int32_t precision,
                     const ltriples_options* o, double* e_out, double* parts,
                     void* ws, size_t ws_bytes, void* stream);
+
+/* Host-only: workspace bytes of ltriples_energy_batched for ndom domains. */
+int ltriples_workspace_size_batched(const ltriples_domain* ds, int32_t ndom,
+                                    int32_t precision, const ltriples_options* o,
+                                    size_t* bytes);
+
+/* E(T) of ndom independent domains in one call (Sec. "Open-Shell LNO-CCSD(T)
+ * Ansatz": the LNO energy is a sum of independent per-orbital domain
+ * contributions, eq. lno_ccsdpt_energy), enqueued on `stream`.
+ *   ds      HOST array [ndom] of domains (device pointers as above)
+ *   e_out   device double[ndom]; parts device double[ndom][4][3] or NULL
+ *   ws      device workspace >= ltriples_workspace_size_batched(), or NULL
+ * Each domain's result is bitwise identical to ltriples_energy on that
+ * domain alone.  Item lists, per-item outputs and stats are not available
+ * here (LT_EINVAL).  With options.graph = 1 (and a caller workspace) the
+ * launch sequence is captured into a hipGraph on the first call and replayed
+ * on later calls whose shapes, pointers and options match; the graph reads
+ * the inputs at replay time.  The orbital energies of every domain are read
+ * back once per call (synchronous) to check the denominators. */
+int ltriples_energy_batched(const ltriples_domain* ds, int32_t ndom,
+                            int32_t precision, const ltriples_options* o,
+                            double* e_out, double* parts, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* Drops every cached hipGraph of ltriples_energy_batched. */
+int ltriples_graph_reset(void);
 
 /* Description of the last error on this thread ("" if none). */
 const char* ltriples_last_error(void);

@@ -71,7 +71,8 @@ class Options(ctypes.Structure):
                 ("e_items", ctypes.c_void_p),
                 ("batch_items", ctypes.c_int32),
                 ("stats", ctypes.POINTER(Stats)),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class LtError(RuntimeError):
@@ -98,9 +99,15 @@ def load_library(path: Optional[str] = None):
     lib.ltriples_flops.argtypes = [Dp, Op, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.ltriples_energy.argtypes = [Dp, ctypes.c_int32, Op, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.ltriples_workspace_size_batched.argtypes = [Dp, ctypes.c_int32, ctypes.c_int32, Op,
+                                                    ctypes.POINTER(ctypes.c_size_t)]
+    lib.ltriples_energy_batched.argtypes = [Dp, ctypes.c_int32, ctypes.c_int32, Op, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.ltriples_graph_reset.argtypes = []
     lib.ltriples_last_error.restype = ctypes.c_char_p
     lib.ltriples_version.restype = ctypes.c_char_p
-    for f in ("ltriples_validate", "ltriples_workspace_size", "ltriples_flops", "ltriples_energy"):
+    for f in ("ltriples_validate", "ltriples_workspace_size", "ltriples_flops", "ltriples_energy",
+              "ltriples_workspace_size_batched", "ltriples_energy_batched", "ltriples_graph_reset"):
         getattr(lib, f).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -222,3 +229,55 @@ def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP3
     _check(code)
     del keep
     return e, parts
+
+
+def _domain_array(dims_list, tensors_list):
+    arr = (Domain * len(dims_list))()
+    for n, (dims, t) in enumerate(zip(dims_list, tensors_list)):
+        arr[n] = make_domain(dims, t)
+    return arr
+
+
+def ltriples_workspace_size_batched(dims_list, tensors_list, precision: int, options: Optional[Options] = None) -> int:
+    lib = load_library()
+    arr = _domain_array(dims_list, tensors_list)
+    n = ctypes.c_size_t(0)
+    _check(lib.ltriples_workspace_size_batched(arr, len(dims_list), int(precision),
+                                               ctypes.byref(options) if options is not None else None,
+                                               ctypes.byref(n)))
+    return n.value
+
+
+def ltriples_energy_batched(tensors_list, dims_list, precision: int = LT_FP32, graph: bool = False,
+                            batch_budget: int = 0, batch_items: int = 0, workspace=None, out=None,
+                            stream=None):
+    """E(T) of several domains in one call.  Returns (e [ndom], parts [ndom,4,3]).
+    With graph=True the launch sequence is captured into a hipGraph on the
+    first call and replayed on later calls with the same shapes, pointers,
+    workspace and output tensors (pass `workspace` and `out` to reuse them)."""
+    import torch
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    ndom = len(dims_list)
+    opts, _ = make_options(batch_budget=batch_budget, batch_items=batch_items)
+    opts.graph = 1 if graph else 0
+    arr = _domain_array(dims_list, tensors_list)
+    dev = next(t for t in tensors_list[0].values() if hasattr(t, "device")).device
+    lib = load_library()
+    n = ctypes.c_size_t(0)
+    _check(lib.ltriples_workspace_size_batched(arr, ndom, int(precision), ctypes.byref(opts), ctypes.byref(n)))
+    if workspace is None:
+        workspace = torch.empty(max(n.value, 1), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = (torch.empty(ndom, dtype=torch.float64, device=dev),
+               torch.empty(ndom, 4, 3, dtype=torch.float64, device=dev))
+    e, parts = out
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    _check(lib.ltriples_energy_batched(arr, ndom, int(precision), ctypes.byref(opts), e.data_ptr(),
+                                       parts.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                       st.cuda_stream))
+    return e, parts
+
+
+def ltriples_graph_reset():
+    _check(load_library().ltriples_graph_reset())

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "lt_internal.h"
@@ -191,7 +192,7 @@ struct Plan {
   size_t per_item[4];             // batch bytes per item (T outputs)
   size_t part_off[4];             // partials offset within scratch (phase 2)
   int64_t ntile[4];
-  size_t total = 0;
+  size_t big = 0, small = 0, small_base = 0, total = 0;
 };
 
 void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options* o,
@@ -249,9 +250,9 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
   if (P.any_mix) take(P.OVab, 8 * D.o[0] * D.v[0] * D.o[1] * D.v[1]);
   P.bf = prec == LT_BF16X3 ? 3 : (prec == LT_BF16 ? 1 : 0);
   if (P.bf) {
-    auto k8 = [](int64_t k) { return (k + 7) & ~int64_t(7); };
+    auto k16 = [](int64_t k) { return (k + 15) & ~int64_t(15); };
     auto take8 = [&](int s, int t, int64_t nblk, int64_t K, int64_t ld) {
-      const size_t bytes = 2 * (size_t)(nblk * k8(K) * ld);
+      const size_t bytes = 2 * (size_t)(nblk * k16(K) * ld) + 2 * 8 * 512;
       take(P.O8h[s][t], bytes);
       take(P.O8l[s][t], bytes);
     };
@@ -276,11 +277,6 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
       }
     }
   }
-  take(P.e_items, 8 * 3 * std::max<int64_t>(L.total, 1));
-  take(P.trip, 4 * 3 * std::max<int64_t>(L.total, 1));
-  take(P.dst, 4 * std::max<int64_t>(L.total, 1));
-  take(P.order, 4 * std::max<int64_t>(L.total, 1));
-  take(P.firstcnt, 4 * 8);
 
   // scratch, phase 1a: (ov|oo) classes and same-spin (ov|ov)
   size_t s1a = 0;
@@ -329,7 +325,18 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
   }
   const size_t sc = std::max(std::max(s1a, s1b), s2);
   take(P.scratch, std::max<size_t>(sc, 256));
-  P.total = off;
+  P.big = off;
+  // per-domain small buffers (item lists, per-item energies), addressed
+  // relative to small_base so that a batch of domains can share the big part
+  off = 0;
+  take(P.e_items, 8 * 3 * std::max<int64_t>(L.total, 1));
+  take(P.trip, 4 * 3 * std::max<int64_t>(L.total, 1));
+  take(P.dst, 4 * std::max<int64_t>(L.total, 1));
+  take(P.order, 4 * std::max<int64_t>(L.total, 1));
+  take(P.firstcnt, 4 * 8);
+  P.small = off;
+  P.small_base = P.big;
+  P.total = P.big + P.small;
 }
 
 void log_plan(const Plan& P) {
@@ -354,6 +361,9 @@ void log_plan(const Plan& P) {
 }
 
 template <typename T> T* at(void* ws, const Buf& b) { return (T*)((char*)ws + b.off); }
+template <typename T> T* at_small(void* ws, const Plan& P, const Buf& b) {
+  return (T*)((char*)ws + P.small_base + b.off);
+}
 
 // HIP-event timing of the call's phases (only when the caller asks for stats)
 struct Timing {
@@ -382,6 +392,39 @@ struct Timing {
 // ---------------------------------------------------------------------------
 // Launch sequence
 // ---------------------------------------------------------------------------
+// Block-ordered item arrays of a domain (host side).
+struct HostItems {
+  std::vector<int32_t> trip, dst;
+  int32_t fc[8];
+};
+
+void host_items(const ItemLists& L, HostItems& H) {
+  for (int b = 0; b < 4; ++b) {
+    H.fc[b] = (int32_t)H.dst.size();
+    H.fc[4 + b] = (int32_t)L.dst[b].size();
+    H.trip.insert(H.trip.end(), L.trip[b].begin(), L.trip[b].end());
+    H.dst.insert(H.dst.end(), L.dst[b].begin(), L.dst[b].end());
+  }
+}
+
+// Copies the item arrays to the domain's small buffers and waits for the
+// copies (host vectors are released afterwards).  Not capturable.
+int upload_items(const Plan& P, const ItemLists& L, void* ws, hipStream_t st) {
+  HostItems H;
+  host_items(L, H);
+  if (!H.trip.empty()) {
+    HIPCHK(hipMemcpyAsync(at_small<int32_t>(ws, P, P.trip), H.trip.data(), H.trip.size() * 4,
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(at_small<int32_t>(ws, P, P.dst), H.dst.data(), H.dst.size() * 4,
+                          hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(hipMemcpyAsync(at_small<int32_t>(ws, P, P.firstcnt), H.fc, sizeof(H.fc), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return LT_OK;
+}
+
+// Enqueues the whole (T) path of one domain on `st` (kernels only; safe to
+// capture into a graph).
 template <typename T>
 int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltriples_options* o,
         double* e_out, double* parts, void* ws, hipStream_t st, Timing& tm) {
@@ -397,27 +440,27 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
   const double* EV[2] = {d->ev_a, d->ev_b};
   char* scr = (char*)ws + P.scratch.off;
 
-  // --- item arrays ---------------------------------------------------------
-  std::vector<int32_t> trip, dst;
+  // --- item arrays (already uploaded by upload_items) --------------------------
   int32_t fc[8];
-  for (int b = 0; b < 4; ++b) {
-    fc[b] = (int32_t)dst.size();
+  for (int b = 0, n = 0; b < 4; ++b) {
+    fc[b] = n;
     fc[4 + b] = (int32_t)L.dst[b].size();
-    trip.insert(trip.end(), L.trip[b].begin(), L.trip[b].end());
-    dst.insert(dst.end(), L.dst[b].begin(), L.dst[b].end());
+    n += fc[4 + b];
   }
-  int32_t* d_trip = at<int32_t>(ws, P.trip);
-  int32_t* d_dst = at<int32_t>(ws, P.dst);
-  int32_t* d_fc = at<int32_t>(ws, P.firstcnt);
-  if (!trip.empty()) {
-    HIPCHK(hipMemcpyAsync(d_trip, trip.data(), trip.size() * 4, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_dst, dst.data(), dst.size() * 4, hipMemcpyHostToDevice, st));
-  }
-  HIPCHK(hipMemcpyAsync(d_fc, fc, sizeof(fc), hipMemcpyHostToDevice, st));
-  // host vectors must outlive the copies
-  HIPCHK(hipStreamSynchronize(st));
-  double* e_items = (o && o->e_items) ? o->e_items : at<double>(ws, P.e_items);
+  int32_t* d_trip = at_small<int32_t>(ws, P, P.trip);
+  int32_t* d_dst = at_small<int32_t>(ws, P, P.dst);
+  int32_t* d_fc = at_small<int32_t>(ws, P, P.firstcnt);
+  double* e_items = (o && o->e_items) ? o->e_items : at_small<double>(ws, P, P.e_items);
   tm.start = tm.mark();
+  if (o && o->e_items && L.total > 0) HIPCHK(lt::launch_zero(o->e_items, 3 * L.total, st));
+  HIPCHK(lt::launch_zero(at_small<double>(ws, P, P.e_items), 3 * std::max<int64_t>(L.total, 1), st));
+  if (L.total == 0 || (D.v[0] == 0 && D.v[1] == 0)) {
+    HIPCHK(lt::launch_zero(e_out, 1, st));
+    if (parts) HIPCHK(lt::launch_zero(parts, 12, st));
+    tm.setup_end = tm.mark();
+    tm.end = tm.setup_end;
+    return LT_OK;
+  }
 
   // --- 1. DF factor layouts --------------------------------------------------
   for (int s = 0; s < 2; ++s) {
@@ -700,6 +743,30 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
   return LT_OK;
 }
 
+// Every occupied energy below every virtual energy (all D < 0), all finite.
+// Reads the orbital energies back to the host (synchronous copy).
+int check_denominators(const ltriples_domain* d) {
+  const Dims D = dims_of(d);
+  double omax = -INFINITY, vmin = INFINITY;
+  for (int s = 0; s < 2; ++s) {
+    const double* eo = s ? d->eo_b : d->eo_a;
+    const double* ev = s ? d->ev_b : d->ev_a;
+    std::vector<double> ho(D.o[s]), hv(D.v[s]);
+    if (D.o[s]) HIPCHK(hipMemcpy(ho.data(), eo, 8 * D.o[s], hipMemcpyDeviceToHost));
+    if (D.v[s]) HIPCHK(hipMemcpy(hv.data(), ev, 8 * D.v[s], hipMemcpyDeviceToHost));
+    for (double x : ho) {
+      if (!std::isfinite(x)) return fail(LT_ENONFINITE, "non-finite occupied energy");
+      omax = std::max(omax, x);
+    }
+    for (double x : hv) {
+      if (!std::isfinite(x)) return fail(LT_ENONFINITE, "non-finite virtual energy");
+      vmin = std::min(vmin, x);
+    }
+  }
+  if (omax >= vmin) return fail(LT_EDENOM, "max occupied energy %.6g >= min virtual energy %.6g", omax, vmin);
+  return LT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -755,20 +822,8 @@ int ltriples_energy(const ltriples_domain* d, int32_t precision, const ltriples_
   hipStream_t st = (hipStream_t)stream;
   const Dims D = dims_of(d);
 
-  // denominators: every occupied energy below every virtual energy, all finite
-  {
-    double omax = -INFINITY, vmin = INFINITY;
-    for (int s = 0; s < 2; ++s) {
-      const double* eo = s ? d->eo_b : d->eo_a;
-      const double* ev = s ? d->ev_b : d->ev_a;
-      std::vector<double> ho(D.o[s]), hv(D.v[s]);
-      if (D.o[s]) HIPCHK(hipMemcpy(ho.data(), eo, 8 * D.o[s], hipMemcpyDeviceToHost));
-      if (D.v[s]) HIPCHK(hipMemcpy(hv.data(), ev, 8 * D.v[s], hipMemcpyDeviceToHost));
-      for (double x : ho) { if (!std::isfinite(x)) return fail(LT_ENONFINITE, "non-finite occupied energy"); omax = std::max(omax, x); }
-      for (double x : hv) { if (!std::isfinite(x)) return fail(LT_ENONFINITE, "non-finite virtual energy"); vmin = std::min(vmin, x); }
-    }
-    if (omax >= vmin) return fail(LT_EDENOM, "max occupied energy %.6g >= min virtual energy %.6g", omax, vmin);
-  }
+  r = check_denominators(d);
+  if (r) return r;
 
   ItemLists L;
   build_items(D, o, L);
@@ -782,14 +837,8 @@ int ltriples_energy(const ltriples_domain* d, int32_t precision, const ltriples_
   } else if (ws_bytes < P.total) {
     return fail(LT_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, P.total);
   }
-  if (o && o->e_items && L.total > 0) HIPCHK(lt::launch_zero(o->e_items, 3 * L.total, st));
-  HIPCHK(lt::launch_zero(at<double>(ws, P.e_items), 3 * std::max<int64_t>(L.total, 1), st));
-  if (L.total == 0 || (D.v[0] == 0 && D.v[1] == 0)) {
-    HIPCHK(lt::launch_zero(e_out, 1, st));
-    if (parts) HIPCHK(lt::launch_zero(parts, 12, st));
-    if (own) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(ws)); }
-    return LT_OK;
-  }
+  r = upload_items(P, L, ws, st);
+  if (r) return r;
   Timing tm;
   tm.on = o && o->stats;
   tm.st = st;
@@ -816,6 +865,196 @@ int ltriples_energy(const ltriples_domain* d, int32_t precision, const ltriples_
     if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) return fail(LT_EHIP, "HIP error at workspace release");
   }
   return r;
+}
+
+// ---------------------------------------------------------------------------
+// Batched domains.  The domains run one after another on the stream and share
+// the big part of the workspace (operands, slabs, scratch); each keeps its own
+// small buffers.  With options.graph = 1 the whole launch sequence is captured
+// into a hipGraph on the first call and replayed on later calls whose shapes,
+// pointers and options match (the graph reads the inputs at replay time).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchPlan {
+  std::vector<ItemLists> L;
+  std::vector<Plan> P;
+  size_t total = 0;
+};
+
+int plan_batch(const ltriples_domain* ds, int32_t ndom, int32_t precision, const ltriples_options* o,
+               BatchPlan& B) {
+  if (ndom < 0) return fail(LT_EINVAL, "ndom < 0");
+  if (ndom > 0 && !ds) return fail(LT_EINVAL, "domains is NULL");
+  if (o && (o->items || o->n_items || o->e_items))
+    return fail(LT_EINVAL, "item lists and per-item outputs are single-domain options");
+  for (int32_t d = 0; d < ndom; ++d) {
+    const int r = validate(&ds[d], precision, nullptr);
+    if (r) return fail(r, "domain %d: %s", d, g_err.c_str());
+  }
+  B.L.resize(ndom);
+  B.P.resize(ndom);
+  size_t big = 0;
+  for (int32_t d = 0; d < ndom; ++d) {
+    build_items(dims_of(&ds[d]), nullptr, B.L[d]);
+    plan_domain(&ds[d], precision, o, B.L[d], B.P[d]);
+    big = std::max(big, B.P[d].big);
+  }
+  size_t off = align256(big);
+  for (int32_t d = 0; d < ndom; ++d) {
+    B.P[d].small_base = off;
+    off = align256(off + B.P[d].small);
+  }
+  B.total = std::max<size_t>(off, 256);
+  return LT_OK;
+}
+
+struct GraphEntry {
+  std::vector<uint64_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;
+constexpr size_t kMaxGraphs = 16;
+
+std::vector<uint64_t> batch_key(const ltriples_domain* ds, int32_t ndom, int32_t precision,
+                                const ltriples_options* o, const void* e_out, const void* parts,
+                                const void* ws, size_t ws_bytes, int device) {
+  std::vector<uint64_t> k = {(uint64_t)device, (uint64_t)precision, (uint64_t)ndom, (uint64_t)(uintptr_t)e_out,
+                             (uint64_t)(uintptr_t)parts, (uint64_t)(uintptr_t)ws, (uint64_t)ws_bytes,
+                             (uint64_t)(o ? o->batch_budget : 0), (uint64_t)(o ? o->batch_items : 0)};
+  for (int32_t d = 0; d < ndom; ++d) {
+    const ltriples_domain& x = ds[d];
+    k.insert(k.end(), {(uint64_t)x.noa, (uint64_t)x.nob, (uint64_t)x.nva, (uint64_t)x.nvb, (uint64_t)x.naux});
+    const void* ptrs[] = {x.t1a, x.t1b, x.t2aa, x.t2bb, x.t2ab, x.Boo_a, x.Bov_a, x.Bvv_a, x.Boo_b,
+                          x.Bov_b, x.Bvv_b, x.eo_a, x.ev_a, x.eo_b, x.ev_b, x.fov_a, x.fov_b};
+    for (const void* p : ptrs) k.push_back((uint64_t)(uintptr_t)p);
+  }
+  return k;
+}
+
+int enqueue_batch(const ltriples_domain* ds, int32_t ndom, int32_t precision, const ltriples_options* o,
+                  const BatchPlan& B, double* e_out, double* parts, void* ws, hipStream_t st) {
+  ltriples_options oo{};
+  if (o) { oo.batch_budget = o->batch_budget; oo.batch_items = o->batch_items; }
+  for (int32_t d = 0; d < ndom; ++d) {
+    Timing tm;  // off
+    const int r = precision == LT_FP64
+                      ? run<double>(&ds[d], B.P[d], B.L[d], &oo, e_out + d, parts ? parts + 12 * d : nullptr, ws, st, tm)
+                      : run<float>(&ds[d], B.P[d], B.L[d], &oo, e_out + d, parts ? parts + 12 * d : nullptr, ws, st, tm);
+    if (r) return r;
+  }
+  return LT_OK;
+}
+
+}  // namespace
+
+int ltriples_workspace_size_batched(const ltriples_domain* ds, int32_t ndom, int32_t precision,
+                                    const ltriples_options* o, size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(LT_EINVAL, "bytes is NULL");
+  BatchPlan B;
+  const int r = plan_batch(ds, ndom, precision, o, B);
+  if (r) return r;
+  *bytes = B.total;
+  return LT_OK;
+}
+
+int ltriples_energy_batched(const ltriples_domain* ds, int32_t ndom, int32_t precision, const ltriples_options* o,
+                            double* e_out, double* parts, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!e_out && ndom > 0) return fail(LT_EINVAL, "e_out is NULL");
+  BatchPlan B;
+  int r = plan_batch(ds, ndom, precision, o, B);
+  if (r) return r;
+  for (int32_t d = 0; d < ndom; ++d) {
+    r = check_denominators(&ds[d]);
+    if (r) return fail(r, "domain %d: %s", d, g_err.c_str());
+  }
+  if (ndom == 0) return LT_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const bool use_graph = o && o->graph && ws != nullptr;
+  bool own = false;
+  if (ws == nullptr) {
+    HIPCHK(hipMalloc(&ws, B.total));
+    own = true;
+  } else if (ws_bytes < B.total) {
+    return fail(LT_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, B.total);
+  }
+  // item tables go to each domain's small region on every call (also before a
+  // replay: the caller may have used the workspace for other calls meanwhile)
+  for (int32_t d = 0; d < ndom; ++d) {
+    r = upload_items(B.P[d], B.L[d], ws, st);
+    if (r) {
+      if (own) (void)hipFree(ws);
+      return r;
+    }
+  }
+  int device = 0;
+  HIPCHK(hipGetDevice(&device));
+  std::vector<uint64_t> key;
+  if (use_graph) {
+    key = batch_key(ds, ndom, precision, o, e_out, parts, ws, ws_bytes, device);
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto& g : g_graphs)
+      if (g.key == key) {
+        HIPCHK(hipGraphLaunch(g.exec, st));
+        return LT_OK;
+      }
+  }
+  if (!use_graph) {
+    r = enqueue_batch(ds, ndom, precision, o, B, e_out, parts, ws, st);
+    if (own) {
+      hipError_t e1 = hipStreamSynchronize(st);
+      hipError_t e2 = hipFree(ws);
+      if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) return fail(LT_EHIP, "HIP error at workspace release");
+    }
+    return r;
+  }
+  // capture on a private stream (the caller's may be the legacy default stream)
+  hipStream_t cs = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipError_t ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (ce != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return fail(LT_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(ce));
+  }
+  r = enqueue_batch(ds, ndom, precision, o, B, e_out, parts, ws, cs);
+  ce = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (r) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return r;
+  }
+  if (ce != hipSuccess) return fail(LT_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
+  hipGraphExec_t exec = nullptr;
+  ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ce != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(LT_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ce));
+  }
+  HIPCHK(hipGraphLaunch(exec, st));
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  if (g_graphs.size() >= kMaxGraphs) {
+    (void)hipGraphExecDestroy(g_graphs.front().exec);
+    (void)hipGraphDestroy(g_graphs.front().graph);
+    g_graphs.erase(g_graphs.begin());
+  }
+  g_graphs.push_back({key, graph, exec});
+  return LT_OK;
+}
+
+int ltriples_graph_reset(void) {
+  g_err.clear();
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (auto& g : g_graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  g_graphs.clear();
+  return LT_OK;
 }
 
 const char* ltriples_last_error(void) { return g_err.c_str(); }

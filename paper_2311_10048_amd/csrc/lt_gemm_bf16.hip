@@ -16,14 +16,14 @@ namespace lt {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-__device__ inline int64_t k8(int64_t k) { return (k + 7) & ~int64_t(7); }
+__device__ inline int64_t k16(int64_t k) { return (k + 15) & ~int64_t(15); }   // rows padded to 16
 
 // Segment idx of the contraction of triplet (i, j, k); see item_seg in
 // lt_gemm.hip for the equations (same terms, same order, same signs).
 __device__ inline Seg8 item_seg8(const ItemOps8& s, int64_t i, int64_t j, int64_t k, int idx) {
   const int64_t o = s.o_s, v = s.v_s, ot = s.o_t, vt = s.v_t;
   const int64_t lv = s.ld_vs, lt_ = s.ld_vt, lp = s.ld_np, lc = s.ld_cb;
-  const int64_t kv = k8(v), ko = k8(o), kvt = k8(vt), kot = k8(ot);
+  const int64_t kv = k16(v), ko = k16(o), kvt = k16(vt), kot = k16(ot);
   // block sizes (elements) of each octet tensor
   const int64_t bT2T = kv * lv, bAs = kv * lp, bGam = ko * lv, bTp = ko * lp;
   auto mk = [](const bf16_t* Lh, const bf16_t* Ll, int64_t lo, int64_t ll, const bf16_t* Rh, const bf16_t* Rl,

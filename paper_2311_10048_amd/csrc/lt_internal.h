@@ -92,9 +92,12 @@ template <typename T> struct GemmArgs {
 // BF16 split operands.  A prepared FP32 operand viewed as [nblk][K][ld]
 // (block, contraction row k, column) is stored as two bf16 arrays
 // hi = bf16(x), lo = bf16(x - hi), each in "octet" layout
-// [nblk][K8/8][ld][8] with K8 = K rounded up to 8 (extra rows zero): one
+// [nblk][K16/8][ld][8] with K16 = K rounded up to 16 (extra rows zero): one
 // 16-byte word holds 8 consecutive k of one column, which is exactly one
-// lane's operand of the 32x32x16 BF16 matrix instruction.
+// lane's operand of the 32x32x16 BF16 matrix instruction, and every K step
+// of 16 lies inside one zero-padded block.  Allocations carry one extra
+// 128-column row of slack so whole-wave loads past the last column stay in
+// bounds (such lanes only feed discarded output rows/columns).
 // ---------------------------------------------------------------------------
 typedef uint16_t bf16_t;
 
@@ -133,7 +136,8 @@ struct GemmArgs16 {
 
 hipError_t launch_gemm_bf16(const GemmArgs16& g, hipStream_t s);
 
-// hi/lo octet tensors from FP32 in[b*ibs + k*iks + c], c < ncol, k < K.
+// hi/lo octet tensors from FP32 in[b*ibs + k*iks + c], c < ncol, k < K
+// (zero elsewhere, rows padded to 16).
 hipError_t launch_split8(bf16_t* hi, bf16_t* lo, int64_t nblk, int32_t K, int64_t ld, int32_t ncol,
                          const float* in, int64_t ibs, int64_t iks, hipStream_t s);
 

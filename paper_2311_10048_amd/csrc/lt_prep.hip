@@ -113,7 +113,7 @@ __device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t
 // one column, split into hi = bf16(x) and lo = bf16(x - hi).
 __global__ __launch_bounds__(256) void k_split8(bf16_t* hi, bf16_t* lo, int64_t nblk, int32_t K, int64_t ld,
                                                 int32_t ncol, const float* in, int64_t ibs, int64_t iks) {
-  const int64_t nq = (K + 7) / 8;
+  const int64_t nq = ((K + 15) / 16) * 2;   // octets per block, rows padded to 16
   const int64_t total = nblk * nq * ld;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_split8(bf16_t* hi, bf16_t* lo, int64_t 
 
 hipError_t launch_split8(bf16_t* hi, bf16_t* lo, int64_t nblk, int32_t K, int64_t ld, int32_t ncol,
                          const float* in, int64_t ibs, int64_t iks, hipStream_t s) {
-  const int64_t total = nblk * ((K + 7) / 8) * ld;
+  const int64_t total = nblk * (((K + 15) / 16) * 2) * ld;
   if (total <= 0) return hipSuccess;
   int64_t nb = (total + 255) / 256;
   if (nb > 65536) nb = 65536;

@@ -101,3 +101,40 @@ def test_energy_rejects_bad_args_without_gpu_work():
     assert code == lt.LT_EPREC
     code = lib.ltriples_energy(ctypes.byref(d), lt.LT_FP64, None, None, None, None, 0, None)
     assert code == lt.LT_EINVAL
+
+
+def _fake_array(dims_list):
+    arr = (lt.Domain * len(dims_list))()
+    for n, dims in enumerate(dims_list):
+        arr[n] = _fake_domain(dims)
+    return arr
+
+
+def test_batched_workspace_is_shared_big_part_plus_small_parts():
+    lib = _lib()
+    dims = [(5, 4, 30, 31, 120), (6, 5, 45, 47, 96), (3, 0, 12, 13, 20)]
+    singles = [lt.ltriples_workspace_size(_fake_domain(x), lt.LT_FP32) for x in dims]
+    n = ctypes.c_size_t(0)
+    assert lib.ltriples_workspace_size_batched(_fake_array(dims), 3, lt.LT_FP32, None, ctypes.byref(n)) == lt.LT_OK
+    # one shared region of the largest domain's size, plus small per-domain tables
+    assert max(singles) <= n.value < sum(singles)
+    n1 = ctypes.c_size_t(0)
+    assert lib.ltriples_workspace_size_batched(_fake_array(dims[1:2]), 1, lt.LT_FP32, None,
+                                               ctypes.byref(n1)) == lt.LT_OK
+    assert n1.value >= singles[1]
+
+
+def test_batched_rejects_item_lists_and_bad_domains():
+    lib = _lib()
+    dims = [(5, 4, 30, 31, 120), (4, 3, 10, 11, 20)]
+    o, keep = lt.make_options(items=[(0, 0, 1, 2)])
+    n = ctypes.c_size_t(0)
+    assert lib.ltriples_workspace_size_batched(_fake_array(dims), 2, lt.LT_FP64, ctypes.byref(o),
+                                               ctypes.byref(n)) == lt.LT_EINVAL
+    bad = _fake_array(dims + [(4, 3, 10, 11, 0)])
+    assert lib.ltriples_workspace_size_batched(bad, 3, lt.LT_FP64, None, ctypes.byref(n)) == lt.LT_ESHAPE
+    assert "domain 2" in lt.ltriples_last_error()
+    assert lib.ltriples_energy_batched(_fake_array(dims), 2, 9, None, None, None, None, 0, None) == lt.LT_EINVAL
+    assert lib.ltriples_energy_batched(_fake_array(dims), 2, 9, None, 0x1000, None, None, 0, None) == lt.LT_EPREC
+    assert lib.ltriples_energy_batched(None, 0, lt.LT_FP64, None, None, None, None, 0, None) == lt.LT_OK
+    assert lib.ltriples_graph_reset() == lt.LT_OK
