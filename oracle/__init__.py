@@ -15,6 +15,9 @@ Modules
   spinorb  brute-force spin-orbital evaluation of the master formula with the
            1/36 weight over all ordered occupied triples (tiny domains only).
   rhf      closed-shell (T) formula for alpha == beta inputs.
+  grad     gradient of the energy with respect to T1, T2 and the DF factors
+           (PyTorch float64 CPU reverse mode over a transcription of the
+           spin-blocked energy; projected convention for symmetric inputs).
 
 What the oracle computes (the paper's eq. cim_pt_energy, summed over the
 central index; the paper defers the definitions of t and W to the standard
@@ -33,6 +36,10 @@ loops; alpha == beta inputs reproduce the independent closed-shell formula;
 invariance under orbital relabelling, orbital phase flips and alpha/beta
 exchange; exact homogeneity in T and B; special cases (T2 = 0, T1 = 0,
 f_ov = 0, E4 <= 0, odd parts); edge shapes; additivity over item lists.
+Gradient pins (tests/test_oracle_grad.py): the transcription's energy
+equals blocks; <dE/dx, d> equals the exact 3-point (T) / 5-point (B) central
+stencil of blocks and of the spin-orbital brute force along random
+directions; the symmetry-image convention of the projected gradient.
 Parity with the paper's molecular results is unpinned (the paper prints no
 per-domain (T) values).
 """

@@ -1,0 +1,162 @@
+"""Pins of the oracle gradient (oracle.grad) against facts that do not come
+from it: exact finite-difference stencils of the independently pinned
+NumPy energy (oracle.blocks) and of the brute-force spin-orbital energy
+(oracle.spinorb), and the symmetry-image convention of the projected
+gradient.  E is quadratic in (T1, T2) and quartic in B, so the 3-point
+central stencil is exact in T and the 5-point one exact in B, up to rounding.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import blocks, grad, spinorb
+
+T_FIELDS = ("t1a", "t1b", "t2aa", "t2bb", "t2ab")
+B_FIELDS = ("Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b")
+SHAPES = [(3, 2, 5, 6, 14), (4, 3, 6, 5, 12), (3, 0, 4, 5, 10), (2, 2, 4, 4, 9)]
+
+
+def _dom(shape, seed=5):
+    # larger f_ov and T1 than the workload recipe so that every term of the
+    # gradient is well above rounding
+    return synth.make_domain(*shape, seed=seed, sigma_f=3e-2, sigma_t1=3e-2)
+
+
+def _direction(dom, field, rng):
+    """A random direction in the constrained subspace of `field`."""
+    x = getattr(dom, field)
+    d = rng.normal(0.0, 1.0, size=x.shape) * (np.std(x) + 1e-3)
+    if field in ("t2aa", "t2bb"):
+        d = d - d.transpose(1, 0, 2, 3)
+        d = d - d.transpose(0, 1, 3, 2)
+    if field.startswith("Boo") or field.startswith("Bvv"):
+        d = d + d.transpose(0, 2, 1)
+    return d
+
+
+def _E(dom, field, d, h, fn):
+    return fn(dom.replace(**{field: getattr(dom, field) + h * d}))
+
+
+def _stencil(dom, field, d, fn):
+    """Exact derivative along d: 3-point for T, 5-point for B."""
+    h = 0.5
+    if field in T_FIELDS:
+        return (_E(dom, field, d, h, fn) - _E(dom, field, d, -h, fn)) / (2 * h)
+    return (-_E(dom, field, d, 2 * h, fn) + 8 * _E(dom, field, d, h, fn)
+            - 8 * _E(dom, field, d, -h, fn) + _E(dom, field, d, -2 * h, fn)) / (12 * h)
+
+
+def _blocks_E(dom):
+    return blocks.energy(dom)["E"]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_transcription_energy_equals_blocks(shape):
+    dom = _dom(shape)
+    E, _ = grad.energy_and_grad(dom)
+    ref = blocks.energy(dom)["E"]
+    assert abs(E - ref) <= 1e-12 * abs(ref)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_directional_derivatives_exact_stencil(shape):
+    """<g, d> equals the exact stencil of the NumPy energy for every input."""
+    dom = _dom(shape)
+    _, g = grad.energy_and_grad(dom)
+    rng = np.random.default_rng(17)
+    for field in T_FIELDS + B_FIELDS:
+        if getattr(dom, field).size == 0:
+            continue
+        d = _direction(dom, field, rng)
+        fd = _stencil(dom, field, d, _blocks_E)
+        an = float(np.sum(g[field] * d))
+        scale = max(abs(fd), 1e-9 * abs(_blocks_E(dom)))
+        assert abs(an - fd) <= 1e-8 * scale, (field, an, fd)
+
+
+def test_directional_derivatives_against_spin_orbital_brute_force():
+    """Same check against the literal 1/36 spin-orbital sum."""
+    dom = _dom((3, 2, 4, 5, 10), seed=9)
+    _, g = grad.energy_and_grad(dom)
+    rng = np.random.default_rng(3)
+    fn = lambda x: spinorb.energy(x)["E"]
+    for field in ("t1b", "t2aa", "t2ab", "Bov_a", "Bvv_b", "Boo_a"):
+        d = _direction(dom, field, rng)
+        fd = _stencil(dom, field, d, fn)
+        an = float(np.sum(g[field] * d))
+        assert abs(an - fd) <= 1e-8 * max(abs(fd), 1e-12), (field, an, fd)
+
+
+def _images_fd(dom, field, idx, imgs, h=1e-2):
+    x = getattr(dom, field)
+    d = np.zeros_like(x)
+    for sgn, ix in imgs(idx):
+        d[ix] = sgn
+    return (_E(dom, field, d, h, _blocks_E) - _E(dom, field, d, -h, _blocks_E)) / (2 * h)
+
+
+def test_projected_convention_symmetry_images():
+    """Moving all signed images of one t2aa element gives 4x the returned
+    element, of one off-diagonal Bvv element 2x, of a diagonal one 1x."""
+    dom = _dom((4, 2, 5, 6, 12))
+    _, g = grad.energy_and_grad(dom)
+    t2img = lambda ix: [(1, ix), (-1, (ix[1], ix[0], ix[2], ix[3])), (-1, (ix[0], ix[1], ix[3], ix[2])),
+                        (1, (ix[1], ix[0], ix[3], ix[2]))]
+    ix = (0, 2, 1, 4)
+    assert abs(_images_fd(dom, "t2aa", ix, t2img) - 4 * g["t2aa"][ix]) <= 1e-9 * abs(4 * g["t2aa"][ix])
+    symimg = lambda ix: [(1, ix), (1, (ix[0], ix[2], ix[1]))]
+    ix = (3, 1, 4)
+    assert abs(_images_fd(dom, "Bvv_b", ix, symimg) - 2 * g["Bvv_b"][ix]) <= 1e-8 * abs(2 * g["Bvv_b"][ix])
+    diag = lambda ix: [(1, ix)]
+    ix = (2, 3, 3)
+    assert abs(_images_fd(dom, "Boo_a", ix, diag) - g["Boo_a"][ix]) <= 1e-8 * abs(g["Boo_a"][ix])
+    # the projected gradients carry the symmetry of their inputs
+    for k, perm, sgn in (("t2aa", (1, 0, 2, 3), -1), ("t2bb", (0, 1, 3, 2), -1), ("Bvv_a", (0, 2, 1), 1),
+                         ("Boo_b", (0, 2, 1), 1)):
+        assert np.max(np.abs(g[k] - sgn * g[k].transpose(*perm))) <= 1e-14 * np.max(np.abs(g[k]))
+
+
+def test_gbar_scales_and_items_add():
+    dom = _dom((4, 3, 5, 6, 12))
+    items = blocks.enumerate_items(dom.noa, dom.nob)
+    _, g = grad.energy_and_grad(dom)
+    _, g2 = grad.energy_and_grad(dom, gbar=-2.0)
+    _, ga = grad.energy_and_grad(dom, items=items[::2])
+    _, gb = grad.energy_and_grad(dom, items=items[1::2])
+    for k in grad.FIELDS:
+        assert np.allclose(g2[k], -2.0 * g[k], rtol=1e-14, atol=0)
+        assert np.allclose(ga[k] + gb[k], g[k], rtol=1e-12, atol=1e-18)
+
+
+def test_planted_unprojected_gradient_is_caught(monkeypatch):
+    """Without the projection the image convention pin fails."""
+    monkeypatch.setattr(grad, "project", lambda g: g)
+    dom = _dom((4, 2, 5, 6, 12))
+    _, g = grad.energy_and_grad(dom)
+    t2img = lambda ix: [(1, ix), (-1, (ix[1], ix[0], ix[2], ix[3])), (-1, (ix[0], ix[1], ix[3], ix[2])),
+                        (1, (ix[1], ix[0], ix[3], ix[2]))]
+    ix = (0, 2, 1, 4)
+    fd = _images_fd(dom, "t2aa", ix, t2img)
+    assert abs(fd - 4 * g["t2aa"][ix]) > 1e-6 * abs(fd)
+
+
+def test_planted_sign_error_in_transcription_is_caught(monkeypatch):
+    """A sign flip of one mixed-block singles term changes the gradient along
+    t1b, and the exact stencil of the NumPy energy sees it."""
+    dom = _dom((3, 2, 5, 6, 12))
+    orig = grad._Item.mixed
+
+    def bad(self, s, i, j, K):
+        t1 = self.X["t1" + "ab"[1 - s]]
+        self.X["t1" + "ab"[1 - s]] = -t1
+        try:
+            return orig(self, s, i, j, K)
+        finally:
+            self.X["t1" + "ab"[1 - s]] = t1
+    monkeypatch.setattr(grad._Item, "mixed", bad)
+    _, g = grad.energy_and_grad(dom)
+    rng = np.random.default_rng(1)
+    d = _direction(dom, "t1b", rng)
+    fd = _stencil(dom, "t1b", d, _blocks_E)
+    assert abs(float(np.sum(g["t1b"] * d)) - fd) > 1e-6 * abs(fd)
