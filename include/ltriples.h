@@ -153,6 +153,50 @@ int ltriples_energy(const ltriples_domain* d, int32_t precision,
                     const ltriples_options* o, double* e_out, double* parts,
                     void* ws, size_t ws_bytes, void* stream);
 
+/* Gradient outputs of ltriples_backward: caller-owned device FP64 buffers in
+ * the layouts of the corresponding ltriples_domain inputs.  A NULL field is
+ * not written.  Gradients of inputs that carry a symmetry are returned
+ * projected onto it: dE/dt2aa and dE/dt2bb antisymmetrised in (i,j) and in
+ * (a,b), dE/dBoo and dE/dBvv symmetrised in their two orbital indices (a
+ * finite difference moving all images of one element together sees 4x
+ * resp. 2x the returned off-diagonal element). */
+typedef struct {
+  double *t1a, *t1b, *t2aa, *t2bb, *t2ab;
+  double *Boo_a, *Bov_a, *Bvv_a, *Boo_b, *Bov_b, *Bvv_b;
+} ltriples_domain_grad;
+
+/* Host-only: workspace bytes of ltriples_backward. */
+int ltriples_backward_workspace_size(const ltriples_domain* d, int32_t precision,
+                                     const ltriples_options* o, size_t* bytes);
+
+/* Adjoint of ltriples_energy: gbar * dE/dx for x in T1, T2 and the DF
+ * factors (orbital energies and f_ov are constants here).  E is the energy
+ * of eq. cim_pt_energy as read by ltriples_energy (all occupied triplets, or
+ * the item subset of options.items).  The connected W is recomputed per item
+ * batch, never stored; the work is about three times the forward flops.
+ *   gbar   device pointer to one double (the incoming adjoint dL/dE)
+ *   grad   host struct of device output pointers (see ltriples_domain_grad)
+ *   ws     device workspace >= ltriples_backward_workspace_size(), or NULL
+ * Precision LT_FP64 or LT_FP32 (the contractions and operand gradients in
+ * that precision, the epilogue, the integral gradients and the DF
+ * back-contraction in FP64); other values give LT_EPREC.  options.e_items
+ * must be NULL.  Enqueued on `stream`; the call synchronises the stream once
+ * after uploading its work descriptors.  Errors as ltriples_energy. */
+int ltriples_backward(const ltriples_domain* d, int32_t precision,
+                      const ltriples_options* o, const double* gbar,
+                      const ltriples_domain_grad* grad, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Host-only self-check of the launch plan (no HIP calls).  With
+ * backward != 0 it builds the adjoint pass's reverse-contraction descriptors
+ * against a placeholder workspace base and verifies that every memory range
+ * they address lies inside its planned buffer, that operands are 16-byte
+ * aligned with row strides that are multiples of 4 elements, and that the
+ * output blocks of one launch do not overlap (element by element for plans
+ * below 256 MiB).  LT_OK, or an error code with a message. */
+int ltriples_plan_check(const ltriples_domain* d, int32_t precision,
+                        const ltriples_options* o, int32_t backward);
+
 /* Host-only: workspace bytes of ltriples_energy_batched for ndom domains. */
 int ltriples_workspace_size_batched(const ltriples_domain* ds, int32_t ndom,
                                     int32_t precision, const ltriples_options* o,

@@ -75,6 +75,13 @@ class Options(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 3)]
 
 
+GRAD_FIELDS = ("t1a", "t1b", "t2aa", "t2bb", "t2ab", "Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b")
+
+
+class DomainGrad(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in GRAD_FIELDS]
+
+
 class LtError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"ltriples error {code}: {msg}")
@@ -104,10 +111,16 @@ def load_library(path: Optional[str] = None):
     lib.ltriples_energy_batched.argtypes = [Dp, ctypes.c_int32, ctypes.c_int32, Op, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.ltriples_graph_reset.argtypes = []
+    lib.ltriples_plan_check.argtypes = [Dp, ctypes.c_int32, Op, ctypes.c_int32]
+    Gp = ctypes.POINTER(DomainGrad)
+    lib.ltriples_backward_workspace_size.argtypes = [Dp, ctypes.c_int32, Op, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ltriples_backward.argtypes = [Dp, ctypes.c_int32, Op, ctypes.c_void_p, Gp, ctypes.c_void_p,
+                                      ctypes.c_size_t, ctypes.c_void_p]
     lib.ltriples_last_error.restype = ctypes.c_char_p
     lib.ltriples_version.restype = ctypes.c_char_p
     for f in ("ltriples_validate", "ltriples_workspace_size", "ltriples_flops", "ltriples_energy",
-              "ltriples_workspace_size_batched", "ltriples_energy_batched", "ltriples_graph_reset"):
+              "ltriples_workspace_size_batched", "ltriples_energy_batched", "ltriples_graph_reset",
+              "ltriples_backward_workspace_size", "ltriples_backward", "ltriples_plan_check"):
         getattr(lib, f).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -281,3 +294,87 @@ def ltriples_energy_batched(tensors_list, dims_list, precision: int = LT_FP32, g
 
 def ltriples_graph_reset():
     _check(load_library().ltriples_graph_reset())
+
+
+def ltriples_backward_workspace_size(dom: Domain, precision: int, options: Optional[Options] = None) -> int:
+    lib = load_library()
+    n = ctypes.c_size_t(0)
+    _check(lib.ltriples_backward_workspace_size(ctypes.byref(dom), int(precision),
+                                                ctypes.byref(options) if options is not None else None,
+                                                ctypes.byref(n)))
+    return n.value
+
+
+def ltriples_backward(tensors: Mapping[str, object], dims, precision: int = LT_FP64, gbar=None, items=None,
+                      batch_budget: int = 0, batch_items: int = 0, workspace=None, out=None, stream=None,
+                      stats: Optional[Stats] = None):
+    """gbar * dE/dx for x in GRAD_FIELDS (projected convention for t2aa, t2bb,
+    Boo, Bvv).  Returns a dict of float64 device tensors shaped like the
+    inputs.  `gbar` is a float64 device tensor with one element (default 1);
+    `out` may supply the output tensors (a dict keyed like the result)."""
+    import torch
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    dom = make_domain(dims, tensors)
+    opts, keep = make_options(items, None, batch_budget, batch_items, stats)
+    dev = next(t for t in tensors.values() if hasattr(t, "device")).device
+    if gbar is None:
+        gbar = torch.ones(1, dtype=torch.float64, device=dev)
+    if gbar.dtype != torch.float64 or gbar.numel() != 1 or not gbar.is_contiguous():
+        raise ValueError("gbar must be one contiguous float64 element")
+    if out is None:
+        out = {k: torch.empty_like(tensors[k]) for k in GRAD_FIELDS}
+    g = DomainGrad()
+    for k in GRAD_FIELDS:
+        setattr(g, k, _ptr(out.get(k)))
+    need = ltriples_backward_workspace_size(dom, precision, opts)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    _check(load_library().ltriples_backward(ctypes.byref(dom), int(precision), ctypes.byref(opts), gbar.data_ptr(),
+                                            ctypes.byref(g), workspace.data_ptr(), workspace.numel(),
+                                            st.cuda_stream))
+    del keep
+    return out
+
+
+def _autograd_function():
+    import torch
+
+    class TriplesEnergy(torch.autograd.Function):
+        """E(T) as a differentiable function of T1, T2 and the DF factors
+        (orbital energies and f_ov are constants)."""
+
+        @staticmethod
+        def forward(ctx, precision, dims, *arrays):
+            tens = dict(zip(ARRAY_FIELDS, arrays))
+            e, _ = ltriples_energy(tens, dims, precision)
+            ctx.precision, ctx.dims = precision, dims
+            ctx.save_for_backward(*arrays)
+            return e.reshape(())
+
+        @staticmethod
+        def backward(ctx, gE):
+            tens = dict(zip(ARRAY_FIELDS, ctx.saved_tensors))
+            prec = ctx.precision if ctx.precision in (LT_FP64, LT_FP32) else LT_FP32
+            gbar = gE.detach().to(torch.float64).reshape(1).contiguous()
+            g = ltriples_backward(tens, ctx.dims, prec, gbar=gbar)
+            return (None, None) + tuple(g.get(k) if ctx.needs_input_grad[2 + n] else None
+                                        for n, k in enumerate(ARRAY_FIELDS))
+
+    return TriplesEnergy
+
+
+_TE = None
+
+
+def triples_energy(tensors: Mapping[str, object], dims, precision="fp64"):
+    """Differentiable E(T) (0-d float64 tensor).  Gradients flow to T1, T2 and
+    the DF factors through ltriples_backward (FP64, or FP32 for the reduced
+    precisions); orbital energies and f_ov receive none."""
+    global _TE
+    if _TE is None:
+        _TE = _autograd_function()
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    return _TE.apply(int(precision), tuple(int(x) for x in dims), *(tensors[k] for k in ARRAY_FIELDS))

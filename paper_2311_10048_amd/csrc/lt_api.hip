@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -181,6 +182,14 @@ struct Plan {
   Buf As[2], Tp[2], T2T[2], GamT[2], U[2];
   Buf LmixT[2], Mst[2], Mts[2], Tmix[2], ZpT[2], TmT[2], OOT[2];
   Buf OVab, e_items, trip, dst, order, firstcnt;
+  // adjoint pass: extra operands, mirrors (gradients of the prepared
+  // operands, same layouts), FP64 four-index integral gradients, descriptors
+  bool bwd = false;
+  Buf T1p[2], Fp[2], Up[2], OVc[2], BvvP64[2];
+  Buf dT2T[2], dTp[2], dAs[2], dGamT[2], dUp[2], dT1p[2];
+  Buf dLmixT[2], dMst[2], dMts[2], dTmix[2], dZpT[2], dTmT[2], dOOT[2], dOVc[2];
+  Buf dOVVV[2][2], dOVOO[2][2], dOVOV[3];   // ovov: aa, bb, ab
+  Buf rblk, rseg, dfblk, dfseg;
   // BF16 modes: hi/lo octet copies of the contraction operands
   int bf = 0;                     // 0: none, 3: split products, 1: plain bf16
   enum { T2T8, As8, GamT8, Tp8, LmixT8, Mst8, Mts8, Tmix8, Tmx28, ZpT8, TmT8, OOT8, NT8 };
@@ -190,14 +199,16 @@ struct Plan {
   size_t sc_OO[2][2], sc_OV[2];   // offsets within scratch (phase 1a)
   int64_t nb[4];                  // items per batch
   size_t per_item[4];             // batch bytes per item (T outputs)
+  size_t o1[4], o2[4];            // aligned per-item bytes of the two output layouts
   size_t part_off[4];             // partials offset within scratch (phase 2)
   int64_t ntile[4];
   size_t big = 0, small = 0, small_base = 0, total = 0;
 };
 
 void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options* o,
-                 const ItemLists& L, Plan& P) {
+                 const ItemLists& L, Plan& P, bool bwd = false) {
   P.prec = prec;
+  P.bwd = bwd;
   P.ts = prec == LT_FP64 ? 8 : 4;   // BF16 modes prepare FP32 operands, then split them
   P.D = dims_of(d);
   const Dims& D = P.D;
@@ -248,6 +259,38 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
     }
   }
   if (P.any_mix) take(P.OVab, 8 * D.o[0] * D.v[0] * D.o[1] * D.v[1]);
+  if (bwd) {
+    for (int s = 0; s < 2; ++s) {
+      const int t = 1 - s;
+      const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
+      const bool need_df = P.need_as[s] || P.any_mix;
+      if (need_df) take(P.BvvP64[s], 8 * Q * P.ldvv[s]);
+      if (need_df) { take(P.T1p[s], ts * os * P.ldv[s]); take(P.Fp[s], ts * os * P.ldv[s]); }
+      if (need_df) take(P.dT1p[s], ts * os * P.ldv[s]);
+      if (P.need_as[s]) {
+        take(P.Up[s], ts * os * os * P.ldnp[s]);
+        take(P.dAs[s], P.As[s].bytes); take(P.dTp[s], P.Tp[s].bytes); take(P.dT2T[s], P.T2T[s].bytes);
+        take(P.dGamT[s], P.GamT[s].bytes); take(P.dUp[s], P.Up[s].bytes);
+      }
+      if (P.need_mix[s]) {
+        take(P.OVc[s], ts * os * ot * P.ldcb[s]);
+        take(P.dLmixT[s], P.LmixT[s].bytes); take(P.dMst[s], P.Mst[s].bytes); take(P.dMts[s], P.Mts[s].bytes);
+        take(P.dTmix[s], P.Tmix[s].bytes); take(P.dZpT[s], P.ZpT[s].bytes); take(P.dTmT[s], P.TmT[s].bytes);
+        take(P.dOOT[s], P.OOT[s].bytes); take(P.dOVc[s], P.OVc[s].bytes);
+      }
+      (void)vt;
+    }
+    for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < 2; ++y) {
+        const bool need = x == y ? P.need_as[x] : (P.need_mix[x] || P.need_mix[y]);
+        if (!need) continue;
+        take(P.dOVVV[x][y], 8 * D.o[x] * D.v[x] * P.ldvv[y]);
+        take(P.dOVOO[x][y], 8 * D.o[x] * D.v[x] * P.ldoo[y]);
+      }
+    for (int s = 0; s < 2; ++s)
+      if (P.need_as[s]) take(P.dOVOV[s], 8 * D.o[s] * D.v[s] * P.ldov[s]);
+    if (P.any_mix) take(P.dOVOV[2], 8 * D.o[0] * D.v[0] * P.ldov[1]);
+  }
   P.bf = prec == LT_BF16X3 ? 3 : (prec == LT_BF16 ? 1 : 0);
   if (P.bf) {
     auto k16 = [](int64_t k) { return (k + 15) & ~int64_t(15); };
@@ -314,7 +357,9 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
       nt = ns * (ns + 1) / 2 * nt_;
     }
     P.ntile[b] = nt;
-    const size_t per = align256(outb) + align256(8 * 3 * (size_t)std::max<int64_t>(nt, 1));
+    P.o1[b] = align256(ts * (size_t)(blk_mixed(b) ? vs * P.ldcb[s] : vs * P.ldnp[s]));
+    P.o2[b] = blk_mixed(b) ? align256(ts * (size_t)(vt * P.ldnp[s])) : 0;
+    const size_t per = (bwd ? 3 : 1) * (P.o1[b] + P.o2[b]) + align256(8 * 3 * (size_t)std::max<int64_t>(nt, 1));
     P.per_item[b] = outb;
     int64_t nb = (o && o->batch_items > 0) ? o->batch_items : (int64_t)std::max<size_t>(1, budget / per);
     nb = std::min<int64_t>(nb, P.n_blk[b]);
@@ -423,45 +468,16 @@ int upload_items(const Plan& P, const ItemLists& L, void* ws, hipStream_t st) {
   return LT_OK;
 }
 
-// Enqueues the whole (T) path of one domain on `st` (kernels only; safe to
-// capture into a graph).
+// Operand preparation (steps 1-4 of the launch sequence): kernels only.
 template <typename T>
-int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltriples_options* o,
-        double* e_out, double* parts, void* ws, hipStream_t st, Timing& tm) {
+int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
   const Dims& D = P.D;
   const int64_t Q = D.Q;
   const double* Bvv[2] = {d->Bvv_a, d->Bvv_b};
   const double* Bov[2] = {d->Bov_a, d->Bov_b};
   const double* Boo[2] = {d->Boo_a, d->Boo_b};
   const double* T2ss[2] = {d->t2aa, d->t2bb};
-  const double* T1[2] = {d->t1a, d->t1b};
-  const double* Fov[2] = {d->fov_a, d->fov_b};
-  const double* EO[2] = {d->eo_a, d->eo_b};
-  const double* EV[2] = {d->ev_a, d->ev_b};
   char* scr = (char*)ws + P.scratch.off;
-
-  // --- item arrays (already uploaded by upload_items) --------------------------
-  int32_t fc[8];
-  for (int b = 0, n = 0; b < 4; ++b) {
-    fc[b] = n;
-    fc[4 + b] = (int32_t)L.dst[b].size();
-    n += fc[4 + b];
-  }
-  int32_t* d_trip = at_small<int32_t>(ws, P, P.trip);
-  int32_t* d_dst = at_small<int32_t>(ws, P, P.dst);
-  int32_t* d_fc = at_small<int32_t>(ws, P, P.firstcnt);
-  double* e_items = (o && o->e_items) ? o->e_items : at_small<double>(ws, P, P.e_items);
-  tm.start = tm.mark();
-  if (o && o->e_items && L.total > 0) HIPCHK(lt::launch_zero(o->e_items, 3 * L.total, st));
-  HIPCHK(lt::launch_zero(at_small<double>(ws, P, P.e_items), 3 * std::max<int64_t>(L.total, 1), st));
-  if (L.total == 0 || (D.v[0] == 0 && D.v[1] == 0)) {
-    HIPCHK(lt::launch_zero(e_out, 1, st));
-    if (parts) HIPCHK(lt::launch_zero(parts, 12, st));
-    tm.setup_end = tm.mark();
-    tm.end = tm.setup_end;
-    return LT_OK;
-  }
-
   // --- 1. DF factor layouts --------------------------------------------------
   for (int s = 0; s < 2; ++s) {
     if (!P.BvvP[s].bytes) continue;
@@ -620,6 +636,84 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
       }
     }
   }
+  if (P.bwd) {
+    // adjoint pass: FP64 padded Bvv for the DF back-contraction; t1, f_ov rows;
+    // <qr||bc> pair-packed; (jb|KC) in the mixed output layout
+    const double* T1[2] = {d->t1a, d->t1b};
+    const double* Fov[2] = {d->fov_a, d->fov_b};
+    const int64_t va = D.v[0], ob = D.o[1], vb = D.v[1];
+    const int64_t so[4] = {va * ob * vb, ob * vb, vb, 1};     // OVab strides (occ_a, vir_a, occ_b, vir_b)
+    for (int s = 0; s < 2; ++s) {
+      const int t = 1 - s;
+      const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t], lv = P.ldv[s], lc = P.ldcb[s];
+      if (P.BvvP64[s].bytes)
+        HIPCHK(lt::launch_copy4d<double, double>(at<double>(ws, P.BvvP64[s]), 0, 0, P.ldvv[s], 1, 1, Q, vs * vs,
+                                                 Bvv[s], 0, 0, vs * vs, 1, nullptr, 0, 0, 0, 0, st));
+      if (P.T1p[s].bytes) {
+        HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.T1p[s]), 0, 0, lv, 1, 1, os, vs, T1[s], 0, 0, vs, 1,
+                                            nullptr, 0, 0, 0, 0, st));
+        HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.Fp[s]), 0, 0, lv, 1, 1, os, vs, Fov[s], 0, 0, vs, 1,
+                                            nullptr, 0, 0, 0, 0, st));
+      }
+      if (P.Up[s].bytes)   // Up[q][r][p(b<c)] = <qr||bc>
+        HIPCHK(lt::launch_pack_pairs<double, T>(at<T>(ws, P.Up[s]), P.ldnp[s], os * os, (int32_t)vs,
+                                                at<double>(ws, P.U[s]), vs * lv, lv, 1, false, st));
+      if (P.OVc[s].bytes) {  // OVc[j][K][C*vs+b] = (jb|KC)
+        const int64_t sj = s == 0 ? so[0] : so[2], sb = s == 0 ? so[1] : so[3];
+        const int64_t sK = s == 0 ? so[2] : so[0], sC = s == 0 ? so[3] : so[1];
+        HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.OVc[s]), ot * lc, lc, vs, os, ot, vt, vs,
+                                            at<double>(ws, P.OVab), sj, sK, sC, sb, nullptr, 0, 0, 0, 0, st));
+      }
+    }
+  }
+  return LT_OK;
+}
+
+// Enqueues the whole (T) path of one domain on `st` (kernels only; safe to
+// capture into a graph).
+template <typename T>
+int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltriples_options* o,
+        double* e_out, double* parts, void* ws, hipStream_t st, Timing& tm) {
+  const Dims& D = P.D;
+  const int64_t Q = D.Q;
+  const double* Bvv[2] = {d->Bvv_a, d->Bvv_b};
+  const double* Bov[2] = {d->Bov_a, d->Bov_b};
+  const double* Boo[2] = {d->Boo_a, d->Boo_b};
+  const double* T2ss[2] = {d->t2aa, d->t2bb};
+  const double* T1[2] = {d->t1a, d->t1b};
+  const double* Fov[2] = {d->fov_a, d->fov_b};
+  const double* EO[2] = {d->eo_a, d->eo_b};
+  const double* EV[2] = {d->ev_a, d->ev_b};
+  char* scr = (char*)ws + P.scratch.off;
+
+  // --- item arrays (already uploaded by upload_items) --------------------------
+  int32_t fc[8];
+  for (int b = 0, n = 0; b < 4; ++b) {
+    fc[b] = n;
+    fc[4 + b] = (int32_t)L.dst[b].size();
+    n += fc[4 + b];
+  }
+  int32_t* d_trip = at_small<int32_t>(ws, P, P.trip);
+  int32_t* d_dst = at_small<int32_t>(ws, P, P.dst);
+  int32_t* d_fc = at_small<int32_t>(ws, P, P.firstcnt);
+  double* e_items = (o && o->e_items) ? o->e_items : at_small<double>(ws, P, P.e_items);
+  tm.start = tm.mark();
+  if (o && o->e_items && L.total > 0) HIPCHK(lt::launch_zero(o->e_items, 3 * L.total, st));
+  HIPCHK(lt::launch_zero(at_small<double>(ws, P, P.e_items), 3 * std::max<int64_t>(L.total, 1), st));
+  if (L.total == 0 || (D.v[0] == 0 && D.v[1] == 0)) {
+    HIPCHK(lt::launch_zero(e_out, 1, st));
+    if (parts) HIPCHK(lt::launch_zero(parts, 12, st));
+    tm.setup_end = tm.mark();
+    tm.end = tm.setup_end;
+    return LT_OK;
+  }
+
+  {
+    const int r = prep<T>(d, P, ws, st);
+    if (r) return r;
+  }
+  const int64_t oa = D.o[0], ob = D.o[1], va = D.v[0], vb = D.v[1];
+  int64_t mstr[2][4] = {{ob * va * vb, va * vb, vb, 1}, {va * vb, ob * va * vb, 1, vb}};
   tm.setup_end = tm.mark();
   // --- 5. triplet batches --------------------------------------------------------------
   for (int b = 0; b < 4; ++b) {
@@ -662,9 +756,9 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
     };
     const int64_t nb = P.nb[b];
     T* out1 = (T*)scr;
-    const size_t o1 = align256(P.ts * (size_t)(mixed ? vs * P.ldcb[s] : vs * P.ldnp[s]));
+    const size_t o1 = P.o1[b];
     T* out2 = (T*)(scr + (size_t)nb * o1);
-    const size_t o2 = mixed ? align256(P.ts * (size_t)(vt * P.ldnp[s])) : 0;
+    const size_t o2 = P.o2[b];
     double* part = (double*)(scr + (size_t)nb * (o1 + o2));
     const int64_t nt = P.ntile[b];
     for (int64_t first = 0; first < nblk; first += nb) {
@@ -764,6 +858,548 @@ int check_denominators(const ltriples_domain* d) {
     }
   }
   if (omax >= vmin) return fail(LT_EDENOM, "max occupied energy %.6g >= min virtual energy %.6g", omax, vmin);
+  return LT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint pass (backward).  Per batch of items: the forward contraction is
+// recomputed (W is never stored), the backward epilogue writes the adjoints of
+// the contraction outputs, and reverse GEMMs accumulate the gradients of every
+// prepared operand into mirror buffers of the same layout.  The mirrors are
+// then mapped back to the amplitudes and to FP64 four-index integral
+// gradients, which the DF back-contraction turns into gradients of the DF
+// factors; the gradients of symmetric inputs are projected last.
+// ---------------------------------------------------------------------------
+template <typename T> struct RevBuilder {
+  struct Tgt { lt::RBlk<T> blk; std::vector<lt::RSeg<T>> segs; };
+  struct Group { bool tb = false; std::map<uintptr_t, Tgt> tg; };
+  struct Launch { bool tb; int64_t blk0, nblk; int32_t max_rows, max_cols; double flops; };
+  std::vector<lt::RBlk<T>> blks;
+  std::vector<lt::RSeg<T>> segs;
+  std::vector<Launch> launches;
+  std::vector<Group> groups;
+  void begin(int n) { groups.assign(n, Group{}); }
+  void add(int gi, bool tb, T* out, int64_t ldo, int64_t rows, int64_t cols, const lt::RSeg<T>& sg) {
+    if (!out || rows <= 0 || cols <= 0 || sg.K <= 0) return;
+    Group& g = groups[gi];
+    g.tb = tb;
+    Tgt& t = g.tg[(uintptr_t)out];
+    if (t.segs.empty()) t.blk = lt::RBlk<T>{out, ldo, (int32_t)rows, (int32_t)cols, 0, 0};
+    t.segs.push_back(sg);
+  }
+  // emits one launch per non-empty group, targets in address order
+  void flush() {
+    for (Group& g : groups) {
+      if (g.tg.empty()) continue;
+      Launch l{g.tb, (int64_t)blks.size(), 0, 0, 0, 0.0};
+      for (auto& kv : g.tg) {
+        lt::RBlk<T> b = kv.second.blk;
+        b.beg = (int32_t)segs.size();
+        for (auto& x : kv.second.segs) {
+          segs.push_back(x);
+          l.flops += 2.0 * b.rows * (double)b.cols * x.K;
+        }
+        b.end = (int32_t)segs.size();
+        l.max_rows = std::max(l.max_rows, b.rows);
+        l.max_cols = std::max(l.max_cols, b.cols);
+        blks.push_back(b);
+        ++l.nblk;
+      }
+      launches.push_back(l);
+    }
+    groups.clear();
+  }
+};
+
+// One forward contraction segment of an item: X = sign * L^T R over K rows,
+// with the mirrors (gradient buffers) of both operands and the reverse groups.
+template <typename T> struct FSeg {
+  const T* L; T* dL; int64_t lks;
+  const T* R; T* dR; int64_t rks;
+  int64_t K; float sign; int gR, gL;
+};
+
+template <typename T>
+void add_rev(RevBuilder<T>& rb, const FSeg<T>& f, const T* dX, int64_t ldX, int64_t M, int64_t N) {
+  if (f.gR >= 0) rb.add(f.gR, false, f.dR, f.rks, f.K, N, lt::RSeg<T>{f.L, f.lks, dX, ldX, (int32_t)M, f.sign});
+  if (f.gL >= 0) rb.add(f.gL, true, f.dL, f.lks, f.K, M, lt::RSeg<T>{f.R, f.rks, dX, ldX, (int32_t)N, f.sign});
+}
+
+// Descriptor lists of every batch (in launch order) for workspace base `ws`.
+template <typename T>
+void build_rev(const Plan& P, const ItemLists& L, char* ws, RevBuilder<T>& rb,
+               std::vector<std::pair<size_t, size_t>>& batch_launch) {
+  const Dims& D = P.D;
+  char* scr = ws + P.scratch.off;
+  auto A = [&](const Buf& b) { return (T*)(ws + b.off); };
+  for (int b = 0; b < 4; ++b) {
+    const int64_t nblk = P.n_blk[b];
+    if (nblk == 0) continue;
+    const int s = blk_sigma(b), t = 1 - s;
+    const bool mixed = blk_mixed(b);
+    const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
+    const int64_t lv = P.ldv[s], lvt = P.ldv[t], lp = P.ldnp[s], lc = P.ldcb[s], np = npair(vs);
+    const int64_t nb = P.nb[b];
+    const size_t o1 = P.o1[b], o2 = P.o2[b];
+    const int64_t s1 = (int64_t)(o1 / P.ts), s2 = (int64_t)(o2 / P.ts);
+    T *T2T = A(P.T2T[s]), *dT2T = A(P.dT2T[s]), *As = A(P.As[s]), *dAs = A(P.dAs[s]);
+    T *Gam = A(P.GamT[s]), *dGam = A(P.dGamT[s]), *Tp = A(P.Tp[s]), *dTp = A(P.dTp[s]);
+    T *Up = A(P.Up[s]), *dUp = A(P.dUp[s]), *T1p = A(P.T1p[s]), *dT1p = A(P.dT1p[s]), *Fp = A(P.Fp[s]);
+    for (int64_t first = 0; first < nblk; first += nb) {
+      const int64_t n = std::min<int64_t>(nb, nblk - first);
+      const size_t l0 = rb.launches.size();
+      const int32_t* tr = L.trip[b].data() + 3 * first;
+      if (!mixed) {
+        T* dS = (T*)(scr + (size_t)nb * o1);
+        T* dSV = (T*)(scr + 2 * (size_t)nb * o1);
+        rb.begin(6);
+        for (int64_t m = 0; m < n; ++m) {
+          const int64_t i = tr[3 * m], j = tr[3 * m + 1], k = tr[3 * m + 2];
+          const int64_t pm[3][3] = {{i, j, k}, {j, i, k}, {k, j, i}};
+          const float sg[3] = {1.f, -1.f, -1.f};
+          const T* dSm = dS + m * s1;
+          const T* dSVm = dSV + m * s1;
+          for (int u = 0; u < 3; ++u) {
+            const int64_t p = pm[u][0], q = pm[u][1], r = pm[u][2];
+            const int64_t ot2 = (q * os + r) * vs * lv, og = (q * os + r) * os * lv;
+            // sum_e t^{ae}_{qr} <ep||bc>
+            add_rev(rb, FSeg<T>{T2T + ot2, dT2T + ot2, lv, As + p * vs * lp, dAs + p * vs * lp, lp, vs, sg[u], 0, 2},
+                    dSm, lp, vs, np);
+            // - sum_m <ma||qr> t^{bc}_{pm}
+            add_rev(rb, FSeg<T>{Gam + og, dGam + og, lv, Tp + p * os * lp, dTp + p * os * lp, lp, os, -sg[u], 1, 3},
+                    dSm, lp, vs, np);
+            // singles and f_ov terms: t1[p] x <qr||bc>, f[p] x t^{bc}_{qr}
+            const int64_t orow = (q * os + r) * lp;
+            add_rev(rb, FSeg<T>{T1p + p * lv, dT1p + p * lv, lv, Up + orow, dUp + orow, lp, 1, sg[u], 4, 5},
+                    dSVm, lp, vs, np);
+            add_rev(rb, FSeg<T>{Fp + p * lv, nullptr, lv, Tp + orow, dTp + orow, lp, 1, sg[u], 4, -1},
+                    dSVm, lp, vs, np);
+          }
+        }
+        rb.flush();
+      } else {
+        T *LmT = A(P.LmixT[s]), *dLmT = A(P.dLmixT[s]), *Mst = A(P.Mst[s]), *dMst = A(P.dMst[s]);
+        T *Mts = A(P.Mts[s]), *dMts = A(P.dMts[s]), *Tmix = A(P.Tmix[s]), *dTmix = A(P.dTmix[s]);
+        T *ZpT = A(P.ZpT[s]), *dZpT = A(P.dZpT[s]), *TmT = A(P.TmT[s]), *dTmT = A(P.dTmT[s]);
+        T *OOT = A(P.OOT[s]), *dOOT = A(P.dOOT[s]), *OVc = A(P.OVc[s]), *dOVc = A(P.dOVc[s]);
+        T *T1t = A(P.T1p[t]), *dT1t = A(P.dT1p[t]), *Ft = A(P.Fp[t]);
+        const size_t q1 = (size_t)nb * (o1 + o2);
+        T* dG = (T*)(scr + q1);
+        T* dY = (T*)(scr + q1 + (size_t)nb * o1);
+        T* dGV = (T*)(scr + 2 * q1);
+        T* dYV = (T*)(scr + 2 * q1 + (size_t)nb * o1);
+        rb.begin(14);
+        for (int64_t m = 0; m < n; ++m) {
+          const int64_t i = tr[3 * m], j = tr[3 * m + 1], K = tr[3 * m + 2];
+          const T* dGm = dG + m * s1;
+          const T* dYm = dY + m * s2;
+          const T* dGVm = dGV + m * s1;
+          const T* dYVm = dYV + m * s2;
+          const int64_t M1 = vs, N1 = vt * vs, M2 = vt, N2 = np;
+          auto lm = [&](int64_t p) { return (p * ot + K) * vt * lv; };
+          auto zp = [&](int64_t p) { return (p * ot + K) * ot * lv; };
+          auto tm = [&](int64_t p) { return (p * ot + K) * vs * lvt; };
+          auto oo = [&](int64_t p) { return (K * os + p) * os * lvt; };
+          const int64_t oij2 = (i * os + j) * vs * lv, oijg = (i * os + j) * os * lv;
+          // G[a][C*vs+b]
+          add_rev(rb, FSeg<T>{LmT + lm(i), dLmT + lm(i), lv, Mst + j * vt * lc, dMst + j * vt * lc, lc, vt, 1.f, 0, 6},
+                  dGm, lc, M1, N1);
+          add_rev(rb, FSeg<T>{LmT + lm(j), dLmT + lm(j), lv, Mst + i * vt * lc, dMst + i * vt * lc, lc, vt, -1.f, 0, 6},
+                  dGm, lc, M1, N1);
+          add_rev(rb, FSeg<T>{T2T + oij2, dT2T + oij2, lv, Mts + K * vs * lc, dMts + K * vs * lc, lc, vs, 1.f, 1, 7},
+                  dGm, lc, M1, N1);
+          add_rev(rb, FSeg<T>{Gam + oijg, dGam + oijg, lv, Tmix + K * lc, dTmix + K * lc, ot * lc, os, 1.f, 2, 8},
+                  dGm, lc, M1, N1);
+          add_rev(rb, FSeg<T>{ZpT + zp(j), dZpT + zp(j), lv, Tmix + i * ot * lc, dTmix + i * ot * lc, lc, ot, 1.f, 3, 9},
+                  dGm, lc, M1, N1);
+          add_rev(rb, FSeg<T>{ZpT + zp(i), dZpT + zp(i), lv, Tmix + j * ot * lc, dTmix + j * ot * lc, lc, ot, -1.f, 3, 9},
+                  dGm, lc, M1, N1);
+          // Y[C][p(a<b)]
+          add_rev(rb, FSeg<T>{TmT + tm(i), dTmT + tm(i), lvt, As + j * vs * lp, dAs + j * vs * lp, lp, vs, 1.f, 4, 10},
+                  dYm, lp, M2, N2);
+          add_rev(rb, FSeg<T>{TmT + tm(j), dTmT + tm(j), lvt, As + i * vs * lp, dAs + i * vs * lp, lp, vs, -1.f, 4, 10},
+                  dYm, lp, M2, N2);
+          add_rev(rb, FSeg<T>{OOT + oo(j), dOOT + oo(j), lvt, Tp + i * os * lp, dTp + i * os * lp, lp, os, -1.f, 5, 11},
+                  dYm, lp, M2, N2);
+          add_rev(rb, FSeg<T>{OOT + oo(i), dOOT + oo(i), lvt, Tp + j * os * lp, dTp + j * os * lp, lp, os, 1.f, 5, 11},
+                  dYm, lp, M2, N2);
+          // singles and f_ov terms of the P(ij)P(ab) part: t1[p] x (qb|KC), f[p] x t^{bC}_{qK}
+          const int64_t pq[2][2] = {{i, j}, {j, i}};
+          const float sg[2] = {1.f, -1.f};
+          for (int u = 0; u < 2; ++u) {
+            const int64_t p = pq[u][0], q = pq[u][1], orow = (q * ot + K) * lc;
+            add_rev(rb, FSeg<T>{T1p + p * lv, dT1p + p * lv, lv, OVc + orow, dOVc + orow, lc, 1, sg[u], 12, 13},
+                    dGVm, lc, M1, N1);
+            add_rev(rb, FSeg<T>{Fp + p * lv, nullptr, lv, Tmix + orow, dTmix + orow, lc, 1, sg[u], 12, -1},
+                    dGVm, lc, M1, N1);
+          }
+          // t1[K][C] <ij||ab>, f[K][C] t^{ab}_{ij}
+          const int64_t orow = (i * os + j) * lp;
+          add_rev(rb, FSeg<T>{T1t + K * lvt, dT1t + K * lvt, lvt, Up + orow, dUp + orow, lp, 1, 1.f, 12, 13},
+                  dYVm, lp, M2, N2);
+          add_rev(rb, FSeg<T>{Ft + K * lvt, nullptr, lvt, Tp + orow, dTp + orow, lp, 1, 1.f, 12, -1},
+                  dYVm, lp, M2, N2);
+        }
+        rb.flush();
+      }
+      batch_launch.push_back({l0, rb.launches.size()});
+    }
+  }
+}
+
+// DF back-contraction descriptors (FP64): gradients of the four-index
+// integral classes -> gradients of Bov, Bvv, Boo (caller's buffers).
+void build_df_rev(const Plan& P, char* ws, const ltriples_domain_grad* g, RevBuilder<double>& rb) {
+  const Dims& D = P.D;
+  const int64_t Q = D.Q;
+  auto A = [&](const Buf& b) { return b.bytes ? (double*)(ws + b.off) : nullptr; };
+  double* gBov[2] = {g->Bov_a, g->Bov_b};
+  double* gBvv[2] = {g->Bvv_a, g->Bvv_b};
+  double* gBoo[2] = {g->Boo_a, g->Boo_b};
+  rb.begin(2);
+  for (int x = 0; x < 2; ++x) {
+    const int64_t nov = D.o[x] * D.v[x];
+    for (int y = 0; y < 2; ++y) {
+      if (double* Z = A(P.dOVVV[x][y])) {
+        rb.add(0, true, gBov[x], nov, Q, nov,
+               lt::RSeg<double>{A(P.BvvP64[y]), P.ldvv[y], Z, P.ldvv[y], (int32_t)(D.v[y] * D.v[y]), 1.f});
+        rb.add(1, false, gBvv[y], D.v[y] * D.v[y], Q, D.v[y] * D.v[y],
+               lt::RSeg<double>{A(P.BovP64[x]), P.ldov[x], Z, P.ldvv[y], (int32_t)nov, 1.f});
+      }
+      if (double* Z = A(P.dOVOO[x][y])) {
+        rb.add(0, true, gBov[x], nov, Q, nov,
+               lt::RSeg<double>{A(P.BooP64[y]), P.ldoo[y], Z, P.ldoo[y], (int32_t)(D.o[y] * D.o[y]), 1.f});
+        rb.add(1, false, gBoo[y], D.o[y] * D.o[y], Q, D.o[y] * D.o[y],
+               lt::RSeg<double>{A(P.BovP64[x]), P.ldov[x], Z, P.ldoo[y], (int32_t)nov, 1.f});
+      }
+    }
+  }
+  // (ia|jb) classes: aa, bb, ab
+  const int xy[3][2] = {{0, 0}, {1, 1}, {0, 1}};
+  for (int c = 0; c < 3; ++c) {
+    double* Z = A(P.dOVOV[c]);
+    if (!Z) continue;
+    const int x = xy[c][0], y = xy[c][1];
+    const int64_t nx = D.o[x] * D.v[x], ny = D.o[y] * D.v[y];
+    rb.add(0, true, gBov[x], nx, Q, nx, lt::RSeg<double>{A(P.BovP64[y]), P.ldov[y], Z, P.ldov[y], (int32_t)ny, 1.f});
+    rb.add(1, false, gBov[y], ny, Q, ny, lt::RSeg<double>{A(P.BovP64[x]), P.ldov[x], Z, P.ldov[y], (int32_t)nx, 1.f});
+  }
+  rb.flush();
+}
+
+const ltriples_domain_grad kNoGrad{};
+char* const kFakeBase = (char*)(uintptr_t)(1ull << 40);
+
+int plan_backward(const ltriples_domain* d, int32_t prec, const ltriples_options* o, const ItemLists& L,
+                  Plan& P) {
+  plan_domain(d, prec, o, L, P, true);
+  size_t nblk = 0, nseg = 0, dblk = 0, dseg = 0;
+  std::vector<std::pair<size_t, size_t>> bl;
+  if (prec == LT_FP64) {
+    RevBuilder<double> rb;
+    build_rev<double>(P, L, kFakeBase, rb, bl);
+    nblk = rb.blks.size(); nseg = rb.segs.size();
+  } else {
+    RevBuilder<float> rb;
+    build_rev<float>(P, L, kFakeBase, rb, bl);
+    nblk = rb.blks.size(); nseg = rb.segs.size();
+  }
+  {
+    ltriples_domain_grad all;
+    double* fake = (double*)kFakeBase;
+    all.t1a = all.t1b = all.t2aa = all.t2bb = all.t2ab = fake;
+    all.Boo_a = fake + 1; all.Bov_a = fake + 2; all.Bvv_a = fake + 3;
+    all.Boo_b = fake + 4; all.Bov_b = fake + 5; all.Bvv_b = fake + 6;
+    RevBuilder<double> rb;
+    build_df_rev(P, kFakeBase, &all, rb);
+    dblk = rb.blks.size(); dseg = rb.segs.size();
+  }
+  size_t off = P.small;
+  auto take = [&](Buf& b, size_t bytes) { b.off = off; b.bytes = bytes; off = align256(off + bytes); };
+  take(P.rblk, sizeof(lt::RBlk<double>) * std::max<size_t>(nblk, 1));
+  take(P.rseg, sizeof(lt::RSeg<double>) * std::max<size_t>(nseg, 1));
+  take(P.dfblk, sizeof(lt::RBlk<double>) * std::max<size_t>(dblk, 1));
+  take(P.dfseg, sizeof(lt::RSeg<double>) * std::max<size_t>(dseg, 1));
+  P.small = off;
+  P.total = P.big + P.small;
+  return LT_OK;
+}
+
+template <typename T>
+int launch_rev_list(const RevBuilder<T>& rb, size_t l0, size_t l1, const lt::RBlk<T>* dblk,
+                    const lt::RSeg<T>* dseg, hipStream_t st) {
+  for (size_t l = l0; l < l1; ++l) {
+    const auto& L = rb.launches[l];
+    lt::RArgs<T> g{};
+    g.nblk = (int32_t)L.nblk; g.max_rows = L.max_rows; g.max_cols = L.max_cols;
+    g.blks = dblk + L.blk0; g.segs = dseg;
+    HIPCHK(lt::launch_rgemm<T>(g, L.tb, st));
+  }
+  return LT_OK;
+}
+
+template <typename T>
+int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltriples_options* o,
+            const double* gbar, const ltriples_domain_grad* gr, void* ws, hipStream_t st, Timing& tm,
+            double* rev_flops) {
+  const Dims& D = P.D;
+  const int64_t Q = D.Q, oa = D.o[0], ob = D.o[1], va = D.v[0], vb = D.v[1];
+  const double* T1[2] = {d->t1a, d->t1b};
+  const double* Fov[2] = {d->fov_a, d->fov_b};
+  const double* EO[2] = {d->eo_a, d->eo_b};
+  const double* EV[2] = {d->ev_a, d->ev_b};
+  const double* T2ss[2] = {d->t2aa, d->t2bb};
+  char* scr = (char*)ws + P.scratch.off;
+  tm.start = tm.mark();
+  // outputs and accumulators start at zero
+  struct Z { double* p; int64_t n; } outs[] = {
+      {gr->t1a, oa * va}, {gr->t1b, ob * vb}, {gr->t2aa, oa * oa * va * va}, {gr->t2bb, ob * ob * vb * vb},
+      {gr->t2ab, oa * ob * va * vb}, {gr->Boo_a, Q * oa * oa}, {gr->Bov_a, Q * oa * va}, {gr->Bvv_a, Q * va * va},
+      {gr->Boo_b, Q * ob * ob}, {gr->Bov_b, Q * ob * vb}, {gr->Bvv_b, Q * vb * vb}};
+  for (auto& z : outs)
+    if (z.p) HIPCHK(lt::launch_zero(z.p, z.n, st));
+  if (L.total == 0 || (va == 0 && vb == 0)) {
+    tm.setup_end = tm.mark();
+    tm.end = tm.setup_end;
+    return LT_OK;
+  }
+  {
+    const Buf* zb[] = {&P.dT2T[0], &P.dT2T[1], &P.dTp[0], &P.dTp[1], &P.dAs[0], &P.dAs[1], &P.dGamT[0],
+                       &P.dGamT[1], &P.dUp[0], &P.dUp[1], &P.dT1p[0], &P.dT1p[1], &P.dLmixT[0], &P.dLmixT[1],
+                       &P.dMst[0], &P.dMst[1], &P.dMts[0], &P.dMts[1], &P.dTmix[0], &P.dTmix[1], &P.dZpT[0],
+                       &P.dZpT[1], &P.dTmT[0], &P.dTmT[1], &P.dOOT[0], &P.dOOT[1], &P.dOVc[0], &P.dOVc[1],
+                       &P.dOVVV[0][0], &P.dOVVV[0][1], &P.dOVVV[1][0], &P.dOVVV[1][1], &P.dOVOO[0][0],
+                       &P.dOVOO[0][1], &P.dOVOO[1][0], &P.dOVOO[1][1], &P.dOVOV[0], &P.dOVOV[1], &P.dOVOV[2]};
+    for (const Buf* b : zb)
+      if (b->bytes) HIPCHK(lt::launch_zero32((char*)ws + b->off, (int64_t)(b->bytes / 4), st));
+  }
+  {
+    const int r = prep<T>(d, P, ws, st);
+    if (r) return r;
+  }
+  tm.setup_end = tm.mark();
+
+  // descriptor lists (host), uploaded once
+  RevBuilder<T> rb;
+  std::vector<std::pair<size_t, size_t>> bl;
+  build_rev<T>(P, L, (char*)ws, rb, bl);
+  RevBuilder<double> df;
+  build_df_rev(P, (char*)ws, gr, df);
+  auto* d_blk = at_small<lt::RBlk<T>>(ws, P, P.rblk);
+  auto* d_seg = at_small<lt::RSeg<T>>(ws, P, P.rseg);
+  auto* d_dfblk = at_small<lt::RBlk<double>>(ws, P, P.dfblk);
+  auto* d_dfseg = at_small<lt::RSeg<double>>(ws, P, P.dfseg);
+  if (rb.blks.size() * sizeof(rb.blks[0]) > P.rblk.bytes || rb.segs.size() * sizeof(rb.segs[0]) > P.rseg.bytes ||
+      df.blks.size() * sizeof(df.blks[0]) > P.dfblk.bytes || df.segs.size() * sizeof(df.segs[0]) > P.dfseg.bytes)
+    return fail(LT_EWORKSPACE, "descriptor lists exceed their plan");
+  if (!rb.blks.empty()) {
+    HIPCHK(hipMemcpyAsync(d_blk, rb.blks.data(), rb.blks.size() * sizeof(rb.blks[0]), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_seg, rb.segs.data(), rb.segs.size() * sizeof(rb.segs[0]), hipMemcpyHostToDevice, st));
+  }
+  if (!df.blks.empty()) {
+    HIPCHK(hipMemcpyAsync(d_dfblk, df.blks.data(), df.blks.size() * sizeof(df.blks[0]), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_dfseg, df.segs.data(), df.segs.size() * sizeof(df.segs[0]), hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));   // host descriptor vectors go out of scope below
+  double rf = 0;
+  for (auto& l : rb.launches) rf += l.flops;
+  *rev_flops = rf;
+
+  int32_t* d_trip = at_small<int32_t>(ws, P, P.trip);
+  int32_t fc[4];
+  for (int b = 0, n = 0; b < 4; ++b) { fc[b] = n; n += (int32_t)L.dst[b].size(); }
+  const int64_t mstr[2][4] = {{ob * va * vb, va * vb, vb, 1}, {va * vb, ob * va * vb, 1, vb}};
+  size_t bi = 0;
+  for (int b = 0; b < 4; ++b) {
+    const int64_t nblk = P.n_blk[b];
+    if (nblk == 0) continue;
+    const int s = blk_sigma(b), t = 1 - s;
+    const bool mixed = blk_mixed(b);
+    const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
+    lt::ItemOps<T> ops{};
+    ops.o_s = (int32_t)os; ops.v_s = (int32_t)vs; ops.o_t = (int32_t)ot; ops.v_t = (int32_t)vt;
+    ops.ld_vs = P.ldv[s]; ops.ld_vt = P.ldv[t]; ops.ld_np = P.ldnp[s]; ops.ld_cb = P.ldcb[s];
+    ops.T2T = at<T>(ws, P.T2T[s]); ops.Tp = at<T>(ws, P.Tp[s]); ops.As = at<T>(ws, P.As[s]);
+    ops.GamT = at<T>(ws, P.GamT[s]);
+    if (mixed) {
+      ops.LmixT = at<T>(ws, P.LmixT[s]); ops.Mst = at<T>(ws, P.Mst[s]); ops.Mts = at<T>(ws, P.Mts[s]);
+      ops.Tmix = at<T>(ws, P.Tmix[s]); ops.ZpT = at<T>(ws, P.ZpT[s]); ops.TmT = at<T>(ws, P.TmT[s]);
+      ops.OOT = at<T>(ws, P.OOT[s]);
+    }
+    const int64_t nb = P.nb[b];
+    const size_t o1 = P.o1[b], o2 = P.o2[b];
+    const int64_t nt = P.ntile[b];
+    for (int64_t first = 0; first < nblk; first += nb, ++bi) {
+      const int64_t n = std::min<int64_t>(nb, nblk - first);
+      const int32_t* items = d_trip + 3 * (fc[b] + first);
+      ops.items = items;
+      lt::GemmArgs<T> g{};
+      g.nbatch = (int32_t)n; g.mode = 1; g.s_nr = 1;
+      hipEvent_t a0 = tm.mark();
+      if (!mixed) {
+        T* S = (T*)scr;
+        ops.kind = 0;
+        g.M = (int32_t)vs; g.N = (int32_t)npair(vs); g.out = S; g.obs = (int64_t)(o1 / P.ts); g.s_mr = P.ldnp[s];
+        g.ops = ops;
+        HIPCHK(lt::launch_gemm<T>(g, st));
+        tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(3 * vs + 3 * os) * (double)n;
+        hipEvent_t a1 = tm.mark();
+        tm.gemm.push_back({a0, a1});
+        lt::BwdSame<T> e{};
+        e.e.o = (int32_t)os; e.e.v = (int32_t)vs; e.e.ld_np = P.ldnp[s];
+        e.e.S = S; e.e.s_item = (int64_t)(o1 / P.ts); e.e.items = items;
+        e.e.nt = (int32_t)cdiv(vs, lt::ET); e.e.ntri = (int32_t)nt;
+        e.e.eo = EO[s]; e.e.ev = EV[s]; e.e.t1 = T1[s]; e.e.f = Fov[s]; e.e.t2 = T2ss[s];
+        e.e.U = at<double>(ws, P.U[s]); e.e.ld_v = P.ldv[s];
+        e.gbar = gbar;
+        e.dS = (T*)(scr + (size_t)nb * o1);
+        e.dSV = (T*)(scr + 2 * (size_t)nb * o1);
+        HIPCHK(lt::launch_bwd_same<T>(e, (int32_t)n, st));
+        tm.epi.push_back({a1, tm.mark()});
+      } else {
+        T* G = (T*)scr;
+        T* Y = (T*)(scr + (size_t)nb * o1);
+        ops.kind = 1;
+        g.M = (int32_t)vs; g.N = (int32_t)(vt * vs); g.out = G; g.obs = (int64_t)(o1 / P.ts); g.s_mr = P.ldcb[s];
+        g.ops = ops;
+        HIPCHK(lt::launch_gemm<T>(g, st));
+        tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(2 * vt + vs + os + 2 * ot) * (double)n;
+        ops.kind = 2;
+        g.M = (int32_t)vt; g.N = (int32_t)npair(vs); g.out = Y; g.obs = (int64_t)(o2 / P.ts); g.s_mr = P.ldnp[s];
+        g.ops = ops;
+        HIPCHK(lt::launch_gemm<T>(g, st));
+        tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(2 * vs + 2 * os) * (double)n;
+        hipEvent_t a1 = tm.mark();
+        tm.gemm.push_back({a0, a1});
+        lt::BwdMixed<T> e{};
+        lt::EpiMixed<T>& x = e.e;
+        x.o_s = (int32_t)os; x.v_s = (int32_t)vs; x.o_t = (int32_t)ot; x.v_t = (int32_t)vt;
+        x.ld_np = P.ldnp[s]; x.ld_cb = P.ldcb[s];
+        x.G = G; x.g_item = (int64_t)(o1 / P.ts); x.Y = Y; x.y_item = (int64_t)(o2 / P.ts);
+        x.items = items;
+        x.nts = (int32_t)cdiv(vs, lt::ET); x.ntt = (int32_t)cdiv(vt, lt::ET); x.ntiles = (int32_t)nt;
+        x.eo_s = EO[s]; x.ev_s = EV[s]; x.eo_t = EO[t]; x.ev_t = EV[t];
+        x.t1_s = T1[s]; x.t1_t = T1[t]; x.f_s = Fov[s]; x.f_t = Fov[t]; x.t2ss = T2ss[s];
+        x.U = at<double>(ws, P.U[s]); x.ld_vs = P.ldv[s];
+        const int64_t so[4] = {va * ob * vb, ob * vb, vb, 1};
+        x.ov = at<double>(ws, P.OVab);
+        if (s == 0) { x.ov_o = so[0]; x.ov_v = so[1]; x.ov_O = so[2]; x.ov_V = so[3]; }
+        else { x.ov_o = so[2]; x.ov_v = so[3]; x.ov_O = so[0]; x.ov_V = so[1]; }
+        x.tm = d->t2ab; x.tm_o = mstr[s][0]; x.tm_v = mstr[s][2]; x.tm_O = mstr[s][1]; x.tm_V = mstr[s][3];
+        e.gbar = gbar;
+        const size_t q1 = (size_t)nb * (o1 + o2);
+        e.dG = (T*)(scr + q1);
+        e.dY = (T*)(scr + q1 + (size_t)nb * o1);
+        e.dGV = (T*)(scr + 2 * q1);
+        e.dYV = (T*)(scr + 2 * q1 + (size_t)nb * o1);
+        HIPCHK(lt::launch_bwd_mixed<T>(e, (int32_t)n, st));
+        tm.epi.push_back({a1, tm.mark()});
+      }
+      hipEvent_t r0 = tm.mark();
+      {
+        const int r = launch_rev_list<T>(rb, bl[bi].first, bl[bi].second, d_blk, d_seg, st);
+        if (r) return r;
+      }
+      tm.gemm.push_back({r0, tm.mark()});
+    }
+  }
+
+  // --- mirrors -> amplitude gradients and FP64 integral gradients ---------------------
+  auto Tb = [&](const Buf& b) { return at<T>(ws, b); };
+  auto Db = [&](const Buf& b) { return at<double>(ws, b); };
+  double* gT1[2] = {gr->t1a, gr->t1b};
+  double* gT2[2] = {gr->t2aa, gr->t2bb};
+  for (int s = 0; s < 2; ++s) {
+    const int t = 1 - s;
+    const int64_t o = D.o[s], v = D.v[s], lv = P.ldv[s], lp = P.ldnp[s];
+    if (P.dT1p[s].bytes && gT1[s]) {
+      const int64_t dd[4] = {1, 1, o, v}, os_[4] = {0, 0, v, 1}, is_[4] = {0, 0, lv, 1};
+      HIPCHK(lt::launch_perm_acc<T>(gT1[s], dd, os_, Tb(P.dT1p[s]), is_, 1.0, st));
+    }
+    if (P.need_as[s]) {
+      if (gT2[s]) {
+        // T2T[i][j][e][a] = t2[i][j][a][e]
+        const int64_t dd[4] = {o, o, v, v}, os_[4] = {o * v * v, v * v, 1, v}, is_[4] = {o * v * lv, v * lv, lv, 1};
+        HIPCHK(lt::launch_perm_acc<T>(gT2[s], dd, os_, Tb(P.dT2T[s]), is_, 1.0, st));
+        // Tp[i][m][p(a<b)] = t2[i][m][a][b]
+        HIPCHK(lt::launch_unpack_acc<T>(gT2[s], o, o, (int32_t)v, o * v * v, v * v, v, 1, Tb(P.dTp[s]), o * lp, lp,
+                                        1.0, 0.0, st));
+      }
+      const int64_t lvv = P.ldvv[s], loo = P.ldoo[s], lov = P.ldov[s];
+      // As[i][e][p(b<c)] = (ic|eb) - (ib|ec)  ->  d(ix|ey) at [i][x][e*v+y]
+      HIPCHK(lt::launch_unpack_acc<T>(Db(P.dOVVV[s][s]), o, v, (int32_t)v, v * lvv, v, lvv, 1, Tb(P.dAs[s]), v * lp,
+                                      lp, -1.0, 1.0, st));
+      // GamT[j][k][m][a] = (ak|mj) - (aj|mk)  ->  d(ka|mj) at [k][a][m*o+j]
+      {
+        const int64_t dd[4] = {o, o, o, v}, is_[4] = {o * o * lv, o * lv, lv, 1};
+        const int64_t o1_[4] = {1, v * loo, o, loo}, o2_[4] = {v * loo, 1, o, loo};
+        HIPCHK(lt::launch_perm_acc<T>(Db(P.dOVOO[s][s]), dd, o1_, Tb(P.dGamT[s]), is_, 1.0, st));
+        HIPCHK(lt::launch_perm_acc<T>(Db(P.dOVOO[s][s]), dd, o2_, Tb(P.dGamT[s]), is_, -1.0, st));
+      }
+      // Up[q][r][p(b<c)] = (qb|rc) - (qc|rb)  ->  d(qx|ry) at [q][x][r*v+y]
+      HIPCHK(lt::launch_unpack_acc<T>(Db(P.dOVOV[s]), o, o, (int32_t)v, v * lov, v, lov, 1, Tb(P.dUp[s]), o * lp, lp,
+                                      1.0, -1.0, st));
+    }
+    if (P.need_mix[s]) {
+      const int64_t os = o, vs = v, ot = D.o[t], vt = D.v[t], lvt = P.ldv[t], lc = P.ldcb[s];
+      const int64_t* m = mstr[s];
+      if (gr->t2ab) {
+        // LmixT[i][K][E][a] = t^{aE}_{iK}; Tmix[i][K][C*vs+b] = t^{bC}_{iK}; TmT[i][K][e][C] = t^{eC}_{iK}
+        const int64_t d1[4] = {os, ot, vt, vs}, i1[4] = {ot * vt * lv, vt * lv, lv, 1}, q1[4] = {m[0], m[1], m[3], m[2]};
+        HIPCHK(lt::launch_perm_acc<T>(gr->t2ab, d1, q1, Tb(P.dLmixT[s]), i1, 1.0, st));
+        const int64_t d2[4] = {os, ot, vt, vs}, i2[4] = {ot * lc, lc, vs, 1}, q2[4] = {m[0], m[1], m[3], m[2]};
+        HIPCHK(lt::launch_perm_acc<T>(gr->t2ab, d2, q2, Tb(P.dTmix[s]), i2, 1.0, st));
+        const int64_t d3[4] = {os, ot, vs, vt}, i3[4] = {ot * vs * lvt, vs * lvt, lvt, 1}, q3[4] = {m[0], m[1], m[2], m[3]};
+        HIPCHK(lt::launch_perm_acc<T>(gr->t2ab, d3, q3, Tb(P.dTmT[s]), i3, 1.0, st));
+      }
+      // Mst[j][E][C*vs+b] = (jb|EC) -> [j][b][E*vt+C] of (ov|vv)_{st}
+      {
+        const int64_t l = P.ldvv[t];
+        const int64_t dd[4] = {os, vt, vt, vs}, is_[4] = {vt * lc, lc, vs, 1}, oo_[4] = {vs * l, vt, 1, l};
+        HIPCHK(lt::launch_perm_acc<T>(Db(P.dOVVV[s][t]), dd, oo_, Tb(P.dMst[s]), is_, 1.0, st));
+      }
+      // Mts[K][e][C*vs+b] = (KC|be) -> [K][C][b*vs+e] of (ov|vv)_{ts}
+      {
+        const int64_t l = P.ldvv[s];
+        const int64_t dd[4] = {ot, vs, vt, vs}, is_[4] = {vs * lc, lc, vs, 1}, oo_[4] = {vt * l, 1, l, vs};
+        HIPCHK(lt::launch_perm_acc<T>(Db(P.dOVVV[t][s]), dd, oo_, Tb(P.dMts[s]), is_, 1.0, st));
+      }
+      // ZpT[j][K][M][a] = (ja|MK) -> [j][a][M*ot+K] of (ov|oo)_{st}
+      {
+        const int64_t l = P.ldoo[t];
+        const int64_t dd[4] = {os, ot, ot, vs}, is_[4] = {ot * ot * lv, ot * lv, lv, 1}, oo_[4] = {vs * l, 1, ot, l};
+        HIPCHK(lt::launch_perm_acc<T>(Db(P.dOVOO[s][t]), dd, oo_, Tb(P.dZpT[s]), is_, 1.0, st));
+      }
+      // OOT[K][j][m][C] = (KC|jm) -> [K][C][j*os+m] of (ov|oo)_{ts}
+      {
+        const int64_t l = P.ldoo[s];
+        const int64_t dd[4] = {ot, os, os, vt}, is_[4] = {os * os * lvt, os * lvt, lvt, 1}, oo_[4] = {vt * l, os, 1, l};
+        HIPCHK(lt::launch_perm_acc<T>(Db(P.dOVOO[t][s]), dd, oo_, Tb(P.dOOT[s]), is_, 1.0, st));
+      }
+      // OVc[j][K][C*vs+b] = (jb|KC) -> (ov|ov)_{ab}
+      {
+        const int64_t l = P.ldov[1];
+        const int64_t dd[4] = {os, ot, vt, vs}, is_[4] = {ot * lc, lc, vs, 1};
+        const int64_t oa_[4] = {va * l, vb, 1, l};    // s = alpha: [j][b][K*vb+C]
+        const int64_t ob_[4] = {vb, va * l, l, 1};    // s = beta:  [K][C][j*vb+b]
+        HIPCHK(lt::launch_perm_acc<T>(Db(P.dOVOV[2]), dd, s == 0 ? oa_ : ob_, Tb(P.dOVc[s]), is_, 1.0, st));
+      }
+    }
+  }
+  // --- DF back-contraction -------------------------------------------------------------
+  {
+    const int r = launch_rev_list<double>(df, 0, df.launches.size(), d_dfblk, d_dfseg, st);
+    if (r) return r;
+  }
+  // --- projections of the constrained inputs -------------------------------------------
+  if (gr->t2aa) HIPCHK(lt::launch_antisym4(gr->t2aa, oa, va, st));
+  if (gr->t2bb) HIPCHK(lt::launch_antisym4(gr->t2bb, ob, vb, st));
+  if (gr->Boo_a) HIPCHK(lt::launch_sym3(gr->Boo_a, Q, oa, st));
+  if (gr->Bvv_a) HIPCHK(lt::launch_sym3(gr->Bvv_a, Q, va, st));
+  if (gr->Boo_b) HIPCHK(lt::launch_sym3(gr->Boo_b, Q, ob, st));
+  if (gr->Bvv_b) HIPCHK(lt::launch_sym3(gr->Bvv_b, Q, vb, st));
+  tm.end = tm.mark();
+  (void)o;
   return LT_OK;
 }
 
@@ -868,6 +1504,210 @@ int ltriples_energy(const ltriples_domain* d, int32_t precision, const ltriples_
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint entry points
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+static int validate_bwd(const ltriples_domain* d, int32_t precision, const ltriples_options* o) {
+  int r = validate(d, precision, o);
+  if (r) return r;
+  if (precision != LT_FP64 && precision != LT_FP32)
+    return fail(LT_EPREC, "the adjoint pass supports FP64 and FP32 only");
+  if (o && o->e_items) return fail(LT_EINVAL, "per-item outputs are a forward option");
+  return LT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Host-only plan self-check of the adjoint descriptors
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Range { uintptr_t lo, hi; const char* name; };
+
+template <typename T>
+int check_rev(const RevBuilder<T>& rb, const std::vector<Range>& bufs, uintptr_t grad_lo, uintptr_t grad_hi,
+              bool element_check) {
+  const size_t ts = sizeof(T);
+  auto inside = [&](uintptr_t a, uintptr_t b) -> const Range* {
+    for (const Range& r : bufs)
+      if (a >= r.lo && b <= r.hi) return &r;
+    if (a >= grad_lo && b <= grad_hi) return &bufs[0];   // caller outputs (checked per field below)
+    return nullptr;
+  };
+  auto r4 = [](int64_t k) { return (k + 3) & ~int64_t(3); };
+  for (size_t li = 0; li < rb.launches.size(); ++li) {
+    const auto& L = rb.launches[li];
+    std::vector<uintptr_t> elems;
+    for (int64_t bi = L.blk0; bi < L.blk0 + L.nblk; ++bi) {
+      const lt::RBlk<T>& b = rb.blks[bi];
+      const uintptr_t o = (uintptr_t)b.out;
+      if (b.rows <= 0 || b.cols <= 0 || b.ldo < b.cols) return fail(LT_ESHAPE, "launch %zu block %lld: bad shape", li, (long long)bi);
+      if (!inside(o, o + ((b.rows - 1) * b.ldo + b.cols) * ts))
+        return fail(LT_EWORKSPACE, "launch %zu block %lld: output outside its buffer", li, (long long)bi);
+      if (element_check)
+        for (int r = 0; r < b.rows; ++r)
+          for (int c = 0; c < b.cols; ++c) elems.push_back(o + (r * b.ldo + c) * ts);
+      for (int32_t si = b.beg; si < b.end; ++si) {
+        const lt::RSeg<T>& sg = rb.segs[si];
+        const uintptr_t a = (uintptr_t)sg.A, bb = (uintptr_t)sg.B;
+        if (sg.K <= 0) continue;
+        if ((a % 16) || (bb % 16) || (sg.lda % 4) || (sg.ldb % 4))
+          return fail(LT_ESHAPE, "launch %zu segment %d: misaligned operand", li, si);
+        if (sg.lda < sg.K && b.rows > 1) return fail(LT_ESHAPE, "launch %zu segment %d: lda < K", li, si);
+        if (!inside(a, a + ((b.rows - 1) * sg.lda + r4(sg.K)) * ts))
+          return fail(LT_EWORKSPACE, "launch %zu segment %d: A outside its buffer", li, si);
+        const uintptr_t bend = L.tb ? bb + ((b.cols - 1) * sg.ldb + r4(sg.K)) * ts
+                                    : bb + ((sg.K - 1) * sg.ldb + r4(b.cols)) * ts;
+        if (!L.tb && sg.ldb < r4(b.cols)) return fail(LT_ESHAPE, "launch %zu segment %d: ldb < cols", li, si);
+        if (!inside(bb, bend)) return fail(LT_EWORKSPACE, "launch %zu segment %d: B outside its buffer", li, si);
+      }
+    }
+    if (element_check) {
+      std::sort(elems.begin(), elems.end());
+      if (std::adjacent_find(elems.begin(), elems.end()) != elems.end())
+        return fail(LT_ESHAPE, "launch %zu: output blocks overlap", li);
+    }
+  }
+  return LT_OK;
+}
+
+template <typename T>
+int plan_check_bwd(const Plan& P, const ItemLists& L, bool element_check) {
+  char* base = kFakeBase;
+  std::vector<Range> bufs;
+  // every planned buffer of the big and small regions
+  const Buf* all[] = {&P.BvvP[0], &P.BvvP[1], &P.BovR[0], &P.BovR[1], &P.BovP64[0], &P.BovP64[1], &P.BooP64[0],
+                      &P.BooP64[1], &P.As[0], &P.As[1], &P.Tp[0], &P.Tp[1], &P.T2T[0], &P.T2T[1], &P.GamT[0],
+                      &P.GamT[1], &P.U[0], &P.U[1], &P.LmixT[0], &P.LmixT[1], &P.Mst[0], &P.Mst[1], &P.Mts[0],
+                      &P.Mts[1], &P.Tmix[0], &P.Tmix[1], &P.ZpT[0], &P.ZpT[1], &P.TmT[0], &P.TmT[1], &P.OOT[0],
+                      &P.OOT[1], &P.OVab, &P.T1p[0], &P.T1p[1], &P.Fp[0], &P.Fp[1], &P.Up[0], &P.Up[1],
+                      &P.OVc[0], &P.OVc[1], &P.BvvP64[0], &P.BvvP64[1], &P.dT2T[0], &P.dT2T[1], &P.dTp[0],
+                      &P.dTp[1], &P.dAs[0], &P.dAs[1], &P.dGamT[0], &P.dGamT[1], &P.dUp[0], &P.dUp[1],
+                      &P.dT1p[0], &P.dT1p[1], &P.dLmixT[0], &P.dLmixT[1], &P.dMst[0], &P.dMst[1], &P.dMts[0],
+                      &P.dMts[1], &P.dTmix[0], &P.dTmix[1], &P.dZpT[0], &P.dZpT[1], &P.dTmT[0], &P.dTmT[1],
+                      &P.dOOT[0], &P.dOOT[1], &P.dOVc[0], &P.dOVc[1], &P.dOVVV[0][0], &P.dOVVV[0][1],
+                      &P.dOVVV[1][0], &P.dOVVV[1][1], &P.dOVOO[0][0], &P.dOVOO[0][1], &P.dOVOO[1][0],
+                      &P.dOVOO[1][1], &P.dOVOV[0], &P.dOVOV[1], &P.dOVOV[2], &P.scratch};
+  for (const Buf* b : all)
+    if (b->bytes) bufs.push_back({(uintptr_t)(base + b->off), (uintptr_t)(base + b->off + b->bytes), ""});
+  if (bufs.empty()) return LT_OK;
+  for (size_t i = 0; i < bufs.size(); ++i)
+    if (bufs[i].hi > (uintptr_t)(base + P.big)) return fail(LT_EWORKSPACE, "buffer beyond the planned region");
+  RevBuilder<T> rb;
+  std::vector<std::pair<size_t, size_t>> bl;
+  build_rev<T>(P, L, base, rb, bl);
+  int r = check_rev<T>(rb, bufs, 0, 0, element_check);
+  if (r) return r;
+  // DF back-contraction: caller outputs as disjoint fake regions
+  const Dims& D = P.D;
+  const int64_t Q = D.Q;
+  ltriples_domain_grad g{};
+  uintptr_t gb = (uintptr_t)(base + P.total + 4096);
+  const int64_t sizes[6] = {Q * D.o[0] * D.o[0], Q * D.o[0] * D.v[0], Q * D.v[0] * D.v[0],
+                            Q * D.o[1] * D.o[1], Q * D.o[1] * D.v[1], Q * D.v[1] * D.v[1]};
+  double** f[6] = {&g.Boo_a, &g.Bov_a, &g.Bvv_a, &g.Boo_b, &g.Bov_b, &g.Bvv_b};
+  std::vector<Range> gr = bufs;
+  for (int k = 0; k < 6; ++k) {
+    *f[k] = (double*)gb;
+    gr.push_back({gb, gb + 8 * (uintptr_t)sizes[k], ""});
+    gb = align256(gb + 8 * (uintptr_t)sizes[k] + 4096);
+  }
+  RevBuilder<double> df;
+  build_df_rev(P, base, &g, df);
+  return check_rev<double>(df, gr, 0, 0, element_check);
+}
+
+}  // namespace
+
+extern "C" int ltriples_plan_check(const ltriples_domain* d, int32_t precision, const ltriples_options* o,
+                                   int32_t backward) {
+  g_err.clear();
+  int r = backward ? validate_bwd(d, precision, o) : validate(d, precision, o);
+  if (r) return r;
+  if (!backward) return LT_OK;
+  ItemLists L;
+  build_items(dims_of(d), o, L);
+  Plan P;
+  plan_backward(d, precision, o, L, P);
+  const bool el = P.total < (size_t(1) << 28);
+  return precision == LT_FP64 ? plan_check_bwd<double>(P, L, el) : plan_check_bwd<float>(P, L, el);
+}
+
+
+extern "C" {
+
+int ltriples_backward_workspace_size(const ltriples_domain* d, int32_t precision, const ltriples_options* o,
+                                     size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(LT_EINVAL, "bytes is NULL");
+  const int r = validate_bwd(d, precision, o);
+  if (r) return r;
+  ItemLists L;
+  build_items(dims_of(d), o, L);
+  Plan P;
+  plan_backward(d, precision, o, L, P);
+  *bytes = P.total;
+  return LT_OK;
+}
+
+int ltriples_backward(const ltriples_domain* d, int32_t precision, const ltriples_options* o, const double* gbar,
+                      const ltriples_domain_grad* grad, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int r = validate_bwd(d, precision, o);
+  if (r) return r;
+  if (!gbar) return fail(LT_EINVAL, "gbar is NULL");
+  if (!grad) return fail(LT_EINVAL, "grad is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  const Dims D = dims_of(d);
+  r = check_denominators(d);
+  if (r) return r;
+  ItemLists L;
+  build_items(D, o, L);
+  Plan P;
+  plan_backward(d, precision, o, L, P);
+  log_plan(P);
+  bool own = false;
+  if (ws == nullptr) {
+    HIPCHK(hipMalloc(&ws, P.total));
+    own = true;
+  } else if (ws_bytes < P.total) {
+    return fail(LT_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, P.total);
+  }
+  r = upload_items(P, L, ws, st);
+  if (r == LT_OK) {
+    Timing tm;
+    tm.on = o && o->stats;
+    tm.st = st;
+    double rev_flops = 0;
+    if (precision == LT_FP64) r = run_bwd<double>(d, P, L, o, gbar, grad, ws, st, tm, &rev_flops);
+    else r = run_bwd<float>(d, P, L, o, gbar, grad, ws, st, tm, &rev_flops);
+    if (r == LT_OK && tm.on) {
+      HIPCHK(hipStreamSynchronize(st));
+      ltriples_stats* S = o->stats;
+      *S = ltriples_stats{};
+      S->total_ms = Timing::ms(tm.start, tm.end);
+      S->setup_ms = Timing::ms(tm.start, tm.setup_end);
+      for (auto& x : tm.gemm) S->triples_gemm_ms += Timing::ms(x.first, x.second);
+      for (auto& x : tm.epi) S->epilogue_ms += Timing::ms(x.first, x.second);
+      S->triples_gemm_launches = (int64_t)tm.gemm.size();
+      S->triples_gemm_flops = tm.gemm_flops + rev_flops;
+      double f = 0;
+      for (int b = 0; b < 4; ++b) f += (double)P.n_blk[b] * item_flops(D, b);
+      S->algorithmic_flops = 3.0 * f;
+      S->n_items = L.total;
+    }
+  }
+  if (own) {
+    hipError_t e1 = hipStreamSynchronize(st);
+    hipError_t e2 = hipFree(ws);
+    if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) return fail(LT_EHIP, "HIP error at workspace release");
+  }
+  return r;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
 // Batched domains.  The domains run one after another on the stream and share
 // the big part of the workspace (operands, slabs, scratch); each keeps its own
 // small buffers.  With options.graph = 1 the whole launch sequence is captured
@@ -949,6 +1789,8 @@ int enqueue_batch(const ltriples_domain* ds, int32_t ndom, int32_t precision, co
 }
 
 }  // namespace
+
+extern "C" {
 
 int ltriples_workspace_size_batched(const ltriples_domain* ds, int32_t ndom, int32_t precision,
                                     const ltriples_options* o, size_t* bytes) {

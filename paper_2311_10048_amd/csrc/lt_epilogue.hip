@@ -227,6 +227,237 @@ __global__ __launch_bounds__(256) void k_epi_mixed(EpiMixed<T> a) {
   block_write3(e4, est, edt, a.part + ((int64_t)item * a.ntiles + tile) * 3);
 }
 
+// ---------------------------------------------------------------------------
+// Backward epilogues.  Same tiles and LDS staging as the forward ones; per
+// unique virtual triple W, V, D are recomputed and the adjoints
+// gbar (2W + V)/D and gbar W/D are scattered to the three (same spin) resp.
+// three (mixed) output positions that W and V read, with the signs of the
+// permutation operator.  Output positions that W never reads (an index
+// repeated) are written with zeros by the tile that owns them, so every
+// element of an item's output layout is written exactly once.
+// ---------------------------------------------------------------------------
+__device__ inline int64_t pidx(int x, int y) { return (int64_t)y * (y - 1) / 2 + x; }   // x < y
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_same(BwdSame<T> A) {
+  const EpiSame<T>& a = A.e;
+  __shared__ T Sb[ET][SROW];
+  __shared__ T Sc[ET][SROW];
+  __shared__ double Uac[3][ET][ET + 1], Uba[3][ET][ET + 1], Tac[3][ET][ET + 1], Tba[3][ET][ET + 1];
+  __shared__ double t1a[3][ET], fa[3][ET], eva[ET];
+
+  const int tid = threadIdx.x;
+  int TA, TB, TC;
+  tri_decode(blockIdx.x, TA, TB, TC);
+  const int item = blockIdx.y;
+  const int32_t* it = a.items + 3 * item;
+  const int occ[3] = {it[0], it[1], it[2]};
+  const int v = a.v;
+  const int a0 = TA * ET, b0 = TB * ET, c0 = TC * ET;
+  const T* S = a.S + (int64_t)item * a.s_item;
+  T* dS = A.dS + (int64_t)item * a.s_item;
+  T* dSV = A.dSV + (int64_t)item * a.s_item;
+  const int64_t ldp = a.ld_np;
+  const int pq[3] = {occ[1], occ[0], occ[1]};
+  const int pr[3] = {occ[2], occ[2], occ[0]};
+  const double sg[3] = {1.0, -1.0, -1.0};
+  const int64_t vv = (int64_t)v * v;
+
+  for (int e = tid; e < ET * ET * ET; e += 256) {
+    const int ta = e & 15, tb = (e >> 4) & 15, tc = e >> 8;
+    const int aa = a0 + ta, bb = b0 + tb, cc = c0 + tc;
+    T x = 0, y = 0;
+    if (cc < v && bb < v) {
+      if (aa < cc) x = S[bb * ldp + pidx(aa, cc)];
+      if (aa < bb) y = S[cc * ldp + pidx(aa, bb)];
+    }
+    Sb[ta][tc * ET + tb] = x;
+    Sc[ta][tc * ET + tb] = y;
+  }
+  for (int e = tid; e < 3 * ET * ET; e += 256) {
+    const int pp = e / (ET * ET), r = e % (ET * ET), ta = r & 15, tx = r >> 4;
+    const int aa = a0 + ta, cc = c0 + tx, bb = b0 + tx;
+    const int64_t ub = ((int64_t)pq[pp] * a.o + pr[pp]) * v * a.ld_v;
+    const int64_t tb_ = ((int64_t)pq[pp] * a.o + pr[pp]) * vv;
+    const bool ac = aa < v && cc < v, ba = aa < v && bb < v;
+    Uac[pp][ta][tx] = ac ? a.U[ub + aa * a.ld_v + cc] : 0.0;
+    Tac[pp][ta][tx] = ac ? a.t2[tb_ + aa * v + cc] : 0.0;
+    Uba[pp][tx][ta] = ba ? a.U[ub + bb * a.ld_v + aa] : 0.0;
+    Tba[pp][tx][ta] = ba ? a.t2[tb_ + bb * v + aa] : 0.0;
+  }
+  if (tid < 3 * ET) {
+    const int pp = tid / ET, ta = tid % ET, aa = a0 + ta;
+    t1a[pp][ta] = aa < v ? a.t1[(int64_t)occ[pp] * v + aa] : 0.0;
+    fa[pp][ta] = aa < v ? a.f[(int64_t)occ[pp] * v + aa] : 0.0;
+  } else if (tid < 4 * ET) {
+    const int ta = tid - 3 * ET, aa = a0 + ta;
+    eva[ta] = aa < v ? a.ev[aa] : 0.0;
+  }
+  __syncthreads();
+
+  const int tb = tid & 15, tc = tid >> 4;
+  const int b = b0 + tb, c = c0 + tc;
+  if (b < c && c < v) {
+    const double g = A.gbar[0];
+    double Ubc[3], Tbc[3], t1b[3], fb[3], t1c[3], fc[3];
+#pragma unroll
+    for (int pp = 0; pp < 3; ++pp) {
+      const int64_t blk = (int64_t)pq[pp] * a.o + pr[pp];
+      Ubc[pp] = sg[pp] * a.U[blk * v * a.ld_v + b * a.ld_v + c];
+      Tbc[pp] = sg[pp] * a.t2[blk * vv + (int64_t)b * v + c];
+      t1b[pp] = sg[pp] * a.t1[(int64_t)occ[pp] * v + b];
+      fb[pp] = sg[pp] * a.f[(int64_t)occ[pp] * v + b];
+      t1c[pp] = sg[pp] * a.t1[(int64_t)occ[pp] * v + c];
+      fc[pp] = sg[pp] * a.f[(int64_t)occ[pp] * v + c];
+    }
+    const double dbc = (a.eo[occ[0]] + a.eo[occ[1]] + a.eo[occ[2]]) - a.ev[b] - a.ev[c];
+    const int64_t pbc = pidx(b, c);
+    const T* Srow = S + pbc;
+    const int na = min(ET, b - a0);
+    for (int ta = 0; ta < na; ++ta) {
+      const int aa = a0 + ta;
+      const double w = (double)Srow[aa * ldp] - (double)Sb[ta][tc * ET + tb] + (double)Sc[ta][tc * ET + tb];
+      double vt = 0.0, vf = 0.0;
+#pragma unroll
+      for (int pp = 0; pp < 3; ++pp) {
+        vt += t1a[pp][ta] * Ubc[pp] - t1b[pp] * Uac[pp][ta][tc] - t1c[pp] * Uba[pp][tb][ta];
+        vf += fa[pp][ta] * Tbc[pp] - fb[pp] * Tac[pp][ta][tc] - fc[pp] * Tba[pp][tb][ta];
+      }
+      const double d = dbc - eva[ta];
+      const double wh = g * (2.0 * w + vt + vf) / d, vh = g * w / d;
+      // W = S[a][bc] - S[b][ac] + S[c][ab]; V likewise from the singles/f_ov intermediate
+      dS[aa * ldp + pbc] = (T)wh;
+      dS[b * ldp + pidx(aa, c)] = (T)(-wh);
+      dS[c * ldp + pidx(aa, b)] = (T)wh;
+      dSV[aa * ldp + pbc] = (T)vh;
+      dSV[b * ldp + pidx(aa, c)] = (T)(-vh);
+      dSV[c * ldp + pidx(aa, b)] = (T)vh;
+    }
+    if (TA == TB) {
+      dS[b * ldp + pbc] = (T)0; dS[c * ldp + pbc] = (T)0;
+      dSV[b * ldp + pbc] = (T)0; dSV[c * ldp + pbc] = (T)0;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_mixed(BwdMixed<T> A) {
+  const EpiMixed<T>& a = A.e;
+  __shared__ T Gb[ET][SROW];
+  __shared__ T Yl[ET][SROW];
+  __shared__ double OVj[ET][ET + 1], OVi[ET][ET + 1], Tmj[ET][ET + 1], Tmi[ET][ET + 1];
+  __shared__ double Uab[ET][ET + 1], T2ab[ET][ET + 1];
+  __shared__ double t1ai[ET], t1aj[ET], fai[ET], faj[ET], eva[ET];
+
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x;
+  const int TC = tile % a.ntt, pi = tile / a.ntt;
+  int TB = 0;
+  while ((TB + 1) * (TB + 2) / 2 <= pi) ++TB;
+  const int TA = pi - TB * (TB + 1) / 2;
+  const int item = blockIdx.y;
+  const int32_t* it = a.items + 3 * item;
+  const int i = it[0], j = it[1], K = it[2];
+  const int vs = a.v_s, vt = a.v_t;
+  const int a0 = TA * ET, b0 = TB * ET, c0 = TC * ET;
+  const T* G = a.G + (int64_t)item * a.g_item;
+  const T* Y = a.Y + (int64_t)item * a.y_item;
+  T* dG = A.dG + (int64_t)item * a.g_item;
+  T* dGV = A.dGV + (int64_t)item * a.g_item;
+  T* dY = A.dY + (int64_t)item * a.y_item;
+  T* dYV = A.dYV + (int64_t)item * a.y_item;
+  const int64_t lc = a.ld_cb, lp = a.ld_np;
+
+  for (int e = tid; e < ET * ET * ET; e += 256) {
+    const int ta = e & 15, tb = (e >> 4) & 15, tc = e >> 8;
+    const int aa = a0 + ta, bb = b0 + tb, cc = c0 + tc;
+    T x = 0, y = 0;
+    if (aa < vs && bb < vs && cc < vt) {
+      x = G[bb * lc + (int64_t)cc * vs + aa];
+      if (aa < bb) y = Y[cc * lp + pidx(aa, bb)];
+    }
+    Gb[ta][tc * ET + tb] = x;
+    Yl[ta][tc * ET + tb] = y;
+  }
+  for (int e = tid; e < ET * ET; e += 256) {
+    const int ta = e & 15, tx = e >> 4;
+    const int aa = a0 + ta, cc = c0 + tx, bb = b0 + tx;
+    const bool ac = aa < vs && cc < vt, ab = aa < vs && bb < vs;
+    OVj[ta][tx] = ac ? a.ov[j * a.ov_o + aa * a.ov_v + K * a.ov_O + cc * a.ov_V] : 0.0;
+    OVi[ta][tx] = ac ? a.ov[i * a.ov_o + aa * a.ov_v + K * a.ov_O + cc * a.ov_V] : 0.0;
+    Tmj[ta][tx] = ac ? a.tm[j * a.tm_o + aa * a.tm_v + K * a.tm_O + cc * a.tm_V] : 0.0;
+    Tmi[ta][tx] = ac ? a.tm[i * a.tm_o + aa * a.tm_v + K * a.tm_O + cc * a.tm_V] : 0.0;
+    const int64_t ij = (int64_t)i * a.o_s + j;
+    Uab[tx][ta] = ab ? a.U[(ij * vs + aa) * a.ld_vs + bb] : 0.0;
+    T2ab[tx][ta] = ab ? a.t2ss[(ij * vs + aa) * vs + bb] : 0.0;
+  }
+  if (tid < ET) {
+    const int aa = a0 + tid;
+    const bool ok = aa < vs;
+    t1ai[tid] = ok ? a.t1_s[(int64_t)i * vs + aa] : 0.0;
+    t1aj[tid] = ok ? a.t1_s[(int64_t)j * vs + aa] : 0.0;
+    fai[tid] = ok ? a.f_s[(int64_t)i * vs + aa] : 0.0;
+    faj[tid] = ok ? a.f_s[(int64_t)j * vs + aa] : 0.0;
+    eva[tid] = ok ? a.ev_s[aa] : 0.0;
+  }
+  __syncthreads();
+
+  const int tb = tid & 15, tc = tid >> 4;
+  const int b = b0 + tb, C = c0 + tc;
+  if (b < vs && C < vt) {
+    const double g = A.gbar[0];
+    const double OVjb = a.ov[j * a.ov_o + b * a.ov_v + K * a.ov_O + C * a.ov_V];
+    const double OVib = a.ov[i * a.ov_o + b * a.ov_v + K * a.ov_O + C * a.ov_V];
+    const double Tmjb = a.tm[j * a.tm_o + b * a.tm_v + K * a.tm_O + C * a.tm_V];
+    const double Tmib = a.tm[i * a.tm_o + b * a.tm_v + K * a.tm_O + C * a.tm_V];
+    const double t1bi = a.t1_s[(int64_t)i * vs + b], t1bj = a.t1_s[(int64_t)j * vs + b];
+    const double fbi = a.f_s[(int64_t)i * vs + b], fbj = a.f_s[(int64_t)j * vs + b];
+    const double t1C = a.t1_t[(int64_t)K * vt + C], fC = a.f_t[(int64_t)K * vt + C];
+    const double dbc = (a.eo_s[i] + a.eo_s[j] + a.eo_t[K]) - a.ev_s[b] - a.ev_t[C];
+    const T* Grow = G + (int64_t)C * vs + b;
+    const int64_t cb = (int64_t)C * vs;
+    const int na = min(ET, b - a0);
+    for (int ta = 0; ta < na; ++ta) {
+      const int aa = a0 + ta;
+      const double w = (double)Grow[aa * lc] - (double)Gb[ta][tc * ET + tb] + (double)Yl[ta][tc * ET + tb];
+      const double vt1 = t1ai[ta] * OVjb - t1aj[ta] * OVib - t1bi * OVj[ta][tc] + t1bj * OVi[ta][tc]
+                         + t1C * Uab[tb][ta];
+      const double vfo = fai[ta] * Tmjb - faj[ta] * Tmib - fbi * Tmj[ta][tc] + fbj * Tmi[ta][tc]
+                         + fC * T2ab[tb][ta];
+      const double d = dbc - eva[ta];
+      const double wh = g * (2.0 * w + vt1 + vfo) / d, vh = g * w / d;
+      // W = G[a][Cb] - G[b][Ca] + Y[C][ab]
+      dG[aa * lc + cb + b] = (T)wh;
+      dG[b * lc + cb + aa] = (T)(-wh);
+      dY[C * lp + pidx(aa, b)] = (T)wh;
+      dGV[aa * lc + cb + b] = (T)vh;
+      dGV[b * lc + cb + aa] = (T)(-vh);
+      dYV[C * lp + pidx(aa, b)] = (T)vh;
+    }
+    if (TA == TB) {
+      dG[b * lc + cb + b] = (T)0;
+      dGV[b * lc + cb + b] = (T)0;
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_bwd_same(const BwdSame<T>& a, int32_t nitems, hipStream_t s) {
+  if (nitems <= 0 || a.e.ntri <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_bwd_same<T>), dim3(a.e.ntri, nitems), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_bwd_mixed(const BwdMixed<T>& a, int32_t nitems, hipStream_t s) {
+  if (nitems <= 0 || a.e.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_bwd_mixed<T>), dim3(a.e.ntiles, nitems), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_bwd_same<float>(const BwdSame<float>&, int32_t, hipStream_t);
+template hipError_t launch_bwd_same<double>(const BwdSame<double>&, int32_t, hipStream_t);
+template hipError_t launch_bwd_mixed<float>(const BwdMixed<float>&, int32_t, hipStream_t);
+template hipError_t launch_bwd_mixed<double>(const BwdMixed<double>&, int32_t, hipStream_t);
+
 template <typename T>
 hipError_t launch_epi_same(const EpiSame<T>& a, int32_t nitems, hipStream_t s) {
   if (nitems <= 0 || a.ntri <= 0) return hipSuccess;

@@ -205,5 +205,70 @@ hipError_t launch_reduce_final(const double* e_items, const int32_t* order,
                                const int32_t* first, const int32_t* count,
                                double* parts, double* e_out, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
+// n 32-bit words of zeros
+hipError_t launch_zero32(void* p, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Adjoint (backward) pass
+// ---------------------------------------------------------------------------
+// Descriptor-driven reverse GEMM.  Output block b accumulates
+//   out[r*ldo + c] += sum_{s in [beg,end)} sign_s sum_{x < K_s} A_s(x, r) B_s(x, c)
+// for r < rows, c < cols, with A_s(x, r) = A[r*lda + x] (contraction index
+// contiguous) and B_s(x, c) = TB ? B[c*ldb + x] : B[x*ldb + c].  Row strides
+// are multiples of 4 elements, rows 16-byte aligned and readable up to the
+// next multiple of 4 past the contraction length.  Distinct blocks of one
+// launch must not overlap in memory.
+template <typename T> struct RSeg {
+  const T* A; int64_t lda;
+  const T* B; int64_t ldb;
+  int32_t K; float sign;
+};
+template <typename T> struct RBlk {
+  T* out; int64_t ldo;
+  int32_t rows, cols, beg, end;
+};
+template <typename T> struct RArgs {
+  int32_t nblk, mt, nt, max_rows, max_cols;
+  const RBlk<T>* blks;
+  const RSeg<T>* segs;
+};
+template <typename T> hipError_t launch_rgemm(RArgs<T> g, bool tb, hipStream_t s);
+
+// Backward epilogues: recompute W (and V, D) from the contraction outputs of
+// one batch and write the adjoints of those outputs,
+//   dX  = gbar (2W + V) / D   placed at the positions W reads (with signs),
+//   dXV = gbar W / D          likewise for the singles/f_ov intermediates,
+// every element of the item's output layout written (zeros where W reads
+// nothing).
+template <typename T> struct BwdSame {
+  EpiSame<T> e;                        // part unused
+  const double* gbar;
+  T* dS; T* dSV;                       // [item][a][ld_np], item stride e.s_item
+};
+template <typename T> struct BwdMixed {
+  EpiMixed<T> e;
+  const double* gbar;
+  T *dG, *dGV;                         // [item][a][ld_cb], stride e.g_item
+  T *dY, *dYV;                         // [item][C][ld_np], stride e.y_item
+};
+template <typename T> hipError_t launch_bwd_same(const BwdSame<T>& a, int32_t nitems, hipStream_t s);
+template <typename T> hipError_t launch_bwd_mixed(const BwdMixed<T>& a, int32_t nitems, hipStream_t s);
+
+// out[x0*o0 + x1*o1 + x2*o2 + x3*o3] += scale * in[x0*i0 + x1*i1 + x2*i2 + x3*i3]
+// over x < d (a bijection: each output element written by one thread).
+template <typename Tin>
+hipError_t launch_perm_acc(double* out, const int64_t d[4], const int64_t os[4], const Tin* in,
+                           const int64_t is[4], double scale, hipStream_t s);
+// Pair-packed rows to squares: for r0 < R0, r1 < R1, x, y < n
+//   out[r0*o0 + r1*o1 + x*ox + y*oy] += x < y ? s_up * in[r0*i0 + r1*i1 + p(x,y)]
+//                                     : x > y ? s_lo * in[r0*i0 + r1*i1 + p(y,x)] : 0
+template <typename Tin>
+hipError_t launch_unpack_acc(double* out, int64_t R0, int64_t R1, int32_t n, int64_t o0, int64_t o1,
+                             int64_t ox, int64_t oy, const Tin* in, int64_t i0, int64_t i1, double s_up,
+                             double s_lo, hipStream_t s);
+// In-place projections: t[o][o][v][v] antisymmetrised in (0,1) and (2,3);
+// b[Q][n][n] symmetrised in (1,2).
+hipError_t launch_antisym4(double* t, int64_t o, int64_t v, hipStream_t s);
+hipError_t launch_sym3(double* b, int64_t Q, int64_t n, hipStream_t s);
 
 }  // namespace lt

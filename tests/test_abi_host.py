@@ -138,3 +138,37 @@ def test_batched_rejects_item_lists_and_bad_domains():
     assert lib.ltriples_energy_batched(_fake_array(dims), 2, 9, None, 0x1000, None, None, 0, None) == lt.LT_EPREC
     assert lib.ltriples_energy_batched(None, 0, lt.LT_FP64, None, None, None, None, 0, None) == lt.LT_OK
     assert lib.ltriples_graph_reset() == lt.LT_OK
+
+
+BWD_SHAPES = [(5, 4, 30, 31, 120), (6, 5, 45, 47, 96), (4, 0, 21, 22, 40), (3, 1, 17, 18, 30), (3, 3, 70, 67, 64),
+              (2, 2, 9, 7, 12), (1, 2, 5, 6, 8), (0, 3, 5, 6, 8), (4, 4, 1, 2, 3), (20, 18, 160, 162, 640)]
+
+
+@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32])
+@pytest.mark.parametrize("shape", BWD_SHAPES)
+def test_backward_plan_descriptors_in_bounds(shape, prec):
+    """Every range the adjoint's reverse-contraction descriptors address lies
+    inside its buffer and the targets of one launch are disjoint (checked on
+    the host before any kernel runs)."""
+    lib = _lib()
+    d = _fake_domain(shape)
+    code = lib.ltriples_plan_check(ctypes.byref(d), prec, None, 1)
+    assert code == lt.LT_OK, lt.ltriples_last_error()
+    for bi in (1, 3):
+        o, keep = lt.make_options(batch_items=bi)
+        code = lib.ltriples_plan_check(ctypes.byref(d), prec, ctypes.byref(o), 1)
+        assert code == lt.LT_OK, lt.ltriples_last_error()
+
+
+def test_backward_plan_item_subsets_and_errors():
+    lib = _lib()
+    d = _fake_domain((6, 5, 20, 23, 40))
+    items = synth.sample_items(6, 5, 3, seed=4)
+    o, keep = lt.make_options(items=items, batch_items=2)
+    assert lib.ltriples_plan_check(ctypes.byref(d), lt.LT_FP32, ctypes.byref(o), 1) == lt.LT_OK, \
+        lt.ltriples_last_error()
+    assert lib.ltriples_plan_check(ctypes.byref(d), lt.LT_BF16X3, None, 1) == lt.LT_EPREC
+    n = ctypes.c_size_t(0)
+    assert lib.ltriples_backward_workspace_size(ctypes.byref(d), lt.LT_FP64, None, ctypes.byref(n)) == lt.LT_OK
+    assert n.value > lt.ltriples_workspace_size(d, lt.LT_FP64)
+    assert lib.ltriples_backward(ctypes.byref(d), lt.LT_FP64, None, None, None, None, 0, None) == lt.LT_EINVAL
