@@ -189,7 +189,7 @@ struct Plan {
   Buf dT2T[2], dTp[2], dAs[2], dGamT[2], dUp[2], dT1p[2];
   Buf dLmixT[2], dMst[2], dMts[2], dTmix[2], dZpT[2], dTmT[2], dOOT[2], dOVc[2];
   Buf dOVVV[2][2], dOVOO[2][2], dOVOV[3];   // ovov: aa, bb, ab
-  Buf rblk, rseg, dfblk, dfseg;
+  Buf rblk, rseg, dfblk, dfseg, rred, dfred, rpart;
   // BF16 modes: hi/lo octet copies of the contraction operands
   int bf = 0;                     // 0: none, 3: split products, 1: plain bf16
   enum { T2T8, As8, GamT8, Tp8, LmixT8, Mst8, Mts8, Tmix8, Tmx28, ZpT8, TmT8, OOT8, NT8 };
@@ -873,9 +873,19 @@ int check_denominators(const ltriples_domain* d) {
 template <typename T> struct RevBuilder {
   struct Tgt { lt::RBlk<T> blk; std::vector<lt::RSeg<T>> segs; };
   struct Group { bool tb = false; std::map<uintptr_t, Tgt> tg; };
-  struct Launch { bool tb; int64_t blk0, nblk; int32_t max_rows, max_cols; double flops; };
+  struct Launch {
+    bool tb; int64_t blk0, nblk; int32_t max_rows, max_cols; double flops;
+    int64_t red0, nred; int32_t max_red;
+  };
+  // Long contractions are split at segment boundaries into chunks of about
+  // kChunk elements that write partial sums into `part` (capacity part_cap
+  // elements, reused by every launch); a fixed-order reduce adds them.
+  static constexpr int64_t kChunk = 8192;
+  T* part = nullptr;
+  int64_t part_cap = 0, part_max = 0;
   std::vector<lt::RBlk<T>> blks;
   std::vector<lt::RSeg<T>> segs;
+  std::vector<lt::RRed<T>> reds;
   std::vector<Launch> launches;
   std::vector<Group> groups;
   void begin(int n) { groups.assign(n, Group{}); }
@@ -884,27 +894,77 @@ template <typename T> struct RevBuilder {
     Group& g = groups[gi];
     g.tb = tb;
     Tgt& t = g.tg[(uintptr_t)out];
-    if (t.segs.empty()) t.blk = lt::RBlk<T>{out, ldo, (int32_t)rows, (int32_t)cols, 0, 0};
+    if (t.segs.empty()) t.blk = lt::RBlk<T>{out, ldo, (int32_t)rows, (int32_t)cols, 0, 0, 0, 0};
     t.segs.push_back(sg);
   }
   // emits one launch per non-empty group, targets in address order
   void flush() {
     for (Group& g : groups) {
       if (g.tg.empty()) continue;
-      Launch l{g.tb, (int64_t)blks.size(), 0, 0, 0, 0.0};
+      // chunks per target, halved together until the partials fit
+      std::vector<int64_t> nch;
       for (auto& kv : g.tg) {
-        lt::RBlk<T> b = kv.second.blk;
-        b.beg = (int32_t)segs.size();
-        for (auto& x : kv.second.segs) {
-          segs.push_back(x);
-          l.flops += 2.0 * b.rows * (double)b.cols * x.K;
-        }
-        b.end = (int32_t)segs.size();
-        l.max_rows = std::max(l.max_rows, b.rows);
-        l.max_cols = std::max(l.max_cols, b.cols);
-        blks.push_back(b);
-        ++l.nblk;
+        int64_t K = 0;
+        for (auto& x : kv.second.segs) K += x.K;
+        nch.push_back(std::min<int64_t>((int64_t)kv.second.segs.size(), std::max<int64_t>(1, cdiv(K, kChunk))));
       }
+      for (;;) {
+        int64_t need = 0;
+        size_t q = 0;
+        for (auto& kv : g.tg) {
+          if (nch[q] > 1) need += nch[q] * kv.second.blk.rows * (int64_t)kv.second.blk.cols;
+          ++q;
+        }
+        if (need <= part_cap) break;
+        bool any = false;
+        for (auto& c : nch)
+          if (c > 1) { c = c / 2; any = true; }
+        if (!any) break;
+      }
+      Launch l{g.tb, (int64_t)blks.size(), 0, 0, 0, 0.0, (int64_t)reds.size(), 0, 0};
+      int64_t poff = 0;
+      size_t q = 0;
+      for (auto& kv : g.tg) {
+        const lt::RBlk<T> tb = kv.second.blk;
+        const auto& sv = kv.second.segs;
+        int64_t K = 0;
+        for (auto& x : sv) K += x.K;
+        for (auto& x : sv) l.flops += 2.0 * tb.rows * (double)tb.cols * x.K;
+        l.max_rows = std::max(l.max_rows, tb.rows);
+        l.max_cols = std::max(l.max_cols, tb.cols);
+        const int64_t c = nch[q++];
+        if (c <= 1) {
+          lt::RBlk<T> b = tb;
+          b.beg = (int32_t)segs.size();
+          segs.insert(segs.end(), sv.begin(), sv.end());
+          b.end = (int32_t)segs.size();
+          blks.push_back(b);
+          ++l.nblk;
+          continue;
+        }
+        // contiguous segment ranges of about K/c contraction elements each
+        const int64_t elems = (int64_t)tb.rows * tb.cols;
+        int64_t made = 0, acc = 0;
+        size_t si = 0;
+        while (si < sv.size()) {
+          lt::RBlk<T> b = tb;
+          b.out = part + poff + made * elems;
+          b.ldo = tb.cols;
+          b.store = 1;
+          b.beg = (int32_t)segs.size();
+          const int64_t goal = (made + 1) * K / c;
+          do { acc += sv[si].K; segs.push_back(sv[si]); ++si; } while (si < sv.size() && acc < goal);
+          b.end = (int32_t)segs.size();
+          blks.push_back(b);
+          ++l.nblk;
+          ++made;
+        }
+        reds.push_back(lt::RRed<T>{tb.out, tb.ldo, part + poff, tb.rows, tb.cols, (int32_t)made, 0});
+        ++l.nred;
+        l.max_red = std::max<int32_t>(l.max_red, (int32_t)elems);
+        poff += made * elems;
+      }
+      part_max = std::max(part_max, poff);
       launches.push_back(l);
     }
     groups.clear();
@@ -1090,19 +1150,23 @@ void build_df_rev(const Plan& P, char* ws, const ltriples_domain_grad* g, RevBui
 const ltriples_domain_grad kNoGrad{};
 char* const kFakeBase = (char*)(uintptr_t)(1ull << 40);
 
+constexpr size_t kPartBytes = size_t(256) << 20;   // split-contraction partials
+
 int plan_backward(const ltriples_domain* d, int32_t prec, const ltriples_options* o, const ItemLists& L,
                   Plan& P) {
   plan_domain(d, prec, o, L, P, true);
-  size_t nblk = 0, nseg = 0, dblk = 0, dseg = 0;
+  size_t nblk = 0, nseg = 0, nred = 0, dblk = 0, dseg = 0, dred = 0, part = 0;
   std::vector<std::pair<size_t, size_t>> bl;
   if (prec == LT_FP64) {
     RevBuilder<double> rb;
+    rb.part = (double*)kFakeBase; rb.part_cap = kPartBytes / 8;
     build_rev<double>(P, L, kFakeBase, rb, bl);
-    nblk = rb.blks.size(); nseg = rb.segs.size();
+    nblk = rb.blks.size(); nseg = rb.segs.size(); nred = rb.reds.size(); part = 8 * rb.part_max;
   } else {
     RevBuilder<float> rb;
+    rb.part = (float*)kFakeBase; rb.part_cap = kPartBytes / 4;
     build_rev<float>(P, L, kFakeBase, rb, bl);
-    nblk = rb.blks.size(); nseg = rb.segs.size();
+    nblk = rb.blks.size(); nseg = rb.segs.size(); nred = rb.reds.size(); part = 4 * rb.part_max;
   }
   {
     ltriples_domain_grad all;
@@ -1111,29 +1175,54 @@ int plan_backward(const ltriples_domain* d, int32_t prec, const ltriples_options
     all.Boo_a = fake + 1; all.Bov_a = fake + 2; all.Bvv_a = fake + 3;
     all.Boo_b = fake + 4; all.Bov_b = fake + 5; all.Bvv_b = fake + 6;
     RevBuilder<double> rb;
+    rb.part = (double*)kFakeBase; rb.part_cap = kPartBytes / 8;
     build_df_rev(P, kFakeBase, &all, rb);
-    dblk = rb.blks.size(); dseg = rb.segs.size();
+    dblk = rb.blks.size(); dseg = rb.segs.size(); dred = rb.reds.size();
+    part = std::max(part, (size_t)(8 * rb.part_max));
   }
   size_t off = P.small;
   auto take = [&](Buf& b, size_t bytes) { b.off = off; b.bytes = bytes; off = align256(off + bytes); };
   take(P.rblk, sizeof(lt::RBlk<double>) * std::max<size_t>(nblk, 1));
   take(P.rseg, sizeof(lt::RSeg<double>) * std::max<size_t>(nseg, 1));
+  take(P.rred, sizeof(lt::RRed<double>) * std::max<size_t>(nred, 1));
   take(P.dfblk, sizeof(lt::RBlk<double>) * std::max<size_t>(dblk, 1));
   take(P.dfseg, sizeof(lt::RSeg<double>) * std::max<size_t>(dseg, 1));
+  take(P.dfred, sizeof(lt::RRed<double>) * std::max<size_t>(dred, 1));
+  take(P.rpart, std::max<size_t>(part, 256));
   P.small = off;
   P.total = P.big + P.small;
   return LT_OK;
 }
 
 template <typename T>
+void log_rev(const RevBuilder<T>& rb) {
+  if (!getenv("LTRIPLES_LOG")) return;
+  for (size_t l = 0; l < rb.launches.size(); ++l) {
+    const auto& L = rb.launches[l];
+    int64_t nseg = 0, kmax = 0;
+    for (int64_t b = L.blk0; b < L.blk0 + L.nblk; ++b) {
+      const auto& B = rb.blks[b];
+      nseg += B.end - B.beg;
+      int64_t k = 0;
+      for (int32_t s = B.beg; s < B.end; ++s) k += rb.segs[s].K;
+      kmax = std::max(kmax, k);
+    }
+    fprintf(stderr, "[ltriples] rev launch %zu tb=%d blocks=%lld rows<=%d cols<=%d segs=%lld maxK=%lld flops=%.3e\n", l,
+            (int)L.tb, (long long)L.nblk, L.max_rows, L.max_cols, (long long)nseg, (long long)kmax, L.flops);
+  }
+}
+
+template <typename T>
 int launch_rev_list(const RevBuilder<T>& rb, size_t l0, size_t l1, const lt::RBlk<T>* dblk,
-                    const lt::RSeg<T>* dseg, hipStream_t st) {
+                    const lt::RSeg<T>* dseg, const lt::RRed<T>* dred, hipStream_t st) {
   for (size_t l = l0; l < l1; ++l) {
     const auto& L = rb.launches[l];
     lt::RArgs<T> g{};
     g.nblk = (int32_t)L.nblk; g.max_rows = L.max_rows; g.max_cols = L.max_cols;
     g.blks = dblk + L.blk0; g.segs = dseg;
     HIPCHK(lt::launch_rgemm<T>(g, L.tb, st));
+    for (int64_t r = 0; r < L.nred; r += 65535)
+      HIPCHK(lt::launch_rreduce<T>(dred + L.red0 + r, (int32_t)std::min<int64_t>(65535, L.nred - r), L.max_red, st));
   }
   return LT_OK;
 }
@@ -1182,24 +1271,31 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
   // descriptor lists (host), uploaded once
   RevBuilder<T> rb;
   std::vector<std::pair<size_t, size_t>> bl;
+  rb.part = at_small<T>(ws, P, P.rpart); rb.part_cap = kPartBytes / sizeof(T);
   build_rev<T>(P, L, (char*)ws, rb, bl);
   RevBuilder<double> df;
+  df.part = at_small<double>(ws, P, P.rpart); df.part_cap = kPartBytes / 8;
   build_df_rev(P, (char*)ws, gr, df);
   auto* d_blk = at_small<lt::RBlk<T>>(ws, P, P.rblk);
   auto* d_seg = at_small<lt::RSeg<T>>(ws, P, P.rseg);
+  auto* d_red = at_small<lt::RRed<T>>(ws, P, P.rred);
   auto* d_dfblk = at_small<lt::RBlk<double>>(ws, P, P.dfblk);
   auto* d_dfseg = at_small<lt::RSeg<double>>(ws, P, P.dfseg);
+  auto* d_dfred = at_small<lt::RRed<double>>(ws, P, P.dfred);
   if (rb.blks.size() * sizeof(rb.blks[0]) > P.rblk.bytes || rb.segs.size() * sizeof(rb.segs[0]) > P.rseg.bytes ||
-      df.blks.size() * sizeof(df.blks[0]) > P.dfblk.bytes || df.segs.size() * sizeof(df.segs[0]) > P.dfseg.bytes)
+      rb.reds.size() * sizeof(lt::RRed<T>) > P.rred.bytes || df.blks.size() * sizeof(df.blks[0]) > P.dfblk.bytes ||
+      df.segs.size() * sizeof(df.segs[0]) > P.dfseg.bytes || df.reds.size() * sizeof(df.reds[0]) > P.dfred.bytes ||
+      (size_t)rb.part_max * sizeof(T) > P.rpart.bytes || (size_t)df.part_max * 8 > P.rpart.bytes)
     return fail(LT_EWORKSPACE, "descriptor lists exceed their plan");
-  if (!rb.blks.empty()) {
-    HIPCHK(hipMemcpyAsync(d_blk, rb.blks.data(), rb.blks.size() * sizeof(rb.blks[0]), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_seg, rb.segs.data(), rb.segs.size() * sizeof(rb.segs[0]), hipMemcpyHostToDevice, st));
-  }
-  if (!df.blks.empty()) {
-    HIPCHK(hipMemcpyAsync(d_dfblk, df.blks.data(), df.blks.size() * sizeof(df.blks[0]), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_dfseg, df.segs.data(), df.segs.size() * sizeof(df.segs[0]), hipMemcpyHostToDevice, st));
-  }
+  auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+  };
+  HIPCHK(up(d_blk, rb.blks.data(), rb.blks.size() * sizeof(rb.blks[0])));
+  HIPCHK(up(d_seg, rb.segs.data(), rb.segs.size() * sizeof(rb.segs[0])));
+  HIPCHK(up(d_red, rb.reds.data(), rb.reds.size() * sizeof(lt::RRed<T>)));
+  HIPCHK(up(d_dfblk, df.blks.data(), df.blks.size() * sizeof(df.blks[0])));
+  HIPCHK(up(d_dfseg, df.segs.data(), df.segs.size() * sizeof(df.segs[0])));
+  HIPCHK(up(d_dfred, df.reds.data(), df.reds.size() * sizeof(df.reds[0])));
   HIPCHK(hipStreamSynchronize(st));   // host descriptor vectors go out of scope below
   double rf = 0;
   for (auto& l : rb.launches) rf += l.flops;
@@ -1297,7 +1393,7 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
       }
       hipEvent_t r0 = tm.mark();
       {
-        const int r = launch_rev_list<T>(rb, bl[bi].first, bl[bi].second, d_blk, d_seg, st);
+        const int r = launch_rev_list<T>(rb, bl[bi].first, bl[bi].second, d_blk, d_seg, d_red, st);
         if (r) return r;
       }
       tm.gemm.push_back({r0, tm.mark()});
@@ -1388,7 +1484,7 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
   }
   // --- DF back-contraction -------------------------------------------------------------
   {
-    const int r = launch_rev_list<double>(df, 0, df.launches.size(), d_dfblk, d_dfseg, st);
+    const int r = launch_rev_list<double>(df, 0, df.launches.size(), d_dfblk, d_dfseg, d_dfred, st);
     if (r) return r;
   }
   // --- projections of the constrained inputs -------------------------------------------
@@ -1572,6 +1668,22 @@ int check_rev(const RevBuilder<T>& rb, const std::vector<Range>& bufs, uintptr_t
 }
 
 template <typename T>
+int check_red(const RevBuilder<T>& rb, const std::vector<Range>& outs, const Range& part) {
+  const size_t ts = sizeof(T);
+  for (size_t i = 0; i < rb.reds.size(); ++i) {
+    const lt::RRed<T>& r = rb.reds[i];
+    const uintptr_t o = (uintptr_t)r.out, p = (uintptr_t)r.part;
+    bool ok = false;
+    for (const Range& x : outs)
+      if (o >= x.lo && o + ((r.rows - 1) * r.ldo + r.cols) * ts <= x.hi) ok = true;
+    if (!ok) return fail(LT_EWORKSPACE, "reduce %zu: target outside its buffer", i);
+    if (!(p >= part.lo && p + (size_t)r.nchunk * r.rows * r.cols * ts <= part.hi))
+      return fail(LT_EWORKSPACE, "reduce %zu: partials outside their buffer", i);
+  }
+  return LT_OK;
+}
+
+template <typename T>
 int plan_check_bwd(const Plan& P, const ItemLists& L, bool element_check) {
   char* base = kFakeBase;
   std::vector<Range> bufs;
@@ -1593,10 +1705,19 @@ int plan_check_bwd(const Plan& P, const ItemLists& L, bool element_check) {
   if (bufs.empty()) return LT_OK;
   for (size_t i = 0; i < bufs.size(); ++i)
     if (bufs[i].hi > (uintptr_t)(base + P.big)) return fail(LT_EWORKSPACE, "buffer beyond the planned region");
+  char* pbase = base + P.small_base + P.rpart.off;
+  const Range part{(uintptr_t)pbase, (uintptr_t)(pbase + P.rpart.bytes), "part"};
+  if (part.hi > (uintptr_t)(base + P.total)) return fail(LT_EWORKSPACE, "partials beyond the workspace");
+  const std::vector<Range> mirrors = bufs;
+  bufs.push_back(part);
   RevBuilder<T> rb;
   std::vector<std::pair<size_t, size_t>> bl;
+  rb.part = (T*)pbase; rb.part_cap = kPartBytes / sizeof(T);
   build_rev<T>(P, L, base, rb, bl);
+  log_rev(rb);
   int r = check_rev<T>(rb, bufs, 0, 0, element_check);
+  if (r) return r;
+  r = check_red<T>(rb, mirrors, part);
   if (r) return r;
   // DF back-contraction: caller outputs as disjoint fake regions
   const Dims& D = P.D;
@@ -1613,8 +1734,13 @@ int plan_check_bwd(const Plan& P, const ItemLists& L, bool element_check) {
     gb = align256(gb + 8 * (uintptr_t)sizes[k] + 4096);
   }
   RevBuilder<double> df;
+  df.part = (double*)pbase; df.part_cap = kPartBytes / 8;
   build_df_rev(P, base, &g, df);
-  return check_rev<double>(df, gr, 0, 0, element_check);
+  std::vector<Range> gp = gr;
+  gp.push_back(part);
+  r = check_rev<double>(df, gp, 0, 0, element_check);
+  if (r) return r;
+  return check_red<double>(df, gr, part);
 }
 
 }  // namespace

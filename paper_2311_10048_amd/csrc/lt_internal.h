@@ -226,7 +226,18 @@ template <typename T> struct RSeg {
 template <typename T> struct RBlk {
   T* out; int64_t ldo;
   int32_t rows, cols, beg, end;
+  int32_t store;                   // 1: out = sum (partial of a split target), 0: out += sum
+  int32_t pad;
 };
+// Split targets: out[r*ldo + c] += sum_{j < nchunk} part[j*rows*cols + r*cols + c]
+// (FP64 sum in chunk order).
+template <typename T> struct RRed {
+  T* out; int64_t ldo;
+  const T* part;
+  int32_t rows, cols, nchunk, pad;
+};
+template <typename T> hipError_t launch_rreduce(const RRed<T>* reds, int32_t nred, int32_t max_elems,
+                                                hipStream_t s);
 template <typename T> struct RArgs {
   int32_t nblk, mt, nt, max_rows, max_cols;
   const RBlk<T>* blks;

@@ -191,7 +191,11 @@ __global__ __launch_bounds__(256) void k_rgemm(RArgs<T> g) {
 #pragma unroll
       for (int r = 0; r < F::NACC; ++r) {
         const int m = m0 + wm * MBW * BR + mb * BR + F::c_row(lane, r);
-        if (m < bk.rows) bk.out[(int64_t)m * bk.ldo + n] += TWO ? tot[mb][nb][r] : acc[mb][nb][r];
+        if (m < bk.rows) {
+          T* o = bk.out + (int64_t)m * bk.ldo + n;
+          const T x = TWO ? tot[mb][nb][r] : acc[mb][nb][r];
+          *o = bk.store ? x : *o + x;
+        }
       }
   }
 }
@@ -210,6 +214,29 @@ hipError_t rcfg(RArgs<T> g, bool tb, hipStream_t s) {
     hipLaunchKernelGGL((k_rgemm<T, MBW, NBW, WM, BK, false>), dim3((unsigned)nwg), dim3(256), 0, s, g);
   return hipGetLastError();
 }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_rreduce(const RRed<T>* reds) {
+  const RRed<T> r = reds[blockIdx.y];
+  const int64_t n = (int64_t)r.rows * r.cols;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    double sum = 0.0;
+    for (int j = 0; j < r.nchunk; ++j) sum += (double)r.part[(int64_t)j * n + e];
+    T* o = r.out + (e / r.cols) * r.ldo + e % r.cols;
+    *o = (T)((double)*o + sum);
+  }
+}
+
+template <typename T>
+hipError_t launch_rreduce(const RRed<T>* reds, int32_t nred, int32_t max_elems, hipStream_t s) {
+  if (nred <= 0 || max_elems <= 0) return hipSuccess;
+  int64_t gx = (max_elems + 255) / 256;
+  if (gx > 1024) gx = 1024;
+  hipLaunchKernelGGL((k_rreduce<T>), dim3((unsigned)gx, (unsigned)nred), dim3(256), 0, s, reds);
+  return hipGetLastError();
+}
+template hipError_t launch_rreduce<float>(const RRed<float>*, int32_t, int32_t, hipStream_t);
+template hipError_t launch_rreduce<double>(const RRed<double>*, int32_t, int32_t, hipStream_t);
 
 template <> hipError_t launch_rgemm<float>(RArgs<float> g, bool tb, hipStream_t s) {
   const int need = (g.max_rows + 31) / 32;
