@@ -29,12 +29,15 @@ __global__ __launch_bounds__(256) void k_rgemm(RArgs<T> g) {
   constexpr int BM = WM * MBW * BR;
   constexpr int BN = WN * NBW * BC;
   constexpr int KQ = BK / VN;                       // vectors along the contraction
+  constexpr int KP = BK + 16 / (int)sizeof(T);      // padded LDS row of a contraction-contiguous tile
   constexpr int AV = BM * KQ;
   constexpr int BV = TB ? BN * KQ : BK * (BN / VN);
   constexpr int AVT = (AV + 255) / 256, BVT = (BV + 255) / 256;
 
-  __shared__ __attribute__((aligned(16))) T As[2][BK][BM];
-  __shared__ __attribute__((aligned(16))) T Bs[2][BK][BN];
+  // A tiles (and B tiles read transposed) keep the contraction index
+  // contiguous in LDS: one 16-byte store per loaded vector.
+  __shared__ __attribute__((aligned(16))) T As[2][BM][KP];
+  __shared__ __attribute__((aligned(16))) T Bs[2][TB ? BN : BK][TB ? KP : BN];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
@@ -82,8 +85,7 @@ __global__ __launch_bounds__(256) void k_rgemm(RArgs<T> g) {
   };
 
   V ra[AVT], rb[BVT];
-  auto gload = [&](int s, int k0) {
-    const RSeg<T> sg = segs[s];
+  auto gload = [&](const RSeg<T>& sg, int k0) {
 #pragma unroll
     for (int u = 0; u < AVT; ++u) {
       const int e = tid + u * 256;
@@ -124,32 +126,22 @@ __global__ __launch_bounds__(256) void k_rgemm(RArgs<T> g) {
 #pragma unroll
     for (int u = 0; u < AVT; ++u) {
       const int e = tid + u * 256;
-      if (e < AV) {
-        const int m = e / KQ, q = e % KQ;
-        const T* pv = (const T*)&ra[u];
-#pragma unroll
-        for (int t = 0; t < VN; ++t) As[buf][q * VN + t][m] = pv[t];
-      }
+      if (e < AV) *(V*)&As[buf][e / KQ][(e % KQ) * VN] = ra[u];
     }
 #pragma unroll
     for (int u = 0; u < BVT; ++u) {
       const int e = tid + u * 256;
       if (e < BV) {
-        if constexpr (TB) {
-          const int n = e / KQ, q = e % KQ;
-          const T* pv = (const T*)&rb[u];
-#pragma unroll
-          for (int t = 0; t < VN; ++t) Bs[buf][q * VN + t][n] = pv[t];
-        } else {
-          *(V*)&Bs[buf][e / (BN / VN)][(e % (BN / VN)) * VN] = rb[u];
-        }
+        if constexpr (TB) *(V*)&Bs[buf][e / KQ][(e % KQ) * VN] = rb[u];
+        else *(V*)&Bs[buf][e / (BN / VN)][(e % (BN / VN)) * VN] = rb[u];
       }
     }
   };
 
   int s = 0, k0 = 0;
   while (s < nseg && segs[s].K <= 0) ++s;
-  if (s < nseg) { gload(s, k0); sstore(0); }
+  RSeg<T> cs{};                  // descriptor of the segment being loaded (reloaded on change only)
+  if (s < nseg) { cs = segs[s]; gload(cs, k0); sstore(0); }
   __syncthreads();
   int cur = 0;
   int seg_of[2] = {s, s};        // segment of the data staged in each LDS buffer
@@ -158,9 +150,12 @@ __global__ __launch_bounds__(256) void k_rgemm(RArgs<T> g) {
   const int bcol0 = wn * NBW * BC + F::c_col(lane);
   while (s < nseg) {
     k0 += BK;
-    while (s < nseg && k0 >= segs[s].K) { ++s; k0 = 0; }
+    while (s < nseg && k0 >= cs.K) {
+      ++s; k0 = 0;
+      if (s < nseg) cs = segs[s];
+    }
     const bool more = s < nseg;
-    if (more) gload(s, k0);
+    if (more) gload(cs, k0);
     if (TWO && (seg_of[cur] != last || steps == FOLD)) { fold(); last = seg_of[cur]; steps = 0; }
     ++steps;
 #pragma unroll
@@ -168,10 +163,13 @@ __global__ __launch_bounds__(256) void k_rgemm(RArgs<T> g) {
       const int kr = ks + F::a_k(lane);
       T bv[NBW];
 #pragma unroll
-      for (int nb = 0; nb < NBW; ++nb) bv[nb] = Bs[cur][kr][bcol0 + nb * BC];
+      for (int nb = 0; nb < NBW; ++nb) {
+        if constexpr (TB) bv[nb] = Bs[cur][bcol0 + nb * BC][kr];
+        else bv[nb] = Bs[cur][kr][bcol0 + nb * BC];
+      }
 #pragma unroll
       for (int mb = 0; mb < MBW; ++mb) {
-        const T av = As[cur][kr][arow0 + mb * BR];
+        const T av = As[cur][arow0 + mb * BR][kr];
 #pragma unroll
         for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = F::mma(av, bv[nb], acc[mb][nb]);
       }
@@ -242,6 +240,10 @@ template <> hipError_t launch_rgemm<float>(RArgs<float> g, bool tb, hipStream_t 
   const int need = (g.max_rows + 31) / 32;
   if (need <= 1) return rcfg<float, 1, 1, 1, 16>(g, tb, s);
   if (need <= 2) return rcfg<float, 2, 1, 1, 16>(g, tb, s);
+  if (need <= 3) return rcfg<float, 3, 1, 1, 16>(g, tb, s);
+  if (need <= 4) return rcfg<float, 2, 2, 2, 16>(g, tb, s);
+  if (need <= 5) return rcfg<float, 5, 1, 1, 16>(g, tb, s);
+  if (need <= 6) return rcfg<float, 3, 2, 2, 16>(g, tb, s);
   return rcfg<float, 2, 2, 2, 16>(g, tb, s);
 }
 
@@ -249,6 +251,8 @@ template <> hipError_t launch_rgemm<double>(RArgs<double> g, bool tb, hipStream_
   const int need = (g.max_rows + 15) / 16;
   if (need <= 2) return rcfg<double, 2, 1, 1, 8>(g, tb, s);
   if (need <= 4) return rcfg<double, 4, 1, 1, 8>(g, tb, s);
+  if (need <= 8) return rcfg<double, 4, 2, 2, 8>(g, tb, s);
+  if (need <= 10) return rcfg<double, 5, 2, 2, 8>(g, tb, s);
   return rcfg<double, 4, 2, 2, 8>(g, tb, s);
 }
 
