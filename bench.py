@@ -6,17 +6,27 @@ One step is one full ltriples_energy call on the domain (operand layouts,
 density-fitting integral builds, every occupied triplet of the four spin
 blocks, FP64 energy epilogue and reductions), with the inputs resident in HBM.
 The printed JSON line also carries:
-  roofline      the triplet-contraction GEMM kernel (k_tgemm) against the
-                matrix-core peak of its dtype, timed live with HIP events
+  roofline      the triplet-contraction GEMM kernel against the matrix-core
+                peak of its dtype, timed live with HIP events on the library's
+                stream; traffic from the committed counter summary when it was
+                taken on the current kernel source (else null)
   fp64_gpu      the same path in FP64 (the "plain FP64 GPU" baseline), timed
                 on a stratified item sample and scaled to the whole domain
   parity        per-item values of the timed run against the FP64 CPU oracle
                 on the CPU-baseline items, and against the FP64 GPU run
   cpu_baseline  the FP64 CPU oracle timed on the host on a small item sample
+  backward      the adjoint pass (dE/dT1, dE/dT2, dE/dB) on the gradient
+                workload (20,18,160,162,640), FP32 and FP64, with a sampled
+                check against the oracle gradient
+
+Profiling aids (not headline measurements): --sample-items K restricts the
+timed step to K sampled triplets per spin block; --copy-calibration runs only
+a plain 1 GiB device copy (for scaling HBM byte counters).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,6 +41,11 @@ if ROOT not in sys.path:
 METRIC = "(T) triples GFLOP/s & MFMA util vs plain FP64 GPU, at |ΔE(T)|≤1e-6 Eh"
 # dense matrix-core peaks of MI355X (TFLOP/s)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16": 2500.0}
+# matrix-core products per algorithmic multiply-add
+MFMA_PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16": 1}
+GEMM_SOURCES = {"bf16x3": "lt_gemm_bf16.hip", "bf16": "lt_gemm_bf16.hip", "fp32": "lt_gemm.hip",
+                "fp64": "lt_gemm.hip"}
+TOL = {"fp64": 1e-11, "fp32": 1e-8, "bf16x3": 1e-6, "bf16": None}
 
 
 def _blas_threads():
@@ -44,16 +59,51 @@ def _blas_threads():
     return os.cpu_count() or 1
 
 
+def kernel_source_hash(precision):
+    src = os.path.join(ROOT, "paper_2311_10048_amd", "csrc", GEMM_SOURCES[precision])
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def committed_traffic(precision, workload):
+    """Per-launch HBM bytes of the contraction kernel from the committed
+    counter summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{precision}_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_source_hash(precision):
+        return None
+    return t
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3", "bf16"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "fp64", "bf16x3", "bf16"])
     ap.add_argument("--workload", default="lno", choices=["tiny", "lno", "grad"])
     ap.add_argument("--fp64-sample", type=int, default=48, help="items per block for the FP64 GPU comparison")
     ap.add_argument("--cpu-sample", type=int, default=1, help="items per block for the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--sample-items", type=int, default=0, help="profiling aid: K sampled triplets per block")
+    ap.add_argument("--copy-calibration", action="store_true", help="profiling aid: plain 1 GiB device copy")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -71,6 +121,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     dev = torch.device("cuda:0")
     prec = lt.PRECISIONS[args.precision]
 
@@ -83,14 +136,19 @@ def main():
     tens = {k: torch.from_numpy(v).to(dev) for k, v in dom.arrays().items()}
     torch.cuda.synchronize()
     d = lt.make_domain(dom.dims, tens)
-    F_all, n_all = lt.ltriples_flops(d)
-    ws = torch.empty(lt.ltriples_workspace_size(d, prec), dtype=torch.uint8, device=dev)
+    step_items = None
+    if args.sample_items > 0:
+        step_items = synth.sample_items(dom.noa, dom.nob, args.sample_items, seed=99)
+    ostep, _keep0 = lt.make_options(items=step_items)
+    F_all, n_all = lt.ltriples_flops(d, ostep)
+    ws = torch.empty(lt.ltriples_workspace_size(d, prec, ostep), dtype=torch.uint8, device=dev)
     e_items = torch.zeros(n_all, 3, dtype=torch.float64, device=dev)
     log(f"items {n_all}, algorithmic flops {F_all:.4e}, workspace {ws.numel() / 1e9:.1f} GB")
 
     def step():
         st = lt.Stats()
-        e, parts = lt.ltriples_energy(tens, dom.dims, prec, e_items=e_items, workspace=ws, stats=st)
+        e, parts = lt.ltriples_energy(tens, dom.dims, prec, items=step_items, e_items=e_items, workspace=ws,
+                                      stats=st)
         return e, parts, st
 
     for w in range(args.warmup):
@@ -115,24 +173,45 @@ def main():
     parts = parts.cpu().numpy()
     value = F_all / (ms_per_step * 1e-3) / 1e9
 
+    # roofline of the contraction kernel: algorithmic flops per launch over the
+    # launches' average HIP-event duration (events on the library's stream)
     gemm_ms = sum(s.triples_gemm_ms for s in stats)
     gemm_flops = sum(s.triples_gemm_flops for s in stats)
     launches = sum(s.triples_gemm_launches for s in stats)
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
-    roofline = {"bound": "mfma", "kernel": "k_tgemm (triplet contraction GEMM)",
+    avg_ms = gemm_ms / max(launches, 1)
+    traffic = None
+    tr = committed_traffic(args.precision, args.workload)
+    if tr is not None:
+        traffic = tr["bytes_per_launch"]
+    kname = "k_tgemm_bf16" if args.precision.startswith("bf16") else "k_tgemm"
+    roofline = {"bound": "mfma", "kernel": f"{kname} (triplet contraction GEMM)",
                 "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "avg_launch_ms": round(gemm_ms / max(launches, 1), 4),
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "avg_launch_ms": round(avg_ms, 4),
                 "launches_per_step": launches // max(len(stats), 1),
-                "flops_per_launch": gemm_flops / max(launches, 1)}
+                "flops_per_launch": gemm_flops / max(launches, 1),
+                "kernel_source_hash": kernel_source_hash(args.precision)}
+    # matrix-core utilisation counts every product the split performs
+    mfma_util = MFMA_PRODUCTS[args.precision] * achieved / peak
     phase = {"setup_ms": round(stats[-1].setup_ms, 2), "triples_gemm_ms": round(stats[-1].triples_gemm_ms, 2),
              "epilogue_ms": round(stats[-1].epilogue_ms, 2), "total_ms": round(stats[-1].total_ms, 2)}
     log(f"E = {E:.10e}  {ms_per_step / 1e3:.2f} s/step  {value:.1f} GFLOP/s  gemm {achieved:.1f} TFLOP/s")
 
+    full_items = step_items if step_items is not None else None
+
+    def positions(items):
+        if full_items is None:
+            return _item_index(dom.noa, dom.nob, items)
+        lut = {tuple(r): n for n, r in enumerate(np.asarray(full_items).reshape(-1, 4).tolist())}
+        return np.asarray([lut[tuple(r)] for r in np.asarray(items).reshape(-1, 4).tolist()], dtype=np.int64)
+
     # ---- FP64 GPU path on a stratified sample, scaled to the domain -----------------------
     fp64 = None
     items64 = synth.sample_items(dom.noa, dom.nob, args.fp64_sample, seed=2311)
+    if step_items is not None:
+        items64 = step_items
     if args.fp64_sample > 0 and len(items64):
         o64, _keep = lt.make_options(items=items64)
         F_s, n_s = lt.ltriples_flops(d, o64)
@@ -143,9 +222,7 @@ def main():
         torch.cuda.synchronize()
         per_flop_ms = (st64.triples_gemm_ms + st64.epilogue_ms) / F_s
         est_ms = st64.setup_ms + per_flop_ms * F_all
-        # the timed run's values at the same items
-        full_idx = _item_index(dom.noa, dom.nob, items64)
-        mine = e_items.cpu().numpy()[full_idx]
+        mine = e_items.cpu().numpy()[positions(items64)]
         ref64 = ei64.cpu().numpy()
         s_mine, s_ref = mine.sum(), ref64.sum()
         fp64 = {"sample_items": int(n_s), "sample_ms": round(st64.total_ms, 2),
@@ -161,6 +238,8 @@ def main():
     if not args.no_cpu_baseline and args.cpu_sample > 0:
         from oracle import blocks
         itc = synth.sample_items(dom.noa, dom.nob, args.cpu_sample, seed=11)
+        if step_items is not None:
+            itc = step_items[:4]
         oc, _k2 = lt.make_options(items=itc)
         F_c, n_c = lt.ltriples_flops(d, oc)
         tc = time.perf_counter()
@@ -170,14 +249,17 @@ def main():
                "sample": f"{n_c} occupied triplets ({args.cpu_sample} per spin block) of the same domain, "
                          f"{F_c:.3e} flops in {dt:.1f} s, NumPy FP64",
                "seconds": round(dt, 2), "est_full_domain_s": round(dt * F_all / F_c, 1)}
-        full_idx = _item_index(dom.noa, dom.nob, itc)
-        g = e_items.cpu().numpy()[full_idx]
+        g = e_items.cpu().numpy()[positions(itc)]
         r = ref["items"]
         tot = np.abs(g.sum(axis=1) - r.sum(axis=1)) / np.maximum(1.0, np.abs(r.sum(axis=1)))
-        tol = {"fp64": 1e-11, "fp32": 1e-8, "bf16x3": 1e-6, "bf16": None}[args.precision]
+        tol = TOL[args.precision]
         parity = {"oracle_items": int(n_c), "max_rel_err_item_E": float(tot.max()), "tolerance": tol,
                   "pass": None if tol is None else bool(tot.max() <= tol)}
         log(f"cpu oracle {dt:.1f} s for {n_c} items; max item rel err {tot.max():.2e}")
+
+    backward = None
+    if not args.no_backward and step_items is None:
+        backward = run_backward(lt, synth, torch, log)
 
     out = {
         "metric": METRIC,
@@ -193,19 +275,64 @@ def main():
         "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": f"{args.workload} domain: noa={dom.noa} nob={dom.nob} nva={dom.nva} "
-                               f"nvb={dom.nvb} naux={dom.naux}, all {n_all} occupied triplets",
+                               f"nvb={dom.nvb} naux={dom.naux}, "
+                               + (f"all {n_all} occupied triplets" if step_items is None
+                                  else f"{n_all} sampled triplets (profiling run)"),
                    "algorithmic_flops": F_all, "precision": args.precision,
                    "wall_ms_per_step": round(wall_ms / args.steps, 2)},
         "E": E,
         "parts": parts.tolist(),
         "phases": phase,
         "roofline": roofline,
-        "mfma_util": roofline["frac"],
+        "mfma_util": round(mfma_util, 4),
         "fp64_gpu": fp64,
         "parity": parity,
         "cpu_baseline": cpu,
+        "backward": backward,
     }
     print(json.dumps(out), flush=True)
+
+
+def run_backward(lt, synth, torch, log):
+    """Adjoint pass on the gradient workload: FP32 (timed after one warmup)
+    and FP64; 3F / t in GFLOP/s; sampled items against the oracle gradient."""
+    from oracle import grad as ograd
+    dom = synth.config_domain("grad")
+    tens = {k: torch.from_numpy(v).cuda() for k, v in dom.arrays().items()}
+    d = lt.make_domain(dom.dims, tens)
+    F, n = lt.ltriples_flops(d)
+    res = {"workload": f"grad domain: noa={dom.noa} nob={dom.nob} nva={dom.nva} nvb={dom.nvb} naux={dom.naux}, "
+                       f"all {n} occupied triplets", "algorithmic_flops_3F": 3 * F}
+    for name, prec in (("fp32", lt.LT_FP32), ("fp64", lt.LT_FP64)):
+        ws = torch.empty(lt.ltriples_backward_workspace_size(d, prec), dtype=torch.uint8, device="cuda")
+        reps = 2 if name == "fp32" else 1
+        for r in range(reps):
+            st = lt.Stats()
+            g = lt.ltriples_backward(tens, dom.dims, prec, workspace=ws, stats=st)
+            torch.cuda.synchronize()
+        res[name] = {"ms": round(st.total_ms, 1), "GFLOP/s": round(3 * F / (st.total_ms * 1e-3) / 1e9, 1),
+                     "gemm_ms": round(st.triples_gemm_ms, 1), "epilogue_ms": round(st.epilogue_ms, 1)}
+        log(f"backward {name}: {st.total_ms / 1e3:.2f} s")
+        del ws, g
+    items = synth.sample_items(dom.noa, dom.nob, 1, seed=77)
+    tc = time.perf_counter()
+    _, ref = ograd.energy_and_grad(dom, items=items)
+    dt = time.perf_counter() - tc
+    err = {}
+    for name, prec in (("fp32", lt.LT_FP32), ("fp64", lt.LT_FP64)):
+        g = lt.ltriples_backward(tens, dom.dims, prec, items=items)
+        torch.cuda.synchronize()
+        worst = 0.0
+        for k in lt.GRAD_FIELDS:
+            r = ref[k]
+            if r.size:
+                worst = max(worst, float(np.max(np.abs(g[k].cpu().numpy() - r)) / np.max(np.abs(r))))
+        err[name] = worst
+    res["parity"] = {"oracle_items": int(len(items)), "max_rel_err_fp64": err["fp64"], "tol_fp64": 1e-10,
+                     "max_rel_err_fp32": err["fp32"], "tol_fp32": 1e-5,
+                     "pass": bool(err["fp64"] <= 1e-10 and err["fp32"] <= 1e-5), "oracle_seconds": round(dt, 1)}
+    log(f"backward parity: fp64 {err['fp64']:.2e}, fp32 {err['fp32']:.2e}")
+    return res
 
 
 def _item_index(noa, nob, items):
@@ -219,7 +346,6 @@ def _item_index(noa, nob, items):
     for b, p, q, r in np.asarray(items).reshape(-1, 4):
         if b in (0, 3):
             n = nob if b == 3 else noa
-            # rank of (p<q<r) in lexicographic order
             k = 0
             for i in range(p):
                 k += (n - 1 - i) * (n - 2 - i) // 2
