@@ -1373,7 +1373,8 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
         x.ld_np = P.ldnp[s]; x.ld_cb = P.ldcb[s];
         x.G = G; x.g_item = (int64_t)(o1 / P.ts); x.Y = Y; x.y_item = (int64_t)(o2 / P.ts);
         x.items = items;
-        x.nts = (int32_t)cdiv(vs, lt::ET); x.ntt = (int32_t)cdiv(vt, lt::ET); x.ntiles = (int32_t)nt;
+        x.nts = (int32_t)cdiv(vs, lt::ET); x.ntt = (int32_t)cdiv(vt, lt::ET);
+        x.ntiles = x.nts * (x.nts + 1) / 2 * x.ntt;
         x.eo_s = EO[s]; x.ev_s = EV[s]; x.eo_t = EO[t]; x.ev_t = EV[t];
         x.t1_s = T1[s]; x.t1_t = T1[t]; x.f_s = Fov[s]; x.f_t = Fov[t]; x.t2ss = T2ss[s];
         x.U = at<double>(ws, P.U[s]); x.ld_vs = P.ldv[s];

@@ -46,6 +46,20 @@ __device__ inline void tri_decode(int t, int& A, int& B, int& C) {
 
 constexpr int SROW = ET * ET + 1;   // padded LDS row for [ta][tc*16+tb]
 
+// 1/d by Newton-Raphson from the hardware reciprocal approximation: each step
+// r <- r + r(1 - d r) squares the relative error, two steps reach FP64
+// rounding (within an ulp or two of the correctly rounded quotient).  Falls
+// back to division for |d| outside the normal range.
+__device__ inline double rcp64(double d) {
+  const double ad = fabs(d);
+  if (!(ad > 1e-300 && ad < 1e300)) return 1.0 / d;
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_epi_same(EpiSame<T> a) {
   __shared__ T Sb[ET][SROW];        // S[b][p(a,c)]
@@ -119,18 +133,20 @@ __global__ __launch_bounds__(256) void k_epi_same(EpiSame<T> a) {
     const double dbc = (a.eo[occ[0]] + a.eo[occ[1]] + a.eo[occ[2]]) - a.ev[b] - a.ev[c];
     const T* Srow = S + (int64_t)c * (c - 1) / 2 + b;
     const int na = min(ET, b - a0);
-    for (int ta = 0; ta < na; ++ta) {
-      const int aa = a0 + ta;
-      const double w = (double)Srow[aa * ldp] - (double)Sb[ta][tc * ET + tb] + (double)Sc[ta][tc * ET + tb];
+    T sd[ET];                        // direct-term operands, loaded in one burst
+#pragma unroll
+    for (int ta = 0; ta < ET; ++ta) sd[ta] = ta < na ? Srow[(a0 + ta) * ldp] : (T)0;
+#pragma unroll
+    for (int ta = 0; ta < ET; ++ta) {
+      if (ta >= na) break;
+      const double w = (double)sd[ta] - (double)Sb[ta][tc * ET + tb] + (double)Sc[ta][tc * ET + tb];
       double vt = 0.0, vf = 0.0;
 #pragma unroll
       for (int pp = 0; pp < 3; ++pp) {
         vt += t1a[pp][ta] * Ubc[pp] - t1b[pp] * Uac[pp][ta][tc] - t1c[pp] * Uba[pp][tb][ta];
         vf += fa[pp][ta] * Tbc[pp] - fb[pp] * Tac[pp][ta][tc] - fc[pp] * Tba[pp][tb][ta];
       }
-      // t1a/fa carry no sign: fold the occupied-permutation sign of the first term here
-      const double d = dbc - eva[ta];
-      const double wd = w / d;
+      const double wd = w * rcp64(dbc - eva[ta]);
       e4 += wd * w;
       est += wd * vt;
       edt += wd * vf;
@@ -210,15 +226,18 @@ __global__ __launch_bounds__(256) void k_epi_mixed(EpiMixed<T> a) {
     const double dbc = (a.eo_s[i] + a.eo_s[j] + a.eo_t[K]) - a.ev_s[b] - a.ev_t[C];
     const T* Grow = G + (int64_t)C * vs + b;
     const int na = min(ET, b - a0);
-    for (int ta = 0; ta < na; ++ta) {
-      const int aa = a0 + ta;
-      const double w = (double)Grow[aa * lc] - (double)Gb[ta][tc * ET + tb] + (double)Yl[ta][tc * ET + tb];
+    T gd[ET];                        // direct-term operands, loaded in one burst
+#pragma unroll
+    for (int ta = 0; ta < ET; ++ta) gd[ta] = ta < na ? Grow[(a0 + ta) * lc] : (T)0;
+#pragma unroll
+    for (int ta = 0; ta < ET; ++ta) {
+      if (ta >= na) break;
+      const double w = (double)gd[ta] - (double)Gb[ta][tc * ET + tb] + (double)Yl[ta][tc * ET + tb];
       const double vt1 = t1ai[ta] * OVjb - t1aj[ta] * OVib - t1bi * OVj[ta][tc] + t1bj * OVi[ta][tc]
                          + t1C * Uab[tb][ta];
       const double vfo = fai[ta] * Tmjb - faj[ta] * Tmib - fbi * Tmj[ta][tc] + fbj * Tmi[ta][tc]
                          + fC * T2ab[tb][ta];
-      const double d = dbc - eva[ta];
-      const double wd = w / d;
+      const double wd = w * rcp64(dbc - eva[ta]);
       e4 += wd * w;
       est += wd * vt1;
       edt += wd * vfo;
@@ -323,8 +342,8 @@ __global__ __launch_bounds__(256) void k_bwd_same(BwdSame<T> A) {
         vt += t1a[pp][ta] * Ubc[pp] - t1b[pp] * Uac[pp][ta][tc] - t1c[pp] * Uba[pp][tb][ta];
         vf += fa[pp][ta] * Tbc[pp] - fb[pp] * Tac[pp][ta][tc] - fc[pp] * Tba[pp][tb][ta];
       }
-      const double d = dbc - eva[ta];
-      const double wh = g * (2.0 * w + vt + vf) / d, vh = g * w / d;
+      const double rd = rcp64(dbc - eva[ta]);
+      const double wh = g * (2.0 * w + vt + vf) * rd, vh = g * w * rd;
       // W = S[a][bc] - S[b][ac] + S[c][ab]; V likewise from the singles/f_ov intermediate
       dS[aa * ldp + pbc] = (T)wh;
       dS[b * ldp + pidx(aa, c)] = (T)(-wh);
@@ -424,8 +443,8 @@ __global__ __launch_bounds__(256) void k_bwd_mixed(BwdMixed<T> A) {
                          + t1C * Uab[tb][ta];
       const double vfo = fai[ta] * Tmjb - faj[ta] * Tmib - fbi * Tmj[ta][tc] + fbj * Tmi[ta][tc]
                          + fC * T2ab[tb][ta];
-      const double d = dbc - eva[ta];
-      const double wh = g * (2.0 * w + vt1 + vfo) / d, vh = g * w / d;
+      const double rd = rcp64(dbc - eva[ta]);
+      const double wh = g * (2.0 * w + vt1 + vfo) * rd, vh = g * w * rd;
       // W = G[a][Cb] - G[b][Ca] + Y[C][ab]
       dG[aa * lc + cb + b] = (T)wh;
       dG[b * lc + cb + aa] = (T)(-wh);
