@@ -104,55 +104,73 @@ __global__ __launch_bounds__(256) void k_tgemm_bf16(GemmArgs16 g) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.f;
 
-  uint4 ra[AVT], rb[BVT];
-  auto gload = [&](int s, int k0) {
+  // Loads are unmasked: each octet tensor is zero-padded to 16 contraction
+  // rows per block and carries slack past its last column, so whole-tile
+  // loads stay in bounds, rows k >= K read zeros, and columns/rows past the
+  // output shape only feed discarded outputs.  Each thread keeps 32-bit
+  // offsets (in octets) from the segment's wave-uniform bases, set when the
+  // segment changes and advanced by a constant per stage.
+  uint32_t oa[AVT], ob[BVT];
+  const uint4 *Lh = nullptr, *Ll = nullptr, *Rh = nullptr, *Rl = nullptr;
+  uint32_t sa = 0, sb = 0, flip = 0;
+  int K = 0;
+  auto setseg = [&](int s) {
     const Seg8 sg = item_seg8(g.ops, ti, tj, tk, s);
-    const uint32_t flip = sg.sign < 0.f ? 0x80008000u : 0u;
+    K = sg.K;
+    flip = sg.sign < 0.f ? 0x80008000u : 0u;
+    sa = (uint32_t)(2 * sg.lq / 8); sb = (uint32_t)(2 * sg.rq / 8);
+    Lh = (const uint4*)sg.Lh; Ll = (const uint4*)sg.Ll; Rh = (const uint4*)sg.Rh; Rl = (const uint4*)sg.Rl;
+#pragma unroll
+    for (int u = 0; u < AVT; ++u) {
+      const int r = (tid + u * 256) % AO;
+      oa[u] = (uint32_t)((r / BM) * (sg.lq / 8) + m0 + r % BM);
+    }
+#pragma unroll
+    for (int u = 0; u < BVT; ++u) {
+      const int r = (tid + u * 256) % BO;
+      ob[u] = (uint32_t)((r / BN) * (sg.rq / 8) + n0 + r % BN);
+    }
+  };
+  uint4 ra[AVT], rb[BVT];
+  auto gload = [&]() {
 #pragma unroll
     for (int u = 0; u < AVT; ++u) {
       const int e = tid + u * 256;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (e < 2 * AO) {
-        const int hl = e / AO, r = e % AO, q = r / BM, m = m0 + r % BM, k = k0 + 8 * q;
-        if (k < sg.K && m < g.M) {
-          const bf16_t* base = hl ? sg.Ll : sg.Lh;
-          v = *(const uint4*)(base + (int64_t)(k >> 3) * sg.lq + (int64_t)m * 8);
-          v.x ^= flip; v.y ^= flip; v.z ^= flip; v.w ^= flip;
-        }
-      }
-      ra[u] = v;
+      if ((2 * AO) % 256 == 0 || e < 2 * AO) ra[u] = (e >= AO ? Ll : Lh)[oa[u]];
+      oa[u] += sa;
     }
 #pragma unroll
     for (int u = 0; u < BVT; ++u) {
       const int e = tid + u * 256;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (e < 2 * BO) {
-        const int hl = e / BO, r = e % BO, q = r / BN, n = n0 + r % BN, k = k0 + 8 * q;
-        if (k < sg.K && n < g.N) {
-          const bf16_t* base = hl ? sg.Rl : sg.Rh;
-          v = *(const uint4*)(base + (int64_t)(k >> 3) * sg.rq + (int64_t)n * 8);
-        }
-      }
-      rb[u] = v;
+      if ((2 * BO) % 256 == 0 || e < 2 * BO) rb[u] = (e >= BO ? Rl : Rh)[ob[u]];
+      ob[u] += sb;
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < AVT; ++u) {
       const int e = tid + u * 256;
-      if (e < 2 * AO) { const int hl = e / AO, r = e % AO; As[buf][hl][r / BM][r % BM] = ra[u]; }
+      if ((2 * AO) % 256 == 0 || e < 2 * AO) {
+        const int hl = e / AO, r = e % AO;
+        uint4 v = ra[u];
+        v.x ^= flip; v.y ^= flip; v.z ^= flip; v.w ^= flip;
+        As[buf][hl][r / BM][r % BM] = v;
+      }
     }
 #pragma unroll
     for (int u = 0; u < BVT; ++u) {
       const int e = tid + u * 256;
-      if (e < 2 * BO) { const int hl = e / BO, r = e % BO; Bs[buf][hl][r / BN][r % BN] = rb[u]; }
+      if ((2 * BO) % 256 == 0 || e < 2 * BO) {
+        const int hl = e / BO, r = e % BO;
+        Bs[buf][hl][r / BN][r % BN] = rb[u];
+      }
     }
   };
 
   constexpr int BK = 8 * BKQ;
   int s = 0, k0 = 0;
   while (s < nseg && item_seg8(g.ops, ti, tj, tk, s).K <= 0) ++s;
-  if (s < nseg) { gload(s, k0); sstore(0); }
+  if (s < nseg) { setseg(s); gload(); sstore(0); }
   __syncthreads();
   int cur = 0;
   const int arow = wm * MBW * BR + (lane & 31);
@@ -160,9 +178,13 @@ __global__ __launch_bounds__(256) void k_tgemm_bf16(GemmArgs16 g) {
   const int q = lane >> 5;
   while (s < nseg) {
     k0 += BK;
-    while (s < nseg && k0 >= item_seg8(g.ops, ti, tj, tk, s).K) { ++s; k0 = 0; }
+    if (k0 >= K) {
+      ++s; k0 = 0;
+      while (s < nseg && item_seg8(g.ops, ti, tj, tk, s).K <= 0) ++s;
+      if (s < nseg) setseg(s);
+    }
     const bool more = s < nseg;
-    if (more) gload(s, k0);
+    if (more) gload();
     bf16x8 bh[NBW], bl[NBW];
 #pragma unroll
     for (int nb = 0; nb < NBW; ++nb) {
