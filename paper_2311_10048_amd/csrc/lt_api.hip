@@ -181,7 +181,7 @@ struct Plan {
   Buf BvvP[2], BovR[2], BovP64[2], BooP64[2];
   Buf As[2], Tp[2], T2T[2], GamT[2], U[2];
   Buf LmixT[2], Mst[2], Mts[2], Tmix[2], ZpT[2], TmT[2], OOT[2];
-  Buf OVab, e_items, trip, dst, order, firstcnt;
+  Buf OVab, e_items, trip, dst, order, firstcnt, segtab;
   // adjoint pass: extra operands, mirrors (gradients of the prepared
   // operands, same layouts), FP64 four-index integral gradients, descriptors
   bool bwd = false;
@@ -379,6 +379,7 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
   take(P.dst, 4 * std::max<int64_t>(L.total, 1));
   take(P.order, 4 * std::max<int64_t>(L.total, 1));
   take(P.firstcnt, 4 * 8);
+  if (P.bf) take(P.segtab, 2 * 6 * sizeof(lt::Seg8) * (size_t)std::max<int64_t>(L.total, 1));
   P.small = off;
   P.small_base = P.big;
   P.total = P.big + P.small;
@@ -745,13 +746,29 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
       o8.Tmx2h = H(Plan::Tmx28); o8.Tmx2l = Lo(Plan::Tmx28); o8.ZpTh = H(Plan::ZpT8); o8.ZpTl = Lo(Plan::ZpT8);
       o8.TmTh = H(Plan::TmT8); o8.TmTl = Lo(Plan::TmT8); o8.OOTh = H(Plan::OOT8); o8.OOTl = Lo(Plan::OOT8);
     }
+    // BF16 modes: segment descriptors of every item of the block, per output
+    // layout (S or G in the first half of the table, Y in the second)
+    lt::Seg8* tab0 = P.bf ? at_small<lt::Seg8>(ws, P, P.segtab) : nullptr;
+    lt::Seg8* tab1 = P.bf ? tab0 + 6 * std::max<int64_t>(L.total, 1) : nullptr;
+    if (P.bf) {
+      lt::ItemOps8 t8 = o8;
+      t8.items = d_trip + 3 * fc[b];
+      t8.kind = mixed ? 1 : 0;
+      HIPCHK(lt::launch_seg8_table(t8, (int32_t)nblk, tab0 + 6 * (int64_t)fc[b], st));
+      if (mixed) {
+        t8.kind = 2;
+        HIPCHK(lt::launch_seg8_table(t8, (int32_t)nblk, tab1 + 6 * (int64_t)fc[b], st));
+      }
+    }
     // contraction of one batch: FP64/FP32 matrix cores, or split BF16
     auto contract = [&](lt::GemmArgs<T>& g) -> hipError_t {
       if (!P.bf) return lt::launch_gemm<T>(g, st);
       lt::GemmArgs16 h{};
       h.M = g.M; h.N = g.N; h.nbatch = g.nbatch; h.nprod = P.bf;
       h.out = (float*)g.out; h.obs = g.obs; h.ldo = g.s_mr;
-      h.ops = o8; h.ops.kind = g.ops.kind; h.ops.items = g.ops.items;
+      h.kind = g.ops.kind;
+      const int64_t first_item = (g.ops.items - d_trip) / 3;     // index in the block-ordered item list
+      h.tab = (g.ops.kind == 2 ? tab1 : tab0) + 6 * first_item;
       return lt::launch_gemm_bf16(h, st);
     };
     const int64_t nb = P.nb[b];

@@ -65,8 +65,15 @@ __device__ inline bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast(bf16x8, 
 
 constexpr int GI = 8;   // items per column-tile group (measured: about 10% over one)
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4 guint4;   // global-memory octet
+
+// Two work-groups per CU (two waves per SIMD): the compiler keeps the 160
+// accumulators and the staged loads within 256 registers per lane, spilling
+// a few address words; measured about 20% faster than one work-group per CU.
+
 template <int MBW, int NBW, int WM, int NPROD>
-__global__ __launch_bounds__(256) void k_tgemm_bf16(GemmArgs16 g) {
+__global__ __launch_bounds__(256, 2) void k_tgemm_bf16(GemmArgs16 g) {
   constexpr int BR = 32, BC = 32, BKQ = 2;      // 16 k per stage
   constexpr int WN = 4 / WM;
   constexpr int BM = WM * MBW * BR, BN = WN * NBW * BC;
@@ -92,9 +99,8 @@ __global__ __launch_bounds__(256) void k_tgemm_bf16(GemmArgs16 g) {
   const int batch = b * GI + ig;
   if (batch >= g.nbatch) return;                 // whole work-group: before any barrier
   const int m0 = mtile * BM, n0 = ntile * BN;
-  const int32_t* it = g.ops.items + 3 * batch;
-  const int64_t ti = it[0], tj = it[1], tk = it[2];
-  const int nseg = g.ops.kind == 2 ? 4 : 6;
+  const Seg8* tab = g.tab + (int64_t)batch * 6;   // read with wave-uniform (scalar) loads
+  const int nseg = g.kind == 2 ? 4 : 6;
 
   f32x16 acc[MBW][NBW];
 #pragma unroll
@@ -110,25 +116,31 @@ __global__ __launch_bounds__(256) void k_tgemm_bf16(GemmArgs16 g) {
   // output shape only feed discarded outputs.  Each thread keeps 32-bit
   // offsets (in octets) from the segment's wave-uniform bases, set when the
   // segment changes and advanced by a constant per stage.
+  // The lo array of every tensor lies after its hi array in the workspace
+  // (less than 2^32 octets apart, checked by the planner), so a thread's
+  // offset from the hi base covers both halves and no base is selected per
+  // load.
   uint32_t oa[AVT], ob[BVT];
-  const uint4 *Lh = nullptr, *Ll = nullptr, *Rh = nullptr, *Rl = nullptr;
+  guint4 *Lh = nullptr, *Rh = nullptr;
   uint32_t sa = 0, sb = 0, flip = 0;
   int K = 0;
   auto setseg = [&](int s) {
-    const Seg8 sg = item_seg8(g.ops, ti, tj, tk, s);
+    const Seg8 sg = tab[s];
     K = sg.K;
     flip = sg.sign < 0.f ? 0x80008000u : 0u;
     sa = (uint32_t)(2 * sg.lq / 8); sb = (uint32_t)(2 * sg.rq / 8);
-    Lh = (const uint4*)sg.Lh; Ll = (const uint4*)sg.Ll; Rh = (const uint4*)sg.Rh; Rl = (const uint4*)sg.Rl;
+    Lh = (guint4*)sg.Lh; Rh = (guint4*)sg.Rh;
+    const uint32_t dA = (uint32_t)((const uint4*)sg.Ll - (const uint4*)sg.Lh);
+    const uint32_t dB = (uint32_t)((const uint4*)sg.Rl - (const uint4*)sg.Rh);
 #pragma unroll
     for (int u = 0; u < AVT; ++u) {
-      const int r = (tid + u * 256) % AO;
-      oa[u] = (uint32_t)((r / BM) * (sg.lq / 8) + m0 + r % BM);
+      const int e = tid + u * 256, r = e % AO;
+      oa[u] = (uint32_t)((r / BM) * (sg.lq / 8) + m0 + r % BM) + (e >= AO ? dA : 0u);
     }
 #pragma unroll
     for (int u = 0; u < BVT; ++u) {
-      const int r = (tid + u * 256) % BO;
-      ob[u] = (uint32_t)((r / BN) * (sg.rq / 8) + n0 + r % BN);
+      const int e = tid + u * 256, r = e % BO;
+      ob[u] = (uint32_t)((r / BN) * (sg.rq / 8) + n0 + r % BN) + (e >= BO ? dB : 0u);
     }
   };
   uint4 ra[AVT], rb[BVT];
@@ -136,13 +148,13 @@ __global__ __launch_bounds__(256) void k_tgemm_bf16(GemmArgs16 g) {
 #pragma unroll
     for (int u = 0; u < AVT; ++u) {
       const int e = tid + u * 256;
-      if ((2 * AO) % 256 == 0 || e < 2 * AO) ra[u] = (e >= AO ? Ll : Lh)[oa[u]];
+      if ((2 * AO) % 256 == 0 || e < 2 * AO) ra[u] = __builtin_bit_cast(uint4, Lh[oa[u]]);
       oa[u] += sa;
     }
 #pragma unroll
     for (int u = 0; u < BVT; ++u) {
       const int e = tid + u * 256;
-      if ((2 * BO) % 256 == 0 || e < 2 * BO) rb[u] = (e >= BO ? Rl : Rh)[ob[u]];
+      if ((2 * BO) % 256 == 0 || e < 2 * BO) rb[u] = __builtin_bit_cast(uint4, Rh[ob[u]]);
       ob[u] += sb;
     }
   };
@@ -169,7 +181,7 @@ __global__ __launch_bounds__(256) void k_tgemm_bf16(GemmArgs16 g) {
 
   constexpr int BK = 8 * BKQ;
   int s = 0, k0 = 0;
-  while (s < nseg && item_seg8(g.ops, ti, tj, tk, s).K <= 0) ++s;
+  while (s < nseg && tab[s].K <= 0) ++s;
   if (s < nseg) { setseg(s); gload(); sstore(0); }
   __syncthreads();
   int cur = 0;
@@ -180,7 +192,7 @@ __global__ __launch_bounds__(256) void k_tgemm_bf16(GemmArgs16 g) {
     k0 += BK;
     if (k0 >= K) {
       ++s; k0 = 0;
-      while (s < nseg && item_seg8(g.ops, ti, tj, tk, s).K <= 0) ++s;
+      while (s < nseg && tab[s].K <= 0) ++s;
       if (s < nseg) setseg(s);
     }
     const bool more = s < nseg;
@@ -223,6 +235,26 @@ __global__ __launch_bounds__(256) void k_tgemm_bf16(GemmArgs16 g) {
         if (m < g.M) out[(int64_t)m * g.ldo + n] = acc[mb][nb][r];
       }
   }
+}
+
+__global__ __launch_bounds__(256) void k_seg8_table(ItemOps8 ops, int32_t nitems, Seg8* tab) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)nitems * 6) return;
+  const int64_t n = e / 6;
+  const int sidx = (int)(e % 6);
+  const int nseg = ops.kind == 2 ? 4 : 6;
+  const int32_t* it = ops.items + 3 * n;
+  Seg8 sg{};
+  if (sidx < nseg) sg = item_seg8(ops, it[0], it[1], it[2], sidx);
+  else sg.K = 0;
+  tab[e] = sg;
+}
+
+hipError_t launch_seg8_table(const ItemOps8& ops, int32_t nitems, Seg8* tab, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  const int64_t n = (int64_t)nitems * 6;
+  hipLaunchKernelGGL(k_seg8_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ops, nitems, tab);
+  return hipGetLastError();
 }
 
 template <int MBW, int NBW, int WM, int NPROD>

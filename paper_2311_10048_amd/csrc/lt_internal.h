@@ -131,10 +131,14 @@ struct GemmArgs16 {
   int32_t M, N, nbatch, mt, nt;
   int32_t nprod;                         // 3: hi*hi + hi*lo + lo*hi, 1: hi*hi
   float* out; int64_t obs, ldo;
-  ItemOps8 ops;
+  int32_t kind;                          // 0: S, 1: G, 2: Y (number of segments 6, 6, 4)
+  const Seg8* tab;                       // [nbatch][6] segment descriptors of the launch's items
 };
 
 hipError_t launch_gemm_bf16(const GemmArgs16& g, hipStream_t s);
+// tab[n][s] = descriptor of segment s of item n (ops.kind, ops.items), s < 6;
+// unused slots get K = 0.
+hipError_t launch_seg8_table(const ItemOps8& ops, int32_t nitems, Seg8* tab, hipStream_t s);
 
 // hi/lo octet tensors from FP32 in[b*ibs + k*iks + c], c < ncol, k < K
 // (zero elsewhere, rows padded to 16).
