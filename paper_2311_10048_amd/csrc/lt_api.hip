@@ -385,6 +385,17 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
   P.total = P.big + P.small;
 }
 
+// The BF16 contraction addresses a tensor's lo half through 32-bit octet
+// offsets from its hi half.
+int check_plan(const Plan& P) {
+  if (!P.bf) return LT_OK;
+  for (int s = 0; s < 2; ++s)
+    for (int t8 = 0; t8 < Plan::NT8; ++t8)
+      if (P.O8h[s][t8].bytes && P.O8l[s][t8].off - P.O8h[s][t8].off >= (size_t(1) << 36))
+        return fail(LT_ESHAPE, "BF16 operand tensor too large (over 64 GiB per half)");
+  return LT_OK;
+}
+
 void log_plan(const Plan& P) {
   if (!getenv("LTRIPLES_LOG")) return;
   fprintf(stderr, "[ltriples] plan prec=%d total=%zu bytes\n", P.prec, P.total);
@@ -1580,6 +1591,8 @@ int ltriples_energy(const ltriples_domain* d, int32_t precision, const ltriples_
   Plan P;
   plan_domain(d, precision, o, L, P);
   log_plan(P);
+  r = check_plan(P);
+  if (r) return r;
   bool own = false;
   if (ws == nullptr) {
     HIPCHK(hipMalloc(&ws, P.total));
@@ -1882,6 +1895,8 @@ int plan_batch(const ltriples_domain* ds, int32_t ndom, int32_t precision, const
   for (int32_t d = 0; d < ndom; ++d) {
     build_items(dims_of(&ds[d]), nullptr, B.L[d]);
     plan_domain(&ds[d], precision, o, B.L[d], B.P[d]);
+    const int r = check_plan(B.P[d]);
+    if (r) return r;
     big = std::max(big, B.P[d].big);
   }
   size_t off = align256(big);
