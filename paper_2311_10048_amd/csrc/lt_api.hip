@@ -227,7 +227,17 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
     P.ldoo[s] = ld4(D.o[s] * D.o[s]);
   }
   size_t off = 0;
+  P.bf = prec == LT_BF16X3 ? 3 : (prec == LT_BF16 ? 1 : 0);
+  // BF16 modes keep only the split (octet) copies of the contraction
+  // operands: every FP32 operand tensor is built in one shared staging
+  // buffer and split before the next one is built.
+  std::vector<Buf*> staged;
   auto take = [&](Buf& b, size_t bytes) { b.off = off; b.bytes = bytes; off = align256(off + bytes); };
+  auto take_op = [&](Buf& b, size_t bytes) {
+    if (!P.bf) { take(b, bytes); return; }
+    b.bytes = bytes;
+    staged.push_back(&b);
+  };
   const size_t ts = P.ts;
   const int64_t Q = D.Q;
   for (int s = 0; s < 2; ++s) {
@@ -240,23 +250,30 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
       take(P.BooP64[s], 8 * Q * P.ldoo[s]);
     }
     if (P.need_as[s]) {
-      take(P.As[s], ts * os * vs * P.ldnp[s]);
-      take(P.Tp[s], ts * os * os * P.ldnp[s]);
-      take(P.T2T[s], ts * os * os * vs * P.ldv[s]);
-      take(P.GamT[s], ts * os * os * os * P.ldv[s]);
+      take_op(P.As[s], ts * os * vs * P.ldnp[s]);
+      take_op(P.Tp[s], ts * os * os * P.ldnp[s]);
+      take_op(P.T2T[s], ts * os * os * vs * P.ldv[s]);
+      take_op(P.GamT[s], ts * os * os * os * P.ldv[s]);
       take(P.U[s], 8 * os * os * vs * P.ldv[s]);
     }
     if (P.need_mix[s]) {
       const int t = 1 - s;
       const int64_t ot = D.o[t], vt = D.v[t];
-      take(P.LmixT[s], ts * os * ot * vt * P.ldv[s]);
-      take(P.Mst[s], ts * os * vt * P.ldcb[s]);
-      take(P.Mts[s], ts * ot * vs * P.ldcb[s]);
-      take(P.Tmix[s], ts * os * ot * P.ldcb[s]);
-      take(P.ZpT[s], ts * os * ot * ot * P.ldv[s]);
-      take(P.TmT[s], ts * os * ot * vs * P.ldv[t]);
-      take(P.OOT[s], ts * ot * os * os * P.ldv[t]);
+      take_op(P.LmixT[s], ts * os * ot * vt * P.ldv[s]);
+      take_op(P.Mst[s], ts * os * vt * P.ldcb[s]);
+      take_op(P.Mts[s], ts * ot * vs * P.ldcb[s]);
+      take_op(P.Tmix[s], ts * os * ot * P.ldcb[s]);
+      take_op(P.ZpT[s], ts * os * ot * ot * P.ldv[s]);
+      take_op(P.TmT[s], ts * os * ot * vs * P.ldv[t]);
+      take_op(P.OOT[s], ts * ot * os * os * P.ldv[t]);
     }
+  }
+  if (!staged.empty()) {
+    size_t mx = 0;
+    for (Buf* b : staged) mx = std::max(mx, b->bytes);
+    Buf stage;
+    take(stage, mx);
+    for (Buf* b : staged) b->off = stage.off;
   }
   if (P.any_mix) take(P.OVab, 8 * D.o[0] * D.v[0] * D.o[1] * D.v[1]);
   if (bwd) {
@@ -291,7 +308,6 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
       if (P.need_as[s]) take(P.dOVOV[s], 8 * D.o[s] * D.v[s] * P.ldov[s]);
     if (P.any_mix) take(P.dOVOV[2], 8 * D.o[0] * D.v[0] * P.ldov[1]);
   }
-  P.bf = prec == LT_BF16X3 ? 3 : (prec == LT_BF16 ? 1 : 0);
   if (P.bf) {
     auto k16 = [](int64_t k) { return (k + 15) & ~int64_t(15); };
     auto take8 = [&](int s, int t, int64_t nblk, int64_t K, int64_t ld) {
@@ -490,6 +506,33 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
   const double* Boo[2] = {d->Boo_a, d->Boo_b};
   const double* T2ss[2] = {d->t2aa, d->t2bb};
   char* scr = (char*)ws + P.scratch.off;
+  // BF16 modes: split one freshly built FP32 operand tensor into its hi/lo
+  // octet copies (the FP32 tensors share one staging buffer)
+  auto split_op = [&](int s, int t8) -> hipError_t {
+    if (!P.bf) return hipSuccess;
+    const int t = 1 - s;
+    const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
+    const int64_t lv = P.ldv[s], lvt = P.ldv[t], lp = P.ldnp[s], lc = P.ldcb[s], np = npair(vs);
+    auto sp = [&](int64_t nblk, int64_t K, int64_t ld, int64_t ncol, const Buf& in, int64_t ibs,
+                  int64_t iks) -> hipError_t {
+      return lt::launch_split8(at<lt::bf16_t>(ws, P.O8h[s][t8]), at<lt::bf16_t>(ws, P.O8l[s][t8]), nblk,
+                               (int32_t)K, ld, (int32_t)ncol, at<float>(ws, in), ibs, iks, st);
+    };
+    switch (t8) {
+      case Plan::T2T8: return sp(os * os, vs, lv, vs, P.T2T[s], vs * lv, lv);
+      case Plan::As8: return sp(os, vs, lp, np, P.As[s], vs * lp, lp);
+      case Plan::GamT8: return sp(os * os, os, lv, vs, P.GamT[s], os * lv, lv);
+      case Plan::Tp8: return sp(os, os, lp, np, P.Tp[s], os * lp, lp);
+      case Plan::LmixT8: return sp(os * ot, vt, lv, vs, P.LmixT[s], vt * lv, lv);
+      case Plan::Mst8: return sp(os, vt, lc, vt * vs, P.Mst[s], vt * lc, lc);
+      case Plan::Mts8: return sp(ot, vs, lc, vt * vs, P.Mts[s], vs * lc, lc);
+      case Plan::Tmix8: return sp(os, ot, lc, vt * vs, P.Tmix[s], ot * lc, lc);
+      case Plan::Tmx28: return sp(ot, os, lc, vt * vs, P.Tmix[s], lc, ot * lc);
+      case Plan::ZpT8: return sp(os * ot, ot, lv, vs, P.ZpT[s], ot * lv, lv);
+      case Plan::TmT8: return sp(os * ot, vs, lvt, vt, P.TmT[s], vs * lvt, lvt);
+      default: return sp(ot * os, os, lvt, vt, P.OOT[s], os * lvt, lvt);
+    }
+  };
   // --- 1. DF factor layouts --------------------------------------------------
   for (int s = 0; s < 2; ++s) {
     if (!P.BvvP[s].bytes) continue;
@@ -537,6 +580,7 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
     const double* oo = OO[s][s];
     HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.GamT[s]), o * o * lv, o * lv, lv, o, o, o, v,
                                         oo, 1, v * o * o, o, o * o, oo, v * o * o, 1, o, o * o, st));
+    HIPCHK(split_op(s, Plan::GamT8));
   }
   if (P.any_mix) {
     const int64_t oa = D.o[0], va = D.v[0], ob = D.o[1], vb = D.v[1];
@@ -551,10 +595,12 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
     HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.ZpT[s]), ot * ot * P.ldv[s], ot * P.ldv[s], P.ldv[s],
                                         os, ot, ot, vs, OO[s][t], vs * ot * ot, 1, ot, ot * ot,
                                         nullptr, 0, 0, 0, 0, st));
+    HIPCHK(split_op(s, Plan::ZpT8));
     // OOT[K][j][m][C] = OO_ts[K][C][j][m]
     HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.OOT[s]), os * os * P.ldv[t], os * P.ldv[t], P.ldv[t],
                                         ot, os, os, vt, OO[t][s], vt * os * os, os, 1, os * os,
                                         nullptr, 0, 0, 0, 0, st));
+    HIPCHK(split_op(s, Plan::OOT8));
   }
 
   // --- 3. amplitude operands ----------------------------------------------------
@@ -565,9 +611,11 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
     // T2T[i][j][e][a] = t2[i][j][a][e]
     HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.T2T[s]), o * v * lv, v * lv, lv, o, o, v, v,
                                         T2ss[s], o * v * v, v * v, 1, v, nullptr, 0, 0, 0, 0, st));
+    HIPCHK(split_op(s, Plan::T2T8));
     // Tp[i][m][p(a<b)] = t2[i][m][a][b]
     HIPCHK(lt::launch_pack_pairs<double, T>(at<T>(ws, P.Tp[s]), P.ldnp[s], o * o, (int32_t)v, T2ss[s],
                                             v * v, v, 1, false, st));
+    HIPCHK(split_op(s, Plan::Tp8));
   }
   // mixed amplitude t^{xY}_{pQ} (p,x of pair spin; Q,Y of odd spin): strides (p, Q, x, Y)
   int64_t mstr[2][4] = {{ob * va * vb, va * vb, vb, 1}, {va * vb, ob * va * vb, 1, vb}};
@@ -579,12 +627,16 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
     // LmixT[i][K][E][a] = t^{aE}_{iK}
     HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.LmixT[s]), ot * vt * P.ldv[s], vt * P.ldv[s], P.ldv[s],
                                         os, ot, vt, vs, d->t2ab, m[0], m[1], m[3], m[2], nullptr, 0, 0, 0, 0, st));
+    HIPCHK(split_op(s, Plan::LmixT8));
     // Tmix[i][K][C*vs+b] = t^{bC}_{iK}
     HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.Tmix[s]), ot * P.ldcb[s], P.ldcb[s], vs,
                                         os, ot, vt, vs, d->t2ab, m[0], m[1], m[3], m[2], nullptr, 0, 0, 0, 0, st));
+    HIPCHK(split_op(s, Plan::Tmix8));
+    HIPCHK(split_op(s, Plan::Tmx28));
     // TmT[i][K][e][C] = t^{eC}_{iK}
     HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.TmT[s]), ot * vs * P.ldv[t], vs * P.ldv[t], P.ldv[t],
                                         os, ot, vs, vt, d->t2ab, m[0], m[1], m[2], m[3], nullptr, 0, 0, 0, 0, st));
+    HIPCHK(split_op(s, Plan::TmT8));
   }
 
   // --- 4. (ov|vv) slabs ------------------------------------------------------------
@@ -607,6 +659,7 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
     // As[i][e][p(b<c)] = Kx[i][e][b][c] - Kx[i][e][c][b]
     HIPCHK(lt::launch_pack_pairs<T, T>(at<T>(ws, P.As[s]), P.ldnp[s], o * v, (int32_t)v, Kx, v * lv, lv, 1,
                                        true, st));
+    HIPCHK(split_op(s, Plan::As8));
   }
   for (int s = 0; s < 2; ++s) {
     if (!P.need_mix[s]) continue;
@@ -615,39 +668,13 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
     // Mst[j][E][C*vs+b] = (jb|EC): rows (E,C), cols b
     HIPCHK(gemmT(vt * vt, vs, os, at<T>(ws, P.BvvP[t]), P.ldvv[t], 0, at<T>(ws, P.BovR[s]), P.ldv[s],
                  Q * P.ldv[s], at<T>(ws, P.Mst[s]), vt * lc, lc, vs, (int32_t)vt, 0, 1, 0));
+    HIPCHK(split_op(s, Plan::Mst8));
     // Mts[K][e][C*vs+b] = (be|KC): rows C, cols (e,b)
     HIPCHK(gemmT(vt, vs * vs, ot, at<T>(ws, P.BovR[t]), P.ldv[t], Q * P.ldv[t], at<T>(ws, P.BvvP[s]),
                  P.ldvv[s], 0, at<T>(ws, P.Mts[s]), vs * lc, 0, vs, 0, lc, 1, (int32_t)vs));
+    HIPCHK(split_op(s, Plan::Mts8));
   }
 
-  if (P.bf) {
-    auto split = [&](int s, int t8, int64_t nblk, int64_t K, int64_t ld, int64_t ncol, const T* in, int64_t ibs,
-                     int64_t iks) -> hipError_t {
-      return lt::launch_split8(at<lt::bf16_t>(ws, P.O8h[s][t8]), at<lt::bf16_t>(ws, P.O8l[s][t8]), nblk, (int32_t)K,
-                               ld, (int32_t)ncol, (const float*)in, ibs, iks, st);
-    };
-    for (int s = 0; s < 2; ++s) {
-      const int t = 1 - s;
-      const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
-      const int64_t lv = P.ldv[s], lvt = P.ldv[t], lp = P.ldnp[s], lc = P.ldcb[s], np = npair(vs);
-      if (P.need_as[s]) {
-        HIPCHK(split(s, Plan::T2T8, os * os, vs, lv, vs, at<T>(ws, P.T2T[s]), vs * lv, lv));
-        HIPCHK(split(s, Plan::As8, os, vs, lp, np, at<T>(ws, P.As[s]), vs * lp, lp));
-        HIPCHK(split(s, Plan::GamT8, os * os, os, lv, vs, at<T>(ws, P.GamT[s]), os * lv, lv));
-        HIPCHK(split(s, Plan::Tp8, os, os, lp, np, at<T>(ws, P.Tp[s]), os * lp, lp));
-      }
-      if (P.need_mix[s]) {
-        HIPCHK(split(s, Plan::LmixT8, os * ot, vt, lv, vs, at<T>(ws, P.LmixT[s]), vt * lv, lv));
-        HIPCHK(split(s, Plan::Mst8, os, vt, lc, vt * vs, at<T>(ws, P.Mst[s]), vt * lc, lc));
-        HIPCHK(split(s, Plan::Mts8, ot, vs, lc, vt * vs, at<T>(ws, P.Mts[s]), vs * lc, lc));
-        HIPCHK(split(s, Plan::Tmix8, os, ot, lc, vt * vs, at<T>(ws, P.Tmix[s]), ot * lc, lc));
-        HIPCHK(split(s, Plan::Tmx28, ot, os, lc, vt * vs, at<T>(ws, P.Tmix[s]), lc, ot * lc));
-        HIPCHK(split(s, Plan::ZpT8, os * ot, ot, lv, vs, at<T>(ws, P.ZpT[s]), ot * lv, lv));
-        HIPCHK(split(s, Plan::TmT8, os * ot, vs, lvt, vt, at<T>(ws, P.TmT[s]), vs * lvt, lvt));
-        HIPCHK(split(s, Plan::OOT8, ot * os, os, lvt, vt, at<T>(ws, P.OOT[s]), os * lvt, lvt));
-      }
-    }
-  }
   if (P.bwd) {
     // adjoint pass: FP64 padded Bvv for the DF back-contraction; t1, f_ov rows;
     // <qr||bc> pair-packed; (jb|KC) in the mixed output layout
