@@ -369,8 +369,8 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
       nt = n * (n + 1) * (n + 2) / 6;
     } else {
       outb = ts * (size_t)(vs * P.ldcb[s] + vt * P.ldnp[s]);
-      const int64_t ns = cdiv(vs, lt::ET), nt_ = cdiv(vt, lt::ET);
-      nt = ns * (ns + 1) / 2 * nt_;
+      const int64_t ns = cdiv(vs, lt::ET);
+      nt = ns * (ns + 1) / 2;          // one partial per (a-tile <= b-tile) pair
     }
     P.ntile[b] = nt;
     P.o1[b] = align256(ts * (size_t)(blk_mixed(b) ? vs * P.ldcb[s] : vs * P.ldnp[s]));

@@ -44,6 +44,15 @@ __device__ inline void tri_decode(int t, int& A, int& B, int& C) {
   A = t; B = b; C = c;
 }
 
+// Linear work-group id -> logical id such that consecutive logical ids run on
+// one XCD (the dispatcher deals work-groups round-robin over the 8 XCDs).
+// Neighbouring tiles read the two 64-byte halves of the same 128-byte lines,
+// which then meet in that XCD's L2.
+__device__ inline int xcd_logical(int w, int total) {
+  const int x = w & 7, q = total >> 3, r = total & 7;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + (w >> 3);
+}
+
 constexpr int SROW = ET * ET + 1;   // padded LDS row for [ta][tc*16+tb]
 
 // 1/d by Newton-Raphson from the hardware reciprocal approximation: each step
@@ -69,8 +78,10 @@ __global__ __launch_bounds__(256) void k_epi_same(EpiSame<T> a) {
 
   const int tid = threadIdx.x;
   int TA, TB, TC;
-  tri_decode(blockIdx.x, TA, TB, TC);
-  const int item = blockIdx.y;
+  const int L = xcd_logical(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int tix = L % gridDim.x;
+  tri_decode(tix, TA, TB, TC);
+  const int item = L / gridDim.x;
   const int32_t* it = a.items + 3 * item;
   const int occ[3] = {it[0], it[1], it[2]};
   const int v = a.v;
@@ -152,9 +163,16 @@ __global__ __launch_bounds__(256) void k_epi_same(EpiSame<T> a) {
       edt += wd * vf;
     }
   }
-  block_write3(e4, est, edt, a.part + ((int64_t)item * a.ntri + blockIdx.x) * 3);
+  block_write3(e4, est, edt, a.part + ((int64_t)item * a.ntri + tix) * 3);
 }
 
+// Mixed blocks: one work-group per (item, a-tile <= b-tile) walks all C
+// tiles; the operands of the next C tile are loaded into registers while the
+// current one is computed (software pipelining), and the C-independent
+// operands (t1, f_ov, e_vir of the a-tile, <ij||ab>, t^{ab}_{ij}) are staged
+// once.  Thread (b, C) of a tile loops over the tile's a < b; each thread's
+// FP64 partial sums run over all C tiles and one partial per work-group is
+// written.
 template <typename T>
 __global__ __launch_bounds__(256) void k_epi_mixed(EpiMixed<T> a) {
   __shared__ T Gb[ET][SROW];        // G[b][C*v+a]
@@ -164,40 +182,25 @@ __global__ __launch_bounds__(256) void k_epi_mixed(EpiMixed<T> a) {
   __shared__ double t1ai[ET], t1aj[ET], fai[ET], faj[ET], eva[ET];
 
   const int tid = threadIdx.x;
-  const int tile = blockIdx.x;
-  const int TC = tile % a.ntt, pi = tile / a.ntt;
+  const int L = xcd_logical(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int pi = L % gridDim.x;
   int TB = 0;
   while ((TB + 1) * (TB + 2) / 2 <= pi) ++TB;
   const int TA = pi - TB * (TB + 1) / 2;
-  const int item = blockIdx.y;
+  const int item = L / gridDim.x;
   const int32_t* it = a.items + 3 * item;
   const int i = it[0], j = it[1], K = it[2];
   const int vs = a.v_s, vt = a.v_t;
-  const int a0 = TA * ET, b0 = TB * ET, c0 = TC * ET;
+  const int a0 = TA * ET, b0 = TB * ET;
   const T* G = a.G + (int64_t)item * a.g_item;
   const T* Y = a.Y + (int64_t)item * a.y_item;
   const int64_t lc = a.ld_cb, lp = a.ld_np;
 
-  for (int e = tid; e < ET * ET * ET; e += 256) {
-    const int ta = e & 15, tb = (e >> 4) & 15, tc = e >> 8;
-    const int aa = a0 + ta, bb = b0 + tb, cc = c0 + tc;
-    T x = 0, y = 0;
-    if (aa < vs && bb < vs && cc < vt) {
-      x = G[bb * lc + (int64_t)cc * vs + aa];
-      if (aa < bb) y = Y[cc * lp + (int64_t)bb * (bb - 1) / 2 + aa];
-    }
-    Gb[ta][tc * ET + tb] = x;
-    Yl[ta][tc * ET + tb] = y;
-  }
-  for (int e = tid; e < ET * ET; e += 256) {
-    const int ta = e & 15, tx = e >> 4;
-    const int aa = a0 + ta, cc = c0 + tx, bb = b0 + tx;
-    const bool ac = aa < vs && cc < vt, ab = aa < vs && bb < vs;
-    OVj[ta][tx] = ac ? a.ov[j * a.ov_o + aa * a.ov_v + K * a.ov_O + cc * a.ov_V] : 0.0;
-    OVi[ta][tx] = ac ? a.ov[i * a.ov_o + aa * a.ov_v + K * a.ov_O + cc * a.ov_V] : 0.0;
-    Tmj[ta][tx] = ac ? a.tm[j * a.tm_o + aa * a.tm_v + K * a.tm_O + cc * a.tm_V] : 0.0;
-    Tmi[ta][tx] = ac ? a.tm[i * a.tm_o + aa * a.tm_v + K * a.tm_O + cc * a.tm_V] : 0.0;
+  // C-independent operands
+  {
     const int64_t ij = (int64_t)i * a.o_s + j;
+    const int tx = tid & 15, ta = tid >> 4, aa = a0 + ta, bb = b0 + tx;
+    const bool ab = aa < vs && bb < vs;
     Uab[tx][ta] = ab ? a.U[(ij * vs + aa) * a.ld_vs + bb] : 0.0;
     T2ab[tx][ta] = ab ? a.t2ss[(ij * vs + aa) * vs + bb] : 0.0;
   }
@@ -210,40 +213,99 @@ __global__ __launch_bounds__(256) void k_epi_mixed(EpiMixed<T> a) {
     faj[tid] = ok ? a.f_s[(int64_t)j * vs + aa] : 0.0;
     eva[tid] = ok ? a.ev_s[aa] : 0.0;
   }
-  __syncthreads();
-
   const int tb = tid & 15, tc = tid >> 4;
-  const int b = b0 + tb, C = c0 + tc;
-  double e4 = 0.0, est = 0.0, edt = 0.0;
-  if (b < vs && C < vt) {
-    const double OVjb = a.ov[j * a.ov_o + b * a.ov_v + K * a.ov_O + C * a.ov_V];
-    const double OVib = a.ov[i * a.ov_o + b * a.ov_v + K * a.ov_O + C * a.ov_V];
-    const double Tmjb = a.tm[j * a.tm_o + b * a.tm_v + K * a.tm_O + C * a.tm_V];
-    const double Tmib = a.tm[i * a.tm_o + b * a.tm_v + K * a.tm_O + C * a.tm_V];
-    const double t1bi = a.t1_s[(int64_t)i * vs + b], t1bj = a.t1_s[(int64_t)j * vs + b];
-    const double fbi = a.f_s[(int64_t)i * vs + b], fbj = a.f_s[(int64_t)j * vs + b];
-    const double t1C = a.t1_t[(int64_t)K * vt + C], fC = a.f_t[(int64_t)K * vt + C];
-    const double dbc = (a.eo_s[i] + a.eo_s[j] + a.eo_t[K]) - a.ev_s[b] - a.ev_t[C];
+  const int b = b0 + tb;
+  const bool brow = b < vs;
+  const double t1bi = brow ? a.t1_s[(int64_t)i * vs + b] : 0.0, t1bj = brow ? a.t1_s[(int64_t)j * vs + b] : 0.0;
+  const double fbi = brow ? a.f_s[(int64_t)i * vs + b] : 0.0, fbj = brow ? a.f_s[(int64_t)j * vs + b] : 0.0;
+  const double dob = (a.eo_s[i] + a.eo_s[j] + a.eo_t[K]) - (brow ? a.ev_s[b] : 0.0);
+  const int na = min(ET, b - a0);
+  // staging of one C tile: thread tid stages elements tid + 256*u of the
+  // permuted G block and of Y, one element of each small FP64 block, and its
+  // own direct-term run
+  const bool ovc = a.ov_V == 1, tmc = a.tm_V == 1;
+  const int ov_ta = ovc ? tid >> 4 : tid & 15, ov_tx = ovc ? tid & 15 : tid >> 4;
+  const int tm_ta = tmc ? tid >> 4 : tid & 15, tm_tx = tmc ? tid & 15 : tid >> 4;
+  T rg[ET], ry[ET], rd[ET];
+  double rovj, rovi, rtmj, rtmi, rOVjb, rOVib, rTmjb, rTmib, rt1C, rfC, revC;
+  auto fetch = [&](int TCn) {
+    const int c0 = TCn * ET;
+#pragma unroll
+    for (int u = 0; u < ET; ++u) {
+      const int e = tid + 256 * u;
+      const int ta = e & 15, tbb = (e >> 4) & 15, tcc = e >> 8;
+      const int aa = a0 + ta, bb = b0 + tbb, cc = c0 + tcc;
+      T x = 0, y = 0;
+      if (aa < vs && bb < vs && cc < vt) {
+        x = G[bb * lc + (int64_t)cc * vs + aa];
+        if (aa < bb) y = Y[cc * lp + (int64_t)bb * (bb - 1) / 2 + aa];
+      }
+      rg[u] = x;
+      ry[u] = y;
+    }
+    {
+      const int aa = a0 + ov_ta, cc = c0 + ov_tx;
+      const bool ac = aa < vs && cc < vt;
+      rovj = ac ? a.ov[j * a.ov_o + aa * a.ov_v + K * a.ov_O + cc * a.ov_V] : 0.0;
+      rovi = ac ? a.ov[i * a.ov_o + aa * a.ov_v + K * a.ov_O + cc * a.ov_V] : 0.0;
+    }
+    {
+      const int aa = a0 + tm_ta, cc = c0 + tm_tx;
+      const bool ac = aa < vs && cc < vt;
+      rtmj = ac ? a.tm[j * a.tm_o + aa * a.tm_v + K * a.tm_O + cc * a.tm_V] : 0.0;
+      rtmi = ac ? a.tm[i * a.tm_o + aa * a.tm_v + K * a.tm_O + cc * a.tm_V] : 0.0;
+    }
+    const int C = c0 + tc;
+    const bool ok = brow && C < vt;
+    rOVjb = ok ? a.ov[j * a.ov_o + b * a.ov_v + K * a.ov_O + C * a.ov_V] : 0.0;
+    rOVib = ok ? a.ov[i * a.ov_o + b * a.ov_v + K * a.ov_O + C * a.ov_V] : 0.0;
+    rTmjb = ok ? a.tm[j * a.tm_o + b * a.tm_v + K * a.tm_O + C * a.tm_V] : 0.0;
+    rTmib = ok ? a.tm[i * a.tm_o + b * a.tm_v + K * a.tm_O + C * a.tm_V] : 0.0;
+    rt1C = ok ? a.t1_t[(int64_t)K * vt + C] : 0.0;
+    rfC = ok ? a.f_t[(int64_t)K * vt + C] : 0.0;
+    revC = ok ? a.ev_t[C] : 0.0;
     const T* Grow = G + (int64_t)C * vs + b;
-    const int na = min(ET, b - a0);
-    T gd[ET];                        // direct-term operands, loaded in one burst
 #pragma unroll
-    for (int ta = 0; ta < ET; ++ta) gd[ta] = ta < na ? Grow[(a0 + ta) * lc] : (T)0;
+    for (int ta = 0; ta < ET; ++ta) rd[ta] = (ok && ta < na) ? Grow[(a0 + ta) * lc] : (T)0;
+  };
+
+  double e4 = 0.0, est = 0.0, edt = 0.0;
+  fetch(0);
+  for (int TC = 0; TC < a.ntt; ++TC) {
+    __syncthreads();                 // previous tile's LDS reads are done
 #pragma unroll
-    for (int ta = 0; ta < ET; ++ta) {
-      if (ta >= na) break;
-      const double w = (double)gd[ta] - (double)Gb[ta][tc * ET + tb] + (double)Yl[ta][tc * ET + tb];
-      const double vt1 = t1ai[ta] * OVjb - t1aj[ta] * OVib - t1bi * OVj[ta][tc] + t1bj * OVi[ta][tc]
-                         + t1C * Uab[tb][ta];
-      const double vfo = fai[ta] * Tmjb - faj[ta] * Tmib - fbi * Tmj[ta][tc] + fbj * Tmi[ta][tc]
-                         + fC * T2ab[tb][ta];
-      const double wd = w * rcp64(dbc - eva[ta]);
-      e4 += wd * w;
-      est += wd * vt1;
-      edt += wd * vfo;
+    for (int u = 0; u < ET; ++u) {
+      const int e = tid + 256 * u;
+      Gb[e & 15][(e >> 8) * ET + ((e >> 4) & 15)] = rg[u];
+      Yl[e & 15][(e >> 8) * ET + ((e >> 4) & 15)] = ry[u];
+    }
+    OVj[ov_ta][ov_tx] = rovj; OVi[ov_ta][ov_tx] = rovi;
+    Tmj[tm_ta][tm_tx] = rtmj; Tmi[tm_ta][tm_tx] = rtmi;
+    const double OVjb = rOVjb, OVib = rOVib, Tmjb = rTmjb, Tmib = rTmib, t1C = rt1C, fC = rfC;
+    const double dbc = dob - revC;
+    const bool ok = brow && TC * ET + tc < vt;
+    T gd[ET];
+#pragma unroll
+    for (int ta = 0; ta < ET; ++ta) gd[ta] = rd[ta];
+    __syncthreads();
+    if (TC + 1 < a.ntt) fetch(TC + 1);   // next tile's loads in flight during this tile's work
+    if (ok) {
+#pragma unroll
+      for (int ta = 0; ta < ET; ++ta) {
+        if (ta >= na) break;
+        const double w = (double)gd[ta] - (double)Gb[ta][tc * ET + tb] + (double)Yl[ta][tc * ET + tb];
+        const double vt1 = t1ai[ta] * OVjb - t1aj[ta] * OVib - t1bi * OVj[ta][tc] + t1bj * OVi[ta][tc]
+                           + t1C * Uab[tb][ta];
+        const double vfo = fai[ta] * Tmjb - faj[ta] * Tmib - fbi * Tmj[ta][tc] + fbj * Tmi[ta][tc]
+                           + fC * T2ab[tb][ta];
+        const double wd = w * rcp64(dbc - eva[ta]);
+        e4 += wd * w;
+        est += wd * vt1;
+        edt += wd * vfo;
+      }
     }
   }
-  block_write3(e4, est, edt, a.part + ((int64_t)item * a.ntiles + tile) * 3);
+  block_write3(e4, est, edt, a.part + ((int64_t)item * a.ntiles + pi) * 3);
 }
 
 // ---------------------------------------------------------------------------
@@ -486,6 +548,7 @@ hipError_t launch_epi_same(const EpiSame<T>& a, int32_t nitems, hipStream_t s) {
 template <typename T>
 hipError_t launch_epi_mixed(const EpiMixed<T>& a, int32_t nitems, hipStream_t s) {
   if (nitems <= 0 || a.ntiles <= 0) return hipSuccess;
+  // one work-group per (a-tile <= b-tile) pair; ntiles = that pair count
   hipLaunchKernelGGL((k_epi_mixed<T>), dim3(a.ntiles, nitems), dim3(256), 0, s, a);
   return hipGetLastError();
 }
