@@ -91,6 +91,67 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
 
 
+def _csv_rows(path, kernel):
+    import csv
+    with open(path) as f:
+        return [r for r in csv.DictReader(f) if kernel in r["Kernel_Name"]]
+
+
+def traffic_from(pmc_dir, trace_csv, precision, workload):
+    """Write profiles/traffic_<precision>_<workload>.json from rocprofv3
+    counter runs (fetch/write of the sampled bench, cfetch/cwrite of
+    --copy-calibration, csv output under pmc_dir) and the kernel trace of the
+    full bench (trace_csv).  Bytes per work-group are taken per launch grid
+    from the sampled run, whose contraction launches have the full step's
+    grids; each launch of the full step is priced at its grid's figure
+    (launches whose grid the sample lacks at the sample's mean per
+    work-group), scaled by the counters' reading of a plain device copy."""
+    kern = "k_tgemm_bf16" if precision in ("bf16x3", "bf16") else "k_tgemm<"
+    raw = {}
+    for c in ("fetch", "write"):
+        for r in _csv_rows(os.path.join(pmc_dir, f"{c}_counter_collection.csv"), kern):
+            g = int(r["Grid_Size"])
+            raw.setdefault(g, {"fetch": [], "write": []})[c].append(float(r["Counter_Value"]))
+    cal = {}
+    for c in ("fetch", "write"):
+        v = [float(r["Counter_Value"]) for r in
+             _csv_rows(os.path.join(pmc_dir, f"c{c}_counter_collection.csv"), "__amd_rocclr_copyBuffer")]
+        cal[c] = (float(1 << 30) / 1024.0) / (sum(v) / len(v))
+    per_wg = {g: {c: 1024.0 * cal[c] * (sum(v[c]) / len(v[c])) / (g / 256) for c in ("fetch", "write")}
+              for g, v in raw.items()}
+    wgs = sum(g / 256 * len(v["fetch"]) for g, v in raw.items())
+    mean_wg = {c: sum(per_wg[g][c] * g / 256 * len(raw[g]["fetch"]) for g in raw) / wgs for c in ("fetch", "write")}
+    trace = [int(r["Grid_Size_X"]) * int(r.get("Grid_Size_Y") or 1) * int(r.get("Grid_Size_Z") or 1)
+             for r in _csv_rows(trace_csv, kern)]
+    mix = {}
+    tot = {"fetch": 0.0, "write": 0.0}
+    for g in trace:
+        mix[g] = mix.get(g, 0) + 1
+        for c in ("fetch", "write"):
+            tot[c] += (per_wg[g][c] if g in per_wg else mean_wg[c]) * (g / 256)
+    n = len(trace)
+    out = {
+        "kernel": kern, "precision": precision, "workload": workload,
+        "bytes_per_launch": (tot["fetch"] + tot["write"]) / n,
+        "fetch_bytes_per_launch": tot["fetch"] / n, "write_bytes_per_launch": tot["write"] / n,
+        "fetch_scale": round(cal["fetch"], 4), "write_scale": round(cal["write"], 4),
+        "sampled_raw_KiB_per_launch_by_grid": {
+            str(g): {"launches": len(v["fetch"]), "FETCH_SIZE": sum(v["fetch"]) / len(v["fetch"]),
+                     "WRITE_SIZE": sum(v["write"]) / len(v["write"])} for g, v in sorted(raw.items())},
+        "full_trace_launches_by_grid": {str(g): k for g, k in sorted(mix.items())},
+        "unsampled_grid_launches": sum(k for g, k in mix.items() if g not in per_wg),
+        "source_hash": kernel_source_hash(precision),
+        "method": "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two rocprofv3 --pmc runs of bench.py on "
+                  "sampled triplets (same launch grids as the full step), per work-group per grid, priced over "
+                  "the full step's launches from its kernel trace, scaled by the counters' reading of a plain "
+                  "1 GiB device copy (bench.py --copy-calibration)",
+    }
+    dst = os.path.join(ROOT, "profiles", f"traffic_{precision}_{workload}.json")
+    with open(dst, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps({"wrote": dst, "bytes_per_launch": out["bytes_per_launch"], "launches": n}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,8 +164,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--sample-items", type=int, default=0, help="profiling aid: K sampled triplets per block")
+    ap.add_argument("--prefix-items", type=int, default=0,
+                    help="profiling aid: the first K triplets per block in the whole-domain order")
     ap.add_argument("--copy-calibration", action="store_true", help="profiling aid: plain 1 GiB device copy")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("PMC_DIR", "TRACE_CSV"),
+                    help="profiling aid (no GPU): write the HBM traffic summary from counter and trace csv files")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from(*args.traffic_from, args.precision, args.workload)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -139,6 +207,8 @@ def main():
     step_items = None
     if args.sample_items > 0:
         step_items = synth.sample_items(dom.noa, dom.nob, args.sample_items, seed=99)
+    elif args.prefix_items > 0:
+        step_items = synth.first_items(dom.noa, dom.nob, args.prefix_items)
     ostep, _keep0 = lt.make_options(items=step_items)
     F_all, n_all = lt.ltriples_flops(d, ostep)
     ws = torch.empty(lt.ltriples_workspace_size(d, prec, ostep), dtype=torch.uint8, device=dev)
@@ -277,7 +347,7 @@ def main():
         "config": {"workload": f"{args.workload} domain: noa={dom.noa} nob={dom.nob} nva={dom.nva} "
                                f"nvb={dom.nvb} naux={dom.naux}, "
                                + (f"all {n_all} occupied triplets" if step_items is None
-                                  else f"{n_all} sampled triplets (profiling run)"),
+                                  else f"{n_all} {'sampled' if args.sample_items > 0 else 'leading'} triplets (profiling run)"),
                    "algorithmic_flops": F_all, "precision": args.precision,
                    "wall_ms_per_step": round(wall_ms / args.steps, 2)},
         "E": E,

@@ -209,6 +209,24 @@ def flip_spin(dom: Domain) -> Domain:
                   dom.eo_b, dom.ev_b, dom.eo_a, dom.ev_a, dom.fov_b, dom.fov_a)
 
 
+def _block_lists(noa: int, nob: int):
+    aaa = [(0, i, j, k) for i in range(noa) for j in range(i + 1, noa) for k in range(j + 1, noa)]
+    aab = [(1, i, j, k) for i in range(noa) for j in range(i + 1, noa) for k in range(nob)]
+    abb = [(2, i, j, k) for i in range(nob) for j in range(i + 1, nob) for k in range(noa)]
+    bbb = [(3, i, j, k) for i in range(nob) for j in range(i + 1, nob) for k in range(j + 1, nob)]
+    return aaa, aab, abb, bbb
+
+
+def first_items(noa: int, nob: int, per_block: int):
+    """The first `per_block` occupied triplets of each spin block in the
+    natural enumeration order (the order in which a whole-domain call visits
+    and batches them), same row format as sample_items."""
+    rows = []
+    for cands in _block_lists(noa, nob):
+        rows += cands[:per_block]
+    return np.asarray(rows, dtype=np.int32).reshape(-1, 4)
+
+
 def sample_items(noa: int, nob: int, per_block: int, seed: int):
     """Seeded sample of unique occupied triplets, `per_block` per spin block.
 
@@ -225,10 +243,6 @@ def sample_items(noa: int, nob: int, per_block: int, seed: int):
         sel = rng.choice(len(cands), size=min(per_block, len(cands)), replace=False)
         return [cands[s] for s in sorted(sel)]
 
-    aaa = [(0, i, j, k) for i in range(noa) for j in range(i + 1, noa) for k in range(j + 1, noa)]
-    aab = [(1, i, j, k) for i in range(noa) for j in range(i + 1, noa) for k in range(nob)]
-    abb = [(2, i, j, k) for i in range(nob) for j in range(i + 1, nob) for k in range(noa)]
-    bbb = [(3, i, j, k) for i in range(nob) for j in range(i + 1, nob) for k in range(j + 1, nob)]
-    for cands in (aaa, aab, abb, bbb):
+    for cands in _block_lists(noa, nob):
         rows += pick(cands)
     return np.asarray(rows, dtype=np.int32).reshape(-1, 4)
