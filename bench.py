@@ -160,7 +160,7 @@ def main():
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "fp64", "bf16x3", "bf16"])
     ap.add_argument("--workload", default="lno", choices=["tiny", "lno", "grad"])
     ap.add_argument("--fp64-sample", type=int, default=48, help="items per block for the FP64 GPU comparison")
-    ap.add_argument("--cpu-sample", type=int, default=1, help="items per block for the CPU oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=3, help="items per block for the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--sample-items", type=int, default=0, help="profiling aid: K sampled triplets per block")

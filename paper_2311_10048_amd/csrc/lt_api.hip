@@ -1574,6 +1574,7 @@ int ltriples_workspace_size(const ltriples_domain* d, int32_t precision, const l
   build_items(dims_of(d), o, L);
   Plan P;
   plan_domain(d, precision, o, L, P);
+  log_plan(P);
   *bytes = P.total;
   return LT_OK;
 }
