@@ -252,7 +252,8 @@ def main():
     peak = PEAK_TFLOPS[args.precision]
     avg_ms = gemm_ms / max(launches, 1)
     traffic = None
-    tr = committed_traffic(args.precision, args.workload)
+    # the committed counter summary prices the whole-domain step only
+    tr = committed_traffic(args.precision, args.workload) if step_items is None else None
     if tr is not None:
         traffic = tr["bytes_per_launch"]
     kname = "k_tgemm_bf16" if args.precision.startswith("bf16") else "k_tgemm"
