@@ -54,7 +54,8 @@ extern "C" {
 #define LT_OK 0
 #define LT_EINVAL (-1)      /* null pointer or negative dimension */
 #define LT_ESHAPE (-2)      /* inconsistent dimensions or item list */
-#define LT_EDENOM (-3)      /* max occupied e >= min virtual e: some D >= 0 */
+#define LT_EDENOM (-3)      /* max occupied e >= min virtual e (some D >= 0), occupied-
+                               virtual gap below 1e-100, or an |e| above 1e100 */
 #define LT_EPREC (-4)       /* unsupported precision */
 #define LT_EWORKSPACE (-5)  /* workspace too small */
 #define LT_EHIP (-6)        /* HIP runtime error */
@@ -145,8 +146,10 @@ int ltriples_flops(const ltriples_domain* d, const ltriples_options* o,
  *   ws     device workspace of ws_bytes >= ltriples_workspace_size(), or
  *          NULL to let the library allocate and free it inside the call.
  * The call reads the orbital energies back to the host once (a synchronous
- * copy) to check that every denominator is negative (LT_EDENOM) and finite
- * (LT_ENONFINITE); everything else is asynchronous on `stream`.
+ * copy) to check that they are finite (LT_ENONFINITE), at most 1e100 in
+ * magnitude, and that every virtual energy exceeds every occupied one by at
+ * least 1e-100 (LT_EDENOM), so every denominator D lies in [-6e100, -3e-100];
+ * everything else is asynchronous on `stream`.
  * Fewer than 3 occupied orbitals in total, or empty virtual spaces, give
  * E = 0 and LT_OK. */
 int ltriples_energy(const ltriples_domain* d, int32_t precision,

@@ -892,8 +892,11 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
   return LT_OK;
 }
 
-// Every occupied energy below every virtual energy (all D < 0), all finite.
-// Reads the orbital energies back to the host (synchronous copy).
+// Every occupied energy below every virtual energy by at least 1e-100 and
+// every energy finite and at most 1e100 in magnitude, so every denominator
+// D = e_i + e_j + e_k - e_a - e_b - e_c lies in [-6e100, -3e-100] (the range
+// the epilogues' reciprocal assumes).  Reads the orbital energies back to the
+// host (synchronous copy).
 int check_denominators(const ltriples_domain* d) {
   const Dims D = dims_of(d);
   double omax = -INFINITY, vmin = INFINITY;
@@ -905,14 +908,18 @@ int check_denominators(const ltriples_domain* d) {
     if (D.v[s]) HIPCHK(hipMemcpy(hv.data(), ev, 8 * D.v[s], hipMemcpyDeviceToHost));
     for (double x : ho) {
       if (!std::isfinite(x)) return fail(LT_ENONFINITE, "non-finite occupied energy");
+      if (std::fabs(x) > 1e100) return fail(LT_EDENOM, "occupied energy %.6g above 1e100 in magnitude", x);
       omax = std::max(omax, x);
     }
     for (double x : hv) {
       if (!std::isfinite(x)) return fail(LT_ENONFINITE, "non-finite virtual energy");
+      if (std::fabs(x) > 1e100) return fail(LT_EDENOM, "virtual energy %.6g above 1e100 in magnitude", x);
       vmin = std::min(vmin, x);
     }
   }
   if (omax >= vmin) return fail(LT_EDENOM, "max occupied energy %.6g >= min virtual energy %.6g", omax, vmin);
+  if (vmin - omax < 1e-100)
+    return fail(LT_EDENOM, "occupied-virtual gap %.6g below 1e-100", vmin - omax);
   return LT_OK;
 }
 

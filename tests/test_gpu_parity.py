@@ -95,6 +95,23 @@ def test_denominator_check():
     assert ei.value.code == lt.LT_EDENOM
 
 
+@pytest.mark.parametrize("case", ["tiny_gap", "huge_energy"])
+def test_denominator_range_check(case):
+    """Energies that would put some |D| outside [3e-100, 6e100] are rejected
+    before any kernel runs (the epilogues' reciprocal assumes that range)."""
+    dom = synth.make_domain(3, 2, 6, 7, 16, seed=3)
+    if case == "tiny_gap":
+        # occupied energies below the virtual ones, but only 2e-101 apart
+        sc = 1e-101
+        bad = dom.replace(eo_a=-sc * (1.0 + np.arange(dom.eo_a.size)), eo_b=-sc * (1.0 + np.arange(dom.eo_b.size)),
+                          ev_a=sc * (1.0 + np.arange(dom.ev_a.size)), ev_b=sc * (1.0 + np.arange(dom.ev_b.size)))
+    else:
+        bad = dom.replace(ev_b=dom.ev_b + 1e101)
+    with pytest.raises(lt.LtError) as ei:
+        gpu_energy(bad, lt.LT_FP64)
+    assert ei.value.code == lt.LT_EDENOM
+
+
 def test_plain_bf16_ablation_runs():
     """Single-product BF16 (ablation): finite and within 1e-3 of the oracle
     on the ragged shape; reported, not a precision claim."""
