@@ -97,7 +97,7 @@ def _csv_rows(path, kernel):
         return [r for r in csv.DictReader(f) if kernel in r["Kernel_Name"]]
 
 
-def traffic_from(pmc_dir, trace_csv, precision, workload):
+def traffic_from(pmc_dir, trace_csv, precision, workload, dst=None):
     """Write profiles/traffic_<precision>_<workload>.json from rocprofv3
     counter runs (fetch/write of the sampled bench, cfetch/cwrite of
     --copy-calibration, csv output under pmc_dir) and the kernel trace of the
@@ -146,10 +146,12 @@ def traffic_from(pmc_dir, trace_csv, precision, workload):
                   "the full step's launches from its kernel trace, scaled by the counters' reading of a plain "
                   "1 GiB device copy (bench.py --copy-calibration)",
     }
-    dst = os.path.join(ROOT, "profiles", f"traffic_{precision}_{workload}.json")
+    if dst is None:
+        dst = os.path.join(ROOT, "profiles", f"traffic_{precision}_{workload}.json")
     with open(dst, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps({"wrote": dst, "bytes_per_launch": out["bytes_per_launch"], "launches": n}))
+    return out
 
 
 def main():
