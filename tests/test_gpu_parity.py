@@ -23,7 +23,9 @@ SHAPES = {
     "no_beta_occ": (4, 0, 21, 22, 40),     # only the aaa block
     "one_beta": (3, 1, 17, 18, 30),        # aaa, aab
     "wide": (3, 3, 70, 67, 64),            # v > 64: several GEMM and epilogue tiles
+    "tall": (3, 1, 400, 401, 48),          # v > 384: several row tiles per contraction (aaa, aab)
 }
+_REF = {}   # oracle results per shape, shared by the three precisions
 
 
 def _check(dom, prec, ref=None, items=None):
@@ -52,7 +54,9 @@ def _check(dom, prec, ref=None, items=None):
 def test_parity_shapes(name, prec):
     dom = synth.make_domain(*SHAPES[name], seed=synth.BASE_SEED + 17)
     print(f"[parity] {name} {SHAPES[name]} prec={prec}", flush=True)
-    _check(dom, prec)
+    if name not in _REF:
+        _REF[name] = blocks.energy(dom)
+    _check(dom, prec, ref=_REF[name])
 
 
 @pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32, lt.LT_BF16X3])
