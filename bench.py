@@ -160,7 +160,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "fp64", "bf16x3", "bf16"])
-    ap.add_argument("--workload", default="lno", choices=["tiny", "lno", "grad"])
+    ap.add_argument("--workload", default="lno", choices=["tiny", "lno", "grad", "large"])
     ap.add_argument("--fp64-sample", type=int, default=48, help="items per block for the FP64 GPU comparison")
     ap.add_argument("--cpu-sample", type=int, default=3, help="items per block for the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -285,10 +285,18 @@ def main():
     items64 = synth.sample_items(dom.noa, dom.nob, args.fp64_sample, seed=2311)
     if step_items is not None:
         items64 = step_items
+    need64 = 0
     if args.fp64_sample > 0 and len(items64):
         o64, _keep = lt.make_options(items=items64)
+        need64 = lt.ltriples_workspace_size(d, lt.LT_FP64, o64)
+        del ws
+        torch.cuda.empty_cache()
+        if need64 > torch.cuda.mem_get_info(dev)[0] - (1 << 30):
+            fp64 = {"skipped": f"FP64 workspace of {need64 / 1e9:.1f} GB does not fit beside the inputs"}
+            log(fp64["skipped"])
+    if args.fp64_sample > 0 and len(items64) and fp64 is None:
         F_s, n_s = lt.ltriples_flops(d, o64)
-        ws64 = torch.empty(lt.ltriples_workspace_size(d, lt.LT_FP64, o64), dtype=torch.uint8, device=dev)
+        ws64 = torch.empty(need64, dtype=torch.uint8, device=dev)
         ei64 = torch.zeros(n_s, 3, dtype=torch.float64, device=dev)
         st64 = lt.Stats()
         lt.ltriples_energy(tens, dom.dims, lt.LT_FP64, items=items64, e_items=ei64, workspace=ws64, stats=st64)

@@ -121,7 +121,13 @@ typedef struct ltriples_options {
    * hipGraph on the first call and replay it on later calls with the same
    * shapes, pointers, workspace and options (requires a caller workspace) */
   int32_t graph;
-  int32_t reserved[3];
+  /* the largest operand builds (<ei||bc>, (jb|EC), (be|KC) and the same-spin
+   * (ov|ov) behind <qr||yz>) run in chunks of their leading occupied index
+   * of at most this many MiB each (0 = default 2048).  Smaller chunks shrink
+   * the staging and scratch parts of the workspace; results are bitwise
+   * unchanged. */
+  int32_t build_chunk_mib;
+  int32_t reserved[2];
 } ltriples_options;
 
 /* Host-only validation of sizes, pointers, precision and item list.  Makes

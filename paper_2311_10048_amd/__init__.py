@@ -72,7 +72,8 @@ class Options(ctypes.Structure):
                 ("batch_items", ctypes.c_int32),
                 ("stats", ctypes.POINTER(Stats)),
                 ("graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("build_chunk_mib", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 GRAD_FIELDS = ("t1a", "t1b", "t2aa", "t2bb", "t2ab", "Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b")
@@ -168,12 +169,13 @@ def make_domain(dims, tensors: Optional[Mapping[str, object]] = None) -> Domain:
 
 
 def make_options(items=None, e_items=None, batch_budget: int = 0, batch_items: int = 0,
-                 stats: Optional[Stats] = None):
+                 stats: Optional[Stats] = None, build_chunk_mib: int = 0):
     """ltriples_options; `items` is a host int32 array [n][4] (kept alive by
     the returned tuple's second element)."""
     o = Options()
     o.batch_budget = int(batch_budget)
     o.batch_items = int(batch_items)
+    o.build_chunk_mib = int(build_chunk_mib)
     if stats is not None:
         o.stats = ctypes.pointer(stats)
     keep = None
@@ -212,7 +214,7 @@ def ltriples_flops(dom: Domain, options: Optional[Options] = None):
 
 def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP32, items=None,
                     e_items=None, batch_budget: int = 0, batch_items: int = 0, workspace=None,
-                    stream=None, stats: Optional[Stats] = None):
+                    stream=None, stats: Optional[Stats] = None, build_chunk_mib: int = 0):
     """E(T) of one domain on the current HIP device.
 
     Returns (e, parts): a float64 device tensor of shape [1] and one of shape
@@ -227,7 +229,7 @@ def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP3
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     dom = make_domain(dims, tensors)
-    opts, keep = make_options(items, e_items, batch_budget, batch_items, stats)
+    opts, keep = make_options(items, e_items, batch_budget, batch_items, stats, build_chunk_mib)
     dev = next(t for t in tensors.values() if hasattr(t, "device")).device
     need = ltriples_workspace_size(dom, precision, opts)
     if workspace is None:
@@ -263,7 +265,7 @@ def ltriples_workspace_size_batched(dims_list, tensors_list, precision: int, opt
 
 def ltriples_energy_batched(tensors_list, dims_list, precision: int = LT_FP32, graph: bool = False,
                             batch_budget: int = 0, batch_items: int = 0, workspace=None, out=None,
-                            stream=None):
+                            stream=None, build_chunk_mib: int = 0):
     """E(T) of several domains in one call.  Returns (e [ndom], parts [ndom,4,3]).
     With graph=True the launch sequence is captured into a hipGraph on the
     first call and replayed on later calls with the same shapes, pointers,
@@ -272,7 +274,7 @@ def ltriples_energy_batched(tensors_list, dims_list, precision: int = LT_FP32, g
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     ndom = len(dims_list)
-    opts, _ = make_options(batch_budget=batch_budget, batch_items=batch_items)
+    opts, _ = make_options(batch_budget=batch_budget, batch_items=batch_items, build_chunk_mib=build_chunk_mib)
     opts.graph = 1 if graph else 0
     arr = _domain_array(dims_list, tensors_list)
     dev = next(t for t in tensors_list[0].values() if hasattr(t, "device")).device
@@ -307,7 +309,7 @@ def ltriples_backward_workspace_size(dom: Domain, precision: int, options: Optio
 
 def ltriples_backward(tensors: Mapping[str, object], dims, precision: int = LT_FP64, gbar=None, items=None,
                       batch_budget: int = 0, batch_items: int = 0, workspace=None, out=None, stream=None,
-                      stats: Optional[Stats] = None):
+                      stats: Optional[Stats] = None, build_chunk_mib: int = 0):
     """gbar * dE/dx for x in GRAD_FIELDS (projected convention for t2aa, t2bb,
     Boo, Bvv).  Returns a dict of float64 device tensors shaped like the
     inputs.  `gbar` is a float64 device tensor with one element (default 1);
@@ -316,7 +318,7 @@ def ltriples_backward(tensors: Mapping[str, object], dims, precision: int = LT_F
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     dom = make_domain(dims, tensors)
-    opts, keep = make_options(items, None, batch_budget, batch_items, stats)
+    opts, keep = make_options(items, None, batch_budget, batch_items, stats, build_chunk_mib)
     dev = next(t for t in tensors.values() if hasattr(t, "device")).device
     if gbar is None:
         gbar = torch.ones(1, dtype=torch.float64, device=dev)

@@ -194,9 +194,14 @@ struct Plan {
   int bf = 0;                     // 0: none, 3: split products, 1: plain bf16
   enum { T2T8, As8, GamT8, Tp8, LmixT8, Mst8, Mts8, Tmix8, Tmx28, ZpT8, TmT8, OOT8, NT8 };
   Buf O8h[2][NT8], O8l[2][NT8];
+  // operand builds split along their leading occupied index: blocks per
+  // chunk of <ei||bc> (and its (eb|ic) intermediate), (jb|EC), (be|KC) and
+  // of the same-spin (ov|ov) rows behind <qr||yz>
+  int64_t cAs[2] = {1, 1}, cMst[2] = {1, 1}, cMts[2] = {1, 1}, cOV[2] = {1, 1};
+  Buf stage;                      // BF16 modes: staging of one FP32 operand tensor (or chunk)
   // scratch
   Buf scratch;
-  size_t sc_OO[2][2], sc_OV[2];   // offsets within scratch (phase 1a)
+  size_t sc_OO[2][2], sc_OV;      // offsets within scratch (phase 1a)
   int64_t nb[4];                  // items per batch
   size_t per_item[4];             // batch bytes per item (T outputs)
   size_t o1[4], o2[4];            // aligned per-item bytes of the two output layouts
@@ -231,15 +236,28 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
   // BF16 modes keep only the split (octet) copies of the contraction
   // operands: every FP32 operand tensor is built in one shared staging
   // buffer and split before the next one is built.
-  std::vector<Buf*> staged;
+  std::vector<std::pair<Buf*, size_t>> staged;
   auto take = [&](Buf& b, size_t bytes) { b.off = off; b.bytes = bytes; off = align256(off + bytes); };
-  auto take_op = [&](Buf& b, size_t bytes) {
+  auto take_op = [&](Buf& b, size_t bytes, size_t stage_bytes = 0) {
     if (!P.bf) { take(b, bytes); return; }
     b.bytes = bytes;
-    staged.push_back(&b);
+    staged.push_back({&b, stage_bytes ? stage_bytes : bytes});
   };
   const size_t ts = P.ts;
   const int64_t Q = D.Q;
+  // chunks of the big operand builds: at most build_chunk_mib MiB each
+  const size_t cap = (size_t)((o && o->build_chunk_mib > 0) ? o->build_chunk_mib : 2048) << 20;
+  auto per_chunk = [&](int64_t nblk, size_t blk_bytes) -> int64_t {
+    return std::max<int64_t>(1, std::min<int64_t>(nblk, (int64_t)(cap / std::max<size_t>(blk_bytes, 1))));
+  };
+  for (int s = 0; s < 2; ++s) {
+    const int t = 1 - s;
+    const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
+    P.cAs[s] = per_chunk(os, ts * (size_t)(vs * vs * P.ldv[s]));   // (eb|ic) rows of one i
+    P.cMst[s] = per_chunk(os, ts * (size_t)(vt * P.ldcb[s]));
+    P.cMts[s] = per_chunk(ot, ts * (size_t)(vs * P.ldcb[s]));
+    P.cOV[s] = per_chunk(os, 8 * (size_t)(vs * os * vs));          // (ov|ov) rows of one q
+  }
   for (int s = 0; s < 2; ++s) {
     const bool need_df = P.need_as[s] || P.any_mix;
     const int64_t os = D.o[s], vs = D.v[s];
@@ -250,7 +268,7 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
       take(P.BooP64[s], 8 * Q * P.ldoo[s]);
     }
     if (P.need_as[s]) {
-      take_op(P.As[s], ts * os * vs * P.ldnp[s]);
+      take_op(P.As[s], ts * os * vs * P.ldnp[s], ts * P.cAs[s] * vs * P.ldnp[s]);
       take_op(P.Tp[s], ts * os * os * P.ldnp[s]);
       take_op(P.T2T[s], ts * os * os * vs * P.ldv[s]);
       take_op(P.GamT[s], ts * os * os * os * P.ldv[s]);
@@ -260,8 +278,8 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
       const int t = 1 - s;
       const int64_t ot = D.o[t], vt = D.v[t];
       take_op(P.LmixT[s], ts * os * ot * vt * P.ldv[s]);
-      take_op(P.Mst[s], ts * os * vt * P.ldcb[s]);
-      take_op(P.Mts[s], ts * ot * vs * P.ldcb[s]);
+      take_op(P.Mst[s], ts * os * vt * P.ldcb[s], ts * P.cMst[s] * vt * P.ldcb[s]);
+      take_op(P.Mts[s], ts * ot * vs * P.ldcb[s], ts * P.cMts[s] * vs * P.ldcb[s]);
       take_op(P.Tmix[s], ts * os * ot * P.ldcb[s]);
       take_op(P.ZpT[s], ts * os * ot * ot * P.ldv[s]);
       take_op(P.TmT[s], ts * os * ot * vs * P.ldv[t]);
@@ -270,10 +288,9 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
   }
   if (!staged.empty()) {
     size_t mx = 0;
-    for (Buf* b : staged) mx = std::max(mx, b->bytes);
-    Buf stage;
-    take(stage, mx);
-    for (Buf* b : staged) b->off = stage.off;
+    for (auto& b : staged) mx = std::max(mx, b.second);
+    take(P.stage, mx);
+    for (auto& b : staged) b.first->off = P.stage.off;
   }
   if (P.any_mix) take(P.OVab, 8 * D.o[0] * D.v[0] * D.o[1] * D.v[1]);
   if (bwd) {
@@ -345,14 +362,17 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
       P.sc_OO[x][y] = s1a;
       if (need) s1a = align256(s1a + 8 * (size_t)(D.o[x] * D.v[x] * D.o[y] * D.o[y]));
     }
-  for (int s = 0; s < 2; ++s) {
-    P.sc_OV[s] = s1a;
-    if (P.need_as[s]) s1a = align256(s1a + 8 * (size_t)(D.o[s] * D.v[s] * D.o[s] * D.v[s]));
+  {
+    P.sc_OV = s1a;                 // one chunk of (ov|ov) rows, both spins in turn
+    size_t ov = 0;
+    for (int s = 0; s < 2; ++s)
+      if (P.need_as[s]) ov = std::max(ov, 8 * (size_t)(P.cOV[s] * D.v[s] * D.o[s] * D.v[s]));
+    s1a = align256(s1a + ov);
   }
-  // phase 1b: (eb|ic) before pair packing
+  // phase 1b: (eb|ic) of one chunk of i before pair packing
   size_t s1b = 0;
   for (int s = 0; s < 2; ++s)
-    if (P.need_as[s]) s1b = std::max(s1b, ts * (size_t)(D.o[s] * D.v[s] * D.v[s] * P.ldv[s]));
+    if (P.need_as[s]) s1b = std::max(s1b, ts * (size_t)(P.cAs[s] * D.v[s] * D.v[s] * P.ldv[s]));
   // phase 2: batch buffers + partials
   const size_t budget = (o && o->batch_budget) ? o->batch_budget : (size_t(8) << 30);
   size_t s2 = 0;
@@ -533,6 +553,20 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
       default: return sp(ot * os, os, lvt, vt, P.OOT[s], os * lvt, lvt);
     }
   };
+  // BF16 modes: split blocks [b0, b0 + n) of a chunked operand, built in the
+  // staging buffer, into their octet copies
+  auto split_chunk = [&](int s, int t8, int64_t b0, int64_t n) -> hipError_t {
+    if (!P.bf) return hipSuccess;
+    const int t = 1 - s;
+    const int64_t vs = D.v[s], vt = D.v[t], lp = P.ldnp[s], lc = P.ldcb[s];
+    int64_t K, ld, ncol, ibs, iks;
+    if (t8 == Plan::As8) { K = vs; ld = lp; ncol = npair(vs); ibs = vs * lp; iks = lp; }
+    else if (t8 == Plan::Mst8) { K = vt; ld = lc; ncol = vt * vs; ibs = vt * lc; iks = lc; }
+    else { K = vs; ld = lc; ncol = vt * vs; ibs = vs * lc; iks = lc; }   // Mts8
+    const int64_t blk = ((K + 15) / 16) * 16 * ld;                       // elements per octet block
+    return lt::launch_split8(at<lt::bf16_t>(ws, P.O8h[s][t8]) + b0 * blk, at<lt::bf16_t>(ws, P.O8l[s][t8]) + b0 * blk,
+                             n, (int32_t)K, ld, (int32_t)ncol, at<float>(ws, P.stage), ibs, iks, st);
+  };
   // --- 1. DF factor layouts --------------------------------------------------
   for (int s = 0; s < 2; ++s) {
     if (!P.BvvP[s].bytes) continue;
@@ -570,12 +604,16 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
   for (int s = 0; s < 2; ++s) {
     if (!P.need_as[s]) continue;
     const int64_t o = D.o[s], v = D.v[s], lv = P.ldv[s];
-    double* OV = (double*)(scr + P.sc_OV[s]);
-    HIPCHK(gemm64(o * v, o * v, at<double>(ws, P.BovP64[s]), P.ldov[s], at<double>(ws, P.BovP64[s]),
-                  P.ldov[s], OV, o * v));
-    // U[q][r][y][z] = OV[q][y][r][z] - OV[q][z][r][y]
-    HIPCHK(lt::launch_copy4d<double, double>(at<double>(ws, P.U[s]), o * v * lv, v * lv, lv, o, o, v, v,
-                                             OV, v * o * v, v, o * v, 1, OV, v * o * v, v, 1, o * v, st));
+    double* OV = (double*)(scr + P.sc_OV);
+    // (ov|ov) rows (q, y) of a chunk of q, then U[q][r][y][z] = OV[q][y][r][z] - OV[q][z][r][y]
+    for (int64_t q0 = 0; q0 < o; q0 += P.cOV[s]) {
+      const int64_t n = std::min<int64_t>(P.cOV[s], o - q0);
+      HIPCHK(gemm64(n * v, o * v, at<double>(ws, P.BovP64[s]) + q0 * v, P.ldov[s], at<double>(ws, P.BovP64[s]),
+                    P.ldov[s], OV, o * v));
+      HIPCHK(lt::launch_copy4d<double, double>(at<double>(ws, P.U[s]) + q0 * o * v * lv, o * v * lv, v * lv, lv,
+                                               n, o, v, v, OV, v * o * v, v, o * v, 1, OV, v * o * v, v, 1, o * v,
+                                               st));
+    }
     // GamT[j][k][m][a] = OO[k][a][m][j] - OO[j][a][m][k]
     const double* oo = OO[s][s];
     HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.GamT[s]), o * o * lv, o * lv, lv, o, o, o, v,
@@ -653,26 +691,37 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
     if (!P.need_as[s]) continue;
     const int64_t o = D.o[s], v = D.v[s], lv = P.ldv[s];
     T* Kx = (T*)scr;
-    // Kx[i][(e,b)][c] = (eb|ic)
-    HIPCHK(gemmT(v * v, v, o, at<T>(ws, P.BvvP[s]), P.ldvv[s], 0, at<T>(ws, P.BovR[s]), lv, Q * lv,
-                 Kx, v * v * lv, 0, lv, 0, 0, 1, 0));
-    // As[i][e][p(b<c)] = Kx[i][e][b][c] - Kx[i][e][c][b]
-    HIPCHK(lt::launch_pack_pairs<T, T>(at<T>(ws, P.As[s]), P.ldnp[s], o * v, (int32_t)v, Kx, v * lv, lv, 1,
-                                       true, st));
-    HIPCHK(split_op(s, Plan::As8));
+    for (int64_t i0 = 0; i0 < o; i0 += P.cAs[s]) {
+      const int64_t n = std::min<int64_t>(P.cAs[s], o - i0);
+      // Kx[i][(e,b)][c] = (eb|ic) for i in [i0, i0 + n)
+      HIPCHK(gemmT(v * v, v, n, at<T>(ws, P.BvvP[s]), P.ldvv[s], 0, at<T>(ws, P.BovR[s]) + i0 * Q * lv, lv,
+                   Q * lv, Kx, v * v * lv, 0, lv, 0, 0, 1, 0));
+      // As[i][e][p(b<c)] = Kx[i][e][b][c] - Kx[i][e][c][b] (BF16 modes: into staging, then split)
+      T* dst = P.bf ? at<T>(ws, P.stage) : at<T>(ws, P.As[s]) + i0 * v * P.ldnp[s];
+      HIPCHK(lt::launch_pack_pairs<T, T>(dst, P.ldnp[s], n * v, (int32_t)v, Kx, v * lv, lv, 1, true, st));
+      HIPCHK(split_chunk(s, Plan::As8, i0, n));
+    }
   }
   for (int s = 0; s < 2; ++s) {
     if (!P.need_mix[s]) continue;
     const int t = 1 - s;
     const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t], lc = P.ldcb[s];
-    // Mst[j][E][C*vs+b] = (jb|EC): rows (E,C), cols b
-    HIPCHK(gemmT(vt * vt, vs, os, at<T>(ws, P.BvvP[t]), P.ldvv[t], 0, at<T>(ws, P.BovR[s]), P.ldv[s],
-                 Q * P.ldv[s], at<T>(ws, P.Mst[s]), vt * lc, lc, vs, (int32_t)vt, 0, 1, 0));
-    HIPCHK(split_op(s, Plan::Mst8));
-    // Mts[K][e][C*vs+b] = (be|KC): rows C, cols (e,b)
-    HIPCHK(gemmT(vt, vs * vs, ot, at<T>(ws, P.BovR[t]), P.ldv[t], Q * P.ldv[t], at<T>(ws, P.BvvP[s]),
-                 P.ldvv[s], 0, at<T>(ws, P.Mts[s]), vs * lc, 0, vs, 0, lc, 1, (int32_t)vs));
-    HIPCHK(split_op(s, Plan::Mts8));
+    // Mst[j][E][C*vs+b] = (jb|EC): rows (E,C), cols b; chunks of j
+    for (int64_t j0 = 0; j0 < os; j0 += P.cMst[s]) {
+      const int64_t n = std::min<int64_t>(P.cMst[s], os - j0);
+      T* dst = P.bf ? at<T>(ws, P.stage) : at<T>(ws, P.Mst[s]) + j0 * vt * lc;
+      HIPCHK(gemmT(vt * vt, vs, n, at<T>(ws, P.BvvP[t]), P.ldvv[t], 0, at<T>(ws, P.BovR[s]) + j0 * Q * P.ldv[s],
+                   P.ldv[s], Q * P.ldv[s], dst, vt * lc, lc, vs, (int32_t)vt, 0, 1, 0));
+      HIPCHK(split_chunk(s, Plan::Mst8, j0, n));
+    }
+    // Mts[K][e][C*vs+b] = (be|KC): rows C, cols (e,b); chunks of K
+    for (int64_t k0 = 0; k0 < ot; k0 += P.cMts[s]) {
+      const int64_t n = std::min<int64_t>(P.cMts[s], ot - k0);
+      T* dst = P.bf ? at<T>(ws, P.stage) : at<T>(ws, P.Mts[s]) + k0 * vs * lc;
+      HIPCHK(gemmT(vt, vs * vs, n, at<T>(ws, P.BovR[t]) + k0 * Q * P.ldv[t], P.ldv[t], Q * P.ldv[t],
+                   at<T>(ws, P.BvvP[s]), P.ldvv[s], 0, dst, vs * lc, 0, vs, 0, lc, 1, (int32_t)vs));
+      HIPCHK(split_chunk(s, Plan::Mts8, k0, n));
+    }
   }
 
   if (P.bwd) {

@@ -172,3 +172,29 @@ def test_backward_plan_item_subsets_and_errors():
     assert lib.ltriples_backward_workspace_size(ctypes.byref(d), lt.LT_FP64, None, ctypes.byref(n)) == lt.LT_OK
     assert n.value > lt.ltriples_workspace_size(d, lt.LT_FP64)
     assert lib.ltriples_backward(ctypes.byref(d), lt.LT_FP64, None, None, None, None, 0, None) == lt.LT_EINVAL
+
+
+def test_build_chunks_fit_the_large_domain_on_one_gpu():
+    """Chunked operand builds keep the BF16x3 workspace of the largest
+    domain (60,58,500,502,2000) plus its FP64 inputs under one MI355X's
+    288 GiB, and smaller chunks only shrink the workspace."""
+    dims = synth.SHAPES["large"]
+    d = _fake_domain(dims)
+    no, nb, va, vb, q = dims
+    inputs = 8 * (no * va + nb * vb + no * no * va * va + nb * nb * vb * vb + no * nb * va * vb
+                  + q * (no * no + no * va + va * va + nb * nb + nb * vb + vb * vb)
+                  + 2 * (no + va + nb + vb) + no * va + nb * vb)
+    w = {p: lt.ltriples_workspace_size(d, p) for p in (lt.LT_FP32, lt.LT_BF16X3)}
+    assert w[lt.LT_BF16X3] + inputs < 0.95 * 288 * 2 ** 30, (w, inputs)
+    o, _ = lt.make_options(build_chunk_mib=64)
+    for p in (lt.LT_FP64, lt.LT_FP32, lt.LT_BF16X3):
+        small = lt.ltriples_workspace_size(d, p, o)
+        assert small <= lt.ltriples_workspace_size(d, p), p
+
+
+@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32])
+def test_backward_plan_in_bounds_with_small_build_chunks(prec):
+    d = _fake_domain((6, 5, 45, 47, 96))
+    o, _ = lt.make_options(build_chunk_mib=1)
+    lib = lt.load_library()
+    assert lib.ltriples_plan_check(ctypes.byref(d), prec, ctypes.byref(o), 1) == lt.LT_OK

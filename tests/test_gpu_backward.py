@@ -76,6 +76,17 @@ def test_backward_small_batches_and_gbar():
     _compare(g2, {k: -2.5 * v for k, v in g1.items()}, 1e-14, "gbar")
 
 
+def test_backward_chunked_builds_bitwise_equal():
+    """The adjoint with its forward operand builds in 1 MiB chunks gives
+    exactly the default gradient."""
+    dom = _dom(SHAPES["wide"])
+    t = to_device(dom)
+    g0 = _gpu_grad(dom, lt.LT_FP64, tensors=t)
+    g1 = _gpu_grad(dom, lt.LT_FP64, tensors=t, build_chunk_mib=1)
+    for k in lt.GRAD_FIELDS:
+        assert np.array_equal(g0[k], g1[k]), k
+
+
 def test_backward_workspace_garbage_never_read():
     import torch
     dom = _dom(SHAPES["wide"])

@@ -22,6 +22,7 @@ TOL_ITEM = {lt.LT_BF16X3: 1e-6, lt.LT_FP64: 1e-10}
 
 def test_lno_whole_domain_bf16x3_sampled_items():
     import torch
+    torch.cuda.empty_cache()          # blocks cached by earlier tests
     dom = synth.config_domain("lno")
     print(f"[full] lno {dom.dims}: whole domain, BF16X3", flush=True)
     t = to_device(dom)
@@ -61,3 +62,29 @@ def test_lno_whole_domain_bf16x3_sampled_items():
         s = max(1.0, abs(r))
         assert abs(ei[idx[n]].sum() - r) <= TOL_ITEM[lt.LT_BF16X3] * s, (items[n], ei[idx[n]], ref[n])
         assert abs(e64[n].sum() - r) <= TOL_ITEM[lt.LT_FP64] * s, (items[n], e64[n], ref[n])
+
+
+def test_large_domain_bf16x3_on_one_gpu_sampled_items():
+    """The largest domain (60,58,500,502,2000) in BF16X3 on one GPU (chunked
+    operand builds keep workspace and inputs within its memory): one sampled
+    triplet per spin block against the FP64 CPU oracle.  Contractions here
+    have M = 500 or 502, i.e. two row tiles."""
+    import torch
+    torch.cuda.empty_cache()          # blocks cached by earlier tests
+    dom = synth.config_domain("large")
+    print(f"[full] large {dom.dims}: BF16X3, 4 sampled triplets", flush=True)
+    t = to_device(dom)
+    items = synth.sample_items(dom.noa, dom.nob, 1, seed=5151)
+    ei = torch.full((len(items), 3), float("nan"), dtype=torch.float64, device="cuda")
+    E, parts = lt.ltriples_energy(t, dom.dims, lt.LT_BF16X3, items=items, e_items=ei)
+    torch.cuda.synchronize()
+    E, ei = float(E.item()), ei.cpu().numpy()
+    del t
+    torch.cuda.empty_cache()
+    assert np.isfinite(ei).all()
+    assert abs(E - math.fsum(ei.ravel())) <= 1e-12 * abs(E)
+    print("[full] oracle on the sampled triplets", flush=True)
+    ref = blocks.energy(dom, items=items, return_items=True)["items"]
+    for n in range(len(items)):
+        r = ref[n].sum()
+        assert abs(ei[n].sum() - r) <= TOL_ITEM[lt.LT_BF16X3] * max(1.0, abs(r)), (items[n], ei[n], ref[n])

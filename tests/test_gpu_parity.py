@@ -70,6 +70,19 @@ def test_workspace_garbage_never_read(prec):
     assert E0 == E1 and np.array_equal(p0, p1)
 
 
+@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32, lt.LT_BF16X3])
+@pytest.mark.parametrize("name", ["wide", "tall"])
+def test_chunked_operand_builds_bitwise_equal(name, prec):
+    """Operand builds in 1 MiB chunks of their occupied index (several chunks
+    of <ei||bc>, (jb|EC), (be|KC) and the (ov|ov) rows on these shapes) give
+    exactly the default result."""
+    dom = synth.make_domain(*SHAPES[name], seed=synth.BASE_SEED + 17)
+    print(f"[chunks] {name} {SHAPES[name]} prec={prec}", flush=True)
+    E0, p0, _ = gpu_energy(dom, prec)
+    E1, p1, _ = gpu_energy(dom, prec, build_chunk_mib=1)
+    assert E0 == E1 and np.array_equal(p0, p1)
+
+
 def test_parity_config0_items_fp64():
     """Per-item values of every triplet of the small domain, in caller order."""
     dom = synth.config_domain("tiny")
