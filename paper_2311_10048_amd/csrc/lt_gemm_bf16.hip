@@ -63,7 +63,11 @@ __device__ inline Seg8 item_seg8(const ItemOps8& s, int64_t i, int64_t j, int64_
 
 __device__ inline bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast(bf16x8, u); }
 
-constexpr int GI = 4;   // items per column-tile group (measured fastest of 2, 3, 4, 8 and 16)
+// Items per column-tile group: four work-groups per group in all (row tiles
+// times items).  Measured on both domain sizes: for one row tile 4 items beat
+// 8 by 3.5 % and 16 by 10 % (2 equal to 4); for two row tiles 2 items beat 4
+// by 1 % and 8 by 20 %.
+__host__ __device__ inline int items_per_group(int mt) { return mt >= 4 ? 1 : 4 / mt; }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const u32x4 guint4;   // global-memory octet
@@ -94,6 +98,7 @@ __global__ __launch_bounds__(256, 2) void k_tgemm_bf16(GemmArgs16 g) {
   // tile order: row tile, then GI consecutive items, then column tile, so the
   // work-groups in flight on one XCD share right-operand slices in its L2
   const int mtile = b % g.mt; b /= g.mt;
+  const int GI = items_per_group(g.mt);
   const int ig = b % GI; b /= GI;
   const int ntile = b % g.nt; b /= g.nt;
   const int batch = b * GI + ig;
@@ -262,6 +267,7 @@ static hipError_t launch16(GemmArgs16 g, hipStream_t s) {
   constexpr int BM = WM * MBW * 32, BN = (4 / WM) * NBW * 32;
   g.mt = (g.M + BM - 1) / BM;
   g.nt = (g.N + BN - 1) / BN;
+  const int GI = items_per_group(g.mt);
   const int64_t nblk = (int64_t)g.mt * g.nt * ((g.nbatch + GI - 1) / GI) * GI;
   if (nblk <= 0) return hipSuccess;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
