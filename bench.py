@@ -19,9 +19,16 @@ The printed JSON line also carries:
                 workload (20,18,160,162,640), FP32 and FP64, with a sampled
                 check against the oracle gradient
 
+Other workloads (not the headline line): --workload large runs the largest
+domain (60,58,500,502,2000); --workload batch runs the set of 64 uneven
+domains through ltriples_energy_batched, eager and as a captured hipGraph
+(first call with capture, then replays).
+
 Profiling aids (not headline measurements): --sample-items K restricts the
-timed step to K sampled triplets per spin block; --copy-calibration runs only
-a plain 1 GiB device copy (for scaling HBM byte counters).
+timed step to K sampled triplets per spin block, --prefix-items K to the
+first K per block in the whole-domain order; --copy-calibration runs only a
+plain 1 GiB device copy (for scaling HBM byte counters); --traffic-from
+writes the HBM traffic summary from counter csv files (no GPU).
 """
 from __future__ import annotations
 
@@ -160,7 +167,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "fp64", "bf16x3", "bf16"])
-    ap.add_argument("--workload", default="lno", choices=["tiny", "lno", "grad", "large"])
+    ap.add_argument("--workload", default="lno", choices=["tiny", "lno", "grad", "large", "batch"])
     ap.add_argument("--fp64-sample", type=int, default=48, help="items per block for the FP64 GPU comparison")
     ap.add_argument("--cpu-sample", type=int, default=3, help="items per block for the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -193,6 +200,9 @@ def main():
         sys.exit(1)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "batch":
+        run_batch(args, lt, synth, torch)
         return
     dev = torch.device("cuda:0")
     prec = lt.PRECISIONS[args.precision]
@@ -372,6 +382,82 @@ def main():
         "backward": backward,
     }
     print(json.dumps(out), flush=True)
+
+
+def run_batch(args, lt, synth, torch):
+    """The 64 uneven domains through ltriples_energy_batched, as two calls of
+    32 domains (even- and odd-indexed, so the halves carry similar work): eager
+    steps, then the graph path (the first call of each half captures its
+    launch sequence and runs it; later calls replay it).  Inputs are generated
+    and copied to the device one domain at a time."""
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    prec = lt.PRECISIONS[args.precision]
+    shapes = synth.batch_shapes()
+    t0 = time.time()
+    tens, dims, F = [], [], []
+    for n in range(len(shapes)):
+        dom = synth.batch_domain(n, shapes)
+        tens.append({k: torch.from_numpy(v).cuda() for k, v in dom.arrays().items()})
+        dims.append(dom.dims)
+        F.append(lt.ltriples_flops(lt.make_domain(dom.dims, tens[-1]), None)[0])
+        del dom
+    torch.cuda.synchronize()
+    halves = [list(range(0, len(shapes), 2)), list(range(1, len(shapes), 2))]
+    Ftot = sum(F)
+    log(f"generated and uploaded {len(shapes)} domains in {time.time() - t0:.1f} s, F = {Ftot:.4e}")
+    opts, _ = lt.make_options()
+    need = max(lt.ltriples_workspace_size_batched([dims[n] for n in h], [tens[n] for n in h], prec, opts)
+               for h in halves)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    outs = [(torch.empty(len(h), dtype=torch.float64, device="cuda"),
+             torch.empty(len(h), 4, 3, dtype=torch.float64, device="cuda")) for h in halves]
+    log(f"workspace {need / 1e9:.1f} GB (shared by the two halves)")
+
+    def step(graph, label):
+        ms = 0.0
+        for k, h in enumerate(halves):
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            lt.ltriples_energy_batched([tens[n] for n in h], [dims[n] for n in h], prec, graph=graph,
+                                       workspace=ws, out=outs[k])
+            ev1.record()
+            torch.cuda.synchronize()
+            ms += ev0.elapsed_time(ev1)
+            log(f"{label}: half {k + 1}/2 done ({ev0.elapsed_time(ev1) / 1e3:.2f} s)")
+        e = np.zeros(len(shapes))
+        for k, h in enumerate(halves):
+            e[h] = outs[k][0].cpu().numpy()
+        return ms, e
+
+    for w in range(args.warmup):
+        step(False, f"warmup {w + 1}")
+    eager = [step(False, f"eager step {k + 1}") for k in range(args.steps)]
+    lt.ltriples_graph_reset()
+    first = step(True, "graph first call")
+    replays = [step(True, f"graph replay {k + 1}") for k in range(args.steps)]
+    lt.ltriples_graph_reset()
+    e_eager, e_graph = eager[-1][1], replays[-1][1]
+    same = bool(np.array_equal(e_eager, e_graph)) and bool(np.array_equal(e_eager, first[1]))
+    ms = sum(x[0] for x in eager) / len(eager)
+    rms = sum(x[0] for x in replays) / len(replays)
+    log(f"eager {ms / 1e3:.2f} s, graph first call {first[0] / 1e3:.2f} s, replay {rms / 1e3:.2f} s, "
+        f"graph == eager: {same}")
+    res = {
+        "metric": METRIC, "value": round(Ftot / (ms * 1e-3) / 1e9, 1), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 2), "higher_is_better": True,
+        "scaling": "strong", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"batch: {len(dims)} uneven domains (nocc 10-40, nvir 80-320, naux 4 nvir), "
+                               "two ltriples_energy_batched calls of 32 domains per step",
+                   "algorithmic_flops": Ftot, "precision": args.precision},
+        "graph": {"first_call_ms": round(first[0], 2), "replay_ms": round(rms, 2),
+                  "replay_GFLOP/s": round(Ftot / (rms * 1e-3) / 1e9, 1), "bitwise_equal_to_eager": same},
+        "E_per_domain": [float(x) for x in e_eager],
+    }
+    print(json.dumps(res), flush=True)
 
 
 def run_backward(lt, synth, torch, log):

@@ -77,3 +77,53 @@ def test_graph_replays_track_inputs(prec):
         torch.cuda.synchronize()
         assert float(e1.item()) == got[0]
     lt.ltriples_graph_reset()
+
+
+def test_batch_config_smallest_domains_bf16x3():
+    """The four smallest domains of the 64-domain batched workload (by flop
+    count), batched in BF16X3, eager and as a captured graph: every domain's
+    E equals the FP64 batched result to 1e-6 of max(1, |E|); FP64 batched
+    equals FP64 single-domain bitwise; and the FP64 path matches the oracle
+    on sampled triplets of each domain to 1e-10."""
+    import torch
+    from tests.gpu_util import gpu_energy
+    shapes = synth.batch_shapes()
+    flops = []
+    for s in shapes:
+        no, nb, va, vb, _ = s
+        flops.append((no ** 3 + nb ** 3) * (va + vb) ** 4)
+    pick = [int(x) for x in np.argsort(flops)[:4]]
+    doms = [synth.batch_domain(n, shapes) for n in pick]
+    print(f"[batch config] domains {pick}: {[d.dims for d in doms]}", flush=True)
+    tens = [to_device(d) for d in doms]
+    dims = [d.dims for d in doms]
+    e64, _ = lt.ltriples_energy_batched(tens, dims, lt.LT_FP64)
+    eb, pb = lt.ltriples_energy_batched(tens, dims, lt.LT_BF16X3)
+    torch.cuda.synchronize()
+    e64, eb = e64.cpu().numpy(), eb.cpu().numpy()
+    for n in range(len(doms)):
+        assert abs(eb[n] - e64[n]) <= TOL_E[lt.LT_BF16X3] * max(1.0, abs(e64[n])), (n, eb[n], e64[n])
+        e1, _ = lt.ltriples_energy(tens[n], dims[n], lt.LT_FP64)
+        torch.cuda.synchronize()
+        assert float(e1.item()) == e64[n], n
+    # graph capture and replays of the BF16X3 batch reproduce the eager call
+    lt.ltriples_graph_reset()
+    opts, _ = lt.make_options()
+    ws = torch.empty(lt.ltriples_workspace_size_batched(dims, tens, lt.LT_BF16X3, opts), dtype=torch.uint8,
+                     device="cuda")
+    out = (torch.empty(len(doms), dtype=torch.float64, device="cuda"),
+           torch.empty(len(doms), 4, 3, dtype=torch.float64, device="cuda"))
+    for rep in range(3):
+        out[0].fill_(float("nan"))
+        lt.ltriples_energy_batched(tens, dims, lt.LT_BF16X3, graph=True, workspace=ws, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out[0].cpu().numpy(), eb), rep
+    lt.ltriples_graph_reset()
+    # FP64 path against the oracle on sampled triplets
+    for n, d in enumerate(doms):
+        items = synth.sample_items(d.noa, d.nob, 2, seed=700 + n)
+        _, _, ei = gpu_energy(d, lt.LT_FP64, items=items, tensors=tens[n])
+        ref = blocks.energy(d, items=items, return_items=True)["items"]
+        for k in range(len(items)):
+            r = ref[k].sum()
+            assert abs(ei[k].sum() - r) <= 1e-10 * max(1.0, abs(r)), (n, items[k], ei[k], ref[k])
