@@ -149,6 +149,51 @@ def test_backward_directional_derivative_gradient_workload():
     assert abs(an - fd) <= 1e-9 * max(abs(fd), 1e-12 * abs(float(e0.item()))), (an, fd)
 
 
+def test_backward_central_differences_random_entries():
+    """50 random entries of the FP64 GPU gradient, spread over all eleven
+    gradient inputs, against central differences (h = 1e-5) of the FP64 GPU
+    energy.  Each difference moves all symmetry images of the entry, so it
+    sees 4x (t2aa, t2bb) or 2x (off-diagonal Boo, Bvv) the returned projected
+    element."""
+    import torch
+    dom = _dom(SHAPES["ragged"])
+    t = to_device(dom)
+    g = _gpu_grad(dom, lt.LT_FP64, tensors=t)
+    rng = np.random.default_rng(2024)
+    h = 1e-5
+    fields = [k for k in lt.GRAD_FIELDS if getattr(dom, k).size > 0]
+    for n in range(50):
+        k = fields[n % len(fields)]
+        x = getattr(dom, k)
+        idx = tuple(int(rng.integers(0, m)) for m in x.shape)
+        images, mult = [(idx, 1.0)], 1.0
+        if k in ("t2aa", "t2bb"):
+            i, j, a, b = idx
+            if i == j or a == b:        # zero by antisymmetry: pick another entry
+                i, j, a, b = 0, 1, 0, 1
+            idx = (i, j, a, b)
+            images = [((i, j, a, b), 1.0), ((j, i, a, b), -1.0), ((i, j, b, a), -1.0), ((j, i, b, a), 1.0)]
+            mult = 4.0
+        elif k in ("Boo_a", "Boo_b", "Bvv_a", "Bvv_b"):
+            q, p, r = idx
+            if p != r:
+                images, mult = [((q, p, r), 1.0), ((q, r, p), 1.0)], 2.0
+        es = []
+        for sgn in (1.0, -1.0):
+            tp = dict(t)
+            y = t[k].clone()
+            for im, w in images:
+                y[im] += sgn * w * h
+            tp[k] = y
+            e, _ = lt.ltriples_energy(tp, dom.dims, lt.LT_FP64)
+            torch.cuda.synchronize()
+            es.append(float(e.item()))
+        fd = (es[0] - es[1]) / (2 * h)
+        want = mult * g[k][idx]
+        scale = np.max(np.abs(g[k]))
+        assert abs(fd - want) <= 1e-6 * scale + 1e-6 * abs(want), (k, idx, fd, want, scale)
+
+
 def test_autograd_function_matches_backward():
     import torch
     dom = _dom(SHAPES["tiny"])
