@@ -208,19 +208,39 @@ __global__ __launch_bounds__(256, 2) void k_tgemm_bf16(GemmArgs16 g) {
       bh[nb] = as_bf16x8(Bs[cur][0][q][bcol + nb * BC]);
       if (NPROD == 3) bl[nb] = as_bf16x8(Bs[cur][1][q][bcol + nb * BC]);
     }
+    // two row blocks at a time, product by product: between two MFMAs on the
+    // same accumulator the pipe gets at least three independent ones (each
+    // accumulator still sums lo*hi, hi*lo, hi*hi in that order)
 #pragma unroll
-    for (int mb = 0; mb < MBW; ++mb) {
-      const bf16x8 ah = as_bf16x8(As[cur][0][q][arow + mb * BR]);
-      bf16x8 al;
-      if (NPROD == 3) al = as_bf16x8(As[cur][1][q][arow + mb * BR]);
+    for (int m2 = 0; m2 < MBW; m2 += 2) {
+      constexpr int P = 2;
+      bf16x8 ah[P], al[P];
 #pragma unroll
-      for (int nb = 0; nb < NBW; ++nb) {
-        if (NPROD == 3) {
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[nb], acc[mb][nb], 0, 0, 0);
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[nb], acc[mb][nb], 0, 0, 0);
+      for (int x = 0; x < P; ++x)
+        if (m2 + x < MBW) {
+          ah[x] = as_bf16x8(As[cur][0][q][arow + (m2 + x) * BR]);
+          if (NPROD == 3) al[x] = as_bf16x8(As[cur][1][q][arow + (m2 + x) * BR]);
         }
-        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[nb], acc[mb][nb], 0, 0, 0);
+      if (NPROD == 3) {
+#pragma unroll
+        for (int x = 0; x < P; ++x)
+#pragma unroll
+          for (int nb = 0; nb < NBW; ++nb)
+            if (m2 + x < MBW)
+              acc[m2 + x][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[x], bh[nb], acc[m2 + x][nb], 0, 0, 0);
+#pragma unroll
+        for (int x = 0; x < P; ++x)
+#pragma unroll
+          for (int nb = 0; nb < NBW; ++nb)
+            if (m2 + x < MBW)
+              acc[m2 + x][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bl[nb], acc[m2 + x][nb], 0, 0, 0);
       }
+#pragma unroll
+      for (int x = 0; x < P; ++x)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb)
+          if (m2 + x < MBW)
+            acc[m2 + x][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bh[nb], acc[m2 + x][nb], 0, 0, 0);
     }
     if (more) sstore(cur ^ 1);
     __syncthreads();
