@@ -386,7 +386,7 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
     if (!blk_mixed(b)) {
       outb = ts * (size_t)(vs * P.ldnp[s]);
       const int64_t n = cdiv(vs, lt::ET);
-      nt = n * (n + 1) * (n + 2) / 6;
+      nt = n * (n + 1) / 2;            // one partial per (a-tile <= b-tile) pair
     } else {
       outb = ts * (size_t)(vs * P.ldcb[s] + vt * P.ldnp[s]);
       const int64_t ns = cdiv(vs, lt::ET);
@@ -1455,7 +1455,11 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
         lt::BwdSame<T> e{};
         e.e.o = (int32_t)os; e.e.v = (int32_t)vs; e.e.ld_np = P.ldnp[s];
         e.e.S = S; e.e.s_item = (int64_t)(o1 / P.ts); e.e.items = items;
-        e.e.nt = (int32_t)cdiv(vs, lt::ET); e.e.ntri = (int32_t)nt;
+        {
+          const int64_t nt1 = cdiv(vs, lt::ET);
+          e.e.nt = (int32_t)nt1;
+          e.e.ntri = (int32_t)(nt1 * (nt1 + 1) * (nt1 + 2) / 6);   // backward grid: a <= b <= c tiles
+        }
         e.e.eo = EO[s]; e.e.ev = EV[s]; e.e.t1 = T1[s]; e.e.f = Fov[s]; e.e.t2 = T2ss[s];
         e.e.U = at<double>(ws, P.U[s]); e.e.ld_v = P.ldv[s];
         e.gbar = gbar;

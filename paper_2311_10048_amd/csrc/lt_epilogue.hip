@@ -70,22 +70,29 @@ __device__ inline double rcp64(double d) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_epi_same(EpiSame<T> a) {
+__global__ __launch_bounds__(256, 2) void k_epi_same(EpiSame<T> a) {
+  // One work-group per (item, a-tile <= b-tile) walks the c-tiles from the
+  // b-tile on; the operands of the next c-tile are loaded into registers while
+  // the current one is computed, and the (a, b) and a-only operands are
+  // staged once.  One FP64 partial per work-group.
   __shared__ T Sb[ET][SROW];        // S[b][p(a,c)]
   __shared__ T Sc[ET][SROW];        // S[c][p(a,b)]
-  __shared__ double Uac[3][ET][ET + 1], Uba[3][ET][ET + 1], Tac[3][ET][ET + 1], Tba[3][ET][ET + 1];
+  __shared__ double Uac[3][ET][ET + 1], Tac[3][ET][ET + 1];   // per c-tile
+  __shared__ double Uba[3][ET][ET + 1], Tba[3][ET][ET + 1];   // once
   __shared__ double t1a[3][ET], fa[3][ET], eva[ET];
+  __shared__ double t1cs[3][ET], fcs[3][ET], evcs[ET];         // per c-tile
 
   const int tid = threadIdx.x;
-  int TA, TB, TC;
   const int L = xcd_logical(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-  const int tix = L % gridDim.x;
-  tri_decode(tix, TA, TB, TC);
+  const int pi = L % gridDim.x;
+  int TB = 0;
+  while ((TB + 1) * (TB + 2) / 2 <= pi) ++TB;
+  const int TA = pi - TB * (TB + 1) / 2;
   const int item = L / gridDim.x;
   const int32_t* it = a.items + 3 * item;
   const int occ[3] = {it[0], it[1], it[2]};
   const int v = a.v;
-  const int a0 = TA * ET, b0 = TB * ET, c0 = TC * ET;
+  const int a0 = TA * ET, b0 = TB * ET;
   const T* S = a.S + (int64_t)item * a.s_item;
   const int64_t ldp = a.ld_np;
   // occupied pair (q, r), sign and t1 index of the three occupied permutations
@@ -93,28 +100,20 @@ __global__ __launch_bounds__(256) void k_epi_same(EpiSame<T> a) {
   const int pr[3] = {occ[2], occ[2], occ[0]};
   const double sg[3] = {1.0, -1.0, -1.0};
   const int64_t vv = (int64_t)v * v;
-
-  for (int e = tid; e < ET * ET * ET; e += 256) {
-    const int ta = e & 15, tb = (e >> 4) & 15, tc = e >> 8;
-    const int aa = a0 + ta, bb = b0 + tb, cc = c0 + tc;
-    T x = 0, y = 0;
-    if (cc < v && bb < v) {
-      if (aa < cc) x = S[bb * ldp + (int64_t)cc * (cc - 1) / 2 + aa];
-      if (aa < bb) y = S[cc * ldp + (int64_t)bb * (bb - 1) / 2 + aa];
-    }
-    Sb[ta][tc * ET + tb] = x;
-    Sc[ta][tc * ET + tb] = y;
+  int64_t ub[3], tb2[3];
+#pragma unroll
+  for (int pp = 0; pp < 3; ++pp) {
+    ub[pp] = ((int64_t)pq[pp] * a.o + pr[pp]) * v * a.ld_v;
+    tb2[pp] = ((int64_t)pq[pp] * a.o + pr[pp]) * vv;
   }
+
+  // (a, b) and a-only operands
   for (int e = tid; e < 3 * ET * ET; e += 256) {
     const int pp = e / (ET * ET), r = e % (ET * ET), ta = r & 15, tx = r >> 4;
-    const int aa = a0 + ta, cc = c0 + tx, bb = b0 + tx;
-    const int64_t ub = ((int64_t)pq[pp] * a.o + pr[pp]) * v * a.ld_v;
-    const int64_t tb_ = ((int64_t)pq[pp] * a.o + pr[pp]) * vv;
-    const bool ac = aa < v && cc < v, ba = aa < v && bb < v;
-    Uac[pp][ta][tx] = ac ? a.U[ub + aa * a.ld_v + cc] : 0.0;
-    Tac[pp][ta][tx] = ac ? a.t2[tb_ + aa * v + cc] : 0.0;
-    Uba[pp][tx][ta] = ba ? a.U[ub + bb * a.ld_v + aa] : 0.0;
-    Tba[pp][tx][ta] = ba ? a.t2[tb_ + bb * v + aa] : 0.0;
+    const int aa = a0 + ta, bb = b0 + tx;
+    const bool ba = aa < v && bb < v;
+    Uba[pp][tx][ta] = ba ? a.U[ub[pp] + bb * a.ld_v + aa] : 0.0;
+    Tba[pp][tx][ta] = ba ? a.t2[tb2[pp] + bb * v + aa] : 0.0;
   }
   if (tid < 3 * ET) {
     const int pp = tid / ET, ta = tid % ET, aa = a0 + ta;
@@ -124,46 +123,118 @@ __global__ __launch_bounds__(256) void k_epi_same(EpiSame<T> a) {
     const int ta = tid - 3 * ET, aa = a0 + ta;
     eva[ta] = aa < v ? a.ev[aa] : 0.0;
   }
-  __syncthreads();
-
   const int tb = tid & 15, tc = tid >> 4;
-  const int b = b0 + tb, c = c0 + tc;
-  double e4 = 0.0, est = 0.0, edt = 0.0;
-  if (b < c && c < v) {
-    double Ubc[3], Tbc[3], t1b[3], fb[3], t1c[3], fc[3];
+  const int b = b0 + tb;
+  const bool brow = b < v;
+  double t1b[3], fb[3];
 #pragma unroll
-    for (int pp = 0; pp < 3; ++pp) {
-      const int64_t blk = (int64_t)pq[pp] * a.o + pr[pp];
-      Ubc[pp] = sg[pp] * a.U[blk * v * a.ld_v + b * a.ld_v + c];
-      Tbc[pp] = sg[pp] * a.t2[blk * vv + (int64_t)b * v + c];
-      t1b[pp] = sg[pp] * a.t1[(int64_t)occ[pp] * v + b];
-      fb[pp] = sg[pp] * a.f[(int64_t)occ[pp] * v + b];
-      t1c[pp] = sg[pp] * a.t1[(int64_t)occ[pp] * v + c];
-      fc[pp] = sg[pp] * a.f[(int64_t)occ[pp] * v + c];
+  for (int pp = 0; pp < 3; ++pp) {
+    t1b[pp] = brow ? sg[pp] * a.t1[(int64_t)occ[pp] * v + b] : 0.0;
+    fb[pp] = brow ? sg[pp] * a.f[(int64_t)occ[pp] * v + b] : 0.0;
+  }
+  const double dob = (a.eo[occ[0]] + a.eo[occ[1]] + a.eo[occ[2]]) - (brow ? a.ev[b] : 0.0);
+  const int na = min(ET, b - a0);
+
+  // staging of one c-tile: elements tid + 256*u of the two permuted S blocks,
+  // one element of each (a, c) block, one c-only value (threads 0..111), and
+  // the thread's own (b, c) operands and direct-term run
+  T rg[ET], ry[ET], rd[ET];
+  double ruac[3], rtac[3], rUbc[3], rTbc[3], rcv;
+  auto fetch = [&](int TCn) {
+    const int c0 = TCn * ET;
+#pragma unroll
+    for (int u = 0; u < ET; ++u) {
+      const int e = tid + 256 * u;
+      const int ta = e & 15, tbb = (e >> 4) & 15, tcc = e >> 8;
+      const int aa = a0 + ta, bb = b0 + tbb, cc = c0 + tcc;
+      T x = 0, y = 0;
+      if (cc < v && bb < v) {
+        if (aa < cc) x = S[bb * ldp + (int64_t)cc * (cc - 1) / 2 + aa];
+        if (aa < bb) y = S[cc * ldp + (int64_t)bb * (bb - 1) / 2 + aa];
+      }
+      rg[u] = x;
+      ry[u] = y;
     }
-    const double dbc = (a.eo[occ[0]] + a.eo[occ[1]] + a.eo[occ[2]]) - a.ev[b] - a.ev[c];
-    const T* Srow = S + (int64_t)c * (c - 1) / 2 + b;
-    const int na = min(ET, b - a0);
-    T sd[ET];                        // direct-term operands, loaded in one burst
-#pragma unroll
-    for (int ta = 0; ta < ET; ++ta) sd[ta] = ta < na ? Srow[(a0 + ta) * ldp] : (T)0;
-#pragma unroll
-    for (int ta = 0; ta < ET; ++ta) {
-      if (ta >= na) break;
-      const double w = (double)sd[ta] - (double)Sb[ta][tc * ET + tb] + (double)Sc[ta][tc * ET + tb];
-      double vt = 0.0, vf = 0.0;
+    {
+      const int ta = tid & 15, tx = tid >> 4, aa = a0 + ta, cc = c0 + tx;
+      const bool ac = aa < v && cc < v;
 #pragma unroll
       for (int pp = 0; pp < 3; ++pp) {
-        vt += t1a[pp][ta] * Ubc[pp] - t1b[pp] * Uac[pp][ta][tc] - t1c[pp] * Uba[pp][tb][ta];
-        vf += fa[pp][ta] * Tbc[pp] - fb[pp] * Tac[pp][ta][tc] - fc[pp] * Tba[pp][tb][ta];
+        ruac[pp] = ac ? a.U[ub[pp] + aa * a.ld_v + cc] : 0.0;
+        rtac[pp] = ac ? a.t2[tb2[pp] + aa * v + cc] : 0.0;
       }
-      const double wd = w * rcp64(dbc - eva[ta]);
-      e4 += wd * w;
-      est += wd * vt;
-      edt += wd * vf;
+    }
+    const int c = c0 + tc;
+    const bool ok = brow && b < c && c < v;
+#pragma unroll
+    for (int pp = 0; pp < 3; ++pp) {
+      rUbc[pp] = ok ? sg[pp] * a.U[ub[pp] + b * a.ld_v + c] : 0.0;
+      rTbc[pp] = ok ? sg[pp] * a.t2[tb2[pp] + (int64_t)b * v + c] : 0.0;
+    }
+    {
+      // c-only values: t1 (threads 0..47), f_ov (48..95), e_vir (96..111)
+      const int x = tid & 15, cc = c0 + x, pp = (tid >> 4) % 3;
+      rcv = 0.0;
+      if (cc < v) {
+        if (tid < 48) rcv = sg[pp] * a.t1[(int64_t)occ[pp] * v + cc];
+        else if (tid < 96) rcv = sg[pp] * a.f[(int64_t)occ[pp] * v + cc];
+        else if (tid < 112) rcv = a.ev[cc];
+      }
+    }
+    const T* Srow = S + (int64_t)c * (c - 1) / 2 + b;
+#pragma unroll
+    for (int ta = 0; ta < ET; ++ta) rd[ta] = (ok && ta < na) ? Srow[(a0 + ta) * ldp] : (T)0;
+  };
+
+  double e4 = 0.0, est = 0.0, edt = 0.0;
+  fetch(TB);
+  for (int TC = TB; TC < a.nt; ++TC) {
+    __syncthreads();                 // previous tile's LDS reads are done (first pass: nothing)
+#pragma unroll
+    for (int u = 0; u < ET; ++u) {
+      const int e = tid + 256 * u;
+      Sb[e & 15][(e >> 8) * ET + ((e >> 4) & 15)] = rg[u];
+      Sc[e & 15][(e >> 8) * ET + ((e >> 4) & 15)] = ry[u];
+    }
+#pragma unroll
+    for (int pp = 0; pp < 3; ++pp) {
+      Uac[pp][tid & 15][tid >> 4] = ruac[pp];
+      Tac[pp][tid & 15][tid >> 4] = rtac[pp];
+    }
+    if (tid < 48) t1cs[(tid >> 4) % 3][tid & 15] = rcv;
+    else if (tid < 96) fcs[(tid >> 4) % 3][tid & 15] = rcv;
+    else if (tid < 112) evcs[tid & 15] = rcv;
+    double Ubc[3], Tbc[3];
+#pragma unroll
+    for (int pp = 0; pp < 3; ++pp) { Ubc[pp] = rUbc[pp]; Tbc[pp] = rTbc[pp]; }
+    const int c = TC * ET + tc;
+    const bool ok = brow && b < c && c < v;
+    T sd[ET];
+#pragma unroll
+    for (int ta = 0; ta < ET; ++ta) sd[ta] = rd[ta];
+    __syncthreads();
+    double t1c[3], fc[3];
+#pragma unroll
+    for (int pp = 0; pp < 3; ++pp) { t1c[pp] = t1cs[pp][tc]; fc[pp] = fcs[pp][tc]; }
+    const double dbc = dob - evcs[tc];
+    if (TC + 1 < a.nt) fetch(TC + 1);   // next tile's loads in flight during this tile's work
+    if (ok) {
+      for (int ta = 0; ta < na; ++ta) {
+        const double w = (double)sd[ta] - (double)Sb[ta][tc * ET + tb] + (double)Sc[ta][tc * ET + tb];
+        double vt = 0.0, vf = 0.0;
+#pragma unroll
+        for (int pp = 0; pp < 3; ++pp) {
+          vt += t1a[pp][ta] * Ubc[pp] - t1b[pp] * Uac[pp][ta][tc] - t1c[pp] * Uba[pp][tb][ta];
+          vf += fa[pp][ta] * Tbc[pp] - fb[pp] * Tac[pp][ta][tc] - fc[pp] * Tba[pp][tb][ta];
+        }
+        const double wd = w * rcp64(dbc - eva[ta]);
+        e4 += wd * w;
+        est += wd * vt;
+        edt += wd * vf;
+      }
     }
   }
-  block_write3(e4, est, edt, a.part + ((int64_t)item * a.ntri + tix) * 3);
+  block_write3(e4, est, edt, a.part + ((int64_t)item * a.ntri + pi) * 3);
 }
 
 // Mixed blocks: one work-group per (item, a-tile <= b-tile) walks all C
