@@ -483,14 +483,14 @@ def run_backward(lt, synth, torch, log):
         del ws, g
     items = synth.sample_items(dom.noa, dom.nob, 1, seed=77)
     tc = time.perf_counter()
-    _, ref = ograd.energy_and_grad(dom, items=items)
+    _, ref = ograd.energy_and_grad(dom, items=items, fock=True)
     dt = time.perf_counter() - tc
     err = {}
     for name, prec in (("fp32", lt.LT_FP32), ("fp64", lt.LT_FP64)):
         g = lt.ltriples_backward(tens, dom.dims, prec, items=items)
         torch.cuda.synchronize()
         worst = 0.0
-        for k in lt.GRAD_FIELDS:
+        for k in lt.GRAD_FIELDS + lt.FOCK_GRAD_FIELDS:
             r = ref[k]
             if r.size:
                 worst = max(worst, float(np.max(np.abs(g[k].cpu().numpy() - r)) / np.max(np.abs(r))))

@@ -172,14 +172,15 @@ int ltriples_energy(const ltriples_domain* d, int32_t precision,
 typedef struct {
   double *t1a, *t1b, *t2aa, *t2bb, *t2ab;
   double *Boo_a, *Bov_a, *Bvv_a, *Boo_b, *Bov_b, *Bvv_b;
+  double *fov_a, *fov_b;               /* dE/df_ia (f_ov enters V linearly) */
 } ltriples_domain_grad;
 
 /* Host-only: workspace bytes of ltriples_backward. */
 int ltriples_backward_workspace_size(const ltriples_domain* d, int32_t precision,
                                      const ltriples_options* o, size_t* bytes);
 
-/* Adjoint of ltriples_energy: gbar * dE/dx for x in T1, T2 and the DF
- * factors (orbital energies and f_ov are constants here).  E is the energy
+/* Adjoint of ltriples_energy: gbar * dE/dx for x in T1, T2, the DF factors
+ * and f_ov (the orbital energies are constants here).  E is the energy
  * of eq. cim_pt_energy as read by ltriples_energy (all occupied triplets, or
  * the item subset of options.items).  The connected W is recomputed per item
  * batch, never stored; the work is about three times the forward flops.

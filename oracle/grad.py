@@ -1,5 +1,6 @@
-"""Gradient of the spin-blocked (T) energy with respect to the amplitudes and
-the density-fitting factors (FP64, CPU).
+"""Gradient of the spin-blocked (T) energy with respect to the amplitudes, the
+density-fitting factors and, on request, the occupied-virtual Fock block f_ov
+(FP64, CPU).
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py); never used by the product.
 
@@ -12,7 +13,8 @@ this transcription is checked against oracle.blocks, and its gradient
 against exact finite-difference stencils of oracle.blocks and of the
 brute-force spin-orbital energy (E is a quadratic polynomial in (T1, T2) and
 a quartic one in B, so a 3-point resp. 5-point central stencil is exact up
-to rounding).
+to rounding; f_ov enters only V, linearly, so E is a quadratic polynomial in
+it as well).
 
 Convention for inputs that carry a symmetry (the projected gradient): the
 returned dE/dt2aa and dE/dt2bb are antisymmetrised in (i,j) and (a,b), dE/dBoo
@@ -27,6 +29,7 @@ import numpy as np
 import torch
 
 FIELDS = ("t1a", "t1b", "t2aa", "t2bb", "t2ab", "Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b")
+FOCK_FIELDS = ("fov_a", "fov_b")
 
 
 def _mixed_amp(X, s):
@@ -175,9 +178,10 @@ def project(grads):
     return out
 
 
-def energy_and_grad(dom, items=None, gbar=1.0, threads=None):
+def energy_and_grad(dom, items=None, gbar=1.0, threads=None, fock=False):
     """E(T) of the domain (or of an item subset) and gbar * dE/dx for every
-    field in FIELDS (projected convention), as float64 numpy arrays."""
+    field in FIELDS (projected convention), as float64 numpy arrays; with
+    `fock`, also for the fields of FOCK_FIELDS (f_ov carries no constraint)."""
     from oracle.blocks import enumerate_items
     if threads:
         torch.set_num_threads(int(threads))
@@ -185,7 +189,8 @@ def energy_and_grad(dom, items=None, gbar=1.0, threads=None):
         items = enumerate_items(dom.noa, dom.nob)
     items = np.asarray(items).reshape(-1, 4)
     X = {k: torch.tensor(np.asarray(getattr(dom, k)), dtype=torch.float64, requires_grad=True) for k in FIELDS}
-    C = {k: torch.tensor(np.asarray(getattr(dom, k)), dtype=torch.float64)
+    C = {k: torch.tensor(np.asarray(getattr(dom, k)), dtype=torch.float64,
+                         requires_grad=bool(fock) and k in FOCK_FIELDS)
          for k in ("fov_a", "fov_b", "eo_a", "ev_a", "eo_b", "ev_b")}
     it = _Item(X, C)
     E = 0.0
@@ -195,4 +200,8 @@ def energy_and_grad(dom, items=None, gbar=1.0, threads=None):
         E += float(e.detach())
     grads = {k: (X[k].grad.numpy().copy() if X[k].grad is not None else np.zeros(X[k].shape))
              for k in FIELDS}
-    return E, project(grads)
+    grads = project(grads)
+    if fock:
+        for k in FOCK_FIELDS:
+            grads[k] = C[k].grad.numpy().copy() if C[k].grad is not None else np.zeros(C[k].shape)
+    return E, grads

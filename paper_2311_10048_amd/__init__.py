@@ -77,10 +77,11 @@ class Options(ctypes.Structure):
 
 
 GRAD_FIELDS = ("t1a", "t1b", "t2aa", "t2bb", "t2ab", "Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b")
+FOCK_GRAD_FIELDS = ("fov_a", "fov_b")
 
 
 class DomainGrad(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_void_p) for n in GRAD_FIELDS]
+    _fields_ = [(n, ctypes.c_void_p) for n in GRAD_FIELDS + FOCK_GRAD_FIELDS]
 
 
 class LtError(RuntimeError):
@@ -311,9 +312,10 @@ def ltriples_backward(tensors: Mapping[str, object], dims, precision: int = LT_F
                       batch_budget: int = 0, batch_items: int = 0, workspace=None, out=None, stream=None,
                       stats: Optional[Stats] = None, build_chunk_mib: int = 0):
     """gbar * dE/dx for x in GRAD_FIELDS (projected convention for t2aa, t2bb,
-    Boo, Bvv).  Returns a dict of float64 device tensors shaped like the
-    inputs.  `gbar` is a float64 device tensor with one element (default 1);
-    `out` may supply the output tensors (a dict keyed like the result)."""
+    Boo, Bvv) and FOCK_GRAD_FIELDS (f_ov).  Returns a dict of float64 device
+    tensors shaped like the inputs.  `gbar` is a float64 device tensor with
+    one element (default 1); `out` may supply the output tensors (a dict keyed
+    like the result; missing keys are not computed)."""
     import torch
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
@@ -325,9 +327,9 @@ def ltriples_backward(tensors: Mapping[str, object], dims, precision: int = LT_F
     if gbar.dtype != torch.float64 or gbar.numel() != 1 or not gbar.is_contiguous():
         raise ValueError("gbar must be one contiguous float64 element")
     if out is None:
-        out = {k: torch.empty_like(tensors[k]) for k in GRAD_FIELDS}
+        out = {k: torch.empty_like(tensors[k]) for k in GRAD_FIELDS + FOCK_GRAD_FIELDS}
     g = DomainGrad()
-    for k in GRAD_FIELDS:
+    for k in GRAD_FIELDS + FOCK_GRAD_FIELDS:
         setattr(g, k, _ptr(out.get(k)))
     need = ltriples_backward_workspace_size(dom, precision, opts)
     if workspace is None:
@@ -344,8 +346,8 @@ def _autograd_function():
     import torch
 
     class TriplesEnergy(torch.autograd.Function):
-        """E(T) as a differentiable function of T1, T2 and the DF factors
-        (orbital energies and f_ov are constants)."""
+        """E(T) as a differentiable function of T1, T2, the DF factors and
+        f_ov (the orbital energies are constants)."""
 
         @staticmethod
         def forward(ctx, precision, dims, *arrays):

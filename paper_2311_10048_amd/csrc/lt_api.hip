@@ -186,7 +186,7 @@ struct Plan {
   // operands, same layouts), FP64 four-index integral gradients, descriptors
   bool bwd = false;
   Buf T1p[2], Fp[2], Up[2], OVc[2], BvvP64[2];
-  Buf dT2T[2], dTp[2], dAs[2], dGamT[2], dUp[2], dT1p[2];
+  Buf dT2T[2], dTp[2], dAs[2], dGamT[2], dUp[2], dT1p[2], dFp[2];
   Buf dLmixT[2], dMst[2], dMts[2], dTmix[2], dZpT[2], dTmT[2], dOOT[2], dOVc[2];
   Buf dOVVV[2][2], dOVOO[2][2], dOVOV[3];   // ovov: aa, bb, ab
   Buf rblk, rseg, dfblk, dfseg, rred, dfred, rpart;
@@ -300,7 +300,7 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
       const bool need_df = P.need_as[s] || P.any_mix;
       if (need_df) take(P.BvvP64[s], 8 * Q * P.ldvv[s]);
       if (need_df) { take(P.T1p[s], ts * os * P.ldv[s]); take(P.Fp[s], ts * os * P.ldv[s]); }
-      if (need_df) take(P.dT1p[s], ts * os * P.ldv[s]);
+      if (need_df) { take(P.dT1p[s], ts * os * P.ldv[s]); take(P.dFp[s], ts * os * P.ldv[s]); }
       if (P.need_as[s]) {
         take(P.Up[s], ts * os * os * P.ldnp[s]);
         take(P.dAs[s], P.As[s].bytes); take(P.dTp[s], P.Tp[s].bytes); take(P.dT2T[s], P.T2T[s].bytes);
@@ -1116,6 +1116,7 @@ void build_rev(const Plan& P, const ItemLists& L, char* ws, RevBuilder<T>& rb,
     T *T2T = A(P.T2T[s]), *dT2T = A(P.dT2T[s]), *As = A(P.As[s]), *dAs = A(P.dAs[s]);
     T *Gam = A(P.GamT[s]), *dGam = A(P.dGamT[s]), *Tp = A(P.Tp[s]), *dTp = A(P.dTp[s]);
     T *Up = A(P.Up[s]), *dUp = A(P.dUp[s]), *T1p = A(P.T1p[s]), *dT1p = A(P.dT1p[s]), *Fp = A(P.Fp[s]);
+    T* dFp = A(P.dFp[s]);
     for (int64_t first = 0; first < nblk; first += nb) {
       const int64_t n = std::min<int64_t>(nb, nblk - first);
       const size_t l0 = rb.launches.size();
@@ -1143,7 +1144,7 @@ void build_rev(const Plan& P, const ItemLists& L, char* ws, RevBuilder<T>& rb,
             const int64_t orow = (q * os + r) * lp;
             add_rev(rb, FSeg<T>{T1p + p * lv, dT1p + p * lv, lv, Up + orow, dUp + orow, lp, 1, sg[u], 4, 5},
                     dSVm, lp, vs, np);
-            add_rev(rb, FSeg<T>{Fp + p * lv, nullptr, lv, Tp + orow, dTp + orow, lp, 1, sg[u], 4, -1},
+            add_rev(rb, FSeg<T>{Fp + p * lv, dFp + p * lv, lv, Tp + orow, dTp + orow, lp, 1, sg[u], 4, 5},
                     dSVm, lp, vs, np);
           }
         }
@@ -1153,7 +1154,7 @@ void build_rev(const Plan& P, const ItemLists& L, char* ws, RevBuilder<T>& rb,
         T *Mts = A(P.Mts[s]), *dMts = A(P.dMts[s]), *Tmix = A(P.Tmix[s]), *dTmix = A(P.dTmix[s]);
         T *ZpT = A(P.ZpT[s]), *dZpT = A(P.dZpT[s]), *TmT = A(P.TmT[s]), *dTmT = A(P.dTmT[s]);
         T *OOT = A(P.OOT[s]), *dOOT = A(P.dOOT[s]), *OVc = A(P.OVc[s]), *dOVc = A(P.dOVc[s]);
-        T *T1t = A(P.T1p[t]), *dT1t = A(P.dT1p[t]), *Ft = A(P.Fp[t]);
+        T *T1t = A(P.T1p[t]), *dT1t = A(P.dT1p[t]), *Ft = A(P.Fp[t]), *dFt = A(P.dFp[t]);
         const size_t q1 = (size_t)nb * (o1 + o2);
         T* dG = (T*)(scr + q1);
         T* dY = (T*)(scr + q1 + (size_t)nb * o1);
@@ -1201,14 +1202,14 @@ void build_rev(const Plan& P, const ItemLists& L, char* ws, RevBuilder<T>& rb,
             const int64_t p = pq[u][0], q = pq[u][1], orow = (q * ot + K) * lc;
             add_rev(rb, FSeg<T>{T1p + p * lv, dT1p + p * lv, lv, OVc + orow, dOVc + orow, lc, 1, sg[u], 12, 13},
                     dGVm, lc, M1, N1);
-            add_rev(rb, FSeg<T>{Fp + p * lv, nullptr, lv, Tmix + orow, dTmix + orow, lc, 1, sg[u], 12, -1},
+            add_rev(rb, FSeg<T>{Fp + p * lv, dFp + p * lv, lv, Tmix + orow, dTmix + orow, lc, 1, sg[u], 12, 13},
                     dGVm, lc, M1, N1);
           }
           // t1[K][C] <ij||ab>, f[K][C] t^{ab}_{ij}
           const int64_t orow = (i * os + j) * lp;
           add_rev(rb, FSeg<T>{T1t + K * lvt, dT1t + K * lvt, lvt, Up + orow, dUp + orow, lp, 1, 1.f, 12, 13},
                   dYVm, lp, M2, N2);
-          add_rev(rb, FSeg<T>{Ft + K * lvt, nullptr, lvt, Tp + orow, dTp + orow, lp, 1, 1.f, 12, -1},
+          add_rev(rb, FSeg<T>{Ft + K * lvt, dFt + K * lvt, lvt, Tp + orow, dTp + orow, lp, 1, 1.f, 12, 13},
                   dYVm, lp, M2, N2);
         }
         rb.flush();
@@ -1355,7 +1356,8 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
   struct Z { double* p; int64_t n; } outs[] = {
       {gr->t1a, oa * va}, {gr->t1b, ob * vb}, {gr->t2aa, oa * oa * va * va}, {gr->t2bb, ob * ob * vb * vb},
       {gr->t2ab, oa * ob * va * vb}, {gr->Boo_a, Q * oa * oa}, {gr->Bov_a, Q * oa * va}, {gr->Bvv_a, Q * va * va},
-      {gr->Boo_b, Q * ob * ob}, {gr->Bov_b, Q * ob * vb}, {gr->Bvv_b, Q * vb * vb}};
+      {gr->Boo_b, Q * ob * ob}, {gr->Bov_b, Q * ob * vb}, {gr->Bvv_b, Q * vb * vb},
+      {gr->fov_a, oa * va}, {gr->fov_b, ob * vb}};
   for (auto& z : outs)
     if (z.p) HIPCHK(lt::launch_zero(z.p, z.n, st));
   if (L.total == 0 || (va == 0 && vb == 0)) {
@@ -1365,7 +1367,8 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
   }
   {
     const Buf* zb[] = {&P.dT2T[0], &P.dT2T[1], &P.dTp[0], &P.dTp[1], &P.dAs[0], &P.dAs[1], &P.dGamT[0],
-                       &P.dGamT[1], &P.dUp[0], &P.dUp[1], &P.dT1p[0], &P.dT1p[1], &P.dLmixT[0], &P.dLmixT[1],
+                       &P.dGamT[1], &P.dUp[0], &P.dUp[1], &P.dT1p[0], &P.dT1p[1], &P.dFp[0], &P.dFp[1],
+                       &P.dLmixT[0], &P.dLmixT[1],
                        &P.dMst[0], &P.dMst[1], &P.dMts[0], &P.dMts[1], &P.dTmix[0], &P.dTmix[1], &P.dZpT[0],
                        &P.dZpT[1], &P.dTmT[0], &P.dTmT[1], &P.dOOT[0], &P.dOOT[1], &P.dOVc[0], &P.dOVc[1],
                        &P.dOVVV[0][0], &P.dOVVV[0][1], &P.dOVVV[1][0], &P.dOVVV[1][1], &P.dOVOO[0][0],
@@ -1520,6 +1523,7 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
   auto Tb = [&](const Buf& b) { return at<T>(ws, b); };
   auto Db = [&](const Buf& b) { return at<double>(ws, b); };
   double* gT1[2] = {gr->t1a, gr->t1b};
+  double* gF[2] = {gr->fov_a, gr->fov_b};
   double* gT2[2] = {gr->t2aa, gr->t2bb};
   for (int s = 0; s < 2; ++s) {
     const int t = 1 - s;
@@ -1527,6 +1531,10 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
     if (P.dT1p[s].bytes && gT1[s]) {
       const int64_t dd[4] = {1, 1, o, v}, os_[4] = {0, 0, v, 1}, is_[4] = {0, 0, lv, 1};
       HIPCHK(lt::launch_perm_acc<T>(gT1[s], dd, os_, Tb(P.dT1p[s]), is_, 1.0, st));
+    }
+    if (P.dFp[s].bytes && gF[s]) {
+      const int64_t dd[4] = {1, 1, o, v}, os_[4] = {0, 0, v, 1}, is_[4] = {0, 0, lv, 1};
+      HIPCHK(lt::launch_perm_acc<T>(gF[s], dd, os_, Tb(P.dFp[s]), is_, 1.0, st));
     }
     if (P.need_as[s]) {
       if (gT2[s]) {
@@ -1814,7 +1822,8 @@ int plan_check_bwd(const Plan& P, const ItemLists& L, bool element_check) {
                       &P.OOT[1], &P.OVab, &P.T1p[0], &P.T1p[1], &P.Fp[0], &P.Fp[1], &P.Up[0], &P.Up[1],
                       &P.OVc[0], &P.OVc[1], &P.BvvP64[0], &P.BvvP64[1], &P.dT2T[0], &P.dT2T[1], &P.dTp[0],
                       &P.dTp[1], &P.dAs[0], &P.dAs[1], &P.dGamT[0], &P.dGamT[1], &P.dUp[0], &P.dUp[1],
-                      &P.dT1p[0], &P.dT1p[1], &P.dLmixT[0], &P.dLmixT[1], &P.dMst[0], &P.dMst[1], &P.dMts[0],
+                      &P.dT1p[0], &P.dT1p[1], &P.dFp[0], &P.dFp[1], &P.dLmixT[0], &P.dLmixT[1], &P.dMst[0],
+                      &P.dMst[1], &P.dMts[0],
                       &P.dMts[1], &P.dTmix[0], &P.dTmix[1], &P.dZpT[0], &P.dZpT[1], &P.dTmT[0], &P.dTmT[1],
                       &P.dOOT[0], &P.dOOT[1], &P.dOVc[0], &P.dOVc[1], &P.dOVVV[0][0], &P.dOVVV[0][1],
                       &P.dOVVV[1][0], &P.dOVVV[1][1], &P.dOVOO[0][0], &P.dOVOO[0][1], &P.dOVOO[1][0],

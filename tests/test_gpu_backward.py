@@ -5,7 +5,8 @@ FP64 energy, pinned by exact finite-difference stencils).  Bar per gradient
 tensor: max|g_gpu - g_ref| <= tol * max|g_ref| with tol 1e-10 (FP64) and 1e-5
 (FP32).  At the full gradient workload (20,18,160,162,640) the check is the
 oracle gradient of a sampled item subset, and the exact directional
-derivative of the GPU's own FP64 energy (E is quadratic in T1, T2).
+derivative of the GPU's own FP64 energy (E is quadratic in T1, T2 and
+linear in f_ov).
 """
 import numpy as np
 import pytest
@@ -18,6 +19,7 @@ from tests.gpu_util import to_device
 pytestmark = pytest.mark.gpu
 
 TOL = {lt.LT_FP64: 1e-10, lt.LT_FP32: 1e-5}
+ALL_GRAD = lt.GRAD_FIELDS + lt.FOCK_GRAD_FIELDS
 
 SHAPES = {
     "tiny": (5, 4, 30, 31, 120),
@@ -43,7 +45,9 @@ def _gpu_grad(dom, prec, tensors=None, **kw):
 
 
 def _compare(g, ref, tol, label=""):
-    for k in lt.GRAD_FIELDS:
+    for k in ALL_GRAD:
+        if k not in ref:
+            continue
         r = ref[k]
         if r.size == 0:
             continue
@@ -57,7 +61,7 @@ def _compare(g, ref, tol, label=""):
 def test_backward_parity_shapes(name, prec):
     dom = _dom(SHAPES[name])
     print(f"[backward] {name} {SHAPES[name]} prec={prec}", flush=True)
-    _, ref = ograd.energy_and_grad(dom)
+    _, ref = ograd.energy_and_grad(dom, fock=True)
     g = _gpu_grad(dom, prec)
     _compare(g, ref, TOL[prec], name)
 
@@ -83,7 +87,7 @@ def test_backward_chunked_builds_bitwise_equal():
     t = to_device(dom)
     g0 = _gpu_grad(dom, lt.LT_FP64, tensors=t)
     g1 = _gpu_grad(dom, lt.LT_FP64, tensors=t, build_chunk_mib=1)
-    for k in lt.GRAD_FIELDS:
+    for k in ALL_GRAD:
         assert np.array_equal(g0[k], g1[k]), k
 
 
@@ -97,7 +101,7 @@ def test_backward_workspace_garbage_never_read():
     for fill in (0.0, float("nan")):
         ws = torch.full((need // 8 + 1,), fill, dtype=torch.float64, device="cuda").view(torch.uint8)
         outs.append(_gpu_grad(dom, lt.LT_FP64, tensors=t, workspace=ws))
-    for k in lt.GRAD_FIELDS:
+    for k in ALL_GRAD:
         assert np.array_equal(outs[0][k], outs[1][k]), k
 
 
@@ -107,7 +111,7 @@ def test_backward_sampled_items_gradient_workload_fp64():
     dom = synth.config_domain("grad")
     items = synth.sample_items(dom.noa, dom.nob, 1, seed=77)
     print(f"[backward] grad workload {dom.dims}, {len(items)} sampled items", flush=True)
-    _, ref = ograd.energy_and_grad(dom, items=items)
+    _, ref = ograd.energy_and_grad(dom, items=items, fock=True)
     g = _gpu_grad(dom, lt.LT_FP64, items=items)
     _compare(g, ref, 1e-10, "grad-sampled")
 
@@ -123,7 +127,7 @@ def test_backward_directional_derivative_gradient_workload():
     g64 = lt.ltriples_backward(t, dom.dims, lt.LT_FP64)
     g32 = lt.ltriples_backward(t, dom.dims, lt.LT_FP32)
     torch.cuda.synchronize()
-    for k in lt.GRAD_FIELDS:
+    for k in ALL_GRAD:
         a, b = g64[k], g32[k]
         assert float((a - b).abs().max()) <= 1e-5 * float(a.abs().max()), k
     rng = np.random.default_rng(5)
@@ -147,11 +151,25 @@ def test_backward_directional_derivative_gradient_workload():
     fd = (float(ep.item()) - float(em.item())) / (2 * h)
     an = sum(float((g64[k] * d).sum()) for k, d in dirs.items())
     assert abs(an - fd) <= 1e-9 * max(abs(fd), 1e-12 * abs(float(e0.item()))), (an, fd)
+    # f_ov alone: E is linear in it, so the central difference is exact
+    fdirs = {k: torch.from_numpy(rng.normal(0.0, 1.0, size=getattr(dom, k).shape)).cuda()
+             for k in lt.FOCK_GRAD_FIELDS}
+    h = 1.0
+    tp = dict(t); tm = dict(t)
+    for k, d in fdirs.items():
+        tp[k] = t[k] + h * d
+        tm[k] = t[k] - h * d
+    ep, _ = lt.ltriples_energy(tp, dom.dims, lt.LT_FP64)
+    em, _ = lt.ltriples_energy(tm, dom.dims, lt.LT_FP64)
+    torch.cuda.synchronize()
+    fd = (float(ep.item()) - float(em.item())) / (2 * h)
+    an = sum(float((g64[k] * d).sum()) for k, d in fdirs.items())
+    assert abs(an - fd) <= 1e-9 * max(abs(fd), 1e-12 * abs(float(e0.item()))), ("fov", an, fd)
 
 
 def test_backward_central_differences_random_entries():
-    """50 random entries of the FP64 GPU gradient, spread over all eleven
-    gradient inputs, against central differences (h = 1e-5) of the FP64 GPU
+    """52 random entries of the FP64 GPU gradient, spread over all thirteen
+    gradient inputs (f_ov included), against central differences (h = 1e-5) of the FP64 GPU
     energy.  Each difference moves all symmetry images of the entry, so it
     sees 4x (t2aa, t2bb) or 2x (off-diagonal Boo, Bvv) the returned projected
     element."""
@@ -161,8 +179,8 @@ def test_backward_central_differences_random_entries():
     g = _gpu_grad(dom, lt.LT_FP64, tensors=t)
     rng = np.random.default_rng(2024)
     h = 1e-5
-    fields = [k for k in lt.GRAD_FIELDS if getattr(dom, k).size > 0]
-    for n in range(50):
+    fields = [k for k in ALL_GRAD if getattr(dom, k).size > 0]
+    for n in range(52):
         k = fields[n % len(fields)]
         x = getattr(dom, k)
         idx = tuple(int(rng.integers(0, m)) for m in x.shape)
@@ -198,12 +216,12 @@ def test_autograd_function_matches_backward():
     import torch
     dom = _dom(SHAPES["tiny"])
     t = to_device(dom)
-    leaves = {k: (v.clone().requires_grad_(k in lt.GRAD_FIELDS)) for k, v in t.items()}
+    leaves = {k: (v.clone().requires_grad_(k in ALL_GRAD)) for k, v in t.items()}
     E = lt.triples_energy(leaves, dom.dims, "fp64")
     E.backward()
     g = lt.ltriples_backward(t, dom.dims, lt.LT_FP64)
     torch.cuda.synchronize()
-    for k in lt.GRAD_FIELDS:
+    for k in ALL_GRAD:
         assert torch.equal(leaves[k].grad, g[k]), k
     e_ref, _ = lt.ltriples_energy(t, dom.dims, lt.LT_FP64)
     assert float(E.detach()) == float(e_ref.item())

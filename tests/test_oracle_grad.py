@@ -160,3 +160,78 @@ def test_planted_sign_error_in_transcription_is_caught(monkeypatch):
     d = _direction(dom, "t1b", rng)
     fd = _stencil(dom, "t1b", d, _blocks_E)
     assert abs(float(np.sum(g["t1b"] * d)) - fd) > 1e-6 * abs(fd)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fock_gradient_exact_stencil(shape):
+    """f_ov enters only the disconnected V, linearly, so E is linear in f_ov
+    and the central difference of the NumPy energy is exact for any step:
+    along random directions and on single entries."""
+    dom = _dom(shape)
+    E0, g = grad.energy_and_grad(dom, fock=True)
+    _, g0 = grad.energy_and_grad(dom)
+    for k in grad.FIELDS:              # the Fock request changes nothing else
+        assert np.array_equal(g[k], g0[k])
+    rng = np.random.default_rng(23)
+    for field in grad.FOCK_FIELDS:
+        x = getattr(dom, field)
+        if x.size == 0:
+            continue
+        d = rng.normal(0.0, 1.0, size=x.shape)
+        h = 2.0
+        fd = (_E(dom, field, d, h, _blocks_E) - _E(dom, field, d, -h, _blocks_E)) / (2 * h)
+        an = float(np.sum(g[field] * d))
+        assert abs(an - fd) <= 1e-8 * max(abs(fd), 1e-9 * abs(E0)), (field, an, fd)
+        # linearity: the one-sided difference agrees as well
+        fw = (_E(dom, field, d, h, _blocks_E) - _blocks_E(dom)) / h
+        assert abs(an - fw) <= 1e-8 * max(abs(fw), 1e-9 * abs(E0)), (field, an, fw)
+        for ix in ((0, 0), (x.shape[0] - 1, x.shape[1] - 1)):
+            e = np.zeros_like(x)
+            e[ix] = 1.0
+            fd1 = (_E(dom, field, e, 1.0, _blocks_E) - _E(dom, field, e, -1.0, _blocks_E)) / 2.0
+            assert abs(g[field][ix] - fd1) <= 1e-8 * max(abs(fd1), 1e-12 * abs(E0)), (field, ix)
+
+
+def test_fock_gradient_against_spin_orbital_brute_force():
+    dom = _dom((3, 2, 4, 5, 10), seed=9)
+    _, g = grad.energy_and_grad(dom, fock=True)
+    rng = np.random.default_rng(8)
+    fn = lambda x: spinorb.energy(x)["E"]
+    for field in grad.FOCK_FIELDS:
+        d = rng.normal(0.0, 1.0, size=getattr(dom, field).shape)
+        fd = (_E(dom, field, d, 1.0, fn) - _E(dom, field, d, -1.0, fn)) / 2.0
+        an = float(np.sum(g[field] * d))
+        assert abs(an - fd) <= 1e-8 * max(abs(fd), 1e-12), (field, an, fd)
+
+
+def test_fock_gradient_vanishes_without_connected_triples():
+    """dE/df_ov is sum W dV/df / D: with T2 = 0 and no integrals W vanishes
+    and so must the gradient, whatever T1 and f_ov are."""
+    dom = _dom((3, 2, 5, 6, 12))
+    z = {k: np.zeros_like(getattr(dom, k)) for k in ("t2aa", "t2bb", "t2ab")}
+    _, g = grad.energy_and_grad(dom.replace(**z), fock=True)
+    for k in grad.FOCK_FIELDS:
+        assert np.max(np.abs(g[k])) == 0.0
+    _, g = grad.energy_and_grad(dom, fock=True)
+    assert all(np.max(np.abs(g[k])) > 0 for k in grad.FOCK_FIELDS)
+
+
+def test_planted_fock_sign_error_is_caught(monkeypatch):
+    """A sign flip of f_ov inside the mixed blocks only is caught by the exact
+    stencil along f_ov of the other spin's block structure."""
+    dom = _dom((3, 2, 5, 6, 12))
+    orig = grad._Item.mixed
+
+    def bad(self, s, i, j, K):
+        f = self.C["fov_" + "ab"[1 - s]]
+        self.C["fov_" + "ab"[1 - s]] = -f
+        try:
+            return orig(self, s, i, j, K)
+        finally:
+            self.C["fov_" + "ab"[1 - s]] = f
+    monkeypatch.setattr(grad._Item, "mixed", bad)
+    _, g = grad.energy_and_grad(dom, fock=True)
+    rng = np.random.default_rng(2)
+    d = rng.normal(0.0, 1.0, size=dom.fov_b.shape)
+    fd = (_E(dom, "fov_b", d, 1.0, _blocks_E) - _E(dom, "fov_b", d, -1.0, _blocks_E)) / 2.0
+    assert abs(float(np.sum(g["fov_b"] * d)) - fd) > 1e-6 * abs(fd)
