@@ -173,17 +173,22 @@ typedef struct {
   double *t1a, *t1b, *t2aa, *t2bb, *t2ab;
   double *Boo_a, *Bov_a, *Bvv_a, *Boo_b, *Bov_b, *Bvv_b;
   double *fov_a, *fov_b;               /* dE/df_ia (f_ov enters V linearly) */
+  double *eo_a, *ev_a, *eo_b, *ev_b;   /* dE/de: D of eq. cim_pt_energy is the
+                                          sum of the three occupied minus the
+                                          three virtual orbital energies */
 } ltriples_domain_grad;
 
 /* Host-only: workspace bytes of ltriples_backward. */
 int ltriples_backward_workspace_size(const ltriples_domain* d, int32_t precision,
                                      const ltriples_options* o, size_t* bytes);
 
-/* Adjoint of ltriples_energy: gbar * dE/dx for x in T1, T2, the DF factors
- * and f_ov (the orbital energies are constants here).  E is the energy
+/* Adjoint of ltriples_energy: gbar * dE/dx for x in T1, T2, the DF factors,
+ * f_ov and the semicanonical orbital energies.  E is the energy
  * of eq. cim_pt_energy as read by ltriples_energy (all occupied triplets, or
  * the item subset of options.items).  The connected W is recomputed per item
  * batch, never stored; the work is about three times the forward flops.
+ * The orbital-energy gradient costs one more reduction per epilogue tile and
+ * is computed only when one of its four output pointers is set.
  *   gbar   device pointer to one double (the incoming adjoint dL/dE)
  *   grad   host struct of device output pointers (see ltriples_domain_grad)
  *   ws     device workspace >= ltriples_backward_workspace_size(), or NULL

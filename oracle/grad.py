@@ -1,6 +1,6 @@
 """Gradient of the spin-blocked (T) energy with respect to the amplitudes, the
-density-fitting factors and, on request, the occupied-virtual Fock block f_ov
-(FP64, CPU).
+density-fitting factors and, on request, the Fock quantities: the
+occupied-virtual block f_ov and the semicanonical orbital energies (FP64, CPU).
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py); never used by the product.
 
@@ -13,8 +13,9 @@ this transcription is checked against oracle.blocks, and its gradient
 against exact finite-difference stencils of oracle.blocks and of the
 brute-force spin-orbital energy (E is a quadratic polynomial in (T1, T2) and
 a quartic one in B, so a 3-point resp. 5-point central stencil is exact up
-to rounding; f_ov enters only V, linearly, so E is a quadratic polynomial in
-it as well).
+to rounding; f_ov enters only V, linearly, so E is linear in it; the
+orbital energies enter only D, and E is homogeneous of degree -1 in them
+and invariant under a common shift).
 
 Convention for inputs that carry a symmetry (the projected gradient): the
 returned dE/dt2aa and dE/dt2bb are antisymmetrised in (i,j) and (a,b), dE/dBoo
@@ -29,7 +30,7 @@ import numpy as np
 import torch
 
 FIELDS = ("t1a", "t1b", "t2aa", "t2bb", "t2ab", "Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b")
-FOCK_FIELDS = ("fov_a", "fov_b")
+FOCK_FIELDS = ("fov_a", "fov_b", "eo_a", "ev_a", "eo_b", "ev_b")
 
 
 def _mixed_amp(X, s):
@@ -181,7 +182,7 @@ def project(grads):
 def energy_and_grad(dom, items=None, gbar=1.0, threads=None, fock=False):
     """E(T) of the domain (or of an item subset) and gbar * dE/dx for every
     field in FIELDS (projected convention), as float64 numpy arrays; with
-    `fock`, also for the fields of FOCK_FIELDS (f_ov carries no constraint)."""
+    `fock`, also for the fields of FOCK_FIELDS (no constraints)."""
     from oracle.blocks import enumerate_items
     if threads:
         torch.set_num_threads(int(threads))

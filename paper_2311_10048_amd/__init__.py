@@ -77,7 +77,7 @@ class Options(ctypes.Structure):
 
 
 GRAD_FIELDS = ("t1a", "t1b", "t2aa", "t2bb", "t2ab", "Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b")
-FOCK_GRAD_FIELDS = ("fov_a", "fov_b")
+FOCK_GRAD_FIELDS = ("fov_a", "fov_b", "eo_a", "ev_a", "eo_b", "ev_b")
 
 
 class DomainGrad(ctypes.Structure):
@@ -312,7 +312,7 @@ def ltriples_backward(tensors: Mapping[str, object], dims, precision: int = LT_F
                       batch_budget: int = 0, batch_items: int = 0, workspace=None, out=None, stream=None,
                       stats: Optional[Stats] = None, build_chunk_mib: int = 0):
     """gbar * dE/dx for x in GRAD_FIELDS (projected convention for t2aa, t2bb,
-    Boo, Bvv) and FOCK_GRAD_FIELDS (f_ov).  Returns a dict of float64 device
+    Boo, Bvv) and FOCK_GRAD_FIELDS (f_ov and the orbital energies).  Returns a dict of float64 device
     tensors shaped like the inputs.  `gbar` is a float64 device tensor with
     one element (default 1); `out` may supply the output tensors (a dict keyed
     like the result; missing keys are not computed)."""
@@ -346,8 +346,8 @@ def _autograd_function():
     import torch
 
     class TriplesEnergy(torch.autograd.Function):
-        """E(T) as a differentiable function of T1, T2, the DF factors and
-        f_ov (the orbital energies are constants)."""
+        """E(T) as a differentiable function of T1, T2, the DF factors, f_ov
+        and the orbital energies."""
 
         @staticmethod
         def forward(ctx, precision, dims, *arrays):
@@ -373,9 +373,9 @@ _TE = None
 
 
 def triples_energy(tensors: Mapping[str, object], dims, precision="fp64"):
-    """Differentiable E(T) (0-d float64 tensor).  Gradients flow to T1, T2 and
-    the DF factors through ltriples_backward (FP64, or FP32 for the reduced
-    precisions); orbital energies and f_ov receive none."""
+    """Differentiable E(T) (0-d float64 tensor).  Gradients flow to T1, T2,
+    the DF factors, f_ov and the orbital energies through ltriples_backward
+    (FP64, or FP32 for the reduced precisions)."""
     global _TE
     if _TE is None:
         _TE = _autograd_function()

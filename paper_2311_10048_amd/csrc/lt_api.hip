@@ -207,6 +207,8 @@ struct Plan {
   size_t o1[4], o2[4];            // aligned per-item bytes of the two output layouts
   size_t part_off[4];             // partials offset within scratch (phase 2)
   int64_t ntile[4];
+  int64_t bwg[4];                 // backward epilogue tiles per item
+  int64_t ld_ri[4];               // orbital-energy adjoint: per-item index sums
   size_t big = 0, small = 0, small_base = 0, total = 0;
 };
 
@@ -377,7 +379,7 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
   const size_t budget = (o && o->batch_budget) ? o->batch_budget : (size_t(8) << 30);
   size_t s2 = 0;
   for (int b = 0; b < 4; ++b) {
-    P.nb[b] = 0; P.per_item[b] = 0; P.ntile[b] = 0; P.part_off[b] = 0;
+    P.nb[b] = 0; P.per_item[b] = 0; P.ntile[b] = 0; P.part_off[b] = 0; P.bwg[b] = 0; P.ld_ri[b] = 0;
     if (P.n_blk[b] == 0) continue;
     const int s = blk_sigma(b), t = 1 - s;
     const int64_t vs = D.v[s], vt = D.v[t];
@@ -395,7 +397,15 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
     P.ntile[b] = nt;
     P.o1[b] = align256(ts * (size_t)(blk_mixed(b) ? vs * P.ldcb[s] : vs * P.ldnp[s]));
     P.o2[b] = blk_mixed(b) ? align256(ts * (size_t)(vt * P.ldnp[s])) : 0;
-    const size_t per = (bwd ? 3 : 1) * (P.o1[b] + P.o2[b]) + align256(8 * 3 * (size_t)std::max<int64_t>(nt, 1));
+    if (bwd) {
+      const int64_t ns = cdiv(vs, lt::ET), nv = cdiv(vt, lt::ET);
+      P.bwg[b] = blk_mixed(b) ? ns * (ns + 1) / 2 * nv : ns * (ns + 1) * (ns + 2) / 6;
+      P.ld_ri[b] = ld4(vs + (blk_mixed(b) ? vt : 0) + 1);
+    }
+    // backward: three output copies, then the orbital-energy tile sums and
+    // per-item index sums (after all batch outputs, see run_bwd)
+    const size_t per = (bwd ? 3 : 1) * (P.o1[b] + P.o2[b]) + align256(8 * 3 * (size_t)std::max<int64_t>(nt, 1)) +
+                       (bwd ? 512 * (size_t)P.bwg[b] + 8 * (size_t)P.ld_ri[b] : 0);
     P.per_item[b] = outb;
     int64_t nb = (o && o->batch_items > 0) ? o->batch_items : (int64_t)std::max<size_t>(1, budget / per);
     nb = std::min<int64_t>(nb, P.n_blk[b]);
@@ -1357,7 +1367,8 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
       {gr->t1a, oa * va}, {gr->t1b, ob * vb}, {gr->t2aa, oa * oa * va * va}, {gr->t2bb, ob * ob * vb * vb},
       {gr->t2ab, oa * ob * va * vb}, {gr->Boo_a, Q * oa * oa}, {gr->Bov_a, Q * oa * va}, {gr->Bvv_a, Q * va * va},
       {gr->Boo_b, Q * ob * ob}, {gr->Bov_b, Q * ob * vb}, {gr->Bvv_b, Q * vb * vb},
-      {gr->fov_a, oa * va}, {gr->fov_b, ob * vb}};
+      {gr->fov_a, oa * va}, {gr->fov_b, ob * vb}, {gr->eo_a, oa}, {gr->ev_a, va}, {gr->eo_b, ob},
+      {gr->ev_b, vb}};
   for (auto& z : outs)
     if (z.p) HIPCHK(lt::launch_zero(z.p, z.n, st));
   if (L.total == 0 || (va == 0 && vb == 0)) {
@@ -1419,6 +1430,9 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
   int32_t fc[4];
   for (int b = 0, n = 0; b < 4; ++b) { fc[b] = n; n += (int32_t)L.dst[b].size(); }
   const int64_t mstr[2][4] = {{ob * va * vb, va * vb, vb, 1}, {va * vb, ob * va * vb, 1, vb}};
+  double* gEO[2] = {gr->eo_a, gr->eo_b};
+  double* gEV[2] = {gr->ev_a, gr->ev_b};
+  const bool want_eps = gEO[0] || gEO[1] || gEV[0] || gEV[1];
   size_t bi = 0;
   for (int b = 0; b < 4; ++b) {
     const int64_t nblk = P.n_blk[b];
@@ -1439,6 +1453,16 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
     const int64_t nb = P.nb[b];
     const size_t o1 = P.o1[b], o2 = P.o2[b];
     const int64_t nt = P.ntile[b];
+    // orbital-energy adjoint buffers behind the three output copies
+    const size_t ep_off = 3 * (size_t)nb * (o1 + o2), ri_off = ep_off + 512 * (size_t)nb * P.bwg[b];
+    if (want_eps && ri_off + 8 * (size_t)nb * P.ld_ri[b] > P.scratch.bytes)
+      return fail(LT_EWORKSPACE, "orbital-energy adjoint buffers exceed the batch scratch");
+    lt::EpsReduce er{};
+    er.mixed = mixed ? 1 : 0; er.nwg = (int32_t)P.bwg[b];
+    er.nt_s = (int32_t)cdiv(vs, lt::ET); er.nt_t = (int32_t)cdiv(vt, lt::ET);
+    er.o_s = (int32_t)os; er.v_s = (int32_t)vs; er.o_t = (int32_t)ot; er.v_t = (int32_t)vt;
+    er.ep = (double*)(scr + ep_off); er.ri = (double*)(scr + ri_off); er.ld_ri = P.ld_ri[b];
+    er.eo_s = gEO[s]; er.ev_s = gEV[s]; er.eo_t = mixed ? gEO[t] : nullptr; er.ev_t = mixed ? gEV[t] : nullptr;
     for (int64_t first = 0; first < nblk; first += nb, ++bi) {
       const int64_t n = std::min<int64_t>(nb, nblk - first);
       const int32_t* items = d_trip + 3 * (fc[b] + first);
@@ -1468,6 +1492,8 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
         e.gbar = gbar;
         e.dS = (T*)(scr + (size_t)nb * o1);
         e.dSV = (T*)(scr + 2 * (size_t)nb * o1);
+        if (want_eps) e.ep = (double*)(scr + ep_off);
+        if (e.e.ntri != P.bwg[b]) return fail(LT_ESHAPE, "backward epilogue grid does not match its plan");
         HIPCHK(lt::launch_bwd_same<T>(e, (int32_t)n, st));
         tm.epi.push_back({a1, tm.mark()});
       } else {
@@ -1507,8 +1533,14 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
         e.dY = (T*)(scr + q1 + (size_t)nb * o1);
         e.dGV = (T*)(scr + 2 * q1);
         e.dYV = (T*)(scr + 2 * q1 + (size_t)nb * o1);
+        if (want_eps) e.ep = (double*)(scr + ep_off);
+        if (x.ntiles != P.bwg[b]) return fail(LT_ESHAPE, "backward epilogue grid does not match its plan");
         HIPCHK(lt::launch_bwd_mixed<T>(e, (int32_t)n, st));
         tm.epi.push_back({a1, tm.mark()});
+      }
+      if (want_eps) {
+        er.nitems = (int32_t)n; er.items = items;
+        HIPCHK(lt::launch_eps_reduce(er, st));
       }
       hipEvent_t r0 = tm.mark();
       {

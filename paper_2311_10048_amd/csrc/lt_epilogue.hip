@@ -390,7 +390,78 @@ __global__ __launch_bounds__(256) void k_epi_mixed(EpiMixed<T> a) {
 // ---------------------------------------------------------------------------
 __device__ inline int64_t pidx(int x, int y) { return (int64_t)y * (y - 1) / 2 + x; }   // x < y
 
-template <typename T>
+// Tile sums of q for the orbital-energy adjoint.  Thread (tb, tc) = (tid & 15,
+// tid >> 4) holds qa[ta] for its elements and qbc = sum_ta qa[ta].  out gets
+// the sums over the tile with the first index fixed (out[ta]), the second
+// (out[16 + tb]), the third (out[32 + tc]) and the total (out[48]).  The
+// first-index sums leave each wave by transpose-and-add: four exchanges
+// halve the sixteen values per lane (lane l ends with index (l >> 2) & 15
+// over sixteen lanes), two more add the remaining four lanes.  Every sum
+// has a fixed order.  All 256 threads must call this; `lds` (336 doubles)
+// may alias staging memory of the caller, which is not read afterwards.
+__device__ inline void eps_tile_sums(const double (&qa)[ET], double qbc, double* out, double* lds) {
+  double *red = lds, *qs = lds + 4 * ET, *rc = lds + 4 * ET + 256;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double y[8], z[4], u[2];
+  {
+    const bool hi = lane & 32;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double keep = hi ? qa[k + 8] : qa[k], send = hi ? qa[k] : qa[k + 8];
+      y[k] = keep + __shfl_xor(send, 32);
+    }
+  }
+  {
+    const bool hi = lane & 16;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double keep = hi ? y[k + 4] : y[k], send = hi ? y[k] : y[k + 4];
+      z[k] = keep + __shfl_xor(send, 16);
+    }
+  }
+  {
+    const bool hi = lane & 8;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const double keep = hi ? z[k + 2] : z[k], send = hi ? z[k] : z[k + 2];
+      u[k] = keep + __shfl_xor(send, 8);
+    }
+  }
+  double w;
+  {
+    const bool hi = lane & 4;
+    const double keep = hi ? u[1] : u[0], send = hi ? u[0] : u[1];
+    w = keep + __shfl_xor(send, 4);
+  }
+  w += __shfl_xor(w, 2);
+  w += __shfl_xor(w, 1);
+  __syncthreads();                     // every wave is done with the aliased staging
+  if ((lane & 3) == 0) red[wave * ET + (lane >> 2)] = w;
+  qs[tid] = qbc;
+  __syncthreads();
+  if (tid < ET) {
+    out[tid] = ((red[tid] + red[ET + tid]) + red[2 * ET + tid]) + red[3 * ET + tid];
+  } else if (tid < 2 * ET) {
+    const int r = tid - ET;
+    double acc = 0.0;
+    for (int tc = 0; tc < ET; ++tc) acc += qs[r + ET * tc];
+    out[ET + r] = acc;
+  } else if (tid < 3 * ET) {
+    const int r = tid - 2 * ET;
+    double acc = 0.0;
+    for (int tb = 0; tb < ET; ++tb) acc += qs[tb + ET * r];
+    out[2 * ET + r] = acc;
+    rc[r] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double acc = 0.0;
+    for (int r = 0; r < ET; ++r) acc += rc[r];
+    out[3 * ET] = acc;
+  }
+}
+
+template <typename T, bool EPS>
 __global__ __launch_bounds__(256) void k_bwd_same(BwdSame<T> A) {
   const EpiSame<T>& a = A.e;
   __shared__ T Sb[ET][SROW];
@@ -449,6 +520,11 @@ __global__ __launch_bounds__(256) void k_bwd_same(BwdSame<T> A) {
 
   const int tb = tid & 15, tc = tid >> 4;
   const int b = b0 + tb, c = c0 + tc;
+  double qa[ET], qbc = 0.0;
+  if constexpr (EPS) {
+#pragma unroll
+    for (int ta = 0; ta < ET; ++ta) qa[ta] = 0.0;
+  }
   if (b < c && c < v) {
     const double g = A.gbar[0];
     double Ubc[3], Tbc[3], t1b[3], fb[3], t1c[3], fc[3];
@@ -466,7 +542,8 @@ __global__ __launch_bounds__(256) void k_bwd_same(BwdSame<T> A) {
     const int64_t pbc = pidx(b, c);
     const T* Srow = S + pbc;
     const int na = min(ET, b - a0);
-    for (int ta = 0; ta < na; ++ta) {
+    // one element (a0 + ta, b, c); returns q = gbar W (W + V) / D^2
+    auto elem = [&](int ta) -> double {
       const int aa = a0 + ta;
       const double w = (double)Srow[aa * ldp] - (double)Sb[ta][tc * ET + tb] + (double)Sc[ta][tc * ET + tb];
       double vt = 0.0, vf = 0.0;
@@ -484,15 +561,31 @@ __global__ __launch_bounds__(256) void k_bwd_same(BwdSame<T> A) {
       dSV[aa * ldp + pbc] = (T)vh;
       dSV[b * ldp + pidx(aa, c)] = (T)(-vh);
       dSV[c * ldp + pidx(aa, b)] = (T)vh;
+      return vh * (w + vt + vf) * rd;
+    };
+    if constexpr (EPS) {
+#pragma unroll
+      for (int ta = 0; ta < ET; ++ta)
+        if (ta < na) {
+          const double q = elem(ta);
+          qa[ta] = q;
+          qbc += q;
+        }
+    } else {
+      for (int ta = 0; ta < na; ++ta) (void)elem(ta);
     }
     if (TA == TB) {
       dS[b * ldp + pbc] = (T)0; dS[c * ldp + pbc] = (T)0;
       dSV[b * ldp + pbc] = (T)0; dSV[c * ldp + pbc] = (T)0;
     }
   }
+  if constexpr (EPS) {
+    static_assert(sizeof(Sb) >= 336 * sizeof(double), "tile-sum scratch must fit the staging tile");
+    eps_tile_sums(qa, qbc, A.ep + ((int64_t)item * gridDim.x + blockIdx.x) * 64, (double*)&Sb[0][0]);
+  }
 }
 
-template <typename T>
+template <typename T, bool EPS>
 __global__ __launch_bounds__(256) void k_bwd_mixed(BwdMixed<T> A) {
   const EpiMixed<T>& a = A.e;
   __shared__ T Gb[ET][SROW];
@@ -556,6 +649,11 @@ __global__ __launch_bounds__(256) void k_bwd_mixed(BwdMixed<T> A) {
 
   const int tb = tid & 15, tc = tid >> 4;
   const int b = b0 + tb, C = c0 + tc;
+  double qa[ET], qbc = 0.0;
+  if constexpr (EPS) {
+#pragma unroll
+    for (int ta = 0; ta < ET; ++ta) qa[ta] = 0.0;
+  }
   if (b < vs && C < vt) {
     const double g = A.gbar[0];
     const double OVjb = a.ov[j * a.ov_o + b * a.ov_v + K * a.ov_O + C * a.ov_V];
@@ -569,7 +667,8 @@ __global__ __launch_bounds__(256) void k_bwd_mixed(BwdMixed<T> A) {
     const T* Grow = G + (int64_t)C * vs + b;
     const int64_t cb = (int64_t)C * vs;
     const int na = min(ET, b - a0);
-    for (int ta = 0; ta < na; ++ta) {
+    // one element (a0 + ta, b, C); returns q = gbar W (W + V) / D^2
+    auto elem = [&](int ta) -> double {
       const int aa = a0 + ta;
       const double w = (double)Grow[aa * lc] - (double)Gb[ta][tc * ET + tb] + (double)Yl[ta][tc * ET + tb];
       const double vt1 = t1ai[ta] * OVjb - t1aj[ta] * OVib - t1bi * OVj[ta][tc] + t1bj * OVi[ta][tc]
@@ -585,30 +684,144 @@ __global__ __launch_bounds__(256) void k_bwd_mixed(BwdMixed<T> A) {
       dGV[aa * lc + cb + b] = (T)vh;
       dGV[b * lc + cb + aa] = (T)(-vh);
       dYV[C * lp + pidx(aa, b)] = (T)vh;
+      return vh * (w + vt1 + vfo) * rd;
+    };
+    if constexpr (EPS) {
+#pragma unroll
+      for (int ta = 0; ta < ET; ++ta)
+        if (ta < na) {
+          const double q = elem(ta);
+          qa[ta] = q;
+          qbc += q;
+        }
+    } else {
+      for (int ta = 0; ta < na; ++ta) (void)elem(ta);
     }
     if (TA == TB) {
       dG[b * lc + cb + b] = (T)0;
       dGV[b * lc + cb + b] = (T)0;
     }
   }
+  if constexpr (EPS) {
+    static_assert(sizeof(Gb) >= 336 * sizeof(double), "tile-sum scratch must fit the staging tile");
+    eps_tile_sums(qa, qbc, A.ep + ((int64_t)item * gridDim.x + blockIdx.x) * 64, (double*)&Gb[0][0]);
+  }
 }
 
 template <typename T>
 hipError_t launch_bwd_same(const BwdSame<T>& a, int32_t nitems, hipStream_t s) {
   if (nitems <= 0 || a.e.ntri <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_bwd_same<T>), dim3(a.e.ntri, nitems), dim3(256), 0, s, a);
+  if (a.ep) hipLaunchKernelGGL((k_bwd_same<T, true>), dim3(a.e.ntri, nitems), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_bwd_same<T, false>), dim3(a.e.ntri, nitems), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_bwd_mixed(const BwdMixed<T>& a, int32_t nitems, hipStream_t s) {
   if (nitems <= 0 || a.e.ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_bwd_mixed<T>), dim3(a.e.ntiles, nitems), dim3(256), 0, s, a);
+  if (a.ep) hipLaunchKernelGGL((k_bwd_mixed<T, true>), dim3(a.e.ntiles, nitems), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_bwd_mixed<T, false>), dim3(a.e.ntiles, nitems), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 template hipError_t launch_bwd_same<float>(const BwdSame<float>&, int32_t, hipStream_t);
 template hipError_t launch_bwd_same<double>(const BwdSame<double>&, int32_t, hipStream_t);
 template hipError_t launch_bwd_mixed<float>(const BwdMixed<float>&, int32_t, hipStream_t);
 template hipError_t launch_bwd_mixed<double>(const BwdMixed<double>&, int32_t, hipStream_t);
+
+// Per item: index sums of the tile sums (fixed loop order per index), and the
+// item total.  Same spin: tile (A <= B <= C) is number C(C+1)(C+2)/6 +
+// B(B+1)/2 + A; mixed: tile (A <= B, C) is number (B(B+1)/2 + A) nt_t + C.
+__global__ __launch_bounds__(256) void k_eps_item(EpsReduce r) {
+  __shared__ double sh[256];
+  const int item = blockIdx.x, tid = threadIdx.x;
+  const double* P = r.ep + (int64_t)item * r.nwg * 64;
+  double* out = r.ri + (int64_t)item * r.ld_ri;
+  auto wtri = [](int A, int B, int C) { return C * (C + 1) * (C + 2) / 6 + B * (B + 1) / 2 + A; };
+  if (!r.mixed) {
+    const int nt = r.nt_s;
+    for (int x = tid; x < r.v_s; x += 256) {
+      const int T = x / ET, q = x % ET;
+      double acc = 0.0;
+      for (int C = T; C < nt; ++C)                 // x first: T = A <= B <= C
+        for (int B = T; B <= C; ++B) acc += P[(int64_t)wtri(T, B, C) * 64 + q];
+      for (int C = T; C < nt; ++C)                 // x second: A <= T = B <= C
+        for (int A = 0; A <= T; ++A) acc += P[(int64_t)wtri(A, T, C) * 64 + ET + q];
+      for (int B = 0; B <= T; ++B)                 // x third: A <= B <= T = C
+        for (int A = 0; A <= B; ++A) acc += P[(int64_t)wtri(A, B, T) * 64 + 2 * ET + q];
+      out[x] = acc;
+    }
+  } else {
+    const int ns = r.nt_s, ntt = r.nt_t, npr = ns * (ns + 1) / 2;
+    for (int x = tid; x < r.v_s; x += 256) {
+      const int T = x / ET, q = x % ET;
+      double acc = 0.0;
+      for (int B = T; B < ns; ++B)                 // x first: T = A <= B
+        for (int C = 0; C < ntt; ++C) acc += P[((int64_t)(B * (B + 1) / 2 + T) * ntt + C) * 64 + q];
+      for (int A = 0; A <= T; ++A)                 // x second: A <= T = B
+        for (int C = 0; C < ntt; ++C) acc += P[((int64_t)(T * (T + 1) / 2 + A) * ntt + C) * 64 + ET + q];
+      out[x] = acc;
+    }
+    for (int X = tid; X < r.v_t; X += 256) {
+      const int T = X / ET, q = X % ET;
+      double acc = 0.0;
+      for (int pi = 0; pi < npr; ++pi) acc += P[((int64_t)pi * ntt + T) * 64 + 2 * ET + q];
+      out[r.v_s + X] = acc;
+    }
+  }
+  double acc = 0.0;
+  for (int w = tid; w < r.nwg; w += 256) acc += P[(int64_t)w * 64 + 3 * ET];
+  sh[tid] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int k = 0; k < 256; ++k) t += sh[k];
+    out[r.v_s + (r.mixed ? r.v_t : 0)] = t;
+  }
+}
+
+// Over the batch's items, one thread per output index, items in order.
+__global__ __launch_bounds__(64) void k_eps_batch(EpsReduce r) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int vt = r.mixed ? r.v_t : 0, ot = r.mixed ? r.o_t : 0;
+  const int tcol = r.v_s + vt;
+  const double* ri = r.ri;
+  const int64_t ld = r.ld_ri;
+  if (x < r.v_s) {
+    if (!r.ev_s) return;
+    double acc = 0.0;
+    for (int n = 0; n < r.nitems; ++n) acc += ri[n * ld + x];
+    r.ev_s[x] += acc;
+  } else if (x < r.v_s + vt) {
+    const int X = x - r.v_s;
+    if (!r.ev_t) return;
+    double acc = 0.0;
+    for (int n = 0; n < r.nitems; ++n) acc += ri[n * ld + r.v_s + X];
+    r.ev_t[X] += acc;
+  } else if (x < r.v_s + vt + r.o_s) {
+    const int i = x - r.v_s - vt;
+    if (!r.eo_s) return;
+    double acc = 0.0;
+    for (int n = 0; n < r.nitems; ++n) {
+      const int32_t* it = r.items + 3 * n;
+      if (it[0] == i || it[1] == i || (!r.mixed && it[2] == i)) acc += ri[n * ld + tcol];
+    }
+    r.eo_s[i] -= acc;
+  } else if (x < r.v_s + vt + r.o_s + ot) {
+    const int K = x - r.v_s - vt - r.o_s;
+    if (!r.eo_t) return;
+    double acc = 0.0;
+    for (int n = 0; n < r.nitems; ++n)
+      if (r.items[3 * n + 2] == K) acc += ri[n * ld + tcol];
+    r.eo_t[K] -= acc;
+  }
+}
+
+hipError_t launch_eps_reduce(const EpsReduce& r, hipStream_t s) {
+  if (r.nitems <= 0 || r.nwg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eps_item, dim3(r.nitems), dim3(256), 0, s, r);
+  const int n = r.v_s + r.o_s + (r.mixed ? r.v_t + r.o_t : 0);
+  hipLaunchKernelGGL(k_eps_batch, dim3((n + 63) / 64), dim3(64), 0, s, r);
+  return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_epi_same(const EpiSame<T>& a, int32_t nitems, hipStream_t s) {

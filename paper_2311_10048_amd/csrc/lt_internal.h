@@ -254,20 +254,42 @@ template <typename T> hipError_t launch_rgemm(RArgs<T> g, bool tb, hipStream_t s
 //   dX  = gbar (2W + V) / D   placed at the positions W reads (with signs),
 //   dXV = gbar W / D          likewise for the singles/f_ov intermediates,
 // every element of the item's output layout written (zeros where W reads
-// nothing).
+// nothing).  With `ep` set they also reduce q = gbar W (W + V) / D^2, the
+// adjoint of -D, per work-group tile: ep[item][tile][64] holds the sums over
+// the tile's elements with a fixed first (slots 0-15), second (16-31) and
+// third (32-47) virtual index, and the tile total at slot 48.
 template <typename T> struct BwdSame {
   EpiSame<T> e;                        // part unused
   const double* gbar;
   T* dS; T* dSV;                       // [item][a][ld_np], item stride e.s_item
+  double* ep;                          // [item][ntri][64] or null
 };
 template <typename T> struct BwdMixed {
   EpiMixed<T> e;
   const double* gbar;
   T *dG, *dGV;                         // [item][a][ld_cb], stride e.g_item
   T *dY, *dYV;                         // [item][C][ld_np], stride e.y_item
+  double* ep;                          // [item][ntiles][64] or null
 };
 template <typename T> hipError_t launch_bwd_same(const BwdSame<T>& a, int32_t nitems, hipStream_t s);
 template <typename T> hipError_t launch_bwd_mixed(const BwdMixed<T>& a, int32_t nitems, hipStream_t s);
+
+// Orbital-energy adjoint of one batch from the tile sums above.  D =
+// e_i + e_j + e_k - e_a - e_b - e_c, so dE/de_virtual gathers +q over the
+// positions where the index occurs and dE/de_occupied gathers -q over the
+// items that contain it.  Two fixed-order passes: per item and index
+// (ri[item][ld_ri]: spin-s virtuals, spin-t virtuals, item total), then over
+// the batch's items into the outputs (accumulated; null outputs skipped).
+struct EpsReduce {
+  int32_t mixed, nitems, nwg;          // nwg: tiles per item of the epilogue grid
+  int32_t nt_s, nt_t;                  // virtual tiles per spin (nt_t mixed only)
+  int32_t o_s, v_s, o_t, v_t;
+  const double* ep;                    // [item][nwg][64]
+  double* ri; int64_t ld_ri;
+  const int32_t* items;                // [item][3]: (i, j, k) resp. (i, j, K)
+  double *eo_s, *ev_s, *eo_t, *ev_t;
+};
+hipError_t launch_eps_reduce(const EpsReduce& r, hipStream_t s);
 
 // out[x0*o0 + x1*o1 + x2*o2 + x3*o3] += scale * in[x0*i0 + x1*i1 + x2*i2 + x3*i3]
 // over x < d (a bijection: each output element written by one thread).

@@ -153,7 +153,7 @@ def test_backward_directional_derivative_gradient_workload():
     assert abs(an - fd) <= 1e-9 * max(abs(fd), 1e-12 * abs(float(e0.item()))), (an, fd)
     # f_ov alone: E is linear in it, so the central difference is exact
     fdirs = {k: torch.from_numpy(rng.normal(0.0, 1.0, size=getattr(dom, k).shape)).cuda()
-             for k in lt.FOCK_GRAD_FIELDS}
+             for k in ("fov_a", "fov_b")}
     h = 1.0
     tp = dict(t); tm = dict(t)
     for k, d in fdirs.items():
@@ -165,12 +165,21 @@ def test_backward_directional_derivative_gradient_workload():
     fd = (float(ep.item()) - float(em.item())) / (2 * h)
     an = sum(float((g64[k] * d).sum()) for k, d in fdirs.items())
     assert abs(an - fd) <= 1e-9 * max(abs(fd), 1e-12 * abs(float(e0.item()))), ("fov", an, fd)
+    # orbital energies: a common shift leaves every D unchanged (the gradient
+    # sums to zero) and E is homogeneous of degree -1 in them
+    eps = ("eo_a", "ev_a", "eo_b", "ev_b")
+    tot = sum(float(g64[k].sum()) for k in eps)
+    mag = sum(float(g64[k].abs().sum()) for k in eps)
+    assert abs(tot) <= 1e-10 * mag, (tot, mag)
+    euler = sum(float((t[k] * g64[k]).sum()) for k in eps)
+    E0 = float(e0.item())
+    assert abs(euler + E0) <= 1e-10 * abs(E0), (euler, E0)
 
 
 def test_backward_central_differences_random_entries():
-    """52 random entries of the FP64 GPU gradient, spread over all thirteen
-    gradient inputs (f_ov included), against central differences (h = 1e-5) of the FP64 GPU
-    energy.  Each difference moves all symmetry images of the entry, so it
+    """51 random entries of the FP64 GPU gradient, spread over all seventeen
+    gradient inputs (f_ov and the orbital energies included), against
+    central differences (h = 1e-5) of the FP64 GPU energy.  Each difference moves all symmetry images of the entry, so it
     sees 4x (t2aa, t2bb) or 2x (off-diagonal Boo, Bvv) the returned projected
     element."""
     import torch
@@ -180,7 +189,7 @@ def test_backward_central_differences_random_entries():
     rng = np.random.default_rng(2024)
     h = 1e-5
     fields = [k for k in ALL_GRAD if getattr(dom, k).size > 0]
-    for n in range(52):
+    for n in range(51):
         k = fields[n % len(fields)]
         x = getattr(dom, k)
         idx = tuple(int(rng.integers(0, m)) for m in x.shape)

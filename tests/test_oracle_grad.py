@@ -14,6 +14,7 @@ from oracle import blocks, grad, spinorb
 T_FIELDS = ("t1a", "t1b", "t2aa", "t2bb", "t2ab")
 B_FIELDS = ("Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b")
 SHAPES = [(3, 2, 5, 6, 14), (4, 3, 6, 5, 12), (3, 0, 4, 5, 10), (2, 2, 4, 4, 9)]
+FOV_FIELDS = ("fov_a", "fov_b")
 
 
 def _dom(shape, seed=5):
@@ -173,7 +174,7 @@ def test_fock_gradient_exact_stencil(shape):
     for k in grad.FIELDS:              # the Fock request changes nothing else
         assert np.array_equal(g[k], g0[k])
     rng = np.random.default_rng(23)
-    for field in grad.FOCK_FIELDS:
+    for field in FOV_FIELDS:
         x = getattr(dom, field)
         if x.size == 0:
             continue
@@ -197,7 +198,7 @@ def test_fock_gradient_against_spin_orbital_brute_force():
     _, g = grad.energy_and_grad(dom, fock=True)
     rng = np.random.default_rng(8)
     fn = lambda x: spinorb.energy(x)["E"]
-    for field in grad.FOCK_FIELDS:
+    for field in FOV_FIELDS:
         d = rng.normal(0.0, 1.0, size=getattr(dom, field).shape)
         fd = (_E(dom, field, d, 1.0, fn) - _E(dom, field, d, -1.0, fn)) / 2.0
         an = float(np.sum(g[field] * d))
@@ -210,10 +211,10 @@ def test_fock_gradient_vanishes_without_connected_triples():
     dom = _dom((3, 2, 5, 6, 12))
     z = {k: np.zeros_like(getattr(dom, k)) for k in ("t2aa", "t2bb", "t2ab")}
     _, g = grad.energy_and_grad(dom.replace(**z), fock=True)
-    for k in grad.FOCK_FIELDS:
+    for k in FOV_FIELDS:
         assert np.max(np.abs(g[k])) == 0.0
     _, g = grad.energy_and_grad(dom, fock=True)
-    assert all(np.max(np.abs(g[k])) > 0 for k in grad.FOCK_FIELDS)
+    assert all(np.max(np.abs(g[k])) > 0 for k in FOV_FIELDS)
 
 
 def test_planted_fock_sign_error_is_caught(monkeypatch):
@@ -235,3 +236,86 @@ def test_planted_fock_sign_error_is_caught(monkeypatch):
     d = rng.normal(0.0, 1.0, size=dom.fov_b.shape)
     fd = (_E(dom, "fov_b", d, 1.0, _blocks_E) - _E(dom, "fov_b", d, -1.0, _blocks_E)) / 2.0
     assert abs(float(np.sum(g["fov_b"] * d)) - fd) > 1e-6 * abs(fd)
+
+
+EPS_FIELDS = ("eo_a", "ev_a", "eo_b", "ev_b")
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_orbital_energy_gradient_identities(shape):
+    """D is occupied minus virtual orbital energies, so E does not change
+    when every orbital energy moves by the same amount (the gradient sums to
+    zero over both spins), and E is homogeneous of degree -1 in them
+    (sum e dE/de = -E)."""
+    dom = _dom(shape)
+    E, g = grad.energy_and_grad(dom, fock=True)
+    tot = sum(float(np.sum(g[k])) for k in EPS_FIELDS)
+    mag = sum(float(np.sum(np.abs(g[k]))) for k in EPS_FIELDS)
+    assert mag > 0
+    assert abs(tot) <= 1e-12 * mag, (tot, mag)
+    euler = sum(float(np.sum(np.asarray(getattr(dom, k)) * g[k])) for k in EPS_FIELDS)
+    assert abs(euler + E) <= 1e-12 * abs(E), (euler, E)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_orbital_energy_gradient_five_point_stencil(shape):
+    """Against the 5-point central difference of the NumPy energy, along
+    random directions and on single entries (E is smooth in the orbital
+    energies; with steps of 1e-3 against gaps of order one the stencil error
+    is far below the bar)."""
+    dom = _dom(shape)
+    E0, g = grad.energy_and_grad(dom, fock=True)
+    rng = np.random.default_rng(31)
+    h = 1e-3
+
+    def five(field, d):
+        return (-_E(dom, field, d, 2 * h, _blocks_E) + 8 * _E(dom, field, d, h, _blocks_E)
+                - 8 * _E(dom, field, d, -h, _blocks_E) + _E(dom, field, d, -2 * h, _blocks_E)) / (12 * h)
+    for field in EPS_FIELDS:
+        x = np.asarray(getattr(dom, field))
+        if x.size == 0:
+            continue
+        d = rng.normal(0.0, 1.0, size=x.shape)
+        fd = five(field, d)
+        an = float(np.sum(g[field] * d))
+        assert abs(an - fd) <= 1e-7 * max(abs(fd), 1e-9 * abs(E0)), (field, an, fd)
+        for ix in (0, x.shape[0] - 1):
+            e = np.zeros_like(x)
+            e[ix] = 1.0
+            fd1 = five(field, e)
+            assert abs(g[field][ix] - fd1) <= 1e-7 * max(abs(fd1), 1e-9 * abs(E0)), (field, ix, fd1)
+
+
+def test_orbital_energy_gradient_against_spin_orbital_brute_force():
+    dom = _dom((3, 2, 4, 5, 10), seed=9)
+    _, g = grad.energy_and_grad(dom, fock=True)
+    rng = np.random.default_rng(12)
+    fn = lambda x: spinorb.energy(x)["E"]
+    h = 1e-3
+    for field in EPS_FIELDS:
+        d = rng.normal(0.0, 1.0, size=np.asarray(getattr(dom, field)).shape)
+        fd = (-_E(dom, field, d, 2 * h, fn) + 8 * _E(dom, field, d, h, fn)
+              - 8 * _E(dom, field, d, -h, fn) + _E(dom, field, d, -2 * h, fn)) / (12 * h)
+        an = float(np.sum(g[field] * d))
+        assert abs(an - fd) <= 1e-7 * max(abs(fd), 1e-12), (field, an, fd)
+
+
+def test_planted_denominator_error_breaks_shift_invariance(monkeypatch):
+    """A mixed-block denominator that drops the third occupied energy is no
+    longer shift invariant, and the identity pin sees it."""
+    dom = _dom((3, 2, 5, 6, 12))
+    orig = grad._Item.mixed
+
+    def bad(self, s, i, j, K):
+        t = 1 - s
+        eo = self.C["eo_" + "ab"[t]]
+        self.C["eo_" + "ab"[t]] = eo * 0.0
+        try:
+            return orig(self, s, i, j, K)
+        finally:
+            self.C["eo_" + "ab"[t]] = eo
+    monkeypatch.setattr(grad._Item, "mixed", bad)
+    _, g = grad.energy_and_grad(dom, fock=True)
+    tot = sum(float(np.sum(g[k])) for k in EPS_FIELDS)
+    mag = sum(float(np.sum(np.abs(g[k]))) for k in EPS_FIELDS)
+    assert abs(tot) > 1e-6 * mag
