@@ -167,7 +167,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "fp64", "bf16x3", "bf16"])
-    ap.add_argument("--workload", default="lno", choices=["tiny", "lno", "grad", "large", "batch"])
+    ap.add_argument("--workload", default="lno", choices=["tiny", "lno", "grad", "large", "batch", "rhf"])
     ap.add_argument("--fp64-sample", type=int, default=48, help="items per block for the FP64 GPU comparison")
     ap.add_argument("--cpu-sample", type=int, default=3, help="items per block for the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -203,6 +203,9 @@ def main():
         return
     if args.workload == "batch":
         run_batch(args, lt, synth, torch)
+        return
+    if args.workload == "rhf":
+        run_rhf(args, lt, synth, torch)
         return
     dev = torch.device("cuda:0")
     prec = lt.PRECISIONS[args.precision]
@@ -458,6 +461,103 @@ def run_batch(args, lt, synth, torch):
         "E_per_domain": [float(x) for x in e_eager],
     }
     print(json.dumps(res), flush=True)
+
+
+def run_rhf(args, lt, synth, torch):
+    """Closed-shell (SOMO-free) LNO-sized domain through ltriples_energy_rhf;
+    parity and CPU baseline on sampled aaa/aab triplets of the same data
+    through the spin-block entry point and the oracle."""
+    from oracle import blocks
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    prec = lt.PRECISIONS[args.precision]
+    t0 = time.time()
+    dom = synth.rhf_config_domain("rhf")
+    dims = (dom.noa, dom.nva, dom.naux)
+    log(f"generated rhf domain (no, nv, naux) = {dims} in {time.time() - t0:.1f} s")
+    tens = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in synth.rhf_arrays(dom).items()}
+    rd = lt.make_rhf_domain(dims, tens)
+    F, n = lt.ltriples_rhf_flops(rd)
+    ws = torch.empty(lt.ltriples_rhf_workspace_size(rd, prec), dtype=torch.uint8, device=dev)
+    log(f"items {n}, algorithmic flops {F:.4e}, workspace {ws.numel() / 1e9:.1f} GB")
+
+    def step():
+        st = lt.Stats()
+        e, parts = lt.ltriples_energy_rhf(tens, dims, prec, workspace=ws, stats=st)
+        return e, parts, st
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {w + 1}/{args.warmup} done")
+    stats = []
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for k in range(args.steps):
+        e, parts, st = step()
+        stats.append(st)
+        log(f"step {k + 1}/{args.steps}: {st.total_ms / 1e3:.2f} s")
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    E = float(e.item())
+    gemm_ms = sum(x.triples_gemm_ms for x in stats)
+    gemm_flops = sum(x.triples_gemm_flops for x in stats)
+    launches = sum(x.triples_gemm_launches for x in stats)
+    achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    kname = "k_tgemm_bf16" if args.precision.startswith("bf16") else "k_tgemm"
+    roofline = {"bound": "mfma", "kernel": f"{kname} (triplet contraction GEMM)", "achieved": round(achieved, 2),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "avg_launch_ms": round(gemm_ms / max(launches, 1), 4),
+                "launches_per_step": launches // max(len(stats), 1),
+                "flops_per_launch": gemm_flops / max(launches, 1),
+                "kernel_source_hash": kernel_source_hash(args.precision)}
+    log(f"E = {E:.10e}  {ms / 1e3:.2f} s/step  {F / (ms * 1e-3) / 1e9:.1f} GFLOP/s  gemm {achieved:.1f} TFLOP/s")
+    del ws
+    torch.cuda.empty_cache()
+
+    # sampled aaa and aab triplets of the same data: GPU spin-block path vs the oracle
+    parity = cpu = None
+    if not args.no_cpu_baseline and args.cpu_sample > 0:
+        items = [r for r in synth.sample_items(dom.noa, dom.nob, args.cpu_sample, seed=11).tolist() if r[0] in (0, 1)]
+        full = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in dom.arrays().items()}
+        ei = torch.zeros(len(items), 3, dtype=torch.float64, device=dev)
+        lt.ltriples_energy(full, dom.dims, prec, items=items, e_items=ei)
+        torch.cuda.synchronize()
+        d = lt.make_domain(dom.dims, full)
+        oc, _k = lt.make_options(items=items)
+        F_c, n_c = lt.ltriples_flops(d, oc)
+        tc = time.perf_counter()
+        ref = blocks.energy(dom, items=items, return_items=True)
+        dt = time.perf_counter() - tc
+        g = ei.cpu().numpy()
+        r = ref["items"]
+        err = np.abs(g.sum(axis=1) - r.sum(axis=1)) / np.maximum(1.0, np.abs(r.sum(axis=1)))
+        tol = TOL[args.precision]
+        parity = {"oracle_items": int(n_c), "max_rel_err_item_E": float(err.max()), "tolerance": tol,
+                  "pass": None if tol is None else bool(err.max() <= tol)}
+        cpu = {"value": round(F_c / dt / 1e9, 3), "unit": "GFLOP/s", "cores": _blas_threads(), "kind": "oracle",
+               "sample": f"{n_c} aaa/aab triplets of the same closed-shell data, {F_c:.3e} flops in {dt:.1f} s, "
+                         "NumPy FP64", "seconds": round(dt, 2)}
+        log(f"cpu oracle {dt:.1f} s for {n_c} items; max item rel err {err.max():.2e}")
+    out = {
+        "metric": METRIC, "value": round(F / (ms * 1e-3) / 1e9, 1), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 2), "higher_is_better": True,
+        "scaling": "strong", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"rhf domain (closed shell): no={dom.noa} nv={dom.nva} naux={dom.naux}, "
+                               f"all {n} aaa and aab occupied triplets (E = 2 E_aaa + 2 E_aab)",
+                   "algorithmic_flops": F, "precision": args.precision},
+        "E": E, "parts": parts.cpu().numpy().tolist(), "roofline": roofline,
+        "mfma_util": round(MFMA_PRODUCTS[args.precision] * achieved / peak, 4),
+        "parity": parity, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def run_backward(lt, synth, torch, log):

@@ -238,6 +238,40 @@ int ltriples_energy_batched(const ltriples_domain* ds, int32_t ndom,
 /* Drops every cached hipGraph of ltriples_energy_batched. */
 int ltriples_graph_reset(void);
 
+/* One closed-shell (SOMO-free) domain in spatial orbitals, for the domains
+ * whose orbital sets become spin independent once the domain Fock matrix is
+ * spin averaged (section "Approximate long-range spin polarization").
+ *   t1 [no][nv], tau [no][no][nv][nv] with tau^{ab}_{ij} = tau^{ba}_{ji}
+ *   (not checked), Boo [naux][no][no], Bov [naux][no][nv], Bvv
+ *   [naux][nv][nv], eo [no], ev [nv], fov [no][nv]; FP64, device pointers. */
+typedef struct ltriples_rhf_domain {
+  int32_t no, nv, naux;
+  const double *t1, *tau;
+  const double *Boo, *Bov, *Bvv;
+  const double *eo, *ev, *fov;
+} ltriples_rhf_domain;
+
+/* Host-only: workspace bytes of ltriples_energy_rhf. */
+int ltriples_rhf_workspace_size(const ltriples_rhf_domain* d, int32_t precision,
+                                const ltriples_options* o, size_t* bytes);
+
+/* Host-only: W-contraction flops ltriples_energy_rhf executes (as
+ * ltriples_flops counts them) and its number of items. */
+int ltriples_rhf_flops(const ltriples_rhf_domain* d, double* flops, int64_t* n_items_out);
+
+/* Closed-shell E(T) of one domain: the spin-block energy with identical
+ * alpha and beta data, E = 2 E_aaa + 2 E_aab (the bbb and abb blocks equal
+ * the aaa and aab ones and are not computed).  The same-spin amplitudes
+ * tau^{ab}_{ij} - tau^{ba}_{ij} are formed in the workspace.
+ *   e_out  device double[1]; parts device double[3] {E4, E_ST, E_DT} or NULL
+ *   ws     device workspace >= ltriples_rhf_workspace_size(), or NULL
+ * Precisions, batching, chunking and stats as ltriples_energy; options.items,
+ * options.e_items and options.graph must be unset (LT_EINVAL).  Errors as
+ * ltriples_energy. */
+int ltriples_energy_rhf(const ltriples_rhf_domain* d, int32_t precision,
+                        const ltriples_options* o, double* e_out, double* parts,
+                        void* ws, size_t ws_bytes, void* stream);
+
 /* Description of the last error on this thread ("" if none). */
 const char* ltriples_last_error(void);
 

@@ -50,6 +50,14 @@ class Domain(ctypes.Structure):
                 + [(n, ctypes.c_void_p) for n in ARRAY_FIELDS])
 
 
+RHF_FIELDS = ("t1", "tau", "Boo", "Bov", "Bvv", "eo", "ev", "fov")
+
+
+class RhfDomain(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_int32) for n in ("no", "nv", "naux")]
+                + [(n, ctypes.c_void_p) for n in RHF_FIELDS])
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_double),
                 ("setup_ms", ctypes.c_double),
@@ -118,11 +126,17 @@ def load_library(path: Optional[str] = None):
     lib.ltriples_backward_workspace_size.argtypes = [Dp, ctypes.c_int32, Op, ctypes.POINTER(ctypes.c_size_t)]
     lib.ltriples_backward.argtypes = [Dp, ctypes.c_int32, Op, ctypes.c_void_p, Gp, ctypes.c_void_p,
                                       ctypes.c_size_t, ctypes.c_void_p]
+    Rp = ctypes.POINTER(RhfDomain)
+    lib.ltriples_rhf_workspace_size.argtypes = [Rp, ctypes.c_int32, Op, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ltriples_rhf_flops.argtypes = [Rp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.ltriples_energy_rhf.argtypes = [Rp, ctypes.c_int32, Op, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.ltriples_last_error.restype = ctypes.c_char_p
     lib.ltriples_version.restype = ctypes.c_char_p
     for f in ("ltriples_validate", "ltriples_workspace_size", "ltriples_flops", "ltriples_energy",
               "ltriples_workspace_size_batched", "ltriples_energy_batched", "ltriples_graph_reset",
-              "ltriples_backward_workspace_size", "ltriples_backward", "ltriples_plan_check"):
+              "ltriples_backward_workspace_size", "ltriples_backward", "ltriples_plan_check",
+              "ltriples_rhf_workspace_size", "ltriples_rhf_flops", "ltriples_energy_rhf"):
         getattr(lib, f).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -243,6 +257,66 @@ def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP3
                                e.data_ptr(), parts.data_ptr(), workspace.data_ptr(),
                                workspace.numel(), st.cuda_stream)
     _check(code)
+    del keep
+    return e, parts
+
+
+def make_rhf_domain(dims, tensors: Optional[Mapping[str, object]] = None) -> RhfDomain:
+    """ltriples_rhf_domain from (no, nv, naux) and device tensors keyed by
+    RHF_FIELDS; missing arrays are NULL."""
+    d = RhfDomain()
+    d.no, d.nv, d.naux = (int(x) for x in dims)
+    tensors = tensors or {}
+    for n in RHF_FIELDS:
+        t = tensors.get(n)
+        if t is not None and hasattr(t, "is_contiguous"):
+            if not t.is_contiguous():
+                raise ValueError(f"{n} must be contiguous")
+            if str(t.dtype) != "torch.float64":
+                raise ValueError(f"{n} must be float64")
+        setattr(d, n, _ptr(t))
+    return d
+
+
+def ltriples_rhf_workspace_size(dom: RhfDomain, precision: int, options: Optional[Options] = None) -> int:
+    lib = load_library()
+    n = ctypes.c_size_t(0)
+    _check(lib.ltriples_rhf_workspace_size(ctypes.byref(dom), int(precision),
+                                           ctypes.byref(options) if options is not None else None,
+                                           ctypes.byref(n)))
+    return n.value
+
+
+def ltriples_rhf_flops(dom: RhfDomain):
+    """(W-contraction flops executed by ltriples_energy_rhf, number of items)."""
+    lib = load_library()
+    f = ctypes.c_double(0)
+    n = ctypes.c_int64(0)
+    _check(lib.ltriples_rhf_flops(ctypes.byref(dom), ctypes.byref(f), ctypes.byref(n)))
+    return f.value, n.value
+
+
+def ltriples_energy_rhf(tensors: Mapping[str, object], dims, precision: int = LT_FP32, batch_budget: int = 0,
+                        batch_items: int = 0, workspace=None, stream=None, stats: Optional[Stats] = None,
+                        build_chunk_mib: int = 0):
+    """Closed-shell E(T) of one domain given in spatial orbitals (RHF_FIELDS,
+    dims (no, nv, naux)).  Returns (e, parts): float64 device tensors of
+    shapes [1] and [3] ({E4, E_ST, E_DT})."""
+    import torch
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    dom = make_rhf_domain(dims, tensors)
+    opts, keep = make_options(None, None, batch_budget, batch_items, stats, build_chunk_mib)
+    dev = next(t for t in tensors.values() if hasattr(t, "device")).device
+    need = ltriples_rhf_workspace_size(dom, precision, opts)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    e = torch.empty(1, dtype=torch.float64, device=dev)
+    parts = torch.empty(3, dtype=torch.float64, device=dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    lib = load_library()
+    _check(lib.ltriples_energy_rhf(ctypes.byref(dom), int(precision), ctypes.byref(opts), e.data_ptr(),
+                                   parts.data_ptr(), workspace.data_ptr(), workspace.numel(), st.cuda_stream))
     del keep
     return e, parts
 

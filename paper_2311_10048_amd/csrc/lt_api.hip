@@ -2187,6 +2187,134 @@ int ltriples_graph_reset(void) {
   return LT_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Closed-shell domains: the spin-block path with identical alpha and beta
+// data, restricted to the aaa and aab blocks (the bbb and abb blocks equal
+// them), E = 2 (E_aaa + E_aab).  The same-spin amplitudes are formed in the
+// head of the workspace; the spin-block call gets the rest.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct RhfSetup {
+  ltriples_domain d{};
+  ltriples_options o{};
+  std::vector<int32_t> items;
+  size_t t2_bytes = 0, head = 0;
+};
+
+int rhf_setup(const ltriples_rhf_domain* r, const ltriples_options* o, RhfSetup& S) {
+  if (!r) return fail(LT_EINVAL, "domain is NULL");
+  if (r->no < 0 || r->nv < 0 || r->naux < 0) return fail(LT_EINVAL, "negative dimension");
+  if (o && (o->items || o->n_items || o->e_items || o->graph))
+    return fail(LT_EINVAL, "item lists, per-item outputs and graphs are not closed-shell options");
+  const int64_t no = r->no, nv = r->nv, Q = r->naux;
+  const struct { const double* p; int64_t n; const char* name; } ps[] = {
+      {r->t1, no * nv, "t1"}, {r->tau, no * no * nv * nv, "tau"}, {r->Boo, Q * no * no, "Boo"},
+      {r->Bov, Q * no * nv, "Bov"}, {r->Bvv, Q * nv * nv, "Bvv"}, {r->eo, no, "eo"}, {r->ev, nv, "ev"},
+      {r->fov, no * nv, "fov"}};
+  for (auto& x : ps)
+    if (x.n > 0 && !x.p) return fail(LT_EINVAL, "%s is NULL", x.name);
+  const int64_t n0 = no * (no - 1) * (no - 2) / 6, n1 = no * (no - 1) / 2 * no;
+  if (n0 + n1 > (int64_t)INT32_MAX) return fail(LT_ESHAPE, "too many occupied triplets");
+  ltriples_domain& d = S.d;
+  d.noa = d.nob = r->no; d.nva = d.nvb = r->nv; d.naux = r->naux;
+  d.t1a = d.t1b = r->t1;
+  d.t2ab = r->tau;
+  d.t2aa = d.t2bb = r->tau;   // placeholder for validation and planning; the workspace copy at run time
+  d.Boo_a = d.Boo_b = r->Boo; d.Bov_a = d.Bov_b = r->Bov; d.Bvv_a = d.Bvv_b = r->Bvv;
+  d.eo_a = d.eo_b = r->eo; d.ev_a = d.ev_b = r->ev;
+  d.fov_a = d.fov_b = r->fov;
+  S.items.reserve(4 * (size_t)(n0 + n1));
+  for (int32_t i = 0; i < r->no; ++i)
+    for (int32_t j = i + 1; j < r->no; ++j)
+      for (int32_t k = j + 1; k < r->no; ++k) S.items.insert(S.items.end(), {0, i, j, k});
+  for (int32_t i = 0; i < r->no; ++i)
+    for (int32_t j = i + 1; j < r->no; ++j)
+      for (int32_t K = 0; K < r->no; ++K) S.items.insert(S.items.end(), {1, i, j, K});
+  if (o) S.o = *o;
+  S.o.items = S.items.empty() ? nullptr : S.items.data();
+  S.o.n_items = (int32_t)(S.items.size() / 4);
+  S.t2_bytes = align256(8 * (size_t)(no * no * nv * nv));
+  S.head = S.t2_bytes + 256;   // then 13 doubles: E and the four blocks' parts
+  return LT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ltriples_rhf_workspace_size(const ltriples_rhf_domain* d, int32_t precision, const ltriples_options* o,
+                                size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(LT_EINVAL, "bytes is NULL");
+  RhfSetup S;
+  int r = rhf_setup(d, o, S);
+  if (r) return r;
+  size_t inner = 0;
+  r = ltriples_workspace_size(&S.d, precision, &S.o, &inner);
+  if (r) return r;
+  *bytes = S.head + inner;
+  return LT_OK;
+}
+
+int ltriples_rhf_flops(const ltriples_rhf_domain* d, double* flops, int64_t* n_items_out) {
+  g_err.clear();
+  if (!flops) return fail(LT_EINVAL, "NULL argument");
+  RhfSetup S;
+  const int r = rhf_setup(d, nullptr, S);
+  if (r) return r;
+  return ltriples_flops(&S.d, &S.o, flops, n_items_out);
+}
+
+int ltriples_energy_rhf(const ltriples_rhf_domain* rd, int32_t precision, const ltriples_options* o,
+                        double* e_out, double* parts, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  RhfSetup S;
+  int r = rhf_setup(rd, o, S);
+  if (r) return r;
+  if (!e_out) return fail(LT_EINVAL, "e_out is NULL");
+  size_t inner = 0;
+  r = ltriples_workspace_size(&S.d, precision, &S.o, &inner);
+  if (r) return r;
+  const size_t need = S.head + inner;
+  bool own = false;
+  if (ws == nullptr) {
+    HIPCHK(hipMalloc(&ws, need));
+    own = true;
+  } else if (ws_bytes < need) {
+    return fail(LT_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)ws;
+  double* t2 = (double*)base;
+  double* tmp = (double*)(base + S.t2_bytes);
+  const int64_t no = rd->no, nv = rd->nv;
+  // t2aa[i][j][a][b] = tau[i][j][a][b] - tau[i][j][b][a]
+  r = LT_OK;
+  {
+    const hipError_t e = lt::launch_copy4d<double, double>(t2, no * nv * nv, nv * nv, nv, no, no, nv, nv, rd->tau,
+                                                           no * nv * nv, nv * nv, nv, 1, rd->tau, no * nv * nv,
+                                                           nv * nv, 1, nv, st);
+    if (e != hipSuccess) r = fail(LT_EHIP, "HIP error %s", hipGetErrorString(e));
+  }
+  if (r == LT_OK) {
+    S.d.t2aa = S.d.t2bb = t2;
+    r = ltriples_energy(&S.d, precision, &S.o, tmp, tmp + 1, base + S.head, need - S.head, stream);
+  }
+  if (r == LT_OK) {
+    const hipError_t e = lt::launch_rhf_combine(tmp, e_out, parts, st);
+    if (e != hipSuccess) r = fail(LT_EHIP, "HIP error %s", hipGetErrorString(e));
+  }
+  if (own) {
+    hipError_t e1 = hipStreamSynchronize(st);
+    hipError_t e2 = hipFree(ws);
+    if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) return fail(LT_EHIP, "HIP error at workspace release");
+  }
+  return r;
+}
+
 const char* ltriples_last_error(void) { return g_err.c_str(); }
 
 const char* ltriples_version(void) { return "ltriples 0.1.0 (gfx950)"; }

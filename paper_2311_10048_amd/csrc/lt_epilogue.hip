@@ -906,4 +906,19 @@ hipError_t launch_reduce_final(const double* e_items, const int32_t* order,
   return hipGetLastError();
 }
 
+// Closed-shell result from the spin-block one with identical alpha and beta
+// data: E = 2 (E_aaa + E_aab).  in[0] = E_aaa + E_aab, in[1 + 3 b + x] = part
+// x of block b.
+__global__ void k_rhf_combine(const double* in, double* e_out, double* parts) {
+  if (threadIdx.x != 0) return;
+  e_out[0] = 2.0 * in[0];
+  if (parts)
+    for (int x = 0; x < 3; ++x) parts[x] = 2.0 * (in[1 + x] + in[4 + x]);
+}
+
+hipError_t launch_rhf_combine(const double* in, double* e_out, double* parts, hipStream_t s) {
+  hipLaunchKernelGGL(k_rhf_combine, dim3(1), dim3(64), 0, s, in, e_out, parts);
+  return hipGetLastError();
+}
+
 }  // namespace lt

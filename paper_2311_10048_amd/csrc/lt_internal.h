@@ -291,6 +291,9 @@ struct EpsReduce {
 };
 hipError_t launch_eps_reduce(const EpsReduce& r, hipStream_t s);
 
+// e_out[0] = 2 in[0]; parts[x] = 2 (in[1 + x] + in[4 + x]) when parts is set
+hipError_t launch_rhf_combine(const double* in, double* e_out, double* parts, hipStream_t s);
+
 // out[x0*o0 + x1*o1 + x2*o2 + x3*o3] += scale * in[x0*i0 + x1*i1 + x2*i2 + x3*i3]
 // over x < d (a bijection: each output element written by one thread).
 template <typename Tin>

@@ -39,8 +39,10 @@ SHAPES = {
     "grad": (20, 18, 160, 162, 640),     # differentiation domain
     "large": (60, 58, 500, 502, 2000),   # large delocalised-SOMO domain
 }
+# (no, nv, naux) of the closed-shell (SOMO-free) workload: an LNO-sized domain
+RHF_SHAPES = {"rhf": (40, 300, 1200)}
 # seed offsets of the workloads above, and of the batched set
-CONFIG_INDEX = {"tiny": 0, "lno": 1, "batch": 2, "grad": 3, "large": 4}
+CONFIG_INDEX = {"tiny": 0, "lno": 1, "batch": 2, "grad": 3, "large": 4, "rhf": 5}
 
 
 @dataclasses.dataclass
@@ -169,6 +171,21 @@ def make_rhf_domain(no: int, nv: int, naux: int, seed: int, sigma_b: float = 0.0
     return Domain(no, no, nv, nv, naux, c(t1), c(t1.copy()), c(tss), c(tss.copy()), c(tau),
                   boo, bov, bvv, boo.copy(), bov.copy(), bvv.copy(),
                   eo, ev, eo.copy(), ev.copy(), c(fov), c(fov.copy()))
+
+
+RHF_ARRAYS = ("t1", "tau", "Boo", "Bov", "Bvv", "eo", "ev", "fov")
+
+
+def rhf_arrays(dom: Domain) -> dict:
+    """Spatial-orbital arrays of a closed-shell-consistent domain (the alpha
+    data; tau is the mixed-spin block)."""
+    return {"t1": dom.t1a, "tau": dom.t2ab, "Boo": dom.Boo_a, "Bov": dom.Bov_a, "Bvv": dom.Bvv_a,
+            "eo": dom.eo_a, "ev": dom.ev_a, "fov": dom.fov_a}
+
+
+def rhf_config_domain(name: str) -> Domain:
+    no, nv, naux = RHF_SHAPES[name]
+    return make_rhf_domain(no, nv, naux, BASE_SEED + 1000 * CONFIG_INDEX[name])
 
 
 def config_domain(name: str) -> Domain:

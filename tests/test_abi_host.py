@@ -198,3 +198,49 @@ def test_backward_plan_in_bounds_with_small_build_chunks(prec):
     o, _ = lt.make_options(build_chunk_mib=1)
     lib = lt.load_library()
     assert lib.ltriples_plan_check(ctypes.byref(d), prec, ctypes.byref(o), 1) == lt.LT_OK
+
+
+def _fake_rhf(dims, null=()):
+    t = {n: (0 if n in null else 0x1000 * (k + 1)) for k, n in enumerate(lt.RHF_FIELDS)}
+    return lt.make_rhf_domain(dims, t)
+
+
+@pytest.mark.parametrize("no,nv,naux", [(4, 10, 20), (40, 300, 1200), (2, 5, 8), (1, 5, 8)])
+def test_rhf_flops_items_and_workspace(no, nv, naux):
+    """The closed-shell call runs the aaa and aab items of the alpha == beta
+    spin-block domain: their count and flops, and a workspace that holds the
+    same-spin amplitudes ahead of the spin-block workspace."""
+    _lib()
+    d = _fake_rhf((no, nv, naux))
+    f, n = lt.ltriples_rhf_flops(d)
+    n0, n1 = no * (no - 1) * (no - 2) // 6, no * (no - 1) // 2 * no
+    assert n == n0 + n1
+    c = lambda m, k: float(np.prod([m - i for i in range(k)]) / np.prod(range(1, k + 1))) if m >= k else 0.0
+    want = c(no, 3) * (6 * nv**4 + 6 * nv**3 * no) \
+        + c(no, 2) * no * (4 * nv**4 + 6 * nv**4 + 4 * nv**3 * no + 6 * nv**3 * no)
+    assert abs(f - want) <= 1e-12 * max(want, 1.0)
+    # about half of the open-shell work of the same domain
+    fo, _ = lt.ltriples_flops(_fake_domain((no, no, nv, nv, naux)))
+    if fo > 0:
+        assert abs(f / fo - 0.5) < 1e-12
+    for prec in (lt.LT_FP64, lt.LT_FP32, lt.LT_BF16X3):
+        w = lt.ltriples_rhf_workspace_size(d, prec)
+        assert w >= 8 * no * no * nv * nv
+
+
+def test_rhf_rejects_bad_args():
+    lib = _lib()
+    assert lib.ltriples_rhf_workspace_size(None, lt.LT_FP64, None, ctypes.byref(ctypes.c_size_t())) == lt.LT_EINVAL
+    n = ctypes.c_size_t()
+    d = _fake_rhf((4, -1, 20))
+    assert lib.ltriples_rhf_workspace_size(ctypes.byref(d), lt.LT_FP64, None, ctypes.byref(n)) == lt.LT_EINVAL
+    d = _fake_rhf((4, 10, 20), null=("tau",))
+    assert lib.ltriples_rhf_workspace_size(ctypes.byref(d), lt.LT_FP64, None, ctypes.byref(n)) == lt.LT_EINVAL
+    assert "tau" in lt.ltriples_last_error()
+    d = _fake_rhf((4, 10, 20))
+    assert lib.ltriples_rhf_workspace_size(ctypes.byref(d), 11, None, ctypes.byref(n)) == lt.LT_EPREC
+    o, keep = lt.make_options(items=[(0, 0, 1, 2)])
+    assert lib.ltriples_rhf_workspace_size(ctypes.byref(d), lt.LT_FP64, ctypes.byref(o),
+                                           ctypes.byref(n)) == lt.LT_EINVAL
+    assert "closed-shell" in lt.ltriples_last_error()
+    assert lib.ltriples_energy_rhf(ctypes.byref(d), lt.LT_FP64, None, None, None, None, 0, None) == lt.LT_EINVAL

@@ -1,0 +1,101 @@
+"""GPU parity of the closed-shell entry point (ltriples_energy_rhf) through
+the C ABI.
+
+Reference: the oracle's independent closed-shell (T) formula over spatial
+orbitals (oracle.rhf, pinned on the CPU against the spin-orbital brute force
+and the spin-block energy with identical alpha and beta data).  Bars as the
+open-shell parity tests, relative to max(1 Eh, |E|): FP64 1e-11, FP32 1e-8,
+BF16x3 1e-6 on E; the parts E_ST and E_DT against their own magnitude
+(1e-10, 1e-4, 1e-3).  The call must also agree with the open-shell call on
+the same alpha == beta data.
+"""
+import numpy as np
+import pytest
+
+import paper_2311_10048_amd as lt
+import synth
+from oracle import rhf
+from tests.gpu_util import to_device
+
+pytestmark = pytest.mark.gpu
+
+TOL_E = {lt.LT_FP64: 1e-11, lt.LT_FP32: 1e-8, lt.LT_BF16X3: 1e-6}
+TOL_PART = {lt.LT_FP64: 1e-10, lt.LT_FP32: 1e-4, lt.LT_BF16X3: 1e-3}
+
+SHAPES = {
+    "small": (4, 21, 40),      # one epilogue tile plus a ragged one
+    "ragged": (6, 45, 96),     # several tiles, ragged tails
+    "two_occ": (2, 17, 30),    # no aaa items, aab only
+    "wide": (3, 70, 64),       # v > 64: several GEMM tiles
+}
+_REF = {}
+
+
+def _rhf_dev(dom):
+    import torch
+    return {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in synth.rhf_arrays(dom).items()}
+
+
+def _dom(shape):
+    # T1 and f_ov larger than the workload recipe so that E_ST and E_DT are
+    # well above the rounding of E4
+    return synth.make_rhf_domain(*shape, seed=synth.BASE_SEED + 23, sigma_f=3e-2, sigma_t1=3e-2)
+
+
+def _gpu(dom, prec, **kw):
+    import torch
+    e, parts = lt.ltriples_energy_rhf(_rhf_dev(dom), (dom.noa, dom.nva, dom.naux), prec, **kw)
+    torch.cuda.synchronize()
+    return float(e.item()), parts.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32, lt.LT_BF16X3])
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_rhf_parity_shapes(name, prec):
+    dom = _dom(SHAPES[name])
+    print(f"[rhf] {name} {SHAPES[name]} prec={prec}", flush=True)
+    if name not in _REF:
+        _REF[name] = rhf.energy(dom)
+    ref = _REF[name]
+    E, parts = _gpu(dom, prec)
+    scale = max(1.0, abs(ref["E"]))
+    assert abs(E - ref["E"]) <= TOL_E[prec] * scale, (E, ref["E"])
+    assert abs(parts[0] - ref["E4"]) <= 10 * TOL_E[prec] * max(1.0, abs(ref["E4"])), (parts[0], ref["E4"])
+    for x, key in ((1, "E_ST"), (2, "E_DT")):
+        assert abs(parts[x] - ref[key]) <= TOL_PART[prec] * abs(ref[key]) + 1e-300, (key, parts[x], ref[key])
+
+
+def test_rhf_matches_open_shell_call_on_identical_spins():
+    """E = 2 E_aaa + 2 E_aab: the open-shell call on the alpha == beta data
+    returns the same energy (its bbb and abb blocks equal aaa and aab)."""
+    import torch
+    dom = _dom(SHAPES["ragged"])
+    E, parts = _gpu(dom, lt.LT_FP64)
+    e2, p2 = lt.ltriples_energy(to_device(dom), dom.dims, lt.LT_FP64)
+    torch.cuda.synchronize()
+    p2 = p2.cpu().numpy()
+    assert abs(E - float(e2.item())) <= 1e-13 * abs(E)
+    assert np.allclose(p2[0], p2[3], rtol=1e-13, atol=0) and np.allclose(p2[1], p2[2], rtol=1e-13, atol=0)
+    assert np.allclose(parts, p2.sum(axis=0), rtol=1e-12, atol=0)
+
+
+def test_rhf_degenerate_shapes_give_zero():
+    """One doubly occupied orbital has no triples; no virtuals or no
+    occupied orbitals give nothing either."""
+    import torch
+    for shape in ((1, 10, 20), (3, 0, 10), (0, 5, 10)):
+        dom = synth.make_rhf_domain(*shape, seed=3)
+        e, parts = lt.ltriples_energy_rhf(_rhf_dev(dom), shape, lt.LT_FP64)
+        torch.cuda.synchronize()
+        assert float(e.item()) == 0.0 and not parts.cpu().numpy().any(), shape
+
+
+def test_rhf_batching_and_chunks_bitwise():
+    """Small batches and 1 MiB build chunks give the same bits as the
+    defaults (fixed reduction order)."""
+    dom = _dom(SHAPES["wide"])
+    E0, p0 = _gpu(dom, lt.LT_FP32)
+    E1, p1 = _gpu(dom, lt.LT_FP32, build_chunk_mib=1)
+    assert E0 == E1 and np.array_equal(p0, p1)
+    E2, p2 = _gpu(dom, lt.LT_FP32, batch_items=2)
+    assert abs(E2 - E0) <= 1e-12 * abs(E0)
