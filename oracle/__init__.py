@@ -15,9 +15,12 @@ Modules
   spinorb  brute-force spin-orbital evaluation of the master formula with the
            1/36 weight over all ordered occupied triples (tiny domains only).
   rhf      closed-shell (T) formula for alpha == beta inputs.
-  grad     gradient of the energy with respect to T1, T2 and the DF factors
-           (PyTorch float64 CPU reverse mode over a transcription of the
-           spin-blocked energy; projected convention for symmetric inputs).
+  grad     gradient of the energy with respect to T1, T2, the DF factors,
+           f_ov and the orbital energies (PyTorch float64 CPU reverse mode
+           over a transcription of the spin-blocked energy; projected
+           convention for symmetric inputs).
+  naf      natural auxiliary functions: the spin-averaged W of eq. naf_w,
+           its eigenvectors above a threshold, and the compressed factors.
 
 What the oracle computes (the paper's eq. cim_pt_energy, summed over the
 central index; the paper defers the definitions of t and W to the standard
@@ -40,6 +43,9 @@ Gradient pins (tests/test_oracle_grad.py): the transcription's energy
 equals blocks; <dE/dx, d> equals the exact 3-point (T) / 5-point (B) central
 stencil of blocks and of the spin-orbital brute force along random
 directions; the symmetry-image convention of the projected gradient.
+NAF pins (tests/test_oracle_naf.py): exact four-index integrals without
+truncation, discarded weight equal to the discarded eigenvalues, trace of W,
+the closed-shell limit, the rank of exactly low-rank input.
 Parity with the paper's molecular results is unpinned (the paper prints no
 per-domain (T) values).
 """

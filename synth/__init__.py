@@ -188,6 +188,29 @@ def rhf_config_domain(name: str) -> Domain:
     return make_rhf_domain(no, nv, naux, BASE_SEED + 1000 * CONFIG_INDEX[name])
 
 
+def make_naf_input(no_a: int, nv_a: int, no_b: int, nv_b: int, nx: int, seed: int, sigma: float = 0.05,
+                   decay: Optional[float] = None, rotate: bool = True):
+    """Three-index integrals J_s [nx][n_s][n_s] (n_s = no_s + nv_s, occupied
+    first) of both spins in one auxiliary basis: Z_s ~ N(0, sigma) symmetric
+    in the orbital pair, scaled along the auxiliary index by exp(-Y/decay)
+    (no scaling without decay) and, with rotate, mixed by one random
+    orthogonal matrix shared by the spins."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = np.ones(nx) if decay is None else np.exp(-np.arange(nx) / float(decay))
+    Q = np.linalg.qr(rng.normal(size=(nx, nx)))[0] if (rotate and nx > 0) else None
+    out = []
+    for no, nv in ((no_a, nv_a), (no_b, nv_b)):
+        n = no + nv
+        x = rng.normal(0.0, sigma, size=(nx, n, n))
+        z = (x + x.transpose(0, 2, 1)) * (1.0 / np.sqrt(2.0))
+        del x
+        z *= d[:, None, None]
+        if Q is not None:
+            z = (Q @ z.reshape(nx, n * n)).reshape(nx, n, n)
+        out.append(np.ascontiguousarray(z))
+    return out[0], out[1]
+
+
 def config_domain(name: str) -> Domain:
     """The fixed single-domain workloads by name (see SHAPES)."""
     noa, nob, nva, nvb, naux = SHAPES[name]
