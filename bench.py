@@ -167,7 +167,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "fp64", "bf16x3", "bf16"])
-    ap.add_argument("--workload", default="lno", choices=["tiny", "lno", "grad", "large", "batch", "rhf"])
+    ap.add_argument("--workload", default="lno", choices=["tiny", "lno", "grad", "large", "batch", "rhf", "naf"])
     ap.add_argument("--fp64-sample", type=int, default=48, help="items per block for the FP64 GPU comparison")
     ap.add_argument("--cpu-sample", type=int, default=3, help="items per block for the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -206,6 +206,9 @@ def main():
         return
     if args.workload == "rhf":
         run_rhf(args, lt, synth, torch)
+        return
+    if args.workload == "naf":
+        run_naf(args, lt, synth, torch)
         return
     dev = torch.device("cuda:0")
     prec = lt.PRECISIONS[args.precision]
@@ -558,6 +561,74 @@ def run_rhf(args, lt, synth, torch):
         "parity": parity, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def run_naf(args, lt, synth, torch):
+    """Natural-auxiliary-function step of an LNO-sized domain: 340 orbitals
+    per spin (40+300 and 38+302), 2400 auxiliary functions with a decaying
+    spectrum, eps 1e-2.  The oracle runs the same input on the host as the
+    CPU baseline and parity reference."""
+    from oracle import naf
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    shape, eps = (40, 300, 38, 302, 2400), 1e-2
+    t0 = time.time()
+    Ja, Jb = synth.make_naf_input(*shape, seed=synth.BASE_SEED + 6000, decay=250.0, rotate=False)
+    log(f"generated NAF input {shape} in {time.time() - t0:.1f} s")
+    ta, tb = torch.from_numpy(Ja).to(dev), torch.from_numpy(Jb).to(dev)
+    inp = lt.make_naf_input(shape, ta, tb)
+    ws = torch.empty(lt.ltriples_naf_workspace_size(inp), dtype=torch.uint8, device=dev)
+    for w in range(args.warmup):
+        lt.ltriples_naf(ta, tb, shape, eps, workspace=ws)
+        torch.cuda.synchronize()
+        log(f"warmup {w + 1}/{args.warmup} done")
+    times = []
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        m, out = lt.ltriples_naf(ta, tb, shape, eps, workspace=ws)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t) * 1e3)
+        log(f"step {k + 1}/{args.steps}: {times[-1]:.1f} ms, {m} NAFs kept")
+    ms = sum(times) / len(times)
+    na, nb, nx = shape[0] + shape[1], shape[2] + shape[3], shape[4]
+    # W build (pairs p <= q, both spins) and the two factor GEMMs, 2 flops per multiply-add
+    flops = 2.0 * nx * nx * (na * (na + 1) / 2 + nb * (nb + 1) / 2) + 2.0 * m * nx * (na * na + nb * nb)
+    parity = cpu = None
+    if not args.no_cpu_baseline:
+        tc = time.perf_counter()
+        lam, U, m_ref, Bref = naf.naf(Ja, Jb, eps)
+        dt = time.perf_counter() - tc
+        ev = out["eigenvalues"].cpu().numpy()
+        rng = np.random.default_rng(3)
+        idx = rng.choice(na * na, size=200, replace=False)
+        # (pq|rs) on sampled pairs of spin a, from the full [m][n][n] factors
+        full = np.zeros((m, na, na))
+        o = shape[0]
+        full[:, :o, :o] = out["Boo_a"].cpu().numpy()
+        full[:, :o, o:] = out["Bov_a"].cpu().numpy()
+        full[:, o:, :o] = full[:, :o, o:].transpose(0, 2, 1)
+        full[:, o:, o:] = out["Bvv_a"].cpu().numpy()
+        Xg = full.reshape(m, -1)[:, idx]
+        Xr = Bref[0].reshape(m_ref, -1)[:, idx]
+        gerr = float(np.max(np.abs(Xg.T @ Xg - Xr.T @ Xr)) / np.max(np.abs(Xr.T @ Xr)))
+        parity = {"naux_gpu": int(m), "naux_oracle": int(m_ref),
+                  "max_rel_err_eigenvalues": float(np.max(np.abs(ev - lam)) / abs(lam[0])),
+                  "max_rel_err_sampled_integrals": gerr,
+                  "pass": bool(m == m_ref and gerr <= 1e-12)}
+        cpu = {"value": round(dt * 1e3, 1), "unit": "ms", "cores": _blas_threads(), "kind": "oracle",
+               "sample": "the whole input (NumPy FP64: W over p <= q pairs, eigh, factors)"}
+        log(f"oracle {dt:.1f} s; naux {m} vs {m_ref}; integrals {gerr:.2e}")
+    res = {"metric": "natural-auxiliary-function step time", "value": round(ms, 2), "unit": "ms", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 2), "higher_is_better": False,
+           "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"NAF of an LNO-sized domain: {na} + {nb} orbitals, {nx} auxiliary functions, "
+                                  f"eps {eps}, {m} kept", "flops": flops},
+           "achieved_TFLOP/s": round(flops / (ms * 1e-3) / 1e12, 2), "parity": parity, "cpu_baseline": cpu}
+    print(json.dumps(res), flush=True)
 
 
 def run_backward(lt, synth, torch, log):

@@ -272,6 +272,43 @@ int ltriples_energy_rhf(const ltriples_rhf_domain* d, int32_t precision,
                         const ltriples_options* o, double* e_out, double* parts,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* Three-index integrals of one LIS for the natural-auxiliary-function step
+ * (section "Natural auxiliary functions", eq. naf_w): J_s[X][p][q] for each
+ * spin over all nx auxiliary functions and all n_s = no_s + nv_s orbitals of
+ * that spin (occupied first, then virtual), symmetric in (p, q) (not
+ * checked; the W build reads p <= q only).  Device pointers, FP64. */
+typedef struct ltriples_naf_input {
+  int32_t no_a, nv_a, no_b, nv_b, nx;
+  const double *Ja, *Jb;
+} ltriples_naf_input;
+
+/* Outputs of ltriples_naf: the factors in the NAF basis in the
+ * ltriples_domain layouts ([naux][..][..]), each with room for nx rows of
+ * which the first naux are written; eigenvalues (device double[nx],
+ * decreasing) may be NULL, and so may any factor block. */
+typedef struct ltriples_naf_output {
+  double *Boo_a, *Bov_a, *Bvv_a, *Boo_b, *Bov_b, *Bvv_b;
+  double* eigenvalues;
+} ltriples_naf_output;
+
+/* Host-only: workspace bytes of ltriples_naf. */
+int ltriples_naf_workspace_size(const ltriples_naf_input* in, size_t* bytes);
+
+/* Natural auxiliary functions shared by both spins: W_s = sum_{p<=q}
+ * J_s[X][pq] J_s[Y][pq], W = (W_a + W_b)/2, its eigenvectors U with
+ * eigenvalue > eps kept in order of decreasing eigenvalue, and
+ * B^Q_pq = sum_X U[X][Q] J_s[X][p][q] sliced into the occupied-occupied,
+ * occupied-virtual and virtual-virtual blocks of each spin.  *naux_out
+ * (host) receives the number kept.  W and the compressed factors are formed
+ * by rocBLAS (SYRK, GEMM) and diagonalised by rocSOLVER (syevd) on `stream`;
+ * the call waits for the stream once to count the kept eigenvalues.  The
+ * sign of each NAF is the eigensolver's; (pq|rs) = sum_Q B^Q_pq B^Q_rs does
+ * not depend on it.  ws as the other entry points (NULL: allocated inside).
+ * LT_EHIP also covers a rocBLAS/rocSOLVER failure or an eigensolver that
+ * did not converge. */
+int ltriples_naf(const ltriples_naf_input* in, double eps, const ltriples_naf_output* out,
+                 int32_t* naux_out, void* ws, size_t ws_bytes, void* stream);
+
 /* Description of the last error on this thread ("" if none). */
 const char* ltriples_last_error(void);
 

@@ -51,6 +51,16 @@ class Domain(ctypes.Structure):
 
 
 RHF_FIELDS = ("t1", "tau", "Boo", "Bov", "Bvv", "eo", "ev", "fov")
+NAF_OUT_FIELDS = ("Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b", "eigenvalues")
+
+
+class NafInput(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_int32) for n in ("no_a", "nv_a", "no_b", "nv_b", "nx")]
+                + [("Ja", ctypes.c_void_p), ("Jb", ctypes.c_void_p)])
+
+
+class NafOutput(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in NAF_OUT_FIELDS]
 
 
 class RhfDomain(ctypes.Structure):
@@ -131,12 +141,17 @@ def load_library(path: Optional[str] = None):
     lib.ltriples_rhf_flops.argtypes = [Rp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.ltriples_energy_rhf.argtypes = [Rp, ctypes.c_int32, Op, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    Np = ctypes.POINTER(NafInput)
+    lib.ltriples_naf_workspace_size.argtypes = [Np, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ltriples_naf.argtypes = [Np, ctypes.c_double, ctypes.POINTER(NafOutput), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.ltriples_last_error.restype = ctypes.c_char_p
     lib.ltriples_version.restype = ctypes.c_char_p
     for f in ("ltriples_validate", "ltriples_workspace_size", "ltriples_flops", "ltriples_energy",
               "ltriples_workspace_size_batched", "ltriples_energy_batched", "ltriples_graph_reset",
               "ltriples_backward_workspace_size", "ltriples_backward", "ltriples_plan_check",
-              "ltriples_rhf_workspace_size", "ltriples_rhf_flops", "ltriples_energy_rhf"):
+              "ltriples_rhf_workspace_size", "ltriples_rhf_flops", "ltriples_energy_rhf",
+              "ltriples_naf_workspace_size", "ltriples_naf"):
         getattr(lib, f).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -319,6 +334,55 @@ def ltriples_energy_rhf(tensors: Mapping[str, object], dims, precision: int = LT
                                    parts.data_ptr(), workspace.data_ptr(), workspace.numel(), st.cuda_stream))
     del keep
     return e, parts
+
+
+def make_naf_input(dims, Ja=None, Jb=None) -> NafInput:
+    """ltriples_naf_input from (no_a, nv_a, no_b, nv_b, nx) and the two
+    three-index integral tensors [nx][n_s][n_s] (device)."""
+    x = NafInput()
+    x.no_a, x.nv_a, x.no_b, x.nv_b, x.nx = (int(v) for v in dims)
+    for name, t in (("Ja", Ja), ("Jb", Jb)):
+        if t is not None and hasattr(t, "is_contiguous"):
+            if not t.is_contiguous() or str(t.dtype) != "torch.float64":
+                raise ValueError(f"{name} must be contiguous float64")
+        setattr(x, name, _ptr(t))
+    return x
+
+
+def ltriples_naf_workspace_size(inp: NafInput) -> int:
+    lib = load_library()
+    n = ctypes.c_size_t(0)
+    _check(lib.ltriples_naf_workspace_size(ctypes.byref(inp), ctypes.byref(n)))
+    return n.value
+
+
+def ltriples_naf(Ja, Jb, dims, eps: float, workspace=None, stream=None):
+    """Natural auxiliary functions of one LIS: returns (naux, dict) with the
+    compressed factors Boo_a ... Bvv_b ([naux][..][..]) and all eigenvalues
+    of W in decreasing order, as float64 device tensors."""
+    import torch
+    no_a, nv_a, no_b, nv_b, nx = (int(v) for v in dims)
+    inp = make_naf_input(dims, Ja, Jb)
+    dev = Ja.device
+    need = ltriples_naf_workspace_size(inp)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    shapes = {"Boo_a": (no_a, no_a), "Bov_a": (no_a, nv_a), "Bvv_a": (nv_a, nv_a),
+              "Boo_b": (no_b, no_b), "Bov_b": (no_b, nv_b), "Bvv_b": (nv_b, nv_b)}
+    outs = {k: torch.empty((nx,) + sh, dtype=torch.float64, device=dev) for k, sh in shapes.items()}
+    outs["eigenvalues"] = torch.empty(nx, dtype=torch.float64, device=dev)
+    o = NafOutput()
+    for k in NAF_OUT_FIELDS:
+        setattr(o, k, _ptr(outs[k]) if outs[k].numel() else 0)
+    naux = ctypes.c_int32(0)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    lib = load_library()
+    _check(lib.ltriples_naf(ctypes.byref(inp), float(eps), ctypes.byref(o), ctypes.byref(naux),
+                            workspace.data_ptr(), workspace.numel(), st.cuda_stream))
+    m = naux.value
+    res = {k: v[:m].contiguous() for k, v in outs.items() if k != "eigenvalues"}
+    res["eigenvalues"] = outs["eigenvalues"]
+    return m, res
 
 
 def _domain_array(dims_list, tensors_list):

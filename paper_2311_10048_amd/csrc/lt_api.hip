@@ -22,6 +22,9 @@
 #include <mutex>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include "lt_internal.h"
 #include "ltriples.h"
 
@@ -2311,6 +2314,179 @@ int ltriples_energy_rhf(const ltriples_rhf_domain* rd, int32_t precision, const 
     hipError_t e1 = hipStreamSynchronize(st);
     hipError_t e2 = hipFree(ws);
     if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) return fail(LT_EHIP, "HIP error at workspace release");
+  }
+  return r;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Natural auxiliary functions: pair-packed integrals -> W by SYRK (rocBLAS),
+// eigenvectors by syevd (rocSOLVER), kept vectors in decreasing order, the
+// compressed factors by GEMM and strided slices.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct NafPlan {
+  int64_t n[2], o[2], nx, pmax, nmax;
+  size_t oP, oW, oD, oE, oInfo, oUk, oB, total;
+};
+
+int naf_plan(const ltriples_naf_input* in, NafPlan& P) {
+  if (!in) return fail(LT_EINVAL, "input is NULL");
+  if (in->no_a < 0 || in->nv_a < 0 || in->no_b < 0 || in->nv_b < 0 || in->nx < 0)
+    return fail(LT_EINVAL, "negative dimension");
+  P.o[0] = in->no_a; P.o[1] = in->no_b;
+  P.n[0] = (int64_t)in->no_a + in->nv_a; P.n[1] = (int64_t)in->no_b + in->nv_b;
+  P.nx = in->nx;
+  if (P.n[0] > 46340 || P.n[1] > 46340 || P.nx > 46340) return fail(LT_ESHAPE, "dimension too large");
+  if (P.nx > 0 && P.n[0] > 0 && !in->Ja) return fail(LT_EINVAL, "Ja is NULL");
+  if (P.nx > 0 && P.n[1] > 0 && !in->Jb) return fail(LT_EINVAL, "Jb is NULL");
+  P.nmax = std::max(P.n[0], P.n[1]);
+  P.pmax = P.nmax * (P.nmax + 1) / 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off = align256(off + std::max<size_t>(bytes, 1)); return o; };
+  const size_t nx = (size_t)P.nx;
+  P.oP = take(8 * nx * (size_t)P.pmax);
+  P.oW = take(8 * nx * nx);
+  P.oD = take(8 * nx);
+  P.oE = take(8 * nx);
+  P.oInfo = take(sizeof(rocblas_int));
+  P.oUk = take(8 * nx * nx);
+  P.oB = take(8 * nx * (size_t)(P.nmax * P.nmax));
+  P.total = off;
+  return LT_OK;
+}
+
+#define RBCHK(...)                                                                      \
+  do {                                                                                  \
+    rocblas_status s_ = (__VA_ARGS__);                                                  \
+    if (s_ != rocblas_status_success) {                                                 \
+      r = fail(LT_EHIP, "rocBLAS/rocSOLVER status %d at %s:%d", (int)s_, __FILE__, __LINE__); \
+      goto done;                                                                        \
+    }                                                                                   \
+  } while (0)
+#define HIPGO(...)                                                                      \
+  do {                                                                                  \
+    hipError_t e_ = (__VA_ARGS__);                                                      \
+    if (e_ != hipSuccess) {                                                             \
+      r = fail(LT_EHIP, "HIP error %s at %s:%d", hipGetErrorString(e_), __FILE__, __LINE__); \
+      goto done;                                                                        \
+    }                                                                                   \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int ltriples_naf_workspace_size(const ltriples_naf_input* in, size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(LT_EINVAL, "bytes is NULL");
+  NafPlan P;
+  const int r = naf_plan(in, P);
+  if (r) return r;
+  *bytes = P.total;
+  return LT_OK;
+}
+
+int ltriples_naf(const ltriples_naf_input* in, double eps, const ltriples_naf_output* out, int32_t* naux_out,
+                 void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  NafPlan P;
+  int r = naf_plan(in, P);
+  if (r) return r;
+  if (!out || !naux_out) return fail(LT_EINVAL, "output is NULL");
+  if (std::isnan(eps)) return fail(LT_EINVAL, "eps is NaN");
+  hipStream_t st = (hipStream_t)stream;
+  bool own = false;
+  if (ws == nullptr) {
+    HIPCHK(hipMalloc(&ws, P.total));
+    own = true;
+  } else if (ws_bytes < P.total) {
+    return fail(LT_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, P.total);
+  }
+  char* base = (char*)ws;
+  double* Pk = (double*)(base + P.oP);
+  double* W = (double*)(base + P.oW);
+  double* D = (double*)(base + P.oD);
+  double* E = (double*)(base + P.oE);
+  rocblas_int* info = (rocblas_int*)(base + P.oInfo);
+  double* Uk = (double*)(base + P.oUk);
+  double* Bf = (double*)(base + P.oB);
+  const double* J[2] = {in->Ja, in->Jb};
+  double* outs[2][3] = {{out->Boo_a, out->Bov_a, out->Bvv_a}, {out->Boo_b, out->Bov_b, out->Bvv_b}};
+  const int nx = (int)P.nx;
+  rocblas_handle h = nullptr;
+  std::vector<double> Dh(P.nx);
+  rocblas_int info_h = 0;
+  int64_t m = 0;
+  *naux_out = 0;
+  if (nx == 0) goto done;
+  RBCHK(rocblas_create_handle(&h));
+  RBCHK(rocblas_set_stream(h, st));
+  RBCHK(rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed));   // fixed summation order
+  {
+    // W = (W_a + W_b) / 2, W_s = P_s^T P_s over the pair-packed rows (upper triangle)
+    bool first = true;
+    for (int s = 0; s < 2; ++s) {
+      const int n = (int)P.n[s];
+      if (n == 0) continue;
+      const rocblas_int np = (rocblas_int)((int64_t)n * (n + 1) / 2);
+      HIPGO(lt::launch_naf_pack(Pk, J[s], n, nx, st));
+      const double alpha = 0.5, beta = first ? 0.0 : 1.0;
+      RBCHK(rocblas_dsyrk(h, rocblas_fill_upper, rocblas_operation_transpose, nx, np, &alpha, Pk, np, &beta, W,
+                          nx));
+      first = false;
+    }
+    if (first) HIPGO(lt::launch_zero(W, (int64_t)nx * nx, st));
+  }
+  RBCHK(rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, nx, W, nx, D, E, info));
+  HIPGO(hipMemcpyAsync(Dh.data(), D, 8 * (size_t)nx, hipMemcpyDeviceToHost, st));
+  HIPGO(hipMemcpyAsync(&info_h, info, sizeof(info_h), hipMemcpyDeviceToHost, st));
+  HIPGO(hipStreamSynchronize(st));
+  if (info_h != 0) {
+    r = fail(LT_EHIP, "eigensolver did not converge (info %d)", (int)info_h);
+    goto done;
+  }
+  for (int64_t k = 0; k < P.nx; ++k) m += Dh[k] > eps ? 1 : 0;
+  // eigenvalues and kept vectors in decreasing order (syevd returns them increasing)
+  if (out->eigenvalues)
+    HIPGO(lt::launch_copy4d<double, double>(out->eigenvalues, 0, 0, 0, 1, 1, 1, nx, D + (nx - 1), 0, 0, 0, -1,
+                                            nullptr, 0, 0, 0, 0, st));
+  if (m > 0) {
+    // Uk column Q (column-major, nx x m) = eigenvector nx - 1 - Q
+    HIPGO(lt::launch_copy4d<double, double>(Uk, 0, 0, nx, 1, 1, m, nx, W + (int64_t)(nx - 1) * nx, 0, 0, -nx, 1,
+                                            nullptr, 0, 0, 0, 0, st));
+    for (int s = 0; s < 2; ++s) {
+      const int64_t n = P.n[s], o = P.o[s], v = n - o;
+      if (n == 0 || (!outs[s][0] && !outs[s][1] && !outs[s][2])) continue;
+      // Bf[Q][pq] (column-major n^2 x m) = J_s (n^2 x nx) * Uk
+      const double one = 1.0, zero = 0.0;
+      RBCHK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)(n * n), (rocblas_int)m,
+                          nx, &one, J[s], (rocblas_int)(n * n), Uk, nx, &zero, Bf, (rocblas_int)(n * n)));
+      if (outs[s][0])
+        HIPGO(lt::launch_copy4d<double, double>(outs[s][0], 0, o * o, o, 1, m, o, o, Bf, 0, n * n, n, 1, nullptr, 0,
+                                                0, 0, 0, st));
+      if (outs[s][1])
+        HIPGO(lt::launch_copy4d<double, double>(outs[s][1], 0, o * v, v, 1, m, o, v, Bf + o, 0, n * n, n, 1,
+                                                nullptr, 0, 0, 0, 0, st));
+      if (outs[s][2])
+        HIPGO(lt::launch_copy4d<double, double>(outs[s][2], 0, v * v, v, 1, m, v, v, Bf + o * n + o, 0, n * n, n, 1,
+                                                nullptr, 0, 0, 0, 0, st));
+    }
+  }
+  *naux_out = (int32_t)m;
+done:
+  if (h) {
+    const hipError_t e1 = hipStreamSynchronize(st);
+    const rocblas_status e2 = rocblas_destroy_handle(h);
+    if (r == LT_OK && (e1 != hipSuccess || e2 != rocblas_status_success))
+      r = fail(LT_EHIP, "error at rocBLAS handle release");
+  }
+  if (own) {
+    const hipError_t e1 = hipStreamSynchronize(st);
+    const hipError_t e2 = hipFree(ws);
+    if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) r = fail(LT_EHIP, "HIP error at workspace release");
   }
   return r;
 }

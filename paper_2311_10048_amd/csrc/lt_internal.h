@@ -291,6 +291,9 @@ struct EpsReduce {
 };
 hipError_t launch_eps_reduce(const EpsReduce& r, hipStream_t s);
 
+// P[X][pair] = J[X][p][q] for p <= q (pair-packed rows of n (n + 1) / 2)
+hipError_t launch_naf_pack(double* P, const double* J, int32_t n, int32_t nx, hipStream_t s);
+
 // e_out[0] = 2 in[0]; parts[x] = 2 (in[1 + x] + in[4 + x]) when parts is set
 hipError_t launch_rhf_combine(const double* in, double* e_out, double* parts, hipStream_t s);
 

@@ -81,6 +81,25 @@ hipError_t launch_pack_pairs(Tout* out, int64_t ldo, int64_t rows, int32_t n,
   return hipGetLastError();
 }
 
+// Pair packing for the NAF metric: P[X][pair] = J[X][p][q] over p <= q,
+// pairs ordered row by row (pair = p n - p (p - 1) / 2 + q - p).  One
+// work-group per (p, X) row; reads and writes are contiguous in q.
+__global__ __launch_bounds__(256) void k_naf_pack(double* P, const double* J, int32_t n, int64_t npairs) {
+  const int p = blockIdx.x;
+  const int64_t X = blockIdx.y;
+  const int64_t off = (int64_t)p * n - (int64_t)p * (p - 1) / 2;
+  const double* src = J + X * n * n + (int64_t)p * n;
+  double* dst = P + X * npairs + off;
+  for (int q = p + threadIdx.x; q < n; q += 256) dst[q - p] = src[q];
+}
+
+hipError_t launch_naf_pack(double* P, const double* J, int32_t n, int32_t nx, hipStream_t s) {
+  if (n <= 0 || nx <= 0) return hipSuccess;
+  const int64_t npairs = (int64_t)n * (n + 1) / 2;
+  hipLaunchKernelGGL(k_naf_pack, dim3(n, nx), dim3(256), 0, s, P, J, n, npairs);
+  return hipGetLastError();
+}
+
 template hipError_t launch_copy4d<double, double>(double*, int64_t, int64_t, int64_t, int64_t, int64_t,
                                                   int64_t, int64_t, const double*, int64_t, int64_t,
                                                   int64_t, int64_t, const double*, int64_t, int64_t,

@@ -244,3 +244,23 @@ def test_rhf_rejects_bad_args():
                                            ctypes.byref(n)) == lt.LT_EINVAL
     assert "closed-shell" in lt.ltriples_last_error()
     assert lib.ltriples_energy_rhf(ctypes.byref(d), lt.LT_FP64, None, None, None, None, 0, None) == lt.LT_EINVAL
+
+
+def test_naf_workspace_and_errors():
+    lib = _lib()
+    x = lt.make_naf_input((3, 5, 2, 6, 20), 0x1000, 0x2000)
+    w = lt.ltriples_naf_workspace_size(x)
+    na = nb = 8
+    # pair-packed integrals, W, eigenvectors, the kept vectors and one spin's factors
+    assert w >= 8 * (20 * na * (na + 1) // 2 + 2 * 20 * 20 + 20 * na * na)
+    n = ctypes.c_size_t()
+    bad = lt.make_naf_input((3, 5, 2, 6, 20), 0, 0x2000)
+    assert lib.ltriples_naf_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == lt.LT_EINVAL
+    assert "Ja" in lt.ltriples_last_error()
+    bad = lt.make_naf_input((3, -5, 2, 6, 20), 0x1000, 0x2000)
+    assert lib.ltriples_naf_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == lt.LT_EINVAL
+    out = lt.NafOutput()
+    m = ctypes.c_int32()
+    assert lib.ltriples_naf(ctypes.byref(x), 1e-2, None, ctypes.byref(m), None, 0, None) == lt.LT_EINVAL
+    assert lib.ltriples_naf(ctypes.byref(x), float("nan"), ctypes.byref(out), ctypes.byref(m), None, 0,
+                            None) == lt.LT_EINVAL

@@ -1,0 +1,107 @@
+"""GPU parity of the natural-auxiliary-function step (ltriples_naf) through
+the C ABI against the oracle (oracle.naf, pinned on the CPU).
+
+Compared: the number of kept functions (exact), all eigenvalues of W (to
+1e-12 of the largest), the four-index integrals (pq|rs) = sum_Q B B of both
+spins and the mixed-spin ones (to 1e-12 of the largest; they do not depend
+on the sign of each NAF), each factor up to that sign (to 1e-8 where the
+spectrum is well separated), and E(T) of a domain built from the compressed
+factors against the oracle energy of the oracle's factors (FP64 path, 1e-11).
+"""
+import numpy as np
+import pytest
+
+import paper_2311_10048_amd as lt
+import synth
+from oracle import blocks, naf
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # (no_a, nv_a, no_b, nv_b, nx), decay, eps
+    "keep_all": ((3, 5, 2, 6, 20), None, -1.0),
+    "truncated": ((6, 30, 5, 31, 120), 12.0, 1e-2),
+    "wide_aux": ((4, 40, 4, 40, 300), 40.0, 1e-2),
+    "one_spin_empty": ((4, 9, 0, 0, 40), 8.0, 1e-3),
+}
+
+
+def _run(shape, decay, eps, seed=7):
+    import torch
+    Ja, Jb = synth.make_naf_input(*shape, seed=seed, decay=decay)
+    m, out = lt.ltriples_naf(torch.from_numpy(Ja).cuda(), torch.from_numpy(Jb).cuda(), shape, eps)
+    torch.cuda.synchronize()
+    return Ja, Jb, m, {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _full(B, no):
+    """[m][n][n] from the three blocks of one spin (symmetric)."""
+    Boo, Bov, Bvv = B
+    m, o, v = Bov.shape[0], Boo.shape[1], Bvv.shape[1]
+    F = np.zeros((m, o + v, o + v))
+    F[:, :o, :o] = Boo
+    F[:, :o, o:] = Bov
+    F[:, o:, :o] = Bov.transpose(0, 2, 1)
+    F[:, o:, o:] = Bvv
+    return F
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_naf_parity(name):
+    shape, decay, eps = CASES[name]
+    print(f"[naf] {name} {shape} eps={eps}", flush=True)
+    Ja, Jb, m, g = _run(shape, decay, eps)
+    lam, U, m_ref, Bref = naf.naf(Ja, Jb, eps)
+    assert m == m_ref
+    assert np.max(np.abs(g["eigenvalues"] - lam)) <= 1e-12 * max(abs(lam[0]), 1e-300)
+    no = (shape[0], shape[2])
+    Bg = [_full((g["Boo_a"], g["Bov_a"], g["Bvv_a"]), no[0]), _full((g["Boo_b"], g["Bov_b"], g["Bvv_b"]), no[1])]
+    for s in range(2):
+        n = Bref[s].shape[1]
+        if n == 0 or m == 0:
+            continue
+        Xg, Xr = Bg[s].reshape(m, n * n), Bref[s].reshape(m, n * n)
+        gram, gref = Xg.T @ Xg, Xr.T @ Xr
+        assert np.max(np.abs(gram - gref)) <= 1e-12 * np.max(np.abs(gref)), s
+    if Bref[1].shape[1] and m:
+        na, nb = Bref[0].shape[1], Bref[1].shape[1]
+        mix = Bg[0].reshape(m, na * na).T @ Bg[1].reshape(m, nb * nb)
+        mref = Bref[0].reshape(m, na * na).T @ Bref[1].reshape(m, nb * nb)
+        assert np.max(np.abs(mix - mref)) <= 1e-12 * np.max(np.abs(mref))
+    if decay is not None and m:
+        # separated spectrum: each NAF equals the oracle's up to its sign
+        for s in range(2):
+            if Bref[s].shape[1] == 0:
+                continue
+            for Q in range(m):
+                sg = np.sign(np.sum(Bg[s][Q] * Bref[s][Q]))
+                assert np.max(np.abs(sg * Bg[s][Q] - Bref[s][Q])) <= 1e-8 * np.max(np.abs(Bref[s][Q])), (s, Q)
+
+
+def test_naf_feeds_the_energy():
+    """E(T) of a domain whose factors come from ltriples_naf equals the
+    oracle energy of the same domain with the oracle's factors."""
+    import torch
+    shape = (5, 20, 4, 21, 90)
+    Ja, Jb, m, g = _run(shape, 15.0, 1e-2, seed=21)
+    lam, U, m_ref, Bref = naf.naf(Ja, Jb, 1e-2)
+    assert m == m_ref and 0 < m < shape[4]
+    dom = synth.make_domain(shape[0], shape[2], shape[1], shape[3], m, seed=synth.BASE_SEED + 5)
+    Boo_a, Bov_a, Bvv_a = naf.split(Bref[0], shape[0])
+    Boo_b, Bov_b, Bvv_b = naf.split(Bref[1], shape[2])
+    ref_dom = dom.replace(Boo_a=Boo_a, Bov_a=Bov_a, Bvv_a=Bvv_a, Boo_b=Boo_b, Bov_b=Bov_b, Bvv_b=Bvv_b)
+    ref = blocks.energy(ref_dom)
+    t = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in dom.arrays().items()}
+    for k in ("Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b"):
+        t[k] = torch.from_numpy(np.ascontiguousarray(g[k])).cuda()
+    e, _ = lt.ltriples_energy(t, dom.dims, lt.LT_FP64)
+    torch.cuda.synchronize()
+    E = float(e.item())
+    assert abs(E - ref["E"]) <= 1e-11 * max(1.0, abs(ref["E"])), (E, ref["E"])
+
+
+def test_naf_empty_auxiliary_basis():
+    import torch
+    Ja = torch.zeros((0, 5, 5), dtype=torch.float64, device="cuda")
+    m, out = lt.ltriples_naf(Ja, Ja, (2, 3, 2, 3, 0), 1e-2)
+    assert m == 0
