@@ -300,7 +300,7 @@ int ltriples_naf_workspace_size(const ltriples_naf_input* in, size_t* bytes);
  * B^Q_pq = sum_X U[X][Q] J_s[X][p][q] sliced into the occupied-occupied,
  * occupied-virtual and virtual-virtual blocks of each spin.  *naux_out
  * (host) receives the number kept.  W and the compressed factors are formed
- * by rocBLAS (SYRK, GEMM) and diagonalised by rocSOLVER (syevd) on `stream`;
+ * by rocBLAS GEMMs and W is diagonalised by rocSOLVER (syevd) on `stream`;
  * the call waits for the stream once to count the kept eigenvalues.  The
  * sign of each NAF is the eigensolver's; (pq|rs) = sum_Q B^Q_pq B^Q_rs does
  * not depend on it.  ws as the other entry points (NULL: allocated inside).

@@ -2321,7 +2321,7 @@ int ltriples_energy_rhf(const ltriples_rhf_domain* rd, int32_t precision, const 
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Natural auxiliary functions: pair-packed integrals -> W by SYRK (rocBLAS),
+// Natural auxiliary functions: pair-packed integrals -> W by GEMM (rocBLAS),
 // eigenvectors by syevd (rocSOLVER), kept vectors in decreasing order, the
 // compressed factors by GEMM and strided slices.
 // ---------------------------------------------------------------------------
@@ -2426,7 +2426,11 @@ int ltriples_naf(const ltriples_naf_input* in, double eps, const ltriples_naf_ou
   RBCHK(rocblas_set_stream(h, st));
   RBCHK(rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed));   // fixed summation order
   {
-    // W = (W_a + W_b) / 2, W_s = P_s^T P_s over the pair-packed rows (upper triangle)
+    // W = (W_a + W_b) / 2, W_s = P_s^T P_s over the pair-packed rows.  One
+    // full-square GEMM per spin: with a contraction of ~n^2/2 pairs against
+    // nx^2 outputs, the library's triangular SYRK splits into a few narrow
+    // GEMMs that leave most of the GPU idle, while the square GEMM fills it
+    // (twice the flops, several times faster).
     bool first = true;
     for (int s = 0; s < 2; ++s) {
       const int n = (int)P.n[s];
@@ -2434,8 +2438,8 @@ int ltriples_naf(const ltriples_naf_input* in, double eps, const ltriples_naf_ou
       const rocblas_int np = (rocblas_int)((int64_t)n * (n + 1) / 2);
       HIPGO(lt::launch_naf_pack(Pk, J[s], n, nx, st));
       const double alpha = 0.5, beta = first ? 0.0 : 1.0;
-      RBCHK(rocblas_dsyrk(h, rocblas_fill_upper, rocblas_operation_transpose, nx, np, &alpha, Pk, np, &beta, W,
-                          nx));
+      RBCHK(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, nx, nx, np, &alpha, Pk, np, Pk, np,
+                          &beta, W, nx));
       first = false;
     }
     if (first) HIPGO(lt::launch_zero(W, (int64_t)nx * nx, st));
