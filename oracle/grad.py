@@ -206,3 +206,68 @@ def energy_and_grad(dom, items=None, gbar=1.0, threads=None, fock=False):
         for k in FOCK_FIELDS:
             grads[k] = C[k].grad.numpy().copy() if C[k].grad is not None else np.zeros(C[k].shape)
     return E, grads
+
+
+RHF_FIELDS = ("t1", "tau", "Boo", "Bov", "Bvv", "eo", "ev", "fov")
+
+
+def _rhf_energy_torch(X):
+    """The closed-shell formula of oracle.rhf, transcribed in torch float64
+    (same steps and order): all ordered occupied triples, full virtual
+    cubes."""
+    import itertools
+    t1, tau, f = X["t1"], X["tau"], X["fov"]
+    eo, ev = X["eo"], X["ev"]
+    Boo, Bov, Bvv = X["Boo"], X["Bov"], X["Bvv"]
+    no, nv = t1.shape
+    nq = Bov.shape[0]
+    kc_be = (Bov.reshape(nq, -1).T @ Bvv.reshape(nq, -1)).reshape(no, nv, nv, nv)
+    kc_mj = (Bov.reshape(nq, -1).T @ Boo.reshape(nq, -1)).reshape(no, nv, no, no)
+    ia_jb = (Bov.reshape(nq, -1).T @ Bov.reshape(nq, -1)).reshape(no, nv, no, nv)
+
+    def Xt(i, j, k):
+        x = torch.einsum("ae,cbe->abc", tau[i, j], kc_be[k])
+        y = torch.einsum("mab,cm->abc", tau[i], kc_mj[k][:, :, j])
+        return x - y
+
+    perms = list(itertools.permutations(range(3)))
+    letters = "abc"
+    dv = ev[:, None, None] + ev[None, :, None] + ev[None, None, :]
+    E = 0.0
+    for i in range(no):
+        for j in range(no):
+            for k in range(no):
+                occ = (i, j, k)
+                w = 0.0
+                for p in perms:
+                    sub = "".join(letters[x] for x in p)
+                    w = w + torch.einsum(sub + "->abc", Xt(*(occ[x] for x in p)))
+                vt = (torch.einsum("a,bc->abc", t1[i], ia_jb[j, :, k, :])
+                      + torch.einsum("b,ac->abc", t1[j], ia_jb[i, :, k, :])
+                      + torch.einsum("c,ab->abc", t1[k], ia_jb[i, :, j, :]))
+                vf = (torch.einsum("a,bc->abc", f[i], tau[j, k])
+                      + torch.einsum("b,ac->abc", f[j], tau[i, k])
+                      + torch.einsum("c,ab->abc", f[k], tau[i, j]))
+                v = w + vt + vf
+                z = 4.0 * w + w.permute(1, 2, 0) + w.permute(2, 0, 1)
+                d = (eo[i] + eo[j] + eo[k]) - dv
+                E = E + torch.sum(z * (v - v.permute(2, 1, 0)) / d)
+    return E / 3.0
+
+
+def rhf_energy_and_grad(arrays, gbar=1.0, threads=None):
+    """Closed-shell E(T) of spatial-orbital arrays (keys RHF_FIELDS) and
+    gbar * dE/dx for each, by reverse mode over the closed-shell formula.
+    Convention: dE/dtau is projected onto the symmetry tau^{ab}_{ij} =
+    tau^{ba}_{ji}, dE/dBoo and dE/dBvv are symmetrised in their orbital
+    indices; the others carry no constraint."""
+    if threads:
+        torch.set_num_threads(int(threads))
+    X = {k: torch.tensor(np.asarray(arrays[k]), dtype=torch.float64, requires_grad=True) for k in RHF_FIELDS}
+    E = _rhf_energy_torch(X)
+    (gbar * E).backward()
+    g = {k: (X[k].grad.numpy().copy() if X[k].grad is not None else np.zeros(X[k].shape)) for k in RHF_FIELDS}
+    g["tau"] = 0.5 * (g["tau"] + g["tau"].transpose(1, 0, 3, 2))
+    for k in ("Boo", "Bvv"):
+        g[k] = 0.5 * (g[k] + g[k].transpose(0, 2, 1))
+    return float(E.detach()), g

@@ -319,3 +319,57 @@ def test_planted_denominator_error_breaks_shift_invariance(monkeypatch):
     tot = sum(float(np.sum(g[k])) for k in EPS_FIELDS)
     mag = sum(float(np.sum(np.abs(g[k]))) for k in EPS_FIELDS)
     assert abs(tot) > 1e-6 * mag
+
+
+def _rhf_arrays(shape, seed=13):
+    dom = synth.make_rhf_domain(*shape, seed=seed, sigma_f=3e-2, sigma_t1=3e-2)
+    return dom, synth.rhf_arrays(dom)
+
+
+def _rhf_dir(arr, k, rng):
+    x = np.asarray(arr[k])
+    d = rng.normal(0.0, 1.0, size=x.shape) * (np.std(x) + 1e-3)
+    if k == "tau":
+        d = d + d.transpose(1, 0, 3, 2)
+    if k in ("Boo", "Bvv"):
+        d = d + d.transpose(0, 2, 1)
+    return d
+
+
+@pytest.mark.parametrize("shape", [(3, 5, 12), (4, 4, 10), (2, 5, 9)])
+def test_rhf_gradient_against_closed_shell_formula(shape):
+    """The torch transcription's energy equals oracle.rhf, and <g, d> equals
+    the 5-point central difference of oracle.rhf along random directions in
+    every input's constrained space (exact for the polynomial inputs, to the
+    stencil error for the orbital energies)."""
+    from oracle import rhf
+    dom, arr = _rhf_arrays(shape)
+    E, g = grad.rhf_energy_and_grad(arr)
+    E0 = rhf.energy(dom)["E"]
+    assert abs(E - E0) <= 1e-12 * abs(E0)
+    rng = np.random.default_rng(41)
+
+    def erhf(k, d, h):
+        a = dict(arr)
+        a[k] = np.asarray(arr[k]) + h * d
+        # oracle.rhf reads the alpha arrays of a spin-blocked domain
+        key = {"t1": "t1a", "tau": "t2ab", "Boo": "Boo_a", "Bov": "Bov_a", "Bvv": "Bvv_a", "eo": "eo_a",
+               "ev": "ev_a", "fov": "fov_a"}[k]
+        return rhf.energy(dom.replace(**{key: a[k]}))["E"]
+    for k in grad.RHF_FIELDS:
+        d = _rhf_dir(arr, k, rng)
+        h = 1e-3 if k in ("eo", "ev") else 0.5
+        fd = (-erhf(k, d, 2 * h) + 8 * erhf(k, d, h) - 8 * erhf(k, d, -h) + erhf(k, d, -2 * h)) / (12 * h)
+        an = float(np.sum(g[k] * d))
+        assert abs(an - fd) <= 1e-7 * max(abs(fd), 1e-9 * abs(E0)), (k, an, fd)
+
+
+def test_rhf_gradient_symmetry_and_identities():
+    dom, arr = _rhf_arrays((3, 5, 12))
+    E, g = grad.rhf_energy_and_grad(arr)
+    assert np.max(np.abs(g["tau"] - g["tau"].transpose(1, 0, 3, 2))) <= 1e-15 * np.max(np.abs(g["tau"]))
+    # common shift of the orbital energies, degree -1 homogeneity
+    tot = float(np.sum(g["eo"]) + np.sum(g["ev"]))
+    assert abs(tot) <= 1e-12 * float(np.sum(np.abs(g["eo"])) + np.sum(np.abs(g["ev"])))
+    euler = float(np.sum(arr["eo"] * g["eo"]) + np.sum(arr["ev"] * g["ev"]))
+    assert abs(euler + E) <= 1e-12 * abs(E)
