@@ -272,6 +272,30 @@ int ltriples_energy_rhf(const ltriples_rhf_domain* d, int32_t precision,
                         const ltriples_options* o, double* e_out, double* parts,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* Gradient outputs of ltriples_backward_rhf: caller-owned device FP64
+ * buffers in the layouts of the ltriples_rhf_domain inputs; a NULL field is
+ * not written.  dE/dtau is projected onto tau^{ab}_{ij} = tau^{ba}_{ji};
+ * dE/dBoo and dE/dBvv are symmetrised in their orbital indices. */
+typedef struct ltriples_rhf_grad {
+  double *t1, *tau, *Boo, *Bov, *Bvv, *eo, *ev, *fov;
+} ltriples_rhf_grad;
+
+/* Host-only: workspace bytes of ltriples_backward_rhf. */
+int ltriples_backward_rhf_workspace_size(const ltriples_rhf_domain* d, int32_t precision,
+                                         const ltriples_options* o, size_t* bytes);
+
+/* Adjoint of ltriples_energy_rhf: gbar * dE/dx for every closed-shell
+ * input.  The spin-block adjoint runs on the aliased alpha/beta data over
+ * the aaa and aab items with 2 gbar; the alpha and beta gradients of each
+ * shared input are added, and dE/dtau collects the mixed-spin gradient
+ * (symmetrised) and twice the same-spin ones (tau enters the same-spin
+ * amplitudes as tau^{ab}_{ij} - tau^{ba}_{ij}).  Precision LT_FP64 or
+ * LT_FP32; options as ltriples_energy_rhf; errors as ltriples_backward. */
+int ltriples_backward_rhf(const ltriples_rhf_domain* d, int32_t precision,
+                          const ltriples_options* o, const double* gbar,
+                          const ltriples_rhf_grad* grad, void* ws, size_t ws_bytes,
+                          void* stream);
+
 /* Three-index integrals of one LIS for the natural-auxiliary-function step
  * (section "Natural auxiliary functions", eq. naf_w): J_s[X][p][q] for each
  * spin over all nx auxiliary functions and all n_s = no_s + nv_s orbitals of

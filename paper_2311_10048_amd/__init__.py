@@ -68,6 +68,10 @@ class RhfDomain(ctypes.Structure):
                 + [(n, ctypes.c_void_p) for n in RHF_FIELDS])
 
 
+class RhfGrad(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in RHF_FIELDS]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_double),
                 ("setup_ms", ctypes.c_double),
@@ -141,6 +145,9 @@ def load_library(path: Optional[str] = None):
     lib.ltriples_rhf_flops.argtypes = [Rp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.ltriples_energy_rhf.argtypes = [Rp, ctypes.c_int32, Op, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.ltriples_backward_rhf_workspace_size.argtypes = [Rp, ctypes.c_int32, Op, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ltriples_backward_rhf.argtypes = [Rp, ctypes.c_int32, Op, ctypes.c_void_p, ctypes.POINTER(RhfGrad),
+                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     Np = ctypes.POINTER(NafInput)
     lib.ltriples_naf_workspace_size.argtypes = [Np, ctypes.POINTER(ctypes.c_size_t)]
     lib.ltriples_naf.argtypes = [Np, ctypes.c_double, ctypes.POINTER(NafOutput), ctypes.POINTER(ctypes.c_int32),
@@ -151,6 +158,7 @@ def load_library(path: Optional[str] = None):
               "ltriples_workspace_size_batched", "ltriples_energy_batched", "ltriples_graph_reset",
               "ltriples_backward_workspace_size", "ltriples_backward", "ltriples_plan_check",
               "ltriples_rhf_workspace_size", "ltriples_rhf_flops", "ltriples_energy_rhf",
+              "ltriples_backward_rhf_workspace_size", "ltriples_backward_rhf",
               "ltriples_naf_workspace_size", "ltriples_naf"):
         getattr(lib, f).restype = ctypes.c_int
     if path is None:
@@ -334,6 +342,41 @@ def ltriples_energy_rhf(tensors: Mapping[str, object], dims, precision: int = LT
                                    parts.data_ptr(), workspace.data_ptr(), workspace.numel(), st.cuda_stream))
     del keep
     return e, parts
+
+
+def ltriples_backward_rhf(tensors: Mapping[str, object], dims, precision: int = LT_FP64, gbar=None,
+                          batch_budget: int = 0, batch_items: int = 0, workspace=None, out=None, stream=None,
+                          build_chunk_mib: int = 0):
+    """gbar * dE/dx of the closed-shell energy for x in RHF_FIELDS (dE/dtau
+    projected onto its symmetry, dE/dBoo and dE/dBvv symmetrised).  Returns
+    a dict of float64 device tensors; `out` may supply them (missing keys
+    are not computed)."""
+    import torch
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    dom = make_rhf_domain(dims, tensors)
+    opts, keep = make_options(None, None, batch_budget, batch_items, None, build_chunk_mib)
+    dev = next(t for t in tensors.values() if hasattr(t, "device")).device
+    if gbar is None:
+        gbar = torch.ones(1, dtype=torch.float64, device=dev)
+    if gbar.dtype != torch.float64 or gbar.numel() != 1 or not gbar.is_contiguous():
+        raise ValueError("gbar must be one contiguous float64 element")
+    if out is None:
+        out = {k: torch.empty_like(tensors[k]) for k in RHF_FIELDS}
+    g = RhfGrad()
+    for k in RHF_FIELDS:
+        setattr(g, k, _ptr(out.get(k)))
+    lib = load_library()
+    n = ctypes.c_size_t(0)
+    _check(lib.ltriples_backward_rhf_workspace_size(ctypes.byref(dom), int(precision), ctypes.byref(opts),
+                                                    ctypes.byref(n)))
+    if workspace is None:
+        workspace = torch.empty(max(n.value, 1), dtype=torch.uint8, device=dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    _check(lib.ltriples_backward_rhf(ctypes.byref(dom), int(precision), ctypes.byref(opts), gbar.data_ptr(),
+                                     ctypes.byref(g), workspace.data_ptr(), workspace.numel(), st.cuda_stream))
+    del keep
+    return out
 
 
 def make_naf_input(dims, Ja=None, Jb=None) -> NafInput:

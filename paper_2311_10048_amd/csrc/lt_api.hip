@@ -2320,6 +2320,140 @@ int ltriples_energy_rhf(const ltriples_rhf_domain* rd, int32_t precision, const 
 
 }  // extern "C"
 
+namespace {
+
+// Workspace of the closed-shell adjoint after the forward head: 2 gbar, then
+// the beta-side and amplitude gradients of the spin-block adjoint.
+struct RhfBwd {
+  size_t g2, t1b, t2ab, t2aa, t2bb, Boo, Bov, Bvv, eo, ev, fov, end;
+};
+
+RhfBwd rhf_bwd_layout(const ltriples_rhf_domain* r, size_t head) {
+  const size_t no = r->no, nv = r->nv, Q = r->naux;
+  RhfBwd L{};
+  size_t off = head;
+  auto take = [&](size_t n) { const size_t o = off; off = align256(off + 8 * std::max<size_t>(n, 1)); return o; };
+  L.g2 = take(1);
+  L.t1b = take(no * nv);
+  L.t2ab = take(no * no * nv * nv);
+  L.t2aa = take(no * no * nv * nv);
+  L.t2bb = take(no * no * nv * nv);
+  L.Boo = take(Q * no * no);
+  L.Bov = take(Q * no * nv);
+  L.Bvv = take(Q * nv * nv);
+  L.eo = take(no);
+  L.ev = take(nv);
+  L.fov = take(no * nv);
+  L.end = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ltriples_backward_rhf_workspace_size(const ltriples_rhf_domain* d, int32_t precision, const ltriples_options* o,
+                                         size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(LT_EINVAL, "bytes is NULL");
+  RhfSetup S;
+  int r = rhf_setup(d, o, S);
+  if (r) return r;
+  size_t inner = 0;
+  r = ltriples_backward_workspace_size(&S.d, precision, &S.o, &inner);
+  if (r) return r;
+  *bytes = rhf_bwd_layout(d, S.head).end + inner;
+  return LT_OK;
+}
+
+int ltriples_backward_rhf(const ltriples_rhf_domain* rd, int32_t precision, const ltriples_options* o,
+                          const double* gbar, const ltriples_rhf_grad* grad, void* ws, size_t ws_bytes,
+                          void* stream) {
+  g_err.clear();
+  RhfSetup S;
+  int r = rhf_setup(rd, o, S);
+  if (r) return r;
+  if (!gbar) return fail(LT_EINVAL, "gbar is NULL");
+  if (!grad) return fail(LT_EINVAL, "grad is NULL");
+  size_t inner = 0;
+  r = ltriples_backward_workspace_size(&S.d, precision, &S.o, &inner);
+  if (r) return r;
+  const RhfBwd Lb = rhf_bwd_layout(rd, S.head);
+  const size_t need = Lb.end + inner;
+  bool own = false;
+  if (ws == nullptr) {
+    HIPCHK(hipMalloc(&ws, need));
+    own = true;
+  } else if (ws_bytes < need) {
+    return fail(LT_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)ws;
+  auto D = [&](size_t off) { return (double*)(base + off); };
+  const int64_t no = rd->no, nv = rd->nv, Q = rd->naux;
+  double* t2 = D(0);
+  double* g2 = D(Lb.g2);
+  auto run = [&]() -> int {
+    // same-spin amplitudes tau^{ab}_{ij} - tau^{ba}_{ij}, and 2 gbar
+    HIPCHK(lt::launch_copy4d<double, double>(t2, no * nv * nv, nv * nv, nv, no, no, nv, nv, rd->tau, no * nv * nv,
+                                             nv * nv, nv, 1, rd->tau, no * nv * nv, nv * nv, 1, nv, st));
+    HIPCHK(lt::launch_zero(g2, 1, st));
+    {
+      const int64_t d1[4] = {1, 1, 1, 1}, z[4] = {0, 0, 0, 0};
+      HIPCHK(lt::launch_perm_acc<double>(g2, d1, z, gbar, z, 2.0, st));
+    }
+    S.d.t2aa = S.d.t2bb = t2;
+    ltriples_domain_grad gi{};
+    gi.t1a = grad->t1; gi.t1b = grad->t1 ? D(Lb.t1b) : nullptr;
+    const bool wt = grad->tau != nullptr;
+    gi.t2ab = wt ? D(Lb.t2ab) : nullptr; gi.t2aa = wt ? D(Lb.t2aa) : nullptr; gi.t2bb = wt ? D(Lb.t2bb) : nullptr;
+    gi.Boo_a = grad->Boo; gi.Boo_b = grad->Boo ? D(Lb.Boo) : nullptr;
+    gi.Bov_a = grad->Bov; gi.Bov_b = grad->Bov ? D(Lb.Bov) : nullptr;
+    gi.Bvv_a = grad->Bvv; gi.Bvv_b = grad->Bvv ? D(Lb.Bvv) : nullptr;
+    gi.eo_a = grad->eo; gi.eo_b = grad->eo ? D(Lb.eo) : nullptr;
+    gi.ev_a = grad->ev; gi.ev_b = grad->ev ? D(Lb.ev) : nullptr;
+    gi.fov_a = grad->fov; gi.fov_b = grad->fov ? D(Lb.fov) : nullptr;
+    int rr = ltriples_backward(&S.d, precision, &S.o, g2, &gi, base + Lb.end, need - Lb.end, stream);
+    if (rr) return rr;
+    // alpha + beta for every shared input (flat copies)
+    auto add_flat = [&](double* out, const double* in, int64_t n) -> int {
+      if (!out || n <= 0) return LT_OK;
+      const int64_t d1[4] = {1, 1, 1, n}, s1[4] = {0, 0, 0, 1};
+      HIPCHK(lt::launch_perm_acc<double>(out, d1, s1, in, s1, 1.0, st));
+      return LT_OK;
+    };
+    if ((rr = add_flat(grad->t1, gi.t1b, no * nv))) return rr;
+    if ((rr = add_flat(grad->Boo, gi.Boo_b, Q * no * no))) return rr;
+    if ((rr = add_flat(grad->Bov, gi.Bov_b, Q * no * nv))) return rr;
+    if ((rr = add_flat(grad->Bvv, gi.Bvv_b, Q * nv * nv))) return rr;
+    if ((rr = add_flat(grad->eo, gi.eo_b, no))) return rr;
+    if ((rr = add_flat(grad->ev, gi.ev_b, nv))) return rr;
+    if ((rr = add_flat(grad->fov, gi.fov_b, no * nv))) return rr;
+    if (wt && no > 0 && nv > 0) {
+      // dtau = (g_ab + g_ab^{ji,ba}) / 2 + 2 g_aa + 2 g_bb
+      HIPCHK(lt::launch_zero(grad->tau, no * no * nv * nv, st));
+      const int64_t dd[4] = {no, no, nv, nv}, sid[4] = {no * nv * nv, nv * nv, nv, 1};
+      const int64_t swp[4] = {nv * nv, no * nv * nv, 1, nv};
+      HIPCHK(lt::launch_perm_acc<double>(grad->tau, dd, sid, gi.t2ab, sid, 0.5, st));
+      HIPCHK(lt::launch_perm_acc<double>(grad->tau, dd, sid, gi.t2ab, swp, 0.5, st));
+      HIPCHK(lt::launch_perm_acc<double>(grad->tau, dd, sid, gi.t2aa, sid, 2.0, st));
+      HIPCHK(lt::launch_perm_acc<double>(grad->tau, dd, sid, gi.t2bb, sid, 2.0, st));
+    } else if (wt) {
+      HIPCHK(lt::launch_zero(grad->tau, no * no * nv * nv, st));
+    }
+    return LT_OK;
+  };
+  r = run();
+  if (own) {
+    hipError_t e1 = hipStreamSynchronize(st);
+    hipError_t e2 = hipFree(ws);
+    if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) return fail(LT_EHIP, "HIP error at workspace release");
+  }
+  return r;
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------------------
 // Natural auxiliary functions: pair-packed integrals -> W by GEMM (rocBLAS),
 // eigenvectors by syevd (rocSOLVER), kept vectors in decreasing order, the

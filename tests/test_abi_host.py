@@ -264,3 +264,16 @@ def test_naf_workspace_and_errors():
     assert lib.ltriples_naf(ctypes.byref(x), 1e-2, None, ctypes.byref(m), None, 0, None) == lt.LT_EINVAL
     assert lib.ltriples_naf(ctypes.byref(x), float("nan"), ctypes.byref(out), ctypes.byref(m), None, 0,
                             None) == lt.LT_EINVAL
+
+
+def test_rhf_backward_workspace_and_errors():
+    lib = _lib()
+    d = _fake_rhf((4, 10, 20))
+    n = ctypes.c_size_t()
+    assert lib.ltriples_backward_rhf_workspace_size(ctypes.byref(d), lt.LT_FP64, None, ctypes.byref(n)) == lt.LT_OK
+    assert n.value > 4 * 8 * 4 * 4 * 10 * 10
+    assert lib.ltriples_backward_rhf_workspace_size(ctypes.byref(d), lt.LT_BF16X3, None,
+                                                    ctypes.byref(n)) == lt.LT_EPREC
+    g = lt.RhfGrad()
+    assert lib.ltriples_backward_rhf(ctypes.byref(d), lt.LT_FP64, None, None, ctypes.byref(g), None, 0,
+                                     None) == lt.LT_EINVAL

@@ -99,3 +99,43 @@ def test_rhf_batching_and_chunks_bitwise():
     assert E0 == E1 and np.array_equal(p0, p1)
     E2, p2 = _gpu(dom, lt.LT_FP32, batch_items=2)
     assert abs(E2 - E0) <= 1e-12 * abs(E0)
+
+
+# ---- adjoint ------------------------------------------------------------------------------
+from oracle import grad as ograd  # noqa: E402
+
+GTOL = {lt.LT_FP64: 1e-10, lt.LT_FP32: 1e-5}
+
+
+@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32])
+@pytest.mark.parametrize("shape", [(3, 17, 30), (4, 21, 40), (2, 13, 20)])
+def test_rhf_backward_parity(shape, prec):
+    """Every closed-shell gradient against the oracle's reverse mode over
+    the closed-shell formula: max|dg| <= tol * max|g_ref| per input."""
+    import torch
+    dom = _dom(shape)
+    print(f"[rhf-bwd] {shape} prec={prec}", flush=True)
+    _, ref = ograd.rhf_energy_and_grad(synth.rhf_arrays(dom))
+    g = lt.ltriples_backward_rhf(_rhf_dev(dom), (dom.noa, dom.nva, dom.naux), prec)
+    torch.cuda.synchronize()
+    for k in lt.RHF_FIELDS:
+        r = ref[k]
+        if r.size == 0:
+            continue
+        err = float(np.max(np.abs(g[k].cpu().numpy() - r)))
+        assert err <= GTOL[prec] * max(float(np.max(np.abs(r))), 1e-300), (k, err, float(np.max(np.abs(r))))
+
+
+def test_rhf_backward_gbar_and_partial_outputs():
+    import torch
+    dom = _dom((3, 17, 30))
+    t = _rhf_dev(dom)
+    dims = (dom.noa, dom.nva, dom.naux)
+    g1 = lt.ltriples_backward_rhf(t, dims, lt.LT_FP64)
+    gb = torch.full((1,), -1.5, dtype=torch.float64, device="cuda")
+    only = {"tau": torch.empty_like(t["tau"]), "ev": torch.empty_like(t["ev"])}
+    g2 = lt.ltriples_backward_rhf(t, dims, lt.LT_FP64, gbar=gb, out=only)
+    torch.cuda.synchronize()
+    for k in ("tau", "ev"):
+        err = float((g2[k] + 1.5 * g1[k]).abs().max())
+        assert err <= 1e-13 * float(g1[k].abs().max()), (k, err)
