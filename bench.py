@@ -172,6 +172,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=3, help="items per block for the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: tile shapes of the contraction kernels tuned during the warmup step (results unchanged)")
     ap.add_argument("--sample-items", type=int, default=0, help="profiling aid: K sampled triplets per block")
     ap.add_argument("--prefix-items", type=int, default=0,
                     help="profiling aid: the first K triplets per block in the whole-domain order")
@@ -236,7 +238,7 @@ def main():
     def step():
         st = lt.Stats()
         e, parts = lt.ltriples_energy(tens, dom.dims, prec, items=step_items, e_items=e_items, workspace=ws,
-                                      stats=st)
+                                      stats=st, autotune=bool(args.autotune))
         return e, parts, st
 
     for w in range(args.warmup):
@@ -429,7 +431,7 @@ def run_batch(args, lt, synth, torch):
             ev1 = torch.cuda.Event(enable_timing=True)
             ev0.record()
             lt.ltriples_energy_batched([tens[n] for n in h], [dims[n] for n in h], prec, graph=graph,
-                                       workspace=ws, out=outs[k])
+                                       workspace=ws, out=outs[k], autotune=bool(args.autotune) and not graph)
             ev1.record()
             torch.cuda.synchronize()
             ms += ev0.elapsed_time(ev1)

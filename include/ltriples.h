@@ -127,7 +127,17 @@ typedef struct ltriples_options {
    * the staging and scratch parts of the workspace; results are bitwise
    * unchanged. */
   int32_t build_chunk_mib;
-  int32_t reserved[2];
+  /* 1 = tile-shape autotuning of the BF16 contraction kernels: the first
+   * launch of each shape class in the process (per device: products,
+   * output layout, 32-row blocks of output rows, log2 of the columns) times
+   * every candidate tile configuration on its own data and keeps the
+   * fastest for all later launches of the class, with or without this
+   * flag.  Every configuration sums each output element in the same order,
+   * so the choice changes no result bit.  Tuning waits for the stream; it
+   * is skipped under graph capture (the default or an earlier choice is
+   * used).  ltriples_autotune_reset() forgets the choices. */
+  int32_t autotune;
+  int32_t reserved;
 } ltriples_options;
 
 /* Host-only validation of sizes, pointers, precision and item list.  Makes
@@ -237,6 +247,9 @@ int ltriples_energy_batched(const ltriples_domain* ds, int32_t ndom,
 
 /* Drops every cached hipGraph of ltriples_energy_batched. */
 int ltriples_graph_reset(void);
+
+/* Forgets every tile configuration chosen by options.autotune. */
+int ltriples_autotune_reset(void);
 
 /* One closed-shell (SOMO-free) domain in spatial orbitals, for the domains
  * whose orbital sets become spin independent once the domain Fock matrix is

@@ -95,7 +95,8 @@ class Options(ctypes.Structure):
                 ("stats", ctypes.POINTER(Stats)),
                 ("graph", ctypes.c_int32),
                 ("build_chunk_mib", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("autotune", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 GRAD_FIELDS = ("t1a", "t1b", "t2aa", "t2bb", "t2ab", "Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b")
@@ -135,6 +136,7 @@ def load_library(path: Optional[str] = None):
     lib.ltriples_energy_batched.argtypes = [Dp, ctypes.c_int32, ctypes.c_int32, Op, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.ltriples_graph_reset.argtypes = []
+    lib.ltriples_autotune_reset.argtypes = []
     lib.ltriples_plan_check.argtypes = [Dp, ctypes.c_int32, Op, ctypes.c_int32]
     Gp = ctypes.POINTER(DomainGrad)
     lib.ltriples_backward_workspace_size.argtypes = [Dp, ctypes.c_int32, Op, ctypes.POINTER(ctypes.c_size_t)]
@@ -159,7 +161,7 @@ def load_library(path: Optional[str] = None):
               "ltriples_backward_workspace_size", "ltriples_backward", "ltriples_plan_check",
               "ltriples_rhf_workspace_size", "ltriples_rhf_flops", "ltriples_energy_rhf",
               "ltriples_backward_rhf_workspace_size", "ltriples_backward_rhf",
-              "ltriples_naf_workspace_size", "ltriples_naf"):
+              "ltriples_naf_workspace_size", "ltriples_naf", "ltriples_autotune_reset"):
         getattr(lib, f).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -207,13 +209,14 @@ def make_domain(dims, tensors: Optional[Mapping[str, object]] = None) -> Domain:
 
 
 def make_options(items=None, e_items=None, batch_budget: int = 0, batch_items: int = 0,
-                 stats: Optional[Stats] = None, build_chunk_mib: int = 0):
+                 stats: Optional[Stats] = None, build_chunk_mib: int = 0, autotune: bool = False):
     """ltriples_options; `items` is a host int32 array [n][4] (kept alive by
     the returned tuple's second element)."""
     o = Options()
     o.batch_budget = int(batch_budget)
     o.batch_items = int(batch_items)
     o.build_chunk_mib = int(build_chunk_mib)
+    o.autotune = 1 if autotune else 0
     if stats is not None:
         o.stats = ctypes.pointer(stats)
     keep = None
@@ -252,7 +255,8 @@ def ltriples_flops(dom: Domain, options: Optional[Options] = None):
 
 def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP32, items=None,
                     e_items=None, batch_budget: int = 0, batch_items: int = 0, workspace=None,
-                    stream=None, stats: Optional[Stats] = None, build_chunk_mib: int = 0):
+                    stream=None, stats: Optional[Stats] = None, build_chunk_mib: int = 0,
+                    autotune: bool = False):
     """E(T) of one domain on the current HIP device.
 
     Returns (e, parts): a float64 device tensor of shape [1] and one of shape
@@ -267,7 +271,7 @@ def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP3
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     dom = make_domain(dims, tensors)
-    opts, keep = make_options(items, e_items, batch_budget, batch_items, stats, build_chunk_mib)
+    opts, keep = make_options(items, e_items, batch_budget, batch_items, stats, build_chunk_mib, autotune)
     dev = next(t for t in tensors.values() if hasattr(t, "device")).device
     need = ltriples_workspace_size(dom, precision, opts)
     if workspace is None:
@@ -447,7 +451,7 @@ def ltriples_workspace_size_batched(dims_list, tensors_list, precision: int, opt
 
 def ltriples_energy_batched(tensors_list, dims_list, precision: int = LT_FP32, graph: bool = False,
                             batch_budget: int = 0, batch_items: int = 0, workspace=None, out=None,
-                            stream=None, build_chunk_mib: int = 0):
+                            stream=None, build_chunk_mib: int = 0, autotune: bool = False):
     """E(T) of several domains in one call.  Returns (e [ndom], parts [ndom,4,3]).
     With graph=True the launch sequence is captured into a hipGraph on the
     first call and replayed on later calls with the same shapes, pointers,
@@ -456,7 +460,8 @@ def ltriples_energy_batched(tensors_list, dims_list, precision: int = LT_FP32, g
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     ndom = len(dims_list)
-    opts, _ = make_options(batch_budget=batch_budget, batch_items=batch_items, build_chunk_mib=build_chunk_mib)
+    opts, _ = make_options(batch_budget=batch_budget, batch_items=batch_items, build_chunk_mib=build_chunk_mib,
+                           autotune=autotune)
     opts.graph = 1 if graph else 0
     arr = _domain_array(dims_list, tensors_list)
     dev = next(t for t in tensors_list[0].values() if hasattr(t, "device")).device
@@ -474,6 +479,10 @@ def ltriples_energy_batched(tensors_list, dims_list, precision: int = LT_FP32, g
                                        parts.data_ptr(), workspace.data_ptr(), workspace.numel(),
                                        st.cuda_stream))
     return e, parts
+
+
+def ltriples_autotune_reset():
+    _check(load_library().ltriples_autotune_reset())
 
 
 def ltriples_graph_reset():

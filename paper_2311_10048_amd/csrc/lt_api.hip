@@ -869,7 +869,7 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
       h.kind = g.ops.kind;
       const int64_t first_item = (g.ops.items - d_trip) / 3;     // index in the block-ordered item list
       h.tab = (g.ops.kind == 2 ? tab1 : tab0) + 6 * first_item;
-      return lt::launch_gemm_bf16(h, st);
+      return lt::launch_gemm_bf16(h, st, o && o->autotune);
     };
     const int64_t nb = P.nb[b];
     T* out1 = (T*)scr;
@@ -2627,6 +2627,12 @@ done:
     if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) r = fail(LT_EHIP, "HIP error at workspace release");
   }
   return r;
+}
+
+int ltriples_autotune_reset(void) {
+  g_err.clear();
+  lt::reset_gemm_bf16_tuning();
+  return LT_OK;
 }
 
 const char* ltriples_last_error(void) { return g_err.c_str(); }

@@ -10,6 +10,12 @@
 // MBW x NBW 32x32 blocks, the whole virtual range of the contraction in one
 // work-group tile, K advancing by 16 (two octets) per double-buffered LDS
 // stage; every global load is one 16-byte octet.
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <vector>
+
 #include "lt_internal.h"
 
 namespace lt {
@@ -295,22 +301,116 @@ static hipError_t launch16(GemmArgs16 g, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int NPROD>
-static hipError_t dispatch16(const GemmArgs16& g, hipStream_t s) {
-  const int need = (g.M + 31) / 32;
-  if (need <= 1) return launch16<1, 1, 1, NPROD>(g, s);
-  if (need <= 2) return launch16<2, 1, 1, NPROD>(g, s);
-  if (need <= 3) return launch16<3, 1, 1, NPROD>(g, s);
-  if (need <= 4) return launch16<2, 2, 2, NPROD>(g, s);
-  if (need <= 6) return launch16<3, 2, 2, NPROD>(g, s);
-  if (need <= 8) return launch16<4, 2, 2, NPROD>(g, s);
-  if (need <= 10) return launch16<5, 2, 2, NPROD>(g, s);
-  if (need <= 12) return launch16<6, 2, 2, NPROD>(g, s);
-  return launch16<4, 2, 2, NPROD>(g, s);   // several row tiles
+// ---------------------------------------------------------------------------
+// Tile configurations and their selection.  Every configuration sums each
+// output element over the same segments, k stages and products in the same
+// order, so the choice changes no result bit, only the time.
+// ---------------------------------------------------------------------------
+namespace {
+
+typedef hipError_t (*Fn16)(GemmArgs16, hipStream_t);
+struct Cfg16 {
+  int mbw, nbw, wm;
+  Fn16 f1, f3;   // one product (plain BF16), three products (BF16x3)
+};
+const Cfg16 kCfg16[] = {
+    {1, 1, 1, launch16<1, 1, 1, 1>, launch16<1, 1, 1, 3>}, {2, 1, 1, launch16<2, 1, 1, 1>, launch16<2, 1, 1, 3>},
+    {3, 1, 1, launch16<3, 1, 1, 1>, launch16<3, 1, 1, 3>}, {2, 2, 2, launch16<2, 2, 2, 1>, launch16<2, 2, 2, 3>},
+    {3, 2, 2, launch16<3, 2, 2, 1>, launch16<3, 2, 2, 3>}, {4, 2, 2, launch16<4, 2, 2, 1>, launch16<4, 2, 2, 3>},
+    {5, 2, 2, launch16<5, 2, 2, 1>, launch16<5, 2, 2, 3>}, {6, 2, 2, launch16<6, 2, 2, 1>, launch16<6, 2, 2, 3>}};
+constexpr int kNCfg = (int)(sizeof(kCfg16) / sizeof(kCfg16[0]));
+
+int cfg_rows(int c) { return kCfg16[c].wm * kCfg16[c].mbw * 32; }
+
+// The measured default for `need` 32-row blocks of output rows.
+int default_cfg(int need) {
+  if (need <= 1) return 0;
+  if (need <= 2) return 1;
+  if (need <= 3) return 2;
+  if (need <= 4) return 3;
+  if (need <= 6) return 4;
+  if (need <= 8) return 5;
+  if (need <= 10) return 6;
+  if (need <= 12) return 7;
+  return 5;   // several row tiles
 }
 
-hipError_t launch_gemm_bf16(const GemmArgs16& g, hipStream_t s) {
-  return g.nprod == 3 ? dispatch16<3>(g, s) : dispatch16<1>(g, s);
+// Candidates: the default first, then every configuration whose row tiles
+// pad the rows by at most a quarter.
+std::vector<int> candidates(int need) {
+  std::vector<int> c{default_cfg(need)};
+  const int rows = need * 32;
+  for (int i = 0; i < kNCfg; ++i) {
+    if (i == c[0]) continue;
+    const int br = cfg_rows(i), padded = (rows + br - 1) / br * br;
+    if (4 * padded <= 5 * rows) c.push_back(i);
+  }
+  return c;
+}
+
+struct TuneKey {
+  int dev, nprod, kind, need, nlog;
+  bool operator<(const TuneKey& o) const {
+    if (dev != o.dev) return dev < o.dev;
+    if (nprod != o.nprod) return nprod < o.nprod;
+    if (kind != o.kind) return kind < o.kind;
+    if (need != o.need) return need < o.need;
+    return nlog < o.nlog;
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;
+
+hipError_t run_cfg(int c, const GemmArgs16& g, hipStream_t s) {
+  return g.nprod == 3 ? kCfg16[c].f3(g, s) : kCfg16[c].f1(g, s);
+}
+
+}  // namespace
+
+hipError_t launch_gemm_bf16(const GemmArgs16& g, hipStream_t s, bool tune) {
+  const int need = (g.M + 31) / 32;
+  int nlog = 0;
+  while ((1 << (nlog + 1)) <= g.N) ++nlog;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const TuneKey key{dev, g.nprod, g.kind, need, nlog};
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(key);
+  if (it != g_tuned.end()) return run_cfg(it->second, g, s);
+  const std::vector<int> cand = candidates(need);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (!tune || cand.size() < 2 || hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return run_cfg(cand[0], g, s);
+  // time every candidate on this launch's own data (each run rewrites the
+  // same output with the same bits): one warm run, one timed run
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  int best = cand[0];
+  float best_ms = 0.f;
+  for (size_t i = 0; i < cand.size() && err == hipSuccess; ++i) {
+    err = run_cfg(cand[i], g, s);
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    if (err == hipSuccess) err = run_cfg(cand[i], g, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess && (i == 0 || ms < best_ms)) { best_ms = ms; best = cand[i]; }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return err;
+  g_tuned[key] = best;
+  if (getenv("LTRIPLES_LOG"))
+    fprintf(stderr, "[ltriples] tuned BF16 contraction (kind %d, M %d, N %d, %d products): tile %dx%d rows %d\n",
+            g.kind, g.M, g.N, g.nprod, kCfg16[best].mbw, kCfg16[best].nbw, cfg_rows(best));
+  return hipSuccess;   // the last candidate's run left the (identical) result in place
+}
+
+void reset_gemm_bf16_tuning() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned.clear();
 }
 
 }  // namespace lt

@@ -135,7 +135,13 @@ struct GemmArgs16 {
   const Seg8* tab;                       // [nbatch][6] segment descriptors of the launch's items
 };
 
-hipError_t launch_gemm_bf16(const GemmArgs16& g, hipStream_t s);
+// `tune`: on the first launch of a shape class (device, products, output
+// kind, 32-row blocks, log2 N) time every candidate tile configuration on
+// this launch and keep the fastest for the class (not under graph capture;
+// waits for the stream).  Without it the class keeps a tuned choice if one
+// exists, else the default table.
+hipError_t launch_gemm_bf16(const GemmArgs16& g, hipStream_t s, bool tune = false);
+void reset_gemm_bf16_tuning();
 // tab[n][s] = descriptor of segment s of item n (ops.kind, ops.items), s < 6;
 // unused slots get K = 0.
 hipError_t launch_seg8_table(const ItemOps8& ops, int32_t nitems, Seg8* tab, hipStream_t s);

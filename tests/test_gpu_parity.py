@@ -10,7 +10,7 @@ import pytest
 import paper_2311_10048_amd as lt
 import synth
 from oracle import blocks
-from tests.gpu_util import gpu_energy, rel
+from tests.gpu_util import gpu_energy, rel, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -137,3 +137,26 @@ def test_plain_bf16_ablation_runs():
     E, parts, _ = gpu_energy(dom, lt.LT_BF16)
     assert np.isfinite(E)
     assert abs(E - ref["E"]) / abs(ref["E"]) < 1e-3
+
+
+@pytest.mark.parametrize("name", ["ragged", "wide", "tall"])
+def test_autotune_changes_no_bit(name):
+    """Tile-shape tuning picks among configurations that sum every output in
+    the same order: the energies, parts and per-item values are bitwise
+    those of the default configurations, on the tuning call and after it."""
+    import torch
+    dom = synth.make_domain(*SHAPES[name], seed=synth.BASE_SEED + 17)
+    t = to_device(dom)
+    items = synth.sample_items(dom.noa, dom.nob, 3, seed=5)
+    lt.ltriples_autotune_reset()
+    outs = []
+    for tune in (False, True, False):
+        ei = torch.zeros(len(items), 3, dtype=torch.float64, device="cuda")
+        e, p = lt.ltriples_energy(t, dom.dims, lt.LT_BF16X3, autotune=tune)
+        lt.ltriples_energy(t, dom.dims, lt.LT_BF16X3, items=items, e_items=ei, autotune=tune)
+        torch.cuda.synchronize()
+        outs.append((e.cpu().numpy(), p.cpu().numpy(), ei.cpu().numpy()))
+    lt.ltriples_autotune_reset()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
