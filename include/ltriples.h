@@ -127,9 +127,10 @@ typedef struct ltriples_options {
    * the staging and scratch parts of the workspace; results are bitwise
    * unchanged. */
   int32_t build_chunk_mib;
-  /* 1 = tile-shape autotuning of the BF16 contraction kernels: the first
-   * launch of each shape class in the process (per device: products,
-   * output layout, 32-row blocks of output rows, log2 of the columns) times
+  /* 1 = tile-shape autotuning of the triplet contraction kernels: the first
+   * launch of each shape class in the process (per device: precision or
+   * number of BF16 products, output layout, 32-row blocks of output rows,
+   * log2 of the columns) times
    * every candidate tile configuration on its own data and keeps the
    * fastest for all later launches of the class, with or without this
    * flag.  Every configuration sums each output element in the same order,

@@ -862,7 +862,7 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
     }
     // contraction of one batch: FP64/FP32 matrix cores, or split BF16
     auto contract = [&](lt::GemmArgs<T>& g) -> hipError_t {
-      if (!P.bf) return lt::launch_gemm<T>(g, st);
+      if (!P.bf) return lt::launch_gemm<T>(g, st, o && o->autotune);
       lt::GemmArgs16 h{};
       h.M = g.M; h.N = g.N; h.nbatch = g.nbatch; h.nprod = P.bf;
       h.out = (float*)g.out; h.obs = g.obs; h.ldo = g.s_mr;
@@ -2632,6 +2632,7 @@ done:
 int ltriples_autotune_reset(void) {
   g_err.clear();
   lt::reset_gemm_bf16_tuning();
+  lt::reset_gemm_tuning();
   return LT_OK;
 }
 

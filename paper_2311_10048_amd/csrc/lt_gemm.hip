@@ -16,6 +16,10 @@
 // consecutive logical tiles run on the same XCD (the dispatcher deals
 // work-groups round-robin over the 8 XCDs), which keeps a triplet's small
 // L operand and an R-operand tile shared by the row tiles in one L2.
+#include <map>
+#include <mutex>
+#include <vector>
+
 #include "lt_internal.h"
 
 namespace lt {
@@ -239,31 +243,117 @@ hipError_t launch_cfg(GemmArgs<T> g, hipStream_t s) {
 // Tile choice (measured on gfx950 at the triplet-contraction shapes): the
 // whole M range in one work-group tile when it fits, 2 x 2 waves for
 // M > 96; FP64 with K chunks of 8.  Large-M integral builds use 128-row tiles.
-template <> hipError_t launch_gemm<float>(const GemmArgs<float>& g, hipStream_t s) {
-  const int need = (g.M + 31) / 32;
-  if (need <= 1) return launch_cfg<float, 1, 1, 1, 16>(g, s);
-  if (need <= 2) return launch_cfg<float, 2, 1, 1, 16>(g, s);
-  if (need <= 3) return launch_cfg<float, 3, 1, 1, 16>(g, s);
-  if (need <= 4) return launch_cfg<float, 2, 2, 2, 16>(g, s);
-  if (need <= 6) return launch_cfg<float, 3, 2, 2, 16>(g, s);
-  if (need <= 8) return launch_cfg<float, 4, 2, 2, 16>(g, s);
-  if (need <= 10) return launch_cfg<float, 5, 2, 2, 16>(g, s);
-  if (need <= 12) return launch_cfg<float, 6, 2, 2, 16>(g, s);
-  if (need <= 16) return launch_cfg<float, 4, 2, 2, 16>(g, s);   // two row tiles
-  return launch_cfg<float, 2, 2, 2, 16>(g, s);
+// With tuning, the triplet contractions (mode 1) of each shape class may
+// take another configuration from the candidates below; every configuration
+// sums each output element in the same order, so results do not change.
+namespace {
+
+template <typename T> struct GCfg { int rows; hipError_t (*fn)(GemmArgs<T>, hipStream_t); };
+const GCfg<float> kCfg32[] = {
+    {32, launch_cfg<float, 1, 1, 1, 16>},  {64, launch_cfg<float, 2, 1, 1, 16>},
+    {96, launch_cfg<float, 3, 1, 1, 16>},  {128, launch_cfg<float, 2, 2, 2, 16>},
+    {192, launch_cfg<float, 3, 2, 2, 16>}, {256, launch_cfg<float, 4, 2, 2, 16>},
+    {320, launch_cfg<float, 5, 2, 2, 16>}, {384, launch_cfg<float, 6, 2, 2, 16>}};
+const GCfg<double> kCfg64[] = {
+    {32, launch_cfg<double, 2, 1, 1, 8>},   {64, launch_cfg<double, 4, 1, 1, 8>},
+    {128, launch_cfg<double, 4, 2, 2, 8>},  {192, launch_cfg<double, 6, 2, 2, 8>},
+    {256, launch_cfg<double, 8, 2, 2, 8>},  {320, launch_cfg<double, 10, 2, 2, 8>},
+    {384, launch_cfg<double, 12, 2, 2, 8>}, {512, launch_cfg<double, 16, 2, 2, 8>}};
+
+int default32(int M) {
+  const int need = (M + 31) / 32;
+  if (need <= 1) return 0;
+  if (need <= 2) return 1;
+  if (need <= 3) return 2;
+  if (need <= 4) return 3;
+  if (need <= 6) return 4;
+  if (need <= 8) return 5;
+  if (need <= 10) return 6;
+  if (need <= 12) return 7;
+  if (need <= 16) return 5;   // two row tiles
+  return 3;
+}
+int default64(int M) {
+  const int need = (M + 15) / 16;
+  if (need <= 2) return 0;
+  if (need <= 4) return 1;
+  if (need <= 8) return 2;
+  if (need <= 12) return 3;
+  if (need <= 16) return 4;
+  if (need <= 20) return 5;
+  if (need <= 24) return 6;
+  if (need <= 32) return 7;
+  return 2;
 }
 
-template <> hipError_t launch_gemm<double>(const GemmArgs<double>& g, hipStream_t s) {
-  const int need = (g.M + 15) / 16;
-  if (need <= 2) return launch_cfg<double, 2, 1, 1, 8>(g, s);
-  if (need <= 4) return launch_cfg<double, 4, 1, 1, 8>(g, s);
-  if (need <= 8) return launch_cfg<double, 4, 2, 2, 8>(g, s);
-  if (need <= 12) return launch_cfg<double, 6, 2, 2, 8>(g, s);
-  if (need <= 16) return launch_cfg<double, 8, 2, 2, 8>(g, s);
-  if (need <= 20) return launch_cfg<double, 10, 2, 2, 8>(g, s);
-  if (need <= 24) return launch_cfg<double, 12, 2, 2, 8>(g, s);
-  if (need <= 32) return launch_cfg<double, 16, 2, 2, 8>(g, s);
-  return launch_cfg<double, 4, 2, 2, 8>(g, s);
+struct GKey {
+  int dev, bytes, kind, rows32, nlog;
+  bool operator<(const GKey& o) const {
+    if (dev != o.dev) return dev < o.dev;
+    if (bytes != o.bytes) return bytes < o.bytes;
+    if (kind != o.kind) return kind < o.kind;
+    if (rows32 != o.rows32) return rows32 < o.rows32;
+    return nlog < o.nlog;
+  }
+};
+std::mutex g_mu;
+std::map<GKey, int> g_pick;
+
+template <typename T, int NC>
+hipError_t dispatch(const GCfg<T> (&cfg)[NC], int def, const GemmArgs<T>& g, hipStream_t s, bool tune) {
+  if (g.mode != 1) return cfg[def].fn(g, s);
+  int nlog = 0;
+  while ((1 << (nlog + 1)) <= g.N) ++nlog;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const GKey key{dev, (int)sizeof(T), g.ops.kind, (g.M + 31) / 32, nlog};
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_pick.find(key);
+  if (it != g_pick.end()) return cfg[it->second].fn(g, s);
+  // candidates: the default, then every tile whose row padding stays within a quarter
+  std::vector<int> cand{def};
+  for (int i = 0; i < NC; ++i) {
+    const int padded = (g.M + cfg[i].rows - 1) / cfg[i].rows * cfg[i].rows;
+    if (i != def && 4 * padded <= 5 * g.M) cand.push_back(i);
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (!tune || cand.size() < 2 || hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return cfg[def].fn(g, s);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  int best = def;
+  float best_ms = 0.f;
+  for (size_t i = 0; i < cand.size() && err == hipSuccess; ++i) {
+    err = cfg[cand[i]].fn(g, s);                      // warm run (same output bits)
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    if (err == hipSuccess) err = cfg[cand[i]].fn(g, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess && (i == 0 || ms < best_ms)) { best_ms = ms; best = cand[i]; }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return err;
+  g_pick[key] = best;
+  return hipSuccess;
+}
+
+}  // namespace
+
+template <> hipError_t launch_gemm<float>(const GemmArgs<float>& g, hipStream_t s, bool tune) {
+  return dispatch(kCfg32, default32(g.M), g, s, tune);
+}
+
+template <> hipError_t launch_gemm<double>(const GemmArgs<double>& g, hipStream_t s, bool tune) {
+  return dispatch(kCfg64, default64(g.M), g, s, tune);
+}
+
+void reset_gemm_tuning() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_pick.clear();
 }
 #endif
 

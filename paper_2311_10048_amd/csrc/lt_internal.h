@@ -185,7 +185,9 @@ template <typename T> struct EpiMixed {
 // ---------------------------------------------------------------------------
 // Launchers (all asynchronous on `s`)
 // ---------------------------------------------------------------------------
-template <typename T> hipError_t launch_gemm(const GemmArgs<T>& g, hipStream_t s);
+// `tune`: as launch_gemm_bf16, for the triplet contractions (mode 1).
+template <typename T> hipError_t launch_gemm(const GemmArgs<T>& g, hipStream_t s, bool tune = false);
+void reset_gemm_tuning();
 
 // out[d0][d1][d2][d3] (out strides os0..os2, unit stride in d3)
 //   = in[d0*s0 + d1*s1 + d2*s2 + d3*s3] - (in2 ? in2[d0*u0 + ... + d3*u3] : 0)

@@ -139,8 +139,9 @@ def test_plain_bf16_ablation_runs():
     assert abs(E - ref["E"]) / abs(ref["E"]) < 1e-3
 
 
+@pytest.mark.parametrize("prec", [lt.LT_BF16X3, lt.LT_FP32, lt.LT_FP64])
 @pytest.mark.parametrize("name", ["ragged", "wide", "tall"])
-def test_autotune_changes_no_bit(name):
+def test_autotune_changes_no_bit(name, prec):
     """Tile-shape tuning picks among configurations that sum every output in
     the same order: the energies, parts and per-item values are bitwise
     those of the default configurations, on the tuning call and after it."""
@@ -152,8 +153,8 @@ def test_autotune_changes_no_bit(name):
     outs = []
     for tune in (False, True, False):
         ei = torch.zeros(len(items), 3, dtype=torch.float64, device="cuda")
-        e, p = lt.ltriples_energy(t, dom.dims, lt.LT_BF16X3, autotune=tune)
-        lt.ltriples_energy(t, dom.dims, lt.LT_BF16X3, items=items, e_items=ei, autotune=tune)
+        e, p = lt.ltriples_energy(t, dom.dims, prec, autotune=tune)
+        lt.ltriples_energy(t, dom.dims, prec, items=items, e_items=ei, autotune=tune)
         torch.cuda.synchronize()
         outs.append((e.cpu().numpy(), p.cpu().numpy(), ei.cpu().numpy()))
     lt.ltriples_autotune_reset()
