@@ -234,3 +234,57 @@ def test_autograd_function_matches_backward():
         assert torch.equal(leaves[k].grad, g[k]), k
     e_ref, _ = lt.ltriples_energy(t, dom.dims, lt.LT_FP64)
     assert float(E.detach()) == float(e_ref.item())
+
+
+def test_backward_tall_shape_identities():
+    """v > 384 (several row tiles in every reverse GEMM and contraction):
+    <dE/dT, d> equals the exact central difference of the FP64 GPU energy
+    (E is quadratic in T1, T2), the f_ov gradient the exact difference along
+    f_ov (E is linear in it), the orbital-energy gradient satisfies the shift
+    and homogeneity identities, and FP32 agrees with FP64 to 1e-5."""
+    import torch
+    dom = _dom((3, 1, 400, 401, 48))
+    print(f"[backward] tall {dom.dims}", flush=True)
+    t = to_device(dom)
+    g64 = lt.ltriples_backward(t, dom.dims, lt.LT_FP64)
+    g32 = lt.ltriples_backward(t, dom.dims, lt.LT_FP32)
+    e0, _ = lt.ltriples_energy(t, dom.dims, lt.LT_FP64)
+    torch.cuda.synchronize()
+    E0 = float(e0.item())
+    for k in ALL_GRAD:
+        a, b = g64[k], g32[k]
+        if a.numel():
+            assert float((a - b).abs().max()) <= 1e-5 * float(a.abs().max()), k
+    rng = np.random.default_rng(9)
+
+    def fd(dirs, h):
+        tp = dict(t); tm = dict(t)
+        for k, d in dirs.items():
+            tp[k] = t[k] + h * d
+            tm[k] = t[k] - h * d
+        ep, _ = lt.ltriples_energy(tp, dom.dims, lt.LT_FP64)
+        em, _ = lt.ltriples_energy(tm, dom.dims, lt.LT_FP64)
+        torch.cuda.synchronize()
+        return (float(ep.item()) - float(em.item())) / (2 * h)
+    dirs = {}
+    for k in ("t1a", "t1b", "t2aa", "t2ab"):
+        x = getattr(dom, k)
+        d = rng.normal(0.0, 1.0, size=x.shape) * np.std(x)
+        if k == "t2aa":
+            d = d - d.transpose(1, 0, 2, 3)
+            d = d - d.transpose(0, 1, 3, 2)
+        dirs[k] = torch.from_numpy(d).cuda()
+    an = sum(float((g64[k] * d).sum()) for k, d in dirs.items())
+    num = fd(dirs, 0.25)
+    assert abs(an - num) <= 1e-9 * max(abs(num), 1e-12 * abs(E0)), (an, num)
+    fdirs = {k: torch.from_numpy(rng.normal(0.0, 1.0, size=getattr(dom, k).shape)).cuda()
+             for k in ("fov_a", "fov_b")}
+    an = sum(float((g64[k] * d).sum()) for k, d in fdirs.items())
+    num = fd(fdirs, 1.0)
+    assert abs(an - num) <= 1e-9 * max(abs(num), 1e-12 * abs(E0)), ("fov", an, num)
+    eps = ("eo_a", "ev_a", "eo_b", "ev_b")
+    tot = sum(float(g64[k].sum()) for k in eps)
+    mag = sum(float(g64[k].abs().sum()) for k in eps)
+    assert abs(tot) <= 1e-10 * mag, (tot, mag)
+    euler = sum(float((t[k] * g64[k]).sum()) for k in eps)
+    assert abs(euler + E0) <= 1e-10 * abs(E0), (euler, E0)
