@@ -105,3 +105,21 @@ def test_naf_empty_auxiliary_basis():
     Ja = torch.zeros((0, 5, 5), dtype=torch.float64, device="cuda")
     m, out = lt.ltriples_naf(Ja, Ja, (2, 3, 2, 3, 0), 1e-2)
     assert m == 0
+
+
+def test_naf_rank_deficient_metric():
+    """More auxiliary functions than orbital pairs: W has rank at most the
+    number of pairs of both spins, the rest of its spectrum is rounding
+    noise; a threshold between the two keeps exactly the oracle's count, and
+    the kept factors reproduce every integral."""
+    shape = (2, 3, 1, 3, 40)            # 15 + 10 pairs < 40 auxiliary functions
+    Ja, Jb, m, g = _run(shape, None, 1e-8, seed=12)
+    lam, U, m_ref, Bref = naf.naf(Ja, Jb, 1e-8)
+    assert m == m_ref and m <= 25
+    assert np.max(np.abs(g["eigenvalues"] - lam)) <= 1e-12 * lam[0]
+    for s, J in enumerate((Ja, Jb)):
+        n = J.shape[1]
+        F = _full(tuple(g[k] for k in (("Boo_a", "Bov_a", "Bvv_a"), ("Boo_b", "Bov_b", "Bvv_b"))[s]), shape[2 * s])
+        gram = F.reshape(m, n * n).T @ F.reshape(m, n * n)
+        ref = J.reshape(J.shape[0], n * n).T @ J.reshape(J.shape[0], n * n)
+        assert np.max(np.abs(gram - ref)) <= 1e-11 * np.max(np.abs(ref)), s
