@@ -35,11 +35,16 @@
  *  - A work item is one unique occupied triplet (block, p, q, r):
  *      block 0 aaa (i<j<k), 1 aab (i<j alpha, K beta),
  *      2 abb (I<J beta, k alpha), 3 bbb (I<J<K).
- *  - Results are deterministic: bitwise identical across runs and batch
- *    sizes for the same inputs, precision and item list.
+ *  - Results are deterministic.  Energies are bitwise identical across runs,
+ *    batch sizes and tile configurations for the same inputs, precision and
+ *    item list; adjoints are bitwise identical across runs for a fixed
+ *    batching (other batchings agree to rounding).
  *
- * Errors: every entry point returns LT_OK (0) or a negative code; on error
- * nothing is enqueued and ltriples_last_error() (thread-local) describes it.
+ * Errors: every entry point returns LT_OK (0) or a negative code, and
+ * ltriples_last_error() (thread-local) describes it.  Argument, shape,
+ * precision, workspace and orbital-energy errors are found before anything
+ * is enqueued; a HIP, rocBLAS or rocSOLVER failure (LT_EHIP) may leave
+ * earlier work of the call enqueued.
  */
 #ifndef LTRIPLES_H
 #define LTRIPLES_H

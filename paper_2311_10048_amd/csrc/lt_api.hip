@@ -2282,6 +2282,8 @@ int ltriples_energy_rhf(const ltriples_rhf_domain* rd, int32_t precision, const 
   r = ltriples_workspace_size(&S.d, precision, &S.o, &inner);
   if (r) return r;
   const size_t need = S.head + inner;
+  r = check_denominators(&S.d);   // before anything is allocated or enqueued
+  if (r) return r;
   bool own = false;
   if (ws == nullptr) {
     HIPCHK(hipMalloc(&ws, need));
@@ -2380,6 +2382,8 @@ int ltriples_backward_rhf(const ltriples_rhf_domain* rd, int32_t precision, cons
   if (r) return r;
   const RhfBwd Lb = rhf_bwd_layout(rd, S.head);
   const size_t need = Lb.end + inner;
+  r = check_denominators(&S.d);   // before anything is allocated or enqueued
+  if (r) return r;
   bool own = false;
   if (ws == nullptr) {
     HIPCHK(hipMalloc(&ws, need));

@@ -139,3 +139,21 @@ def test_rhf_backward_gbar_and_partial_outputs():
     for k in ("tau", "ev"):
         err = float((g2[k] + 1.5 * g1[k]).abs().max())
         assert err <= 1e-13 * float(g1[k].abs().max()), (k, err)
+
+
+def test_rhf_rejects_bad_denominators():
+    """An occupied energy above a virtual one is rejected before any work,
+    by the energy and by the adjoint."""
+    import torch
+    dom = _dom((3, 17, 30))
+    t = _rhf_dev(dom)
+    t["ev"] = t["ev"].clone()
+    t["ev"][0] = float(t["eo"].max().item()) + 0.0   # gap of zero
+    dims = (dom.noa, dom.nva, dom.naux)
+    with pytest.raises(lt.LtError) as ei:
+        lt.ltriples_energy_rhf(t, dims, lt.LT_FP64)
+    assert ei.value.code == lt.LT_EDENOM
+    with pytest.raises(lt.LtError) as ei:
+        lt.ltriples_backward_rhf(t, dims, lt.LT_FP64)
+    assert ei.value.code == lt.LT_EDENOM
+    torch.cuda.synchronize()
