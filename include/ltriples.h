@@ -36,9 +36,10 @@
  *      block 0 aaa (i<j<k), 1 aab (i<j alpha, K beta),
  *      2 abb (I<J beta, k alpha), 3 bbb (I<J<K).
  *  - Results are deterministic.  Energies are bitwise identical across runs,
- *    batch sizes and tile configurations for the same inputs, precision and
- *    item list; adjoints are bitwise identical across runs for a fixed
- *    batching (other batchings agree to rounding).
+ *    batch sizes, tile configurations and orders of the item list for the
+ *    same inputs, precision and item set (each block's items are processed
+ *    in canonical order); adjoints are bitwise identical across runs for a
+ *    fixed batching (other batchings agree to rounding).
  *
  * Errors: every entry point returns LT_OK (0) or a negative code, and
  * ltriples_last_error() (thread-local) describes it.  Argument, shape,

@@ -12,6 +12,7 @@
 //     batch buffers, then the FP64 energy epilogue and per-item reduction;
 //  6. per-block parts and the total, summed in a fixed order.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -128,10 +129,23 @@ struct ItemLists {
 
 void build_items(const Dims& D, const ltriples_options* o, ItemLists& L) {
   if (o && o->items) {
+    // each block's items in canonical (p, q, r) order, whatever the caller's
+    // order: batches, launch order and every reduction order then depend on
+    // the item set only (per-item values still go to the caller's positions)
+    std::vector<std::array<int32_t, 4>> blk[4];
     for (int32_t n = 0; n < o->n_items; ++n) {
       const int32_t* it = o->items + 4 * n;
-      L.trip[it[0]].insert(L.trip[it[0]].end(), {it[1], it[2], it[3]});
-      L.dst[it[0]].push_back(n);
+      blk[it[0]].push_back({it[1], it[2], it[3], n});
+    }
+    for (int b = 0; b < 4; ++b) {
+      std::stable_sort(blk[b].begin(), blk[b].end(), [](const std::array<int32_t, 4>& x,
+                                                          const std::array<int32_t, 4>& y) {
+        return x[0] != y[0] ? x[0] < y[0] : x[1] != y[1] ? x[1] < y[1] : x[2] < y[2];
+      });
+      for (auto& x : blk[b]) {
+        L.trip[b].insert(L.trip[b].end(), {x[0], x[1], x[2]});
+        L.dst[b].push_back(x[3]);
+      }
     }
     L.total = o->n_items;
     return;

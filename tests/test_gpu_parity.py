@@ -161,3 +161,17 @@ def test_autotune_changes_no_bit(name, prec):
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_BF16X3])
+def test_item_order_changes_no_bit(prec):
+    """The same item set in a shuffled order gives bitwise the same energy
+    and parts, and each item's value at its caller position."""
+    dom = synth.make_domain(*SHAPES["ragged"], seed=synth.BASE_SEED + 17)
+    items = np.asarray(synth.sample_items(dom.noa, dom.nob, 6, seed=3)).reshape(-1, 4)
+    perm = np.random.default_rng(4).permutation(len(items))
+    t = to_device(dom)
+    E1, p1, e1 = gpu_energy(dom, prec, items=items, tensors=t)
+    E2, p2, e2 = gpu_energy(dom, prec, items=items[perm], tensors=t)
+    assert E1 == E2 and np.array_equal(p1, p2)
+    assert np.array_equal(e1[perm], e2)
