@@ -175,3 +175,26 @@ def test_item_order_changes_no_bit(prec):
     E2, p2, e2 = gpu_energy(dom, prec, items=items[perm], tensors=t)
     assert E1 == E2 and np.array_equal(p1, p2)
     assert np.array_equal(e1[perm], e2)
+
+
+def test_workspace_too_small_and_nonfinite_energies():
+    """LT_EWORKSPACE for a caller workspace one byte short, LT_ENONFINITE
+    for a NaN orbital energy; both before any work is enqueued."""
+    import torch
+    dom = synth.config_domain("tiny")
+    t = to_device(dom)
+    d = lt.make_domain(dom.dims, t)
+    need = lt.ltriples_workspace_size(d, lt.LT_FP32)
+    ws = torch.empty(need - 1, dtype=torch.uint8, device="cuda")
+    with pytest.raises(lt.LtError) as ei:
+        lt.ltriples_energy(t, dom.dims, lt.LT_FP32, workspace=ws)
+    assert ei.value.code == lt.LT_EWORKSPACE
+    t2 = dict(t)
+    t2["eo_b"] = t["eo_b"].clone()
+    t2["eo_b"][1] = float("nan")
+    with pytest.raises(lt.LtError) as ei:
+        lt.ltriples_energy(t2, dom.dims, lt.LT_FP32)
+    assert ei.value.code == lt.LT_ENONFINITE
+    e, _ = lt.ltriples_energy(t, dom.dims, lt.LT_FP32)      # the library is still usable
+    torch.cuda.synchronize()
+    assert np.isfinite(float(e.item()))
