@@ -277,3 +277,39 @@ def test_rhf_backward_workspace_and_errors():
     g = lt.RhfGrad()
     assert lib.ltriples_backward_rhf(ctypes.byref(d), lt.LT_FP64, None, None, ctypes.byref(g), None, 0,
                                      None) == lt.LT_EINVAL
+
+
+def test_ctypes_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures have the C sizes and field offsets of
+    the header's structs (compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {
+        "ltriples_domain": (lt.Domain, ["noa", "t1a", "fov_b"]),
+        "ltriples_options": (lt.Options, ["items", "e_items", "stats", "graph", "build_chunk_mib", "autotune"]),
+        "ltriples_stats": (lt.Stats, ["n_items"]),
+        "ltriples_domain_grad": (lt.DomainGrad, ["t1a", "fov_b", "eo_a", "ev_b"]),
+        "ltriples_rhf_domain": (lt.RhfDomain, ["no", "t1", "fov"]),
+        "ltriples_rhf_grad": (lt.RhfGrad, ["t1", "fov"]),
+        "ltriples_naf_input": (lt.NafInput, ["nx", "Ja", "Jb"]),
+        "ltriples_naf_output": (lt.NafOutput, ["Boo_a", "eigenvalues"]),
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ltriples.h"', "int main(void) {"]
+    for name, (_, fields) in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f in fields:
+            lines.append(f'  printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                                check=True).stdout.split("\n") if line)
+    for name, (cls, fields) in structs.items():
+        assert int(out[name]) == ctypes.sizeof(cls), name
+        for f in fields:
+            assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
