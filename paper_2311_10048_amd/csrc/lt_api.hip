@@ -876,6 +876,9 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
     }
     // contraction of one batch: FP64/FP32 matrix cores, or split BF16
     auto contract = [&](lt::GemmArgs<T>& g) -> hipError_t {
+      // an empty output (a virtual space of size zero) has nothing to compute;
+      // the tile selection below divides by the row-tile count
+      if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return hipSuccess;
       if (!P.bf) return lt::launch_gemm<T>(g, st, o && o->autotune);
       lt::GemmArgs16 h{};
       h.M = g.M; h.N = g.N; h.nbatch = g.nbatch; h.nprod = P.bf;

@@ -27,6 +27,8 @@ SHAPES = {
     "no_beta_occ": (4, 0, 21, 22, 40),
     "one_beta": (3, 1, 17, 18, 30),
     "wide": (3, 3, 70, 67, 64),
+    "no_beta_vir": (4, 3, 20, 0, 30),
+    "no_alpha_vir": (3, 3, 0, 5, 20),
 }
 
 

@@ -24,6 +24,8 @@ SHAPES = {
     "one_beta": (3, 1, 17, 18, 30),        # aaa, aab
     "wide": (3, 3, 70, 67, 64),            # v > 64: several GEMM and epilogue tiles
     "tall": (3, 1, 400, 401, 48),          # v > 384: several row tiles per contraction (aaa, aab)
+    "no_beta_vir": (4, 3, 20, 0, 30),      # empty beta virtual space: mixed blocks have no C
+    "no_alpha_vir": (3, 3, 0, 5, 20),      # empty alpha virtual space: only bbb contributes
 }
 _REF = {}   # oracle results per shape, shared by the three precisions
 
