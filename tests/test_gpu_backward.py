@@ -29,6 +29,8 @@ SHAPES = {
     "wide": (3, 3, 70, 67, 64),
     "no_beta_vir": (4, 3, 20, 0, 30),
     "no_alpha_vir": (3, 3, 0, 5, 20),
+    "no_alpha_occ": (0, 4, 21, 22, 40),
+    "one_alpha_two_beta": (1, 2, 15, 16, 30),
 }
 
 

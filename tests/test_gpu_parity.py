@@ -26,6 +26,8 @@ SHAPES = {
     "tall": (3, 1, 400, 401, 48),          # v > 384: several row tiles per contraction (aaa, aab)
     "no_beta_vir": (4, 3, 20, 0, 30),      # empty beta virtual space: mixed blocks have no C
     "no_alpha_vir": (3, 3, 0, 5, 20),      # empty alpha virtual space: only bbb contributes
+    "no_alpha_occ": (0, 4, 21, 22, 40),    # only the bbb block
+    "one_alpha_two_beta": (1, 2, 15, 16, 30),   # only the abb block, one item
 }
 _REF = {}   # oracle results per shape, shared by the three precisions
 
