@@ -17,8 +17,10 @@ pytestmark = pytest.mark.gpu
 TOL_E = {lt.LT_FP64: 1e-11, lt.LT_FP32: 1e-8, lt.LT_BF16X3: 1e-6}
 
 # uneven domains: different sizes, one with a single beta orbital, one with
-# fewer than three occupied orbitals (zero energy)
-BATCH = [(5, 4, 30, 31, 120), (3, 1, 17, 18, 30), (6, 5, 45, 47, 96), (2, 0, 9, 10, 12), (4, 4, 26, 22, 50)]
+# fewer than three occupied orbitals (zero energy), one with an empty beta
+# virtual space and one with only the bbb block
+BATCH = [(5, 4, 30, 31, 120), (3, 1, 17, 18, 30), (6, 5, 45, 47, 96), (2, 0, 9, 10, 12), (4, 4, 26, 22, 50),
+         (4, 3, 20, 0, 30), (0, 4, 21, 22, 40)]
 
 
 def _doms():
