@@ -123,3 +123,12 @@ def test_naf_rank_deficient_metric():
         gram = F.reshape(m, n * n).T @ F.reshape(m, n * n)
         ref = J.reshape(J.shape[0], n * n).T @ J.reshape(J.shape[0], n * n)
         assert np.max(np.abs(gram - ref)) <= 1e-11 * np.max(np.abs(ref)), s
+
+
+def test_naf_threshold_above_spectrum_keeps_nothing():
+    shape = (3, 5, 2, 6, 20)
+    Ja, Jb, m, g = _run(shape, None, 1e6)
+    lam, U, m_ref, Bref = naf.naf(Ja, Jb, 1e6)
+    assert m == 0 == m_ref
+    assert all(g[k].shape[0] == 0 for k in ("Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b"))
+    assert np.max(np.abs(g["eigenvalues"] - lam)) <= 1e-12 * lam[0]
