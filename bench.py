@@ -300,65 +300,77 @@ def main():
 
     # ---- FP64 GPU path on a stratified sample, scaled to the domain -----------------------
     fp64 = None
-    items64 = synth.sample_items(dom.noa, dom.nob, args.fp64_sample, seed=2311)
-    if step_items is not None:
-        items64 = step_items
-    need64 = 0
-    if args.fp64_sample > 0 and len(items64):
-        o64, _keep = lt.make_options(items=items64)
-        need64 = lt.ltriples_workspace_size(d, lt.LT_FP64, o64)
-        del ws
-        torch.cuda.empty_cache()
-        if need64 > torch.cuda.mem_get_info(dev)[0] - (1 << 30):
-            fp64 = {"skipped": f"FP64 workspace of {need64 / 1e9:.1f} GB does not fit beside the inputs"}
-            log(fp64["skipped"])
-    if args.fp64_sample > 0 and len(items64) and fp64 is None:
-        F_s, n_s = lt.ltriples_flops(d, o64)
-        ws64 = torch.empty(need64, dtype=torch.uint8, device=dev)
-        ei64 = torch.zeros(n_s, 3, dtype=torch.float64, device=dev)
-        st64 = lt.Stats()
-        lt.ltriples_energy(tens, dom.dims, lt.LT_FP64, items=items64, e_items=ei64, workspace=ws64, stats=st64)
-        torch.cuda.synchronize()
-        per_flop_ms = (st64.triples_gemm_ms + st64.epilogue_ms) / F_s
-        est_ms = st64.setup_ms + per_flop_ms * F_all
-        mine = e_items.cpu().numpy()[positions(items64)]
-        ref64 = ei64.cpu().numpy()
-        s_mine, s_ref = mine.sum(), ref64.sum()
-        fp64 = {"sample_items": int(n_s), "sample_ms": round(st64.total_ms, 2),
-                "est_full_s": round(est_ms / 1e3, 2), "speedup_vs_fp64": round(est_ms / ms_per_step, 3),
-                "sample_rel_diff_vs_fp64": float(abs(s_mine - s_ref) / max(1.0, abs(s_ref))),
-                "gemm_tflops": round(st64.triples_gemm_flops / (st64.triples_gemm_ms * 1e-3) / 1e12, 2)}
-        log(f"fp64 sample: est {est_ms / 1e3:.1f} s for the domain, speedup {est_ms / ms_per_step:.2f}x")
-        del ws64
+    try:
+        items64 = synth.sample_items(dom.noa, dom.nob, args.fp64_sample, seed=2311)
+        if step_items is not None:
+            items64 = step_items
+        need64 = 0
+        if args.fp64_sample > 0 and len(items64):
+            o64, _keep = lt.make_options(items=items64)
+            need64 = lt.ltriples_workspace_size(d, lt.LT_FP64, o64)
+            del ws
+            torch.cuda.empty_cache()
+            if need64 > torch.cuda.mem_get_info(dev)[0] - (1 << 30):
+                fp64 = {"skipped": f"FP64 workspace of {need64 / 1e9:.1f} GB does not fit beside the inputs"}
+                log(fp64["skipped"])
+        if args.fp64_sample > 0 and len(items64) and fp64 is None:
+            F_s, n_s = lt.ltriples_flops(d, o64)
+            ws64 = torch.empty(need64, dtype=torch.uint8, device=dev)
+            ei64 = torch.zeros(n_s, 3, dtype=torch.float64, device=dev)
+            st64 = lt.Stats()
+            lt.ltriples_energy(tens, dom.dims, lt.LT_FP64, items=items64, e_items=ei64, workspace=ws64, stats=st64)
+            torch.cuda.synchronize()
+            per_flop_ms = (st64.triples_gemm_ms + st64.epilogue_ms) / F_s
+            est_ms = st64.setup_ms + per_flop_ms * F_all
+            mine = e_items.cpu().numpy()[positions(items64)]
+            ref64 = ei64.cpu().numpy()
+            s_mine, s_ref = mine.sum(), ref64.sum()
+            fp64 = {"sample_items": int(n_s), "sample_ms": round(st64.total_ms, 2),
+                    "est_full_s": round(est_ms / 1e3, 2), "speedup_vs_fp64": round(est_ms / ms_per_step, 3),
+                    "sample_rel_diff_vs_fp64": float(abs(s_mine - s_ref) / max(1.0, abs(s_ref))),
+                    "gemm_tflops": round(st64.triples_gemm_flops / (st64.triples_gemm_ms * 1e-3) / 1e12, 2)}
+            log(f"fp64 sample: est {est_ms / 1e3:.1f} s for the domain, speedup {est_ms / ms_per_step:.2f}x")
+            del ws64
+    except Exception as ex:   # a failed side leg must not lose the measured step
+        fp64 = {"error": f"{type(ex).__name__}: {ex}"}
+        log(f"fp64 leg failed: {ex}")
 
     # ---- CPU oracle baseline + parity on its items ------------------------------------------
     cpu = None
     parity = None
-    if not args.no_cpu_baseline and args.cpu_sample > 0:
-        from oracle import blocks
-        itc = synth.sample_items(dom.noa, dom.nob, args.cpu_sample, seed=11)
-        if step_items is not None:
-            itc = step_items[:4]
-        oc, _k2 = lt.make_options(items=itc)
-        F_c, n_c = lt.ltriples_flops(d, oc)
-        tc = time.perf_counter()
-        ref = blocks.energy(dom, items=itc, return_items=True)
-        dt = time.perf_counter() - tc
-        cpu = {"value": round(F_c / dt / 1e9, 3), "unit": "GFLOP/s", "cores": _blas_threads(), "kind": "oracle",
-               "sample": f"{n_c} occupied triplets ({args.cpu_sample} per spin block) of the same domain, "
-                         f"{F_c:.3e} flops in {dt:.1f} s, NumPy FP64",
-               "seconds": round(dt, 2), "est_full_domain_s": round(dt * F_all / F_c, 1)}
-        g = e_items.cpu().numpy()[positions(itc)]
-        r = ref["items"]
-        tot = np.abs(g.sum(axis=1) - r.sum(axis=1)) / np.maximum(1.0, np.abs(r.sum(axis=1)))
-        tol = TOL[args.precision]
-        parity = {"oracle_items": int(n_c), "max_rel_err_item_E": float(tot.max()), "tolerance": tol,
-                  "pass": None if tol is None else bool(tot.max() <= tol)}
-        log(f"cpu oracle {dt:.1f} s for {n_c} items; max item rel err {tot.max():.2e}")
+    try:
+        if not args.no_cpu_baseline and args.cpu_sample > 0:
+            from oracle import blocks
+            itc = synth.sample_items(dom.noa, dom.nob, args.cpu_sample, seed=11)
+            if step_items is not None:
+                itc = step_items[:4]
+            oc, _k2 = lt.make_options(items=itc)
+            F_c, n_c = lt.ltriples_flops(d, oc)
+            tc = time.perf_counter()
+            ref = blocks.energy(dom, items=itc, return_items=True)
+            dt = time.perf_counter() - tc
+            cpu = {"value": round(F_c / dt / 1e9, 3), "unit": "GFLOP/s", "cores": _blas_threads(), "kind": "oracle",
+                   "sample": f"{n_c} occupied triplets ({args.cpu_sample} per spin block) of the same domain, "
+                             f"{F_c:.3e} flops in {dt:.1f} s, NumPy FP64",
+                   "seconds": round(dt, 2), "est_full_domain_s": round(dt * F_all / F_c, 1)}
+            g = e_items.cpu().numpy()[positions(itc)]
+            r = ref["items"]
+            tot = np.abs(g.sum(axis=1) - r.sum(axis=1)) / np.maximum(1.0, np.abs(r.sum(axis=1)))
+            tol = TOL[args.precision]
+            parity = {"oracle_items": int(n_c), "max_rel_err_item_E": float(tot.max()), "tolerance": tol,
+                      "pass": None if tol is None else bool(tot.max() <= tol)}
+            log(f"cpu oracle {dt:.1f} s for {n_c} items; max item rel err {tot.max():.2e}")
+    except Exception as ex:   # a failed side leg must not lose the measured step
+        cpu = {"error": f"{type(ex).__name__}: {ex}"}
+        log(f"cpu-baseline leg failed: {ex}")
 
     backward = None
-    if not args.no_backward and step_items is None:
-        backward = run_backward(lt, synth, torch, log)
+    try:
+        if not args.no_backward and step_items is None:
+            backward = run_backward(lt, synth, torch, log)
+    except Exception as ex:   # a failed side leg must not lose the measured step
+        backward = {"error": f"{type(ex).__name__}: {ex}"}
+        log(f"backward leg failed: {ex}")
 
     out = {
         "metric": METRIC,
