@@ -188,8 +188,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}): "
-              "the (T) energy of one domain is measured on a single MI355X; see DESIGN.md for how "
-              "the path would shard across GPUs.", file=sys.stderr)
+              "the (T) energy of one domain is measured on a single MI355X; sharding across GPUs "
+              "is a design note, not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -13,7 +13,7 @@ auxiliary functions").  SOMOs count as alpha occupied and beta virtual
 (Sec. "PAO construction"), so n_occ_b = n_occ_a - n_somo and
 n_vir_b = n_vir_a + n_somo.
 
-Readings of the synthetic recipe (also listed in the design doc):
+Readings of the synthetic recipe:
   * N(0, s) means standard deviation s (numpy ``normal(0, s)``).
   * B^Q_pq per spin: X ~ N(0, s) over the full (occ+vir) range, then
     B = (X + X^T)/sqrt(2), sliced into oo/ov/vv.  alpha and beta are drawn
