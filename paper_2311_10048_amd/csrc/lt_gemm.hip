@@ -16,6 +16,8 @@
 // consecutive logical tiles run on the same XCD (the dispatcher deals
 // work-groups round-robin over the 8 XCDs), which keeps a triplet's small
 // L operand and an R-operand tile shared by the row tiles in one L2.
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -338,6 +340,9 @@ hipError_t dispatch(const GCfg<T> (&cfg)[NC], int def, const GemmArgs<T>& g, hip
   if (e1) (void)hipEventDestroy(e1);
   if (err != hipSuccess) return err;
   g_pick[key] = best;
+  if (getenv("LTRIPLES_LOG"))
+    fprintf(stderr, "[ltriples] tuned %s contraction (kind %d, M %d, N %d): tile rows %d (default %d)\n",
+            sizeof(T) == 8 ? "FP64" : "FP32", g.ops.kind, g.M, g.N, cfg[best].rows, cfg[def].rows);
   return hipSuccess;
 }
 
