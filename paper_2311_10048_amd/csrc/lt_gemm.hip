@@ -245,6 +245,10 @@ hipError_t launch_cfg(GemmArgs<T> g, hipStream_t s) {
 // Tile choice (measured on gfx950 at the triplet-contraction shapes): the
 // whole M range in one work-group tile when it fits, 2 x 2 waves for
 // M > 96; FP64 with K chunks of 8.  Large-M integral builds use 128-row tiles.
+// Triplet contractions with more than 256 rows and at least 2^15 columns (the
+// whole-domain shapes) take 64-row tiles instead: timed against the whole-M
+// and 256-row tiles at M = 300 and 500 in FP32 and M = 300 in FP64, they cut
+// the contraction time by 10-25 %.
 // With tuning, the triplet contractions (mode 1) of each shape class may
 // take another configuration from the candidates below; every configuration
 // sums each output element in the same order, so results do not change.
@@ -346,14 +350,17 @@ hipError_t dispatch(const GCfg<T> (&cfg)[NC], int def, const GemmArgs<T>& g, hip
   return hipSuccess;
 }
 
+bool wide_contraction(const GemmArgs<float>& g) { return g.mode == 1 && g.M > 256 && g.N >= (1 << 15); }
+bool wide_contraction(const GemmArgs<double>& g) { return g.mode == 1 && g.M > 256 && g.N >= (1 << 15); }
+
 }  // namespace
 
 template <> hipError_t launch_gemm<float>(const GemmArgs<float>& g, hipStream_t s, bool tune) {
-  return dispatch(kCfg32, default32(g.M), g, s, tune);
+  return dispatch(kCfg32, wide_contraction(g) ? 1 : default32(g.M), g, s, tune);   // kCfg32[1]: 64 rows
 }
 
 template <> hipError_t launch_gemm<double>(const GemmArgs<double>& g, hipStream_t s, bool tune) {
-  return dispatch(kCfg64, default64(g.M), g, s, tune);
+  return dispatch(kCfg64, wide_contraction(g) ? 1 : default64(g.M), g, s, tune);   // kCfg64[1]: 64 rows
 }
 
 void reset_gemm_tuning() {
