@@ -11,18 +11,22 @@ The printed JSON line also carries:
                 stream; traffic from the committed counter summary when it was
                 taken on the current kernel source (else null)
   fp64_gpu      the same path in FP64 (the "plain FP64 GPU" baseline), timed
-                on a stratified item sample and scaled to the whole domain
+                on a stratified item sample and scaled to the whole domain;
+                with --autotune 1 its tiles are tuned on that sample first
   parity        per-item values of the timed run against the FP64 CPU oracle
                 on the CPU-baseline items, and against the FP64 GPU run
   cpu_baseline  the FP64 CPU oracle timed on the host on a small item sample
-  backward      the adjoint pass (dE/dT1, dE/dT2, dE/dB) on the gradient
-                workload (20,18,160,162,640), FP32 and FP64, with a sampled
-                check against the oracle gradient
+  backward      the adjoint pass (dE/dT1, dE/dT2, dE/dB, dE/df_ov, dE/deps)
+                on the gradient workload (20,18,160,162,640), FP32 and FP64,
+                with a sampled check against the oracle gradient
 
 Other workloads (not the headline line): --workload large runs the largest
 domain (60,58,500,502,2000); --workload batch runs the set of 64 uneven
 domains through ltriples_energy_batched, eager and as a captured hipGraph
-(first call with capture, then replays).
+(first call with capture, then replays); --workload rhf runs a closed-shell
+domain (40 occupied, 300 virtual, 1200 auxiliary) through
+ltriples_energy_rhf; --workload naf times the natural-auxiliary-function
+compression that produces B^Q.
 
 Profiling aids (not headline measurements): --sample-items K restricts the
 timed step to K sampled triplets per spin block, --prefix-items K to the
