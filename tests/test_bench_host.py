@@ -80,3 +80,41 @@ def test_committed_traffic_is_gated_by_kernel_source_hash(monkeypatch):
     assert t["bytes_per_launch"] > 0
     monkeypatch.setattr(bench, "kernel_source_hash", lambda precision: "0" * 16)
     assert bench.committed_traffic("bf16x3", "lno") is None
+
+
+COMMON = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+          "scaling", "vs_baseline", "dtype", "data", "config")
+
+
+def _profiles():
+    d = os.path.join(ROOT, "profiles")
+    return sorted(os.path.join(d, f) for f in os.listdir(d) if f.startswith("bench_") and f.endswith(".json"))
+
+
+@pytest.mark.parametrize("path", _profiles(), ids=os.path.basename)
+def test_committed_bench_lines_keep_the_contract(path):
+    """Every committed bench line carries the contract's keys, names its
+    workload, ran on one GPU, and (where it has one) its roofline fraction
+    is achieved over peak."""
+    with open(path) as f:
+        line = json.load(f)
+    for k in COMMON:
+        assert k in line, k
+    assert line["n_gpus"] == 1 and line["steps"] >= 1
+    assert "workload" in line["config"] and "model" not in line["config"]
+    assert line["data"] == "synthetic" and line["value"] > 0
+    r = line.get("roofline")
+    if r is not None:
+        assert r["bound"] in ("hbm", "mfma", "alu") and r["unit"] in ("GB/s", "TFLOP/s")
+        assert abs(r["frac"] - r["achieved"] / r["peak"]) <= 1e-4
+        assert "traffic" in r
+
+
+def test_headline_line_has_roofline_traffic_and_cpu_baseline():
+    with open(os.path.join(ROOT, "profiles", "bench_bf16x3_lno_domain.json")) as f:
+        line = json.load(f)
+    r = line["roofline"]
+    assert r["peak"] == bench.PEAK_TFLOPS["bf16x3"] and r["traffic"] > 0
+    c = line["cpu_baseline"]
+    assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0 and c["sample"]
+    assert line["parity"]["pass"] is True
