@@ -1,7 +1,9 @@
 """The library's host code (validation, planning, descriptor building and
-their self-checks) built with AddressSanitizer on the host side only and
-driven through its C ABI without a GPU (tests/asan_host_driver.cpp).  Any
-out-of-bounds access or use-after-free in the planner fails the test."""
+their self-checks) built with AddressSanitizer and UndefinedBehaviorSanitizer
+on the host side only and driven through its C ABI without a GPU
+(tests/asan_host_driver.cpp).  Any out-of-bounds access or use-after-free in
+the planner, or undefined arithmetic in its size and offset computations
+(signed overflow, out-of-range shifts), fails the test."""
 import os
 import shutil
 import subprocess
@@ -23,7 +25,8 @@ def test_host_code_under_address_sanitizer():
         exe = os.path.join(tmp, "drv")
         cmd = [hipcc, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-               "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer",
+               "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+               "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
                "-I", os.path.join(ROOT, "include"), "-I", CSRC]
         cmd += [os.path.join(CSRC, s) for s in SOURCES]
         cmd += [os.path.join(ROOT, "tests", "asan_host_driver.cpp"), "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas",
@@ -35,3 +38,4 @@ def test_host_code_under_address_sanitizer():
         assert r.returncode == 0, (r.stdout[-4000:], r.stderr[-4000:])
         assert "0 failures" in r.stdout
         assert "AddressSanitizer" not in r.stderr
+        assert "runtime error" not in r.stderr
