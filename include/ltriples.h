@@ -59,7 +59,7 @@ extern "C" {
 
 #define LT_OK 0
 #define LT_EINVAL (-1)      /* null pointer or negative dimension */
-#define LT_ESHAPE (-2)      /* inconsistent dimensions or item list */
+#define LT_ESHAPE (-2)      /* inconsistent or too large dimensions, or a bad item list */
 #define LT_EDENOM (-3)      /* max occupied e >= min virtual e (some D >= 0), occupied-
                                virtual gap below 1e-100, or an |e| above 1e100 */
 #define LT_EPREC (-4)       /* unsupported precision */
@@ -80,7 +80,10 @@ typedef enum {
 } ltriples_precision;
 
 /* One LIS domain: sizes and device pointers in the layouts above.  A pointer
- * may be NULL only when its array has zero elements. */
+ * may be NULL only when its array has zero elements.  Size limits (LT_ESHAPE
+ * beyond them): nva, nvb <= 46340; noa, nob <= 4096; naux <= 2^24; and all
+ * FP64 input arrays together at most 2^37 elements (1 TiB), more than one
+ * device can hold. */
 typedef struct ltriples_domain {
   int32_t noa, nob, nva, nvb, naux;
   const double *t1a, *t1b;

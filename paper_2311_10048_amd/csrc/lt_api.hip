@@ -97,6 +97,9 @@ int validate(const ltriples_domain* d, int32_t prec, const ltriples_options* o) 
   if (prec != LT_FP64 && prec != LT_FP32 && prec != LT_BF16X3 && prec != LT_BF16)
     return fail(LT_EPREC, "unsupported precision %d", prec);
   const int64_t oa = d->noa, ob = d->nob, va = d->nva, vb = d->nvb, Q = d->naux;
+  // per-dimension limits first, so that the element counts below cannot overflow
+  if (va > 46340 || vb > 46340 || oa > 4096 || ob > 4096 || Q > (int64_t(1) << 24))
+    return fail(LT_ESHAPE, "dimension too large");
   struct P { const double* p; int64_t n; const char* name; } ps[] = {
       {d->t1a, oa * va, "t1a"}, {d->t1b, ob * vb, "t1b"},
       {d->t2aa, oa * oa * va * va, "t2aa"}, {d->t2bb, ob * ob * vb * vb, "t2bb"},
@@ -109,8 +112,12 @@ int validate(const ltriples_domain* d, int32_t prec, const ltriples_options* o) 
     if (x.n > 0 && !x.p) return fail(LT_EINVAL, "%s is NULL", x.name);
   if ((va > 0 || vb > 0) && (oa + ob) >= 3 && Q == 0)
     return fail(LT_ESHAPE, "naux = 0");
-  if (va > 46340 || vb > 46340 || oa > 4096 || ob > 4096)
-    return fail(LT_ESHAPE, "dimension too large");
+  // FP64 inputs beyond 1 TiB cannot be resident on one device; the bound also
+  // keeps every workspace size the planner derives far from size_t overflow
+  int64_t total = 0;
+  for (auto& x : ps) total += x.n;   // each term below 2^56 under the limits above
+  if (total > (int64_t(1) << 37))
+    return fail(LT_ESHAPE, "inputs too large (%lld FP64 elements, limit 2^37)", (long long)total);
   if (o && o->items && o->n_items > 0) {
     const int r = check_items(dims_of(d), o);
     if (r) return r;
@@ -2230,6 +2237,8 @@ int rhf_setup(const ltriples_rhf_domain* r, const ltriples_options* o, RhfSetup&
   if (o && (o->items || o->n_items || o->e_items || o->graph))
     return fail(LT_EINVAL, "item lists, per-item outputs and graphs are not closed-shell options");
   const int64_t no = r->no, nv = r->nv, Q = r->naux;
+  // the open-shell limits, before any product of dimensions is formed
+  if (nv > 46340 || no > 4096 || Q > (int64_t(1) << 24)) return fail(LT_ESHAPE, "dimension too large");
   const struct { const double* p; int64_t n; const char* name; } ps[] = {
       {r->t1, no * nv, "t1"}, {r->tau, no * no * nv * nv, "tau"}, {r->Boo, Q * no * no, "Boo"},
       {r->Bov, Q * no * nv, "Bov"}, {r->Bvv, Q * nv * nv, "Bvv"}, {r->eo, no, "eo"}, {r->ev, nv, "ev"},

@@ -1,8 +1,9 @@
-// Host-only driver for the AddressSanitizer build of the library: exercises
+// Host-only driver for the sanitizer build of the library: exercises
 // validation, workspace sizing, flop counts and the launch-plan self-checks
-// (forward for every precision, adjoint for FP64/FP32), the closed-shell and
-// NAF sizing calls, and the error paths, without any GPU call.  Device
-// pointers are placeholders that are never dereferenced.
+// (forward for every precision, adjoint for FP64/FP32) on small and full-size
+// domains, the rejection of domains too large for any device, the
+// closed-shell and NAF sizing calls, and the error paths, without any GPU
+// call.  Device pointers are placeholders that are never dereferenced.
 #include <cstdint>
 #include <cstdio>
 
@@ -16,16 +17,21 @@ static void expect(int got, int want, const char* what) {
   }
 }
 
+static ltriples_domain fake_domain(const int32_t (&sh)[5], const double* p) {
+  ltriples_domain d{};
+  d.noa = sh[0]; d.nob = sh[1]; d.nva = sh[2]; d.nvb = sh[3]; d.naux = sh[4];
+  const double** fields[] = {&d.t1a, &d.t1b, &d.t2aa, &d.t2bb, &d.t2ab, &d.Boo_a, &d.Bov_a, &d.Bvv_a, &d.Boo_b,
+                             &d.Bov_b, &d.Bvv_b, &d.eo_a, &d.ev_a, &d.eo_b, &d.ev_b, &d.fov_a, &d.fov_b};
+  for (auto f : fields) *f = p;
+  return d;
+}
+
 int main() {
   static double placeholder[4];
   const int32_t shapes[][5] = {{5, 4, 30, 31, 120}, {4, 0, 21, 22, 40}, {3, 1, 400, 401, 48},
                                {6, 5, 45, 47, 96},  {3, 3, 70, 67, 64}, {2, 2, 4, 4, 9}};
   for (const auto& sh : shapes) {
-    ltriples_domain d{};
-    d.noa = sh[0]; d.nob = sh[1]; d.nva = sh[2]; d.nvb = sh[3]; d.naux = sh[4];
-    const double** fields[] = {&d.t1a, &d.t1b, &d.t2aa, &d.t2bb, &d.t2ab, &d.Boo_a, &d.Bov_a, &d.Bvv_a, &d.Boo_b,
-                               &d.Bov_b, &d.Bvv_b, &d.eo_a, &d.ev_a, &d.eo_b, &d.ev_b, &d.fov_a, &d.fov_b};
-    for (auto f : fields) *f = placeholder;
+    ltriples_domain d = fake_domain(sh, placeholder);
     for (int prec = 0; prec < 4; ++prec) {
       size_t ws = 0;
       expect(ltriples_validate(&d, prec, nullptr), LT_OK, "validate");
@@ -52,6 +58,40 @@ int main() {
     if (d.noa >= 3) expect(ltriples_validate(&d, LT_FP64, &o), LT_OK, "good item");
     o.items = bad;
     expect(ltriples_validate(&d, LT_FP64, &o), LT_ESHAPE, "bad item");
+  }
+  // full-size shapes (the gradient, LNO-sized and largest domains): sizing,
+  // flop counts and the forward plan, with byte offsets beyond 2^31
+  const int32_t big[][5] = {{20, 18, 160, 162, 640}, {40, 38, 300, 302, 1200}, {60, 58, 500, 502, 2000}};
+  for (const auto& sh : big) {
+    ltriples_domain d = fake_domain(sh, placeholder);
+    for (int prec = 0; prec < 3; ++prec) {
+      size_t ws = 0;
+      expect(ltriples_workspace_size(&d, prec, nullptr, &ws), LT_OK, "full-size workspace");
+      if (ws < ((size_t)1 << 31)) expect(0, 1, "full-size workspace beyond 2 GiB");
+      expect(ltriples_plan_check(&d, prec, nullptr, 0), LT_OK, "full-size forward plan");
+    }
+    size_t ws = 0;
+    expect(ltriples_backward_workspace_size(&d, LT_FP32, nullptr, &ws), LT_OK, "full-size backward workspace");
+    double f = 0;
+    int64_t n = 0;
+    expect(ltriples_flops(&d, nullptr, &f, &n), LT_OK, "full-size flops");
+  }
+  // domains no device can hold are rejected before any size is derived from
+  // them: inputs over 1 TiB, and dimensions whose products would overflow
+  const int32_t huge[][5] = {{40, 38, 20000, 20000, 1200}, {2000000000, 2000000000, 46340, 46340, 2000000000},
+                             {4096, 4096, 46340, 46340, 1 << 24}, {3, 3, 30, 30, 2000000000}};
+  for (const auto& sh : huge) {
+    ltriples_domain d = fake_domain(sh, placeholder);
+    size_t ws = 0;
+    expect(ltriples_validate(&d, LT_FP32, nullptr), LT_ESHAPE, "oversized domain");
+    expect(ltriples_workspace_size(&d, LT_FP32, nullptr, &ws), LT_ESHAPE, "oversized domain workspace");
+  }
+  {
+    ltriples_rhf_domain r{};
+    r.no = 2000000000; r.nv = 46340; r.naux = 2000000000;
+    r.t1 = r.tau = r.Boo = r.Bov = r.Bvv = r.eo = r.ev = r.fov = placeholder;
+    size_t ws = 0;
+    expect(ltriples_rhf_workspace_size(&r, LT_FP32, nullptr, &ws), LT_ESHAPE, "oversized closed-shell domain");
   }
   // closed shell and NAF sizing
   ltriples_rhf_domain r{};

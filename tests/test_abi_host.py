@@ -51,6 +51,14 @@ def test_validate_ok_and_errors():
     assert lt.ltriples_validate(_fake_domain((4, 3, 10, 11, 20), null=("t2ab",)), lt.LT_FP64) == lt.LT_EINVAL
     assert "t2ab" in lt.ltriples_last_error()
     assert lt.ltriples_validate(_fake_domain((4, 3, 10, 11, 0)), lt.LT_FP64) == lt.LT_ESHAPE
+    # size limits: per dimension, and 2^37 FP64 input elements in all (checked
+    # before any product of dimensions is formed)
+    assert lt.ltriples_validate(_fake_domain((4097, 3, 10, 11, 20)), lt.LT_FP64) == lt.LT_ESHAPE
+    assert lt.ltriples_validate(_fake_domain((4, 3, 46341, 11, 20)), lt.LT_FP64) == lt.LT_ESHAPE
+    assert lt.ltriples_validate(_fake_domain((3, 3, 30, 30, 2**31 - 1)), lt.LT_FP64) == lt.LT_ESHAPE
+    assert lt.ltriples_validate(_fake_domain((40, 38, 20000, 20000, 1200)), lt.LT_FP64) == lt.LT_ESHAPE
+    assert "inputs too large" in lt.ltriples_last_error()
+    assert lt.ltriples_validate(_fake_domain((60, 58, 500, 502, 2000)), lt.LT_FP64) == lt.LT_OK
     # NULL allowed for empty arrays
     assert lt.ltriples_validate(_fake_domain((4, 0, 10, 11, 20), null=("t1b", "t2bb", "t2ab", "Boo_b",
                                                                        "Bov_b", "eo_b", "fov_b")),
