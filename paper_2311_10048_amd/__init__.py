@@ -181,6 +181,39 @@ def _check(code: int):
         raise LtError(code, ltriples_last_error())
 
 
+def domain_sizes(dims) -> dict:
+    """Element count of every ltriples_domain array for (noa, nob, nva, nvb, naux)."""
+    oa, ob, va, vb, q = (int(x) for x in dims)
+    return {"t1a": oa * va, "t1b": ob * vb, "t2aa": oa * oa * va * va, "t2bb": ob * ob * vb * vb,
+            "t2ab": oa * ob * va * vb, "Boo_a": q * oa * oa, "Bov_a": q * oa * va, "Bvv_a": q * va * va,
+            "Boo_b": q * ob * ob, "Bov_b": q * ob * vb, "Bvv_b": q * vb * vb, "eo_a": oa, "ev_a": va,
+            "eo_b": ob, "ev_b": vb, "fov_a": oa * va, "fov_b": ob * vb}
+
+
+def rhf_sizes(dims) -> dict:
+    """Element count of every ltriples_rhf_domain array for (no, nv, naux)."""
+    o, v, q = (int(x) for x in dims)
+    return {"t1": o * v, "tau": o * o * v * v, "Boo": q * o * o, "Bov": q * o * v, "Bvv": q * v * v,
+            "eo": o, "ev": v, "fov": o * v}
+
+
+def check_array(name: str, t, need: int, device: bool = True) -> None:
+    """The kernels read (or write) `need` float64 elements through this
+    tensor's pointer: it must be contiguous float64 with at least that many
+    elements and, with `device`, live in GPU memory.  Raw integer addresses
+    are passed through unchecked."""
+    if t is None or isinstance(t, int) or not hasattr(t, "is_contiguous"):
+        return
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if str(t.dtype) != "torch.float64":
+        raise ValueError(f"{name} must be float64")
+    if t.numel() < need:
+        raise ValueError(f"{name} has {t.numel()} elements; the dimensions need {need}")
+    if device and need > 0 and t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor (got one on {t.device})")
+
+
 def _ptr(x) -> int:
     if x is None:
         return 0
@@ -197,13 +230,10 @@ def make_domain(dims, tensors: Optional[Mapping[str, object]] = None) -> Domain:
     d = Domain()
     d.noa, d.nob, d.nva, d.nvb, d.naux = (int(x) for x in dims)
     tensors = tensors or {}
+    need = domain_sizes(dims)
     for n in ARRAY_FIELDS:
         t = tensors.get(n)
-        if t is not None and hasattr(t, "is_contiguous"):
-            if not t.is_contiguous():
-                raise ValueError(f"{n} must be contiguous")
-            if str(t.dtype) != "torch.float64":
-                raise ValueError(f"{n} must be float64")
+        check_array(n, t, need[n])
         setattr(d, n, _ptr(t))
     return d
 
@@ -294,13 +324,10 @@ def make_rhf_domain(dims, tensors: Optional[Mapping[str, object]] = None) -> Rhf
     d = RhfDomain()
     d.no, d.nv, d.naux = (int(x) for x in dims)
     tensors = tensors or {}
+    need = rhf_sizes(dims)
     for n in RHF_FIELDS:
         t = tensors.get(n)
-        if t is not None and hasattr(t, "is_contiguous"):
-            if not t.is_contiguous():
-                raise ValueError(f"{n} must be contiguous")
-            if str(t.dtype) != "torch.float64":
-                raise ValueError(f"{n} must be float64")
+        check_array(n, t, need[n])
         setattr(d, n, _ptr(t))
     return d
 
@@ -368,7 +395,9 @@ def ltriples_backward_rhf(tensors: Mapping[str, object], dims, precision: int = 
     if out is None:
         out = {k: torch.empty_like(tensors[k]) for k in RHF_FIELDS}
     g = RhfGrad()
+    need_g = rhf_sizes(dims)
     for k in RHF_FIELDS:
+        check_array(f"out[{k!r}]", out.get(k), need_g[k])
         setattr(g, k, _ptr(out.get(k)))
     lib = load_library()
     n = ctypes.c_size_t(0)
@@ -388,10 +417,9 @@ def make_naf_input(dims, Ja=None, Jb=None) -> NafInput:
     three-index integral tensors [nx][n_s][n_s] (device)."""
     x = NafInput()
     x.no_a, x.nv_a, x.no_b, x.nv_b, x.nx = (int(v) for v in dims)
-    for name, t in (("Ja", Ja), ("Jb", Jb)):
-        if t is not None and hasattr(t, "is_contiguous"):
-            if not t.is_contiguous() or str(t.dtype) != "torch.float64":
-                raise ValueError(f"{name} must be contiguous float64")
+    na, nb = x.no_a + x.nv_a, x.no_b + x.nv_b
+    for name, t, n in (("Ja", Ja, na), ("Jb", Jb, nb)):
+        check_array(name, t, x.nx * n * n)
         setattr(x, name, _ptr(t))
     return x
 
@@ -519,7 +547,9 @@ def ltriples_backward(tensors: Mapping[str, object], dims, precision: int = LT_F
     if out is None:
         out = {k: torch.empty_like(tensors[k]) for k in GRAD_FIELDS + FOCK_GRAD_FIELDS}
     g = DomainGrad()
+    need_g = domain_sizes(dims)
     for k in GRAD_FIELDS + FOCK_GRAD_FIELDS:
+        check_array(f"out[{k!r}]", out.get(k), need_g[k])
         setattr(g, k, _ptr(out.get(k)))
     need = ltriples_backward_workspace_size(dom, precision, opts)
     if workspace is None:

@@ -1,0 +1,75 @@
+"""Host-side checks of the Python binding's argument checks (no GPU): every
+tensor handed to the kernels must be contiguous float64, large enough for
+the declared dimensions and resident on the GPU, and the synthetic domains
+of every GPU test shape meet the size rule exactly."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2311_10048_amd as lt
+import synth
+from tests import test_gpu_backward, test_gpu_naf, test_gpu_parity, test_gpu_rhf
+
+OPEN_SHAPES = sorted(set(test_gpu_parity.SHAPES.values()) | set(test_gpu_backward.SHAPES.values()))
+RHF_SHAPES = sorted(set(test_gpu_rhf.SHAPES.values()))
+
+
+@pytest.mark.parametrize("shape", OPEN_SHAPES)
+def test_open_shell_test_domains_have_the_declared_sizes(shape):
+    dom = synth.make_domain(*shape, seed=1)
+    need = lt.domain_sizes(dom.dims)
+    assert set(dom.arrays()) == set(lt.ARRAY_FIELDS)
+    for k, v in dom.arrays().items():
+        assert v.size == need[k], k
+        lt.check_array(k, torch.from_numpy(np.ascontiguousarray(v)), need[k], device=False)
+
+
+@pytest.mark.parametrize("shape", RHF_SHAPES)
+def test_closed_shell_test_domains_have_the_declared_sizes(shape):
+    dom = synth.make_rhf_domain(*shape, seed=1)
+    need = lt.rhf_sizes(shape)
+    arrs = synth.rhf_arrays(dom)
+    assert set(arrs) == set(lt.RHF_FIELDS)
+    for k, v in arrs.items():
+        assert v.size == need[k], k
+
+
+@pytest.mark.parametrize("shape", sorted({s for s, _d, _e in test_gpu_naf.CASES.values()}))
+def test_naf_test_inputs_have_the_declared_sizes(shape):
+    Ja, Jb = synth.make_naf_input(*shape, seed=1, decay=10.0)
+    na, nb = shape[0] + shape[1], shape[2] + shape[3]
+    assert Ja.size == shape[4] * na * na and Jb.size == shape[4] * nb * nb
+
+
+def test_check_array_rejects_what_the_kernels_cannot_use():
+    t = torch.zeros(12, dtype=torch.float64)
+    lt.check_array("x", t, 12, device=False)
+    lt.check_array("x", t, 10, device=False)                 # a larger buffer is fine
+    with pytest.raises(ValueError, match="elements"):
+        lt.check_array("x", t, 13, device=False)
+    with pytest.raises(ValueError, match="float64"):
+        lt.check_array("x", t.float(), 12, device=False)
+    with pytest.raises(ValueError, match="contiguous"):
+        lt.check_array("x", t.reshape(3, 4).t(), 12, device=False)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        lt.check_array("x", t, 12)
+    lt.check_array("x", torch.zeros(0, dtype=torch.float64), 0)   # empty arrays may live anywhere
+    lt.check_array("x", 0x1000, 12)                               # raw addresses pass through
+
+
+def test_make_domain_rejects_host_and_undersized_tensors():
+    dims = (3, 2, 5, 6, 8)
+    need = lt.domain_sizes(dims)
+    host = {k: torch.zeros(need[k], dtype=torch.float64) for k in lt.ARRAY_FIELDS}
+    with pytest.raises(ValueError, match="GPU tensor"):
+        lt.make_domain(dims, host)
+    addrs = {k: 0x1000 * (n + 1) for n, k in enumerate(lt.ARRAY_FIELDS)}
+    addrs["t2ab"] = torch.zeros(need["t2ab"] - 1, dtype=torch.float64)
+    with pytest.raises(ValueError, match="t2ab has"):
+        lt.make_domain(dims, addrs)
+    rd = (3, 5, 8)
+    rneed = lt.rhf_sizes(rd)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        lt.make_rhf_domain(rd, {k: torch.zeros(rneed[k], dtype=torch.float64) for k in lt.RHF_FIELDS})
+    with pytest.raises(ValueError, match="GPU tensor"):
+        lt.make_naf_input((2, 3, 2, 3, 4), torch.zeros(4 * 25, dtype=torch.float64), 0x1000)
