@@ -302,6 +302,13 @@ def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP3
         precision = PRECISIONS[precision]
     dom = make_domain(dims, tensors)
     opts, keep = make_options(items, e_items, batch_budget, batch_items, stats, build_chunk_mib, autotune)
+    if e_items is not None and not isinstance(e_items, int):
+        try:
+            n_it = ltriples_flops(dom, opts)[1]
+        except LtError:
+            n_it = None          # the energy call below reports the same error
+        if n_it is not None:
+            check_array("e_items", e_items, 3 * n_it)
     dev = next(t for t in tensors.values() if hasattr(t, "device")).device
     need = ltriples_workspace_size(dom, precision, opts)
     if workspace is None:

@@ -73,3 +73,20 @@ def test_make_domain_rejects_host_and_undersized_tensors():
         lt.make_rhf_domain(rd, {k: torch.zeros(rneed[k], dtype=torch.float64) for k in lt.RHF_FIELDS})
     with pytest.raises(ValueError, match="GPU tensor"):
         lt.make_naf_input((2, 3, 2, 3, 4), torch.zeros(4 * 25, dtype=torch.float64), 0x1000)
+
+
+def test_energy_rejects_short_or_host_item_outputs():
+    """e_items receives three doubles per item: a shorter or host tensor is
+    refused before anything is enqueued (the domain arrays here are fake
+    device addresses that are never dereferenced)."""
+    try:
+        lt.load_library()
+    except Exception as ex:             # the library is built by the build step
+        pytest.skip(f"library not built: {ex}")
+    dims = (4, 3, 10, 11, 20)
+    addrs = {k: 0x1000 * (n + 1) for n, k in enumerate(lt.ARRAY_FIELDS)}
+    items = [[0, 0, 1, 2], [1, 0, 1, 2]]
+    with pytest.raises(ValueError, match="e_items has 5 elements"):
+        lt.ltriples_energy(addrs, dims, lt.LT_FP64, items=items, e_items=torch.zeros(5, dtype=torch.float64))
+    with pytest.raises(ValueError, match="GPU tensor"):
+        lt.ltriples_energy(addrs, dims, lt.LT_FP64, items=items, e_items=torch.zeros(2, 3, dtype=torch.float64))
