@@ -224,6 +224,25 @@ def _ptr(x) -> int:
     raise TypeError(f"cannot take a device pointer of {type(x)}")
 
 
+def _device_of(tensors: Mapping[str, object]):
+    """The device of the first torch tensor among the arguments."""
+    for t in tensors.values():
+        if hasattr(t, "device"):
+            return t.device
+    raise ValueError("no torch tensor among the arrays: pass device tensors (raw addresses only to the "
+                     "ctypes-level calls)")
+
+
+def _grad_like(tensors: Mapping[str, object], k: str, n: int, dev):
+    """Output for the gradient of input k: shaped like the input, or a flat
+    tensor of its element count when the input was passed as None."""
+    import torch
+    t = tensors.get(k)
+    if hasattr(t, "shape"):
+        return torch.empty_like(t)
+    return torch.empty(n, dtype=torch.float64, device=dev)
+
+
 def make_domain(dims, tensors: Optional[Mapping[str, object]] = None) -> Domain:
     """ltriples_domain from (noa, nob, nva, nvb, naux) and device tensors
     (or raw device addresses) keyed by field name; missing arrays are NULL."""
@@ -309,7 +328,7 @@ def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP3
             n_it = None          # the energy call below reports the same error
         if n_it is not None:
             check_array("e_items", e_items, 3 * n_it)
-    dev = next(t for t in tensors.values() if hasattr(t, "device")).device
+    dev = _device_of(tensors)
     need = ltriples_workspace_size(dom, precision, opts)
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
@@ -368,7 +387,7 @@ def ltriples_energy_rhf(tensors: Mapping[str, object], dims, precision: int = LT
         precision = PRECISIONS[precision]
     dom = make_rhf_domain(dims, tensors)
     opts, keep = make_options(None, None, batch_budget, batch_items, stats, build_chunk_mib)
-    dev = next(t for t in tensors.values() if hasattr(t, "device")).device
+    dev = _device_of(tensors)
     need = ltriples_rhf_workspace_size(dom, precision, opts)
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
@@ -394,13 +413,13 @@ def ltriples_backward_rhf(tensors: Mapping[str, object], dims, precision: int = 
         precision = PRECISIONS[precision]
     dom = make_rhf_domain(dims, tensors)
     opts, keep = make_options(None, None, batch_budget, batch_items, None, build_chunk_mib)
-    dev = next(t for t in tensors.values() if hasattr(t, "device")).device
+    dev = _device_of(tensors)
     if gbar is None:
         gbar = torch.ones(1, dtype=torch.float64, device=dev)
     if gbar.dtype != torch.float64 or gbar.numel() != 1 or not gbar.is_contiguous():
         raise ValueError("gbar must be one contiguous float64 element")
     if out is None:
-        out = {k: torch.empty_like(tensors[k]) for k in RHF_FIELDS}
+        out = {k: _grad_like(tensors, k, n_k, dev) for k, n_k in rhf_sizes(dims).items()}
     g = RhfGrad()
     need_g = rhf_sizes(dims)
     for k in RHF_FIELDS:
@@ -499,7 +518,7 @@ def ltriples_energy_batched(tensors_list, dims_list, precision: int = LT_FP32, g
                            autotune=autotune)
     opts.graph = 1 if graph else 0
     arr = _domain_array(dims_list, tensors_list)
-    dev = next(t for t in tensors_list[0].values() if hasattr(t, "device")).device
+    dev = _device_of(tensors_list[0])
     lib = load_library()
     n = ctypes.c_size_t(0)
     _check(lib.ltriples_workspace_size_batched(arr, ndom, int(precision), ctypes.byref(opts), ctypes.byref(n)))
@@ -546,13 +565,14 @@ def ltriples_backward(tensors: Mapping[str, object], dims, precision: int = LT_F
         precision = PRECISIONS[precision]
     dom = make_domain(dims, tensors)
     opts, keep = make_options(items, None, batch_budget, batch_items, stats, build_chunk_mib)
-    dev = next(t for t in tensors.values() if hasattr(t, "device")).device
+    dev = _device_of(tensors)
     if gbar is None:
         gbar = torch.ones(1, dtype=torch.float64, device=dev)
     if gbar.dtype != torch.float64 or gbar.numel() != 1 or not gbar.is_contiguous():
         raise ValueError("gbar must be one contiguous float64 element")
     if out is None:
-        out = {k: torch.empty_like(tensors[k]) for k in GRAD_FIELDS + FOCK_GRAD_FIELDS}
+        sizes = domain_sizes(dims)
+        out = {k: _grad_like(tensors, k, sizes[k], dev) for k in GRAD_FIELDS + FOCK_GRAD_FIELDS}
     g = DomainGrad()
     need_g = domain_sizes(dims)
     for k in GRAD_FIELDS + FOCK_GRAD_FIELDS:

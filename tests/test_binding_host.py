@@ -90,3 +90,23 @@ def test_energy_rejects_short_or_host_item_outputs():
         lt.ltriples_energy(addrs, dims, lt.LT_FP64, items=items, e_items=torch.zeros(5, dtype=torch.float64))
     with pytest.raises(ValueError, match="GPU tensor"):
         lt.ltriples_energy(addrs, dims, lt.LT_FP64, items=items, e_items=torch.zeros(2, 3, dtype=torch.float64))
+
+
+def test_arrays_without_any_tensor_get_a_clear_error():
+    try:
+        lt.load_library()
+    except Exception as ex:
+        pytest.skip(f"library not built: {ex}")
+    addrs = {k: 0x1000 * (n + 1) for n, k in enumerate(lt.ARRAY_FIELDS)}
+    with pytest.raises(ValueError, match="no torch tensor"):
+        lt.ltriples_energy(addrs, (4, 3, 10, 11, 20), lt.LT_FP64)
+
+
+def test_gradient_outputs_for_arrays_passed_as_none():
+    """An empty input may be passed as None; its gradient output is then a
+    flat tensor of the (zero) element count instead of a failure."""
+    t = {"t1a": torch.zeros(2, 5, dtype=torch.float64), "t1b": None}
+    g = lt._grad_like(t, "t1a", 10, torch.device("cpu"))
+    assert g.shape == (2, 5)
+    g = lt._grad_like(t, "t1b", 0, torch.device("cpu"))
+    assert g.shape == (0,) and g.dtype == torch.float64
