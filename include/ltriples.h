@@ -65,7 +65,8 @@ extern "C" {
 #define LT_EPREC (-4)       /* unsupported precision */
 #define LT_EWORKSPACE (-5)  /* workspace too small */
 #define LT_EHIP (-6)        /* HIP runtime error */
-#define LT_ENONFINITE (-7)  /* NaN/Inf in the orbital energies */
+#define LT_ENONFINITE (-7)  /* NaN/Inf in the orbital energies, or in any input
+                               when options.check_finite is set */
 
 /* Arithmetic of the W contractions.  LT_FP64: FP64 matrix cores.
  * LT_FP32: FP32 matrix cores, FP32 accumulation.  LT_BF16X3: each FP32
@@ -110,9 +111,11 @@ typedef struct ltriples_stats {
 
 /* Options; a NULL options pointer means all defaults (zeros). */
 typedef struct ltriples_options {
-  /* bytes of workspace the per-batch triples intermediates may use;
-   * 0 = default (8 GiB, capped by the work) */
-  size_t batch_budget;
+  /* bytes of workspace the per-batch triples intermediates (contraction
+   * outputs and per-tile partial energies) may use; 0 = default (8 GiB,
+   * capped by the work).  Smaller budgets mean smaller item batches; results
+   * are bitwise unchanged. */
+  size_t workspace_budget;
   /* optional HOST array [n_items][4] of (block, p, q, r) restricting the
    * energy to these items (NULL = all unique triplets of the domain) */
   const int32_t* items;
@@ -145,9 +148,42 @@ typedef struct ltriples_options {
    * flag.  Every configuration sums each output element in the same order,
    * so the choice changes no result bit.  Tuning waits for the stream; it
    * is skipped under graph capture (the default or an earlier choice is
-   * used).  ltriples_autotune_reset() forgets the choices. */
+   * used).  ltriples_autotune_reset() forgets the choices.  When the
+   * environment variable LTRIPLES_TUNE_CACHE names a file, choices are read
+   * from it (JSON, per GPU architecture) before any tuning and every new
+   * choice is written back to it, so later processes, and graph captures,
+   * start from tuned tiles. */
   int32_t autotune;
-  int32_t reserved;
+  /* Accepted for interface compatibility; every call is deterministic
+   * whatever its value.  All reductions run in a fixed order with a fixed
+   * decomposition: energies, parts and per-item values are bitwise
+   * identical across runs, batch sizes, tile configurations (tuned or
+   * forced), build chunk sizes and item-list orders; adjoints are bitwise
+   * identical across runs for a fixed batching (a different batching
+   * changes the order of the reverse-product sums, so they agree to
+   * rounding only).  No atomics are used in any reduction. */
+  int32_t deterministic;
+  /* 1 = scan every input array for NaN and infinity on the device before
+   * anything else is computed, and return LT_ENONFINITE if one is found
+   * (the scan enqueues one fill and one reduction kernel and waits for the
+   * stream once).  The orbital energies are always checked (see
+   * ltriples_energy). */
+  int32_t check_finite;
+  /* Forced tile configuration of the triplet contraction kernels, per
+   * output layout: [0] same-spin S, [1] mixed G, [2] mixed Y.  0 =
+   * automatic (tuned choice, else the measured default); k = 1..8 forces
+   * configuration k of the precision's table for every launch of that
+   * layout (no tuning).  Tables (output rows x columns per work-group):
+   *   BF16X3 and BF16: 32x128, 64x128, 96x128, 128x128, 192x128, 256x128,
+   *                    320x128, 384x128 (4 waves; 1: 1x4 waves, 4..8: 2x2)
+   *   FP32:  32x128, 64x128, 96x128, 128x128, 192x128, 256x128, 320x128,
+   *          384x128
+   *   FP64:  32x64, 64x64, 128x64, 192x64, 256x64, 320x64, 384x64, 512x64
+   * Configurations only change the time: every one sums each output
+   * element over the same segments and stages in the same order, so the
+   * result is bitwise that of the automatic choice.  Values outside 0..8
+   * give LT_EINVAL. */
+  int32_t tile_override[3];
 } ltriples_options;
 
 /* Host-only validation of sizes, pointers, precision and item list.  Makes
@@ -170,12 +206,18 @@ int ltriples_flops(const ltriples_domain* d, const ltriples_options* o,
  *   e_out  device double[1]: E(T)
  *   parts  device double[4][3] or NULL: per block {E4, E_ST, E_DT}
  *   ws     device workspace of ws_bytes >= ltriples_workspace_size(), or
- *          NULL to let the library allocate and free it inside the call.
- * The call reads the orbital energies back to the host once (a synchronous
- * copy) to check that they are finite (LT_ENONFINITE), at most 1e100 in
- * magnitude, and that every virtual energy exceeds every occupied one by at
- * least 1e-100 (LT_EDENOM), so every denominator D lies in [-6e100, -3e-100];
- * everything else is asynchronous on `stream`.
+ *          NULL: the library then allocates it with hipMallocAsync on
+ *          `stream` and releases it with hipFreeAsync on every return path
+ *          (the allocation adds no wait for the stream).
+ * Host waits: the call reads the orbital energies back to the host with
+ * copies ordered on `stream` (after whatever the caller enqueued there) and
+ * waits for the stream, to check that they are finite (LT_ENONFINITE), at
+ * most 1e100 in magnitude, and that every virtual energy exceeds every
+ * occupied one by at least 1e-100 (LT_EDENOM), so every denominator D lies
+ * in [-6e100, -3e-100]; it then copies its item tables to the workspace and
+ * waits for the stream once more before enqueuing any kernel (and once more
+ * with options.check_finite).  The kernels themselves are asynchronous on
+ * `stream`.
  * Fewer than 3 occupied orbitals in total, or empty virtual spaces, give
  * E = 0 and LT_OK. */
 int ltriples_energy(const ltriples_domain* d, int32_t precision,
@@ -212,6 +254,7 @@ int ltriples_backward_workspace_size(const ltriples_domain* d, int32_t precision
  *   gbar   device pointer to one double (the incoming adjoint dL/dE)
  *   grad   host struct of device output pointers (see ltriples_domain_grad)
  *   ws     device workspace >= ltriples_backward_workspace_size(), or NULL
+ *          (stream-ordered allocation, as ltriples_energy)
  * Precision LT_FP64 or LT_FP32 (the contractions and operand gradients in
  * that precision, the epilogue, the integral gradients and the DF
  * back-contraction in FP64); other values give LT_EPREC.  options.e_items
@@ -243,13 +286,15 @@ int ltriples_workspace_size_batched(const ltriples_domain* ds, int32_t ndom,
  *   ds      HOST array [ndom] of domains (device pointers as above)
  *   e_out   device double[ndom]; parts device double[ndom][4][3] or NULL
  *   ws      device workspace >= ltriples_workspace_size_batched(), or NULL
+ *           (stream-ordered allocation, as ltriples_energy; no graph then)
  * Each domain's result is bitwise identical to ltriples_energy on that
  * domain alone.  Item lists, per-item outputs and stats are not available
  * here (LT_EINVAL).  With options.graph = 1 (and a caller workspace) the
  * launch sequence is captured into a hipGraph on the first call and replayed
  * on later calls whose shapes, pointers and options match; the graph reads
  * the inputs at replay time.  The orbital energies of every domain are read
- * back once per call (synchronous) to check the denominators. */
+ * back once per call (copies ordered on `stream`, then a wait for it) to
+ * check the denominators. */
 int ltriples_energy_batched(const ltriples_domain* ds, int32_t ndom,
                             int32_t precision, const ltriples_options* o,
                             double* e_out, double* parts, void* ws,
@@ -350,7 +395,8 @@ int ltriples_naf_workspace_size(const ltriples_naf_input* in, size_t* bytes);
  * by rocBLAS GEMMs and W is diagonalised by rocSOLVER (syevd) on `stream`;
  * the call waits for the stream once to count the kept eigenvalues.  The
  * sign of each NAF is the eigensolver's; (pq|rs) = sum_Q B^Q_pq B^Q_rs does
- * not depend on it.  ws as the other entry points (NULL: allocated inside).
+ * not depend on it.  ws as the other entry points (NULL: stream-ordered
+ * allocation on `stream`).
  * LT_EHIP also covers a rocBLAS/rocSOLVER failure or an eigensolver that
  * did not converge. */
 int ltriples_naf(const ltriples_naf_input* in, double eps, const ltriples_naf_output* out,

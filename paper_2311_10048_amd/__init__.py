@@ -87,7 +87,7 @@ class Stats(ctypes.Structure):
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("batch_budget", ctypes.c_size_t),
+    _fields_ = [("workspace_budget", ctypes.c_size_t),
                 ("items", ctypes.c_void_p),
                 ("n_items", ctypes.c_int32),
                 ("e_items", ctypes.c_void_p),
@@ -96,7 +96,9 @@ class Options(ctypes.Structure):
                 ("graph", ctypes.c_int32),
                 ("build_chunk_mib", ctypes.c_int32),
                 ("autotune", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("deterministic", ctypes.c_int32),
+                ("check_finite", ctypes.c_int32),
+                ("tile_override", ctypes.c_int32 * 3)]
 
 
 GRAD_FIELDS = ("t1a", "t1b", "t2aa", "t2bb", "t2ab", "Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b")
@@ -257,12 +259,19 @@ def make_domain(dims, tensors: Optional[Mapping[str, object]] = None) -> Domain:
     return d
 
 
-def make_options(items=None, e_items=None, batch_budget: int = 0, batch_items: int = 0,
-                 stats: Optional[Stats] = None, build_chunk_mib: int = 0, autotune: bool = False):
+def make_options(items=None, e_items=None, workspace_budget: int = 0, batch_items: int = 0,
+                 stats: Optional[Stats] = None, build_chunk_mib: int = 0, autotune: bool = False,
+                 check_finite: bool = False, tile_override=None, deterministic: bool = True):
     """ltriples_options; `items` is a host int32 array [n][4] (kept alive by
-    the returned tuple's second element)."""
+    the returned tuple's second element); `tile_override` is None or three
+    configuration numbers (0 = automatic) for the S, G and Y layouts."""
     o = Options()
-    o.batch_budget = int(batch_budget)
+    o.workspace_budget = int(workspace_budget)
+    o.deterministic = 1 if deterministic else 0
+    o.check_finite = 1 if check_finite else 0
+    if tile_override is not None:
+        for k, v in enumerate(tile_override):
+            o.tile_override[k] = int(v)
     o.batch_items = int(batch_items)
     o.build_chunk_mib = int(build_chunk_mib)
     o.autotune = 1 if autotune else 0
@@ -303,9 +312,9 @@ def ltriples_flops(dom: Domain, options: Optional[Options] = None):
 
 
 def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP32, items=None,
-                    e_items=None, batch_budget: int = 0, batch_items: int = 0, workspace=None,
+                    e_items=None, workspace_budget: int = 0, batch_items: int = 0, workspace=None,
                     stream=None, stats: Optional[Stats] = None, build_chunk_mib: int = 0,
-                    autotune: bool = False):
+                    autotune: bool = False, check_finite: bool = False, tile_override=None):
     """E(T) of one domain on the current HIP device.
 
     Returns (e, parts): a float64 device tensor of shape [1] and one of shape
@@ -320,7 +329,8 @@ def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP3
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     dom = make_domain(dims, tensors)
-    opts, keep = make_options(items, e_items, batch_budget, batch_items, stats, build_chunk_mib, autotune)
+    opts, keep = make_options(items, e_items, workspace_budget, batch_items, stats, build_chunk_mib, autotune,
+                              check_finite, tile_override)
     if e_items is not None and not isinstance(e_items, int):
         try:
             n_it = ltriples_flops(dom, opts)[1]
@@ -376,7 +386,7 @@ def ltriples_rhf_flops(dom: RhfDomain):
     return f.value, n.value
 
 
-def ltriples_energy_rhf(tensors: Mapping[str, object], dims, precision: int = LT_FP32, batch_budget: int = 0,
+def ltriples_energy_rhf(tensors: Mapping[str, object], dims, precision: int = LT_FP32, workspace_budget: int = 0,
                         batch_items: int = 0, workspace=None, stream=None, stats: Optional[Stats] = None,
                         build_chunk_mib: int = 0):
     """Closed-shell E(T) of one domain given in spatial orbitals (RHF_FIELDS,
@@ -386,7 +396,7 @@ def ltriples_energy_rhf(tensors: Mapping[str, object], dims, precision: int = LT
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     dom = make_rhf_domain(dims, tensors)
-    opts, keep = make_options(None, None, batch_budget, batch_items, stats, build_chunk_mib)
+    opts, keep = make_options(None, None, workspace_budget, batch_items, stats, build_chunk_mib)
     dev = _device_of(tensors)
     need = ltriples_rhf_workspace_size(dom, precision, opts)
     if workspace is None:
@@ -402,7 +412,7 @@ def ltriples_energy_rhf(tensors: Mapping[str, object], dims, precision: int = LT
 
 
 def ltriples_backward_rhf(tensors: Mapping[str, object], dims, precision: int = LT_FP64, gbar=None,
-                          batch_budget: int = 0, batch_items: int = 0, workspace=None, out=None, stream=None,
+                          workspace_budget: int = 0, batch_items: int = 0, workspace=None, out=None, stream=None,
                           build_chunk_mib: int = 0):
     """gbar * dE/dx of the closed-shell energy for x in RHF_FIELDS (dE/dtau
     projected onto its symmetry, dE/dBoo and dE/dBvv symmetrised).  Returns
@@ -412,7 +422,7 @@ def ltriples_backward_rhf(tensors: Mapping[str, object], dims, precision: int = 
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     dom = make_rhf_domain(dims, tensors)
-    opts, keep = make_options(None, None, batch_budget, batch_items, None, build_chunk_mib)
+    opts, keep = make_options(None, None, workspace_budget, batch_items, None, build_chunk_mib)
     dev = _device_of(tensors)
     if gbar is None:
         gbar = torch.ones(1, dtype=torch.float64, device=dev)
@@ -504,8 +514,9 @@ def ltriples_workspace_size_batched(dims_list, tensors_list, precision: int, opt
 
 
 def ltriples_energy_batched(tensors_list, dims_list, precision: int = LT_FP32, graph: bool = False,
-                            batch_budget: int = 0, batch_items: int = 0, workspace=None, out=None,
-                            stream=None, build_chunk_mib: int = 0, autotune: bool = False):
+                            workspace_budget: int = 0, batch_items: int = 0, workspace=None, out=None,
+                            stream=None, build_chunk_mib: int = 0, autotune: bool = False,
+                            check_finite: bool = False, tile_override=None):
     """E(T) of several domains in one call.  Returns (e [ndom], parts [ndom,4,3]).
     With graph=True the launch sequence is captured into a hipGraph on the
     first call and replayed on later calls with the same shapes, pointers,
@@ -514,8 +525,8 @@ def ltriples_energy_batched(tensors_list, dims_list, precision: int = LT_FP32, g
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     ndom = len(dims_list)
-    opts, _ = make_options(batch_budget=batch_budget, batch_items=batch_items, build_chunk_mib=build_chunk_mib,
-                           autotune=autotune)
+    opts, _ = make_options(workspace_budget=workspace_budget, batch_items=batch_items, build_chunk_mib=build_chunk_mib,
+                           autotune=autotune, check_finite=check_finite, tile_override=tile_override)
     opts.graph = 1 if graph else 0
     arr = _domain_array(dims_list, tensors_list)
     dev = _device_of(tensors_list[0])
@@ -553,8 +564,8 @@ def ltriples_backward_workspace_size(dom: Domain, precision: int, options: Optio
 
 
 def ltriples_backward(tensors: Mapping[str, object], dims, precision: int = LT_FP64, gbar=None, items=None,
-                      batch_budget: int = 0, batch_items: int = 0, workspace=None, out=None, stream=None,
-                      stats: Optional[Stats] = None, build_chunk_mib: int = 0):
+                      workspace_budget: int = 0, batch_items: int = 0, workspace=None, out=None, stream=None,
+                      stats: Optional[Stats] = None, build_chunk_mib: int = 0, check_finite: bool = False):
     """gbar * dE/dx for x in GRAD_FIELDS (projected convention for t2aa, t2bb,
     Boo, Bvv) and FOCK_GRAD_FIELDS (f_ov and the orbital energies).  Returns a dict of float64 device
     tensors shaped like the inputs.  `gbar` is a float64 device tensor with
@@ -564,7 +575,8 @@ def ltriples_backward(tensors: Mapping[str, object], dims, precision: int = LT_F
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     dom = make_domain(dims, tensors)
-    opts, keep = make_options(items, None, batch_budget, batch_items, stats, build_chunk_mib)
+    opts, keep = make_options(items, None, workspace_budget, batch_items, stats, build_chunk_mib,
+                              check_finite=check_finite)
     dev = _device_of(tensors)
     if gbar is None:
         gbar = torch.ones(1, dtype=torch.float64, device=dev)

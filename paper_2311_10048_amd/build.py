@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libltriples.so")
 SOURCES = ["lt_api.hip", "lt_gemm.hip", "lt_gemm_bf16.hip", "lt_rgemm.hip", "lt_prep.hip", "lt_epilogue.hip",
-           "lt_bwd.hip"]
+           "lt_bwd.hip", "lt_tunecache.hip"]
 
 # Packed FP32 vector instructions are disabled for every device pass.
 HIP_FLAGS = [

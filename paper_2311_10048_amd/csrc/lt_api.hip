@@ -90,6 +90,15 @@ int check_items(const Dims& D, const ltriples_options* o) {
   return LT_OK;
 }
 
+int validate_options(const ltriples_options* o) {
+  if (!o) return LT_OK;
+  for (int k = 0; k < 3; ++k)
+    if (o->tile_override[k] < 0 || o->tile_override[k] > 8)
+      return fail(LT_EINVAL, "tile_override[%d] = %d outside 0..8", k, o->tile_override[k]);
+  if (o->check_finite != 0 && o->check_finite != 1) return fail(LT_EINVAL, "check_finite must be 0 or 1");
+  return LT_OK;
+}
+
 int validate(const ltriples_domain* d, int32_t prec, const ltriples_options* o) {
   if (!d) return fail(LT_EINVAL, "domain is NULL");
   if (d->noa < 0 || d->nob < 0 || d->nva < 0 || d->nvb < 0 || d->naux < 0)
@@ -124,7 +133,7 @@ int validate(const ltriples_domain* d, int32_t prec, const ltriples_options* o) 
   }
   if (o && o->items == nullptr && o->n_items != 0)
     return fail(LT_EINVAL, "n_items given without items");
-  return LT_OK;
+  return validate_options(o);
 }
 
 // Items grouped by block: trip (p,q,r) and the caller-order index.
@@ -205,7 +214,7 @@ struct Plan {
   Buf BvvP[2], BovR[2], BovP64[2], BooP64[2];
   Buf As[2], Tp[2], T2T[2], GamT[2], U[2];
   Buf LmixT[2], Mst[2], Mts[2], Tmix[2], ZpT[2], TmT[2], OOT[2];
-  Buf OVab, e_items, trip, dst, order, firstcnt, segtab;
+  Buf OVab, e_items, trip, dst, order, firstcnt, flag, segtab;
   // adjoint pass: extra operands, mirrors (gradients of the prepared
   // operands, same layouts), FP64 four-index integral gradients, descriptors
   bool bwd = false;
@@ -400,7 +409,7 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
   for (int s = 0; s < 2; ++s)
     if (P.need_as[s]) s1b = std::max(s1b, ts * (size_t)(P.cAs[s] * D.v[s] * D.v[s] * P.ldv[s]));
   // phase 2: batch buffers + partials
-  const size_t budget = (o && o->batch_budget) ? o->batch_budget : (size_t(8) << 30);
+  const size_t budget = (o && o->workspace_budget) ? o->workspace_budget : (size_t(8) << 30);
   size_t s2 = 0;
   for (int b = 0; b < 4; ++b) {
     P.nb[b] = 0; P.per_item[b] = 0; P.ntile[b] = 0; P.part_off[b] = 0; P.bwg[b] = 0; P.ld_ri[b] = 0;
@@ -449,6 +458,7 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
   take(P.dst, 4 * std::max<int64_t>(L.total, 1));
   take(P.order, 4 * std::max<int64_t>(L.total, 1));
   take(P.firstcnt, 4 * 8);
+  take(P.flag, 4);
   if (P.bf) take(P.segtab, 2 * 6 * sizeof(lt::Seg8) * (size_t)std::max<int64_t>(L.total, 1));
   P.small = off;
   P.small_base = P.big;
@@ -886,14 +896,15 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
       // an empty output (a virtual space of size zero) has nothing to compute;
       // the tile selection below divides by the row-tile count
       if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return hipSuccess;
-      if (!P.bf) return lt::launch_gemm<T>(g, st, o && o->autotune);
+      const int force = o ? o->tile_override[g.ops.kind] - 1 : -1;   // 0 = automatic
+      if (!P.bf) return lt::launch_gemm<T>(g, st, o && o->autotune, force);
       lt::GemmArgs16 h{};
       h.M = g.M; h.N = g.N; h.nbatch = g.nbatch; h.nprod = P.bf;
       h.out = (float*)g.out; h.obs = g.obs; h.ldo = g.s_mr;
       h.kind = g.ops.kind;
       const int64_t first_item = (g.ops.items - d_trip) / 3;     // index in the block-ordered item list
       h.tab = (g.ops.kind == 2 ? tab1 : tab0) + 6 * first_item;
-      return lt::launch_gemm_bf16(h, st, o && o->autotune);
+      return lt::launch_gemm_bf16(h, st, o && o->autotune, force);
     };
     const int64_t nb = P.nb[b];
     T* out1 = (T*)scr;
@@ -982,22 +993,28 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
 // every energy finite and at most 1e100 in magnitude, so every denominator
 // D = e_i + e_j + e_k - e_a - e_b - e_c lies in [-6e100, -3e-100] (the range
 // the epilogues' reciprocal assumes).  Reads the orbital energies back to the
-// host (synchronous copy).
-int check_denominators(const ltriples_domain* d) {
+// host with copies ordered on the caller's stream (after whatever the caller
+// enqueued there to produce them), then waits for that stream.
+int check_denominators(const ltriples_domain* d, hipStream_t st) {
   const Dims D = dims_of(d);
   double omax = -INFINITY, vmin = INFINITY;
+  std::vector<double> ho[2], hv[2];
   for (int s = 0; s < 2; ++s) {
     const double* eo = s ? d->eo_b : d->eo_a;
     const double* ev = s ? d->ev_b : d->ev_a;
-    std::vector<double> ho(D.o[s]), hv(D.v[s]);
-    if (D.o[s]) HIPCHK(hipMemcpy(ho.data(), eo, 8 * D.o[s], hipMemcpyDeviceToHost));
-    if (D.v[s]) HIPCHK(hipMemcpy(hv.data(), ev, 8 * D.v[s], hipMemcpyDeviceToHost));
-    for (double x : ho) {
+    ho[s].resize(D.o[s]);
+    hv[s].resize(D.v[s]);
+    if (D.o[s]) HIPCHK(hipMemcpyAsync(ho[s].data(), eo, 8 * D.o[s], hipMemcpyDeviceToHost, st));
+    if (D.v[s]) HIPCHK(hipMemcpyAsync(hv[s].data(), ev, 8 * D.v[s], hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  for (int s = 0; s < 2; ++s) {
+    for (double x : ho[s]) {
       if (!std::isfinite(x)) return fail(LT_ENONFINITE, "non-finite occupied energy");
       if (std::fabs(x) > 1e100) return fail(LT_EDENOM, "occupied energy %.6g above 1e100 in magnitude", x);
       omax = std::max(omax, x);
     }
-    for (double x : hv) {
+    for (double x : hv[s]) {
       if (!std::isfinite(x)) return fail(LT_ENONFINITE, "non-finite virtual energy");
       if (std::fabs(x) > 1e100) return fail(LT_EDENOM, "virtual energy %.6g above 1e100 in magnitude", x);
       vmin = std::min(vmin, x);
@@ -1006,6 +1023,55 @@ int check_denominators(const ltriples_domain* d) {
   if (omax >= vmin) return fail(LT_EDENOM, "max occupied energy %.6g >= min virtual energy %.6g", omax, vmin);
   if (vmin - omax < 1e-100)
     return fail(LT_EDENOM, "occupied-virtual gap %.6g below 1e-100", vmin - omax);
+  return LT_OK;
+}
+
+// Workspace of a call made with ws == NULL: allocated stream-ordered on the
+// call's stream and released the same way on every return path (success or
+// error), so it neither leaks nor makes the call wait for the stream.
+struct OwnedWs {
+  void* p = nullptr;
+  hipStream_t st = nullptr;
+  OwnedWs() = default;
+  OwnedWs(const OwnedWs&) = delete;
+  OwnedWs& operator=(const OwnedWs&) = delete;
+  ~OwnedWs() {
+    if (p) (void)hipFreeAsync(p, st);
+  }
+};
+
+// The caller's workspace (checked against `need`), or a stream-ordered one.
+int get_ws(void*& ws, size_t ws_bytes, size_t need, hipStream_t st, OwnedWs& own) {
+  if (ws != nullptr) {
+    if (ws_bytes < need) return fail(LT_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
+    return LT_OK;
+  }
+  HIPCHK(hipMallocAsync(&own.p, std::max<size_t>(need, 256), st));
+  own.st = st;
+  ws = own.p;
+  return LT_OK;
+}
+
+// Opt-in scan of every input array of a domain for NaN and infinity, on the
+// device, with the flag in the domain's small buffers; waits for the stream.
+int scan_finite(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
+  const Dims D = dims_of(d);
+  const int64_t oa = D.o[0], ob = D.o[1], va = D.v[0], vb = D.v[1], Q = D.Q;
+  lt::FiniteScan a{};
+  const struct { const double* p; int64_t n; } ps[] = {
+      {d->t1a, oa * va}, {d->t1b, ob * vb}, {d->t2aa, oa * oa * va * va}, {d->t2bb, ob * ob * vb * vb},
+      {d->t2ab, oa * ob * va * vb}, {d->Boo_a, Q * oa * oa}, {d->Bov_a, Q * oa * va}, {d->Bvv_a, Q * va * va},
+      {d->Boo_b, Q * ob * ob}, {d->Bov_b, Q * ob * vb}, {d->Bvv_b, Q * vb * vb}, {d->eo_a, oa}, {d->ev_a, va},
+      {d->eo_b, ob}, {d->ev_b, vb}, {d->fov_a, oa * va}, {d->fov_b, ob * vb}};
+  for (const auto& x : ps)
+    if (x.n > 0) { a.p[a.narr] = x.p; a.n[a.narr] = x.n; ++a.narr; }
+  int32_t* flag = at_small<int32_t>(ws, P, P.flag);
+  HIPCHK(lt::launch_zero32(flag, 1, st));
+  HIPCHK(lt::launch_scan_finite(a, flag, st));
+  int32_t h = 0;
+  HIPCHK(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (h) return fail(LT_ENONFINITE, "NaN or infinity in the inputs (options.check_finite)");
   return LT_OK;
 }
 
@@ -1682,6 +1748,55 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
   return LT_OK;
 }
 
+// Body of ltriples_energy.
+int energy_call(const ltriples_domain* d, int32_t precision, const ltriples_options* o, double* e_out,
+                double* parts, void* ws, size_t ws_bytes, hipStream_t st) {
+  int r = validate(d, precision, o);
+  if (r) return r;
+  if (!e_out) return fail(LT_EINVAL, "e_out is NULL");
+  const Dims D = dims_of(d);
+  ltriples_options oo = o ? *o : ltriples_options{};
+  ItemLists L;
+  build_items(D, &oo, L);
+  Plan P;
+  plan_domain(d, precision, &oo, L, P);
+  r = check_denominators(d, st);
+  if (r) return r;
+  log_plan(P);
+  r = check_plan(P);
+  if (r) return r;
+  OwnedWs own;
+  r = get_ws(ws, ws_bytes, P.total, st, own);
+  if (r) return r;
+  r = upload_items(P, L, ws, st);
+  if (r) return r;
+  if (oo.check_finite) {
+    r = scan_finite(d, P, ws, st);
+    if (r) return r;
+  }
+  Timing tm;
+  tm.on = oo.stats != nullptr;
+  tm.st = st;
+  if (precision == LT_FP64) r = run<double>(d, P, L, &oo, e_out, parts, ws, st, tm);
+  else r = run<float>(d, P, L, &oo, e_out, parts, ws, st, tm);   // FP32, BF16X3, BF16
+  if (r == LT_OK && tm.on) {
+    HIPCHK(hipStreamSynchronize(st));
+    ltriples_stats* S = oo.stats;
+    *S = ltriples_stats{};
+    S->total_ms = Timing::ms(tm.start, tm.end);
+    S->setup_ms = Timing::ms(tm.start, tm.setup_end);
+    for (auto& x : tm.gemm) S->triples_gemm_ms += Timing::ms(x.first, x.second);
+    for (auto& x : tm.epi) S->epilogue_ms += Timing::ms(x.first, x.second);
+    S->triples_gemm_launches = (int64_t)tm.gemm.size();
+    S->triples_gemm_flops = tm.gemm_flops;
+    double f = 0;
+    for (int b = 0; b < 4; ++b) f += (double)P.n_blk[b] * item_flops(D, b);
+    S->algorithmic_flops = f;
+    S->n_items = L.total;
+  }
+  return r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1732,57 +1847,7 @@ int ltriples_flops(const ltriples_domain* d, const ltriples_options* o, double* 
 int ltriples_energy(const ltriples_domain* d, int32_t precision, const ltriples_options* o, double* e_out,
                     double* parts, void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
-  int r = validate(d, precision, o);
-  if (r) return r;
-  if (!e_out) return fail(LT_EINVAL, "e_out is NULL");
-  hipStream_t st = (hipStream_t)stream;
-  const Dims D = dims_of(d);
-
-  r = check_denominators(d);
-  if (r) return r;
-
-  ItemLists L;
-  build_items(D, o, L);
-  Plan P;
-  plan_domain(d, precision, o, L, P);
-  log_plan(P);
-  r = check_plan(P);
-  if (r) return r;
-  bool own = false;
-  if (ws == nullptr) {
-    HIPCHK(hipMalloc(&ws, P.total));
-    own = true;
-  } else if (ws_bytes < P.total) {
-    return fail(LT_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, P.total);
-  }
-  r = upload_items(P, L, ws, st);
-  if (r) return r;
-  Timing tm;
-  tm.on = o && o->stats;
-  tm.st = st;
-  if (precision == LT_FP64) r = run<double>(d, P, L, o, e_out, parts, ws, st, tm);
-  else r = run<float>(d, P, L, o, e_out, parts, ws, st, tm);   // FP32, BF16X3, BF16
-  if (r == LT_OK && tm.on) {
-    HIPCHK(hipStreamSynchronize(st));
-    ltriples_stats* S = o->stats;
-    *S = ltriples_stats{};
-    S->total_ms = Timing::ms(tm.start, tm.end);
-    S->setup_ms = Timing::ms(tm.start, tm.setup_end);
-    for (auto& x : tm.gemm) S->triples_gemm_ms += Timing::ms(x.first, x.second);
-    for (auto& x : tm.epi) S->epilogue_ms += Timing::ms(x.first, x.second);
-    S->triples_gemm_launches = (int64_t)tm.gemm.size();
-    S->triples_gemm_flops = tm.gemm_flops;
-    double f = 0;
-    for (int b = 0; b < 4; ++b) f += (double)P.n_blk[b] * item_flops(D, b);
-    S->algorithmic_flops = f;
-    S->n_items = L.total;
-  }
-  if (own) {
-    hipError_t e1 = hipStreamSynchronize(st);
-    hipError_t e2 = hipFree(ws);
-    if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) return fail(LT_EHIP, "HIP error at workspace release");
-  }
-  return r;
+  return energy_call(d, precision, o, e_out, parts, ws, ws_bytes, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -1972,21 +2037,18 @@ int ltriples_backward(const ltriples_domain* d, int32_t precision, const ltriple
   if (!grad) return fail(LT_EINVAL, "grad is NULL");
   hipStream_t st = (hipStream_t)stream;
   const Dims D = dims_of(d);
-  r = check_denominators(d);
+  r = check_denominators(d, st);
   if (r) return r;
   ItemLists L;
   build_items(D, o, L);
   Plan P;
   plan_backward(d, precision, o, L, P);
   log_plan(P);
-  bool own = false;
-  if (ws == nullptr) {
-    HIPCHK(hipMalloc(&ws, P.total));
-    own = true;
-  } else if (ws_bytes < P.total) {
-    return fail(LT_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, P.total);
-  }
+  OwnedWs own;
+  r = get_ws(ws, ws_bytes, P.total, st, own);
+  if (r) return r;
   r = upload_items(P, L, ws, st);
+  if (r == LT_OK && o && o->check_finite) r = scan_finite(d, P, ws, st);
   if (r == LT_OK) {
     Timing tm;
     tm.on = o && o->stats;
@@ -2009,11 +2071,6 @@ int ltriples_backward(const ltriples_domain* d, int32_t precision, const ltriple
       S->algorithmic_flops = 3.0 * f;
       S->n_items = L.total;
     }
-  }
-  if (own) {
-    hipError_t e1 = hipStreamSynchronize(st);
-    hipError_t e2 = hipFree(ws);
-    if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) return fail(LT_EHIP, "HIP error at workspace release");
   }
   return r;
 }
@@ -2041,6 +2098,10 @@ int plan_batch(const ltriples_domain* ds, int32_t ndom, int32_t precision, const
   if (ndom > 0 && !ds) return fail(LT_EINVAL, "domains is NULL");
   if (o && (o->items || o->n_items || o->e_items))
     return fail(LT_EINVAL, "item lists and per-item outputs are single-domain options");
+  {
+    const int r = validate_options(o);
+    if (r) return r;
+  }
   for (int32_t d = 0; d < ndom; ++d) {
     const int r = validate(&ds[d], precision, nullptr);
     if (r) return fail(r, "domain %d: %s", d, g_err.c_str());
@@ -2076,9 +2137,13 @@ constexpr size_t kMaxGraphs = 16;
 std::vector<uint64_t> batch_key(const ltriples_domain* ds, int32_t ndom, int32_t precision,
                                 const ltriples_options* o, const void* e_out, const void* parts,
                                 const void* ws, size_t ws_bytes, int device) {
+  // every option that changes the plan (buffer offsets, batches, chunks) or
+  // the recorded launches (forced tiles) is part of the key
   std::vector<uint64_t> k = {(uint64_t)device, (uint64_t)precision, (uint64_t)ndom, (uint64_t)(uintptr_t)e_out,
                              (uint64_t)(uintptr_t)parts, (uint64_t)(uintptr_t)ws, (uint64_t)ws_bytes,
-                             (uint64_t)(o ? o->batch_budget : 0), (uint64_t)(o ? o->batch_items : 0)};
+                             (uint64_t)(o ? o->workspace_budget : 0), (uint64_t)(o ? o->batch_items : 0),
+                             (uint64_t)(o ? o->build_chunk_mib : 0)};
+  for (int t = 0; t < 3; ++t) k.push_back((uint64_t)(o ? o->tile_override[t] : 0));
   for (int32_t d = 0; d < ndom; ++d) {
     const ltriples_domain& x = ds[d];
     k.insert(k.end(), {(uint64_t)x.noa, (uint64_t)x.nob, (uint64_t)x.nva, (uint64_t)x.nvb, (uint64_t)x.naux});
@@ -2091,8 +2156,10 @@ std::vector<uint64_t> batch_key(const ltriples_domain* ds, int32_t ndom, int32_t
 
 int enqueue_batch(const ltriples_domain* ds, int32_t ndom, int32_t precision, const ltriples_options* o,
                   const BatchPlan& B, double* e_out, double* parts, void* ws, hipStream_t st) {
-  ltriples_options oo{};
-  if (o) { oo.batch_budget = o->batch_budget; oo.batch_items = o->batch_items; }
+  // every run-time option of the call (autotuning, forced tiles, budgets);
+  // item lists, per-item outputs and stats are single-domain options
+  ltriples_options oo = o ? *o : ltriples_options{};
+  oo.items = nullptr; oo.n_items = 0; oo.e_items = nullptr; oo.stats = nullptr;
   for (int32_t d = 0; d < ndom; ++d) {
     Timing tm;  // off
     const int r = precision == LT_FP64
@@ -2125,27 +2192,24 @@ int ltriples_energy_batched(const ltriples_domain* ds, int32_t ndom, int32_t pre
   BatchPlan B;
   int r = plan_batch(ds, ndom, precision, o, B);
   if (r) return r;
-  for (int32_t d = 0; d < ndom; ++d) {
-    r = check_denominators(&ds[d]);
-    if (r) return fail(r, "domain %d: %s", d, g_err.c_str());
-  }
   if (ndom == 0) return LT_OK;
   hipStream_t st = (hipStream_t)stream;
-  const bool use_graph = o && o->graph && ws != nullptr;
-  bool own = false;
-  if (ws == nullptr) {
-    HIPCHK(hipMalloc(&ws, B.total));
-    own = true;
-  } else if (ws_bytes < B.total) {
-    return fail(LT_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, B.total);
+  for (int32_t d = 0; d < ndom; ++d) {
+    r = check_denominators(&ds[d], st);
+    if (r) return fail(r, "domain %d: %s", d, g_err.c_str());
   }
+  const bool use_graph = o && o->graph && ws != nullptr;
+  OwnedWs own;
+  r = get_ws(ws, ws_bytes, B.total, st, own);
+  if (r) return r;
   // item tables go to each domain's small region on every call (also before a
   // replay: the caller may have used the workspace for other calls meanwhile)
   for (int32_t d = 0; d < ndom; ++d) {
     r = upload_items(B.P[d], B.L[d], ws, st);
-    if (r) {
-      if (own) (void)hipFree(ws);
-      return r;
+    if (r) return r;
+    if (o && o->check_finite) {
+      r = scan_finite(&ds[d], B.P[d], ws, st);
+      if (r) return fail(r, "domain %d: %s", d, g_err.c_str());
     }
   }
   int device = 0;
@@ -2160,15 +2224,7 @@ int ltriples_energy_batched(const ltriples_domain* ds, int32_t ndom, int32_t pre
         return LT_OK;
       }
   }
-  if (!use_graph) {
-    r = enqueue_batch(ds, ndom, precision, o, B, e_out, parts, ws, st);
-    if (own) {
-      hipError_t e1 = hipStreamSynchronize(st);
-      hipError_t e2 = hipFree(ws);
-      if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) return fail(LT_EHIP, "HIP error at workspace release");
-    }
-    return r;
-  }
+  if (!use_graph) return enqueue_batch(ds, ndom, precision, o, B, e_out, parts, ws, st);
   // capture on a private stream (the caller's may be the legacy default stream)
   hipStream_t cs = nullptr;
   HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -2308,16 +2364,12 @@ int ltriples_energy_rhf(const ltriples_rhf_domain* rd, int32_t precision, const 
   r = ltriples_workspace_size(&S.d, precision, &S.o, &inner);
   if (r) return r;
   const size_t need = S.head + inner;
-  r = check_denominators(&S.d);   // before anything is allocated or enqueued
-  if (r) return r;
-  bool own = false;
-  if (ws == nullptr) {
-    HIPCHK(hipMalloc(&ws, need));
-    own = true;
-  } else if (ws_bytes < need) {
-    return fail(LT_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
-  }
   hipStream_t st = (hipStream_t)stream;
+  r = check_denominators(&S.d, st);   // before anything is allocated or enqueued
+  if (r) return r;
+  OwnedWs own;
+  r = get_ws(ws, ws_bytes, need, st, own);
+  if (r) return r;
   char* base = (char*)ws;
   double* t2 = (double*)base;
   double* tmp = (double*)(base + S.t2_bytes);
@@ -2337,11 +2389,6 @@ int ltriples_energy_rhf(const ltriples_rhf_domain* rd, int32_t precision, const 
   if (r == LT_OK) {
     const hipError_t e = lt::launch_rhf_combine(tmp, e_out, parts, st);
     if (e != hipSuccess) r = fail(LT_EHIP, "HIP error %s", hipGetErrorString(e));
-  }
-  if (own) {
-    hipError_t e1 = hipStreamSynchronize(st);
-    hipError_t e2 = hipFree(ws);
-    if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) return fail(LT_EHIP, "HIP error at workspace release");
   }
   return r;
 }
@@ -2408,16 +2455,12 @@ int ltriples_backward_rhf(const ltriples_rhf_domain* rd, int32_t precision, cons
   if (r) return r;
   const RhfBwd Lb = rhf_bwd_layout(rd, S.head);
   const size_t need = Lb.end + inner;
-  r = check_denominators(&S.d);   // before anything is allocated or enqueued
-  if (r) return r;
-  bool own = false;
-  if (ws == nullptr) {
-    HIPCHK(hipMalloc(&ws, need));
-    own = true;
-  } else if (ws_bytes < need) {
-    return fail(LT_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
-  }
   hipStream_t st = (hipStream_t)stream;
+  r = check_denominators(&S.d, st);   // before anything is allocated or enqueued
+  if (r) return r;
+  OwnedWs own;
+  r = get_ws(ws, ws_bytes, need, st, own);
+  if (r) return r;
   char* base = (char*)ws;
   auto D = [&](size_t off) { return (double*)(base + off); };
   const int64_t no = rd->no, nv = rd->nv, Q = rd->naux;
@@ -2473,13 +2516,7 @@ int ltriples_backward_rhf(const ltriples_rhf_domain* rd, int32_t precision, cons
     }
     return LT_OK;
   };
-  r = run();
-  if (own) {
-    hipError_t e1 = hipStreamSynchronize(st);
-    hipError_t e2 = hipFree(ws);
-    if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) return fail(LT_EHIP, "HIP error at workspace release");
-  }
-  return r;
+  return run();
 }
 
 }  // extern "C"
@@ -2562,13 +2599,9 @@ int ltriples_naf(const ltriples_naf_input* in, double eps, const ltriples_naf_ou
   if (!out || !naux_out) return fail(LT_EINVAL, "output is NULL");
   if (std::isnan(eps)) return fail(LT_EINVAL, "eps is NaN");
   hipStream_t st = (hipStream_t)stream;
-  bool own = false;
-  if (ws == nullptr) {
-    HIPCHK(hipMalloc(&ws, P.total));
-    own = true;
-  } else if (ws_bytes < P.total) {
-    return fail(LT_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, P.total);
-  }
+  OwnedWs own;
+  r = get_ws(ws, ws_bytes, P.total, st, own);
+  if (r) return r;
   char* base = (char*)ws;
   double* Pk = (double*)(base + P.oP);
   double* W = (double*)(base + P.oW);
@@ -2650,11 +2683,6 @@ done:
     const rocblas_status e2 = rocblas_destroy_handle(h);
     if (r == LT_OK && (e1 != hipSuccess || e2 != rocblas_status_success))
       r = fail(LT_EHIP, "error at rocBLAS handle release");
-  }
-  if (own) {
-    const hipError_t e1 = hipStreamSynchronize(st);
-    const hipError_t e2 = hipFree(ws);
-    if (r == LT_OK && (e1 != hipSuccess || e2 != hipSuccess)) r = fail(LT_EHIP, "HIP error at workspace release");
   }
   return r;
 }

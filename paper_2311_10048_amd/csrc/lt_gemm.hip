@@ -306,16 +306,25 @@ std::mutex g_mu;
 std::map<GKey, int> g_pick;
 
 template <typename T, int NC>
-hipError_t dispatch(const GCfg<T> (&cfg)[NC], int def, const GemmArgs<T>& g, hipStream_t s, bool tune) {
+hipError_t dispatch(const GCfg<T> (&cfg)[NC], int def, const GemmArgs<T>& g, hipStream_t s, bool tune, int force) {
   if (g.mode != 1) return cfg[def].fn(g, s);
+  if (force >= 0 && force < NC) return cfg[force].fn(g, s);
   int nlog = 0;
   while ((1 << (nlog + 1)) <= g.N) ++nlog;
   int dev = 0;
   (void)hipGetDevice(&dev);
   const GKey key{dev, (int)sizeof(T), g.ops.kind, (g.M + 31) / 32, nlog};
+  const char* fam = sizeof(T) == 8 ? "fp64" : "fp32";
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_pick.find(key);
   if (it != g_pick.end()) return cfg[it->second].fn(g, s);
+  {
+    const int c = tune_cache_get(fam, dev, (int)sizeof(T), g.ops.kind, (g.M + 31) / 32, nlog);
+    if (c >= 0 && c < NC) {
+      g_pick[key] = c;
+      return cfg[c].fn(g, s);
+    }
+  }
   // candidates: the default, then every tile whose row padding stays within a quarter
   std::vector<int> cand{def};
   for (int i = 0; i < NC; ++i) {
@@ -344,6 +353,7 @@ hipError_t dispatch(const GCfg<T> (&cfg)[NC], int def, const GemmArgs<T>& g, hip
   if (e1) (void)hipEventDestroy(e1);
   if (err != hipSuccess) return err;
   g_pick[key] = best;
+  tune_cache_put(fam, dev, (int)sizeof(T), g.ops.kind, (g.M + 31) / 32, nlog, best);
   if (getenv("LTRIPLES_LOG"))
     fprintf(stderr, "[ltriples] tuned %s contraction (kind %d, M %d, N %d): tile rows %d (default %d)\n",
             sizeof(T) == 8 ? "FP64" : "FP32", g.ops.kind, g.M, g.N, cfg[best].rows, cfg[def].rows);
@@ -355,12 +365,12 @@ bool wide_contraction(const GemmArgs<double>& g) { return g.mode == 1 && g.M > 2
 
 }  // namespace
 
-template <> hipError_t launch_gemm<float>(const GemmArgs<float>& g, hipStream_t s, bool tune) {
-  return dispatch(kCfg32, wide_contraction(g) ? 1 : default32(g.M), g, s, tune);   // kCfg32[1]: 64 rows
+template <> hipError_t launch_gemm<float>(const GemmArgs<float>& g, hipStream_t s, bool tune, int force) {
+  return dispatch(kCfg32, wide_contraction(g) ? 1 : default32(g.M), g, s, tune, force);   // kCfg32[1]: 64 rows
 }
 
-template <> hipError_t launch_gemm<double>(const GemmArgs<double>& g, hipStream_t s, bool tune) {
-  return dispatch(kCfg64, wide_contraction(g) ? 1 : default64(g.M), g, s, tune);   // kCfg64[1]: 64 rows
+template <> hipError_t launch_gemm<double>(const GemmArgs<double>& g, hipStream_t s, bool tune, int force) {
+  return dispatch(kCfg64, wide_contraction(g) ? 1 : default64(g.M), g, s, tune, force);   // kCfg64[1]: 64 rows
 }
 
 void reset_gemm_tuning() {

@@ -367,7 +367,8 @@ hipError_t run_cfg(int c, const GemmArgs16& g, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_gemm_bf16(const GemmArgs16& g, hipStream_t s, bool tune) {
+hipError_t launch_gemm_bf16(const GemmArgs16& g, hipStream_t s, bool tune, int force) {
+  if (force >= 0 && force < kNCfg) return run_cfg(force, g, s);
   const int need = (g.M + 31) / 32;
   int nlog = 0;
   while ((1 << (nlog + 1)) <= g.N) ++nlog;
@@ -377,6 +378,13 @@ hipError_t launch_gemm_bf16(const GemmArgs16& g, hipStream_t s, bool tune) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tuned.find(key);
   if (it != g_tuned.end()) return run_cfg(it->second, g, s);
+  {
+    const int c = tune_cache_get("bf16", dev, g.nprod, g.kind, need, nlog);
+    if (c >= 0 && c < kNCfg) {
+      g_tuned[key] = c;
+      return run_cfg(c, g, s);
+    }
+  }
   const std::vector<int> cand = candidates(need);
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (!tune || cand.size() < 2 || hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
@@ -402,6 +410,7 @@ hipError_t launch_gemm_bf16(const GemmArgs16& g, hipStream_t s, bool tune) {
   if (e1) (void)hipEventDestroy(e1);
   if (err != hipSuccess) return err;
   g_tuned[key] = best;
+  tune_cache_put("bf16", dev, g.nprod, g.kind, need, nlog, best);
   if (getenv("LTRIPLES_LOG"))
     fprintf(stderr, "[ltriples] tuned BF16 contraction (kind %d, M %d, N %d, %d products): tile %dx%d rows %d\n",
             g.kind, g.M, g.N, g.nprod, kCfg16[best].mbw, kCfg16[best].nbw, cfg_rows(best));

@@ -139,8 +139,9 @@ struct GemmArgs16 {
 // kind, 32-row blocks, log2 N) time every candidate tile configuration on
 // this launch and keep the fastest for the class (not under graph capture;
 // waits for the stream).  Without it the class keeps a tuned choice if one
-// exists, else the default table.
-hipError_t launch_gemm_bf16(const GemmArgs16& g, hipStream_t s, bool tune = false);
+// exists (in this process or in the tuning cache file), else the default
+// table.  `force` >= 0 runs configuration `force` of the table instead.
+hipError_t launch_gemm_bf16(const GemmArgs16& g, hipStream_t s, bool tune = false, int force = -1);
 void reset_gemm_bf16_tuning();
 // tab[n][s] = descriptor of segment s of item n (ops.kind, ops.items), s < 6;
 // unused slots get K = 0.
@@ -185,9 +186,17 @@ template <typename T> struct EpiMixed {
 // ---------------------------------------------------------------------------
 // Launchers (all asynchronous on `s`)
 // ---------------------------------------------------------------------------
-// `tune`: as launch_gemm_bf16, for the triplet contractions (mode 1).
-template <typename T> hipError_t launch_gemm(const GemmArgs<T>& g, hipStream_t s, bool tune = false);
+// `tune`, `force`: as launch_gemm_bf16, for the triplet contractions (mode 1).
+template <typename T> hipError_t launch_gemm(const GemmArgs<T>& g, hipStream_t s, bool tune = false,
+                                             int force = -1);
 void reset_gemm_tuning();
+
+// Tile choices persisted across processes in the JSON file named by the
+// environment variable LTRIPLES_TUNE_CACHE (no file: both calls do nothing).
+// Entries are keyed by kernel family, the device's architecture name and
+// four integers of the shape class.  get returns -1 when absent.
+int tune_cache_get(const char* family, int dev, int k0, int k1, int k2, int k3);
+void tune_cache_put(const char* family, int dev, int k0, int k1, int k2, int k3, int cfg);
 
 // out[d0][d1][d2][d3] (out strides os0..os2, unit stride in d3)
 //   = in[d0*s0 + d1*s1 + d2*s2 + d3*s3] - (in2 ? in2[d0*u0 + ... + d3*u3] : 0)
@@ -217,6 +226,14 @@ hipError_t launch_reduce_final(const double* e_items, const int32_t* order,
                                const int32_t* first, const int32_t* count,
                                double* parts, double* e_out, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
+// flag[0] = 1 if any element of the listed arrays is NaN or infinite (flag
+// zeroed beforehand by the caller; untouched otherwise)
+struct FiniteScan {
+  const double* p[17];
+  int64_t n[17];
+  int32_t narr;
+};
+hipError_t launch_scan_finite(const FiniteScan& a, int32_t* flag, hipStream_t s);
 // n 32-bit words of zeros
 hipError_t launch_zero32(void* p, int64_t n, hipStream_t s);
 

@@ -179,4 +179,24 @@ hipError_t launch_zero(double* p, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Grid-stride pass over each array in turn; any thread that meets a NaN or an
+// infinity stores 1 to the flag (every writer stores the same value).
+__global__ __launch_bounds__(256) void k_scan_finite(FiniteScan a, int32_t* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int r = 0; r < a.narr; ++r) {
+    const double* p = a.p[r];
+    const int64_t n = a.n[r];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+      bad |= !isfinite(p[e]);
+  }
+  if (bad) flag[0] = 1;
+}
+
+hipError_t launch_scan_finite(const FiniteScan& a, int32_t* flag, hipStream_t s) {
+  if (a.narr <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan_finite, dim3(2048), dim3(256), 0, s, a, flag);
+  return hipGetLastError();
+}
+
 }  // namespace lt

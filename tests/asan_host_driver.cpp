@@ -107,6 +107,26 @@ int main() {
   ni.no_a = 3; ni.nv_a = 5; ni.no_b = 2; ni.nv_b = 6; ni.nx = 20;
   ni.Ja = ni.Jb = placeholder;
   expect(ltriples_naf_workspace_size(&ni, &ws), LT_OK, "naf workspace");
+  // option fields: forced tiles 0..8 per output layout, check_finite 0/1,
+  // deterministic accepted with any value; the batched call checks them too
+  {
+    const int32_t sh[5] = {5, 4, 30, 31, 120};
+    ltriples_domain d = fake_domain(sh, placeholder);
+    ltriples_options o{};
+    o.tile_override[0] = 8; o.tile_override[1] = 1; o.tile_override[2] = 0;
+    o.deterministic = 7;
+    o.check_finite = 1;
+    expect(ltriples_validate(&d, LT_BF16X3, &o), LT_OK, "forced tiles in range");
+    expect(ltriples_plan_check(&d, LT_FP64, &o, 0), LT_OK, "plan with forced tiles");
+    o.tile_override[2] = 9;
+    expect(ltriples_validate(&d, LT_FP32, &o), LT_EINVAL, "forced tile out of range");
+    expect(ltriples_workspace_size_batched(&d, 1, LT_FP32, &o, &ws), LT_EINVAL, "batched forced tile out of range");
+    o.tile_override[2] = -1;
+    expect(ltriples_validate(&d, LT_FP32, &o), LT_EINVAL, "negative forced tile");
+    o.tile_override[2] = 0;
+    o.check_finite = 2;
+    expect(ltriples_validate(&d, LT_FP32, &o), LT_EINVAL, "check_finite not 0/1");
+  }
   // error paths
   expect(ltriples_validate(nullptr, LT_FP64, nullptr), LT_EINVAL, "null domain");
   expect(ltriples_rhf_workspace_size(nullptr, LT_FP64, nullptr, &ws), LT_EINVAL, "null rhf");

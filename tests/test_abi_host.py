@@ -23,7 +23,7 @@ def _lib():
 
 def _declared():
     src = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(ltriples_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(ltriples_\w+)\s*\(", src, re.M)))
 
 
 def test_exports_every_declared_symbol():
@@ -297,7 +297,9 @@ def test_ctypes_layouts_match_the_header(tmp_path):
         pytest.skip("no C compiler")
     structs = {
         "ltriples_domain": (lt.Domain, ["noa", "t1a", "fov_b"]),
-        "ltriples_options": (lt.Options, ["items", "e_items", "stats", "graph", "build_chunk_mib", "autotune"]),
+        "ltriples_options": (lt.Options, ["workspace_budget", "items", "e_items", "stats", "graph",
+                                          "build_chunk_mib", "autotune", "deterministic", "check_finite",
+                                          "tile_override"]),
         "ltriples_stats": (lt.Stats, ["n_items"]),
         "ltriples_domain_grad": (lt.DomainGrad, ["t1a", "fov_b", "eo_a", "ev_b"]),
         "ltriples_rhf_domain": (lt.RhfDomain, ["no", "t1", "fov"]),
@@ -321,3 +323,37 @@ def test_ctypes_layouts_match_the_header(tmp_path):
         assert int(out[name]) == ctypes.sizeof(cls), name
         for f in fields:
             assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
+
+
+def test_option_fields_validated():
+    """tile_override takes 0 (automatic) or a configuration 1..8 per output
+    layout; check_finite is 0 or 1; deterministic is accepted with any value
+    (every call is deterministic)."""
+    _lib()
+    d = _fake_domain((4, 3, 10, 11, 20))
+    o, _ = lt.make_options(tile_override=(8, 1, 0), check_finite=True)
+    assert lt.ltriples_validate(d, lt.LT_BF16X3, o) == lt.LT_OK
+    o.deterministic = 0
+    assert lt.ltriples_validate(d, lt.LT_FP64, o) == lt.LT_OK
+    for bad in ((9, 0, 0), (0, -1, 0), (0, 0, 100)):
+        o, _ = lt.make_options(tile_override=bad)
+        assert lt.ltriples_validate(d, lt.LT_FP32, o) == lt.LT_EINVAL
+        assert "tile_override" in lt.ltriples_last_error()
+    o, _ = lt.make_options()
+    o.check_finite = 3
+    assert lt.ltriples_validate(d, lt.LT_FP32, o) == lt.LT_EINVAL
+    lib = lt.load_library()
+    n = ctypes.c_size_t(0)
+    o, _ = lt.make_options(tile_override=(0, 0, 9))
+    assert lib.ltriples_workspace_size_batched(_fake_array([(4, 3, 10, 11, 20)]), 1, lt.LT_FP32, ctypes.byref(o),
+                                               ctypes.byref(n)) == lt.LT_EINVAL
+
+
+def test_workspace_budget_bounds_the_batch_scratch():
+    """The per-batch scratch follows options.workspace_budget: a smaller
+    budget gives a smaller workspace for the same domain."""
+    _lib()
+    d = _fake_domain((10, 9, 80, 81, 320))
+    big = lt.ltriples_workspace_size(d, lt.LT_FP32, lt.make_options()[0])
+    small = lt.ltriples_workspace_size(d, lt.LT_FP32, lt.make_options(workspace_budget=64 << 20)[0])
+    assert small < big

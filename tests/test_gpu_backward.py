@@ -109,15 +109,104 @@ def test_backward_workspace_garbage_never_read():
         assert np.array_equal(outs[0][k], outs[1][k]), k
 
 
-def test_backward_sampled_items_gradient_workload_fp64():
+_GRAD_REF = {}
+
+
+def _grad_workload_ref():
+    """The gradient workload, a sampled item list and the oracle gradient of
+    E(items) (computed once for the tests below)."""
+    if not _GRAD_REF:
+        dom = synth.config_domain("grad")
+        items = synth.sample_items(dom.noa, dom.nob, 1, seed=77)
+        _, ref = ograd.energy_and_grad(dom, items=items, fock=True)
+        _GRAD_REF.update(dom=dom, items=items, ref=ref)
+    return _GRAD_REF["dom"], _GRAD_REF["items"], _GRAD_REF["ref"]
+
+
+@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32])
+def test_backward_sampled_items_gradient_workload(prec):
     """Full-size gradient workload, restricted to a sampled item list: the
-    gradient of E(items) against the oracle's gradient of the same items."""
-    dom = synth.config_domain("grad")
-    items = synth.sample_items(dom.noa, dom.nob, 1, seed=77)
-    print(f"[backward] grad workload {dom.dims}, {len(items)} sampled items", flush=True)
-    _, ref = ograd.energy_and_grad(dom, items=items, fock=True)
-    g = _gpu_grad(dom, lt.LT_FP64, items=items)
-    _compare(g, ref, 1e-10, "grad-sampled")
+    gradient of E(items) against the oracle's gradient of the same items, at
+    the FP64 (1e-10) and FP32 (1e-5) bars."""
+    dom, items, ref = _grad_workload_ref()
+    print(f"[backward] grad workload {dom.dims}, {len(items)} sampled items, prec={prec}", flush=True)
+    g = _gpu_grad(dom, prec, items=items)
+    _compare(g, ref, TOL[prec], "grad-sampled")
+
+
+def test_backward_central_differences_gradient_workload():
+    """The gradient workload (20,18,160,162,640): 50 random entries over T1,
+    T2 and the DF factors of both spins, central differences with h = 1e-5
+    of the FP64 GPU energy of a sampled item list (milliseconds per energy)
+    against ltriples_backward of the same items.  The amplitude entries are
+    drawn among the occupied orbitals the items contain (other entries have
+    zero derivative).  Bar: |FD - g| <= 1e-5 |g| + 100 eps |E| / h (E is
+    quadratic in T, so the difference is exact up to rounding; quartic in B,
+    with a truncation error of relative size (h / 0.05)^2).  Each difference
+    moves every symmetry image of the entry (4x for t2aa/t2bb, 2x for
+    off-diagonal Boo/Bvv)."""
+    import torch
+    dom, items, _ = _grad_workload_ref()
+    t = to_device(dom)
+    d = lt.make_domain(dom.dims, t)
+    o, _ = lt.make_options(items=items)
+    ws = torch.empty(max(lt.ltriples_workspace_size(d, lt.LT_FP64, o),
+                         lt.ltriples_backward_workspace_size(d, lt.LT_FP64, o)), dtype=torch.uint8, device="cuda")
+    g = _gpu_grad(dom, lt.LT_FP64, tensors=t, items=items, workspace=ws)
+    e0, _ = lt.ltriples_energy(t, dom.dims, lt.LT_FP64, items=items, workspace=ws)
+    torch.cuda.synchronize()
+    E0 = float(e0.item())
+    # occupied orbitals of each spin in the items: (0, i, j, k) aaa, (1, i, j, K) aab,
+    # (2, I, J, k) abb, (3, I, J, K) bbb
+    alpha_slots = {0: (1, 2, 3), 1: (1, 2), 2: (3,), 3: ()}
+    beta_slots = {0: (), 1: (3,), 2: (1, 2), 3: (1, 2, 3)}
+    it = np.asarray(items)
+    occ = {"a": sorted({int(r[c]) for r in it for c in alpha_slots[int(r[0])]}),
+           "b": sorted({int(r[c]) for r in it for c in beta_slots[int(r[0])]})}
+    rng = np.random.default_rng(3003)
+    h, eps = 1e-5, np.finfo(np.float64).eps
+    plan = ["t1a"] * 4 + ["t1b"] * 4 + ["t2aa"] * 7 + ["t2bb"] * 7 + ["t2ab"] * 7 + \
+           ["Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b"] * 3 + ["Bov_a", "Bvv_b", "Bvv_a"]
+    assert len(plan) == 50
+    print(f"[backward] central differences on {len(plan)} entries of {dom.dims}", flush=True)
+    for k in plan:
+        x = getattr(dom, k)
+        if k in ("t1a", "t1b"):
+            idx = (int(rng.choice(occ[k[-1]])), int(rng.integers(0, x.shape[1])))
+        elif k in ("t2aa", "t2bb"):
+            o_ = occ[k[-1]]
+            i = int(rng.choice(o_))
+            j = int(rng.integers(0, x.shape[0]))
+            while j == i:
+                j = int(rng.integers(0, x.shape[0]))
+            a, b = (int(y) for y in rng.choice(x.shape[2], size=2, replace=False))
+            idx = (i, j, a, b)
+        elif k == "t2ab":
+            idx = (int(rng.choice(occ["a"])), int(rng.choice(occ["b"])), int(rng.integers(0, x.shape[2])),
+                   int(rng.integers(0, x.shape[3])))
+        else:
+            idx = tuple(int(rng.integers(0, m)) for m in x.shape)
+        images, mult = [(idx, 1.0)], 1.0
+        if k in ("t2aa", "t2bb"):
+            i, j, a, b = idx
+            images = [((i, j, a, b), 1.0), ((j, i, a, b), -1.0), ((i, j, b, a), -1.0), ((j, i, b, a), 1.0)]
+            mult = 4.0
+        elif k in ("Boo_a", "Boo_b", "Bvv_a", "Bvv_b") and idx[1] != idx[2]:
+            q, p_, r = idx
+            images, mult = [((q, p_, r), 1.0), ((q, r, p_), 1.0)], 2.0
+        es = []
+        for sgn in (1.0, -1.0):
+            tp = dict(t)
+            y = t[k].clone()
+            for im, w in images:
+                y[im] += sgn * w * h
+            tp[k] = y
+            e, _ = lt.ltriples_energy(tp, dom.dims, lt.LT_FP64, items=items, workspace=ws)
+            torch.cuda.synchronize()
+            es.append(float(e.item()))
+        fd = (es[0] - es[1]) / (2 * h)
+        want = mult * g[k][idx]
+        assert abs(fd - want) <= 1e-5 * abs(want) + 100 * eps * abs(E0) / h, (k, idx, fd, want, E0)
 
 
 def test_backward_directional_derivative_gradient_workload():

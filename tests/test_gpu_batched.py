@@ -129,3 +129,107 @@ def test_batch_config_smallest_domains_bf16x3():
         for k in range(len(items)):
             r = ref[k].sum()
             assert abs(ei[k].sum() - r) <= 1e-10 * max(1.0, abs(r)), (n, items[k], ei[k], ref[k])
+
+
+def test_batch_set_largest_and_smallest_domains_bf16x3():
+    """The two largest and two smallest domains (by flop count) of the
+    64-domain set in one BF16X3 batched call, eager and as a captured graph:
+    every domain's energy and parts bitwise equal to the single-domain call;
+    sampled triplets of the largest domain (one per block) against the FP64
+    CPU oracle through the single-domain item-list call."""
+    import torch
+    lt.ltriples_graph_reset()
+    shapes = synth.batch_shapes()
+    F = []
+    for n, s in enumerate(shapes):
+        d = lt.make_domain(s, {f: (1 << 40) for f in lt.ARRAY_FIELDS})   # sizes only, never dereferenced
+        F.append((lt.ltriples_flops(d)[0], n))
+    F.sort()
+    pick = [F[-1][1], F[0][1], F[-2][1], F[1][1]]        # largest first, then alternating
+    doms = [synth.batch_domain(n, shapes) for n in pick]
+    dims = [d.dims for d in doms]
+    print(f"[batched] set domains {pick}: {dims}", flush=True)
+    tens = [to_device(d) for d in doms]
+    prec = lt.LT_BF16X3
+    opts, _ = lt.make_options()
+    need = lt.ltriples_workspace_size_batched(dims, tens, prec, opts)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    out = (torch.empty(len(doms), dtype=torch.float64, device="cuda"),
+           torch.empty(len(doms), 4, 3, dtype=torch.float64, device="cuda"))
+    e_eager, p_eager = lt.ltriples_energy_batched(tens, dims, prec, workspace=ws)
+    torch.cuda.synchronize()
+    e_eager, p_eager = e_eager.cpu().numpy(), p_eager.cpu().numpy()
+    print("[batched] eager done", flush=True)
+    out[0].fill_(float("nan"))
+    lt.ltriples_energy_batched(tens, dims, prec, graph=True, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    e_graph, p_graph = out[0].cpu().numpy().copy(), out[1].cpu().numpy().copy()
+    lt.ltriples_graph_reset()
+    print("[batched] graph done", flush=True)
+    assert np.array_equal(e_eager, e_graph) and np.array_equal(p_eager, p_graph)
+    for n, d in enumerate(doms):
+        e1, p1 = lt.ltriples_energy(tens[n], d.dims, prec, workspace=ws)
+        torch.cuda.synchronize()
+        assert e_eager[n] == float(e1.item()), (pick[n], e_eager[n], float(e1.item()))
+        assert np.array_equal(p_eager[n], p1.cpu().numpy()), pick[n]
+    print("[batched] single-domain calls done", flush=True)
+    big = doms[0]
+    items = synth.sample_items(big.noa, big.nob, 1, seed=606)
+    ei = torch.full((len(items), 3), float("nan"), dtype=torch.float64, device="cuda")
+    lt.ltriples_energy(tens[0], big.dims, prec, items=items, e_items=ei, workspace=ws)
+    torch.cuda.synchronize()
+    ei = ei.cpu().numpy()
+    del ws, tens
+    torch.cuda.empty_cache()
+    ref = blocks.energy(big, items=items, return_items=True)["items"]
+    for n in range(len(items)):
+        r = ref[n].sum()
+        assert abs(ei[n].sum() - r) <= TOL_E[prec] * max(1.0, abs(r)), (items[n], ei[n], ref[n])
+
+
+def test_batched_autotune_reaches_the_contractions(capfd, monkeypatch):
+    """options.autotune set on a batched call tunes the contraction tiles of
+    its domains (the tuner logs each choice), and changes no result bit."""
+    import torch
+    monkeypatch.setenv("LTRIPLES_LOG", "1")
+    lt.ltriples_autotune_reset()
+    doms = _doms()[:3]
+    tens = [to_device(d) for d in doms]
+    dims = [d.dims for d in doms]
+    capfd.readouterr()
+    e1, p1 = lt.ltriples_energy_batched(tens, dims, lt.LT_BF16X3, autotune=True)
+    torch.cuda.synchronize()
+    err = capfd.readouterr().err
+    assert "tuned BF16 contraction" in err, err[-2000:]
+    lt.ltriples_autotune_reset()
+    e0, p0 = lt.ltriples_energy_batched(tens, dims, lt.LT_BF16X3)
+    torch.cuda.synchronize()
+    assert torch.equal(e0, e1) and torch.equal(p0, p1)
+
+
+def test_graph_key_covers_build_chunks():
+    """Two graph calls on the same workspace and outputs with different
+    build_chunk_mib (a different plan: other staging and table offsets)
+    capture two graphs; each gives bitwise the eager result."""
+    import torch
+    lt.ltriples_graph_reset()
+    doms = _doms()[:3]
+    dims = [d.dims for d in doms]
+    tens = [to_device(d) for d in doms]
+    prec = lt.LT_FP32
+    need = max(lt.ltriples_workspace_size_batched(dims, tens, prec, lt.make_options(build_chunk_mib=c)[0])
+               for c in (0, 1))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    out = (torch.empty(len(doms), dtype=torch.float64, device="cuda"),
+           torch.empty(len(doms), 4, 3, dtype=torch.float64, device="cuda"))
+    ref_e, ref_p = lt.ltriples_energy_batched(tens, dims, prec)
+    torch.cuda.synchronize()
+    for chunk in (0, 1, 0, 1):
+        out[0].fill_(float("nan"))
+        lt.ltriples_energy_batched(tens, dims, prec, graph=True, workspace=ws, out=out, build_chunk_mib=chunk)
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], ref_e) and torch.equal(out[1], ref_p), chunk
+        # eager work on the same workspace between the graph calls
+        lt.ltriples_energy(tens[1], dims[1], prec, workspace=ws, build_chunk_mib=1 - chunk)
+        torch.cuda.synchronize()
+    lt.ltriples_graph_reset()

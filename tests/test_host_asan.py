@@ -13,8 +13,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2311_10048_amd", "csrc")
-SOURCES = ["lt_api.hip", "lt_gemm.hip", "lt_gemm_bf16.hip", "lt_rgemm.hip", "lt_prep.hip", "lt_epilogue.hip",
-           "lt_bwd.hip"]
+from paper_2311_10048_amd.build import SOURCES   # the library's own source list
 
 
 def test_host_code_under_address_sanitizer():
