@@ -21,6 +21,11 @@ Modules
            convention for symmetric inputs).
   naf      natural auxiliary functions: the spin-averaged W of eq. naf_w,
            its eigenvectors above a threshold, and the compressed factors.
+  central  the (T) share of one central LMO (eq. local_pt): the central
+           occupied index rotated to a vector c, the energy denominator
+           replaced by a Laplace quadrature (eq. laplace_transform), or its
+           exact-denominator limit.
+  laplace  the Laplace quadrature itself (minimax exponential sums of 1/x).
 
 What the oracle computes (the paper's eq. cim_pt_energy, summed over the
 central index; the paper defers the definitions of t and W to the standard
@@ -43,6 +48,14 @@ Gradient pins (tests/test_oracle_grad.py): the transcription's energy
 equals blocks; <dE/dx, d> equals the exact 3-point (T) / 5-point (B) central
 stencil of blocks and of the spin-orbital brute force along random
 directions; the symmetry-image convention of the projected gradient.
+Central-share pins (tests/test_oracle_central.py): with exact denominators a
+unit vector c = e_i gives one third of the per-item energies of blocks over
+the items containing i; the shares of any orthonormal basis of both spins
+add up to E(T) (exact) or to the element-wise Laplace energy (any
+quadrature); the Laplace share lies within the quadrature's error bound of
+the exact one, and the Laplace energy approaches E(T) as points are added;
+planted mistakes are caught.  Quadrature pins: the error falls with every
+added point and equioscillates where the exchange converged.
 NAF pins (tests/test_oracle_naf.py): exact four-index integrals without
 truncation, discarded weight equal to the discarded eigenvalues, trace of W,
 the closed-shell limit, the rank of exactly low-rank input.

@@ -98,7 +98,10 @@ def _P_a_bc(z):
     return z - z.transpose(1, 0, 2) - z.transpose(2, 1, 0)
 
 
-def _item_same_spin(ints, s, i, j, k):
+def same_spin_cubes(ints, s, i, j, k):
+    """W, V_t1, V_f and D of the same-spin triple (i, j, k) of spin s over the
+    full virtual cube [a][b][c], for any order of i, j, k (W and V are
+    antisymmetric in the occupied indices, so a repeated index gives zero)."""
     sp = ints.sp[s]
     t1, t2, f = sp.t1, sp.t2, sp.f
     nv = t1.shape[1]
@@ -136,12 +139,19 @@ def _item_same_spin(ints, s, i, j, k):
     vf = _P_a_bc(vf_i - vf_j - vf_k)
     ev = sp.ev
     d = (sp.eo[i] + sp.eo[j] + sp.eo[k]) - ev[:, None, None] - ev[None, :, None] - ev[None, None, :]
+    return w, vt, vf, d
+
+
+def _item_same_spin(ints, s, i, j, k):
+    w, vt, vf, d = same_spin_cubes(ints, s, i, j, k)
     wd = w / d
     return np.array([np.sum(wd * w), np.sum(wd * vt), np.sum(wd * vf)]) / 6.0
 
 
-def _item_mixed(ints, dom, s, i, j, K):
-    """Mixed block with the same-spin pair of spin s and the odd index of spin 1-s."""
+def mixed_cubes(ints, dom, s, i, j, K):
+    """W, V_t1, V_f and D of the mixed triple with the same-spin pair (i, j)
+    of spin s and the odd index K of spin 1-s, over the full virtual cube
+    [a][b][C], for either order of i, j (antisymmetric in them)."""
     t = 1 - s
     ss, st = ints.sp[s], ints.sp[t]
 
@@ -217,6 +227,12 @@ def _item_mixed(ints, dom, s, i, j, K):
 
     d = ((ss.eo[i] + ss.eo[j] + st.eo[K]) - ss.ev[:, None, None] - ss.ev[None, :, None]
          - st.ev[None, None, :])
+    return w, vt, vf, d
+
+
+def _item_mixed(ints, dom, s, i, j, K):
+    """Mixed block with the same-spin pair of spin s and the odd index of spin 1-s."""
+    w, vt, vf, d = mixed_cubes(ints, dom, s, i, j, K)
     wd = w / d
     return np.array([np.sum(wd * w), np.sum(wd * vt), np.sum(wd * vf)]) / 2.0
 
