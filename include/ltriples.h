@@ -224,6 +224,29 @@ int ltriples_energy(const ltriples_domain* d, int32_t precision,
                     const ltriples_options* o, double* e_out, double* parts,
                     void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): E(T) of one
+ * domain exactly as ltriples_energy computes it (same kernels, bitwise the
+ * same result), with the whole workspace in a fixed device array that the
+ * library holds on each GPU it runs on, from the first call there until the
+ * process ends (ltriples_noalloc_capacity() bytes, 256 MiB).  The call makes
+ * no hipMalloc, hipFree or other allocating call.  When the domain's plan
+ * does not fit the array, it is refitted with smaller item batches and build
+ * chunks (which change no result bit); a domain that does not fit even with
+ * single-item batches gives LT_EWORKSPACE before anything is enqueued.
+ * options.stats and options.autotune must be unset (LT_EINVAL); the other
+ * options and every error code are as ltriples_energy, and so are the host
+ * waits.  All calls on one GPU share its array, which keeps the last call's
+ * contents (every word a call reads is written by that call first): calls
+ * that overlap on one GPU (on different streams or from different threads)
+ * race on it and must be serialised by the caller. */
+int ltriples_energy_noalloc(const ltriples_domain* d, int32_t precision,
+                            const ltriples_options* o, double* e_out,
+                            double* parts, void* stream);
+
+/* Bytes of the fixed per-device array of ltriples_energy_noalloc. */
+size_t ltriples_noalloc_capacity(void);
+
 /* Gradient outputs of ltriples_backward: caller-owned device FP64 buffers in
  * the layouts of the corresponding ltriples_domain inputs.  A NULL field is
  * not written.  Gradients of inputs that carry a symmetry are returned

@@ -133,6 +133,10 @@ def load_library(path: Optional[str] = None):
     lib.ltriples_flops.argtypes = [Dp, Op, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.ltriples_energy.argtypes = [Dp, ctypes.c_int32, Op, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.ltriples_energy_noalloc.argtypes = [Dp, ctypes.c_int32, Op, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p]
+    lib.ltriples_noalloc_capacity.argtypes = []
+    lib.ltriples_noalloc_capacity.restype = ctypes.c_size_t
     lib.ltriples_workspace_size_batched.argtypes = [Dp, ctypes.c_int32, ctypes.c_int32, Op,
                                                     ctypes.POINTER(ctypes.c_size_t)]
     lib.ltriples_energy_batched.argtypes = [Dp, ctypes.c_int32, ctypes.c_int32, Op, ctypes.c_void_p,
@@ -159,6 +163,7 @@ def load_library(path: Optional[str] = None):
     lib.ltriples_last_error.restype = ctypes.c_char_p
     lib.ltriples_version.restype = ctypes.c_char_p
     for f in ("ltriples_validate", "ltriples_workspace_size", "ltriples_flops", "ltriples_energy",
+              "ltriples_energy_noalloc",
               "ltriples_workspace_size_batched", "ltriples_energy_batched", "ltriples_graph_reset",
               "ltriples_backward_workspace_size", "ltriples_backward", "ltriples_plan_check",
               "ltriples_rhf_workspace_size", "ltriples_rhf_flops", "ltriples_energy_rhf",
@@ -350,6 +355,44 @@ def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP3
                                e.data_ptr(), parts.data_ptr(), workspace.data_ptr(),
                                workspace.numel(), st.cuda_stream)
     _check(code)
+    del keep
+    return e, parts
+
+
+def ltriples_noalloc_capacity() -> int:
+    """Bytes of the fixed per-device workspace of ltriples_energy_noalloc."""
+    return int(load_library().ltriples_noalloc_capacity())
+
+
+def ltriples_energy_noalloc(tensors: Mapping[str, object], dims, precision: int = LT_FP32, items=None,
+                            e_items=None, out=None, stream=None, workspace_budget: int = 0, batch_items: int = 0,
+                            build_chunk_mib: int = 0, check_finite: bool = False, tile_override=None):
+    """E(T) of one domain through the no-allocation entry point: the library
+    uses its fixed per-device workspace and allocates nothing.  `out` may
+    supply the (e [1], parts [4, 3]) float64 device tensors (otherwise they
+    are allocated here, by torch, before the call).  Returns (e, parts)."""
+    import torch
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    dom = make_domain(dims, tensors)
+    opts, keep = make_options(items, e_items, workspace_budget, batch_items, None, build_chunk_mib, False,
+                              check_finite, tile_override)
+    if e_items is not None and not isinstance(e_items, int):
+        try:
+            n_it = ltriples_flops(dom, opts)[1]
+        except LtError:
+            n_it = None
+        if n_it is not None:
+            check_array("e_items", e_items, 3 * n_it)
+    dev = _device_of(tensors)
+    if out is None:
+        out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty(4, 3, dtype=torch.float64, device=dev))
+    e, parts = out
+    check_array("e", e, 1)
+    check_array("parts", parts, 12)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    _check(load_library().ltriples_energy_noalloc(ctypes.byref(dom), int(precision), ctypes.byref(opts),
+                                                  e.data_ptr(), parts.data_ptr(), st.cuda_stream))
     del keep
     return e, parts
 

@@ -1748,23 +1748,75 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
   return LT_OK;
 }
 
-// Body of ltriples_energy.
+// Scratch of ltriples_energy_noalloc: the whole workspace of such a call
+// (operand layouts, integral slabs, per-batch intermediates, item tables).
+// One copy per device, placed when the library's code object is loaded on
+// it and held until the process ends.  Host code never uses the symbol's
+// name as an address: each device's copy is found once with
+// hipGetSymbolAddress (noalloc_scratch) and that pointer is passed on.
+constexpr size_t kNoAllocBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // per device index
+
+// This device's copy of `scratch` (looked up on the first call on it).
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(LT_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LT_OK;
+}
+
+// Shared body of ltriples_energy and ltriples_energy_noalloc.  With
+// `noalloc` the workspace is this device's `scratch`: the plan is refitted to
+// it with smaller item batches and build chunks when needed (results are
+// bitwise the same for any batching and chunking), and nothing is allocated
+// (options.stats and options.autotune, which create HIP events, are refused).
 int energy_call(const ltriples_domain* d, int32_t precision, const ltriples_options* o, double* e_out,
-                double* parts, void* ws, size_t ws_bytes, hipStream_t st) {
+                double* parts, void* ws, size_t ws_bytes, hipStream_t st, bool noalloc) {
   int r = validate(d, precision, o);
   if (r) return r;
   if (!e_out) return fail(LT_EINVAL, "e_out is NULL");
+  if (noalloc && o && (o->stats || o->autotune))
+    return fail(LT_EINVAL, "the no-allocation entry point takes no stats and no autotuning");
   const Dims D = dims_of(d);
   ltriples_options oo = o ? *o : ltriples_options{};
   ItemLists L;
   build_items(D, &oo, L);
   Plan P;
   plan_domain(d, precision, &oo, L, P);
+  if (noalloc) {
+    static const int64_t budgets_mib[] = {128, 64, 32, 16, 8, 4, 2, 1};
+    for (int k = 0; P.total > kNoAllocBytes && k < (int)(sizeof(budgets_mib) / sizeof(budgets_mib[0])); ++k) {
+      oo.workspace_budget = (size_t)budgets_mib[k] << 20;
+      oo.build_chunk_mib = (int32_t)std::min<int64_t>(16, budgets_mib[k]);
+      P = Plan{};
+      plan_domain(d, precision, &oo, L, P);
+    }
+    if (P.total > kNoAllocBytes)
+      return fail(LT_EWORKSPACE, "domain needs %zu bytes of workspace even in single-item batches; the "
+                  "no-allocation entry point has %zu", P.total, kNoAllocBytes);
+  }
   r = check_denominators(d, st);
   if (r) return r;
   log_plan(P);
   r = check_plan(P);
   if (r) return r;
+  if (noalloc) {
+    r = noalloc_scratch(&ws);
+    if (r) return r;
+    ws_bytes = kNoAllocBytes;
+  }
   OwnedWs own;
   r = get_ws(ws, ws_bytes, P.total, st, own);
   if (r) return r;
@@ -1847,8 +1899,16 @@ int ltriples_flops(const ltriples_domain* d, const ltriples_options* o, double* 
 int ltriples_energy(const ltriples_domain* d, int32_t precision, const ltriples_options* o, double* e_out,
                     double* parts, void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
-  return energy_call(d, precision, o, e_out, parts, ws, ws_bytes, (hipStream_t)stream);
+  return energy_call(d, precision, o, e_out, parts, ws, ws_bytes, (hipStream_t)stream, false);
 }
+
+int ltriples_energy_noalloc(const ltriples_domain* d, int32_t precision, const ltriples_options* o,
+                            double* e_out, double* parts, void* stream) {
+  g_err.clear();
+  return energy_call(d, precision, o, e_out, parts, nullptr, 0, (hipStream_t)stream, true);
+}
+
+size_t ltriples_noalloc_capacity(void) { return kNoAllocBytes; }
 
 // ---------------------------------------------------------------------------
 // Adjoint entry points
