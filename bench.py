@@ -171,11 +171,13 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "fp64", "bf16x3", "bf16"])
-    ap.add_argument("--workload", default="lno", choices=["tiny", "lno", "grad", "large", "batch", "rhf", "naf"])
-    ap.add_argument("--fp64-sample", type=int, default=48, help="items per block for the FP64 GPU comparison")
+    ap.add_argument("--workload", default="lno",
+                    choices=["tiny", "lno", "grad", "large", "batch", "rhf", "naf", "central"])
+    ap.add_argument("--fp64-sample", type=int, default=24, help="items per block for the FP64 GPU comparison")
     ap.add_argument("--cpu-sample", type=int, default=3, help="items per block for the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--backward-fp64", action="store_true", help="also time the FP64 adjoint in the backward leg")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: tile shapes of the contraction kernels tuned during the warmup step (results unchanged)")
     ap.add_argument("--sample-items", type=int, default=0, help="profiling aid: K sampled triplets per block")
@@ -215,6 +217,9 @@ def main():
         return
     if args.workload == "naf":
         run_naf(args, lt, synth, torch)
+        return
+    if args.workload == "central":
+        run_central(args, lt, synth, torch)
         return
     dev = torch.device("cuda:0")
     prec = lt.PRECISIONS[args.precision]
@@ -267,14 +272,19 @@ def main():
     parts = parts.cpu().numpy()
     value = F_all / (ms_per_step * 1e-3) / 1e9
 
-    # roofline of the contraction kernel: algorithmic flops per launch over the
-    # launches' average HIP-event duration (events on the library's stream)
+    # roofline of the contraction kernel: the step's algorithmic flops F (the
+    # block formulas over the full virtual cube) per launch over the launches'
+    # average HIP-event duration (events on the library's stream); the flops
+    # the kernel executes (2 M N K over the pair-packed outputs) give frac_executed
     gemm_ms = sum(s.triples_gemm_ms for s in stats)
     gemm_flops = sum(s.triples_gemm_flops for s in stats)
     launches = sum(s.triples_gemm_launches for s in stats)
-    achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
+    achieved_exec = gemm_flops / (gemm_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     avg_ms = gemm_ms / max(launches, 1)
+    per_step = max(launches // max(len(stats), 1), 1)
+    F_launch = F_all / per_step
+    achieved = F_launch / (avg_ms * 1e-3) / 1e12
     traffic = None
     # the committed counter summary prices the whole-domain step only
     tr = committed_traffic(args.precision, args.workload) if step_items is None else None
@@ -285,14 +295,17 @@ def main():
                 "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "avg_launch_ms": round(avg_ms, 4),
-                "launches_per_step": launches // max(len(stats), 1),
-                "flops_per_launch": gemm_flops / max(launches, 1),
+                "launches_per_step": per_step,
+                "flops_per_launch": F_launch,
+                "achieved_executed": round(achieved_exec, 2),
+                "frac_executed": round(achieved_exec / peak, 4),
+                "executed_flops_per_launch": gemm_flops / max(launches, 1),
                 "kernel_source_hash": kernel_source_hash(args.precision)}
     # matrix-core utilisation counts every product the split performs
-    mfma_util = MFMA_PRODUCTS[args.precision] * achieved / peak
+    mfma_util = MFMA_PRODUCTS[args.precision] * achieved_exec / peak
     phase = {"setup_ms": round(stats[-1].setup_ms, 2), "triples_gemm_ms": round(stats[-1].triples_gemm_ms, 2),
              "epilogue_ms": round(stats[-1].epilogue_ms, 2), "total_ms": round(stats[-1].total_ms, 2)}
-    log(f"E = {E:.10e}  {ms_per_step / 1e3:.2f} s/step  {value:.1f} GFLOP/s  gemm {achieved:.1f} TFLOP/s")
+    log(f"E = {E:.10e}  {ms_per_step / 1e3:.2f} s/step  {value:.1f} GFLOP/s  gemm {achieved:.1f} TFLOP/s (F)")
 
     full_items = step_items if step_items is not None else None
 
@@ -365,7 +378,8 @@ def main():
             cpu = {"value": round(F_c / dt / 1e9, 3), "unit": "GFLOP/s", "cores": _blas_threads(), "kind": "oracle",
                    "sample": f"{n_c} occupied triplets ({args.cpu_sample} per spin block) of the same domain, "
                              f"{F_c:.3e} flops in {dt:.1f} s, NumPy FP64",
-                   "seconds": round(dt, 2), "est_full_domain_s": round(dt * F_all / F_c, 1)}
+                   "seconds": round(dt, 2), "est_full_domain_s": round(dt * F_all / F_c, 1),
+                   "cpu_model": _cpu_model(), "single_thread": _single_thread_tiny(lt, synth)}
             g = e_items.cpu().numpy()[positions(itc)]
             r = ref["items"]
             tot = np.abs(g.sum(axis=1) - r.sum(axis=1)) / np.maximum(1.0, np.abs(r.sum(axis=1)))
@@ -380,7 +394,7 @@ def main():
     backward = None
     try:
         if not args.no_backward and step_items is None:
-            backward = run_backward(lt, synth, torch, log)
+            backward = run_backward(lt, synth, torch, log, fp64=args.backward_fp64)
     except Exception as ex:   # a failed side leg must not lose the measured step
         backward = {"error": f"{type(ex).__name__}: {ex}"}
         log(f"backward leg failed: {ex}")
@@ -658,9 +672,10 @@ def run_naf(args, lt, synth, torch):
     print(json.dumps(res), flush=True)
 
 
-def run_backward(lt, synth, torch, log):
+def run_backward(lt, synth, torch, log, fp64=False):
     """Adjoint pass on the gradient workload: FP32 (timed after one warmup)
-    and FP64; 3F / t in GFLOP/s; sampled items against the oracle gradient."""
+    and, with fp64, FP64; 3F / t in GFLOP/s; sampled items against the oracle
+    gradient in both precisions."""
     from oracle import grad as ograd
     dom = synth.config_domain("grad")
     tens = {k: torch.from_numpy(v).cuda() for k, v in dom.arrays().items()}
@@ -668,7 +683,7 @@ def run_backward(lt, synth, torch, log):
     F, n = lt.ltriples_flops(d)
     res = {"workload": f"grad domain: noa={dom.noa} nob={dom.nob} nva={dom.nva} nvb={dom.nvb} naux={dom.naux}, "
                        f"all {n} occupied triplets", "algorithmic_flops_3F": 3 * F}
-    for name, prec in (("fp32", lt.LT_FP32), ("fp64", lt.LT_FP64)):
+    for name, prec in (("fp32", lt.LT_FP32), ("fp64", lt.LT_FP64))[:2 if fp64 else 1]:
         ws = torch.empty(lt.ltriples_backward_workspace_size(d, prec), dtype=torch.uint8, device="cuda")
         reps = 2 if name == "fp32" else 1
         for r in range(reps):
@@ -698,6 +713,118 @@ def run_backward(lt, synth, torch, log):
                      "pass": bool(err["fp64"] <= 1e-10 and err["fp32"] <= 1e-5), "oracle_seconds": round(dt, 1)}
     log(f"backward parity: fp64 {err['fp64']:.2e}, fp32 {err['fp32']:.2e}")
     return res
+
+
+def _cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or the platform string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def _single_thread_tiny(lt, synth):
+    """The oracle on the whole small domain (5,4,30,31,120) with one BLAS
+    thread: seconds and GFLOP/s of the algorithmic count."""
+    from oracle import blocks
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:
+        return None
+    dom = synth.config_domain("tiny")
+    F = lt.ltriples_flops(lt.make_domain(dom.dims, {k: (1 << 40) for k in lt.ARRAY_FIELDS}))[0]
+    with threadpool_limits(limits=1):
+        blocks.energy(dom)                    # warm caches and imports
+        t = time.perf_counter()
+        blocks.energy(dom)
+        dt = time.perf_counter() - t
+    return {"workload": f"tiny domain {dom.dims}, all triplets", "threads": 1, "seconds": round(dt, 3),
+            "GFLOP/s": round(F / dt / 1e9, 3)}
+
+
+def run_central(args, lt, synth, torch):
+    """The (T) share of one central orbital of the LNO-sized domain
+    (eq. local_pt): an alpha orbital given as a seeded unit vector over the
+    domain's occupied alpha orbitals, with a seeded four-point Laplace
+    quadrature (the cost does not depend on the points).  Parity: the same
+    share through the FP64 GPU path (which the GPU tests hold to the oracle at
+    1e-11 on smaller domains); CPU baseline: the oracle on a restricted
+    central vector (one nonzero coefficient) of the small domain."""
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    prec = lt.PRECISIONS[args.precision]
+    dom = synth.config_domain("lno")
+    tens = {k: torch.from_numpy(v).to(dev) for k, v in dom.arrays().items()}
+    c, s, w = synth.central_inputs(dom.noa, 4, seed=synth.BASE_SEED + 7000)
+    cd = torch.from_numpy(c).to(dev)
+    d = lt.make_domain(dom.dims, tens)
+    cen, keepq = lt.make_central(0, cd, s, w)
+    ws = torch.empty(lt.ltriples_central_workspace_size(d, cen, prec), dtype=torch.uint8, device=dev)
+    log(f"central share of lno {dom.dims}: workspace {ws.numel() / 1e9:.1f} GB")
+
+    def step():
+        st = lt.Stats()
+        e, parts = lt.ltriples_energy_central(tens, dom.dims, 0, cd, s, w, prec, workspace=ws, stats=st,
+                                              autotune=bool(args.autotune))
+        return e, parts, st
+
+    for k in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {k + 1}/{args.warmup} done")
+    stats = []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for k in range(args.steps):
+        e, parts, st = step()
+        stats.append(st)
+        log(f"step {k + 1}/{args.steps}: {st.total_ms / 1e3:.3f} s")
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    E = float(e.item())
+    F = stats[-1].algorithmic_flops
+    gemm_ms = sum(x.triples_gemm_ms for x in stats)
+    launches = sum(x.triples_gemm_launches for x in stats)
+    per_step = max(launches // len(stats), 1)
+    avg = gemm_ms / max(launches, 1)
+    achieved = F / per_step / (avg * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    del ws
+    torch.cuda.empty_cache()
+    ref = None
+    if prec != lt.LT_FP64:
+        e64, _ = lt.ltriples_energy_central(tens, dom.dims, 0, cd, s, w, lt.LT_FP64)
+        torch.cuda.synchronize()
+        ref = float(e64.item())
+    tol = TOL[args.precision]
+    parity = None if ref is None else {"fp64_gpu": ref, "rel_err": abs(E - ref) / max(1.0, abs(ref)),
+                                       "tolerance": tol, "pass": None if tol is None else
+                                       bool(abs(E - ref) / max(1.0, abs(ref)) <= tol)}
+    out = {"metric": METRIC, "value": round(F / (ms * 1e-3) / 1e9, 1), "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 2), "higher_is_better": True,
+           "scaling": "strong", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+           "config": {"workload": f"central-orbital share of the lno domain {dom.dims}: alpha central orbital, "
+                                  f"4 Laplace points, {stats[-1].n_items} triplets", "algorithmic_flops": F,
+                      "precision": args.precision},
+           "E": E, "parts": parts.cpu().numpy().tolist(),
+           "roofline": {"bound": "mfma", "kernel": "k_tgemm_bf16" if args.precision.startswith("bf16") else "k_tgemm",
+                        "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                        "frac": round(achieved / peak, 4), "traffic": None, "avg_launch_ms": round(avg, 4),
+                        "launches_per_step": per_step},
+           "phases": {"setup_ms": round(stats[-1].setup_ms, 2), "triples_gemm_ms": round(stats[-1].triples_gemm_ms, 2),
+                      "epilogue_ms": round(stats[-1].epilogue_ms, 2)},
+           "parity": parity}
+    print(json.dumps(out), flush=True)
 
 
 def _item_index(noa, nob, items):

@@ -247,6 +247,59 @@ int ltriples_energy_noalloc(const ltriples_domain* d, int32_t precision,
 /* Bytes of the fixed per-device array of ltriples_energy_noalloc. */
 size_t ltriples_noalloc_capacity(void);
 
+/* The central localized molecular orbital of a domain and the Laplace
+ * quadrature of its (T) share (Sec. "Correlation energy calculation in the
+ * LIS", eqs. laplace_transform and local_pt).
+ *   spin   0: the central orbital is an alpha orbital, 1: beta
+ *   c      DEVICE double[no_spin]: the central orbital in the domain's
+ *          occupied orbitals of that spin (normally of unit norm; any vector
+ *          is accepted, the share is quadratic in it)
+ *   nq     number of quadrature points, 1..64
+ *   s, w   HOST double[nq]: points t_q > 0 and weights w_q with
+ *          1/x ~ sum_q w_q exp(-t_q x) for the positive denominators x = -D
+ *          (the paper uses 3-4 points chosen per system; any quadrature,
+ *          e.g. a minimax exponential sum over the domain's range of -D) */
+typedef struct ltriples_central {
+  int32_t spin;
+  const double* c;
+  int32_t nq;
+  const double* s;
+  const double* w;
+} ltriples_central;
+
+/* Host-only: workspace bytes of ltriples_energy_central. */
+int ltriples_central_workspace_size(const ltriples_domain* d, const ltriples_central* c,
+                                    int32_t precision, const ltriples_options* o,
+                                    size_t* bytes);
+
+/* The (T) share of the central orbital c of eq. local_pt: one third of the
+ * triples energy of the occupied triplets that hold c once (with the other
+ * two indices j < k of its spin, j of its spin and K of the other, or
+ * J < K of the other spin), over the unique virtual ranges, with 1/D
+ * replaced by the Laplace sum -sum_q w_q exp(t_q D) and the central
+ * orbital's half of each point's factor exp(t_q D) absorbed into it:
+ *   dE_c = -(1/3) sum_q w_q sum W_c (W_c + V_c) exp(t_q D'),
+ *   W_c = sum_i c_i exp(t_q e_i / 2) W_{i..}  (likewise V_c),
+ * D' the denominator without the central orbital's energy.  For c = e_i and
+ * a quadrature exact on the domain's denominators this is one third of the
+ * energy of the items that contain orbital i; the shares of an orthonormal
+ * basis of both spins' occupied orbitals add up to the energy with the
+ * Laplace denominators.  The cost is about 3 n_q / o of the whole domain's.
+ *   e_out  device double[1]; parts device double[4][3] or NULL: per block
+ *          (aaa, aab, abb, bbb) {E4, E_ST, E_DT} (the blocks of the central
+ *          spin's triplets only; the others are zero)
+ *   ws     device workspace >= ltriples_central_workspace_size(), or NULL
+ *          (stream-ordered allocation, as ltriples_energy)
+ * Precisions, batching, chunking, tiles, stats and host waits as
+ * ltriples_energy; options.items, options.e_items and options.graph must be
+ * unset (LT_EINVAL).  LT_EINVAL also for a bad spin, nq, point (t_q <= 0 or
+ * not finite) or weight, LT_ESHAPE when the central spin has no occupied
+ * orbital.  Exponentials overflow (giving infinities) only when some
+ * t_q |e| exceeds about 700. */
+int ltriples_energy_central(const ltriples_domain* d, const ltriples_central* c,
+                            int32_t precision, const ltriples_options* o, double* e_out,
+                            double* parts, void* ws, size_t ws_bytes, void* stream);
+
 /* Gradient outputs of ltriples_backward: caller-owned device FP64 buffers in
  * the layouts of the corresponding ltriples_domain inputs.  A NULL field is
  * not written.  Gradients of inputs that carry a symmetry are returned

@@ -72,6 +72,11 @@ class RhfGrad(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in RHF_FIELDS]
 
 
+class Central(ctypes.Structure):
+    _fields_ = [("spin", ctypes.c_int32), ("c", ctypes.c_void_p), ("nq", ctypes.c_int32),
+                ("s", ctypes.POINTER(ctypes.c_double)), ("w", ctypes.POINTER(ctypes.c_double))]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_double),
                 ("setup_ms", ctypes.c_double),
@@ -137,6 +142,10 @@ def load_library(path: Optional[str] = None):
                                             ctypes.c_void_p]
     lib.ltriples_noalloc_capacity.argtypes = []
     lib.ltriples_noalloc_capacity.restype = ctypes.c_size_t
+    Cp = ctypes.POINTER(Central)
+    lib.ltriples_central_workspace_size.argtypes = [Dp, Cp, ctypes.c_int32, Op, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ltriples_energy_central.argtypes = [Dp, Cp, ctypes.c_int32, Op, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.ltriples_workspace_size_batched.argtypes = [Dp, ctypes.c_int32, ctypes.c_int32, Op,
                                                     ctypes.POINTER(ctypes.c_size_t)]
     lib.ltriples_energy_batched.argtypes = [Dp, ctypes.c_int32, ctypes.c_int32, Op, ctypes.c_void_p,
@@ -168,7 +177,8 @@ def load_library(path: Optional[str] = None):
               "ltriples_backward_workspace_size", "ltriples_backward", "ltriples_plan_check",
               "ltriples_rhf_workspace_size", "ltriples_rhf_flops", "ltriples_energy_rhf",
               "ltriples_backward_rhf_workspace_size", "ltriples_backward_rhf",
-              "ltriples_naf_workspace_size", "ltriples_naf", "ltriples_autotune_reset"):
+              "ltriples_naf_workspace_size", "ltriples_naf", "ltriples_autotune_reset",
+              "ltriples_central_workspace_size", "ltriples_energy_central"):
         getattr(lib, f).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -394,6 +404,64 @@ def ltriples_energy_noalloc(tensors: Mapping[str, object], dims, precision: int 
     _check(load_library().ltriples_energy_noalloc(ctypes.byref(dom), int(precision), ctypes.byref(opts),
                                                   e.data_ptr(), parts.data_ptr(), st.cuda_stream))
     del keep
+    return e, parts
+
+
+def make_central(spin: int, c, s, w):
+    """ltriples_central from the central orbital's spin, its coefficients
+    (device tensor, or a raw address) and the quadrature points and weights
+    (host sequences; kept alive by the returned tuple's second element)."""
+    x = Central()
+    x.spin = int(spin)
+    x.c = _ptr(c)
+    sv = np.ascontiguousarray(np.asarray(s, dtype=np.float64).ravel())
+    wv = np.ascontiguousarray(np.asarray(w, dtype=np.float64).ravel())
+    if sv.size != wv.size:
+        raise ValueError("quadrature points and weights differ in length")
+    x.nq = int(sv.size)
+    x.s = sv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    x.w = wv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return x, (sv, wv)
+
+
+def ltriples_central_workspace_size(dom: Domain, central: Central, precision: int,
+                                    options: Optional[Options] = None) -> int:
+    lib = load_library()
+    n = ctypes.c_size_t(0)
+    _check(lib.ltriples_central_workspace_size(ctypes.byref(dom), ctypes.byref(central), int(precision),
+                                               ctypes.byref(options) if options is not None else None,
+                                               ctypes.byref(n)))
+    return n.value
+
+
+def ltriples_energy_central(tensors: Mapping[str, object], dims, spin: int, c, s, w, precision: int = LT_FP32,
+                            workspace_budget: int = 0, batch_items: int = 0, workspace=None, stream=None,
+                            stats: Optional[Stats] = None, build_chunk_mib: int = 0, autotune: bool = False,
+                            check_finite: bool = False, tile_override=None):
+    """(T) share of the central orbital `c` (device float64 tensor over the
+    occupied orbitals of `spin`) with the Laplace points `s` and weights `w`
+    (host sequences).  Returns (e [1], parts [4, 3]) as float64 device
+    tensors."""
+    import torch
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    dom = make_domain(dims, tensors)
+    nocc = int(dims[0]) if int(spin) == 0 else int(dims[1])
+    check_array("c", c, nocc)
+    cen, keep_q = make_central(spin, c, s, w)
+    opts, keep = make_options(None, None, workspace_budget, batch_items, stats, build_chunk_mib, autotune,
+                              check_finite, tile_override)
+    dev = _device_of(tensors)
+    need = ltriples_central_workspace_size(dom, cen, precision, opts)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    e = torch.empty(1, dtype=torch.float64, device=dev)
+    parts = torch.empty(4, 3, dtype=torch.float64, device=dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    _check(load_library().ltriples_energy_central(ctypes.byref(dom), ctypes.byref(cen), int(precision),
+                                                  ctypes.byref(opts), e.data_ptr(), parts.data_ptr(),
+                                                  workspace.data_ptr(), workspace.numel(), st.cuda_stream))
+    del keep, keep_q
     return e, parts
 
 

@@ -56,13 +56,19 @@ inline int64_t npair(int64_t n) { return n * (n - 1) / 2; }
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
+// o: occupied orbitals per spin (they index the amplitudes, factors and
+// items); oi: the first oi of them are the ones the contractions sum over.
+// oi = o, except for a central-orbital share, whose rotated central
+// orbitals are appended after the LIS orbitals and only ever appear as an
+// item's own (external) index.
 struct Dims {
-  int64_t o[2], v[2], Q;
+  int64_t o[2], v[2], Q, oi[2];
 };
 
 Dims dims_of(const ltriples_domain* d) {
   Dims x;
   x.o[0] = d->noa; x.o[1] = d->nob; x.v[0] = d->nva; x.v[1] = d->nvb; x.Q = d->naux;
+  x.oi[0] = x.o[0]; x.oi[1] = x.o[1];
   return x;
 }
 
@@ -189,9 +195,10 @@ int64_t count_all_items(const Dims& D) {
          ob * (ob - 1) * (ob - 2) / 6;
 }
 
+// the occupied contraction lengths are the summed orbitals (oi)
 double item_flops(const Dims& D, int b) {
   const int s = blk_sigma(b), t = 1 - s;
-  const double o = (double)D.o[s], v = (double)D.v[s], ot = (double)D.o[t], vt = (double)D.v[t];
+  const double o = (double)D.oi[s], v = (double)D.v[s], ot = (double)D.oi[t], vt = (double)D.v[t];
   if (!blk_mixed(b)) return 6 * v * v * v * v + 6 * v * v * v * o;
   return 4 * v * v * vt * vt + 6 * v * v * v * vt + 4 * v * v * vt * ot + 6 * v * v * vt * o;
 }
@@ -243,14 +250,21 @@ struct Plan {
   int64_t bwg[4];                 // backward epilogue tiles per item
   int64_t ld_ri[4];               // orbital-energy adjoint: per-item index sums
   size_t big = 0, small = 0, small_base = 0, total = 0;
+  // central-orbital share: device table [nq][2] of (point, signed weight)
+  // and the spin of the central orbital (-1: an ordinary energy)
+  const double* lap = nullptr;
+  int lap_spin = -1;
 };
 
+// `oi` (optional): the summed occupied orbitals per spin, when they are fewer
+// than the domain's (a central-orbital share); default all of them.
 void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options* o,
-                 const ItemLists& L, Plan& P, bool bwd = false) {
+                 const ItemLists& L, Plan& P, bool bwd = false, const int64_t* oi = nullptr) {
   P.prec = prec;
   P.bwd = bwd;
   P.ts = prec == LT_FP64 ? 8 : 4;   // BF16 modes prepare FP32 operands, then split them
   P.D = dims_of(d);
+  if (oi) { P.D.oi[0] = oi[0]; P.D.oi[1] = oi[1]; }
   const Dims& D = P.D;
   for (int b = 0; b < 4; ++b) P.n_blk[b] = (int64_t)L.dst[b].size();
   for (int b = 0; b < 4; ++b)
@@ -370,21 +384,22 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
     for (int s = 0; s < 2; ++s) {
       const int t = 1 - s;
       const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
+      const int64_t ois = D.oi[s], oit = D.oi[t];   // occupied contraction rows
       if (P.need_as[s]) {
         take8(s, Plan::T2T8, os * os, vs, P.ldv[s]);
         take8(s, Plan::As8, os, vs, P.ldnp[s]);
-        take8(s, Plan::GamT8, os * os, os, P.ldv[s]);
-        take8(s, Plan::Tp8, os, os, P.ldnp[s]);
+        take8(s, Plan::GamT8, os * os, ois, P.ldv[s]);
+        take8(s, Plan::Tp8, os, ois, P.ldnp[s]);
       }
       if (P.need_mix[s]) {
         take8(s, Plan::LmixT8, os * ot, vt, P.ldv[s]);
         take8(s, Plan::Mst8, os, vt, P.ldcb[s]);
         take8(s, Plan::Mts8, ot, vs, P.ldcb[s]);
-        take8(s, Plan::Tmix8, os, ot, P.ldcb[s]);
-        take8(s, Plan::Tmx28, ot, os, P.ldcb[s]);
-        take8(s, Plan::ZpT8, os * ot, ot, P.ldv[s]);
+        take8(s, Plan::Tmix8, os, oit, P.ldcb[s]);
+        take8(s, Plan::Tmx28, ot, ois, P.ldcb[s]);
+        take8(s, Plan::ZpT8, os * ot, oit, P.ldv[s]);
         take8(s, Plan::TmT8, os * ot, vs, P.ldv[t]);
-        take8(s, Plan::OOT8, ot * os, os, P.ldv[t]);
+        take8(s, Plan::OOT8, ot * os, ois, P.ldv[t]);
       }
     }
   }
@@ -575,7 +590,7 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
   auto split_op = [&](int s, int t8) -> hipError_t {
     if (!P.bf) return hipSuccess;
     const int t = 1 - s;
-    const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
+    const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t], ois = D.oi[s], oit = D.oi[t];
     const int64_t lv = P.ldv[s], lvt = P.ldv[t], lp = P.ldnp[s], lc = P.ldcb[s], np = npair(vs);
     auto sp = [&](int64_t nblk, int64_t K, int64_t ld, int64_t ncol, const Buf& in, int64_t ibs,
                   int64_t iks) -> hipError_t {
@@ -585,16 +600,16 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
     switch (t8) {
       case Plan::T2T8: return sp(os * os, vs, lv, vs, P.T2T[s], vs * lv, lv);
       case Plan::As8: return sp(os, vs, lp, np, P.As[s], vs * lp, lp);
-      case Plan::GamT8: return sp(os * os, os, lv, vs, P.GamT[s], os * lv, lv);
-      case Plan::Tp8: return sp(os, os, lp, np, P.Tp[s], os * lp, lp);
+      case Plan::GamT8: return sp(os * os, ois, lv, vs, P.GamT[s], os * lv, lv);
+      case Plan::Tp8: return sp(os, ois, lp, np, P.Tp[s], os * lp, lp);
       case Plan::LmixT8: return sp(os * ot, vt, lv, vs, P.LmixT[s], vt * lv, lv);
       case Plan::Mst8: return sp(os, vt, lc, vt * vs, P.Mst[s], vt * lc, lc);
       case Plan::Mts8: return sp(ot, vs, lc, vt * vs, P.Mts[s], vs * lc, lc);
-      case Plan::Tmix8: return sp(os, ot, lc, vt * vs, P.Tmix[s], ot * lc, lc);
-      case Plan::Tmx28: return sp(ot, os, lc, vt * vs, P.Tmix[s], lc, ot * lc);
-      case Plan::ZpT8: return sp(os * ot, ot, lv, vs, P.ZpT[s], ot * lv, lv);
+      case Plan::Tmix8: return sp(os, oit, lc, vt * vs, P.Tmix[s], ot * lc, lc);
+      case Plan::Tmx28: return sp(ot, ois, lc, vt * vs, P.Tmix[s], lc, ot * lc);
+      case Plan::ZpT8: return sp(os * ot, oit, lv, vs, P.ZpT[s], ot * lv, lv);
       case Plan::TmT8: return sp(os * ot, vs, lvt, vt, P.TmT[s], vs * lvt, lvt);
-      default: return sp(ot * os, os, lvt, vt, P.OOT[s], os * lvt, lvt);
+      default: return sp(ot * os, ois, lvt, vt, P.OOT[s], os * lvt, lvt);
     }
   };
   // BF16 modes: split blocks [b0, b0 + n) of a chunked operand, built in the
@@ -856,6 +871,7 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
     const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
     lt::ItemOps<T> ops{};
     ops.o_s = (int32_t)os; ops.v_s = (int32_t)vs; ops.o_t = (int32_t)ot; ops.v_t = (int32_t)vt;
+    ops.oi_s = (int32_t)D.oi[s]; ops.oi_t = (int32_t)D.oi[t];
     ops.ld_vs = P.ldv[s]; ops.ld_vt = P.ldv[t]; ops.ld_np = P.ldnp[s]; ops.ld_cb = P.ldcb[s];
     ops.T2T = at<T>(ws, P.T2T[s]); ops.Tp = at<T>(ws, P.Tp[s]); ops.As = at<T>(ws, P.As[s]);
     ops.GamT = at<T>(ws, P.GamT[s]);
@@ -867,6 +883,7 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
     lt::ItemOps8 o8{};
     if (P.bf) {
       o8.o_s = ops.o_s; o8.v_s = ops.v_s; o8.o_t = ops.o_t; o8.v_t = ops.v_t;
+      o8.oi_s = ops.oi_s; o8.oi_t = ops.oi_t;
       o8.ld_vs = ops.ld_vs; o8.ld_vt = ops.ld_vt; o8.ld_np = ops.ld_np; o8.ld_cb = ops.ld_cb;
       auto H = [&](int t8) { return P.O8h[s][t8].bytes ? at<lt::bf16_t>(ws, P.O8h[s][t8]) : nullptr; };
       auto Lo = [&](int t8) { return P.O8l[s][t8].bytes ? at<lt::bf16_t>(ws, P.O8l[s][t8]) : nullptr; };
@@ -937,6 +954,7 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
         e.nt = (int32_t)cdiv(vs, lt::ET); e.ntri = (int32_t)nt;
         e.eo = EO[s]; e.ev = EV[s]; e.t1 = T1[s]; e.f = Fov[s]; e.t2 = T2ss[s];
         e.U = at<double>(ws, P.U[s]); e.ld_v = P.ldv[s]; e.part = part;
+        if (P.lap) { e.lap = P.lap; e.lap_o0 = (int32_t)D.oi[s]; e.lap_slot = 2; }   // (j, k, central)
         HIPCHK(lt::launch_epi_same<T>(e, (int32_t)n, st));
       } else {
         ops.kind = 1;
@@ -975,6 +993,11 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
         else { e.ov_o = so[2]; e.ov_v = so[3]; e.ov_O = so[0]; e.ov_V = so[1]; }
         e.tm = d->t2ab; e.tm_o = mstr[s][0]; e.tm_v = mstr[s][2]; e.tm_O = mstr[s][1]; e.tm_V = mstr[s][3];
         e.part = part;
+        if (P.lap) {   // central orbital in the same-spin pair (i, central, K) or the odd slot (I, J, central)
+          e.lap = P.lap;
+          e.lap_slot = s == P.lap_spin ? 1 : 2;
+          e.lap_o0 = (int32_t)D.oi[P.lap_spin];
+        }
         HIPCHK(lt::launch_epi_mixed<T>(e, (int32_t)n, st));
       }
       HIPCHK(lt::launch_reduce_items(part, (int32_t)n, (int32_t)nt, d_dst + fc[b] + first, e_items, st));
@@ -1535,6 +1558,7 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
     const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
     lt::ItemOps<T> ops{};
     ops.o_s = (int32_t)os; ops.v_s = (int32_t)vs; ops.o_t = (int32_t)ot; ops.v_t = (int32_t)vt;
+    ops.oi_s = (int32_t)os; ops.oi_t = (int32_t)ot;   // the adjoint sums over every orbital
     ops.ld_vs = P.ldv[s]; ops.ld_vt = P.ldv[t]; ops.ld_np = P.ldnp[s]; ops.ld_cb = P.ldcb[s];
     ops.T2T = at<T>(ws, P.T2T[s]); ops.Tp = at<T>(ws, P.Tp[s]); ops.As = at<T>(ws, P.As[s]);
     ops.GamT = at<T>(ws, P.GamT[s]);
@@ -2328,6 +2352,251 @@ int ltriples_graph_reset(void) {
   }
   g_graphs.clear();
   return LT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Central-orbital share (eq. local_pt with the quadrature of eq.
+// laplace_transform).  For each point q the central orbital, scaled by its
+// half of the point's exp(D s) factor, c~_q[i] = c[i] exp(s_q e_i / 2), is
+// appended to the occupied orbitals of its spin: every input with an
+// occupied index of that spin gets the rows sum_i c~_q[i] X[i] (both indices
+// of Boo and of the same-spin amplitudes), with orbital energy 0.  The items
+// are the triplets of that extended domain holding one appended orbital; the
+// contractions sum only over the LIS orbitals (the appended ones are never an
+// internal index), and the epilogue weighs each element by
+// -(w_q / 3) exp(s_q D'), D' the denominator without the central energy.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct CentralSetup {
+  ltriples_domain d{};     // the extended domain (head buffers or the caller's arrays)
+  int spin = 0, nq = 0;
+  int64_t o = 0;           // LIS occupied orbitals of the central spin
+  ltriples_options opt{};
+  std::vector<int32_t> items;
+  std::vector<double> lap; // [nq][2]: (s_q, -w_q / 3)
+  // head of the workspace: Laplace table, coefficients, extended inputs, scratch
+  size_t o_lap = 0, o_coef = 0, o_t1 = 0, o_fov = 0, o_eo = 0, o_Boo = 0, o_Bov = 0, o_t2 = 0, o_t2ab = 0,
+         o_tmp = 0, head = 0;
+};
+
+int central_setup(const ltriples_domain* d, const ltriples_central* c, int32_t precision,
+                  const ltriples_options* o, CentralSetup& S) {
+  int r = validate(d, precision, o);
+  if (r) return r;
+  if (!c) return fail(LT_EINVAL, "central is NULL");
+  if (c->spin != 0 && c->spin != 1) return fail(LT_EINVAL, "central spin %d (0 alpha, 1 beta)", c->spin);
+  if (c->nq < 1 || c->nq > 64) return fail(LT_EINVAL, "nq = %d outside 1..64", c->nq);
+  if (!c->s || !c->w) return fail(LT_EINVAL, "quadrature points or weights are NULL");
+  for (int q = 0; q < c->nq; ++q)
+    if (!(std::isfinite(c->s[q]) && c->s[q] > 0.0 && std::isfinite(c->w[q])))
+      return fail(LT_EINVAL, "quadrature point %d: need a finite t > 0 and a finite weight", q);
+  if (o && (o->items || o->n_items || o->e_items || o->graph))
+    return fail(LT_EINVAL, "item lists, per-item outputs and graphs are not central-share options");
+  const Dims D0 = dims_of(d);
+  S.spin = c->spin;
+  S.nq = c->nq;
+  S.o = D0.o[S.spin];
+  if (S.o < 1) return fail(LT_ESHAPE, "no occupied orbital of the central spin");
+  if (!c->c) return fail(LT_EINVAL, "central orbital coefficients are NULL");
+  if (S.o + S.nq > 4096) return fail(LT_ESHAPE, "too many occupied orbitals with the quadrature points");
+  const int sp = S.spin, tp = 1 - sp;
+  const int64_t no = S.o, oe = no + S.nq, ot = D0.o[tp], v = D0.v[sp], vt = D0.v[tp], Q = D0.Q;
+  // head layout (FP64)
+  size_t off = 0;
+  auto take = [&](int64_t n) { const size_t x = off; off = align256(off + 8 * (size_t)std::max<int64_t>(n, 1)); return x; };
+  S.o_lap = take(2 * S.nq);
+  S.o_coef = take(S.nq * no);
+  S.o_t1 = take(oe * v);
+  S.o_fov = take(oe * v);
+  S.o_eo = take(oe);
+  S.o_Boo = take(Q * oe * oe);
+  S.o_Bov = take(Q * oe * v);
+  S.o_t2 = take(oe * oe * v * v);
+  S.o_t2ab = take(oe * ot * v * vt);
+  S.o_tmp = take(std::max(oe * no * v * v, Q * oe * no));   // first pass of the two-index extensions
+  S.head = off;
+  S.lap.resize(2 * (size_t)S.nq);
+  for (int q = 0; q < S.nq; ++q) {
+    S.lap[2 * q] = c->s[q];
+    S.lap[2 * q + 1] = -c->w[q] / 3.0;   // 1/D -> -sum_q w_q exp(s_q D); one third per eq. local_pt
+  }
+  // the extended domain (placeholder addresses below the head until the workspace is known)
+  ltriples_domain& x = S.d;
+  x = *d;
+  int32_t* nocc[2] = {&x.noa, &x.nob};
+  *nocc[sp] = (int32_t)oe;
+  // items with exactly one appended orbital, ordered by block
+  const int32_t oo = (int32_t)no, ott = (int32_t)ot;
+  const int b_same = sp == 0 ? 0 : 3, b_pair = sp == 0 ? 1 : 2, b_odd = sp == 0 ? 2 : 1;
+  for (int32_t q = 0; q < S.nq; ++q) {
+    const int32_t cq = oo + q;
+    for (int32_t j = 0; j < oo; ++j)
+      for (int32_t k = j + 1; k < oo; ++k) S.items.insert(S.items.end(), {b_same, j, k, cq});
+    for (int32_t i = 0; i < oo; ++i)
+      for (int32_t K = 0; K < ott; ++K) S.items.insert(S.items.end(), {b_pair, i, cq, K});
+    for (int32_t I = 0; I < ott; ++I)
+      for (int32_t J = I + 1; J < ott; ++J) S.items.insert(S.items.end(), {b_odd, I, J, cq});
+  }
+  if (S.items.size() / 4 > (size_t)INT32_MAX) return fail(LT_ESHAPE, "too many items");
+  if (o) S.opt = *o;
+  S.opt.items = S.items.empty() ? nullptr : S.items.data();
+  S.opt.n_items = (int32_t)(S.items.size() / 4);
+  return LT_OK;
+}
+
+// Points the extended domain at the head buffers (and the caller's arrays of
+// the other spin and of Bvv).
+void central_bind(CentralSetup& S, const ltriples_domain* d, char* head) {
+  ltriples_domain& x = S.d;
+  x = *d;
+  const int sp = S.spin;
+  const int32_t oe = (int32_t)(S.o + S.nq);
+  auto P = [&](size_t off) { return (const double*)(head + off); };
+  if (sp == 0) {
+    x.noa = oe;
+    x.t1a = P(S.o_t1); x.fov_a = P(S.o_fov); x.eo_a = P(S.o_eo);
+    x.Boo_a = P(S.o_Boo); x.Bov_a = P(S.o_Bov); x.t2aa = P(S.o_t2);
+  } else {
+    x.nob = oe;
+    x.t1b = P(S.o_t1); x.fov_b = P(S.o_fov); x.eo_b = P(S.o_eo);
+    x.Boo_b = P(S.o_Boo); x.Bov_b = P(S.o_Bov); x.t2bb = P(S.o_t2);
+  }
+  x.t2ab = P(S.o_t2ab);
+}
+
+// Enqueues the extended inputs into the head (kernels and one table copy).
+int central_inputs(const CentralSetup& S, const ltriples_domain* d, const ltriples_central* c, char* head,
+                   hipStream_t st) {
+  const Dims D0 = dims_of(d);
+  const int sp = S.spin, tp = 1 - sp;
+  const int64_t o = S.o, oe = o + S.nq, ot = D0.o[tp], v = D0.v[sp], vt = D0.v[tp], Q = D0.Q;
+  const int32_t oi = (int32_t)o, nq = S.nq;
+  auto W = [&](size_t off) { return (double*)(head + off); };
+  const double* t1 = sp ? d->t1b : d->t1a;
+  const double* fov = sp ? d->fov_b : d->fov_a;
+  const double* eo = sp ? d->eo_b : d->eo_a;
+  const double* Boo = sp ? d->Boo_b : d->Boo_a;
+  const double* Bov = sp ? d->Bov_b : d->Bov_a;
+  const double* t2 = sp ? d->t2bb : d->t2aa;
+  HIPCHK(hipMemcpyAsync(W(S.o_lap), S.lap.data(), 8 * S.lap.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(lt::launch_central_coef(W(S.o_coef), c->c, eo, W(S.o_lap), oi, nq, st));
+  const double* coef = W(S.o_coef);
+  HIPCHK(lt::launch_aug_axis(W(S.o_t1), t1, coef, 1, oi, nq, v, st));
+  HIPCHK(lt::launch_aug_axis(W(S.o_fov), fov, coef, 1, oi, nq, v, st));
+  // orbital energies: the LIS ones, then zeros (the central factor sits in the coefficients)
+  HIPCHK(lt::launch_zero(W(S.o_eo), oe, st));
+  HIPCHK(lt::launch_copy4d<double, double>(W(S.o_eo), 0, 0, 0, 1, 1, 1, o, eo, 0, 0, 0, 1, nullptr, 0, 0, 0, 0, st));
+  // factors: Bov along its occupied index, Boo along both
+  HIPCHK(lt::launch_aug_axis(W(S.o_Bov), Bov, coef, Q, oi, nq, v, st));
+  HIPCHK(lt::launch_aug_axis(W(S.o_tmp), Boo, coef, Q, oi, nq, o, st));
+  HIPCHK(lt::launch_aug_axis(W(S.o_Boo), W(S.o_tmp), coef, Q * oe, oi, nq, 1, st));
+  // same-spin amplitudes along both occupied indices (the appended pair block,
+  // never read, is not zero by construction but is antisymmetric like the rest)
+  HIPCHK(lt::launch_aug_axis(W(S.o_tmp), t2, coef, 1, oi, nq, o * v * v, st));
+  HIPCHK(lt::launch_aug_axis(W(S.o_t2), W(S.o_tmp), coef, oe, oi, nq, v * v, st));
+  // mixed amplitudes along the central spin's occupied index: t2ab [oa][ob][va][vb]
+  if (sp == 0) HIPCHK(lt::launch_aug_axis(W(S.o_t2ab), d->t2ab, coef, 1, oi, nq, ot * v * vt, st));
+  else HIPCHK(lt::launch_aug_axis(W(S.o_t2ab), d->t2ab, coef, ot, oi, nq, vt * v, st));
+  return LT_OK;
+}
+
+// Plan of the extended domain, with the LIS orbitals as the summed ones.
+void central_plan(const CentralSetup& S, int32_t precision, ItemLists& L, Plan& P) {
+  const Dims D = dims_of(&S.d);
+  build_items(D, &S.opt, L);
+  int64_t oi[2] = {D.o[0], D.o[1]};
+  oi[S.spin] = S.o;
+  plan_domain(&S.d, precision, &S.opt, L, P, false, oi);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ltriples_central_workspace_size(const ltriples_domain* d, const ltriples_central* c, int32_t precision,
+                                    const ltriples_options* o, size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(LT_EINVAL, "bytes is NULL");
+  CentralSetup S;
+  int r = central_setup(d, c, precision, o, S);
+  if (r) return r;
+  central_bind(S, d, kFakeBase);
+  ItemLists L;
+  Plan P;
+  central_plan(S, precision, L, P);
+  *bytes = S.head + P.total;
+  return LT_OK;
+}
+
+int ltriples_energy_central(const ltriples_domain* d, const ltriples_central* c, int32_t precision,
+                            const ltriples_options* o, double* e_out, double* parts, void* ws, size_t ws_bytes,
+                            void* stream) {
+  g_err.clear();
+  CentralSetup S;
+  int r = central_setup(d, c, precision, o, S);
+  if (r) return r;
+  if (!e_out) return fail(LT_EINVAL, "e_out is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  central_bind(S, d, kFakeBase);
+  ItemLists L;
+  Plan P;
+  central_plan(S, precision, L, P);
+  r = check_plan(P);
+  if (r) return r;
+  const size_t need = S.head + P.total;
+  r = check_denominators(d, st);
+  if (r) return r;
+  OwnedWs own;
+  r = get_ws(ws, ws_bytes, need, st, own);
+  if (r) return r;
+  char* head = (char*)ws;
+  void* inner = head + S.head;
+  central_bind(S, d, head);
+  log_plan(P);
+  r = upload_items(P, L, inner, st);
+  if (r) return r;
+  if (S.opt.check_finite) {
+    r = scan_finite(d, P, inner, st);
+    if (r) return r;
+    const double* cc = c->c;
+    lt::FiniteScan a{};
+    a.p[0] = cc; a.n[0] = S.o; a.narr = 1;
+    int32_t* flag = at_small<int32_t>(inner, P, P.flag);
+    HIPCHK(lt::launch_zero32(flag, 1, st));
+    HIPCHK(lt::launch_scan_finite(a, flag, st));
+    int32_t h = 0;
+    HIPCHK(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (h) return fail(LT_ENONFINITE, "NaN or infinity in the central orbital (options.check_finite)");
+  }
+  r = central_inputs(S, d, c, head, st);
+  if (r) return r;
+  P.lap = (const double*)(head + S.o_lap);
+  P.lap_spin = S.spin;
+  Timing tm;
+  tm.on = S.opt.stats != nullptr;
+  tm.st = st;
+  if (precision == LT_FP64) r = run<double>(&S.d, P, L, &S.opt, e_out, parts, inner, st, tm);
+  else r = run<float>(&S.d, P, L, &S.opt, e_out, parts, inner, st, tm);
+  if (r == LT_OK && tm.on) {
+    HIPCHK(hipStreamSynchronize(st));
+    ltriples_stats* St = S.opt.stats;
+    *St = ltriples_stats{};
+    St->total_ms = Timing::ms(tm.start, tm.end);
+    St->setup_ms = Timing::ms(tm.start, tm.setup_end);
+    for (auto& x : tm.gemm) St->triples_gemm_ms += Timing::ms(x.first, x.second);
+    for (auto& x : tm.epi) St->epilogue_ms += Timing::ms(x.first, x.second);
+    St->triples_gemm_launches = (int64_t)tm.gemm.size();
+    St->triples_gemm_flops = tm.gemm_flops;
+    double f = 0;
+    for (int b = 0; b < 4; ++b) f += (double)P.n_blk[b] * item_flops(P.D, b);
+    St->algorithmic_flops = f;
+    St->n_items = L.total;
+  }
+  return r;
 }
 
 }  // extern "C"

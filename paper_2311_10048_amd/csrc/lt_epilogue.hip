@@ -69,7 +69,10 @@ __device__ inline double rcp64(double d) {
   return fma(r, e, r);
 }
 
-template <typename T>
+// With LAP (a central-orbital share) the staged virtual energies hold
+// exp(-s ev) instead and the occupied part exp(s (e_i + e_j + e_k - ev_b)) times
+// the point's weight, so each element's weight is a product, not a reciprocal.
+template <typename T, bool LAP>
 __global__ __launch_bounds__(256, 2) void k_epi_same(EpiSame<T> a) {
   // One work-group per (item, a-tile <= b-tile) walks the c-tiles from the
   // b-tile on; the operands of the next c-tile are loaded into registers while
@@ -92,6 +95,12 @@ __global__ __launch_bounds__(256, 2) void k_epi_same(EpiSame<T> a) {
   const int32_t* it = a.items + 3 * item;
   const int occ[3] = {it[0], it[1], it[2]};
   const int v = a.v;
+  double ls = 0.0, lw = 0.0;          // Laplace point and signed weight of this item
+  if (LAP) {
+    const int q = occ[a.lap_slot] - a.lap_o0;
+    ls = a.lap[2 * q];
+    lw = a.lap[2 * q + 1];
+  }
   const int a0 = TA * ET, b0 = TB * ET;
   const T* S = a.S + (int64_t)item * a.s_item;
   const int64_t ldp = a.ld_np;
@@ -121,7 +130,7 @@ __global__ __launch_bounds__(256, 2) void k_epi_same(EpiSame<T> a) {
     fa[pp][ta] = aa < v ? a.f[(int64_t)occ[pp] * v + aa] : 0.0;
   } else if (tid < 4 * ET) {
     const int ta = tid - 3 * ET, aa = a0 + ta;
-    eva[ta] = aa < v ? a.ev[aa] : 0.0;
+    eva[ta] = aa < v ? (LAP ? exp(-ls * a.ev[aa]) : a.ev[aa]) : 0.0;
   }
   const int tb = tid & 15, tc = tid >> 4;
   const int b = b0 + tb;
@@ -132,7 +141,8 @@ __global__ __launch_bounds__(256, 2) void k_epi_same(EpiSame<T> a) {
     t1b[pp] = brow ? sg[pp] * a.t1[(int64_t)occ[pp] * v + b] : 0.0;
     fb[pp] = brow ? sg[pp] * a.f[(int64_t)occ[pp] * v + b] : 0.0;
   }
-  const double dob = (a.eo[occ[0]] + a.eo[occ[1]] + a.eo[occ[2]]) - (brow ? a.ev[b] : 0.0);
+  double dob = (a.eo[occ[0]] + a.eo[occ[1]] + a.eo[occ[2]]) - (brow ? a.ev[b] : 0.0);
+  if (LAP) dob = lw * exp(ls * dob);
   const int na = min(ET, b - a0);
 
   // staging of one c-tile: elements tid + 256*u of the two permuted S blocks,
@@ -178,7 +188,7 @@ __global__ __launch_bounds__(256, 2) void k_epi_same(EpiSame<T> a) {
       if (cc < v) {
         if (tid < 48) rcv = sg[pp] * a.t1[(int64_t)occ[pp] * v + cc];
         else if (tid < 96) rcv = sg[pp] * a.f[(int64_t)occ[pp] * v + cc];
-        else if (tid < 112) rcv = a.ev[cc];
+        else if (tid < 112) rcv = LAP ? exp(-ls * a.ev[cc]) : a.ev[cc];
       }
     }
     const T* Srow = S + (int64_t)c * (c - 1) / 2 + b;
@@ -216,7 +226,7 @@ __global__ __launch_bounds__(256, 2) void k_epi_same(EpiSame<T> a) {
     double t1c[3], fc[3];
 #pragma unroll
     for (int pp = 0; pp < 3; ++pp) { t1c[pp] = t1cs[pp][tc]; fc[pp] = fcs[pp][tc]; }
-    const double dbc = dob - evcs[tc];
+    const double dbc = LAP ? dob * evcs[tc] : dob - evcs[tc];
     if (TC + 1 < a.nt) fetch(TC + 1);   // next tile's loads in flight during this tile's work
     if (ok) {
       for (int ta = 0; ta < na; ++ta) {
@@ -227,7 +237,7 @@ __global__ __launch_bounds__(256, 2) void k_epi_same(EpiSame<T> a) {
           vt += t1a[pp][ta] * Ubc[pp] - t1b[pp] * Uac[pp][ta][tc] - t1c[pp] * Uba[pp][tb][ta];
           vf += fa[pp][ta] * Tbc[pp] - fb[pp] * Tac[pp][ta][tc] - fc[pp] * Tba[pp][tb][ta];
         }
-        const double wd = w * rcp64(dbc - eva[ta]);
+        const double wd = w * (LAP ? dbc * eva[ta] : rcp64(dbc - eva[ta]));
         e4 += wd * w;
         est += wd * vt;
         edt += wd * vf;
@@ -244,7 +254,7 @@ __global__ __launch_bounds__(256, 2) void k_epi_same(EpiSame<T> a) {
 // once.  Thread (b, C) of a tile loops over the tile's a < b; each thread's
 // FP64 partial sums run over all C tiles and one partial per work-group is
 // written.
-template <typename T>
+template <typename T, bool LAP>
 __global__ __launch_bounds__(256) void k_epi_mixed(EpiMixed<T> a) {
   __shared__ T Gb[ET][SROW];        // G[b][C*v+a]
   __shared__ T Yl[ET][SROW];        // Y[C][p(a,b)]
@@ -263,6 +273,12 @@ __global__ __launch_bounds__(256) void k_epi_mixed(EpiMixed<T> a) {
   const int i = it[0], j = it[1], K = it[2];
   const int vs = a.v_s, vt = a.v_t;
   const int a0 = TA * ET, b0 = TB * ET;
+  double ls = 0.0, lw = 0.0;          // Laplace point and signed weight (as k_epi_same)
+  if (LAP) {
+    const int q = it[a.lap_slot] - a.lap_o0;
+    ls = a.lap[2 * q];
+    lw = a.lap[2 * q + 1];
+  }
   const T* G = a.G + (int64_t)item * a.g_item;
   const T* Y = a.Y + (int64_t)item * a.y_item;
   const int64_t lc = a.ld_cb, lp = a.ld_np;
@@ -282,14 +298,15 @@ __global__ __launch_bounds__(256) void k_epi_mixed(EpiMixed<T> a) {
     t1aj[tid] = ok ? a.t1_s[(int64_t)j * vs + aa] : 0.0;
     fai[tid] = ok ? a.f_s[(int64_t)i * vs + aa] : 0.0;
     faj[tid] = ok ? a.f_s[(int64_t)j * vs + aa] : 0.0;
-    eva[tid] = ok ? a.ev_s[aa] : 0.0;
+    eva[tid] = ok ? (LAP ? exp(-ls * a.ev_s[aa]) : a.ev_s[aa]) : 0.0;
   }
   const int tb = tid & 15, tc = tid >> 4;
   const int b = b0 + tb;
   const bool brow = b < vs;
   const double t1bi = brow ? a.t1_s[(int64_t)i * vs + b] : 0.0, t1bj = brow ? a.t1_s[(int64_t)j * vs + b] : 0.0;
   const double fbi = brow ? a.f_s[(int64_t)i * vs + b] : 0.0, fbj = brow ? a.f_s[(int64_t)j * vs + b] : 0.0;
-  const double dob = (a.eo_s[i] + a.eo_s[j] + a.eo_t[K]) - (brow ? a.ev_s[b] : 0.0);
+  double dob = (a.eo_s[i] + a.eo_s[j] + a.eo_t[K]) - (brow ? a.ev_s[b] : 0.0);
+  if (LAP) dob = lw * exp(ls * dob);
   const int na = min(ET, b - a0);
   // staging of one C tile: thread tid stages elements tid + 256*u of the
   // permuted G block and of Y, one element of each small FP64 block, and its
@@ -334,7 +351,7 @@ __global__ __launch_bounds__(256) void k_epi_mixed(EpiMixed<T> a) {
     rTmib = ok ? a.tm[i * a.tm_o + b * a.tm_v + K * a.tm_O + C * a.tm_V] : 0.0;
     rt1C = ok ? a.t1_t[(int64_t)K * vt + C] : 0.0;
     rfC = ok ? a.f_t[(int64_t)K * vt + C] : 0.0;
-    revC = ok ? a.ev_t[C] : 0.0;
+    revC = ok ? (LAP ? exp(-ls * a.ev_t[C]) : a.ev_t[C]) : 0.0;
     const T* Grow = G + (int64_t)C * vs + b;
 #pragma unroll
     for (int ta = 0; ta < ET; ++ta) rd[ta] = (ok && ta < na) ? Grow[(a0 + ta) * lc] : (T)0;
@@ -353,7 +370,7 @@ __global__ __launch_bounds__(256) void k_epi_mixed(EpiMixed<T> a) {
     OVj[ov_ta][ov_tx] = rovj; OVi[ov_ta][ov_tx] = rovi;
     Tmj[tm_ta][tm_tx] = rtmj; Tmi[tm_ta][tm_tx] = rtmi;
     const double OVjb = rOVjb, OVib = rOVib, Tmjb = rTmjb, Tmib = rTmib, t1C = rt1C, fC = rfC;
-    const double dbc = dob - revC;
+    const double dbc = LAP ? dob * revC : dob - revC;
     const bool ok = brow && TC * ET + tc < vt;
     T gd[ET];
 #pragma unroll
@@ -369,7 +386,7 @@ __global__ __launch_bounds__(256) void k_epi_mixed(EpiMixed<T> a) {
                            + t1C * Uab[tb][ta];
         const double vfo = fai[ta] * Tmjb - faj[ta] * Tmib - fbi * Tmj[ta][tc] + fbj * Tmi[ta][tc]
                            + fC * T2ab[tb][ta];
-        const double wd = w * rcp64(dbc - eva[ta]);
+        const double wd = w * (LAP ? dbc * eva[ta] : rcp64(dbc - eva[ta]));
         e4 += wd * w;
         est += wd * vt1;
         edt += wd * vfo;
@@ -826,14 +843,16 @@ hipError_t launch_eps_reduce(const EpsReduce& r, hipStream_t s) {
 template <typename T>
 hipError_t launch_epi_same(const EpiSame<T>& a, int32_t nitems, hipStream_t s) {
   if (nitems <= 0 || a.ntri <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_epi_same<T>), dim3(a.ntri, nitems), dim3(256), 0, s, a);
+  if (a.lap) hipLaunchKernelGGL((k_epi_same<T, true>), dim3(a.ntri, nitems), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_epi_same<T, false>), dim3(a.ntri, nitems), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_epi_mixed(const EpiMixed<T>& a, int32_t nitems, hipStream_t s) {
   if (nitems <= 0 || a.ntiles <= 0) return hipSuccess;
   // one work-group per (a-tile <= b-tile) pair; ntiles = that pair count
-  hipLaunchKernelGGL((k_epi_mixed<T>), dim3(a.ntiles, nitems), dim3(256), 0, s, a);
+  if (a.lap) hipLaunchKernelGGL((k_epi_mixed<T, true>), dim3(a.ntiles, nitems), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_epi_mixed<T, false>), dim3(a.ntiles, nitems), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 template hipError_t launch_epi_same<float>(const EpiSame<float>&, int32_t, hipStream_t);

@@ -28,6 +28,8 @@ namespace lt {
 
 // Segment idx of the contraction of one occupied triplet (i, j, k); all
 // arguments are wave-uniform, so the descriptor lives in scalar registers.
+// Operand blocks are indexed over the o_s (o_t) orbitals; the contractions
+// over occupied orbitals run over the first oi_s (oi_t) rows of a block.
 template <typename T>
 __device__ inline Seg<T> item_seg(const ItemOps<T>& s, int64_t i, int64_t j, int64_t k, int idx) {
   const int64_t o = s.o_s, v = s.v_s, ot = s.o_t, vt = s.v_t;
@@ -39,9 +41,9 @@ __device__ inline Seg<T> item_seg(const ItemOps<T>& s, int64_t i, int64_t j, int
       case 0: return {s.T2T + (j * o + k) * tb, lv, s.As + i * ab, lp, (int32_t)v, 1.f};
       case 1: return {s.T2T + (i * o + k) * tb, lv, s.As + j * ab, lp, (int32_t)v, -1.f};
       case 2: return {s.T2T + (j * o + i) * tb, lv, s.As + k * ab, lp, (int32_t)v, -1.f};
-      case 3: return {s.GamT + (j * o + k) * gb, lv, s.Tp + i * pb, lp, (int32_t)o, -1.f};
-      case 4: return {s.GamT + (i * o + k) * gb, lv, s.Tp + j * pb, lp, (int32_t)o, 1.f};
-      default: return {s.GamT + (j * o + i) * gb, lv, s.Tp + k * pb, lp, (int32_t)o, 1.f};
+      case 3: return {s.GamT + (j * o + k) * gb, lv, s.Tp + i * pb, lp, s.oi_s, -1.f};
+      case 4: return {s.GamT + (i * o + k) * gb, lv, s.Tp + j * pb, lp, s.oi_s, 1.f};
+      default: return {s.GamT + (j * o + i) * gb, lv, s.Tp + k * pb, lp, s.oi_s, 1.f};
     }
   }
   if (s.kind == 1) {
@@ -51,9 +53,9 @@ __device__ inline Seg<T> item_seg(const ItemOps<T>& s, int64_t i, int64_t j, int
       case 0: return {s.LmixT + (i * ot + k) * vt * lv, lv, s.Mst + j * vt * lc, lc, (int32_t)vt, 1.f};
       case 1: return {s.LmixT + (j * ot + k) * vt * lv, lv, s.Mst + i * vt * lc, lc, (int32_t)vt, -1.f};
       case 2: return {s.T2T + (i * o + j) * v * lv, lv, s.Mts + k * v * lc, lc, (int32_t)v, 1.f};
-      case 3: return {s.GamT + (i * o + j) * o * lv, lv, s.Tmix + k * lc, ot * lc, (int32_t)o, 1.f};
-      case 4: return {s.ZpT + (j * ot + k) * ot * lv, lv, s.Tmix + i * ot * lc, lc, (int32_t)ot, 1.f};
-      default: return {s.ZpT + (i * ot + k) * ot * lv, lv, s.Tmix + j * ot * lc, lc, (int32_t)ot, -1.f};
+      case 3: return {s.GamT + (i * o + j) * o * lv, lv, s.Tmix + k * lc, ot * lc, s.oi_s, 1.f};
+      case 4: return {s.ZpT + (j * ot + k) * ot * lv, lv, s.Tmix + i * ot * lc, lc, s.oi_t, 1.f};
+      default: return {s.ZpT + (i * ot + k) * ot * lv, lv, s.Tmix + j * ot * lc, lc, s.oi_t, -1.f};
     }
   }
   // Y[C][p(a<b)] = -sum_e t^{eC}_{iK}<je||ab> + sum_e t^{eC}_{jK}<ie||ab>
@@ -61,8 +63,8 @@ __device__ inline Seg<T> item_seg(const ItemOps<T>& s, int64_t i, int64_t j, int
   switch (idx) {
     case 0: return {s.TmT + (i * ot + k) * v * lt_, lt_, s.As + j * v * lp, lp, (int32_t)v, 1.f};
     case 1: return {s.TmT + (j * ot + k) * v * lt_, lt_, s.As + i * v * lp, lp, (int32_t)v, -1.f};
-    case 2: return {s.OOT + (k * o + j) * o * lt_, lt_, s.Tp + i * o * lp, lp, (int32_t)o, -1.f};
-    default: return {s.OOT + (k * o + i) * o * lt_, lt_, s.Tp + j * o * lp, lp, (int32_t)o, 1.f};
+    case 2: return {s.OOT + (k * o + j) * o * lt_, lt_, s.Tp + i * o * lp, lp, s.oi_s, -1.f};
+    default: return {s.OOT + (k * o + i) * o * lt_, lt_, s.Tp + j * o * lp, lp, s.oi_s, 1.f};
   }
 }
 

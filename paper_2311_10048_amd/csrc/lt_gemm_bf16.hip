@@ -26,10 +26,13 @@ __device__ inline int64_t k16(int64_t k) { return (k + 15) & ~int64_t(15); }   /
 
 // Segment idx of the contraction of triplet (i, j, k); see item_seg in
 // lt_gemm.hip for the equations (same terms, same order, same signs).
+// Blocks are indexed over the o_s (o_t) orbitals; occupied contraction rows
+// (K) run over the first oi_s (oi_t), and the octet blocks of those operands
+// hold exactly that many rows (padded to 16).
 __device__ inline Seg8 item_seg8(const ItemOps8& s, int64_t i, int64_t j, int64_t k, int idx) {
-  const int64_t o = s.o_s, v = s.v_s, ot = s.o_t, vt = s.v_t;
+  const int64_t o = s.o_s, v = s.v_s, ot = s.o_t, vt = s.v_t, oi = s.oi_s, oit = s.oi_t;
   const int64_t lv = s.ld_vs, lt_ = s.ld_vt, lp = s.ld_np, lc = s.ld_cb;
-  const int64_t kv = k16(v), ko = k16(o), kvt = k16(vt), kot = k16(ot);
+  const int64_t kv = k16(v), ko = k16(oi), kvt = k16(vt), kot = k16(oit);
   // block sizes (elements) of each octet tensor
   const int64_t bT2T = kv * lv, bAs = kv * lp, bGam = ko * lv, bTp = ko * lp;
   auto mk = [](const bf16_t* Lh, const bf16_t* Ll, int64_t lo, int64_t ll, const bf16_t* Rh, const bf16_t* Rl,
@@ -41,9 +44,9 @@ __device__ inline Seg8 item_seg8(const ItemOps8& s, int64_t i, int64_t j, int64_
       case 0: return mk(s.T2Th, s.T2Tl, (j * o + k) * bT2T, lv, s.Ash, s.Asl, i * bAs, lp, v, 1.f);
       case 1: return mk(s.T2Th, s.T2Tl, (i * o + k) * bT2T, lv, s.Ash, s.Asl, j * bAs, lp, v, -1.f);
       case 2: return mk(s.T2Th, s.T2Tl, (j * o + i) * bT2T, lv, s.Ash, s.Asl, k * bAs, lp, v, -1.f);
-      case 3: return mk(s.GamTh, s.GamTl, (j * o + k) * bGam, lv, s.Tph, s.Tpl, i * bTp, lp, o, -1.f);
-      case 4: return mk(s.GamTh, s.GamTl, (i * o + k) * bGam, lv, s.Tph, s.Tpl, j * bTp, lp, o, 1.f);
-      default: return mk(s.GamTh, s.GamTl, (j * o + i) * bGam, lv, s.Tph, s.Tpl, k * bTp, lp, o, 1.f);
+      case 3: return mk(s.GamTh, s.GamTl, (j * o + k) * bGam, lv, s.Tph, s.Tpl, i * bTp, lp, oi, -1.f);
+      case 4: return mk(s.GamTh, s.GamTl, (i * o + k) * bGam, lv, s.Tph, s.Tpl, j * bTp, lp, oi, 1.f);
+      default: return mk(s.GamTh, s.GamTl, (j * o + i) * bGam, lv, s.Tph, s.Tpl, k * bTp, lp, oi, 1.f);
     }
   }
   if (s.kind == 1) {
@@ -53,17 +56,17 @@ __device__ inline Seg8 item_seg8(const ItemOps8& s, int64_t i, int64_t j, int64_
       case 0: return mk(s.LmixTh, s.LmixTl, (i * ot + k) * bLm, lv, s.Msth, s.Mstl, j * bMst, lc, vt, 1.f);
       case 1: return mk(s.LmixTh, s.LmixTl, (j * ot + k) * bLm, lv, s.Msth, s.Mstl, i * bMst, lc, vt, -1.f);
       case 2: return mk(s.T2Th, s.T2Tl, (i * o + j) * bT2T, lv, s.Mtsh, s.Mtsl, k * bMts, lc, v, 1.f);
-      case 3: return mk(s.GamTh, s.GamTl, (i * o + j) * bGam, lv, s.Tmx2h, s.Tmx2l, k * bTmx2, lc, o, 1.f);
-      case 4: return mk(s.ZpTh, s.ZpTl, (j * ot + k) * bZp, lv, s.Tmixh, s.Tmixl, i * bTmix, lc, ot, 1.f);
-      default: return mk(s.ZpTh, s.ZpTl, (i * ot + k) * bZp, lv, s.Tmixh, s.Tmixl, j * bTmix, lc, ot, -1.f);
+      case 3: return mk(s.GamTh, s.GamTl, (i * o + j) * bGam, lv, s.Tmx2h, s.Tmx2l, k * bTmx2, lc, oi, 1.f);
+      case 4: return mk(s.ZpTh, s.ZpTl, (j * ot + k) * bZp, lv, s.Tmixh, s.Tmixl, i * bTmix, lc, oit, 1.f);
+      default: return mk(s.ZpTh, s.ZpTl, (i * ot + k) * bZp, lv, s.Tmixh, s.Tmixl, j * bTmix, lc, oit, -1.f);
     }
   }
   const int64_t bTmT = kv * lt_, bOOT = ko * lt_;
   switch (idx) {
     case 0: return mk(s.TmTh, s.TmTl, (i * ot + k) * bTmT, lt_, s.Ash, s.Asl, j * bAs, lp, v, 1.f);
     case 1: return mk(s.TmTh, s.TmTl, (j * ot + k) * bTmT, lt_, s.Ash, s.Asl, i * bAs, lp, v, -1.f);
-    case 2: return mk(s.OOTh, s.OOTl, (k * o + j) * bOOT, lt_, s.Tph, s.Tpl, i * bTp, lp, o, -1.f);
-    default: return mk(s.OOTh, s.OOTl, (k * o + i) * bOOT, lt_, s.Tph, s.Tpl, j * bTp, lp, o, 1.f);
+    case 2: return mk(s.OOTh, s.OOTl, (k * o + j) * bOOT, lt_, s.Tph, s.Tpl, i * bTp, lp, oi, -1.f);
+    default: return mk(s.OOTh, s.OOTl, (k * o + i) * bOOT, lt_, s.Tph, s.Tpl, j * bTp, lp, oi, 1.f);
   }
 }
 

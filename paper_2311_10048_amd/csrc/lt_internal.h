@@ -58,6 +58,11 @@ template <typename T> struct Seg {
 template <typename T> struct ItemOps {
   int32_t kind;                 // 0: S (same spin), 1: G (mixed), 2: Y (mixed)
   int32_t o_s, v_s, o_t, v_t;
+  // occupied orbitals the contractions sum over (the internal m, M): the
+  // first oi_s (oi_t) of the o_s (o_t) orbitals that index the operand
+  // blocks.  Equal to o_s, o_t except for a central-orbital share, whose
+  // rotated central orbitals follow the LIS orbitals and are never summed.
+  int32_t oi_s, oi_t;
   int64_t ld_vs, ld_vt, ld_np, ld_cb;
   const T* T2T;    // [o_s][o_s][v_s][ld_vs]   T2T[i][j][e][a] = t^{ae}_{ij}
   const T* Tp;     // [o_s][o_s][ld_np]        Tp[i][m][p(a<b)] = t^{ab}_{im}
@@ -110,20 +115,21 @@ struct Seg8 {
 struct ItemOps8 {
   int32_t kind;                          // 0: S, 1: G, 2: Y (as ItemOps)
   int32_t o_s, v_s, o_t, v_t;
+  int32_t oi_s, oi_t;                    // summed occupied orbitals (as ItemOps)
   int64_t ld_vs, ld_vt, ld_np, ld_cb;
   // hi/lo octet tensors; block = leading indices, K = contraction rows
   const bf16_t *T2Th, *T2Tl;     // blk (i,j)  K v_s  ld_vs
-  const bf16_t *Tph, *Tpl;       // blk i      K o_s  ld_np
+  const bf16_t *Tph, *Tpl;       // blk i      K oi_s ld_np
   const bf16_t *Ash, *Asl;       // blk i      K v_s  ld_np
-  const bf16_t *GamTh, *GamTl;   // blk (j,k)  K o_s  ld_vs
+  const bf16_t *GamTh, *GamTl;   // blk (j,k)  K oi_s ld_vs
   const bf16_t *LmixTh, *LmixTl; // blk (i,K)  K v_t  ld_vs
   const bf16_t *Msth, *Mstl;     // blk j      K v_t  ld_cb
   const bf16_t *Mtsh, *Mtsl;     // blk K      K v_s  ld_cb
-  const bf16_t *Tmixh, *Tmixl;   // blk i      K o_t  ld_cb   (t^{bC}_{iM} over M)
-  const bf16_t *Tmx2h, *Tmx2l;   // blk K      K o_s  ld_cb   (t^{bC}_{mK} over m)
-  const bf16_t *ZpTh, *ZpTl;     // blk (j,K)  K o_t  ld_vs
+  const bf16_t *Tmixh, *Tmixl;   // blk i      K oi_t ld_cb   (t^{bC}_{iM} over M)
+  const bf16_t *Tmx2h, *Tmx2l;   // blk K      K oi_s ld_cb   (t^{bC}_{mK} over m)
+  const bf16_t *ZpTh, *ZpTl;     // blk (j,K)  K oi_t ld_vs
   const bf16_t *TmTh, *TmTl;     // blk (i,K)  K v_s  ld_vt
-  const bf16_t *OOTh, *OOTl;     // blk (K,j)  K o_s  ld_vt
+  const bf16_t *OOTh, *OOTl;     // blk (K,j)  K oi_s ld_vt
   const int32_t* items;
 };
 
@@ -166,6 +172,11 @@ template <typename T> struct EpiSame {
   const double *eo, *ev, *t1, *f, *t2; // t2 [o][o][v][v] (input)
   const double* U; int64_t ld_v;       // U[q][r][y][ld_v] = <qr||yz>
   double* part;                        // [n][ntri][3]
+  // Laplace weights of a central-orbital share (null otherwise): the item's
+  // occupied index in slot lap_slot is the rotated central orbital
+  // lap_o0 + q (its orbital energy set to zero in eo), and 1/D is replaced
+  // by lap[2q + 1] * exp(lap[2q] * D)
+  const double* lap; int32_t lap_o0, lap_slot;
 };
 
 template <typename T> struct EpiMixed {
@@ -181,6 +192,7 @@ template <typename T> struct EpiMixed {
   const double* ov; int64_t ov_o, ov_v, ov_O, ov_V;
   const double* tm; int64_t tm_o, tm_v, tm_O, tm_V;
   double* part;                        // [n][ntiles][3]
+  const double* lap; int32_t lap_o0, lap_slot;   // as EpiSame
 };
 
 // ---------------------------------------------------------------------------
@@ -226,6 +238,15 @@ hipError_t launch_reduce_final(const double* e_items, const int32_t* order,
                                const int32_t* first, const int32_t* count,
                                double* parts, double* e_out, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
+// Central-orbital share inputs.  coef[q][i] = c[i] * exp(lap[2q] * eo[i] / 2)
+// for q < nq, i < o: the central orbital with the point's orbital factor.
+hipError_t launch_central_coef(double* coef, const double* c, const double* eo, const double* lap, int32_t o,
+                               int32_t nq, hipStream_t s);
+// One occupied axis (length o) of in[pre][o][post] extended by nq rotated
+// orbitals: out[x][p][y] = in[x][p][y] for p < o and
+// sum_i coef[p - o][i] in[x][i][y] for o <= p < o + nq.
+hipError_t launch_aug_axis(double* out, const double* in, const double* coef, int64_t pre, int32_t o,
+                           int32_t nq, int64_t post, hipStream_t s);
 // flag[0] = 1 if any element of the listed arrays is NaN or infinite (flag
 // zeroed beforehand by the caller; untouched otherwise)
 struct FiniteScan {

@@ -179,6 +179,53 @@ hipError_t launch_zero(double* p, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_central_coef(double* coef, const double* c, const double* eo,
+                                                      const double* lap, int32_t o, int32_t nq) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= o * nq) return;
+  const int q = e / o, i = e % o;
+  coef[e] = c[i] * exp(0.5 * lap[2 * q] * eo[i]);
+}
+
+hipError_t launch_central_coef(double* coef, const double* c, const double* eo, const double* lap, int32_t o,
+                               int32_t nq, hipStream_t s) {
+  const int n = o * nq;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_central_coef, dim3((n + 255) / 256), dim3(256), 0, s, coef, c, eo, lap, o, nq);
+  return hipGetLastError();
+}
+
+// One thread per output element; the rotated rows (p >= o) sum over the o
+// input rows with coalesced reads along the contiguous trailing index.
+__global__ __launch_bounds__(256) void k_aug_axis(double* out, const double* in, const double* coef, int64_t pre,
+                                                  int32_t o, int32_t nq, int64_t post) {
+  const int64_t np = o + nq, total = pre * np * post;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t y = e % post, r = e / post;
+    const int64_t p = r % np, x = r / np;
+    const double* src = in + x * o * post + y;
+    double acc;
+    if (p < o) {
+      acc = src[p * post];
+    } else {
+      const double* cq = coef + (p - o) * o;
+      acc = 0.0;
+      for (int i = 0; i < o; ++i) acc = fma(cq[i], src[(int64_t)i * post], acc);
+    }
+    out[e] = acc;
+  }
+}
+
+hipError_t launch_aug_axis(double* out, const double* in, const double* coef, int64_t pre, int32_t o, int32_t nq,
+                           int64_t post, hipStream_t s) {
+  const int64_t total = pre * (int64_t)(o + nq) * post;
+  if (total <= 0) return hipSuccess;
+  int64_t nb = (total + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_aug_axis, dim3((unsigned)nb), dim3(256), 0, s, out, in, coef, pre, o, nq, post);
+  return hipGetLastError();
+}
+
 // Grid-stride pass over each array in turn; any thread that meets a NaN or an
 // infinity stores 1 to the flag (every writer stores the same value).
 __global__ __launch_bounds__(256) void k_scan_finite(FiniteScan a, int32_t* flag) {

@@ -286,3 +286,15 @@ def sample_items(noa: int, nob: int, per_block: int, seed: int):
     for cands in _block_lists(noa, nob):
         rows += pick(cands)
     return np.asarray(rows, dtype=np.int32).reshape(-1, 4)
+
+
+def central_inputs(no: int, nq: int, seed: int):
+    """Inputs of a central-orbital share: a seeded unit vector over `no`
+    occupied orbitals, and nq positive quadrature points and weights (seeded
+    draws; the share is defined for any of them).  Draws only."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = rng.normal(size=no)
+    c /= np.linalg.norm(c)
+    s = np.sort(rng.uniform(0.05, 2.0, size=nq))
+    w = rng.uniform(0.1, 1.0, size=nq)
+    return c, s, w

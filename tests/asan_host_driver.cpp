@@ -127,6 +127,22 @@ int main() {
     o.check_finite = 2;
     expect(ltriples_validate(&d, LT_FP32, &o), LT_EINVAL, "check_finite not 0/1");
   }
+  // central-orbital share sizing, both spins, every precision, small and LNO-sized
+  {
+    const double pts[3] = {0.2, 0.7, 1.9}, wts[3] = {0.3, 0.4, 0.6};
+    const int32_t cs[][5] = {{5, 4, 30, 31, 120}, {3, 1, 17, 18, 30}, {40, 38, 300, 302, 1200}};
+    for (const auto& sh : cs) {
+      ltriples_domain d = fake_domain(sh, placeholder);
+      for (int spin = 0; spin < 2; ++spin)
+        for (int prec = 0; prec < 4; ++prec) {
+          ltriples_central c{spin, placeholder, 3, pts, wts};
+          expect(ltriples_central_workspace_size(&d, &c, prec, nullptr, &ws), LT_OK, "central workspace");
+        }
+    }
+    ltriples_domain d = fake_domain(cs[0], placeholder);
+    ltriples_central c{0, placeholder, 0, pts, wts};
+    expect(ltriples_central_workspace_size(&d, &c, LT_FP64, nullptr, &ws), LT_EINVAL, "central nq = 0");
+  }
   // error paths
   expect(ltriples_validate(nullptr, LT_FP64, nullptr), LT_EINVAL, "null domain");
   expect(ltriples_rhf_workspace_size(nullptr, LT_FP64, nullptr, &ws), LT_EINVAL, "null rhf");

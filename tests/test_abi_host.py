@@ -357,3 +357,32 @@ def test_workspace_budget_bounds_the_batch_scratch():
     big = lt.ltriples_workspace_size(d, lt.LT_FP32, lt.make_options()[0])
     small = lt.ltriples_workspace_size(d, lt.LT_FP32, lt.make_options(workspace_budget=64 << 20)[0])
     assert small < big
+
+
+def test_central_share_sizing_and_argument_checks():
+    """ltriples_central_workspace_size: the extended domain (one more
+    occupied orbital per quadrature point) needs a little more workspace
+    than the domain itself; bad central arguments give LT_EINVAL, a central
+    spin without occupied orbitals LT_ESHAPE, all host-only."""
+    _lib()
+    d = _fake_domain((5, 4, 30, 31, 120))
+    base = lt.ltriples_workspace_size(d, lt.LT_BF16X3)
+    for spin in (0, 1):
+        cen, keep = lt.make_central(spin, 0x5000, [0.2, 0.7, 1.9], [0.3, 0.4, 0.6])
+        w = lt.ltriples_central_workspace_size(d, cen, lt.LT_BF16X3)
+        assert base < w < 3 * base
+    lib = lt.load_library()
+    n = ctypes.c_size_t(0)
+    for spin, c, s, w, code in ((3, 0x5000, [0.5], [1.0], lt.LT_EINVAL), (0, 0, [0.5], [1.0], lt.LT_EINVAL),
+                                (0, 0x5000, [0.0], [1.0], lt.LT_EINVAL), (1, 0x5000, [0.5] * 65, [1.0] * 65,
+                                                                          lt.LT_EINVAL)):
+        cen, keep = lt.make_central(spin, c, s, w)
+        assert lib.ltriples_central_workspace_size(ctypes.byref(d), ctypes.byref(cen), lt.LT_FP64, None,
+                                                   ctypes.byref(n)) == code, (spin, c, s, w)
+    cen, keep = lt.make_central(0, 0x5000, [0.5], [1.0])
+    o, _ = lt.make_options(items=[(0, 0, 1, 2)])
+    assert lib.ltriples_central_workspace_size(ctypes.byref(d), ctypes.byref(cen), lt.LT_FP64, ctypes.byref(o),
+                                               ctypes.byref(n)) == lt.LT_EINVAL
+    d0 = _fake_domain((0, 4, 30, 31, 120), null=("t1a", "t2aa", "t2ab", "Boo_a", "Bov_a", "eo_a", "fov_a"))
+    assert lib.ltriples_central_workspace_size(ctypes.byref(d0), ctypes.byref(cen), lt.LT_FP64, None,
+                                               ctypes.byref(n)) == lt.LT_ESHAPE
