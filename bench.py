@@ -102,6 +102,34 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
 
 
+def library_gemm(steps):
+    """Profiling aid: the vendor library's plain BF16 GEMM (torch.matmul, BF16
+    output) on the contraction's average shape, for comparison with the
+    triplet contraction kernel.  K = 2304 is three times the mean contraction
+    depth of the LNO domain (767), i.e. the three BF16 products of one
+    split multiply-add laid end to end; N = 362400 is four triplets' output
+    columns of a mixed G launch."""
+    import torch
+    out = []
+    for M, K, N in ((300, 2304, 362400), (320, 2304, 362400), (8192, 8192, 8192)):
+        A = torch.randn(M, K, device="cuda", dtype=torch.bfloat16)
+        B = torch.randn(K, N, device="cuda", dtype=torch.bfloat16).contiguous()
+        C = torch.empty(M, N, device="cuda", dtype=torch.bfloat16)
+        for _ in range(3):
+            torch.matmul(A, B, out=C)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            torch.matmul(A, B, out=C)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out.append({"M": M, "K": K, "N": N, "ms": round(ms, 4), "TFLOP/s": round(2.0 * M * N * K / ms / 1e9, 1)})
+        del A, B, C
+    print(json.dumps({"library_gemm_bf16": out}), flush=True)
+
+
 def _csv_rows(path, kernel):
     import csv
     with open(path) as f:
@@ -184,6 +212,8 @@ def main():
     ap.add_argument("--prefix-items", type=int, default=0,
                     help="profiling aid: the first K triplets per block in the whole-domain order")
     ap.add_argument("--copy-calibration", action="store_true", help="profiling aid: plain 1 GiB device copy")
+    ap.add_argument("--library-gemm", action="store_true",
+                    help="profiling aid: the library BF16 GEMM on the contraction's average shape")
     ap.add_argument("--traffic-from", nargs=2, metavar=("PMC_DIR", "TRACE_CSV"),
                     help="profiling aid (no GPU): write the HBM traffic summary from counter and trace csv files")
     args = ap.parse_args()
@@ -208,6 +238,9 @@ def main():
         sys.exit(1)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.library_gemm:
+        library_gemm(max(args.steps, 20))
         return
     if args.workload == "batch":
         run_batch(args, lt, synth, torch)
