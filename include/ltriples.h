@@ -300,6 +300,23 @@ int ltriples_energy_central(const ltriples_domain* d, const ltriples_central* c,
                             int32_t precision, const ltriples_options* o, double* e_out,
                             double* parts, void* ws, size_t ws_bytes, void* stream);
 
+/* Debug dump of one triplet's connected triples amplitude W (the quantity of
+ * the master formula, eq. cim_pt_energy, before V and the denominator enter):
+ * runs the forward path of ltriples_energy for the single item `item`
+ * (HOST int32[4], (block, p, q, r) as options.items) in `precision`, and
+ * writes W over the item's full virtual cube to `w` (DEVICE FP64,
+ * row-major): [a][b][c] with v_s^3 entries for a same-spin block, [a][b][C]
+ * with v_s * v_s * v_t entries for a mixed one (a, b of the pair's spin s,
+ * C of the odd index's spin t).  W is formed from the contraction outputs
+ * exactly as the energy epilogues read them (the unique virtual range), and
+ * extended by its antisymmetry in the virtual indices of equal spin (zero
+ * where two of them coincide).  The item's energy goes to `e_out` (DEVICE,
+ * one double).  ws / ws_bytes: as ltriples_energy with options.items = item
+ * (size from ltriples_workspace_size with those options), or NULL.  Errors
+ * as ltriples_energy; LT_EINVAL for a NULL item or w. */
+int ltriples_debug_w(const ltriples_domain* d, int32_t precision, const int32_t* item,
+                     double* w, double* e_out, void* ws, size_t ws_bytes, void* stream);
+
 /* Gradient outputs of ltriples_backward: caller-owned device FP64 buffers in
  * the layouts of the corresponding ltriples_domain inputs.  A NULL field is
  * not written.  Gradients of inputs that carry a symmetry are returned

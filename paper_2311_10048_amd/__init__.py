@@ -131,6 +131,14 @@ def load_library(path: Optional[str] = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"{p} not found: build it with `python -m paper_2311_10048_amd.build`")
+    # torch ships its own copy of the HIP runtime under the same soname; loaded
+    # first, it also serves this library, so device pointers and streams from
+    # torch are valid here.  Loading this library first would bring in the
+    # system copy as a second runtime beside torch's.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(p)
     Dp, Op = ctypes.POINTER(Domain), ctypes.POINTER(Options)
     lib.ltriples_validate.argtypes = [Dp, ctypes.c_int32, Op]
@@ -140,6 +148,8 @@ def load_library(path: Optional[str] = None):
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.ltriples_energy_noalloc.argtypes = [Dp, ctypes.c_int32, Op, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_void_p]
+    lib.ltriples_debug_w.argtypes = [Dp, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.ltriples_noalloc_capacity.argtypes = []
     lib.ltriples_noalloc_capacity.restype = ctypes.c_size_t
     Cp = ctypes.POINTER(Central)
@@ -172,7 +182,7 @@ def load_library(path: Optional[str] = None):
     lib.ltriples_last_error.restype = ctypes.c_char_p
     lib.ltriples_version.restype = ctypes.c_char_p
     for f in ("ltriples_validate", "ltriples_workspace_size", "ltriples_flops", "ltriples_energy",
-              "ltriples_energy_noalloc",
+              "ltriples_energy_noalloc", "ltriples_debug_w",
               "ltriples_workspace_size_batched", "ltriples_energy_batched", "ltriples_graph_reset",
               "ltriples_backward_workspace_size", "ltriples_backward", "ltriples_plan_check",
               "ltriples_rhf_workspace_size", "ltriples_rhf_flops", "ltriples_energy_rhf",
@@ -367,6 +377,37 @@ def ltriples_energy(tensors: Mapping[str, object], dims, precision: int = LT_FP3
     _check(code)
     del keep
     return e, parts
+
+
+def ltriples_debug_w(tensors: Mapping[str, object], dims, item, precision: int = LT_FP64, stream=None):
+    """Debug dump of one triplet's W over its full virtual cube, as the GPU
+    path forms it (see ltriples_debug_w in include/ltriples.h).
+
+    `item` = (block, p, q, r).  Returns (w, e): a float64 device tensor of
+    shape [v_s, v_s, v_s] (same spin) or [v_s, v_s, v_t] (mixed: a, b of the
+    pair's spin s, C of the odd index's spin t), and the item's energy as a
+    float64 device tensor of shape [1].  Waits for nothing beyond what
+    ltriples_energy waits for."""
+    import torch
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    it = np.ascontiguousarray(np.asarray(item, dtype=np.int32).reshape(4))
+    blk = int(it[0])
+    if blk not in (0, 1, 2, 3):
+        raise ValueError("item block must be 0..3")
+    dom = make_domain(dims, tensors)
+    nv = (int(dims[2]), int(dims[3]))
+    s = 0 if blk in (0, 1) else 1
+    shape = (nv[s], nv[s], nv[s]) if blk in (0, 3) else (nv[s], nv[s], nv[1 - s])
+    dev = _device_of(tensors)
+    w = torch.empty(shape, dtype=torch.float64, device=dev)
+    e = torch.empty(1, dtype=torch.float64, device=dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    lib = load_library()
+    code = lib.ltriples_debug_w(ctypes.byref(dom), int(precision), it.ctypes.data, w.data_ptr(), e.data_ptr(),
+                                None, 0, st.cuda_stream)
+    _check(code)
+    return w, e
 
 
 def ltriples_noalloc_capacity() -> int:

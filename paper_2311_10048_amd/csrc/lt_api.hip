@@ -254,6 +254,8 @@ struct Plan {
   // and the spin of the central orbital (-1: an ordinary energy)
   const double* lap = nullptr;
   int lap_spin = -1;
+  // debug dump (a call with a single item): that item's W cube, FP64
+  double* dump_w = nullptr;
 };
 
 // `oi` (optional): the summed occupied orbitals per spin, when they are fewer
@@ -947,6 +949,7 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
           tm.gemm.push_back({a, tm.mark()});
           tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(3 * vs + 3 * os) * (double)n;
         }
+        if (P.dump_w) HIPCHK(lt::launch_dump_w_same<T>(out1, P.ldnp[s], (int32_t)vs, P.dump_w, st));
         ea = tm.mark();
         lt::EpiSame<T> e{};
         e.o = (int32_t)os; e.v = (int32_t)vs; e.ld_np = P.ldnp[s];
@@ -975,6 +978,8 @@ int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltrip
           tm.gemm.push_back({a, tm.mark()});
           tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(2 * vs + 2 * os) * (double)n;
         }
+        if (P.dump_w)
+          HIPCHK(lt::launch_dump_w_mixed<T>(out1, P.ldcb[s], out2, P.ldnp[s], (int32_t)vs, (int32_t)vt, P.dump_w, st));
         ea = tm.mark();
         lt::EpiMixed<T> e{};
         e.o_s = (int32_t)os; e.v_s = (int32_t)vs; e.o_t = (int32_t)ot; e.v_t = (int32_t)vt;
@@ -1807,7 +1812,7 @@ int noalloc_scratch(void** out) {
 // bitwise the same for any batching and chunking), and nothing is allocated
 // (options.stats and options.autotune, which create HIP events, are refused).
 int energy_call(const ltriples_domain* d, int32_t precision, const ltriples_options* o, double* e_out,
-                double* parts, void* ws, size_t ws_bytes, hipStream_t st, bool noalloc) {
+                double* parts, void* ws, size_t ws_bytes, hipStream_t st, bool noalloc, double* dump_w = nullptr) {
   int r = validate(d, precision, o);
   if (r) return r;
   if (!e_out) return fail(LT_EINVAL, "e_out is NULL");
@@ -1819,6 +1824,7 @@ int energy_call(const ltriples_domain* d, int32_t precision, const ltriples_opti
   build_items(D, &oo, L);
   Plan P;
   plan_domain(d, precision, &oo, L, P);
+  P.dump_w = dump_w;
   if (noalloc) {
     static const int64_t budgets_mib[] = {128, 64, 32, 16, 8, 4, 2, 1};
     for (int k = 0; P.total > kNoAllocBytes && k < (int)(sizeof(budgets_mib) / sizeof(budgets_mib[0])); ++k) {
@@ -1933,6 +1939,17 @@ int ltriples_energy_noalloc(const ltriples_domain* d, int32_t precision, const l
 }
 
 size_t ltriples_noalloc_capacity(void) { return kNoAllocBytes; }
+
+int ltriples_debug_w(const ltriples_domain* d, int32_t precision, const int32_t* item, double* w,
+                     double* e_out, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!item) return fail(LT_EINVAL, "item is NULL");
+  if (!w) return fail(LT_EINVAL, "w is NULL");
+  ltriples_options o{};
+  o.items = item;
+  o.n_items = 1;
+  return energy_call(d, precision, &o, e_out, nullptr, ws, ws_bytes, (hipStream_t)stream, false, w);
+}
 
 // ---------------------------------------------------------------------------
 // Adjoint entry points

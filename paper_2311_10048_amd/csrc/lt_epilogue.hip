@@ -11,6 +11,8 @@
 // shuffles and over the work-group in LDS in a fixed order.  Each tile
 // writes its own partial, so the later per-item sums are independent of
 // scheduling.
+#include <algorithm>
+
 #include "lt_internal.h"
 
 namespace lt {
@@ -859,6 +861,70 @@ template hipError_t launch_epi_same<float>(const EpiSame<float>&, int32_t, hipSt
 template hipError_t launch_epi_same<double>(const EpiSame<double>&, int32_t, hipStream_t);
 template hipError_t launch_epi_mixed<float>(const EpiMixed<float>&, int32_t, hipStream_t);
 template hipError_t launch_epi_mixed<double>(const EpiMixed<double>&, int32_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Debug dumps of one item's W (the same formulas as the epilogues' first
+// line, over the whole cube; the antisymmetry fills the other orderings and
+// repeated virtual indices give zero)
+// ---------------------------------------------------------------------------
+__device__ inline int64_t pair_index(int lo, int hi) { return (int64_t)hi * (hi - 1) / 2 + lo; }   // lo < hi
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dump_w_same(const T* S, int64_t ldp, int32_t v, double* w) {
+  const int64_t n = (int64_t)v * v * v, vv = (int64_t)v * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    int x = (int)(e / vv), y = (int)((e / v) % v), z = (int)(e % v);
+    double sg = 1.0;
+    if (x > y) { const int t = x; x = y; y = t; sg = -sg; }
+    if (y > z) { const int t = y; y = z; z = t; sg = -sg; }
+    if (x > y) { const int t = x; x = y; y = t; sg = -sg; }
+    double val = 0.0;
+    if (x < y && y < z)   // W^{xyz} = S[x][p(y,z)] - S[y][p(x,z)] + S[z][p(x,y)]
+      val = ((double)S[x * ldp + pair_index(y, z)] - (double)S[y * ldp + pair_index(x, z)]) +
+            (double)S[z * ldp + pair_index(x, y)];
+    w[e] = sg * val;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dump_w_mixed(const T* G, int64_t lc, const T* Y, int64_t lp, int32_t vs,
+                                                      int32_t vt, double* w) {
+  const int64_t n = (int64_t)vs * vs * vt, sv = (int64_t)vs * vt;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e / sv), b = (int)((e / vt) % vs), C = (int)(e % vt);
+    const int x = a < b ? a : b, y = a < b ? b : a;
+    double val = 0.0;
+    if (x < y)            // W^{xyC} = G[x][C v + y] - G[y][C v + x] + Y[C][p(x,y)]
+      val = ((double)G[x * lc + (int64_t)C * vs + y] - (double)G[y * lc + (int64_t)C * vs + x]) +
+            (double)Y[C * lp + pair_index(x, y)];
+    w[e] = a < b ? val : -val;
+  }
+}
+
+template <typename T>
+hipError_t launch_dump_w_same(const T* S, int64_t ld_np, int32_t v, double* w, hipStream_t s) {
+  const int64_t n = (int64_t)v * v * v;
+  if (n <= 0) return hipSuccess;
+  const int nb = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL((k_dump_w_same<T>), dim3(nb), dim3(256), 0, s, S, ld_np, v, w);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dump_w_mixed(const T* G, int64_t ld_cb, const T* Y, int64_t ld_np, int32_t vs, int32_t vt,
+                               double* w, hipStream_t s) {
+  const int64_t n = (int64_t)vs * vs * vt;
+  if (n <= 0) return hipSuccess;
+  const int nb = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL((k_dump_w_mixed<T>), dim3(nb), dim3(256), 0, s, G, ld_cb, Y, ld_np, vs, vt, w);
+  return hipGetLastError();
+}
+template hipError_t launch_dump_w_same<float>(const float*, int64_t, int32_t, double*, hipStream_t);
+template hipError_t launch_dump_w_same<double>(const double*, int64_t, int32_t, double*, hipStream_t);
+template hipError_t launch_dump_w_mixed<float>(const float*, int64_t, const float*, int64_t, int32_t, int32_t,
+                                               double*, hipStream_t);
+template hipError_t launch_dump_w_mixed<double>(const double*, int64_t, const double*, int64_t, int32_t, int32_t,
+                                                double*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Deterministic reductions

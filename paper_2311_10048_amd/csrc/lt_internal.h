@@ -228,6 +228,13 @@ hipError_t launch_pack_pairs(Tout* out, int64_t ldo, int64_t rows, int32_t n,
 
 template <typename T> hipError_t launch_epi_same(const EpiSame<T>& a, int32_t nitems, hipStream_t s);
 template <typename T> hipError_t launch_epi_mixed(const EpiMixed<T>& a, int32_t nitems, hipStream_t s);
+// Debug dumps of one item's W over its full virtual cube (FP64, row-major),
+// formed from the contraction outputs exactly as the epilogues read them:
+// same spin from S (v^3 entries), mixed from G and Y (v_s * v_s * v_t).
+template <typename T> hipError_t launch_dump_w_same(const T* S, int64_t ld_np, int32_t v, double* w,
+                                                    hipStream_t s);
+template <typename T> hipError_t launch_dump_w_mixed(const T* G, int64_t ld_cb, const T* Y, int64_t ld_np,
+                                                     int32_t vs, int32_t vt, double* w, hipStream_t s);
 
 // e_items[dst[b]][0..2] = sum over t of part[b][t][0..2] (fixed order)
 hipError_t launch_reduce_items(const double* part, int32_t nitems, int32_t ntiles,

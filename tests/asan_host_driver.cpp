@@ -143,6 +143,16 @@ int main() {
     ltriples_central c{0, placeholder, 0, pts, wts};
     expect(ltriples_central_workspace_size(&d, &c, LT_FP64, nullptr, &ws), LT_EINVAL, "central nq = 0");
   }
+  // debug W dump: argument and item checks (all before any device work)
+  {
+    const int32_t sh[5] = {5, 4, 30, 31, 120};
+    ltriples_domain d = fake_domain(sh, placeholder);
+    const int32_t good[4] = {1, 0, 1, 3}, bad[4] = {0, 2, 1, 3};
+    double* wp = (double*)placeholder;
+    expect(ltriples_debug_w(&d, LT_FP64, nullptr, wp, wp, nullptr, 0, nullptr), LT_EINVAL, "debug_w null item");
+    expect(ltriples_debug_w(&d, LT_FP64, good, nullptr, wp, nullptr, 0, nullptr), LT_EINVAL, "debug_w null w");
+    expect(ltriples_debug_w(&d, LT_FP64, bad, wp, wp, nullptr, 0, nullptr), LT_ESHAPE, "debug_w bad item");
+  }
   // error paths
   expect(ltriples_validate(nullptr, LT_FP64, nullptr), LT_EINVAL, "null domain");
   expect(ltriples_rhf_workspace_size(nullptr, LT_FP64, nullptr, &ws), LT_EINVAL, "null rhf");

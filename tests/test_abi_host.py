@@ -386,3 +386,18 @@ def test_central_share_sizing_and_argument_checks():
     d0 = _fake_domain((0, 4, 30, 31, 120), null=("t1a", "t2aa", "t2ab", "Boo_a", "Bov_a", "eo_a", "fov_a"))
     assert lib.ltriples_central_workspace_size(ctypes.byref(d0), ctypes.byref(cen), lt.LT_FP64, None,
                                                ctypes.byref(n)) == lt.LT_ESHAPE
+
+
+def test_debug_w_argument_checks():
+    """ltriples_debug_w: a NULL item or output gives LT_EINVAL and an item
+    outside the domain (or not in canonical order) LT_ESHAPE, all before any
+    device work."""
+    lib = _lib()
+    d = _fake_domain((5, 4, 30, 31, 120))
+    it = (ctypes.c_int32 * 4)(0, 0, 1, 2)
+    assert lib.ltriples_debug_w(ctypes.byref(d), lt.LT_FP64, None, 0x6000, 0x7000, None, 0, None) == lt.LT_EINVAL
+    assert lib.ltriples_debug_w(ctypes.byref(d), lt.LT_FP64, it, None, 0x7000, None, 0, None) == lt.LT_EINVAL
+    for bad in ((0, 0, 0, 1), (1, 0, 1, 4), (2, 1, 0, 0), (3, 0, 1, 4), (5, 0, 1, 2)):
+        b = (ctypes.c_int32 * 4)(*bad)
+        assert lib.ltriples_debug_w(ctypes.byref(d), lt.LT_FP64, b, 0x6000, 0x7000, None, 0,
+                                    None) == lt.LT_ESHAPE, bad
