@@ -412,7 +412,8 @@ def main():
                    "sample": f"{n_c} occupied triplets ({args.cpu_sample} per spin block) of the same domain, "
                              f"{F_c:.3e} flops in {dt:.1f} s, NumPy FP64",
                    "seconds": round(dt, 2), "est_full_domain_s": round(dt * F_all / F_c, 1),
-                   "cpu_model": _cpu_model(), "single_thread": _single_thread_tiny(lt, synth)}
+                   "cpu_model": _cpu_model(), "single_thread": _single_thread_tiny(lt, synth),
+                   "single_thread_grad": _single_thread_grad(lt, synth)}
             g = e_items.cpu().numpy()[positions(itc)]
             r = ref["items"]
             tot = np.abs(g.sum(axis=1) - r.sum(axis=1)) / np.maximum(1.0, np.abs(r.sum(axis=1)))
@@ -759,6 +760,29 @@ def _cpu_model():
         pass
     import platform
     return platform.processor() or platform.machine()
+
+
+def _single_thread_grad(lt, synth):
+    """The oracle's energy with one BLAS thread on a bounded sample of the
+    gradient domain (20,18,160,162,640): one triplet per spin block, with the
+    rate scaled to the whole domain's algorithmic count."""
+    from oracle import blocks
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:
+        return None
+    dom = synth.config_domain("grad")
+    fake = lt.make_domain(dom.dims, {k: (1 << 40) for k in lt.ARRAY_FIELDS})
+    items = synth.sample_items(dom.noa, dom.nob, 1, seed=31)
+    F_s = lt.ltriples_flops(fake, lt.make_options(items=items)[0])[0]
+    F = lt.ltriples_flops(fake)[0]
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        blocks.energy(dom, items=items)
+        dt = time.perf_counter() - t
+    return {"workload": f"grad domain {dom.dims}, {len(items)} triplets (one per spin block)", "threads": 1,
+            "seconds": round(dt, 3), "GFLOP/s": round(F_s / dt / 1e9, 3),
+            "est_full_domain_s": round(dt * F / F_s, 1)}
 
 
 def _single_thread_tiny(lt, synth):
