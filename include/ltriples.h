@@ -416,22 +416,47 @@ typedef struct ltriples_rhf_domain {
 int ltriples_rhf_workspace_size(const ltriples_rhf_domain* d, int32_t precision,
                                 const ltriples_options* o, size_t* bytes);
 
-/* Host-only: W-contraction flops ltriples_energy_rhf executes (as
- * ltriples_flops counts them) and its number of items. */
+/* Host-only: W-contraction flops ltriples_energy_rhf executes,
+ * 12 nv^3 (nv + no) per unordered occupied triple, and its number of items
+ * (the unordered triples i <= j <= k that are not all equal). */
 int ltriples_rhf_flops(const ltriples_rhf_domain* d, double* flops, int64_t* n_items_out);
 
-/* Closed-shell E(T) of one domain: the spin-block energy with identical
- * alpha and beta data, E = 2 E_aaa + 2 E_aab (the bbb and abb blocks equal
- * the aaa and aab ones and are not computed).  The same-spin amplitudes
- * tau^{ab}_{ij} - tau^{ba}_{ij} are formed in the workspace.
- *   e_out  device double[1]; parts device double[3] {E4, E_ST, E_DT} or NULL
+/* Closed-shell E(T) of one domain (the closed-shell limit of the method,
+ * section "Summary and conclusions"; the SOMO-free domains of the long-range
+ * spin-polarization approximation), in the spin-adapted form over spatial
+ * orbitals: W^{abc}_{ijk} as the sum over the six joint permutations of the
+ * pairs (ia), (jb), (kc) of one connected term, and
+ * E = 1/3 sum_{ijk} sum_{abc} (4W^{abc} + W^{bca} + W^{cab})(V^{abc} - V^{cba}) / D
+ * with V = W + the t1 and f_ov disconnected terms.  Each unordered occupied
+ * triple i <= j <= k costs three contractions of nv x nv^2 outputs over
+ * 2 (nv + no) rows; the energy of all its orderings is summed over unique
+ * virtual tiles.  parts = {E4, E_ST, E_DT} from the W, t1 and f_ov parts of V.
+ *   e_out  device double[1]; parts device double[3] or NULL
  *   ws     device workspace >= ltriples_rhf_workspace_size(), or NULL
- * Precisions, batching, chunking and stats as ltriples_energy; options.items,
- * options.e_items and options.graph must be unset (LT_EINVAL).  Errors as
- * ltriples_energy. */
+ * Precisions, batching (options.batch_items, workspace_budget), build chunks,
+ * check_finite, autotune and stats as ltriples_energy; tile_override[0]
+ * forces the contraction's tile (the other entries are not used);
+ * options.items, options.e_items and options.graph must be unset (LT_EINVAL).
+ * Errors as ltriples_energy. */
 int ltriples_energy_rhf(const ltriples_rhf_domain* d, int32_t precision,
                         const ltriples_options* o, double* e_out, double* parts,
                         void* ws, size_t ws_bytes, void* stream);
+
+/* Host-only: workspace bytes of ltriples_energy_rhf_spin_block. */
+int ltriples_rhf_spin_block_workspace_size(const ltriples_rhf_domain* d, int32_t precision,
+                                           const ltriples_options* o, size_t* bytes);
+
+/* The same closed-shell E(T) through the spin-block path with identical
+ * alpha and beta data, E = 2 E_aaa + 2 E_aab (the bbb and abb blocks equal
+ * the aaa and aab ones and are not computed; about 2x the contraction work
+ * of ltriples_energy_rhf).  The same-spin amplitudes
+ * tau^{ab}_{ij} - tau^{ba}_{ij} are formed in the workspace.  Arguments,
+ * options and errors as ltriples_energy_rhf (ws sized by
+ * ltriples_rhf_spin_block_workspace_size); the adjoint
+ * ltriples_backward_rhf differentiates this form. */
+int ltriples_energy_rhf_spin_block(const ltriples_rhf_domain* d, int32_t precision,
+                                   const ltriples_options* o, double* e_out, double* parts,
+                                   void* ws, size_t ws_bytes, void* stream);
 
 /* Gradient outputs of ltriples_backward_rhf: caller-owned device FP64
  * buffers in the layouts of the ltriples_rhf_domain inputs; a NULL field is

@@ -169,6 +169,9 @@ def load_library(path: Optional[str] = None):
                                       ctypes.c_size_t, ctypes.c_void_p]
     Rp = ctypes.POINTER(RhfDomain)
     lib.ltriples_rhf_workspace_size.argtypes = [Rp, ctypes.c_int32, Op, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ltriples_rhf_spin_block_workspace_size.argtypes = [Rp, ctypes.c_int32, Op, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ltriples_energy_rhf_spin_block.argtypes = [Rp, ctypes.c_int32, Op, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.ltriples_rhf_flops.argtypes = [Rp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.ltriples_energy_rhf.argtypes = [Rp, ctypes.c_int32, Op, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
@@ -186,6 +189,7 @@ def load_library(path: Optional[str] = None):
               "ltriples_workspace_size_batched", "ltriples_energy_batched", "ltriples_graph_reset",
               "ltriples_backward_workspace_size", "ltriples_backward", "ltriples_plan_check",
               "ltriples_rhf_workspace_size", "ltriples_rhf_flops", "ltriples_energy_rhf",
+              "ltriples_rhf_spin_block_workspace_size", "ltriples_energy_rhf_spin_block",
               "ltriples_backward_rhf_workspace_size", "ltriples_backward_rhf",
               "ltriples_naf_workspace_size", "ltriples_naf", "ltriples_autotune_reset",
               "ltriples_central_workspace_size", "ltriples_energy_central"):
@@ -538,27 +542,44 @@ def ltriples_rhf_flops(dom: RhfDomain):
     return f.value, n.value
 
 
+def ltriples_rhf_spin_block_workspace_size(dom: RhfDomain, precision: int,
+                                           options: Optional[Options] = None) -> int:
+    lib = load_library()
+    n = ctypes.c_size_t(0)
+    _check(lib.ltriples_rhf_spin_block_workspace_size(ctypes.byref(dom), int(precision),
+                                                      ctypes.byref(options) if options is not None else None,
+                                                      ctypes.byref(n)))
+    return n.value
+
+
 def ltriples_energy_rhf(tensors: Mapping[str, object], dims, precision: int = LT_FP32, workspace_budget: int = 0,
                         batch_items: int = 0, workspace=None, stream=None, stats: Optional[Stats] = None,
-                        build_chunk_mib: int = 0):
+                        build_chunk_mib: int = 0, method: str = "spin_adapted", autotune: bool = False,
+                        check_finite: bool = False, tile_override=None):
     """Closed-shell E(T) of one domain given in spatial orbitals (RHF_FIELDS,
     dims (no, nv, naux)).  Returns (e, parts): float64 device tensors of
-    shapes [1] and [3] ({E4, E_ST, E_DT})."""
+    shapes [1] and [3] ({E4, E_ST, E_DT}).  `method`: "spin_adapted"
+    (ltriples_energy_rhf) or "spin_block" (ltriples_energy_rhf_spin_block)."""
     import torch
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
+    if method not in ("spin_adapted", "spin_block"):
+        raise ValueError("method must be 'spin_adapted' or 'spin_block'")
     dom = make_rhf_domain(dims, tensors)
-    opts, keep = make_options(None, None, workspace_budget, batch_items, stats, build_chunk_mib)
+    opts, keep = make_options(None, None, workspace_budget, batch_items, stats, build_chunk_mib, autotune,
+                              check_finite, tile_override)
     dev = _device_of(tensors)
-    need = ltriples_rhf_workspace_size(dom, precision, opts)
+    sa = method == "spin_adapted"
+    need = (ltriples_rhf_workspace_size if sa else ltriples_rhf_spin_block_workspace_size)(dom, precision, opts)
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     e = torch.empty(1, dtype=torch.float64, device=dev)
     parts = torch.empty(3, dtype=torch.float64, device=dev)
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     lib = load_library()
-    _check(lib.ltriples_energy_rhf(ctypes.byref(dom), int(precision), ctypes.byref(opts), e.data_ptr(),
-                                   parts.data_ptr(), workspace.data_ptr(), workspace.numel(), st.cuda_stream))
+    fn = lib.ltriples_energy_rhf if sa else lib.ltriples_energy_rhf_spin_block
+    _check(fn(ctypes.byref(dom), int(precision), ctypes.byref(opts), e.data_ptr(), parts.data_ptr(),
+              workspace.data_ptr(), workspace.numel(), st.cuda_stream))
     del keep
     return e, parts
 

@@ -2674,10 +2674,320 @@ int rhf_setup(const ltriples_rhf_domain* r, const ltriples_options* o, RhfSetup&
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Closed-shell domains, spin-adapted (the default of ltriples_energy_rhf).
+// Over spatial orbitals with tau^{ab}_{ij} = tau^{ba}_{ji}, W^{abc}_{ijk} is
+// the sum over the six joint permutations of (ia), (jb), (kc) of
+//   sum_e tau^{ae}_{ij}(ck|be) - sum_m tau^{ab}_{im}(ck|mj).
+// Grouped by the virtual index that the tau (or integral) factor carries,
+// the twelve terms form one contraction per occupied triple (p,q,r):
+//   F(p,q,r)[x][y*v+z] = sum_e tau^{xe}_{pq}(rz|ye) + sum_e tau^{xe}_{pr}(qy|ze)
+//                      - sum_m (px|mr) tau^{yz}_{qm} - sum_m (px|mq) tau^{yz}_{mr},
+// and W^{abc}_{ijk} = F(i,j,k)[a][bc] + F(j,i,k)[b][ac] + F(k,i,j)[c][ab].
+// Each unordered occupied triple i <= j <= k (all equal excluded: its
+// contribution vanishes) costs three contractions of v x v^2 outputs over
+// 2(v + o) rows, and the epilogue (lt_epilogue.hip) sums the energy of all
+// its orderings from W over unique virtual tiles.
+// ---------------------------------------------------------------------------
+namespace {
+
+enum { SA_T2T, SA_GCS, SA_TF, SA_TS, SA_RVC, SA_RVS, SA_NOP };
+
+struct SaPlan {
+  int prec = 0, bf = 0;
+  size_t ts = 8;
+  int64_t o = 0, v = 0, Q = 0, ldv = 0, ldvv = 0, ldov = 0, ldoo = 0;
+  int64_t n_items = 0, nb = 0, nt = 0, ntiles = 0, cRV = 1;
+  size_t cube = 0;                              // elements per contraction output cube
+  Buf BvvP, BovR, BovP64, BooP64, OV64, op[SA_NOP], stage, O8h[SA_NOP], O8l[SA_NOP];
+  Buf scratch;                                  // builds: (ov|oo); batches: cubes, then partials
+  size_t part_off = 0;
+  Buf items, fitems, dst, e_items, fc, parts, flag, segtab;
+  size_t total = 0;
+};
+
+int64_t sa_items(int64_t o) { return o <= 1 ? 0 : o * (o + 1) * (o + 2) / 6 - o; }
+
+void sa_plan(const ltriples_rhf_domain* r, int32_t prec, const ltriples_options* o, SaPlan& P) {
+  P.prec = prec;
+  P.ts = prec == LT_FP64 ? 8 : 4;
+  P.bf = prec == LT_BF16X3 ? 3 : (prec == LT_BF16 ? 1 : 0);
+  P.o = r->no; P.v = r->nv; P.Q = r->naux;
+  const int64_t no = P.o, v = P.v, Q = P.Q;
+  const size_t ts = P.ts;
+  P.ldv = ld4(v); P.ldvv = ld4(v * v); P.ldov = ld4(no * v); P.ldoo = ld4(no * no);
+  P.n_items = sa_items(no);
+  P.nt = cdiv(v, lt::ET);
+  P.ntiles = P.nt * (P.nt + 1) / 2;
+  P.cube = (size_t)((v * v * v + 63) & ~int64_t(63));
+  const size_t cap = (size_t)((o && o->build_chunk_mib > 0) ? o->build_chunk_mib : 2048) << 20;
+  P.cRV = std::max<int64_t>(1, std::min<int64_t>(no, (int64_t)(cap / std::max<size_t>(ts * v * P.ldvv, 1))));
+  size_t off = 0;
+  auto take = [&](Buf& b, size_t bytes) { b.off = off; b.bytes = bytes; off = align256(off + bytes); };
+  take(P.BvvP, ts * Q * P.ldvv);
+  take(P.BovR, ts * no * Q * P.ldv);
+  take(P.BovP64, 8 * Q * P.ldov);
+  take(P.BooP64, 8 * Q * P.ldoo);
+  take(P.OV64, 8 * no * v * no * v);
+  // operand tensors (BF16 modes: built one by one in the staging buffer and split)
+  const size_t opb[SA_NOP] = {ts * no * no * v * P.ldv, ts * no * no * no * P.ldv, ts * no * no * P.ldvv,
+                              ts * no * no * P.ldvv, ts * no * v * P.ldvv, ts * no * v * P.ldvv};
+  if (!P.bf) {
+    for (int t = 0; t < SA_NOP; ++t) take(P.op[t], opb[t]);
+  } else {
+    size_t mx = ts * P.cRV * v * P.ldvv;
+    for (int t = 0; t < SA_RVC; ++t) mx = std::max(mx, opb[t]);
+    take(P.stage, mx);
+    for (int t = 0; t < SA_NOP; ++t) { P.op[t].off = P.stage.off; P.op[t].bytes = opb[t]; }
+    auto k16 = [](int64_t k) { return (k + 15) & ~int64_t(15); };
+    const int64_t nblk[SA_NOP] = {no * no, no * no, no, no, no, no};
+    const int64_t K[SA_NOP] = {v, no, no, no, v, v};
+    const int64_t ld[SA_NOP] = {P.ldv, P.ldv, P.ldvv, P.ldvv, P.ldvv, P.ldvv};
+    for (int t = 0; t < SA_NOP; ++t) {
+      const size_t bytes = 2 * (size_t)(nblk[t] * k16(K[t]) * ld[t]) + 2 * 8 * 512;
+      take(P.O8h[t], bytes);
+      take(P.O8l[t], bytes);
+    }
+  }
+  // batches: three cubes per item, then the per-tile partials
+  const size_t budget = (o && o->workspace_budget) ? o->workspace_budget : (size_t(8) << 30);
+  const size_t per = 3 * P.cube * ts + align256(24 * (size_t)std::max<int64_t>(P.ntiles, 1));
+  int64_t nb = (o && o->batch_items > 0) ? o->batch_items : (int64_t)std::max<size_t>(1, budget / per);
+  nb = std::min<int64_t>(nb, std::max<int64_t>(P.n_items, 1));
+  nb = std::min<int64_t>(nb, 21845);   // three contraction items each
+  P.nb = nb;
+  P.part_off = align256(3 * P.cube * ts * (size_t)nb);
+  const size_t s2 = P.part_off + 24 * (size_t)nb * (size_t)std::max<int64_t>(P.ntiles, 1);
+  const size_t s1 = 8 * (size_t)(no * v * no * no);
+  take(P.scratch, std::max<size_t>(std::max(s1, s2), 256));
+  const size_t n = (size_t)std::max<int64_t>(P.n_items, 1);
+  take(P.items, 12 * n);
+  take(P.fitems, 36 * n);
+  take(P.dst, 4 * n);
+  take(P.e_items, 24 * n);
+  take(P.fc, 64);
+  take(P.parts, 16 * 8);
+  take(P.flag, 256);
+  if (P.bf) take(P.segtab, sizeof(lt::Seg8) * 6 * 3 * (size_t)nb);
+  P.total = off;
+}
+
+template <typename T>
+int sa_prep(const ltriples_rhf_domain* r, const SaPlan& P, void* ws, hipStream_t st) {
+  const int64_t no = P.o, v = P.v, Q = P.Q, ldv = P.ldv, ldvv = P.ldvv;
+  char* scr = (char*)ws + P.scratch.off;
+  auto split = [&](int t, int64_t b0, int64_t nblk, int64_t K, int64_t ld, int64_t ncol, int64_t ibs,
+                   int64_t iks) -> hipError_t {
+    if (!P.bf) return hipSuccess;
+    const int64_t blk = ((K + 15) / 16) * 16 * ld;
+    return lt::launch_split8(at<lt::bf16_t>(ws, P.O8h[t]) + b0 * blk, at<lt::bf16_t>(ws, P.O8l[t]) + b0 * blk, nblk,
+                             (int32_t)K, ld, (int32_t)ncol, at<float>(ws, P.stage), ibs, iks, st);
+  };
+  // DF factor layouts
+  HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.BvvP), 0, 0, ldvv, 1, 1, Q, v * v, r->Bvv, 0, 0, v * v, 1,
+                                      nullptr, 0, 0, 0, 0, st));
+  HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.BovR), 0, Q * ldv, ldv, 1, no, Q, v, r->Bov, 0, v, no * v, 1,
+                                      nullptr, 0, 0, 0, 0, st));
+  HIPCHK(lt::launch_copy4d<double, double>(at<double>(ws, P.BovP64), 0, 0, P.ldov, 1, 1, Q, no * v, r->Bov, 0, 0,
+                                           no * v, 1, nullptr, 0, 0, 0, 0, st));
+  HIPCHK(lt::launch_copy4d<double, double>(at<double>(ws, P.BooP64), 0, 0, P.ldoo, 1, 1, Q, no * no, r->Boo, 0, 0,
+                                           no * no, 1, nullptr, 0, 0, 0, 0, st));
+  auto gemm64 = [&](int64_t M, int64_t N, const double* Lp, int64_t lks, const double* Rp, int64_t rks,
+                    double* out, int64_t ldo) -> hipError_t {
+    lt::GemmArgs<double> g{};
+    g.M = (int32_t)M; g.N = (int32_t)N; g.nbatch = 1; g.mode = 0;
+    g.out = out; g.s_mr = ldo; g.s_nr = 1;
+    g.L = Lp; g.lks = lks; g.R = Rp; g.rks = rks; g.K = (int32_t)Q;
+    return lt::launch_gemm<double>(g, st);
+  };
+  auto gemmT = [&](int64_t M, int64_t N, int64_t nbatch, const T* Lp, int64_t lks, int64_t lbs, const T* Rp,
+                   int64_t rks, int64_t rbs, T* out, int64_t obs, int64_t s_mq, int64_t s_mr, int32_t mdiv,
+                   int64_t s_nq, int64_t s_nr, int32_t ndiv) -> hipError_t {
+    lt::GemmArgs<T> g{};
+    g.M = (int32_t)M; g.N = (int32_t)N; g.nbatch = (int32_t)nbatch; g.mode = 0;
+    g.out = out; g.obs = obs; g.s_mq = s_mq; g.s_mr = s_mr; g.mdiv = mdiv; g.s_nq = s_nq; g.s_nr = s_nr; g.ndiv = ndiv;
+    g.L = Lp; g.lks = lks; g.lbs = lbs; g.R = Rp; g.rks = rks; g.rbs = rbs; g.K = (int32_t)Q;
+    return lt::launch_gemm<T>(g, st);
+  };
+  // (ia|jb) as [o][v][o][v] for the epilogue; (ka|mj) as [k][a][m][j] for Gcs
+  HIPCHK(gemm64(no * v, no * v, at<double>(ws, P.BovP64), P.ldov, at<double>(ws, P.BovP64), P.ldov,
+                at<double>(ws, P.OV64), no * v));
+  double* OO = (double*)scr;
+  HIPCHK(gemm64(no * v, no * no, at<double>(ws, P.BovP64), P.ldov, at<double>(ws, P.BooP64), P.ldoo, OO, no * no));
+  // Gcs[x][y][m][a] = (ya|mx) = OO[y][a][m][x]
+  HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.op[SA_GCS]), no * no * ldv, no * ldv, ldv, no, no, no, v, OO, 1,
+                                      v * no * no, no, no * no, nullptr, 0, 0, 0, 0, st));
+  HIPCHK(split(SA_GCS, 0, no * no, no, ldv, v, no * ldv, ldv));
+  // T2T[i][j][e][a] = tau[i][j][a][e]
+  HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.op[SA_T2T]), no * v * ldv, v * ldv, ldv, no, no, v, v, r->tau,
+                                      no * v * v, v * v, 1, v, nullptr, 0, 0, 0, 0, st));
+  HIPCHK(split(SA_T2T, 0, no * no, v, ldv, v, v * ldv, ldv));
+  // Tf[x][m][b*v+c] = tau[x][m][b][c];  Ts[x][m][b*v+c] = tau[m][x][b][c]
+  HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.op[SA_TF]), no * ldvv, ldvv, v, no, no, v, v, r->tau, no * v * v,
+                                      v * v, v, 1, nullptr, 0, 0, 0, 0, st));
+  HIPCHK(split(SA_TF, 0, no, no, ldvv, v * v, no * ldvv, ldvv));
+  HIPCHK(lt::launch_copy4d<double, T>(at<T>(ws, P.op[SA_TS]), no * ldvv, ldvv, v, no, no, v, v, r->tau, v * v,
+                                      no * v * v, v, 1, nullptr, 0, 0, 0, 0, st));
+  HIPCHK(split(SA_TS, 0, no, no, ldvv, v * v, no * ldvv, ldvv));
+  // RVc[r][e][b*v+c] = (rc|be): rows (e,b), cols c; chunks of r
+  for (int64_t r0 = 0; r0 < no; r0 += P.cRV) {
+    const int64_t n = std::min<int64_t>(P.cRV, no - r0);
+    T* dst = P.bf ? at<T>(ws, P.stage) : at<T>(ws, P.op[SA_RVC]) + r0 * v * ldvv;
+    HIPCHK(gemmT(v * v, v, n, at<T>(ws, P.BvvP), ldvv, 0, at<T>(ws, P.BovR) + r0 * Q * ldv, ldv, Q * ldv, dst,
+                 v * ldvv, ldvv, v, (int32_t)v, 0, 1, 0));
+    HIPCHK(split(SA_RVC, r0, n, v, ldvv, v * v, v * ldvv, ldvv));
+  }
+  // RVs[q][e][b*v+c] = (qb|ce): rows b, cols (e,c); chunks of q
+  for (int64_t q0 = 0; q0 < no; q0 += P.cRV) {
+    const int64_t n = std::min<int64_t>(P.cRV, no - q0);
+    T* dst = P.bf ? at<T>(ws, P.stage) : at<T>(ws, P.op[SA_RVS]) + q0 * v * ldvv;
+    HIPCHK(gemmT(v, v * v, n, at<T>(ws, P.BovR) + q0 * Q * ldv, ldv, Q * ldv, at<T>(ws, P.BvvP), ldvv, 0, dst,
+                 v * ldvv, 0, v, 0, ldvv, 1, (int32_t)v));
+    HIPCHK(split(SA_RVS, q0, n, v, ldvv, v * v, v * ldvv, ldvv));
+  }
+  return LT_OK;
+}
+
+template <typename T>
+int sa_run(const ltriples_rhf_domain* r, const SaPlan& P, const ltriples_options* o, double* e_out, double* parts,
+           void* ws, hipStream_t st, Timing& tm) {
+  const int64_t no = P.o, v = P.v;
+  int32_t* d_items = at<int32_t>(ws, P.items);
+  int32_t* d_fitems = at<int32_t>(ws, P.fitems);
+  int32_t* d_dst = at<int32_t>(ws, P.dst);
+  int32_t* d_fc = at<int32_t>(ws, P.fc);
+  double* e_items = at<double>(ws, P.e_items);
+  double* parts16 = at<double>(ws, P.parts);
+  tm.start = tm.mark();
+  if (P.n_items == 0 || v == 0) {
+    HIPCHK(lt::launch_zero(e_out, 1, st));
+    if (parts) HIPCHK(lt::launch_zero(parts, 3, st));
+    tm.setup_end = tm.mark();
+    tm.end = tm.setup_end;
+    return LT_OK;
+  }
+  HIPCHK(lt::launch_zero(e_items, 3 * P.n_items, st));
+  {
+    const int rr = sa_prep<T>(r, P, ws, st);
+    if (rr) return rr;
+  }
+  tm.setup_end = tm.mark();
+  lt::ItemOps<T> ops{};
+  ops.kind = 3;
+  ops.o_s = ops.o_t = (int32_t)no; ops.v_s = ops.v_t = (int32_t)v; ops.oi_s = ops.oi_t = (int32_t)no;
+  ops.ld_vs = ops.ld_vt = P.ldv; ops.ld_vv = P.ldvv;
+  ops.T2T = at<T>(ws, P.op[SA_T2T]); ops.Gcs = at<T>(ws, P.op[SA_GCS]); ops.Tf = at<T>(ws, P.op[SA_TF]);
+  ops.Ts = at<T>(ws, P.op[SA_TS]); ops.RVc = at<T>(ws, P.op[SA_RVC]); ops.RVs = at<T>(ws, P.op[SA_RVS]);
+  lt::ItemOps8 o8{};
+  if (P.bf) {
+    o8.kind = 3;
+    o8.o_s = o8.o_t = (int32_t)no; o8.v_s = o8.v_t = (int32_t)v; o8.oi_s = o8.oi_t = (int32_t)no;
+    o8.ld_vs = o8.ld_vt = P.ldv; o8.ld_vv = P.ldvv;
+    auto H = [&](int t) { return at<lt::bf16_t>(ws, P.O8h[t]); };
+    auto Lo = [&](int t) { return at<lt::bf16_t>(ws, P.O8l[t]); };
+    o8.T2Th = H(SA_T2T); o8.T2Tl = Lo(SA_T2T); o8.Gcsh = H(SA_GCS); o8.Gcsl = Lo(SA_GCS);
+    o8.Tfh = H(SA_TF); o8.Tfl = Lo(SA_TF); o8.Tsh = H(SA_TS); o8.Tsl = Lo(SA_TS);
+    o8.RVch = H(SA_RVC); o8.RVcl = Lo(SA_RVC); o8.RVsh = H(SA_RVS); o8.RVsl = Lo(SA_RVS);
+  }
+  const int force = o ? o->tile_override[0] - 1 : -1;
+  const bool tune = o && o->autotune;
+  char* scr = (char*)ws + P.scratch.off;
+  T* cubes = (T*)scr;
+  double* part = (double*)(scr + P.part_off);
+  for (int64_t first = 0; first < P.n_items; first += P.nb) {
+    const int64_t n = std::min<int64_t>(P.nb, P.n_items - first);
+    const int32_t* fit = d_fitems + 9 * first;
+    {
+      hipEvent_t ea = tm.mark();
+      if (!P.bf) {
+        lt::GemmArgs<T> g{};
+        g.M = (int32_t)v; g.N = (int32_t)(v * v); g.nbatch = (int32_t)(3 * n); g.mode = 1;
+        g.out = cubes; g.obs = (int64_t)P.cube; g.s_mr = v * v; g.s_nr = 1;
+        g.ops = ops;
+        g.ops.items = fit;
+        HIPCHK(lt::launch_gemm<T>(g, st, tune, force));
+      } else {
+        lt::Seg8* tab = at<lt::Seg8>(ws, P.segtab);
+        lt::ItemOps8 t8 = o8;
+        t8.items = fit;
+        HIPCHK(lt::launch_seg8_table(t8, (int32_t)(3 * n), tab, st));
+        lt::GemmArgs16 h{};
+        h.M = (int32_t)v; h.N = (int32_t)(v * v); h.nbatch = (int32_t)(3 * n); h.nprod = P.bf;
+        h.out = (float*)cubes; h.obs = (int64_t)P.cube; h.ldo = v * v; h.kind = 3; h.tab = tab;
+        HIPCHK(lt::launch_gemm_bf16(h, st, tune, force));
+      }
+      tm.gemm.push_back({ea, tm.mark()});
+      tm.gemm_flops += 2.0 * (double)v * (double)(v * v) * (double)(2 * v + 2 * no) * (double)(3 * n);
+    }
+    hipEvent_t eb = tm.mark();
+    HIPCHK(lt::launch_rhf_w<T>(cubes, (int64_t)P.cube, (int32_t)v, (int32_t)n, st));
+    lt::EpiRhf<T> e{};
+    e.o = (int32_t)no; e.v = (int32_t)v; e.nt = (int32_t)P.nt; e.ntiles = (int32_t)P.ntiles;
+    e.W = cubes; e.w_item = 3 * (int64_t)P.cube; e.items = d_items + 3 * first;
+    e.eo = r->eo; e.ev = r->ev; e.t1 = r->t1; e.f = r->fov; e.tau = r->tau; e.ov = at<double>(ws, P.OV64);
+    e.part = part;
+    HIPCHK(lt::launch_epi_rhf<T>(e, (int32_t)n, st));
+    HIPCHK(lt::launch_reduce_items(part, (int32_t)n, (int32_t)P.ntiles, d_dst + first, e_items, st));
+    tm.epi.push_back({eb, tm.mark()});
+  }
+  HIPCHK(lt::launch_reduce_final(e_items, d_dst, d_fc, d_fc + 4, parts16, e_out, st));
+  if (parts)
+    HIPCHK(lt::launch_copy4d<double, double>(parts, 0, 0, 0, 1, 1, 1, 3, parts16, 0, 0, 0, 1, nullptr, 0, 0, 0, 0, st));
+  tm.end = tm.mark();
+  return LT_OK;
+}
+
+// Host tables of the spin-adapted path: the items (i <= j <= k, not all
+// equal), their three contraction triples, identity destinations and the
+// single-block counts of the final reduction.
+int sa_upload(const SaPlan& P, void* ws, hipStream_t st) {
+  std::vector<int32_t> it, fit, dst;
+  it.reserve(3 * (size_t)P.n_items);
+  fit.reserve(9 * (size_t)P.n_items);
+  for (int32_t i = 0; i < P.o; ++i)
+    for (int32_t j = i; j < P.o; ++j)
+      for (int32_t k = j; k < P.o; ++k) {
+        if (i == k) continue;              // i == j == k
+        it.insert(it.end(), {i, j, k});
+        fit.insert(fit.end(), {i, j, k, j, i, k, k, i, j});
+      }
+  dst.resize((size_t)P.n_items);
+  for (int64_t n = 0; n < P.n_items; ++n) dst[(size_t)n] = (int32_t)n;
+  int32_t fc[8] = {0, 0, 0, 0, (int32_t)P.n_items, 0, 0, 0};
+  if (P.n_items > 0) {
+    HIPCHK(hipMemcpyAsync(at<int32_t>(ws, P.items), it.data(), 4 * it.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(at<int32_t>(ws, P.fitems), fit.data(), 4 * fit.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(at<int32_t>(ws, P.dst), dst.data(), 4 * dst.size(), hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(hipMemcpyAsync(at<int32_t>(ws, P.fc), fc, sizeof(fc), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return LT_OK;
+}
+
+int sa_scan_finite(const ltriples_rhf_domain* r, const SaPlan& P, void* ws, hipStream_t st) {
+  const int64_t no = r->no, nv = r->nv, Q = r->naux;
+  lt::FiniteScan a{};
+  const struct { const double* p; int64_t n; } ps[] = {
+      {r->t1, no * nv}, {r->tau, no * no * nv * nv}, {r->Boo, Q * no * no}, {r->Bov, Q * no * nv},
+      {r->Bvv, Q * nv * nv}, {r->eo, no}, {r->ev, nv}, {r->fov, no * nv}};
+  for (const auto& x : ps)
+    if (x.n > 0) { a.p[a.narr] = x.p; a.n[a.narr] = x.n; ++a.narr; }
+  int32_t* flag = at<int32_t>(ws, P.flag);
+  HIPCHK(lt::launch_zero32(flag, 1, st));
+  HIPCHK(lt::launch_scan_finite(a, flag, st));
+  int32_t h = 0;
+  HIPCHK(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (h) return fail(LT_ENONFINITE, "NaN or infinity in the inputs (options.check_finite)");
+  return LT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
-int ltriples_rhf_workspace_size(const ltriples_rhf_domain* d, int32_t precision, const ltriples_options* o,
-                                size_t* bytes) {
+int ltriples_rhf_spin_block_workspace_size(const ltriples_rhf_domain* d, int32_t precision,
+                                           const ltriples_options* o, size_t* bytes) {
   g_err.clear();
   if (!bytes) return fail(LT_EINVAL, "bytes is NULL");
   RhfSetup S;
@@ -2690,17 +3000,84 @@ int ltriples_rhf_workspace_size(const ltriples_rhf_domain* d, int32_t precision,
   return LT_OK;
 }
 
+int ltriples_rhf_workspace_size(const ltriples_rhf_domain* d, int32_t precision, const ltriples_options* o,
+                                size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(LT_EINVAL, "bytes is NULL");
+  RhfSetup S;
+  int r = rhf_setup(d, o, S);
+  if (r) return r;
+  r = validate(&S.d, precision, nullptr);
+  if (r) return r;
+  r = validate_options(o);
+  if (r) return r;
+  SaPlan P;
+  sa_plan(d, precision, o, P);
+  *bytes = P.total;
+  return LT_OK;
+}
+
 int ltriples_rhf_flops(const ltriples_rhf_domain* d, double* flops, int64_t* n_items_out) {
   g_err.clear();
   if (!flops) return fail(LT_EINVAL, "NULL argument");
   RhfSetup S;
   const int r = rhf_setup(d, nullptr, S);
   if (r) return r;
-  return ltriples_flops(&S.d, &S.o, flops, n_items_out);
+  const double no = (double)d->no, nv = (double)d->nv;
+  const int64_t n = sa_items(d->no);
+  *flops = (double)n * 3.0 * 2.0 * nv * nv * nv * (2.0 * nv + 2.0 * no);
+  if (n_items_out) *n_items_out = n;
+  return LT_OK;
 }
 
 int ltriples_energy_rhf(const ltriples_rhf_domain* rd, int32_t precision, const ltriples_options* o,
                         double* e_out, double* parts, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  RhfSetup S;
+  int r = rhf_setup(rd, o, S);
+  if (r) return r;
+  if (!e_out) return fail(LT_EINVAL, "e_out is NULL");
+  r = validate(&S.d, precision, nullptr);
+  if (r) return r;
+  r = validate_options(o);
+  if (r) return r;
+  SaPlan P;
+  sa_plan(rd, precision, o, P);
+  hipStream_t st = (hipStream_t)stream;
+  r = check_denominators(&S.d, st);   // before anything is allocated or enqueued
+  if (r) return r;
+  OwnedWs own;
+  r = get_ws(ws, ws_bytes, P.total, st, own);
+  if (r) return r;
+  r = sa_upload(P, ws, st);
+  if (r) return r;
+  if (o && o->check_finite) {
+    r = sa_scan_finite(rd, P, ws, st);
+    if (r) return r;
+  }
+  Timing tm;
+  tm.on = o && o->stats;
+  tm.st = st;
+  if (precision == LT_FP64) r = sa_run<double>(rd, P, o, e_out, parts, ws, st, tm);
+  else r = sa_run<float>(rd, P, o, e_out, parts, ws, st, tm);
+  if (r == LT_OK && tm.on) {
+    HIPCHK(hipStreamSynchronize(st));
+    ltriples_stats* St = o->stats;
+    *St = ltriples_stats{};
+    St->total_ms = Timing::ms(tm.start, tm.end);
+    St->setup_ms = Timing::ms(tm.start, tm.setup_end);
+    for (auto& x : tm.gemm) St->triples_gemm_ms += Timing::ms(x.first, x.second);
+    for (auto& x : tm.epi) St->epilogue_ms += Timing::ms(x.first, x.second);
+    St->triples_gemm_launches = (int64_t)tm.gemm.size();
+    St->triples_gemm_flops = tm.gemm_flops;
+    St->algorithmic_flops = tm.gemm_flops;
+    St->n_items = P.n_items;
+  }
+  return r;
+}
+
+int ltriples_energy_rhf_spin_block(const ltriples_rhf_domain* rd, int32_t precision, const ltriples_options* o,
+                                   double* e_out, double* parts, void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
   RhfSetup S;
   int r = rhf_setup(rd, o, S);

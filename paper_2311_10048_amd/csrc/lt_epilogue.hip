@@ -863,6 +863,221 @@ template hipError_t launch_epi_mixed<float>(const EpiMixed<float>&, int32_t, hip
 template hipError_t launch_epi_mixed<double>(const EpiMixed<double>&, int32_t, hipStream_t);
 
 // ---------------------------------------------------------------------------
+// Closed-shell (spin-adapted) triples.  With spatial orbitals and
+// tau^{ab}_{ij} = tau^{ba}_{ji}, W^{abc}_{ijk} is invariant under a joint
+// permutation of the pairs (ia), (jb), (kc), and the energy of one occupied
+// triple i <= j <= k (with all its distinct orderings) is
+//   (m/3) sum over ordered (a,b,c) of Y^{abc} (W + V_t1 + V_f)^{abc} / D^{abc},
+//   Y^{abc} = 4W^{abc} + W^{bca} + W^{cab} - 2W^{acb} - 2W^{bac} - 2W^{cba},
+// m the number of distinct orderings of (i,j,k): the closed-shell energy
+// expression summed over the orderings of the occupied triple and written
+// as one symmetric form in the six orderings of (a,b,c).  A work-group takes
+// the tiles a-tile <= b-tile <= c-tile and, for each (a,b,c) in them, adds
+// all six orderings with weight 1/(number of tile permutations that map the
+// tile onto itself), which counts every ordered (a,b,c) once with no test on
+// repeated indices.
+// ---------------------------------------------------------------------------
+
+// W[a][b][c] = A[a][b][c] + B[b][a][c] + C[c][a][b] (C transposed through LDS),
+// in place of A; one work-group per (item, a, 32x32 tile of (b, c)).
+template <typename T>
+__global__ __launch_bounds__(256) void k_rhf_w(T* X, int64_t cube, int32_t v, int32_t nbt) {
+  __shared__ T s[32][33];
+  const int item = blockIdx.z, a = blockIdx.y;
+  const int b0 = (blockIdx.x / nbt) * 32, c0 = (blockIdx.x % nbt) * 32;
+  T* A = X + (int64_t)(3 * item) * cube;
+  const T* B = A + cube;
+  const T* C = A + 2 * cube;
+  const int64_t vv = (int64_t)v * v;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = c0 + ty + 8 * u, b = b0 + tx;
+    s[ty + 8 * u][tx] = (c < v && b < v) ? C[c * vv + (int64_t)a * v + b] : (T)0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int b = b0 + ty + 8 * u, c = c0 + tx;
+    if (b < v && c < v) {
+      const int64_t o = (int64_t)a * vv + (int64_t)b * v + c;
+      A[o] = (A[o] + B[(int64_t)b * vv + (int64_t)a * v + c]) + s[tx][ty + 8 * u];
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_rhf_w(T* X, int64_t cube, int32_t v, int32_t nitems, hipStream_t s) {
+  if (nitems <= 0 || v <= 0) return hipSuccess;
+  if (nitems > 65535 || v > 65535) return hipErrorInvalidValue;
+  const int nbt = (v + 31) / 32;
+  hipLaunchKernelGGL((k_rhf_w<T>), dim3(nbt * nbt, v, nitems), dim3(256), 0, s, X, cube, v, nbt);
+  return hipGetLastError();
+}
+template hipError_t launch_rhf_w<float>(float*, int64_t, int32_t, int32_t, hipStream_t);
+template hipError_t launch_rhf_w<double>(double*, int64_t, int32_t, int32_t, hipStream_t);
+
+// One work-group per (item, a-tile <= b-tile) walks the c-tiles from the
+// b-tile on; thread (b, c) = (tid >> 4, tid & 15) of a tile loops over the
+// a-tile in two halves.  W at (a,b,c) and (b,a,c) is read directly (runs
+// along c); the other four orderings and the (ia|jb), tau blocks with an
+// a index are staged in LDS per half; the (b, c) values are the thread's.
+// Pair q of the occupied triple: 0 (i,j), 1 (j,i), 2 (i,k), 3 (k,i),
+// 4 (j,k), 5 (k,j); J_q[x][y] = (p x|p' y), Tq[x][y] = tau^{xy}_{p p'}.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_epi_rhf(EpiRhf<T> a) {
+  constexpr int HA = ET / 2, S1 = ET + 1;
+  __shared__ T P1[HA][ET][S1], P2[HA][ET][S1], P3[HA][ET][S1], P4[HA][ET][S1];   // [ta][tc][tb]
+  __shared__ double Jab[6][HA][S1], Jac[6][HA][S1], Tab[6][HA][S1], Tac[6][HA][S1];
+  __shared__ double t1a[3][HA], fa[3][HA], eva[HA];
+
+  const int tid = threadIdx.x;
+  const int L = xcd_logical(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int pi = L % gridDim.x;
+  int TB = 0;
+  while ((TB + 1) * (TB + 2) / 2 <= pi) ++TB;
+  const int TA = pi - TB * (TB + 1) / 2;
+  const int item = L / gridDim.x;
+  const int32_t* it = a.items + 3 * item;
+  const int occ[3] = {it[0], it[1], it[2]};
+  const int v = a.v, o = a.o;
+  const int64_t vv = (int64_t)v * v, ovv = (int64_t)o * v;
+  const int pq[6][2] = {{occ[0], occ[1]}, {occ[1], occ[0]}, {occ[0], occ[2]},
+                        {occ[2], occ[0]}, {occ[1], occ[2]}, {occ[2], occ[1]}};
+  const T* W = a.W + (int64_t)item * a.w_item;
+  const int a0 = TA * ET, b0 = TB * ET;
+  const int tb = tid >> 4, tc = tid & 15;
+  const int b = b0 + tb;
+  const bool bok = b < v;
+  double t1b[3], fb[3];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    t1b[x] = bok ? a.t1[(int64_t)occ[x] * v + b] : 0.0;
+    fb[x] = bok ? a.f[(int64_t)occ[x] * v + b] : 0.0;
+  }
+  const double eijk = (a.eo[occ[0]] + a.eo[occ[1]]) + a.eo[occ[2]];
+  const double evb = bok ? a.ev[b] : 0.0;
+
+  double e4 = 0.0, est = 0.0, edt = 0.0;
+  for (int TC = TB; TC < a.nt; ++TC) {
+    const int c0 = TC * ET, c = c0 + tc;
+    const bool ok = bok && c < v;
+    // 1 / (permutations of the tile triple onto itself)
+    const double wt = (TA == TB && TB == TC) ? 1.0 / 6.0 : ((TA == TB || TB == TC) ? 0.5 : 1.0);
+    double Jbc[6], Tbc[6], t1c[3], fc[3];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      Jbc[q] = ok ? a.ov[(int64_t)pq[q][0] * ovv * v + (int64_t)b * ovv + (int64_t)pq[q][1] * v + c] : 0.0;
+      Tbc[q] = ok ? a.tau[((int64_t)pq[q][0] * o + pq[q][1]) * vv + (int64_t)b * v + c] : 0.0;
+    }
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+      t1c[x] = ok ? a.t1[(int64_t)occ[x] * v + c] : 0.0;
+      fc[x] = ok ? a.f[(int64_t)occ[x] * v + c] : 0.0;
+    }
+    const double dbc = eijk - evb - (ok ? a.ev[c] : 0.0);
+    for (int h = 0; h < 2; ++h) {
+      const int ah = a0 + h * HA;
+      __syncthreads();               // the previous half's LDS reads are done
+#pragma unroll 2
+      for (int u = 0; u < HA; ++u) {
+        const int e = tid + 256 * u;
+        {   // P1[ta][tc][tb] = W[a][c][b], runs along b
+          const int x = e >> 8, y = (e >> 4) & 15, z = e & 15;
+          const int aa = ah + x, cc = c0 + y, bb = b0 + z;
+          P1[x][y][z] = (aa < v && cc < v && bb < v) ? W[aa * vv + (int64_t)cc * v + bb] : (T)0;
+        }
+        {   // P2[ta][tc][tb] = W[c][a][b], runs along b
+          const int y = e >> 7, x = (e >> 4) & 7, z = e & 15;
+          const int aa = ah + x, cc = c0 + y, bb = b0 + z;
+          P2[x][y][z] = (aa < v && cc < v && bb < v) ? W[cc * vv + (int64_t)aa * v + bb] : (T)0;
+        }
+        {   // P3[ta][tc][tb] = W[b][c][a], runs along a
+          const int z = e >> 7, y = (e >> 3) & 15, x = e & 7;
+          const int aa = ah + x, cc = c0 + y, bb = b0 + z;
+          P3[x][y][z] = (aa < v && cc < v && bb < v) ? W[bb * vv + (int64_t)cc * v + aa] : (T)0;
+        }
+        {   // P4[ta][tc][tb] = W[c][b][a], runs along a
+          const int y = e >> 7, z = (e >> 3) & 15, x = e & 7;
+          const int aa = ah + x, cc = c0 + y, bb = b0 + z;
+          P4[x][y][z] = (aa < v && cc < v && bb < v) ? W[cc * vv + (int64_t)bb * v + aa] : (T)0;
+        }
+      }
+      for (int e = tid; e < 6 * HA * ET; e += 256) {
+        const int q = e / (HA * ET), r = e % (HA * ET), x = r >> 4, z = r & 15;
+        const int aa = ah + x, bb = b0 + z, cc = c0 + z;
+        const int64_t p0 = pq[q][0], p1 = pq[q][1];
+        const bool ab = aa < v && bb < v, ac = aa < v && cc < v;
+        Jab[q][x][z] = ab ? a.ov[p0 * ovv * v + (int64_t)aa * ovv + p1 * v + bb] : 0.0;
+        Jac[q][x][z] = ac ? a.ov[p0 * ovv * v + (int64_t)aa * ovv + p1 * v + cc] : 0.0;
+        Tab[q][x][z] = ab ? a.tau[(p0 * o + p1) * vv + (int64_t)aa * v + bb] : 0.0;
+        Tac[q][x][z] = ac ? a.tau[(p0 * o + p1) * vv + (int64_t)aa * v + cc] : 0.0;
+      }
+      if (tid < 3 * HA) {
+        const int x = tid / HA, ta = tid % HA, aa = ah + ta;
+        t1a[x][ta] = aa < v ? a.t1[(int64_t)occ[x] * v + aa] : 0.0;
+        fa[x][ta] = aa < v ? a.f[(int64_t)occ[x] * v + aa] : 0.0;
+      } else if (tid < 4 * HA) {
+        const int ta = tid - 3 * HA, aa = ah + ta;
+        eva[ta] = aa < v ? a.ev[aa] : 0.0;
+      }
+      __syncthreads();
+      if (!ok) continue;
+      const int na = min(HA, v - ah);
+      for (int ta = 0; ta < na; ++ta) {
+        const int aa = ah + ta;
+        const double w0 = (double)W[aa * vv + (int64_t)b * v + c];      // abc
+        const double w2 = (double)W[b * vv + (int64_t)aa * v + c];      // bac
+        const double w1 = (double)P1[ta][tc][tb];                       // acb
+        const double w4 = (double)P2[ta][tc][tb];                       // cab
+        const double w3 = (double)P3[ta][tc][tb];                       // bca
+        const double w5 = (double)P4[ta][tc][tb];                       // cba
+        const double se = (w0 + w3) + w4, so = (w1 + w2) + w5;
+        const double ye = se - 2.0 * so, yo = so - 2.0 * se;
+        const double y0 = 3.0 * w0 + ye, y3 = 3.0 * w3 + ye, y4 = 3.0 * w4 + ye;
+        const double y1 = 3.0 * w1 + yo, y2 = 3.0 * w2 + yo, y5 = 3.0 * w5 + yo;
+        const double ya = y0 * w0 + y1 * w1 + y2 * w2 + y3 * w3 + y4 * w4 + y5 * w5;
+        // V_t1 and V_f of the six orderings (abc, acb, bac, bca, cab, cba)
+        const double t0 = t1a[0][ta], t1_ = t1a[1][ta], t2_ = t1a[2][ta];
+        const double vt0 = t0 * Jbc[4] + t1b[1] * Jac[2][ta][tc] + t1c[2] * Jab[0][ta][tb];
+        const double vt1 = t0 * Jbc[5] + t1c[1] * Jab[2][ta][tb] + t1b[2] * Jac[0][ta][tc];
+        const double vt2 = t1b[0] * Jac[4][ta][tc] + t1_ * Jbc[2] + t1c[2] * Jab[1][ta][tb];
+        const double vt3 = t1b[0] * Jac[5][ta][tc] + t1c[1] * Jab[3][ta][tb] + t2_ * Jbc[0];
+        const double vt4 = t1c[0] * Jab[4][ta][tb] + t1_ * Jbc[3] + t1b[2] * Jac[1][ta][tc];
+        const double vt5 = t1c[0] * Jab[5][ta][tb] + t1b[1] * Jac[3][ta][tc] + t2_ * Jbc[1];
+        const double f0 = fa[0][ta], f1 = fa[1][ta], f2 = fa[2][ta];
+        const double vf0 = f0 * Tbc[4] + fb[1] * Tac[2][ta][tc] + fc[2] * Tab[0][ta][tb];
+        const double vf1 = f0 * Tbc[5] + fc[1] * Tab[2][ta][tb] + fb[2] * Tac[0][ta][tc];
+        const double vf2 = fb[0] * Tac[4][ta][tc] + f1 * Tbc[2] + fc[2] * Tab[1][ta][tb];
+        const double vf3 = fb[0] * Tac[5][ta][tc] + fc[1] * Tab[3][ta][tb] + f2 * Tbc[0];
+        const double vf4 = fc[0] * Tab[4][ta][tb] + f1 * Tbc[3] + fb[2] * Tac[1][ta][tc];
+        const double vf5 = fc[0] * Tab[5][ta][tb] + fb[1] * Tac[3][ta][tc] + f2 * Tbc[1];
+        const double yt = y0 * vt0 + y1 * vt1 + y2 * vt2 + y3 * vt3 + y4 * vt4 + y5 * vt5;
+        const double yf = y0 * vf0 + y1 * vf1 + y2 * vf2 + y3 * vf3 + y4 * vf4 + y5 * vf5;
+        const double g = wt * rcp64(dbc - eva[ta]);
+        e4 += g * ya;
+        est += g * yt;
+        edt += g * yf;
+      }
+    }
+  }
+  // m / 3 with m the number of distinct orderings of (i, j, k)
+  const double m = (occ[0] == occ[1] || occ[1] == occ[2]) ? 3.0 : 6.0;
+  const double s = m / 3.0;
+  block_write3(s * e4, s * est, s * edt, a.part + ((int64_t)item * a.ntiles + pi) * 3);
+}
+
+template <typename T>
+hipError_t launch_epi_rhf(const EpiRhf<T>& a, int32_t nitems, hipStream_t s) {
+  if (nitems <= 0 || a.ntiles <= 0) return hipSuccess;
+  if (a.ntiles != a.nt * (a.nt + 1) / 2 || nitems > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_epi_rhf<T>), dim3(a.ntiles, nitems), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_epi_rhf<float>(const EpiRhf<float>&, int32_t, hipStream_t);
+template hipError_t launch_epi_rhf<double>(const EpiRhf<double>&, int32_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
 // Debug dumps of one item's W (the same formulas as the epilogues' first
 // line, over the whole cube; the antisymmetry fills the other orderings and
 // repeated virtual indices give zero)

@@ -46,6 +46,18 @@ __device__ inline Seg<T> item_seg(const ItemOps<T>& s, int64_t i, int64_t j, int
       default: return {s.GamT + (j * o + i) * gb, lv, s.Tp + k * pb, lp, s.oi_s, 1.f};
     }
   }
+  if (s.kind == 3) {
+    // closed shell, occupied triple (p,q,r) = (i,j,k) over spatial orbitals:
+    // F[a][b*v+c] = sum_e tau^{ae}_{ij}(kc|be) + sum_e tau^{ae}_{ik}(jb|ce)
+    //             - sum_m (ia|mk) tau^{bc}_{jm} - sum_m (ia|mj) tau^{bc}_{mk}
+    const int64_t lvv = s.ld_vv;
+    switch (idx) {
+      case 0: return {s.T2T + (i * o + j) * v * lv, lv, s.RVc + k * v * lvv, lvv, (int32_t)v, 1.f};
+      case 1: return {s.T2T + (i * o + k) * v * lv, lv, s.RVs + j * v * lvv, lvv, (int32_t)v, 1.f};
+      case 2: return {s.Gcs + (k * o + i) * o * lv, lv, s.Tf + j * o * lvv, lvv, s.oi_s, -1.f};
+      default: return {s.Gcs + (j * o + i) * o * lv, lv, s.Ts + k * o * lvv, lvv, s.oi_s, -1.f};
+    }
+  }
   if (s.kind == 1) {
     // G[a][C*v+b] = sum_E t^{aE}_{iK}(jb|EC) - sum_E t^{aE}_{jK}(ib|EC) + sum_e t^{ae}_{ij}(be|KC)
     //             - sum_m <am||ij> t^{bC}_{mK} + sum_M (aj|MK) t^{bC}_{iM} - sum_M (ai|MK) t^{bC}_{jM}
@@ -116,7 +128,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& g) {
   if (g.mode == 1) {
     const int32_t* it = g.ops.items + 3 * batch;
     ti = it[0]; tj = it[1]; tk = it[2];
-    nseg = g.ops.kind == 2 ? 4 : 6;
+    nseg = g.ops.kind >= 2 ? 4 : 6;
   }
   auto seg = [&](int idx) -> Seg<T> {
     if (g.mode == 0)

@@ -25,7 +25,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 __device__ inline int64_t k16(int64_t k) { return (k + 15) & ~int64_t(15); }   // rows padded to 16
 
 // Segment idx of the contraction of triplet (i, j, k); see item_seg in
-// lt_gemm.hip for the equations (same terms, same order, same signs).
+// lt_gemm.hip for the equations (same terms, same order, same signs; kind 3
+// is the closed-shell contraction over spatial orbitals).
 // Blocks are indexed over the o_s (o_t) orbitals; occupied contraction rows
 // (K) run over the first oi_s (oi_t), and the octet blocks of those operands
 // hold exactly that many rows (padded to 16).
@@ -47,6 +48,15 @@ __device__ inline Seg8 item_seg8(const ItemOps8& s, int64_t i, int64_t j, int64_
       case 3: return mk(s.GamTh, s.GamTl, (j * o + k) * bGam, lv, s.Tph, s.Tpl, i * bTp, lp, oi, -1.f);
       case 4: return mk(s.GamTh, s.GamTl, (i * o + k) * bGam, lv, s.Tph, s.Tpl, j * bTp, lp, oi, 1.f);
       default: return mk(s.GamTh, s.GamTl, (j * o + i) * bGam, lv, s.Tph, s.Tpl, k * bTp, lp, oi, 1.f);
+    }
+  }
+  if (s.kind == 3) {
+    const int64_t lvv = s.ld_vv, bRV = kv * lvv, bTf = ko * lvv, bG = ko * lv;
+    switch (idx) {
+      case 0: return mk(s.T2Th, s.T2Tl, (i * o + j) * bT2T, lv, s.RVch, s.RVcl, k * bRV, lvv, v, 1.f);
+      case 1: return mk(s.T2Th, s.T2Tl, (i * o + k) * bT2T, lv, s.RVsh, s.RVsl, j * bRV, lvv, v, 1.f);
+      case 2: return mk(s.Gcsh, s.Gcsl, (k * o + i) * bG, lv, s.Tfh, s.Tfl, j * bTf, lvv, oi, -1.f);
+      default: return mk(s.Gcsh, s.Gcsl, (j * o + i) * bG, lv, s.Tsh, s.Tsl, k * bTf, lvv, oi, -1.f);
     }
   }
   if (s.kind == 1) {
@@ -114,7 +124,7 @@ __global__ __launch_bounds__(256, 2) void k_tgemm_bf16(GemmArgs16 g) {
   if (batch >= g.nbatch) return;                 // whole work-group: before any barrier
   const int m0 = mtile * BM, n0 = ntile * BN;
   const Seg8* tab = g.tab + (int64_t)batch * 6;   // read with wave-uniform (scalar) loads
-  const int nseg = g.kind == 2 ? 4 : 6;
+  const int nseg = g.kind >= 2 ? 4 : 6;
 
   f32x16 acc[MBW][NBW];
 #pragma unroll
@@ -276,7 +286,7 @@ __global__ __launch_bounds__(256) void k_seg8_table(ItemOps8 ops, int32_t nitems
   if (e >= (int64_t)nitems * 6) return;
   const int64_t n = e / 6;
   const int sidx = (int)(e % 6);
-  const int nseg = ops.kind == 2 ? 4 : 6;
+  const int nseg = ops.kind >= 2 ? 4 : 6;
   const int32_t* it = ops.items + 3 * n;
   Seg8 sg{};
   if (sidx < nseg) sg = item_seg8(ops, it[0], it[1], it[2], sidx);

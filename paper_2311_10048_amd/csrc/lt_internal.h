@@ -56,7 +56,7 @@ template <typename T> struct Seg {
 // Prepared operands of one spin block (sigma = spin of the same-spin pair,
 // tau = spin of the odd index of a mixed block).  All row lengths padded.
 template <typename T> struct ItemOps {
-  int32_t kind;                 // 0: S (same spin), 1: G (mixed), 2: Y (mixed)
+  int32_t kind;                 // 0: S (same spin), 1: G (mixed), 2: Y (mixed), 3: closed shell
   int32_t o_s, v_s, o_t, v_t;
   // occupied orbitals the contractions sum over (the internal m, M): the
   // first oi_s (oi_t) of the o_s (o_t) orbitals that index the operand
@@ -75,6 +75,14 @@ template <typename T> struct ItemOps {
   const T* ZpT;    // [o_s][o_t][o_t][ld_vs]   ZpT[j][K][M][a] = (aj|MK)
   const T* TmT;    // [o_s][o_t][v_s][ld_vt]   TmT[i][K][e][C] = t^{eC}_{iK}
   const T* OOT;    // [o_t][o_s][o_s][ld_vt]   OOT[K][j][m][C] = (jm|CK)
+  // closed-shell (kind 3) operands over spatial orbitals, tau the spatial
+  // amplitudes; T2T above holds T2T[i][j][e][a] = tau^{ae}_{ij}
+  int64_t ld_vv;
+  const T* RVc;    // [o][v][ld_vv]            RVc[r][e][b*v+c] = (rc|be)
+  const T* RVs;    // [o][v][ld_vv]            RVs[q][e][b*v+c] = (qb|ce)
+  const T* Tf;     // [o][o][ld_vv]            Tf[x][m][b*v+c] = tau^{bc}_{xm}
+  const T* Ts;     // [o][o][ld_vv]            Ts[x][m][b*v+c] = tau^{bc}_{mx}
+  const T* Gcs;    // [o][o][o][ld_vs]         Gcs[x][y][m][a] = (ya|mx)
   const int32_t* items;  // [n][3] occupied triplets of the batch
 };
 
@@ -113,7 +121,7 @@ struct Seg8 {
 };
 
 struct ItemOps8 {
-  int32_t kind;                          // 0: S, 1: G, 2: Y (as ItemOps)
+  int32_t kind;                          // 0: S, 1: G, 2: Y, 3: closed shell (as ItemOps)
   int32_t o_s, v_s, o_t, v_t;
   int32_t oi_s, oi_t;                    // summed occupied orbitals (as ItemOps)
   int64_t ld_vs, ld_vt, ld_np, ld_cb;
@@ -130,6 +138,13 @@ struct ItemOps8 {
   const bf16_t *ZpTh, *ZpTl;     // blk (j,K)  K oi_t ld_vs
   const bf16_t *TmTh, *TmTl;     // blk (i,K)  K v_s  ld_vt
   const bf16_t *OOTh, *OOTl;     // blk (K,j)  K oi_s ld_vt
+  // closed-shell (kind 3), as ItemOps; T2T above is the spatial one
+  int64_t ld_vv;
+  const bf16_t *RVch, *RVcl;     // blk r      K v_s  ld_vv
+  const bf16_t *RVsh, *RVsl;     // blk q      K v_s  ld_vv
+  const bf16_t *Tfh, *Tfl;       // blk x      K oi_s ld_vv
+  const bf16_t *Tsh, *Tsl;       // blk x      K oi_s ld_vv
+  const bf16_t *Gcsh, *Gcsl;     // blk (x,y)  K oi_s ld_vs
   const int32_t* items;
 };
 
@@ -137,7 +152,7 @@ struct GemmArgs16 {
   int32_t M, N, nbatch, mt, nt;
   int32_t nprod;                         // 3: hi*hi + hi*lo + lo*hi, 1: hi*hi
   float* out; int64_t obs, ldo;
-  int32_t kind;                          // 0: S, 1: G, 2: Y (number of segments 6, 6, 4)
+  int32_t kind;                          // 0: S, 1: G, 2: Y, 3: closed shell (segments 6, 6, 4, 4)
   const Seg8* tab;                       // [nbatch][6] segment descriptors of the launch's items
 };
 
@@ -228,6 +243,21 @@ hipError_t launch_pack_pairs(Tout* out, int64_t ldo, int64_t rows, int32_t n,
 
 template <typename T> hipError_t launch_epi_same(const EpiSame<T>& a, int32_t nitems, hipStream_t s);
 template <typename T> hipError_t launch_epi_mixed(const EpiMixed<T>& a, int32_t nitems, hipStream_t s);
+// Closed-shell (spin-adapted) path.  For an occupied triple i <= j <= k the
+// contraction writes three cubes F(i,j,k)[a][b*v+c], F(j,i,k)[b][a*v+c] and
+// F(k,i,j)[c][a*v+b] (item stride 3 * cube elements); launch_rhf_w forms
+// W^{abc} = their sum in place of the first.
+template <typename T> hipError_t launch_rhf_w(T* X, int64_t cube, int32_t v, int32_t nitems, hipStream_t s);
+template <typename T> struct EpiRhf {
+  int32_t o, v, nt, ntiles;           // 16-wide virtual tiles, ntiles = nt(nt+1)/2 (a-tile <= b-tile)
+  const T* W; int64_t w_item;         // W[item][a][b*v+c] at W + item*w_item
+  const int32_t* items;               // [n][3] occupied triples i <= j <= k, not all equal
+  const double *eo, *ev, *t1, *f;     // orbital energies, t1 [o][v], f_ov [o][v]
+  const double* tau;                  // [o][o][v][v] spatial amplitudes
+  const double* ov;                   // [o][v][o][v] (ia|jb)
+  double* part;                       // [n][ntiles][3]
+};
+template <typename T> hipError_t launch_epi_rhf(const EpiRhf<T>& a, int32_t nitems, hipStream_t s);
 // Debug dumps of one item's W over its full virtual cube (FP64, row-major),
 // formed from the contraction outputs exactly as the epilogues read them:
 // same spin from S (v^3 entries), mixed from G and Y (v_s * v_s * v_t).

@@ -215,25 +215,32 @@ def _fake_rhf(dims, null=()):
 
 @pytest.mark.parametrize("no,nv,naux", [(4, 10, 20), (40, 300, 1200), (2, 5, 8), (1, 5, 8)])
 def test_rhf_flops_items_and_workspace(no, nv, naux):
-    """The closed-shell call runs the aaa and aab items of the alpha == beta
-    spin-block domain: their count and flops, and a workspace that holds the
-    same-spin amplitudes ahead of the spin-block workspace."""
+    """The spin-adapted closed-shell call runs the unordered occupied
+    triples i <= j <= k that are not all equal, three contractions of
+    nv x nv^2 outputs over 2 (nv + no) rows each; the spin-block entry
+    point runs the aaa and aab items of the alpha == beta domain, half the
+    open-shell count, and needs more workspace on the LNO-sized domain."""
     _lib()
     d = _fake_rhf((no, nv, naux))
     f, n = lt.ltriples_rhf_flops(d)
-    n0, n1 = no * (no - 1) * (no - 2) // 6, no * (no - 1) // 2 * no
-    assert n == n0 + n1
+    n_sa = (no * (no + 1) * (no + 2) // 6 - no) if no > 1 else 0
+    assert n == n_sa
+    assert abs(f - n_sa * 12.0 * nv**3 * (nv + no)) <= 1e-12 * max(f, 1.0)
     c = lambda m, k: float(np.prod([m - i for i in range(k)]) / np.prod(range(1, k + 1))) if m >= k else 0.0
-    want = c(no, 3) * (6 * nv**4 + 6 * nv**3 * no) \
+    f_sb = c(no, 3) * (6 * nv**4 + 6 * nv**3 * no) \
         + c(no, 2) * no * (4 * nv**4 + 6 * nv**4 + 4 * nv**3 * no + 6 * nv**3 * no)
-    assert abs(f - want) <= 1e-12 * max(want, 1.0)
-    # about half of the open-shell work of the same domain
     fo, _ = lt.ltriples_flops(_fake_domain((no, no, nv, nv, naux)))
     if fo > 0:
-        assert abs(f / fo - 0.5) < 1e-12
+        assert abs(f_sb / fo - 0.5) < 1e-12
+    if no == 40:
+        assert f < 0.4 * f_sb                 # the spin-adapted form's saving on the LNO-sized domain
     for prec in (lt.LT_FP64, lt.LT_FP32, lt.LT_BF16X3):
         w = lt.ltriples_rhf_workspace_size(d, prec)
         assert w >= 8 * no * no * nv * nv
+        assert lt.ltriples_rhf_spin_block_workspace_size(d, prec) >= 8 * no * no * nv * nv
+    if no == 40:
+        assert lt.ltriples_rhf_workspace_size(d, lt.LT_BF16X3) < lt.ltriples_rhf_spin_block_workspace_size(
+            d, lt.LT_BF16X3)
 
 
 def test_rhf_rejects_bad_args():

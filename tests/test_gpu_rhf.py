@@ -1,5 +1,5 @@
-"""GPU parity of the closed-shell entry point (ltriples_energy_rhf) through
-the C ABI.
+"""GPU parity of the closed-shell entry points (ltriples_energy_rhf, the
+spin-adapted path, and ltriples_energy_rhf_spin_block) through the C ABI.
 
 Reference: the oracle's independent closed-shell (T) formula over spatial
 orbitals (oracle.rhf, pinned on the CPU against the spin-orbital brute force
@@ -99,6 +99,67 @@ def test_rhf_batching_and_chunks_bitwise():
     assert E0 == E1 and np.array_equal(p0, p1)
     E2, p2 = _gpu(dom, lt.LT_FP32, batch_items=2)
     assert abs(E2 - E0) <= 1e-12 * abs(E0)
+
+
+def test_spin_adapted_matches_spin_block_path():
+    """The two closed-shell GPU paths (spin-adapted contractions over
+    spatial orbitals; spin-block reuse with identical spins) on the same
+    data, FP64: E and every part within 1e-12 relative of each other."""
+    for name in ("ragged", "two_occ"):
+        dom = _dom(SHAPES[name])
+        E0, p0 = _gpu(dom, lt.LT_FP64)
+        E1, p1 = _gpu(dom, lt.LT_FP64, method="spin_block")
+        assert abs(E0 - E1) <= 1e-12 * abs(E1), (name, E0, E1)
+        assert np.allclose(p0, p1, rtol=1e-11, atol=0), (name, p0, p1)
+
+
+def test_rhf_forced_tiles_and_autotune_change_no_bit():
+    """Forced contraction tiles (tile_override[0]) and the autotuner change
+    no bit of the spin-adapted energy (every tile sums the same segments in
+    the same order)."""
+    dom = _dom(SHAPES["wide"])
+    for prec in (lt.LT_FP32, lt.LT_BF16X3, lt.LT_FP64):
+        E0, p0 = _gpu(dom, prec)
+        for kw in ({"tile_override": (1, 0, 0)}, {"tile_override": (3, 0, 0)}, {"autotune": True}):
+            E1, p1 = _gpu(dom, prec, **kw)
+            assert E0 == E1 and np.array_equal(p0, p1), (prec, kw)
+
+
+def test_rhf_check_finite_rejects_nan():
+    import torch
+    dom = _dom(SHAPES["small"])
+    t = _rhf_dev(dom)
+    t["tau"][1, 2, 3, 4] = float("nan")
+    with pytest.raises(lt.LtError) as ei:
+        lt.ltriples_energy_rhf(t, (dom.noa, dom.nva, dom.naux), lt.LT_FP64, check_finite=True)
+    assert ei.value.code == lt.LT_ENONFINITE
+    torch.cuda.synchronize()
+
+
+def test_rhf_lno_sized_domain_two_paths():
+    """The closed-shell LNO-sized workload (40,300,1200): the spin-adapted
+    BF16X3 energy against the spin-block BF16X3 path at the BF16x3 bar, and
+    the FP32 spin-adapted energy against both at the same bar (the oracle
+    would need hours at this size; the FP64 paths are held to it above)."""
+    import torch
+    torch.cuda.empty_cache()
+    dom = synth.rhf_config_domain("rhf")
+    t = _rhf_dev(dom)
+    dims = (dom.noa, dom.nva, dom.naux)
+    print(f"[rhf] lno-sized {dims}", flush=True)
+    res = {}
+    for key, prec, method in (("sa", lt.LT_BF16X3, "spin_adapted"), ("sb", lt.LT_BF16X3, "spin_block"),
+                              ("sa32", lt.LT_FP32, "spin_adapted")):
+        e, p = lt.ltriples_energy_rhf(t, dims, prec, method=method)
+        torch.cuda.synchronize()
+        res[key] = (float(e.item()), p.cpu().numpy())
+        torch.cuda.empty_cache()
+        print(f"[rhf] {key} done", flush=True)
+    E = res["sb"][0]
+    for key in ("sa", "sa32"):
+        assert abs(res[key][0] - E) <= TOL_E[lt.LT_BF16X3] * max(1.0, abs(E)), (key, res[key][0], E)
+    del t
+    torch.cuda.empty_cache()
 
 
 # ---- adjoint ------------------------------------------------------------------------------
