@@ -782,21 +782,20 @@ def _autograd_function():
         and the orbital energies."""
 
         @staticmethod
-        def forward(ctx, precision, dims, *arrays):
+        def forward(ctx, precision, bprec, dims, *arrays):
             tens = dict(zip(ARRAY_FIELDS, arrays))
             e, _ = ltriples_energy(tens, dims, precision)
-            ctx.precision, ctx.dims = precision, dims
+            ctx.bprec, ctx.dims = bprec, dims
             ctx.save_for_backward(*arrays)
             return e.reshape(())
 
         @staticmethod
         def backward(ctx, gE):
             tens = dict(zip(ARRAY_FIELDS, ctx.saved_tensors))
-            prec = ctx.precision if ctx.precision in (LT_FP64, LT_FP32) else LT_FP32
             gbar = gE.detach().to(torch.float64).reshape(1).contiguous()
-            g = ltriples_backward(tens, ctx.dims, prec, gbar=gbar)
-            return (None, None) + tuple(g.get(k) if ctx.needs_input_grad[2 + n] else None
-                                        for n, k in enumerate(ARRAY_FIELDS))
+            g = ltriples_backward(tens, ctx.dims, ctx.bprec, gbar=gbar)
+            return (None, None, None) + tuple(g.get(k) if ctx.needs_input_grad[3 + n] else None
+                                              for n, k in enumerate(ARRAY_FIELDS))
 
     return TriplesEnergy
 
@@ -804,13 +803,22 @@ def _autograd_function():
 _TE = None
 
 
-def triples_energy(tensors: Mapping[str, object], dims, precision="fp64"):
+def triples_energy(tensors: Mapping[str, object], dims, precision="fp64", backward_precision=None):
     """Differentiable E(T) (0-d float64 tensor).  Gradients flow to T1, T2,
-    the DF factors, f_ov and the orbital energies through ltriples_backward
-    (FP64, or FP32 for the reduced precisions)."""
+    the DF factors, f_ov and the orbital energies through ltriples_backward,
+    which has FP64 and FP32 kernels only: `backward_precision` picks one
+    ("fp64" or "fp32"); by default FP64 for an FP64 forward and FP32 for
+    every reduced-precision forward (FP32, BF16X3, BF16), i.e. the gradient
+    of a BF16X3 energy is the FP32 adjoint of the same function."""
     global _TE
     if _TE is None:
         _TE = _autograd_function()
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
-    return _TE.apply(int(precision), tuple(int(x) for x in dims), *(tensors[k] for k in ARRAY_FIELDS))
+    if backward_precision is None:
+        bprec = LT_FP64 if precision == LT_FP64 else LT_FP32
+    else:
+        bprec = PRECISIONS[backward_precision] if isinstance(backward_precision, str) else int(backward_precision)
+        if bprec not in (LT_FP64, LT_FP32):
+            raise ValueError("backward_precision must be fp64 or fp32 (the adjoint has no BF16 kernels)")
+    return _TE.apply(int(precision), int(bprec), tuple(int(x) for x in dims), *(tensors[k] for k in ARRAY_FIELDS))

@@ -110,3 +110,11 @@ def test_gradient_outputs_for_arrays_passed_as_none():
     assert g.shape == (2, 5)
     g = lt._grad_like(t, "t1b", 0, torch.device("cpu"))
     assert g.shape == (0,) and g.dtype == torch.float64
+
+
+def test_autograd_backward_precision_is_fp64_or_fp32():
+    """The adjoint has FP64 and FP32 kernels only: asking the differentiable
+    energy for a BF16 backward is refused before anything runs."""
+    dims = (5, 4, 30, 31, 120)
+    with pytest.raises(ValueError):
+        lt.triples_energy({k: None for k in lt.ARRAY_FIELDS}, dims, "bf16x3", backward_precision="bf16x3")

@@ -327,6 +327,15 @@ def test_autograd_function_matches_backward():
         assert torch.equal(leaves[k].grad, g[k]), k
     e_ref, _ = lt.ltriples_energy(t, dom.dims, lt.LT_FP64)
     assert float(E.detach()) == float(e_ref.item())
+    # a BF16X3 forward is differentiated by the FP32 adjoint unless FP64 is asked for
+    g32 = lt.ltriples_backward(t, dom.dims, lt.LT_FP32)
+    for bp, ref in ((None, g32), ("fp64", g)):
+        lv = {k: (v.clone().requires_grad_(k in ALL_GRAD)) for k, v in t.items()}
+        E = lt.triples_energy(lv, dom.dims, "bf16x3", backward_precision=bp)
+        E.backward()
+        torch.cuda.synchronize()
+        for k in ALL_GRAD:
+            assert torch.equal(lv[k].grad, ref[k]), (bp, k)
 
 
 def test_backward_tall_shape_identities():
