@@ -2686,8 +2686,9 @@ int rhf_setup(const ltriples_rhf_domain* r, const ltriples_options* o, RhfSetup&
 // and W^{abc}_{ijk} = F(i,j,k)[a][bc] + F(j,i,k)[b][ac] + F(k,i,j)[c][ab].
 // Each unordered occupied triple i <= j <= k (all equal excluded: its
 // contribution vanishes) costs three contractions of v x v^2 outputs over
-// 2(v + o) rows, and the epilogue (lt_epilogue.hip) sums the energy of all
-// its orderings from W over unique virtual tiles.
+// 2(v + o) rows, written as three cubes; the epilogue (lt_epilogue.hip)
+// forms W from them and sums the energy of all orderings of the triple over
+// unique virtual tiles.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -2920,10 +2921,9 @@ int sa_run(const ltriples_rhf_domain* r, const SaPlan& P, const ltriples_options
       tm.gemm_flops += 2.0 * (double)v * (double)(v * v) * (double)(2 * v + 2 * no) * (double)(3 * n);
     }
     hipEvent_t eb = tm.mark();
-    HIPCHK(lt::launch_rhf_w<T>(cubes, (int64_t)P.cube, (int32_t)v, (int32_t)n, st));
     lt::EpiRhf<T> e{};
     e.o = (int32_t)no; e.v = (int32_t)v; e.nt = (int32_t)P.nt; e.ntiles = (int32_t)P.ntiles;
-    e.W = cubes; e.w_item = 3 * (int64_t)P.cube; e.items = d_items + 3 * first;
+    e.W = cubes; e.w_item = 3 * (int64_t)P.cube; e.cube = (int64_t)P.cube; e.items = d_items + 3 * first;
     e.eo = r->eo; e.ev = r->ev; e.t1 = r->t1; e.f = r->fov; e.tau = r->tau; e.ov = at<double>(ws, P.OV64);
     e.part = part;
     HIPCHK(lt::launch_epi_rhf<T>(e, (int32_t)n, st));

@@ -878,56 +878,22 @@ template hipError_t launch_epi_mixed<double>(const EpiMixed<double>&, int32_t, h
 // repeated indices.
 // ---------------------------------------------------------------------------
 
-// W[a][b][c] = A[a][b][c] + B[b][a][c] + C[c][a][b] (C transposed through LDS),
-// in place of A; one work-group per (item, a, 32x32 tile of (b, c)).
-template <typename T>
-__global__ __launch_bounds__(256) void k_rhf_w(T* X, int64_t cube, int32_t v, int32_t nbt) {
-  __shared__ T s[32][33];
-  const int item = blockIdx.z, a = blockIdx.y;
-  const int b0 = (blockIdx.x / nbt) * 32, c0 = (blockIdx.x % nbt) * 32;
-  T* A = X + (int64_t)(3 * item) * cube;
-  const T* B = A + cube;
-  const T* C = A + 2 * cube;
-  const int64_t vv = (int64_t)v * v;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int c = c0 + ty + 8 * u, b = b0 + tx;
-    s[ty + 8 * u][tx] = (c < v && b < v) ? C[c * vv + (int64_t)a * v + b] : (T)0;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int b = b0 + ty + 8 * u, c = c0 + tx;
-    if (b < v && c < v) {
-      const int64_t o = (int64_t)a * vv + (int64_t)b * v + c;
-      A[o] = (A[o] + B[(int64_t)b * vv + (int64_t)a * v + c]) + s[tx][ty + 8 * u];
-    }
-  }
-}
-
-template <typename T>
-hipError_t launch_rhf_w(T* X, int64_t cube, int32_t v, int32_t nitems, hipStream_t s) {
-  if (nitems <= 0 || v <= 0) return hipSuccess;
-  if (nitems > 65535 || v > 65535) return hipErrorInvalidValue;
-  const int nbt = (v + 31) / 32;
-  hipLaunchKernelGGL((k_rhf_w<T>), dim3(nbt * nbt, v, nitems), dim3(256), 0, s, X, cube, v, nbt);
-  return hipGetLastError();
-}
-template hipError_t launch_rhf_w<float>(float*, int64_t, int32_t, int32_t, hipStream_t);
-template hipError_t launch_rhf_w<double>(double*, int64_t, int32_t, int32_t, hipStream_t);
-
 // One work-group per (item, a-tile <= b-tile) walks the c-tiles from the
 // b-tile on; thread (b, c) = (tid >> 4, tid & 15) of a tile loops over the
-// a-tile in two halves.  W at (a,b,c) and (b,a,c) is read directly (runs
-// along c); the other four orderings and the (ia|jb), tau blocks with an
-// a index are staged in LDS per half; the (b, c) values are the thread's.
+// a-tile in two halves.  W is never stored: the three contraction cubes
+// are read once each, at positions (a,b,c) and (b,a,c) directly (runs along
+// c) and at the other four orderings through LDS, where each ordering's
+// share of W is summed in two phases (runs along b, then along a); the
+// (ia|jb), tau blocks with an a index are staged per half; the (b, c)
+// values are the thread's.
 // Pair q of the occupied triple: 0 (i,j), 1 (j,i), 2 (i,k), 3 (k,i),
 // 4 (j,k), 5 (k,j); J_q[x][y] = (p x|p' y), Tq[x][y] = tau^{xy}_{p p'}.
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_epi_rhf(EpiRhf<T> a) {
   constexpr int HA = ET / 2, S1 = ET + 1;
-  __shared__ T P1[HA][ET][S1], P2[HA][ET][S1], P3[HA][ET][S1], P4[HA][ET][S1];   // [ta][tc][tb]
+  // staged parts of W at the six orderings of (a,b,c), [ta][tc][tb]
+  __shared__ T Sabc[HA][ET][S1], Sacb[HA][ET][S1], Sbac[HA][ET][S1], Sbca[HA][ET][S1], Scab[HA][ET][S1],
+      Scba[HA][ET][S1];
   __shared__ double Jab[6][HA][S1], Jac[6][HA][S1], Tab[6][HA][S1], Tac[6][HA][S1];
   __shared__ double t1a[3][HA], fa[3][HA], eva[HA];
 
@@ -944,7 +910,9 @@ __global__ __launch_bounds__(256, 2) void k_epi_rhf(EpiRhf<T> a) {
   const int64_t vv = (int64_t)v * v, ovv = (int64_t)o * v;
   const int pq[6][2] = {{occ[0], occ[1]}, {occ[1], occ[0]}, {occ[0], occ[2]},
                         {occ[2], occ[0]}, {occ[1], occ[2]}, {occ[2], occ[1]}};
-  const T* W = a.W + (int64_t)item * a.w_item;
+  const T* A = a.W + (int64_t)item * a.w_item;   // F(i,j,k)[a][bc]
+  const T* B = A + a.cube;                         // F(j,i,k)[b][ac]
+  const T* C = A + 2 * a.cube;                     // F(k,i,j)[c][ab]
   const int a0 = TA * ET, b0 = TB * ET;
   const int tb = tid >> 4, tc = tid & 15;
   const int b = b0 + tb;
@@ -979,29 +947,23 @@ __global__ __launch_bounds__(256, 2) void k_epi_rhf(EpiRhf<T> a) {
     for (int h = 0; h < 2; ++h) {
       const int ah = a0 + h * HA;
       __syncthreads();               // the previous half's LDS reads are done
+      // W^{xyz} = A[x][y][z] + B[y][x][z] + C[z][x][y].  Phase 1, runs along b:
+      // positions [a][c][b] and [c][a][b] of the three cubes
 #pragma unroll 2
       for (int u = 0; u < HA; ++u) {
         const int e = tid + 256 * u;
-        {   // P1[ta][tc][tb] = W[a][c][b], runs along b
-          const int x = e >> 8, y = (e >> 4) & 15, z = e & 15;
-          const int aa = ah + x, cc = c0 + y, bb = b0 + z;
-          P1[x][y][z] = (aa < v && cc < v && bb < v) ? W[aa * vv + (int64_t)cc * v + bb] : (T)0;
+        const int x = e >> 8, y = (e >> 4) & 15, z = e & 15;
+        const int aa = ah + x, cc = c0 + y, bb = b0 + z;
+        T acb_a = 0, acb_b = 0, acb_c = 0, cab_a = 0, cab_b = 0, cab_c = 0;
+        if (aa < v && cc < v && bb < v) {
+          const int64_t p1 = aa * vv + (int64_t)cc * v + bb, p2 = cc * vv + (int64_t)aa * v + bb;
+          acb_a = A[p1]; acb_b = B[p1]; acb_c = C[p1];
+          cab_a = A[p2]; cab_b = B[p2]; cab_c = C[p2];
         }
-        {   // P2[ta][tc][tb] = W[c][a][b], runs along b
-          const int y = e >> 7, x = (e >> 4) & 7, z = e & 15;
-          const int aa = ah + x, cc = c0 + y, bb = b0 + z;
-          P2[x][y][z] = (aa < v && cc < v && bb < v) ? W[cc * vv + (int64_t)aa * v + bb] : (T)0;
-        }
-        {   // P3[ta][tc][tb] = W[b][c][a], runs along a
-          const int z = e >> 7, y = (e >> 3) & 15, x = e & 7;
-          const int aa = ah + x, cc = c0 + y, bb = b0 + z;
-          P3[x][y][z] = (aa < v && cc < v && bb < v) ? W[bb * vv + (int64_t)cc * v + aa] : (T)0;
-        }
-        {   // P4[ta][tc][tb] = W[c][b][a], runs along a
-          const int y = e >> 7, z = (e >> 3) & 15, x = e & 7;
-          const int aa = ah + x, cc = c0 + y, bb = b0 + z;
-          P4[x][y][z] = (aa < v && cc < v && bb < v) ? W[cc * vv + (int64_t)bb * v + aa] : (T)0;
-        }
+        Sacb[x][y][z] = acb_a + cab_b;
+        Scab[x][y][z] = acb_b + cab_a;
+        Scba[x][y][z] = acb_c;
+        Sabc[x][y][z] = cab_c;
       }
       for (int e = tid; e < 6 * HA * ET; e += 256) {
         const int q = e / (HA * ET), r = e % (HA * ET), x = r >> 4, z = r & 15;
@@ -1022,16 +984,35 @@ __global__ __launch_bounds__(256, 2) void k_epi_rhf(EpiRhf<T> a) {
         eva[ta] = aa < v ? a.ev[aa] : 0.0;
       }
       __syncthreads();
+      // phase 2, runs along a: positions [b][c][a] and [c][b][a]
+#pragma unroll 2
+      for (int u = 0; u < HA; ++u) {
+        const int e = tid + 256 * u;
+        const int z = e >> 7, y = (e >> 3) & 15, x = e & 7;
+        const int aa = ah + x, cc = c0 + y, bb = b0 + z;
+        T bca_a = 0, bca_b = 0, bca_c = 0, cba_a = 0, cba_b = 0, cba_c = 0;
+        if (aa < v && cc < v && bb < v) {
+          const int64_t p1 = bb * vv + (int64_t)cc * v + aa, p2 = cc * vv + (int64_t)bb * v + aa;
+          bca_a = A[p1]; bca_b = B[p1]; bca_c = C[p1];
+          cba_a = A[p2]; cba_b = B[p2]; cba_c = C[p2];
+        }
+        Sbca[x][y][z] = bca_a + cba_b;
+        Sbac[x][y][z] = cba_c;
+        Scab[x][y][z] += bca_c;
+        Scba[x][y][z] += bca_b + cba_a;
+      }
+      __syncthreads();
       if (!ok) continue;
       const int na = min(HA, v - ah);
       for (int ta = 0; ta < na; ++ta) {
         const int aa = ah + ta;
-        const double w0 = (double)W[aa * vv + (int64_t)b * v + c];      // abc
-        const double w2 = (double)W[b * vv + (int64_t)aa * v + c];      // bac
-        const double w1 = (double)P1[ta][tc][tb];                       // acb
-        const double w4 = (double)P2[ta][tc][tb];                       // cab
-        const double w3 = (double)P3[ta][tc][tb];                       // bca
-        const double w5 = (double)P4[ta][tc][tb];                       // cba
+        const int64_t pabc = aa * vv + (int64_t)b * v + c, pbac = b * vv + (int64_t)aa * v + c;
+        const double w0 = ((double)A[pabc] + (double)B[pbac]) + (double)Sabc[ta][tc][tb];   // abc
+        const double w2 = ((double)A[pbac] + (double)B[pabc]) + (double)Sbac[ta][tc][tb];   // bac
+        const double w1 = (double)Sacb[ta][tc][tb] + (double)C[pbac];                       // acb
+        const double w3 = (double)Sbca[ta][tc][tb] + (double)C[pabc];                       // bca
+        const double w4 = (double)Scab[ta][tc][tb];                                         // cab
+        const double w5 = (double)Scba[ta][tc][tb];                                         // cba
         const double se = (w0 + w3) + w4, so = (w1 + w2) + w5;
         const double ye = se - 2.0 * so, yo = so - 2.0 * se;
         const double y0 = 3.0 * w0 + ye, y3 = 3.0 * w3 + ye, y4 = 3.0 * w4 + ye;

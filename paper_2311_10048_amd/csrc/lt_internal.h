@@ -243,14 +243,13 @@ hipError_t launch_pack_pairs(Tout* out, int64_t ldo, int64_t rows, int32_t n,
 
 template <typename T> hipError_t launch_epi_same(const EpiSame<T>& a, int32_t nitems, hipStream_t s);
 template <typename T> hipError_t launch_epi_mixed(const EpiMixed<T>& a, int32_t nitems, hipStream_t s);
-// Closed-shell (spin-adapted) path.  For an occupied triple i <= j <= k the
-// contraction writes three cubes F(i,j,k)[a][b*v+c], F(j,i,k)[b][a*v+c] and
-// F(k,i,j)[c][a*v+b] (item stride 3 * cube elements); launch_rhf_w forms
-// W^{abc} = their sum in place of the first.
-template <typename T> hipError_t launch_rhf_w(T* X, int64_t cube, int32_t v, int32_t nitems, hipStream_t s);
+// Closed-shell (spin-adapted) energy epilogue.  For an occupied triple
+// i <= j <= k the contraction writes three cubes A = F(i,j,k)[a][b*v+c],
+// B = F(j,i,k)[b][a*v+c], C = F(k,i,j)[c][a*v+b] (see the driver in
+// lt_api.hip); W^{abc} = A[a][b][c] + B[b][a][c] + C[c][a][b].
 template <typename T> struct EpiRhf {
   int32_t o, v, nt, ntiles;           // 16-wide virtual tiles, ntiles = nt(nt+1)/2 (a-tile <= b-tile)
-  const T* W; int64_t w_item;         // W[item][a][b*v+c] at W + item*w_item
+  const T* W; int64_t w_item, cube;   // A of item n at W + n*w_item; B, C at + cube, + 2 cube
   const int32_t* items;               // [n][3] occupied triples i <= j <= k, not all equal
   const double *eo, *ev, *t1, *f;     // orbital energies, t1 [o][v], f_ov [o][v]
   const double* tau;                  // [o][o][v][v] spatial amplitudes
