@@ -200,7 +200,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "fp64", "bf16x3", "bf16"])
     ap.add_argument("--workload", default="lno",
-                    choices=["tiny", "lno", "grad", "large", "batch", "rhf", "naf", "central"])
+                    choices=["tiny", "lno", "grad", "large", "batch", "rhf", "naf", "central", "latency"])
     ap.add_argument("--fp64-sample", type=int, default=24, help="items per block for the FP64 GPU comparison")
     ap.add_argument("--cpu-sample", type=int, default=3, help="items per block for the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -241,6 +241,9 @@ def main():
         return
     if args.library_gemm:
         library_gemm(max(args.steps, 20))
+        return
+    if args.workload == "latency":
+        run_latency(args, lt, synth, torch)
         return
     if args.workload == "batch":
         run_batch(args, lt, synth, torch)
@@ -539,6 +542,52 @@ def run_batch(args, lt, synth, torch):
         "E_per_domain": [float(x) for x in e_eager],
     }
     print(json.dumps(res), flush=True)
+
+
+def run_latency(args, lt, synth, torch):
+    """Call latency on the small domain (5,4,30,31,120): eager single-domain
+    calls against replays of the same launch sequence captured in a hipGraph
+    (a one-domain ltriples_energy_batched call with options.graph), both
+    with a preallocated workspace; energies compared bitwise."""
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    prec = lt.PRECISIONS[args.precision]
+    dom = synth.config_domain("tiny")
+    tens = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in dom.arrays().items()}
+    d = lt.make_domain(dom.dims, tens)
+    ws = torch.empty(max(lt.ltriples_workspace_size(d, prec), 1), dtype=torch.uint8, device=dev)
+    n = max(args.steps, 50)
+
+    def timed(fn):
+        for _ in range(max(args.warmup, 3)):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / n, r
+
+    ms_eager, (e0, _) = timed(lambda: lt.ltriples_energy(tens, dom.dims, prec, workspace=ws))
+    lt.ltriples_graph_reset()
+    import ctypes
+    arr = lt._domain_array([dom.dims], [tens])
+    opts, _k = lt.make_options()
+    opts.graph = 1
+    sz = ctypes.c_size_t(0)
+    lt._check(lt.load_library().ltriples_workspace_size_batched(arr, 1, prec, ctypes.byref(opts), ctypes.byref(sz)))
+    wsb = torch.empty(max(sz.value, 1), dtype=torch.uint8, device=dev)
+    out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty(1, 4, 3, dtype=torch.float64, device=dev))
+    ms_graph, (e1, _) = timed(lambda: lt.ltriples_energy_batched([tens], [dom.dims], prec, graph=True,
+                                                                 workspace=wsb, out=out))
+    same = float(e0.item()) == float(e1[0].item())
+    log(f"tiny {dom.dims}: eager {ms_eager:.3f} ms per call, graph replay {ms_graph:.3f} ms, same E: {same}")
+    print(json.dumps({"workload": f"tiny domain {dom.dims}, call latency", "precision": args.precision,
+                      "calls": n, "eager_ms_per_call": round(ms_eager, 4),
+                      "graph_replay_ms_per_call": round(ms_graph, 4), "bitwise_equal": same}), flush=True)
 
 
 def run_rhf(args, lt, synth, torch):
