@@ -200,7 +200,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "fp64", "bf16x3", "bf16"])
     ap.add_argument("--workload", default="lno",
-                    choices=["tiny", "lno", "grad", "large", "batch", "rhf", "naf", "central", "latency"])
+                    choices=["tiny", "lno", "grad", "large", "batch", "rhf", "naf", "central", "latency",
+                             "batch_rates", "groups"])
     ap.add_argument("--fp64-sample", type=int, default=24, help="items per block for the FP64 GPU comparison")
     ap.add_argument("--cpu-sample", type=int, default=3, help="items per block for the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -212,6 +213,8 @@ def main():
     ap.add_argument("--prefix-items", type=int, default=0,
                     help="profiling aid: the first K triplets per block in the whole-domain order")
     ap.add_argument("--copy-calibration", action="store_true", help="profiling aid: plain 1 GiB device copy")
+    ap.add_argument("--group-budget", type=float, default=0.0,
+                    help="batch workload: launch-group budget in GiB (options.group_budget; 0 = no groups)")
     ap.add_argument("--library-gemm", action="store_true",
                     help="profiling aid: the library BF16 GEMM on the contraction's average shape")
     ap.add_argument("--traffic-from", nargs=2, metavar=("PMC_DIR", "TRACE_CSV"),
@@ -247,6 +250,12 @@ def main():
         return
     if args.workload == "batch":
         run_batch(args, lt, synth, torch)
+        return
+    if args.workload == "batch_rates":
+        run_batch_rates(args, lt, synth, torch)
+        return
+    if args.workload == "groups":
+        run_groups(args, lt, synth, torch)
         return
     if args.workload == "rhf":
         run_rhf(args, lt, synth, torch)
@@ -491,7 +500,8 @@ def run_batch(args, lt, synth, torch):
     halves = [list(range(0, len(shapes), 2)), list(range(1, len(shapes), 2))]
     Ftot = sum(F)
     log(f"generated and uploaded {len(shapes)} domains in {time.time() - t0:.1f} s, F = {Ftot:.4e}")
-    opts, _ = lt.make_options()
+    gbudget = int(args.group_budget * (1 << 30))
+    opts, _ = lt.make_options(group_budget=gbudget)
     need = max(lt.ltriples_workspace_size_batched([dims[n] for n in h], [tens[n] for n in h], prec, opts)
                for h in halves)
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
@@ -507,7 +517,8 @@ def run_batch(args, lt, synth, torch):
             ev1 = torch.cuda.Event(enable_timing=True)
             ev0.record()
             lt.ltriples_energy_batched([tens[n] for n in h], [dims[n] for n in h], prec, graph=graph,
-                                       workspace=ws, out=outs[k], autotune=bool(args.autotune) and not graph)
+                                       workspace=ws, out=outs[k], autotune=bool(args.autotune) and not graph,
+                                       group_budget=gbudget)
             ev1.record()
             torch.cuda.synchronize()
             ms += ev0.elapsed_time(ev1)
@@ -536,12 +547,104 @@ def run_batch(args, lt, synth, torch):
         "scaling": "strong", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
         "config": {"workload": f"batch: {len(dims)} uneven domains (nocc 10-40, nvir 80-320, naux 4 nvir), "
                                "two ltriples_energy_batched calls of 32 domains per step",
-                   "algorithmic_flops": Ftot, "precision": args.precision},
+                   "algorithmic_flops": Ftot, "precision": args.precision,
+                   "group_budget_GiB": args.group_budget, "workspace_GB": round(need / 1e9, 2)},
         "graph": {"first_call_ms": round(first[0], 2), "replay_ms": round(rms, 2),
                   "replay_GFLOP/s": round(Ftot / (rms * 1e-3) / 1e9, 1), "bitwise_equal_to_eager": same},
         "E_per_domain": [float(x) for x in e_eager],
     }
     print(json.dumps(res), flush=True)
+
+
+def run_batch_rates(args, lt, synth, torch):
+    """Where the 64-domain set loses against one large domain: eleven of its
+    domains, spread over the virtual sizes (smallest to largest nva), each
+    timed alone through ltriples_energy with phase statistics (setup,
+    contractions, epilogues); one untimed call first.  Prints one JSON line
+    per domain and a summary line."""
+    prec = lt.PRECISIONS[args.precision]
+    shapes = synth.batch_shapes()
+    order = sorted(range(len(shapes)), key=lambda n: shapes[n][2])
+    pick = [order[i] for i in (0, 1, 8, 16, 24, 32, 40, 48, 56, 62, 63)]
+    out = []
+    for n in pick:
+        dom = synth.batch_domain(n, shapes)
+        t = {k: torch.from_numpy(v).cuda() for k, v in dom.arrays().items()}
+        F = lt.ltriples_flops(lt.make_domain(dom.dims, t), None)[0]
+        for _ in range(max(args.warmup, 1) + 1):
+            st = lt.Stats()
+            lt.ltriples_energy(t, dom.dims, prec, stats=st)
+            torch.cuda.synchronize()
+        s = st.as_dict()
+        row = {"domain": n, "dims": list(dom.dims), "F": F, "total_ms": round(s["total_ms"], 2),
+               "setup_ms": round(s["setup_ms"], 2), "contraction_ms": round(s["triples_gemm_ms"], 2),
+               "epilogue_ms": round(s["epilogue_ms"], 2), "contraction_launches": s["triples_gemm_launches"],
+               "TFLOP/s": round(F / s["total_ms"] / 1e9, 1),
+               "contraction_TFLOP/s_on_F": round(F / max(s["triples_gemm_ms"], 1e-9) / 1e9, 1)}
+        out.append(row)
+        print(json.dumps(row), flush=True)
+        del t, dom
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "batch_rates", "precision": args.precision, "domains": len(out)}), flush=True)
+
+
+def run_groups(args, lt, synth, torch):
+    """Launch groups (options.group_budget) against domains one after
+    another, on three sets of small domains where launches are smallest: 64
+    tiny domains (4-8 occupied, 20-60 virtual), 32 small ones (8-14, 60-120)
+    and the 16 smallest domains of the 64-domain set; eager and graph-replayed
+    calls with a preallocated workspace, energies compared bitwise."""
+    prec = lt.PRECISIONS[args.precision]
+    rng = np.random.default_rng(11)
+    sets = {}
+    no, nv = rng.integers(4, 9, 64), rng.integers(20, 61, 64)
+    sets["64 tiny domains (4-8 occupied, 20-60 virtual)"] = [
+        (int(a), int(a) - 1, int(v), int(v) + 1, 3 * int(v)) for a, v in zip(no, nv)]
+    no, nv = rng.integers(8, 15, 32), rng.integers(60, 121, 32)
+    sets["32 small domains (8-14 occupied, 60-120 virtual)"] = [
+        (int(a), int(a) - 1, int(v), int(v) + 1, 4 * int(v)) for a, v in zip(no, nv)]
+    shapes = synth.batch_shapes()
+    F = sorted((lt.ltriples_flops(lt.make_domain(s, {f: (1 << 40) for f in lt.ARRAY_FIELDS}))[0], n)
+               for n, s in enumerate(shapes))
+    sets["the 16 smallest domains of the 64-domain set"] = [shapes[n] for _, n in F[:16]]
+    reps = max(args.steps, 5)
+    for name, sh in sets.items():
+        doms = [synth.make_domain(*s, seed=synth.BASE_SEED + 900 + k) for k, s in enumerate(sh)]
+        tens = [{k: torch.from_numpy(v).cuda() for k, v in d.arrays().items()} for d in doms]
+        dims = [d.dims for d in doms]
+        Ft = sum(lt.ltriples_flops(lt.make_domain(d, t))[0] for d, t in zip(dims, tens))
+        res, energies = {}, []
+        for budget in (0, 1 << 50):
+            opts, _ = lt.make_options(group_budget=budget)
+            ws = torch.empty(lt.ltriples_workspace_size_batched(dims, tens, prec, opts), dtype=torch.uint8,
+                             device="cuda")
+            out = (torch.empty(len(dims), dtype=torch.float64, device="cuda"),
+                   torch.empty(len(dims), 4, 3, dtype=torch.float64, device="cuda"))
+            for graph in (False, True):
+                lt.ltriples_graph_reset()
+                for _ in range(2):
+                    lt.ltriples_energy_batched(tens, dims, prec, graph=graph, workspace=ws, out=out,
+                                               group_budget=budget)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    lt.ltriples_energy_batched(tens, dims, prec, graph=graph, workspace=ws, out=out,
+                                               group_budget=budget)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                energies.append(out[0].cpu().numpy().copy())
+                key = ("groups" if budget else "one after another") + (", graph" if graph else ", eager")
+                res[key] = {"ms": round(ms, 2), "TFLOP/s": round(Ft / ms / 1e9, 1)}
+            lt.ltriples_graph_reset()
+            res["workspace_GB " + ("groups" if budget else "one after another")] = round(ws.numel() / 1e9, 2)
+            del ws
+        same = all(np.array_equal(energies[0], e) for e in energies)
+        print(json.dumps({"set": name, "domains": len(dims), "F": Ft, "precision": args.precision, **res,
+                          "bitwise_equal": same}), flush=True)
+        del tens, doms
+        torch.cuda.empty_cache()
 
 
 def run_latency(args, lt, synth, torch):

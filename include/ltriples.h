@@ -184,6 +184,19 @@ typedef struct ltriples_options {
    * result is bitwise that of the automatic choice.  Values outside 0..8
    * give LT_EINVAL. */
   int32_t tile_override[3];
+  /* ltriples_energy_batched only: 0 = the domains run one after another,
+   * sharing one workspace region for their operands and intermediates.
+   * > 0 = launch groups: the domains, in descending order of their triples
+   * flops, are packed into groups of at most 16 consecutive domains whose
+   * regions together take at most this many bytes (a domain that alone
+   * exceeds it forms a group of its own).  The domains of a group are
+   * prepared side by side; then, spin block by spin block and item batch by
+   * item batch, each triples contraction launch takes one batch of every
+   * domain of the group (BF16X3 and BF16; FP32 and FP64 launch per domain),
+   * followed by each domain's epilogue.  Each domain's batches, epilogues
+   * and reductions are those of a call on it alone, so every result bit is
+   * unchanged; the workspace grows to the largest group's regions. */
+  size_t group_budget;
 } ltriples_options;
 
 /* Host-only validation of sizes, pointers, precision and item list.  Makes
@@ -381,7 +394,9 @@ int ltriples_workspace_size_batched(const ltriples_domain* ds, int32_t ndom,
  *   ws      device workspace >= ltriples_workspace_size_batched(), or NULL
  *           (stream-ordered allocation, as ltriples_energy; no graph then)
  * Each domain's result is bitwise identical to ltriples_energy on that
- * domain alone.  Item lists, per-item outputs and stats are not available
+ * domain alone, with or without launch groups (options.group_budget, which
+ * ltriples_workspace_size_batched must be given too).  Item lists, per-item
+ * outputs and stats are not available
  * here (LT_EINVAL).  With options.graph = 1 (and a caller workspace) the
  * launch sequence is captured into a hipGraph on the first call and replayed
  * on later calls whose shapes, pointers and options match; the graph reads

@@ -103,7 +103,8 @@ class Options(ctypes.Structure):
                 ("autotune", ctypes.c_int32),
                 ("deterministic", ctypes.c_int32),
                 ("check_finite", ctypes.c_int32),
-                ("tile_override", ctypes.c_int32 * 3)]
+                ("tile_override", ctypes.c_int32 * 3),
+                ("group_budget", ctypes.c_size_t)]
 
 
 GRAD_FIELDS = ("t1a", "t1b", "t2aa", "t2bb", "t2ab", "Boo_a", "Bov_a", "Bvv_a", "Boo_b", "Bov_b", "Bvv_b")
@@ -290,12 +291,15 @@ def make_domain(dims, tensors: Optional[Mapping[str, object]] = None) -> Domain:
 
 def make_options(items=None, e_items=None, workspace_budget: int = 0, batch_items: int = 0,
                  stats: Optional[Stats] = None, build_chunk_mib: int = 0, autotune: bool = False,
-                 check_finite: bool = False, tile_override=None, deterministic: bool = True):
+                 check_finite: bool = False, tile_override=None, deterministic: bool = True,
+                 group_budget: int = 0):
     """ltriples_options; `items` is a host int32 array [n][4] (kept alive by
     the returned tuple's second element); `tile_override` is None or three
-    configuration numbers (0 = automatic) for the S, G and Y layouts."""
+    configuration numbers (0 = automatic) for the S, G and Y layouts;
+    `group_budget` (bytes, batched calls only) enables launch groups."""
     o = Options()
     o.workspace_budget = int(workspace_budget)
+    o.group_budget = int(group_budget)
     o.deterministic = 1 if deterministic else 0
     o.check_finite = 1 if check_finite else 0
     if tile_override is not None:
@@ -689,17 +693,21 @@ def ltriples_workspace_size_batched(dims_list, tensors_list, precision: int, opt
 def ltriples_energy_batched(tensors_list, dims_list, precision: int = LT_FP32, graph: bool = False,
                             workspace_budget: int = 0, batch_items: int = 0, workspace=None, out=None,
                             stream=None, build_chunk_mib: int = 0, autotune: bool = False,
-                            check_finite: bool = False, tile_override=None):
+                            check_finite: bool = False, tile_override=None, group_budget: int = 0):
     """E(T) of several domains in one call.  Returns (e [ndom], parts [ndom,4,3]).
     With graph=True the launch sequence is captured into a hipGraph on the
     first call and replayed on later calls with the same shapes, pointers,
-    workspace and output tensors (pass `workspace` and `out` to reuse them)."""
+    workspace and output tensors (pass `workspace` and `out` to reuse them).
+    group_budget > 0 (bytes) packs the domains, longest first, into launch
+    groups whose contraction launches take items of all their domains
+    (options.group_budget); results are bitwise unchanged."""
     import torch
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     ndom = len(dims_list)
     opts, _ = make_options(workspace_budget=workspace_budget, batch_items=batch_items, build_chunk_mib=build_chunk_mib,
-                           autotune=autotune, check_finite=check_finite, tile_override=tile_override)
+                           autotune=autotune, check_finite=check_finite, tile_override=tile_override,
+                           group_budget=group_budget)
     opts.graph = 1 if graph else 0
     arr = _domain_array(dims_list, tensors_list)
     dev = _device_of(tensors_list[0])

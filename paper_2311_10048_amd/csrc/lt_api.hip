@@ -820,201 +820,313 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
 
 // Enqueues the whole (T) path of one domain on `st` (kernels only; safe to
 // capture into a graph).
-template <typename T>
-int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltriples_options* o,
-        double* e_out, double* parts, void* ws, hipStream_t st, Timing& tm) {
-  const Dims& D = P.D;
-  const int64_t Q = D.Q;
-  const double* Bvv[2] = {d->Bvv_a, d->Bvv_b};
-  const double* Bov[2] = {d->Bov_a, d->Bov_b};
-  const double* Boo[2] = {d->Boo_a, d->Boo_b};
-  const double* T2ss[2] = {d->t2aa, d->t2bb};
-  const double* T1[2] = {d->t1a, d->t1b};
-  const double* Fov[2] = {d->fov_a, d->fov_b};
-  const double* EO[2] = {d->eo_a, d->eo_b};
-  const double* EV[2] = {d->ev_a, d->ev_b};
-  char* scr = (char*)ws + P.scratch.off;
+// One domain of a launch group: its plan, items, outputs and workspace base
+// (the domain's big region starts at ws; its small region at ws + P.small_base).
+struct GroupDom {
+  const ltriples_domain* d;
+  const Plan* P;
+  const ItemLists* L;
+  double* e_out;
+  double* parts;
+  void* ws;
+};
 
-  // --- item arrays (already uploaded by upload_items) --------------------------
-  int32_t fc[8];
-  for (int b = 0, n = 0; b < 4; ++b) {
-    fc[b] = n;
-    fc[4 + b] = (int32_t)L.dst[b].size();
-    n += fc[4 + b];
-  }
-  int32_t* d_trip = at_small<int32_t>(ws, P, P.trip);
-  int32_t* d_dst = at_small<int32_t>(ws, P, P.dst);
-  int32_t* d_fc = at_small<int32_t>(ws, P, P.firstcnt);
-  double* e_items = (o && o->e_items) ? o->e_items : at_small<double>(ws, P, P.e_items);
+// The forward launch sequence of a group of domains (steps 1-6).  Each
+// domain's operands are prepared in its own region; then, spin block by spin
+// block and batch round by batch round, one contraction launch per output
+// layout takes the round's item batch of every domain of the group (BF16X3
+// and BF16; FP32/FP64 launch per domain), followed by each domain's epilogue
+// and per-item reduction.  A domain's batches, epilogues and reductions are
+// exactly those of a call on that domain alone, so every result bit is too.
+// Domains are taken in the given order (the batched entry point passes them
+// longest first).
+template <typename T>
+int run_group(const GroupDom* G, int ng, const ltriples_options* o, hipStream_t st, Timing& tm) {
+  struct Dom {
+    int32_t fc[8];
+    int32_t *d_trip, *d_dst, *d_fc;
+    double* e_items;
+    bool active;
+    char* scr;
+    lt::ItemOps<T> ops;
+    lt::Seg8 *tab0, *tab1;
+  };
+  std::vector<Dom> S((size_t)ng);
   tm.start = tm.mark();
-  if (o && o->e_items && L.total > 0) HIPCHK(lt::launch_zero(o->e_items, 3 * L.total, st));
-  HIPCHK(lt::launch_zero(at_small<double>(ws, P, P.e_items), 3 * std::max<int64_t>(L.total, 1), st));
-  if (L.total == 0 || (D.v[0] == 0 && D.v[1] == 0)) {
-    HIPCHK(lt::launch_zero(e_out, 1, st));
-    if (parts) HIPCHK(lt::launch_zero(parts, 12, st));
-    tm.setup_end = tm.mark();
+  // --- item arrays (already uploaded by upload_items), empty domains, operands
+  for (int x = 0; x < ng; ++x) {
+    const GroupDom& g = G[x];
+    const Plan& P = *g.P;
+    const ItemLists& L = *g.L;
+    Dom& m = S[x];
+    for (int b = 0, n = 0; b < 4; ++b) {
+      m.fc[b] = n;
+      m.fc[4 + b] = (int32_t)L.dst[b].size();
+      n += m.fc[4 + b];
+    }
+    m.d_trip = at_small<int32_t>(g.ws, P, P.trip);
+    m.d_dst = at_small<int32_t>(g.ws, P, P.dst);
+    m.d_fc = at_small<int32_t>(g.ws, P, P.firstcnt);
+    m.e_items = (o && o->e_items) ? o->e_items : at_small<double>(g.ws, P, P.e_items);
+    m.scr = (char*)g.ws + P.scratch.off;
+    if (o && o->e_items && L.total > 0) HIPCHK(lt::launch_zero(o->e_items, 3 * L.total, st));
+    HIPCHK(lt::launch_zero(at_small<double>(g.ws, P, P.e_items), 3 * std::max<int64_t>(L.total, 1), st));
+    m.active = !(L.total == 0 || (P.D.v[0] == 0 && P.D.v[1] == 0));
+    if (!m.active) {
+      HIPCHK(lt::launch_zero(g.e_out, 1, st));
+      if (g.parts) HIPCHK(lt::launch_zero(g.parts, 12, st));
+    }
+  }
+  for (int x = 0; x < ng; ++x)
+    if (S[x].active) {
+      const int r = prep<T>(G[x].d, *G[x].P, G[x].ws, st);
+      if (r) return r;
+    }
+  tm.setup_end = tm.mark();
+  bool any = false;
+  for (int x = 0; x < ng; ++x) any = any || S[x].active;
+  if (!any) {
     tm.end = tm.setup_end;
     return LT_OK;
   }
-
-  {
-    const int r = prep<T>(d, P, ws, st);
-    if (r) return r;
-  }
-  const int64_t oa = D.o[0], ob = D.o[1], va = D.v[0], vb = D.v[1];
-  int64_t mstr[2][4] = {{ob * va * vb, va * vb, vb, 1}, {va * vb, ob * va * vb, 1, vb}};
-  tm.setup_end = tm.mark();
+  const bool bf = G[0].P->bf != 0;   // one precision per call
   // --- 5. triplet batches --------------------------------------------------------------
   for (int b = 0; b < 4; ++b) {
-    const int64_t nblk = P.n_blk[b];
-    if (nblk == 0) continue;
     const int s = blk_sigma(b), t = 1 - s;
     const bool mixed = blk_mixed(b);
-    const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
-    lt::ItemOps<T> ops{};
-    ops.o_s = (int32_t)os; ops.v_s = (int32_t)vs; ops.o_t = (int32_t)ot; ops.v_t = (int32_t)vt;
-    ops.oi_s = (int32_t)D.oi[s]; ops.oi_t = (int32_t)D.oi[t];
-    ops.ld_vs = P.ldv[s]; ops.ld_vt = P.ldv[t]; ops.ld_np = P.ldnp[s]; ops.ld_cb = P.ldcb[s];
-    ops.T2T = at<T>(ws, P.T2T[s]); ops.Tp = at<T>(ws, P.Tp[s]); ops.As = at<T>(ws, P.As[s]);
-    ops.GamT = at<T>(ws, P.GamT[s]);
-    if (mixed) {
-      ops.LmixT = at<T>(ws, P.LmixT[s]); ops.Mst = at<T>(ws, P.Mst[s]); ops.Mts = at<T>(ws, P.Mts[s]);
-      ops.Tmix = at<T>(ws, P.Tmix[s]); ops.ZpT = at<T>(ws, P.ZpT[s]); ops.TmT = at<T>(ws, P.TmT[s]);
-      ops.OOT = at<T>(ws, P.OOT[s]);
-    }
-    lt::ItemOps8 o8{};
-    if (P.bf) {
-      o8.o_s = ops.o_s; o8.v_s = ops.v_s; o8.o_t = ops.o_t; o8.v_t = ops.v_t;
-      o8.oi_s = ops.oi_s; o8.oi_t = ops.oi_t;
-      o8.ld_vs = ops.ld_vs; o8.ld_vt = ops.ld_vt; o8.ld_np = ops.ld_np; o8.ld_cb = ops.ld_cb;
-      auto H = [&](int t8) { return P.O8h[s][t8].bytes ? at<lt::bf16_t>(ws, P.O8h[s][t8]) : nullptr; };
-      auto Lo = [&](int t8) { return P.O8l[s][t8].bytes ? at<lt::bf16_t>(ws, P.O8l[s][t8]) : nullptr; };
-      o8.T2Th = H(Plan::T2T8); o8.T2Tl = Lo(Plan::T2T8); o8.Ash = H(Plan::As8); o8.Asl = Lo(Plan::As8);
-      o8.GamTh = H(Plan::GamT8); o8.GamTl = Lo(Plan::GamT8); o8.Tph = H(Plan::Tp8); o8.Tpl = Lo(Plan::Tp8);
-      o8.LmixTh = H(Plan::LmixT8); o8.LmixTl = Lo(Plan::LmixT8); o8.Msth = H(Plan::Mst8); o8.Mstl = Lo(Plan::Mst8);
-      o8.Mtsh = H(Plan::Mts8); o8.Mtsl = Lo(Plan::Mts8); o8.Tmixh = H(Plan::Tmix8); o8.Tmixl = Lo(Plan::Tmix8);
-      o8.Tmx2h = H(Plan::Tmx28); o8.Tmx2l = Lo(Plan::Tmx28); o8.ZpTh = H(Plan::ZpT8); o8.ZpTl = Lo(Plan::ZpT8);
-      o8.TmTh = H(Plan::TmT8); o8.TmTl = Lo(Plan::TmT8); o8.OOTh = H(Plan::OOT8); o8.OOTl = Lo(Plan::OOT8);
-    }
-    // BF16 modes: segment descriptors of every item of the block, per output
-    // layout (S or G in the first half of the table, Y in the second)
-    lt::Seg8* tab0 = P.bf ? at_small<lt::Seg8>(ws, P, P.segtab) : nullptr;
-    lt::Seg8* tab1 = P.bf ? tab0 + 6 * std::max<int64_t>(L.total, 1) : nullptr;
-    if (P.bf) {
-      lt::ItemOps8 t8 = o8;
-      t8.items = d_trip + 3 * fc[b];
-      t8.kind = mixed ? 1 : 0;
-      HIPCHK(lt::launch_seg8_table(t8, (int32_t)nblk, tab0 + 6 * (int64_t)fc[b], st));
+    int64_t rounds = 0;
+    for (int x = 0; x < ng; ++x) {
+      Dom& m = S[x];
+      const Plan& P = *G[x].P;
+      const Dims& D = P.D;
+      void* ws = G[x].ws;
+      if (!m.active || P.n_blk[b] == 0) continue;
+      rounds = std::max(rounds, cdiv(P.n_blk[b], P.nb[b]));
+      lt::ItemOps<T>& ops = m.ops;
+      ops = lt::ItemOps<T>{};
+      ops.o_s = (int32_t)D.o[s]; ops.v_s = (int32_t)D.v[s]; ops.o_t = (int32_t)D.o[t]; ops.v_t = (int32_t)D.v[t];
+      ops.oi_s = (int32_t)D.oi[s]; ops.oi_t = (int32_t)D.oi[t];
+      ops.ld_vs = P.ldv[s]; ops.ld_vt = P.ldv[t]; ops.ld_np = P.ldnp[s]; ops.ld_cb = P.ldcb[s];
+      ops.T2T = at<T>(ws, P.T2T[s]); ops.Tp = at<T>(ws, P.Tp[s]); ops.As = at<T>(ws, P.As[s]);
+      ops.GamT = at<T>(ws, P.GamT[s]);
       if (mixed) {
-        t8.kind = 2;
-        HIPCHK(lt::launch_seg8_table(t8, (int32_t)nblk, tab1 + 6 * (int64_t)fc[b], st));
+        ops.LmixT = at<T>(ws, P.LmixT[s]); ops.Mst = at<T>(ws, P.Mst[s]); ops.Mts = at<T>(ws, P.Mts[s]);
+        ops.Tmix = at<T>(ws, P.Tmix[s]); ops.ZpT = at<T>(ws, P.ZpT[s]); ops.TmT = at<T>(ws, P.TmT[s]);
+        ops.OOT = at<T>(ws, P.OOT[s]);
+      }
+      // BF16 modes: segment descriptors of every item of the block, per output
+      // layout (S or G in the first half of the table, Y in the second)
+      m.tab0 = m.tab1 = nullptr;
+      if (P.bf) {
+        lt::ItemOps8 o8{};
+        o8.o_s = ops.o_s; o8.v_s = ops.v_s; o8.o_t = ops.o_t; o8.v_t = ops.v_t;
+        o8.oi_s = ops.oi_s; o8.oi_t = ops.oi_t;
+        o8.ld_vs = ops.ld_vs; o8.ld_vt = ops.ld_vt; o8.ld_np = ops.ld_np; o8.ld_cb = ops.ld_cb;
+        auto H = [&](int t8) { return P.O8h[s][t8].bytes ? at<lt::bf16_t>(ws, P.O8h[s][t8]) : nullptr; };
+        auto Lo = [&](int t8) { return P.O8l[s][t8].bytes ? at<lt::bf16_t>(ws, P.O8l[s][t8]) : nullptr; };
+        o8.T2Th = H(Plan::T2T8); o8.T2Tl = Lo(Plan::T2T8); o8.Ash = H(Plan::As8); o8.Asl = Lo(Plan::As8);
+        o8.GamTh = H(Plan::GamT8); o8.GamTl = Lo(Plan::GamT8); o8.Tph = H(Plan::Tp8); o8.Tpl = Lo(Plan::Tp8);
+        o8.LmixTh = H(Plan::LmixT8); o8.LmixTl = Lo(Plan::LmixT8); o8.Msth = H(Plan::Mst8); o8.Mstl = Lo(Plan::Mst8);
+        o8.Mtsh = H(Plan::Mts8); o8.Mtsl = Lo(Plan::Mts8); o8.Tmixh = H(Plan::Tmix8); o8.Tmixl = Lo(Plan::Tmix8);
+        o8.Tmx2h = H(Plan::Tmx28); o8.Tmx2l = Lo(Plan::Tmx28); o8.ZpTh = H(Plan::ZpT8); o8.ZpTl = Lo(Plan::ZpT8);
+        o8.TmTh = H(Plan::TmT8); o8.TmTl = Lo(Plan::TmT8); o8.OOTh = H(Plan::OOT8); o8.OOTl = Lo(Plan::OOT8);
+        m.tab0 = at_small<lt::Seg8>(ws, P, P.segtab);
+        m.tab1 = m.tab0 + 6 * std::max<int64_t>(G[x].L->total, 1);
+        const int64_t nblk = P.n_blk[b];
+        o8.items = m.d_trip + 3 * m.fc[b];
+        o8.kind = mixed ? 1 : 0;
+        HIPCHK(lt::launch_seg8_table(o8, (int32_t)nblk, m.tab0 + 6 * (int64_t)m.fc[b], st));
+        if (mixed) {
+          o8.kind = 2;
+          HIPCHK(lt::launch_seg8_table(o8, (int32_t)nblk, m.tab1 + 6 * (int64_t)m.fc[b], st));
+        }
       }
     }
-    // contraction of one batch: FP64/FP32 matrix cores, or split BF16
-    auto contract = [&](lt::GemmArgs<T>& g) -> hipError_t {
-      // an empty output (a virtual space of size zero) has nothing to compute;
-      // the tile selection below divides by the row-tile count
-      if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return hipSuccess;
-      const int force = o ? o->tile_override[g.ops.kind] - 1 : -1;   // 0 = automatic
-      if (!P.bf) return lt::launch_gemm<T>(g, st, o && o->autotune, force);
-      lt::GemmArgs16 h{};
-      h.M = g.M; h.N = g.N; h.nbatch = g.nbatch; h.nprod = P.bf;
-      h.out = (float*)g.out; h.obs = g.obs; h.ldo = g.s_mr;
-      h.kind = g.ops.kind;
-      const int64_t first_item = (g.ops.items - d_trip) / 3;     // index in the block-ordered item list
-      h.tab = (g.ops.kind == 2 ? tab1 : tab0) + 6 * first_item;
-      return lt::launch_gemm_bf16(h, st, o && o->autotune, force);
-    };
-    const int64_t nb = P.nb[b];
-    T* out1 = (T*)scr;
-    const size_t o1 = P.o1[b];
-    T* out2 = (T*)(scr + (size_t)nb * o1);
-    const size_t o2 = P.o2[b];
-    double* part = (double*)(scr + (size_t)nb * (o1 + o2));
-    const int64_t nt = P.ntile[b];
-    for (int64_t first = 0; first < nblk; first += nb) {
-      const int64_t n = std::min<int64_t>(nb, nblk - first);
-      const int32_t* items = d_trip + 3 * (fc[b] + first);
-      ops.items = items;
-      lt::GemmArgs<T> g{};
-      g.nbatch = (int32_t)n; g.mode = 1; g.s_nr = 1;
-      hipEvent_t ea = nullptr;
-      if (!mixed) {
-        ops.kind = 0;
-        g.M = (int32_t)vs; g.N = (int32_t)npair(vs); g.out = out1; g.obs = (int64_t)(o1 / P.ts); g.s_mr = P.ldnp[s];
-        g.ops = ops;
-        {
-          hipEvent_t a = tm.mark();
-          HIPCHK(contract(g));
-          tm.gemm.push_back({a, tm.mark()});
-          tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(3 * vs + 3 * os) * (double)n;
+    // output layouts of the block: S (same spin), or G then Y (mixed)
+    const int kinds[2] = {mixed ? 1 : 0, 2};
+    const int nkind = mixed ? 2 : 1;
+    for (int64_t r = 0; r < rounds; ++r) {
+      // this round's batch of domain x: items [first, first + n) of block b
+      auto batch_of = [&](int x, int64_t& first, int64_t& n) {
+        const Plan& P = *G[x].P;
+        first = r * P.nb[b];
+        n = (S[x].active && P.n_blk[b] > first) ? std::min<int64_t>(P.nb[b], P.n_blk[b] - first) : 0;
+        return n > 0;
+      };
+      for (int kx = 0; kx < nkind; ++kx) {
+        const int kind = kinds[kx];
+        // one domain's contraction arguments for this round and layout
+        auto args = [&](int x, int64_t first, int64_t n, lt::GemmArgs<T>& g) {
+          const Plan& P = *G[x].P;
+          const Dims& D = P.D;
+          const int64_t vs = D.v[s], vt = D.v[t], os = D.o[s], ot = D.o[t];
+          Dom& m = S[x];
+          g = lt::GemmArgs<T>{};
+          g.nbatch = (int32_t)n; g.mode = 1; g.s_nr = 1;
+          g.ops = m.ops;
+          g.ops.items = m.d_trip + 3 * (m.fc[b] + first);
+          g.ops.kind = kind;
+          if (kind == 0) {
+            g.M = (int32_t)vs; g.N = (int32_t)npair(vs); g.out = (T*)m.scr; g.obs = (int64_t)(P.o1[b] / P.ts);
+            g.s_mr = P.ldnp[s];
+            return 2.0 * (double)g.M * (double)g.N * (double)(3 * vs + 3 * os) * (double)n;
+          }
+          if (kind == 1) {
+            g.M = (int32_t)vs; g.N = (int32_t)(vt * vs); g.out = (T*)m.scr; g.obs = (int64_t)(P.o1[b] / P.ts);
+            g.s_mr = P.ldcb[s];
+            return 2.0 * (double)g.M * (double)g.N * (double)(2 * vt + vs + os + 2 * ot) * (double)n;
+          }
+          g.M = (int32_t)vt; g.N = (int32_t)npair(vs); g.out = (T*)(m.scr + (size_t)P.nb[b] * P.o1[b]);
+          g.obs = (int64_t)(P.o2[b] / P.ts); g.s_mr = P.ldnp[s];
+          return 2.0 * (double)g.M * (double)g.N * (double)(2 * vs + 2 * os) * (double)n;
+        };
+        const int force = o ? o->tile_override[kind] - 1 : -1;   // 0 = automatic
+        const bool tune = o && o->autotune;
+        // an empty output (a virtual space of size zero) has nothing to compute;
+        // the tile selection divides by the row-tile count
+        auto empty = [](const lt::GemmArgs<T>& g) { return g.M <= 0 || g.N <= 0 || g.nbatch <= 0; };
+        // BF16 descriptor of one domain's batch
+        auto chunk = [&](int x, const lt::GemmArgs<T>& g) {
+          const int64_t first_item = (g.ops.items - S[x].d_trip) / 3;   // index in the block-ordered item list
+          return lt::Chunk16{g.M, g.N, g.nbatch, (float*)g.out, g.obs, g.s_mr,
+                             (kind == 2 ? S[x].tab1 : S[x].tab0) + 6 * first_item};
+        };
+        std::vector<int> xs;
+        std::vector<lt::GemmArgs<T>> gs;
+        for (int x = 0; x < ng; ++x) {
+          int64_t first, n;
+          if (!batch_of(x, first, n)) continue;
+          lt::GemmArgs<T> g;
+          tm.gemm_flops += args(x, first, n, g);
+          if (empty(g)) continue;
+          xs.push_back(x);
+          gs.push_back(g);
         }
-        if (P.dump_w) HIPCHK(lt::launch_dump_w_same<T>(out1, P.ldnp[s], (int32_t)vs, P.dump_w, st));
-        ea = tm.mark();
-        lt::EpiSame<T> e{};
-        e.o = (int32_t)os; e.v = (int32_t)vs; e.ld_np = P.ldnp[s];
-        e.S = out1; e.s_item = (int64_t)(o1 / P.ts); e.items = items;
-        e.nt = (int32_t)cdiv(vs, lt::ET); e.ntri = (int32_t)nt;
-        e.eo = EO[s]; e.ev = EV[s]; e.t1 = T1[s]; e.f = Fov[s]; e.t2 = T2ss[s];
-        e.U = at<double>(ws, P.U[s]); e.ld_v = P.ldv[s]; e.part = part;
-        if (P.lap) { e.lap = P.lap; e.lap_o0 = (int32_t)D.oi[s]; e.lap_slot = 2; }   // (j, k, central)
-        HIPCHK(lt::launch_epi_same<T>(e, (int32_t)n, st));
-      } else {
-        ops.kind = 1;
-        g.M = (int32_t)vs; g.N = (int32_t)(vt * vs); g.out = out1; g.obs = (int64_t)(o1 / P.ts); g.s_mr = P.ldcb[s];
-        g.ops = ops;
-        {
-          hipEvent_t a = tm.mark();
-          HIPCHK(contract(g));
-          tm.gemm.push_back({a, tm.mark()});
-          tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(2 * vt + vs + os + 2 * ot) * (double)n;
+        hipEvent_t a = tm.mark();
+        if (!bf) {
+          for (auto& g : gs) HIPCHK(lt::launch_gemm<T>(g, st, tune, force));
+        } else if (gs.size() == 1) {
+          const lt::Chunk16 c = chunk(xs[0], gs[0]);
+          lt::GemmArgs16 h{};
+          h.M = c.M; h.N = c.N; h.nbatch = c.nbatch; h.nprod = G[xs[0]].P->bf;
+          h.out = c.out; h.obs = c.obs; h.ldo = c.ldo; h.kind = kind; h.tab = c.tab;
+          HIPCHK(lt::launch_gemm_bf16(h, st, tune, force));
+        } else {
+          // one launch per tile-selection class (32-row blocks of M, log2 N),
+          // so that every domain's items run in the tile shape a launch of
+          // its own would take (a shared larger tile pads the smaller
+          // domains' rows: measured up to 1.5x slower); classes in the order
+          // of their first domain
+          auto cls = [](const lt::GemmArgs<T>& g) {
+            int nlog = 0;
+            while ((1 << (nlog + 1)) <= g.N) ++nlog;
+            return std::make_pair((g.M + 31) / 32, nlog);
+          };
+          std::vector<bool> done(gs.size(), false);
+          for (size_t c0 = 0; c0 < gs.size(); ++c0) {
+            if (done[c0]) continue;
+            lt::GemmArgs16 h{};
+            h.nprod = G[xs[c0]].P->bf; h.kind = kind;
+            for (size_t c = c0; c < gs.size() && h.nchunk < lt::kMaxChunk16; ++c) {
+              if (done[c] || cls(gs[c]) != cls(gs[c0])) continue;
+              const lt::Chunk16 ch = chunk(xs[c], gs[c]);
+              h.ch[h.nchunk++] = ch;
+              h.M = std::max(h.M, ch.M); h.N = std::max(h.N, ch.N); h.nbatch += ch.nbatch;
+              done[c] = true;
+            }
+            if (h.nchunk == 1) {   // alone in its class: the plain launch
+              const lt::Chunk16 c = h.ch[0];
+              h = lt::GemmArgs16{};
+              h.M = c.M; h.N = c.N; h.nbatch = c.nbatch; h.nprod = G[xs[c0]].P->bf;
+              h.out = c.out; h.obs = c.obs; h.ldo = c.ldo; h.kind = kind; h.tab = c.tab;
+            }
+            HIPCHK(lt::launch_gemm_bf16(h, st, tune, force));
+          }
         }
-        ops.kind = 2;
-        g.M = (int32_t)vt; g.N = (int32_t)npair(vs); g.out = out2; g.obs = (int64_t)(o2 / P.ts); g.s_mr = P.ldnp[s];
-        g.ops = ops;
-        {
-          hipEvent_t a = tm.mark();
-          HIPCHK(contract(g));
-          tm.gemm.push_back({a, tm.mark()});
-          tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(2 * vs + 2 * os) * (double)n;
-        }
-        if (P.dump_w)
-          HIPCHK(lt::launch_dump_w_mixed<T>(out1, P.ldcb[s], out2, P.ldnp[s], (int32_t)vs, (int32_t)vt, P.dump_w, st));
-        ea = tm.mark();
-        lt::EpiMixed<T> e{};
-        e.o_s = (int32_t)os; e.v_s = (int32_t)vs; e.o_t = (int32_t)ot; e.v_t = (int32_t)vt;
-        e.ld_np = P.ldnp[s]; e.ld_cb = P.ldcb[s];
-        e.G = out1; e.g_item = (int64_t)(o1 / P.ts); e.Y = out2; e.y_item = (int64_t)(o2 / P.ts);
-        e.items = items;
-        e.nts = (int32_t)cdiv(vs, lt::ET); e.ntt = (int32_t)cdiv(vt, lt::ET); e.ntiles = (int32_t)nt;
-        e.eo_s = EO[s]; e.ev_s = EV[s]; e.eo_t = EO[t]; e.ev_t = EV[t];
-        e.t1_s = T1[s]; e.t1_t = T1[t]; e.f_s = Fov[s]; e.f_t = Fov[t]; e.t2ss = T2ss[s];
-        e.U = at<double>(ws, P.U[s]); e.ld_vs = P.ldv[s];
-        const double* ovab = at<double>(ws, P.OVab);
-        // OVab[i_a][a_a][J_b][B_b]
-        const int64_t so[4] = {va * ob * vb, ob * vb, vb, 1};   // (occ_a, vir_a, occ_b, vir_b)
-        e.ov = ovab;
-        if (s == 0) { e.ov_o = so[0]; e.ov_v = so[1]; e.ov_O = so[2]; e.ov_V = so[3]; }
-        else { e.ov_o = so[2]; e.ov_v = so[3]; e.ov_O = so[0]; e.ov_V = so[1]; }
-        e.tm = d->t2ab; e.tm_o = mstr[s][0]; e.tm_v = mstr[s][2]; e.tm_O = mstr[s][1]; e.tm_V = mstr[s][3];
-        e.part = part;
-        if (P.lap) {   // central orbital in the same-spin pair (i, central, K) or the odd slot (I, J, central)
-          e.lap = P.lap;
-          e.lap_slot = s == P.lap_spin ? 1 : 2;
-          e.lap_o0 = (int32_t)D.oi[P.lap_spin];
-        }
-        HIPCHK(lt::launch_epi_mixed<T>(e, (int32_t)n, st));
+        if (!gs.empty()) tm.gemm.push_back({a, tm.mark()});
       }
-      HIPCHK(lt::launch_reduce_items(part, (int32_t)n, (int32_t)nt, d_dst + fc[b] + first, e_items, st));
-      tm.epi.push_back({ea, tm.mark()});
+      // epilogues and per-item reductions, domain by domain
+      for (int x = 0; x < ng; ++x) {
+        int64_t first, n;
+        if (!batch_of(x, first, n)) continue;
+        const GroupDom& gd = G[x];
+        const ltriples_domain* d = gd.d;
+        const Plan& P = *gd.P;
+        const Dims& D = P.D;
+        Dom& m = S[x];
+        const int64_t os = D.o[s], vs = D.v[s], ot = D.o[t], vt = D.v[t];
+        const int64_t va = D.v[0], ob = D.o[1], vb = D.v[1];
+        const double* T2ss[2] = {d->t2aa, d->t2bb};
+        const double* T1[2] = {d->t1a, d->t1b};
+        const double* Fov[2] = {d->fov_a, d->fov_b};
+        const double* EO[2] = {d->eo_a, d->eo_b};
+        const double* EV[2] = {d->ev_a, d->ev_b};
+        const size_t o1 = P.o1[b], o2 = P.o2[b];
+        const int64_t nb = P.nb[b], nt = P.ntile[b];
+        T* out1 = (T*)m.scr;
+        T* out2 = (T*)(m.scr + (size_t)nb * o1);
+        double* part = (double*)(m.scr + (size_t)nb * (o1 + o2));
+        const int32_t* items = m.d_trip + 3 * (m.fc[b] + first);
+        hipEvent_t ea = nullptr;
+        if (!mixed) {
+          if (P.dump_w) HIPCHK(lt::launch_dump_w_same<T>(out1, P.ldnp[s], (int32_t)vs, P.dump_w, st));
+          ea = tm.mark();
+          lt::EpiSame<T> e{};
+          e.o = (int32_t)os; e.v = (int32_t)vs; e.ld_np = P.ldnp[s];
+          e.S = out1; e.s_item = (int64_t)(o1 / P.ts); e.items = items;
+          e.nt = (int32_t)cdiv(vs, lt::ET); e.ntri = (int32_t)nt;
+          e.eo = EO[s]; e.ev = EV[s]; e.t1 = T1[s]; e.f = Fov[s]; e.t2 = T2ss[s];
+          e.U = at<double>(gd.ws, P.U[s]); e.ld_v = P.ldv[s]; e.part = part;
+          if (P.lap) { e.lap = P.lap; e.lap_o0 = (int32_t)D.oi[s]; e.lap_slot = 2; }   // (j, k, central)
+          HIPCHK(lt::launch_epi_same<T>(e, (int32_t)n, st));
+        } else {
+          if (P.dump_w)
+            HIPCHK(lt::launch_dump_w_mixed<T>(out1, P.ldcb[s], out2, P.ldnp[s], (int32_t)vs, (int32_t)vt, P.dump_w,
+                                              st));
+          ea = tm.mark();
+          lt::EpiMixed<T> e{};
+          e.o_s = (int32_t)os; e.v_s = (int32_t)vs; e.o_t = (int32_t)ot; e.v_t = (int32_t)vt;
+          e.ld_np = P.ldnp[s]; e.ld_cb = P.ldcb[s];
+          e.G = out1; e.g_item = (int64_t)(o1 / P.ts); e.Y = out2; e.y_item = (int64_t)(o2 / P.ts);
+          e.items = items;
+          e.nts = (int32_t)cdiv(vs, lt::ET); e.ntt = (int32_t)cdiv(vt, lt::ET); e.ntiles = (int32_t)nt;
+          e.eo_s = EO[s]; e.ev_s = EV[s]; e.eo_t = EO[t]; e.ev_t = EV[t];
+          e.t1_s = T1[s]; e.t1_t = T1[t]; e.f_s = Fov[s]; e.f_t = Fov[t]; e.t2ss = T2ss[s];
+          e.U = at<double>(gd.ws, P.U[s]); e.ld_vs = P.ldv[s];
+          // OVab[i_a][a_a][J_b][B_b]
+          const int64_t so[4] = {va * ob * vb, ob * vb, vb, 1};   // (occ_a, vir_a, occ_b, vir_b)
+          e.ov = at<double>(gd.ws, P.OVab);
+          if (s == 0) { e.ov_o = so[0]; e.ov_v = so[1]; e.ov_O = so[2]; e.ov_V = so[3]; }
+          else { e.ov_o = so[2]; e.ov_v = so[3]; e.ov_O = so[0]; e.ov_V = so[1]; }
+          const int64_t mstr[2][4] = {{ob * va * vb, va * vb, vb, 1}, {va * vb, ob * va * vb, 1, vb}};
+          e.tm = d->t2ab; e.tm_o = mstr[s][0]; e.tm_v = mstr[s][2]; e.tm_O = mstr[s][1]; e.tm_V = mstr[s][3];
+          e.part = part;
+          if (P.lap) {   // central orbital in the same-spin pair (i, central, K) or the odd slot (I, J, central)
+            e.lap = P.lap;
+            e.lap_slot = s == P.lap_spin ? 1 : 2;
+            e.lap_o0 = (int32_t)D.oi[P.lap_spin];
+          }
+          HIPCHK(lt::launch_epi_mixed<T>(e, (int32_t)n, st));
+        }
+        HIPCHK(lt::launch_reduce_items(part, (int32_t)n, (int32_t)nt, m.d_dst + m.fc[b] + first, m.e_items, st));
+        tm.epi.push_back({ea, tm.mark()});
+      }
     }
   }
 
   // --- 6. totals ----------------------------------------------------------------------
-  HIPCHK(lt::launch_reduce_final(e_items, d_dst, d_fc, d_fc + 4, parts, e_out, st));
+  for (int x = 0; x < ng; ++x)
+    if (S[x].active)
+      HIPCHK(lt::launch_reduce_final(S[x].e_items, S[x].d_dst, S[x].d_fc, S[x].d_fc + 4, G[x].parts, G[x].e_out, st));
   tm.end = tm.mark();
-  (void)ob;
   return LT_OK;
+}
+
+template <typename T>
+int run(const ltriples_domain* d, const Plan& P, const ItemLists& L, const ltriples_options* o,
+        double* e_out, double* parts, void* ws, hipStream_t st, Timing& tm) {
+  const GroupDom g{d, &P, &L, e_out, parts, ws};
+  return run_group<T>(&g, 1, o, st, tm);
 }
 
 // Every occupied energy below every virtual energy by at least 1e-100 and
@@ -2194,6 +2306,8 @@ namespace {
 struct BatchPlan {
   std::vector<ItemLists> L;
   std::vector<Plan> P;
+  std::vector<size_t> base;                 // start of each domain's big region in the workspace
+  std::vector<std::vector<int32_t>> groups; // launch groups, each longest first
   size_t total = 0;
 };
 
@@ -2213,17 +2327,53 @@ int plan_batch(const ltriples_domain* ds, int32_t ndom, int32_t precision, const
   }
   B.L.resize(ndom);
   B.P.resize(ndom);
-  size_t big = 0;
+  std::vector<double> cost(ndom, 0.0);
   for (int32_t d = 0; d < ndom; ++d) {
     build_items(dims_of(&ds[d]), nullptr, B.L[d]);
     plan_domain(&ds[d], precision, o, B.L[d], B.P[d]);
     const int r = check_plan(B.P[d]);
     if (r) return r;
-    big = std::max(big, B.P[d].big);
+    for (int b = 0; b < 4; ++b) cost[d] += (double)B.P[d].n_blk[b] * item_flops(B.P[d].D, b);
+  }
+  // Launch groups.  Without a group budget every domain runs alone and all
+  // share one big region.  With one, the domains in descending order of
+  // their triples flops (longest processing time first; ties by index) are
+  // packed greedily into groups of consecutive domains, at most
+  // kMaxChunk16, whose big regions together stay within the budget (a
+  // domain larger than the budget forms a group of its own); the domains of
+  // a group get big regions of their own, one after another.
+  const size_t gbudget = o ? o->group_budget : 0;
+  std::vector<int32_t> order(ndom);
+  for (int32_t d = 0; d < ndom; ++d) order[d] = d;
+  B.groups.clear();
+  if (gbudget == 0) {
+    for (int32_t d = 0; d < ndom; ++d) B.groups.push_back({d});
+  } else {
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    size_t used = 0;
+    for (int32_t d : order) {
+      const size_t need = align256(B.P[d].big);
+      if (B.groups.empty() || B.groups.back().size() >= (size_t)lt::kMaxChunk16 || used + need > gbudget) {
+        B.groups.push_back({});
+        used = 0;
+      }
+      B.groups.back().push_back(d);
+      used += need;
+    }
+  }
+  B.base.assign(ndom, 0);
+  size_t big = 0;
+  for (const auto& g : B.groups) {
+    size_t off = 0;
+    for (int32_t d : g) {
+      B.base[d] = off;
+      off += align256(B.P[d].big);
+    }
+    big = std::max(big, off);
   }
   size_t off = align256(big);
   for (int32_t d = 0; d < ndom; ++d) {
-    B.P[d].small_base = off;
+    B.P[d].small_base = off - B.base[d];   // relative to the domain's own base
     off = align256(off + B.P[d].small);
   }
   B.total = std::max<size_t>(off, 256);
@@ -2247,7 +2397,7 @@ std::vector<uint64_t> batch_key(const ltriples_domain* ds, int32_t ndom, int32_t
   std::vector<uint64_t> k = {(uint64_t)device, (uint64_t)precision, (uint64_t)ndom, (uint64_t)(uintptr_t)e_out,
                              (uint64_t)(uintptr_t)parts, (uint64_t)(uintptr_t)ws, (uint64_t)ws_bytes,
                              (uint64_t)(o ? o->workspace_budget : 0), (uint64_t)(o ? o->batch_items : 0),
-                             (uint64_t)(o ? o->build_chunk_mib : 0)};
+                             (uint64_t)(o ? o->build_chunk_mib : 0), (uint64_t)(o ? o->group_budget : 0)};
   for (int t = 0; t < 3; ++t) k.push_back((uint64_t)(o ? o->tile_override[t] : 0));
   for (int32_t d = 0; d < ndom; ++d) {
     const ltriples_domain& x = ds[d];
@@ -2265,11 +2415,14 @@ int enqueue_batch(const ltriples_domain* ds, int32_t ndom, int32_t precision, co
   // item lists, per-item outputs and stats are single-domain options
   ltriples_options oo = o ? *o : ltriples_options{};
   oo.items = nullptr; oo.n_items = 0; oo.e_items = nullptr; oo.stats = nullptr;
-  for (int32_t d = 0; d < ndom; ++d) {
+  (void)ndom;
+  for (const auto& grp : B.groups) {
+    std::vector<GroupDom> G;
+    for (int32_t d : grp)
+      G.push_back({&ds[d], &B.P[d], &B.L[d], e_out + d, parts ? parts + 12 * d : nullptr, (char*)ws + B.base[d]});
     Timing tm;  // off
-    const int r = precision == LT_FP64
-                      ? run<double>(&ds[d], B.P[d], B.L[d], &oo, e_out + d, parts ? parts + 12 * d : nullptr, ws, st, tm)
-                      : run<float>(&ds[d], B.P[d], B.L[d], &oo, e_out + d, parts ? parts + 12 * d : nullptr, ws, st, tm);
+    const int r = precision == LT_FP64 ? run_group<double>(G.data(), (int)G.size(), &oo, st, tm)
+                                       : run_group<float>(G.data(), (int)G.size(), &oo, st, tm);
     if (r) return r;
   }
   return LT_OK;
@@ -2310,10 +2463,11 @@ int ltriples_energy_batched(const ltriples_domain* ds, int32_t ndom, int32_t pre
   // item tables go to each domain's small region on every call (also before a
   // replay: the caller may have used the workspace for other calls meanwhile)
   for (int32_t d = 0; d < ndom; ++d) {
-    r = upload_items(B.P[d], B.L[d], ws, st);
+    void* wsd = (char*)ws + B.base[d];
+    r = upload_items(B.P[d], B.L[d], wsd, st);
     if (r) return r;
     if (o && o->check_finite) {
-      r = scan_finite(&ds[d], B.P[d], ws, st);
+      r = scan_finite(&ds[d], B.P[d], wsd, st);
       if (r) return fail(r, "domain %d: %s", d, g_err.c_str());
     }
   }

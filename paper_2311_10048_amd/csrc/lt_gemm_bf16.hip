@@ -114,16 +114,33 @@ __global__ __launch_bounds__(256, 2) void k_tgemm_bf16(GemmArgs16 g) {
     const int nblk = gridDim.x, x = b & 7, q = nblk >> 3, r = nblk & 7;
     b = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + (b >> 3);
   }
+  // the launch's items: one output shape, or chunks of several domains (the
+  // chunk owning this work-group found by a search over their first
+  // work-groups; all of it wave-uniform)
+  int M = g.M, N = g.N, nbatch = g.nbatch, mt = g.mt, nt = g.nt;
+  float* obase = g.out;
+  int64_t obs = g.obs, ldo = g.ldo;
+  const Seg8* tbase = g.tab;
+  if (g.nchunk > 0) {
+    int c = 0;
+#pragma unroll
+    for (int st = kMaxChunk16 / 2; st > 0; st >>= 1)
+      if (c + st < g.nchunk && g.cblk[c + st] <= b) c += st;
+    b -= g.cblk[c];
+    M = g.ch[c].M; N = g.ch[c].N; nbatch = g.ch[c].nbatch;
+    obase = g.ch[c].out; obs = g.ch[c].obs; ldo = g.ch[c].ldo; tbase = g.ch[c].tab;
+    mt = (M + BM - 1) / BM; nt = (N + BN - 1) / BN;
+  }
   // tile order: row tile, then GI consecutive items, then column tile, so the
   // work-groups in flight on one XCD share right-operand slices in its L2
-  const int mtile = b % g.mt; b /= g.mt;
-  const int GI = items_per_group(g.mt);
+  const int mtile = b % mt; b /= mt;
+  const int GI = items_per_group(mt);
   const int ig = b % GI; b /= GI;
-  const int ntile = b % g.nt; b /= g.nt;
+  const int ntile = b % nt; b /= nt;
   const int batch = b * GI + ig;
-  if (batch >= g.nbatch) return;                 // whole work-group: before any barrier
+  if (batch >= nbatch) return;                   // whole work-group: before any barrier
   const int m0 = mtile * BM, n0 = ntile * BN;
-  const Seg8* tab = g.tab + (int64_t)batch * 6;   // read with wave-uniform (scalar) loads
+  const Seg8* tab = tbase + (int64_t)batch * 6;   // read with wave-uniform (scalar) loads
   const int nseg = g.kind >= 2 ? 4 : 6;
 
   f32x16 acc[MBW][NBW];
@@ -266,17 +283,17 @@ __global__ __launch_bounds__(256, 2) void k_tgemm_bf16(GemmArgs16 g) {
     cur ^= 1;
   }
 
-  float* out = g.out + (int64_t)batch * g.obs;
+  float* out = obase + (int64_t)batch * obs;
 #pragma unroll
   for (int nb = 0; nb < NBW; ++nb) {
     const int n = n0 + bcol + nb * BC;
-    if (n >= g.N) continue;
+    if (n >= N) continue;
 #pragma unroll
     for (int mb = 0; mb < MBW; ++mb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int m = m0 + wm * MBW * BR + mb * BR + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (m < g.M) out[(int64_t)m * g.ldo + n] = acc[mb][nb][r];
+        if (m < M) out[(int64_t)m * ldo + n] = acc[mb][nb][r];
       }
   }
 }
@@ -304,10 +321,26 @@ hipError_t launch_seg8_table(const ItemOps8& ops, int32_t nitems, Seg8* tab, hip
 template <int MBW, int NBW, int WM, int NPROD>
 static hipError_t launch16(GemmArgs16 g, hipStream_t s) {
   constexpr int BM = WM * MBW * 32, BN = (4 / WM) * NBW * 32;
+  auto groups = [](int64_t M, int64_t N, int64_t nb) {   // work-groups of one output shape
+    const int64_t mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN, GI = items_per_group((int)mt);
+    return mt * nt * ((nb + GI - 1) / GI) * GI;
+  };
   g.mt = (g.M + BM - 1) / BM;
   g.nt = (g.N + BN - 1) / BN;
-  const int GI = items_per_group(g.mt);
-  const int64_t nblk = (int64_t)g.mt * g.nt * ((g.nbatch + GI - 1) / GI) * GI;
+  int64_t nblk = 0;
+  if (g.nchunk > 0) {
+    if (g.nchunk > kMaxChunk16) return hipErrorInvalidValue;
+    for (int c = 0; c < g.nchunk; ++c) {
+      const Chunk16& h = g.ch[c];
+      if (h.M <= 0 || h.N <= 0 || h.nbatch <= 0) return hipErrorInvalidValue;   // every chunk owns work-groups
+      g.cblk[c] = (int32_t)nblk;
+      nblk += groups(h.M, h.N, h.nbatch);
+      if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+    }
+    g.cblk[g.nchunk] = (int32_t)nblk;
+  } else {
+    nblk = groups(g.M, g.N, g.nbatch);
+  }
   if (nblk <= 0) return hipSuccess;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_tgemm_bf16<MBW, NBW, WM, NPROD>), dim3((unsigned)nblk), dim3(256), 0, s, g);

@@ -148,12 +148,28 @@ struct ItemOps8 {
   const int32_t* items;
 };
 
+// Items of one domain in a launch that covers several domains: their own
+// output shape, output array and segment descriptors.
+struct Chunk16 {
+  int32_t M, N, nbatch;
+  float* out; int64_t obs, ldo;
+  const Seg8* tab;                       // [nbatch][6]
+};
+constexpr int kMaxChunk16 = 16;          // domains per launch
+
 struct GemmArgs16 {
   int32_t M, N, nbatch, mt, nt;
   int32_t nprod;                         // 3: hi*hi + hi*lo + lo*hi, 1: hi*hi
   float* out; int64_t obs, ldo;
   int32_t kind;                          // 0: S, 1: G, 2: Y, 3: closed shell (segments 6, 6, 4, 4)
   const Seg8* tab;                       // [nbatch][6] segment descriptors of the launch's items
+  // nchunk > 0: the launch covers ch[0..nchunk) instead (M and N above are
+  // then the largest chunk's, for the tile choice; out, obs, ldo, tab and
+  // nbatch are unused).  Chunk c owns the work-groups [cblk[c], cblk[c+1]),
+  // filled in by the launcher for the chosen tile shape.
+  int32_t nchunk;
+  int32_t cblk[kMaxChunk16 + 1];
+  Chunk16 ch[kMaxChunk16];
 };
 
 // `tune`: on the first launch of a shape class (device, products, output

@@ -127,6 +127,32 @@ int main() {
     o.check_finite = 2;
     expect(ltriples_validate(&d, LT_FP32, &o), LT_EINVAL, "check_finite not 0/1");
   }
+  // launch groups of the batched call: every budget packs 20 domains (more
+  // than one group's 16) into regions that the sizing accounts for
+  {
+    ltriples_domain ds[20];
+    for (int k = 0; k < 20; ++k) {
+      const int32_t sh[5] = {3 + k % 5, 2 + k % 4, 20 + 7 * k, 19 + 5 * k, 40 + k};
+      ds[k] = fake_domain(sh, placeholder);
+    }
+    size_t plain = 0;
+    expect(ltriples_workspace_size_batched(ds, 20, LT_BF16X3, nullptr, &plain), LT_OK, "batched, no groups");
+    const size_t budgets[] = {1, size_t(64) << 20, size_t(1) << 50};
+    for (size_t b : budgets) {
+      ltriples_options o{};
+      o.group_budget = b;
+      for (int prec = 0; prec < 4; ++prec) {
+        size_t w = 0;
+        expect(ltriples_workspace_size_batched(ds, 20, prec, &o, &w), LT_OK, "batched with groups");
+      }
+      size_t w = 0;
+      expect(ltriples_workspace_size_batched(ds, 20, LT_BF16X3, &o, &w), LT_OK, "batched with groups");
+      if (w < plain) {
+        std::printf("group budget %zu: workspace %zu below the ungrouped %zu\n", b, w, plain);
+        ++fails;
+      }
+    }
+  }
   // central-orbital share sizing, both spins, every precision, small and LNO-sized
   {
     const double pts[3] = {0.2, 0.7, 1.9}, wts[3] = {0.3, 0.4, 0.6};

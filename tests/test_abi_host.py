@@ -132,6 +132,34 @@ def test_batched_workspace_is_shared_big_part_plus_small_parts():
     assert n1.value >= singles[1]
 
 
+def test_batched_workspace_with_launch_groups():
+    """options.group_budget: one group holds every domain's region side by
+    side (about the sum of the single-domain workspaces); a budget below
+    every domain gives one domain per group, sharing one region as without
+    groups; a budget between packs the largest domain alone."""
+    lib = _lib()
+    dims = [(5, 4, 30, 31, 120), (6, 5, 45, 47, 96), (3, 0, 12, 13, 20), (4, 4, 26, 22, 50)]
+    singles = [lt.ltriples_workspace_size(_fake_domain(x), lt.LT_BF16X3) for x in dims]
+
+    def size(budget):
+        o, _ = lt.make_options(group_budget=budget)
+        n = ctypes.c_size_t(0)
+        assert lib.ltriples_workspace_size_batched(_fake_array(dims), len(dims), lt.LT_BF16X3, ctypes.byref(o),
+                                                   ctypes.byref(n)) == lt.LT_OK
+        return n.value
+
+    plain, one, every = size(0), size(1 << 50), size(1)
+    assert every == plain
+    slack = 2 * 256 * len(dims)   # region alignment
+    assert abs(one - sum(singles)) <= slack, (one, sum(singles))
+    # the largest domain (index 1) alone, the other three together in a
+    # region no larger than its own: the same size as without groups
+    assert sum(singles) - singles[1] < singles[1]
+    between = size(max(singles))
+    assert plain <= between < one
+    assert abs(between - plain) <= slack, (between, plain)
+
+
 def test_batched_rejects_item_lists_and_bad_domains():
     lib = _lib()
     dims = [(5, 4, 30, 31, 120), (4, 3, 10, 11, 20)]
