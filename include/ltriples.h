@@ -448,8 +448,9 @@ int ltriples_rhf_flops(const ltriples_rhf_domain* d, double* flops, int64_t* n_i
  * virtual tiles.  parts = {E4, E_ST, E_DT} from the W, t1 and f_ov parts of V.
  *   e_out  device double[1]; parts device double[3] or NULL
  *   ws     device workspace >= ltriples_rhf_workspace_size(), or NULL
- * Precisions, batching (options.batch_items, workspace_budget), build chunks,
- * check_finite, autotune and stats as ltriples_energy; tile_override[0]
+ * Precisions, batching (options.batch_items, workspace_budget; here the
+ * default budget is 16 GiB), build chunks, check_finite, autotune and stats
+ * as ltriples_energy; tile_override[0]
  * forces the contraction's tile (the other entries are not used);
  * options.items, options.e_items and options.graph must be unset (LT_EINVAL).
  * Errors as ltriples_energy. */

@@ -267,8 +267,15 @@ def test_rhf_flops_items_and_workspace(no, nv, naux):
         assert w >= 8 * no * no * nv * nv
         assert lt.ltriples_rhf_spin_block_workspace_size(d, prec) >= 8 * no * no * nv * nv
     if no == 40:
-        assert lt.ltriples_rhf_workspace_size(d, lt.LT_BF16X3) < lt.ltriples_rhf_spin_block_workspace_size(
-            d, lt.LT_BF16X3)
+        # at the same batch budget the spin-adapted form needs less memory (one
+        # v^3 cube per contraction item instead of pair-packed spin-block outputs);
+        # its default budget is twice the spin-block form's
+        o8, _ = lt.make_options(workspace_budget=8 << 30)
+        assert lt.ltriples_rhf_workspace_size(d, lt.LT_BF16X3, o8) < lt.ltriples_rhf_spin_block_workspace_size(
+            d, lt.LT_BF16X3, o8)
+        o16, _ = lt.make_options(workspace_budget=16 << 30)
+        assert lt.ltriples_rhf_workspace_size(d, lt.LT_BF16X3) == lt.ltriples_rhf_workspace_size(
+            d, lt.LT_BF16X3, o16)
 
 
 def test_rhf_rejects_bad_args():
