@@ -112,9 +112,11 @@ typedef struct ltriples_stats {
 /* Options; a NULL options pointer means all defaults (zeros). */
 typedef struct ltriples_options {
   /* bytes of workspace the per-batch triples intermediates (contraction
-   * outputs and per-tile partial energies) may use; 0 = default (8 GiB,
-   * capped by the work).  Smaller budgets mean smaller item batches; results
-   * are bitwise unchanged. */
+   * outputs and per-tile partial energies) may use; 0 = default, capped by
+   * the work: 8 GiB for energies, 16 GiB for the spin-adapted closed-shell
+   * energy, 32 GiB for adjoints.  Smaller budgets mean smaller item batches;
+   * energies are bitwise unchanged (adjoints agree to rounding, as for any
+   * other batching). */
   size_t workspace_budget;
   /* optional HOST array [n_items][4] of (block, p, q, r) restricting the
    * energy to these items (NULL = all unique triplets of the domain) */

@@ -425,8 +425,12 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
   size_t s1b = 0;
   for (int s = 0; s < 2; ++s)
     if (P.need_as[s]) s1b = std::max(s1b, ts * (size_t)(P.cAs[s] * D.v[s] * D.v[s] * P.ldv[s]));
-  // phase 2: batch buffers + partials
-  const size_t budget = (o && o->workspace_budget) ? o->workspace_budget : (size_t(8) << 30);
+  // phase 2: batch buffers + partials.  Default budget: 8 GiB for the energy
+  // (16 GiB measured slower on the LNO-sized domain, 20.39 against 20.18 s);
+  // 32 GiB for the adjoint, whose reverse GEMMs gain from long concatenated
+  // contractions (gradient workload (20,18,160,162,640): FP32 4.40 s with
+  // 8 GiB, 4.07 s with 16, 3.93 s with 32; FP64 7.82, 7.08, 6.62 s)
+  const size_t budget = (o && o->workspace_budget) ? o->workspace_budget : (size_t(bwd ? 32 : 8) << 30);
   size_t s2 = 0;
   for (int b = 0; b < 4; ++b) {
     P.nb[b] = 0; P.per_item[b] = 0; P.ntile[b] = 0; P.part_off[b] = 0; P.bwg[b] = 0; P.ld_ri[b] = 0;
