@@ -207,6 +207,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--backward-fp64", action="store_true", help="also time the FP64 adjoint in the backward leg")
+    ap.add_argument("--backward-bf16x3", action="store_true",
+                    help="also time the BF16X3 adjoint (split-product recompute) in the backward leg")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: tile shapes of the contraction kernels tuned during the warmup step (results unchanged)")
     ap.add_argument("--sample-items", type=int, default=0, help="profiling aid: K sampled triplets per block")
@@ -440,7 +442,7 @@ def main():
     backward = None
     try:
         if not args.no_backward and step_items is None:
-            backward = run_backward(lt, synth, torch, log, fp64=args.backward_fp64)
+            backward = run_backward(lt, synth, torch, log, fp64=args.backward_fp64, bf16x3=args.backward_bf16x3)
     except Exception as ex:   # a failed side leg must not lose the measured step
         backward = {"error": f"{type(ex).__name__}: {ex}"}
         log(f"backward leg failed: {ex}")
@@ -864,10 +866,11 @@ def run_naf(args, lt, synth, torch):
     print(json.dumps(res), flush=True)
 
 
-def run_backward(lt, synth, torch, log, fp64=False):
-    """Adjoint pass on the gradient workload: FP32 (timed after one warmup)
-    and, with fp64, FP64; 3F / t in GFLOP/s; sampled items against the oracle
-    gradient in both precisions."""
+def run_backward(lt, synth, torch, log, fp64=False, bf16x3=False):
+    """Adjoint pass on the gradient workload: FP32 (timed after one warmup),
+    with bf16x3 the BF16X3 adjoint (split-product recompute, FP32 reverse
+    GEMMs; timed after one warmup) and with fp64 FP64; 3F / t in GFLOP/s;
+    sampled items against the oracle gradient in every precision run."""
     from oracle import grad as ograd
     dom = synth.config_domain("grad")
     tens = {k: torch.from_numpy(v).cuda() for k, v in dom.arrays().items()}
@@ -875,9 +878,11 @@ def run_backward(lt, synth, torch, log, fp64=False):
     F, n = lt.ltriples_flops(d)
     res = {"workload": f"grad domain: noa={dom.noa} nob={dom.nob} nva={dom.nva} nvb={dom.nvb} naux={dom.naux}, "
                        f"all {n} occupied triplets", "algorithmic_flops_3F": 3 * F}
-    for name, prec in (("fp32", lt.LT_FP32), ("fp64", lt.LT_FP64))[:2 if fp64 else 1]:
+    legs = [("fp32", lt.LT_FP32)] + ([("bf16x3", lt.LT_BF16X3)] if bf16x3 else []) \
+        + ([("fp64", lt.LT_FP64)] if fp64 else [])
+    for name, prec in legs:
         ws = torch.empty(lt.ltriples_backward_workspace_size(d, prec), dtype=torch.uint8, device="cuda")
-        reps = 2 if name == "fp32" else 1
+        reps = 1 if name == "fp64" else 2
         for r in range(reps):
             st = lt.Stats()
             g = lt.ltriples_backward(tens, dom.dims, prec, workspace=ws, stats=st)
@@ -891,7 +896,7 @@ def run_backward(lt, synth, torch, log, fp64=False):
     _, ref = ograd.energy_and_grad(dom, items=items, fock=True)
     dt = time.perf_counter() - tc
     err = {}
-    for name, prec in (("fp32", lt.LT_FP32), ("fp64", lt.LT_FP64)):
+    for name, prec in (("fp32", lt.LT_FP32), ("fp64", lt.LT_FP64)) + ((("bf16x3", lt.LT_BF16X3),) if bf16x3 else ()):
         g = lt.ltriples_backward(tens, dom.dims, prec, items=items)
         torch.cuda.synchronize()
         worst = 0.0
@@ -902,8 +907,11 @@ def run_backward(lt, synth, torch, log, fp64=False):
         err[name] = worst
     res["parity"] = {"oracle_items": int(len(items)), "max_rel_err_fp64": err["fp64"], "tol_fp64": 1e-10,
                      "max_rel_err_fp32": err["fp32"], "tol_fp32": 1e-5,
-                     "pass": bool(err["fp64"] <= 1e-10 and err["fp32"] <= 1e-5), "oracle_seconds": round(dt, 1)}
-    log(f"backward parity: fp64 {err['fp64']:.2e}, fp32 {err['fp32']:.2e}")
+                     "pass": bool(err["fp64"] <= 1e-10 and err["fp32"] <= 1e-5
+                                  and err.get("bf16x3", 0.0) <= 1e-5), "oracle_seconds": round(dt, 1)}
+    if bf16x3:
+        res["parity"].update({"max_rel_err_bf16x3": err["bf16x3"], "tol_bf16x3": 1e-5})
+    log("backward parity: " + ", ".join(f"{k} {v:.2e}" for k, v in err.items()))
     return res
 
 

@@ -365,7 +365,10 @@ int ltriples_backward_workspace_size(const ltriples_domain* d, int32_t precision
  *          (stream-ordered allocation, as ltriples_energy)
  * Precision LT_FP64 or LT_FP32 (the contractions and operand gradients in
  * that precision, the epilogue, the integral gradients and the DF
- * back-contraction in FP64); other values give LT_EPREC.  options.e_items
+ * back-contraction in FP64), or LT_BF16X3 (the forward contraction
+ * recomputed from split BF16 products as in ltriples_energy, everything
+ * else as LT_FP32; the workspace keeps both the FP32 operands and their
+ * split copies); LT_BF16 gives LT_EPREC.  options.e_items
  * must be NULL.  Enqueued on `stream`; the call synchronises the stream once
  * after uploading its work descriptors.  Errors as ltriples_energy. */
 int ltriples_backward(const ltriples_domain* d, int32_t precision,
@@ -493,8 +496,9 @@ int ltriples_backward_rhf_workspace_size(const ltriples_rhf_domain* d, int32_t p
  * the aaa and aab items with 2 gbar; the alpha and beta gradients of each
  * shared input are added, and dE/dtau collects the mixed-spin gradient
  * (symmetrised) and twice the same-spin ones (tau enters the same-spin
- * amplitudes as tau^{ab}_{ij} - tau^{ba}_{ij}).  Precision LT_FP64 or
- * LT_FP32; options as ltriples_energy_rhf; errors as ltriples_backward. */
+ * amplitudes as tau^{ab}_{ij} - tau^{ba}_{ij}).  Precision LT_FP64, LT_FP32
+ * or LT_BF16X3 (as ltriples_backward); options as ltriples_energy_rhf;
+ * errors as ltriples_backward. */
 int ltriples_backward_rhf(const ltriples_rhf_domain* d, int32_t precision,
                           const ltriples_options* o, const double* gbar,
                           const ltriples_rhf_grad* grad, void* ws, size_t ws_bytes,

@@ -814,10 +814,10 @@ _TE = None
 def triples_energy(tensors: Mapping[str, object], dims, precision="fp64", backward_precision=None):
     """Differentiable E(T) (0-d float64 tensor).  Gradients flow to T1, T2,
     the DF factors, f_ov and the orbital energies through ltriples_backward,
-    which has FP64 and FP32 kernels only: `backward_precision` picks one
-    ("fp64" or "fp32"); by default FP64 for an FP64 forward and FP32 for
-    every reduced-precision forward (FP32, BF16X3, BF16), i.e. the gradient
-    of a BF16X3 energy is the FP32 adjoint of the same function."""
+    which runs in FP64, FP32 or BF16X3 (the forward contraction recomputed in
+    split BF16 products, FP32 reverse GEMMs): `backward_precision` picks one
+    ("fp64", "fp32" or "bf16x3"); by default FP64 for an FP64 forward and
+    FP32 for every reduced-precision forward (FP32, BF16X3, BF16)."""
     global _TE
     if _TE is None:
         _TE = _autograd_function()
@@ -827,6 +827,6 @@ def triples_energy(tensors: Mapping[str, object], dims, precision="fp64", backwa
         bprec = LT_FP64 if precision == LT_FP64 else LT_FP32
     else:
         bprec = PRECISIONS[backward_precision] if isinstance(backward_precision, str) else int(backward_precision)
-        if bprec not in (LT_FP64, LT_FP32):
-            raise ValueError("backward_precision must be fp64 or fp32 (the adjoint has no BF16 kernels)")
+        if bprec not in (LT_FP64, LT_FP32, LT_BF16X3):
+            raise ValueError("backward_precision must be fp64, fp32 or bf16x3")
     return _TE.apply(int(precision), int(bprec), tuple(int(x) for x in dims), *(tensors[k] for k in ARRAY_FIELDS))

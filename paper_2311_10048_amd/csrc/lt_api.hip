@@ -232,6 +232,9 @@ struct Plan {
   Buf rblk, rseg, dfblk, dfseg, rred, dfred, rpart;
   // BF16 modes: hi/lo octet copies of the contraction operands
   int bf = 0;                     // 0: none, 3: split products, 1: plain bf16
+  // BF16X3 adjoint: the FP32 operands stay resident for the reverse GEMMs
+  // beside their octet copies (the forward keeps only the octets)
+  bool keep32 = false;
   enum { T2T8, As8, GamT8, Tp8, LmixT8, Mst8, Mts8, Tmix8, Tmx28, ZpT8, TmT8, OOT8, NT8 };
   Buf O8h[2][NT8], O8l[2][NT8];
   // operand builds split along their leading occupied index: blocks per
@@ -284,13 +287,15 @@ void plan_domain(const ltriples_domain* d, int32_t prec, const ltriples_options*
   }
   size_t off = 0;
   P.bf = prec == LT_BF16X3 ? 3 : (prec == LT_BF16 ? 1 : 0);
-  // BF16 modes keep only the split (octet) copies of the contraction
+  P.keep32 = bwd && P.bf;
+  // BF16 energies keep only the split (octet) copies of the contraction
   // operands: every FP32 operand tensor is built in one shared staging
-  // buffer and split before the next one is built.
+  // buffer and split before the next one is built.  The BF16X3 adjoint keeps
+  // both (the reverse GEMMs read the FP32 operands).
   std::vector<std::pair<Buf*, size_t>> staged;
   auto take = [&](Buf& b, size_t bytes) { b.off = off; b.bytes = bytes; off = align256(off + bytes); };
   auto take_op = [&](Buf& b, size_t bytes, size_t stage_bytes = 0) {
-    if (!P.bf) { take(b, bytes); return; }
+    if (!P.bf || P.keep32) { take(b, bytes); return; }
     b.bytes = bytes;
     staged.push_back({&b, stage_bytes ? stage_bytes : bytes});
   };
@@ -619,18 +624,21 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
     }
   };
   // BF16 modes: split blocks [b0, b0 + n) of a chunked operand, built in the
-  // staging buffer, into their octet copies
+  // staging buffer (or, for the BF16X3 adjoint, in place), into their octet
+  // copies
   auto split_chunk = [&](int s, int t8, int64_t b0, int64_t n) -> hipError_t {
     if (!P.bf) return hipSuccess;
     const int t = 1 - s;
     const int64_t vs = D.v[s], vt = D.v[t], lp = P.ldnp[s], lc = P.ldcb[s];
     int64_t K, ld, ncol, ibs, iks;
-    if (t8 == Plan::As8) { K = vs; ld = lp; ncol = npair(vs); ibs = vs * lp; iks = lp; }
-    else if (t8 == Plan::Mst8) { K = vt; ld = lc; ncol = vt * vs; ibs = vt * lc; iks = lc; }
-    else { K = vs; ld = lc; ncol = vt * vs; ibs = vs * lc; iks = lc; }   // Mts8
+    const Buf* full;
+    if (t8 == Plan::As8) { K = vs; ld = lp; ncol = npair(vs); ibs = vs * lp; iks = lp; full = &P.As[s]; }
+    else if (t8 == Plan::Mst8) { K = vt; ld = lc; ncol = vt * vs; ibs = vt * lc; iks = lc; full = &P.Mst[s]; }
+    else { K = vs; ld = lc; ncol = vt * vs; ibs = vs * lc; iks = lc; full = &P.Mts[s]; }   // Mts8
     const int64_t blk = ((K + 15) / 16) * 16 * ld;                       // elements per octet block
+    const float* src = P.keep32 ? at<float>(ws, *full) + b0 * ibs : at<float>(ws, P.stage);
     return lt::launch_split8(at<lt::bf16_t>(ws, P.O8h[s][t8]) + b0 * blk, at<lt::bf16_t>(ws, P.O8l[s][t8]) + b0 * blk,
-                             n, (int32_t)K, ld, (int32_t)ncol, at<float>(ws, P.stage), ibs, iks, st);
+                             n, (int32_t)K, ld, (int32_t)ncol, src, ibs, iks, st);
   };
   // --- 1. DF factor layouts --------------------------------------------------
   for (int s = 0; s < 2; ++s) {
@@ -762,7 +770,7 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
       HIPCHK(gemmT(v * v, v, n, at<T>(ws, P.BvvP[s]), P.ldvv[s], 0, at<T>(ws, P.BovR[s]) + i0 * Q * lv, lv,
                    Q * lv, Kx, v * v * lv, 0, lv, 0, 0, 1, 0));
       // As[i][e][p(b<c)] = Kx[i][e][b][c] - Kx[i][e][c][b] (BF16 modes: into staging, then split)
-      T* dst = P.bf ? at<T>(ws, P.stage) : at<T>(ws, P.As[s]) + i0 * v * P.ldnp[s];
+      T* dst = P.bf && !P.keep32 ? at<T>(ws, P.stage) : at<T>(ws, P.As[s]) + i0 * v * P.ldnp[s];
       HIPCHK(lt::launch_pack_pairs<T, T>(dst, P.ldnp[s], n * v, (int32_t)v, Kx, v * lv, lv, 1, true, st));
       HIPCHK(split_chunk(s, Plan::As8, i0, n));
     }
@@ -774,7 +782,7 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
     // Mst[j][E][C*vs+b] = (jb|EC): rows (E,C), cols b; chunks of j
     for (int64_t j0 = 0; j0 < os; j0 += P.cMst[s]) {
       const int64_t n = std::min<int64_t>(P.cMst[s], os - j0);
-      T* dst = P.bf ? at<T>(ws, P.stage) : at<T>(ws, P.Mst[s]) + j0 * vt * lc;
+      T* dst = P.bf && !P.keep32 ? at<T>(ws, P.stage) : at<T>(ws, P.Mst[s]) + j0 * vt * lc;
       HIPCHK(gemmT(vt * vt, vs, n, at<T>(ws, P.BvvP[t]), P.ldvv[t], 0, at<T>(ws, P.BovR[s]) + j0 * Q * P.ldv[s],
                    P.ldv[s], Q * P.ldv[s], dst, vt * lc, lc, vs, (int32_t)vt, 0, 1, 0));
       HIPCHK(split_chunk(s, Plan::Mst8, j0, n));
@@ -782,7 +790,7 @@ int prep(const ltriples_domain* d, const Plan& P, void* ws, hipStream_t st) {
     // Mts[K][e][C*vs+b] = (be|KC): rows C, cols (e,b); chunks of K
     for (int64_t k0 = 0; k0 < ot; k0 += P.cMts[s]) {
       const int64_t n = std::min<int64_t>(P.cMts[s], ot - k0);
-      T* dst = P.bf ? at<T>(ws, P.stage) : at<T>(ws, P.Mts[s]) + k0 * vs * lc;
+      T* dst = P.bf && !P.keep32 ? at<T>(ws, P.stage) : at<T>(ws, P.Mts[s]) + k0 * vs * lc;
       HIPCHK(gemmT(vt, vs * vs, n, at<T>(ws, P.BovR[t]) + k0 * Q * P.ldv[t], P.ldv[t], Q * P.ldv[t],
                    at<T>(ws, P.BvvP[s]), P.ldvv[s], 0, dst, vs * lc, 0, vs, 0, lc, 1, (int32_t)vs));
       HIPCHK(split_chunk(s, Plan::Mts8, k0, n));
@@ -1692,6 +1700,43 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
       ops.Tmix = at<T>(ws, P.Tmix[s]); ops.ZpT = at<T>(ws, P.ZpT[s]); ops.TmT = at<T>(ws, P.TmT[s]);
       ops.OOT = at<T>(ws, P.OOT[s]);
     }
+    // BF16X3 adjoint: the forward contraction is recomputed on the split
+    // operands, from segment descriptors of every item of the block (S or G
+    // in the first half of the table, Y in the second); the reverse GEMMs
+    // below stay FP32
+    lt::Seg8 *tab0 = nullptr, *tab1 = nullptr;
+    if (P.bf) {
+      lt::ItemOps8 o8{};
+      o8.o_s = ops.o_s; o8.v_s = ops.v_s; o8.o_t = ops.o_t; o8.v_t = ops.v_t;
+      o8.oi_s = ops.oi_s; o8.oi_t = ops.oi_t;
+      o8.ld_vs = ops.ld_vs; o8.ld_vt = ops.ld_vt; o8.ld_np = ops.ld_np; o8.ld_cb = ops.ld_cb;
+      auto H = [&](int t8) { return P.O8h[s][t8].bytes ? at<lt::bf16_t>(ws, P.O8h[s][t8]) : nullptr; };
+      auto Lo = [&](int t8) { return P.O8l[s][t8].bytes ? at<lt::bf16_t>(ws, P.O8l[s][t8]) : nullptr; };
+      o8.T2Th = H(Plan::T2T8); o8.T2Tl = Lo(Plan::T2T8); o8.Ash = H(Plan::As8); o8.Asl = Lo(Plan::As8);
+      o8.GamTh = H(Plan::GamT8); o8.GamTl = Lo(Plan::GamT8); o8.Tph = H(Plan::Tp8); o8.Tpl = Lo(Plan::Tp8);
+      o8.LmixTh = H(Plan::LmixT8); o8.LmixTl = Lo(Plan::LmixT8); o8.Msth = H(Plan::Mst8); o8.Mstl = Lo(Plan::Mst8);
+      o8.Mtsh = H(Plan::Mts8); o8.Mtsl = Lo(Plan::Mts8); o8.Tmixh = H(Plan::Tmix8); o8.Tmixl = Lo(Plan::Tmix8);
+      o8.Tmx2h = H(Plan::Tmx28); o8.Tmx2l = Lo(Plan::Tmx28); o8.ZpTh = H(Plan::ZpT8); o8.ZpTl = Lo(Plan::ZpT8);
+      o8.TmTh = H(Plan::TmT8); o8.TmTl = Lo(Plan::TmT8); o8.OOTh = H(Plan::OOT8); o8.OOTl = Lo(Plan::OOT8);
+      tab0 = at_small<lt::Seg8>(ws, P, P.segtab);
+      tab1 = tab0 + 6 * std::max<int64_t>(L.total, 1);
+      o8.items = d_trip + 3 * fc[b];
+      o8.kind = mixed ? 1 : 0;
+      HIPCHK(lt::launch_seg8_table(o8, (int32_t)nblk, tab0 + 6 * (int64_t)fc[b], st));
+      if (mixed) {
+        o8.kind = 2;
+        HIPCHK(lt::launch_seg8_table(o8, (int32_t)nblk, tab1 + 6 * (int64_t)fc[b], st));
+      }
+    }
+    auto contract = [&](const lt::GemmArgs<T>& g) -> hipError_t {
+      if (!P.bf) return lt::launch_gemm<T>(g, st);
+      if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return hipSuccess;
+      lt::GemmArgs16 h{};
+      h.M = g.M; h.N = g.N; h.nbatch = g.nbatch; h.nprod = P.bf;
+      h.out = (float*)(void*)g.out; h.obs = g.obs; h.ldo = g.s_mr; h.kind = g.ops.kind;
+      h.tab = (g.ops.kind == 2 ? tab1 : tab0) + 6 * ((g.ops.items - d_trip) / 3);
+      return lt::launch_gemm_bf16(h, st);
+    };
     const int64_t nb = P.nb[b];
     const size_t o1 = P.o1[b], o2 = P.o2[b];
     const int64_t nt = P.ntile[b];
@@ -1717,7 +1762,7 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
         ops.kind = 0;
         g.M = (int32_t)vs; g.N = (int32_t)npair(vs); g.out = S; g.obs = (int64_t)(o1 / P.ts); g.s_mr = P.ldnp[s];
         g.ops = ops;
-        HIPCHK(lt::launch_gemm<T>(g, st));
+        HIPCHK(contract(g));
         tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(3 * vs + 3 * os) * (double)n;
         hipEvent_t a1 = tm.mark();
         tm.gemm.push_back({a0, a1});
@@ -1744,12 +1789,12 @@ int run_bwd(const ltriples_domain* d, const Plan& P, const ItemLists& L, const l
         ops.kind = 1;
         g.M = (int32_t)vs; g.N = (int32_t)(vt * vs); g.out = G; g.obs = (int64_t)(o1 / P.ts); g.s_mr = P.ldcb[s];
         g.ops = ops;
-        HIPCHK(lt::launch_gemm<T>(g, st));
+        HIPCHK(contract(g));
         tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(2 * vt + vs + os + 2 * ot) * (double)n;
         ops.kind = 2;
         g.M = (int32_t)vt; g.N = (int32_t)npair(vs); g.out = Y; g.obs = (int64_t)(o2 / P.ts); g.s_mr = P.ldnp[s];
         g.ops = ops;
-        HIPCHK(lt::launch_gemm<T>(g, st));
+        HIPCHK(contract(g));
         tm.gemm_flops += 2.0 * (double)g.M * (double)g.N * (double)(2 * vs + 2 * os) * (double)n;
         hipEvent_t a1 = tm.mark();
         tm.gemm.push_back({a0, a1});
@@ -2079,8 +2124,8 @@ int ltriples_debug_w(const ltriples_domain* d, int32_t precision, const int32_t*
 static int validate_bwd(const ltriples_domain* d, int32_t precision, const ltriples_options* o) {
   int r = validate(d, precision, o);
   if (r) return r;
-  if (precision != LT_FP64 && precision != LT_FP32)
-    return fail(LT_EPREC, "the adjoint pass supports FP64 and FP32 only");
+  if (precision != LT_FP64 && precision != LT_FP32 && precision != LT_BF16X3)
+    return fail(LT_EPREC, "the adjoint pass supports FP64, FP32 and BF16X3 only");
   if (o && o->e_items) return fail(LT_EINVAL, "per-item outputs are a forward option");
   return LT_OK;
 }

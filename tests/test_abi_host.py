@@ -180,7 +180,7 @@ BWD_SHAPES = [(5, 4, 30, 31, 120), (6, 5, 45, 47, 96), (4, 0, 21, 22, 40), (3, 1
               (2, 2, 9, 7, 12), (1, 2, 5, 6, 8), (0, 3, 5, 6, 8), (4, 4, 1, 2, 3), (20, 18, 160, 162, 640)]
 
 
-@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32])
+@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32, lt.LT_BF16X3])
 @pytest.mark.parametrize("shape", BWD_SHAPES)
 def test_backward_plan_descriptors_in_bounds(shape, prec):
     """Every range the adjoint's reverse-contraction descriptors address lies
@@ -203,7 +203,10 @@ def test_backward_plan_item_subsets_and_errors():
     o, keep = lt.make_options(items=items, batch_items=2)
     assert lib.ltriples_plan_check(ctypes.byref(d), lt.LT_FP32, ctypes.byref(o), 1) == lt.LT_OK, \
         lt.ltriples_last_error()
-    assert lib.ltriples_plan_check(ctypes.byref(d), lt.LT_BF16X3, None, 1) == lt.LT_EPREC
+    assert lib.ltriples_plan_check(ctypes.byref(d), lt.LT_BF16X3, None, 1) == lt.LT_OK
+    assert lib.ltriples_plan_check(ctypes.byref(d), lt.LT_BF16, None, 1) == lt.LT_EPREC
+    # the BF16X3 adjoint keeps the FP32 operands beside their split copies
+    assert lt.ltriples_backward_workspace_size(d, lt.LT_BF16X3) > lt.ltriples_backward_workspace_size(d, lt.LT_FP32)
     n = ctypes.c_size_t(0)
     assert lib.ltriples_backward_workspace_size(ctypes.byref(d), lt.LT_FP64, None, ctypes.byref(n)) == lt.LT_OK
     assert n.value > lt.ltriples_workspace_size(d, lt.LT_FP64)
@@ -228,7 +231,7 @@ def test_build_chunks_fit_the_large_domain_on_one_gpu():
         assert small <= lt.ltriples_workspace_size(d, p), p
 
 
-@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32])
+@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32, lt.LT_BF16X3])
 def test_backward_plan_in_bounds_with_small_build_chunks(prec):
     d = _fake_domain((6, 5, 45, 47, 96))
     o, _ = lt.make_options(build_chunk_mib=1)
@@ -323,6 +326,8 @@ def test_rhf_backward_workspace_and_errors():
     assert lib.ltriples_backward_rhf_workspace_size(ctypes.byref(d), lt.LT_FP64, None, ctypes.byref(n)) == lt.LT_OK
     assert n.value > 4 * 8 * 4 * 4 * 10 * 10
     assert lib.ltriples_backward_rhf_workspace_size(ctypes.byref(d), lt.LT_BF16X3, None,
+                                                    ctypes.byref(n)) == lt.LT_OK
+    assert lib.ltriples_backward_rhf_workspace_size(ctypes.byref(d), lt.LT_BF16, None,
                                                     ctypes.byref(n)) == lt.LT_EPREC
     g = lt.RhfGrad()
     assert lib.ltriples_backward_rhf(ctypes.byref(d), lt.LT_FP64, None, None, ctypes.byref(g), None, 0,

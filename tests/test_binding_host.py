@@ -112,9 +112,10 @@ def test_gradient_outputs_for_arrays_passed_as_none():
     assert g.shape == (0,) and g.dtype == torch.float64
 
 
-def test_autograd_backward_precision_is_fp64_or_fp32():
-    """The adjoint has FP64 and FP32 kernels only: asking the differentiable
-    energy for a BF16 backward is refused before anything runs."""
+def test_autograd_backward_precision_is_fp64_fp32_or_bf16x3():
+    """The adjoint runs in FP64, FP32 or BF16X3 (split-product recompute, FP32
+    reverse GEMMs): asking the differentiable energy for the plain-BF16
+    ablation as its backward is refused before anything runs."""
     dims = (5, 4, 30, 31, 120)
     with pytest.raises(ValueError):
-        lt.triples_energy({k: None for k in lt.ARRAY_FIELDS}, dims, "bf16x3", backward_precision="bf16x3")
+        lt.triples_energy({k: None for k in lt.ARRAY_FIELDS}, dims, "bf16x3", backward_precision="bf16")

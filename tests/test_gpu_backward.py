@@ -3,7 +3,8 @@
 Reference: the oracle gradient (reverse-mode derivative of the spin-blocked
 FP64 energy, pinned by exact finite-difference stencils).  Bar per gradient
 tensor: max|g_gpu - g_ref| <= tol * max|g_ref| with tol 1e-10 (FP64) and 1e-5
-(FP32).  At the full gradient workload (20,18,160,162,640) the check is the
+(FP32, and BF16X3: the forward contraction recomputed in split BF16 products,
+whose W carries about 1e-6 of relative error, with FP32 reverse GEMMs).  At the full gradient workload (20,18,160,162,640) the check is the
 oracle gradient of a sampled item subset, and the exact directional
 derivative of the GPU's own FP64 energy (E is quadratic in T1, T2 and
 linear in f_ov).
@@ -18,7 +19,7 @@ from tests.gpu_util import to_device
 
 pytestmark = pytest.mark.gpu
 
-TOL = {lt.LT_FP64: 1e-10, lt.LT_FP32: 1e-5}
+TOL = {lt.LT_FP64: 1e-10, lt.LT_FP32: 1e-5, lt.LT_BF16X3: 1e-5}
 ALL_GRAD = lt.GRAD_FIELDS + lt.FOCK_GRAD_FIELDS
 
 SHAPES = {
@@ -60,7 +61,7 @@ def _compare(g, ref, tol, label=""):
         assert err <= tol * max(scale, 1e-300), (label, k, err, scale)
 
 
-@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32])
+@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32, lt.LT_BF16X3])
 @pytest.mark.parametrize("name", list(SHAPES))
 def test_backward_parity_shapes(name, prec):
     dom = _dom(SHAPES[name])
@@ -123,7 +124,7 @@ def _grad_workload_ref():
     return _GRAD_REF["dom"], _GRAD_REF["items"], _GRAD_REF["ref"]
 
 
-@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32])
+@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32, lt.LT_BF16X3])
 def test_backward_sampled_items_gradient_workload(prec):
     """Full-size gradient workload, restricted to a sampled item list: the
     gradient of E(items) against the oracle's gradient of the same items, at
@@ -327,9 +328,11 @@ def test_autograd_function_matches_backward():
         assert torch.equal(leaves[k].grad, g[k]), k
     e_ref, _ = lt.ltriples_energy(t, dom.dims, lt.LT_FP64)
     assert float(E.detach()) == float(e_ref.item())
-    # a BF16X3 forward is differentiated by the FP32 adjoint unless FP64 is asked for
+    # a BF16X3 forward is differentiated by the FP32 adjoint unless FP64 or
+    # the BF16X3 adjoint is asked for
     g32 = lt.ltriples_backward(t, dom.dims, lt.LT_FP32)
-    for bp, ref in ((None, g32), ("fp64", g)):
+    gbf = lt.ltriples_backward(t, dom.dims, lt.LT_BF16X3)
+    for bp, ref in ((None, g32), ("fp64", g), ("bf16x3", gbf)):
         lv = {k: (v.clone().requires_grad_(k in ALL_GRAD)) for k, v in t.items()}
         E = lt.triples_energy(lv, dom.dims, "bf16x3", backward_precision=bp)
         E.backward()

@@ -165,10 +165,10 @@ def test_rhf_lno_sized_domain_two_paths():
 # ---- adjoint ------------------------------------------------------------------------------
 from oracle import grad as ograd  # noqa: E402
 
-GTOL = {lt.LT_FP64: 1e-10, lt.LT_FP32: 1e-5}
+GTOL = {lt.LT_FP64: 1e-10, lt.LT_FP32: 1e-5, lt.LT_BF16X3: 1e-5}
 
 
-@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32])
+@pytest.mark.parametrize("prec", [lt.LT_FP64, lt.LT_FP32, lt.LT_BF16X3])
 @pytest.mark.parametrize("shape", [(3, 17, 30), (4, 21, 40), (2, 13, 20)])
 def test_rhf_backward_parity(shape, prec):
     """Every closed-shell gradient against the oracle's reverse mode over
