@@ -844,11 +844,11 @@ struct GroupDom {
 };
 
 // The forward launch sequence of a group of domains (steps 1-6).  Each
-// domain's operands are prepared in its own region; then, spin block by spin
-// block and batch round by batch round, one contraction launch per output
-// layout takes the round's item batch of every domain of the group (BF16X3
-// and BF16; FP32/FP64 launch per domain), followed by each domain's epilogue
-// and per-item reduction.  A domain's batches, epilogues and reductions are
+// domain's operands are prepared in its own region; then, for every spin
+// block and every batch index r, one contraction launch per output layout
+// takes the r-th item batch of every domain of the group (BF16X3 and BF16;
+// FP32/FP64 launch per domain), followed by each domain's epilogue and
+// per-item reduction.  A domain's batches, epilogues and reductions are
 // exactly those of a call on that domain alone, so every result bit is too.
 // Domains are taken in the given order (the batched entry point passes them
 // longest first).
@@ -906,14 +906,14 @@ int run_group(const GroupDom* G, int ng, const ltriples_options* o, hipStream_t 
   for (int b = 0; b < 4; ++b) {
     const int s = blk_sigma(b), t = 1 - s;
     const bool mixed = blk_mixed(b);
-    int64_t rounds = 0;
+    int64_t nbatches = 0;   // batches of the domain with the most
     for (int x = 0; x < ng; ++x) {
       Dom& m = S[x];
       const Plan& P = *G[x].P;
       const Dims& D = P.D;
       void* ws = G[x].ws;
       if (!m.active || P.n_blk[b] == 0) continue;
-      rounds = std::max(rounds, cdiv(P.n_blk[b], P.nb[b]));
+      nbatches = std::max(nbatches, cdiv(P.n_blk[b], P.nb[b]));
       lt::ItemOps<T>& ops = m.ops;
       ops = lt::ItemOps<T>{};
       ops.o_s = (int32_t)D.o[s]; ops.v_s = (int32_t)D.v[s]; ops.o_t = (int32_t)D.o[t]; ops.v_t = (int32_t)D.v[t];
@@ -957,8 +957,8 @@ int run_group(const GroupDom* G, int ng, const ltriples_options* o, hipStream_t 
     // output layouts of the block: S (same spin), or G then Y (mixed)
     const int kinds[2] = {mixed ? 1 : 0, 2};
     const int nkind = mixed ? 2 : 1;
-    for (int64_t r = 0; r < rounds; ++r) {
-      // this round's batch of domain x: items [first, first + n) of block b
+    for (int64_t r = 0; r < nbatches; ++r) {
+      // the r-th batch of domain x: items [first, first + n) of block b
       auto batch_of = [&](int x, int64_t& first, int64_t& n) {
         const Plan& P = *G[x].P;
         first = r * P.nb[b];
@@ -967,7 +967,7 @@ int run_group(const GroupDom* G, int ng, const ltriples_options* o, hipStream_t 
       };
       for (int kx = 0; kx < nkind; ++kx) {
         const int kind = kinds[kx];
-        // one domain's contraction arguments for this round and layout
+        // one domain's contraction arguments for batch r and this layout
         auto args = [&](int x, int64_t first, int64_t n, lt::GemmArgs<T>& g) {
           const Plan& P = *G[x].P;
           const Dims& D = P.D;
