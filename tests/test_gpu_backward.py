@@ -96,6 +96,24 @@ def test_backward_chunked_builds_bitwise_equal():
         assert np.array_equal(g0[k], g1[k]), k
 
 
+def test_backward_bf16x3_chunks_and_batches():
+    """The BF16X3 adjoint keeps the FP32 operands beside their split copies
+    and splits chunked operand builds in place: with 1 MiB build chunks
+    (several chunks per operand on this shape) it gives exactly the default
+    gradient; with batches of 3 items it agrees to rounding (the batching
+    orders the reverse sums), and both stay at the FP32 bar."""
+    dom = _dom(SHAPES["wide"])
+    t = to_device(dom)
+    g0 = _gpu_grad(dom, lt.LT_BF16X3, tensors=t)
+    g1 = _gpu_grad(dom, lt.LT_BF16X3, tensors=t, build_chunk_mib=1)
+    for k in ALL_GRAD:
+        assert np.array_equal(g0[k], g1[k]), k
+    g3 = _gpu_grad(dom, lt.LT_BF16X3, tensors=t, batch_items=3)
+    _compare(g3, g0, 1e-6, "bf16x3 batch3")
+    _, ref = ograd.energy_and_grad(dom, fock=True)
+    _compare(g1, ref, TOL[lt.LT_BF16X3], "bf16x3 chunks")
+
+
 def test_backward_workspace_garbage_never_read():
     import torch
     dom = _dom(SHAPES["wide"])
